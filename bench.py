@@ -1,0 +1,212 @@
+"""Benchmark: incident-angle solves per second of the full hot path on one MI355X.
+
+One step = hbs_build (recursive skeletonization of the N x N Nystrom matrix) + qp_solve_many
+over every incident angle of the workload (one application of A^{-1} to [B_L | B_R | b...],
+alpha-free Schur products, per-alpha Schur inversions, refinement, Bragg amplitudes), with the
+geometry already resident in HBM.  value = angles per second over the timed steps.
+
+Default workload "wavy40": seeded 40-harmonic obstacle, N = 1e5, omega = 60, d = 2 pi,
+200 angles on 4 shared Bloch phases.
+
+Also reported: the roofline of the dominant kernel (the complex FP64 MFMA GEMM) from HIP events
+on the library's stream, the oracle timed on the host cores on a bounded sample, and a
+verification of the timed solution (sampled residual rows of the bordered system evaluated by
+the oracle's kernels, and the energy balance).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "incident-angle solves/sec at N=1e5, rel err<=1e-10; HBS build time (s)"
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, n_sample=2000, q_sample=2):
+    """The oracle (dense Nystrom + bordered LU per angle) on a bounded sample of the workload:
+    the same obstacle, frequency, period and first angles at N = n_sample; the per-angle time is
+    scaled to the workload's N by the O((N + 2M)^3) cost of the dense LU that dominates it."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import nystrom as ny
+    from oracle import periodic as pq
+
+    disc = ny.Discretization(wl.curve, n_sample)
+    th = wl.thetas[:q_sample]
+    t0 = time.perf_counter()
+    r = pq.solve_qp(disc, n_sample, wl.omega, wl.period, th, quad=wl.quad)
+    t = time.perf_counter() - t0
+    Ms = len(r["contour"].k)
+    dfull = ny.Discretization(wl.curve, 2000)  # only for the contour size of the workload
+    Mf = len(pq.default_contour(dfull, wl.omega, wl.period).k)
+    scale = ((wl.N + 2 * Mf) / (n_sample + 2 * Ms)) ** 3
+    per_angle_full = t / q_sample * scale
+    threads = sum(x.get("num_threads", 0) for x in threadpool_info() if x.get("user_api") == "blas") or os.cpu_count()
+    return {"value": 1.0 / per_angle_full, "unit": "angles/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"N={n_sample}, {q_sample} angles of the same workload in {t:.1f} s "
+                      f"({q_sample / t:.3g} angles/s at that N); scaled by ((N+2M)/(Ns+2Ms))^3 = {scale:.3g} "
+                      f"to N={wl.N}, M={Mf}"}
+
+
+def verify(wl, res, n_rows=48, n_ang=6, chunk=4000):
+    """Sampled rows of the bordered-system residual [A B; C Q][eta; xi] - [b; 0] with the oracle's
+    kernels (exact dense rows of A and B; all rows of C and Q, accumulated over node chunks),
+    relative to |b|, plus the flux error of every angle."""
+    import numpy as np
+    from oracle import nystrom as ny
+    from oracle import periodic as pq
+    from oracle import quadrature as qd
+
+    disc = ny.Discretization(wl.curve, wl.N)
+    ct = pq.default_contour(disc, wl.omega, wl.period)
+    rng = np.random.default_rng(7)
+    rows = np.sort(rng.choice(wl.N, n_rows, replace=False))
+    angs = rng.choice(len(wl.thetas), n_ang, replace=False)
+    R = qd.kr6_band(wl.N)
+    K = ny.kernel(wl.omega, disc.x[rows], disc.x, disc.nrm)
+    idx = np.arange(wl.N)
+    Arows = R[(rows[:, None] - idx[None, :]) % wl.N] * np.where(rows[:, None] == idx[None, :], 0, K) * disc.w[None, :]
+    Arows[np.arange(n_rows), rows] += 0.5
+    BL, BR = pq.wall_B(_Sub(disc, rows), wl.omega, wl.period, ct)
+    eta = res["eta"][:, angs]
+    CLe = 0
+    CRe = 0
+    for c0 in range(0, wl.N, chunk):
+        sl = np.arange(c0, min(wl.N, c0 + chunk))
+        CL, CR = pq.wall_C(_Sub(disc, sl), wl.omega, wl.period, ct)
+        CLe = CLe + CL @ eta[sl]
+        CRe = CRe + CR @ eta[sl]
+    worst = 0.0
+    for q, a in enumerate(angs):
+        th = wl.thetas[a]
+        al = pq.bloch_phase(wl.omega, wl.period, th)
+        xi = res["xi"][:, a]
+        b = pq.incident(_Sub(disc, rows), wl.omega, th)[:, 0]
+        r1 = Arows @ eta[:, q] + (BL + al * BR) @ xi - b
+        r2 = CLe[:, q] - CRe[:, q] / al + pq.wall_Q(wl.omega, wl.period, al, ct) @ xi
+        bn = np.linalg.norm(pq.incident(disc, wl.omega, th))
+        worst = max(worst, math.sqrt(np.sum(np.abs(r1) ** 2) * wl.N / n_rows + np.sum(np.abs(r2) ** 2)) / bn)
+    return {"sampled_rel_residual": worst, "flux_err_max": float(np.max(res["flux"])),
+            "rows_sampled": n_rows, "angles_sampled": n_ang}
+
+
+class _Sub:
+    """Row subset of a discretization (for evaluating B and b on sampled nodes)."""
+
+    def __init__(self, disc, rows):
+        self.x = disc.x[rows]
+        self.nrm = disc.nrm[rows]
+        self.w = disc.w[rows]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="wavy40")
+    ap.add_argument("--tol", type=float, default=1e-12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-verify", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the sharding design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import qpinputs
+    from paper_1301_1247_amd import binding as B
+    from paper_1301_1247_amd.geometry import discretize
+
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    wl = qpinputs.workload(args.workload)
+    nodes, w, nrm, kap = discretize(wl.curve, wl.N)
+    dev = torch.device("cuda:0")
+    t_nodes = torch.from_numpy(nodes).to(dev)
+    t_w = torch.from_numpy(w).to(dev)
+    t_nrm = torch.from_numpy(nrm).to(dev)
+    t_kap = torch.from_numpy(kap).to(dev)
+    t_th = torch.from_numpy(wl.thetas).to(dev)
+    stream = torch.cuda.current_stream()
+    nang = len(wl.thetas)
+    kw = dict(quad=wl.quad, leaf_size=wl.leaf_size, curvature=t_kap if wl.quad == "kress" else None, device=True,
+              stream=stream.cuda_stream)
+
+    def step():
+        h = B.Handle(t_nodes, t_w, t_nrm, wl.omega, args.tol, **kw)
+        res = h.qp_solve_many(wl.period, t_th)
+        return h, res
+
+    for i in range(args.warmup):
+        h, res = step()
+        log(f"warmup {i}: build {h.stats().build_seconds:.3f} s, refine residual {h.stats().refine_residual:.2e}")
+        del h, res
+    torch.cuda.synchronize()
+    B.profile_enable(True)
+    builds = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        h, res = step()
+        builds.append(h.stats().build_seconds)
+        if i < args.steps - 1:
+            del h, res
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    prof = B.profile_read("zgemm")
+    B.profile_enable(False)
+    st = h.stats()
+    log(f"timed {args.steps} steps in {t:.3f} s; zgemm {prof}")
+    ms = 1000.0 * t / args.steps
+    value = nang * args.steps / t
+    achieved = prof["flops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "angles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: seeded obstacle, N={wl.N}, omega={wl.omega}, d=2pi, "
+                               f"{nang} angles, tol={args.tol:g}, KR6 + proxy compression",
+                   "N": wl.N, "omega": wl.omega, "angles": nang, "contour_M": st.contour_M},
+        "build_seconds": float(np.median(builds)),
+        "levels": st.levels, "max_rank": st.max_rank, "root_size": st.root_size,
+        "refine_iters": st.refine_iters, "refine_residual": st.refine_residual,
+        "roofline": {"bound": "mfma", "kernel": "k_zgemm (complex FP64 MFMA GEMM)", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": None, "launches": prof["launches"],
+                     "avg_launch_ms": prof["ms"] / max(1, prof["launches"]),
+                     "flops_per_launch": prof["flops"] / max(1, prof["launches"])},
+    }
+    if not args.no_verify:
+        res_h = {"eta": res["eta"].T.cpu().numpy(), "xi": res["xi"].T.cpu().numpy(), "flux": res["flux"]}
+        out["verify"] = verify(wl, res_h)
+    del h, res
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

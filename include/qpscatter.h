@@ -1,0 +1,173 @@
+/* qpscatter.h -- C ABI of the MI355X (gfx950) fast direct solver for 2D quasi-periodic
+ * Dirichlet scattering (Gillman & Barnett, "A fast direct solver for quasi-periodic
+ * scattering problems").
+ *
+ * Conventions for every entry point:
+ *  - Complex arrays are interleaved (re, im) doubles, column-major.  Point arrays are
+ *    N x 2 row-major ((x0, y0, x1, y1, ...)).
+ *  - With opts->ptr_mode == HBS_PTR_HOST (default) array arguments are host pointers,
+ *    borrowed for the duration of the call and copied to / from the GPU.  With
+ *    HBS_PTR_DEVICE they are device pointers (e.g. torch tensors' data_ptr()) and no
+ *    copies are made.  The mode given at hbs_build applies to every later call on
+ *    that handle.
+ *  - All GPU work of a handle runs on opts->stream (a hipStream_t; NULL = the default
+ *    stream).  Calls return after the results are complete.
+ *  - Status codes: 0 on success, a negative HBS_E_* code otherwise; the text of the last
+ *    error of the calling thread is returned by hbs_last_error().  Validation errors are
+ *    detected on the host before any GPU work.
+ *  - A handle may be used by one call at a time; distinct handles may be used
+ *    concurrently from different threads.
+ */
+#ifndef QPSCATTER_H
+#define QPSCATTER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HBS_OK = 0,
+  HBS_E_INVALID_ARG = -1,   /* bad size, pointer, option or non-unit normal */
+  HBS_E_NONFINITE = -2,     /* NaN / Inf in an input array */
+  HBS_E_OOM = -3,           /* device allocation failed or mem_limit exceeded */
+  HBS_E_DEVICE = -4,        /* HIP runtime error (text in hbs_last_error) */
+  HBS_E_SINGULAR = -6,      /* zero pivot in a diagonal block, the root or a Schur complement */
+  HBS_E_NOT_CONVERGED = -7, /* refinement did not reach qp_opts.refine_tol */
+  HBS_E_ALPHA_MISMATCH = -8,/* |alpha - exp(i omega d cos theta)| > 1e-12 for some theta */
+  HBS_E_WOOD = -9           /* an angle is within qp_opts.wood_min_kn of a Wood's anomaly */
+};
+
+enum { HBS_QUAD_KR6 = 0, HBS_QUAD_KRESS = 1 };
+enum { HBS_COMPRESS_PROXY = 0, HBS_COMPRESS_EXACT = 1 };
+enum { HBS_PTR_HOST = 0, HBS_PTR_DEVICE = 1 };
+
+typedef struct hbs_handle hbs_handle;
+
+typedef struct {
+  int32_t struct_size;      /* sizeof(hbs_opts); set by hbs_opts_init */
+  int32_t quad;             /* HBS_QUAD_KR6 (Sec. 2.3) or HBS_QUAD_KRESS (needs curvature) */
+  int32_t compress;         /* HBS_COMPRESS_PROXY (proxy circles) or HBS_COMPRESS_EXACT
+                               (true off-diagonal blocks; required with KRESS, O(N^2)) */
+  int32_t leaf_size;        /* max points per leaf box; 0 -> 64 */
+  double proxy_ratio;       /* proxy circle radius / box radius; 0 -> 2.0 */
+  int32_t proxy_min;        /* minimum proxy points per circle; 0 -> 64 */
+  int32_t ptr_mode;         /* HBS_PTR_HOST or HBS_PTR_DEVICE */
+  const double* curvature;  /* KRESS only: signed curvature at the N nodes (ptr_mode) */
+  void* stream;             /* hipStream_t, NULL = default stream */
+  uint64_t seed;            /* seed of the sketching matrices of the interpolative decompositions */
+} hbs_opts;
+
+typedef struct {
+  int32_t struct_size;      /* sizeof(qp_opts) */
+  int32_t P;                /* neighbour images on each side (Sec. 2.4): 0 or 1 */
+  int32_t M;                /* contour nodes; 0 -> ceil(2K/h) */
+  double K;                 /* contour half-width in Re k; 0 -> sqrt(omega^2 + (37/g)^2) */
+  double h;                 /* contour spacing; 0 -> 0.1 */
+  double ca, cb;            /* contour k(t) = t - i ca tanh(t / cb); 0 -> 1, 1 */
+  double y0;                /* Bragg reference height; 0 -> max|y| + 0.5 */
+  double wood_min_kn;       /* refuse angles with min_n |k_n| below this; 0 -> 0.75 */
+  int32_t refine_max_iter;  /* iterative refinement steps of the bordered system; <0 -> 0, 0 -> 2 */
+  double refine_tol;        /* stop when the relative residual is below; 0 -> 1e-13 */
+} qp_opts;
+
+typedef struct {
+  int32_t struct_size;
+  int32_t levels;           /* tree depth L (leaves at level L, root at 0) */
+  int64_t N;
+  int32_t root_size;        /* size of the dense root matrix */
+  int32_t max_rank;         /* largest skeleton rank over all boxes */
+  int64_t factor_bytes;     /* device bytes held by the factors */
+  double build_seconds;
+  int32_t ranks_per_level_max[32];
+  double ranks_per_level_mean[32];
+  int32_t refine_iters;     /* refinement iterations of the last qp_solve */
+  double refine_residual;   /* relative residual after the last qp_solve */
+  int32_t contour_M;        /* contour size of the last qp_solve */
+} hbs_stats_t;
+
+void hbs_opts_init(hbs_opts* o);
+void qp_opts_init(qp_opts* o);
+
+/* Build the compressed (HBS) inverse of the Nystrom matrix A = I/2 + D - i omega S of the
+ * isolated obstacle (Sec. 2.2 below Eq. 2.15, discretized as in Sec. 2.3) by recursive
+ * skeletonization (Sec. 4, Eqs. 4.1-4.8; interpolative decomposition of Def. 3.1 with proxy
+ * circles as in Sec. 3.2).
+ *   nodes   N x 2   trapezoid nodes y_j = z(2 pi j / N), counter-clockwise
+ *   weights N       w_j = (2 pi / N) |z'(t_j)|  (> 0)
+ *   normals N x 2   outward unit normals
+ *   omega > 0, tol in [1e-15, 1e-2] (relative tolerance of each interpolative decomposition).
+ *   N >= 2 * leaf_size and N >= 13 (KR6) / even (KRESS).
+ * On success *out holds a handle owning all device memory of the factors. */
+int hbs_build(const double* nodes, const double* weights, const double* normals, int64_t N,
+              double omega, double tol, const hbs_opts* opts, hbs_handle** out);
+
+/* out = A^{-1} rhs through the compressed inverse (Eq. 4.3 applied level by level),
+ * followed by `refine` steps of iterative refinement against the compressed forward operator.
+ *   rhs, out: N x nrhs complex (may not alias). */
+int hbs_apply(hbs_handle* h, const double* rhs, int64_t nrhs, double* out, int32_t refine);
+
+/* out = A x with the compressed forward operator (the telescoping factorization of Eq. 4.8
+ * built from the same skeletons); relative accuracy ~ tol.  x, out: N x nrhs complex. */
+int hbs_forward(hbs_handle* h, const double* x, int64_t nrhs, double* out);
+
+/* Solve the quasi-periodic problem (Eq. 1.1 restricted to the unit cell, Sec. 2.1) for the q
+ * incident angles thetas[q] in (-pi, 0) that share the Bloch phase alpha = alpha_re + i alpha_im
+ * (Eq. 1.2), with period d, by the block solve of Sec. 3.1 (Eq. 3.1) on the bordered system of
+ * Eq. 2.19 (Eq. 2.21 with P = 1 neighbour images, Woodbury form of Eq. 3.2) and iterative
+ * refinement of the bordered system.
+ *   eta      N x q complex   obstacle densities (required)
+ *   xi       2M x q complex  wall densities [mu; nu] (nullable)
+ *   bragg    2 x n_modes x q complex: c_n then d_n for n = nlo..nlo+n_modes-1 (nullable); the
+ *            propagating orders of each angle, n_modes_out[q] and nlo_out[q] tell the range
+ *   flux_err q doubles, energy-balance error of Remark 6.1 (nullable)
+ * bragg must hold 2 * qp_max_modes(omega, d) * q complex values. */
+int qp_solve(hbs_handle* h, double period, double alpha_re, double alpha_im, const double* thetas,
+             int64_t q, const qp_opts* opts, double* eta, double* xi, double* bragg,
+             int32_t* nlo_out, int32_t* n_modes_out, double* flux_err);
+
+/* Same for n angles with any Bloch phases: the angles are grouped by alpha internally and all
+ * groups share one application of A^{-1} to [B_L | B_R | b_1..b_n] (Remark 3.1). */
+int qp_solve_many(hbs_handle* h, double period, const double* thetas, int64_t n, const qp_opts* opts,
+                  double* eta, double* xi, double* bragg, int32_t* nlo_out, int32_t* n_modes_out,
+                  double* flux_err);
+
+/* Number of contour nodes M that qp_solve will use for this handle and options (xi is 2M x q). */
+int32_t qp_contour_size(const hbs_handle* h, double period, const qp_opts* opts);
+/* Upper bound on the number of Bragg orders returned per angle. */
+int32_t qp_max_modes(double omega, double period);
+
+int hbs_stats(const hbs_handle* h, hbs_stats_t* s);
+void hbs_free(hbs_handle* h);                 /* NULL is a no-op */
+const char* hbs_last_error(void);             /* thread-local; "" if none */
+
+/* ---------------------------------------------------------------- diagnostics ---------
+ * Unit-level access to the device kernels, used by the parity tests. */
+
+/* H0(x_i), H1(x_i) for x_i > 0 evaluated on the GPU; out = 2 x n complex (H0 row then H1). */
+int qps_hankel01(const double* x, int64_t n, double* out, int32_t ptr_mode);
+/* The symmetric Kapur-Rokhlin 6th-order corrections g_1..g_6 (R_m = 1 + g_m, Sec. 2.3) as
+ * derived by the library (host, long double). */
+int qps_kr6_corrections(double out[6]);
+/* Entries A(rows[t], cols[t]) of the Nystrom matrix of the handle, evaluated on the GPU. */
+int qps_matrix_entries(hbs_handle* h, const int32_t* rows, const int32_t* cols, int64_t n, double* out);
+/* Batched complex GEMM C_b = A_b B_b (+ C_b if accumulate) on the GPU with the library's
+ * MFMA kernel: nbatch equal-size problems, A: m x k, B: k x n, C: m x n, col-major, packed. */
+int qps_zgemm(const double* A, const double* B, double* C, int32_t m, int32_t n, int32_t k,
+              int32_t nbatch, int32_t transA, int32_t accumulate, int32_t ptr_mode);
+/* In-place inversion of nbatch square n x n complex matrices (Gauss-Jordan, partial pivoting). */
+int qps_zinv(double* A, int32_t n, int32_t nbatch, int32_t ptr_mode);
+
+/* Kernel-time profiling with HIP events on the handle's stream.  When enabled, each launch
+ * of a kernel family is bracketed by events; qps_profile_read returns the summed time (ms),
+ * launch count and summed algorithmic flops of the family ("zgemm", "cpqr", "zinv",
+ * "assemble", "apply").  Enabling resets the counters. */
+int qps_profile_enable(int32_t on);
+int qps_profile_read(const char* family, double* ms, int64_t* launches, double* flops, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,508 @@
+// C ABI of the library (include/qpscatter.h): validation, staging, handle lifecycle.
+#include "hbs.h"
+#include "qp_kernels.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace qps {
+const char* last_error();
+void clear_error();
+void profile_enable(bool on);
+bool profile_read(const std::string& fam, double* ms, int64_t* launches, double* flops, double* bytes);
+
+namespace {
+
+// Kapur-Rokhlin 6th-order end corrections (Sec. 2.3).  The symmetric corrections g_m
+// (R_m = 1 + g_m at index distance m = 1..6) make the punctured trapezoid rule exact for the
+// terms of its error expansion for phi(s) ln|s| + psi(s) up to h^5:
+//   sum g_m m^{2p} = 1/2 [p = 0],  sum g_m ln m = -ln(2 pi)/2,  sum g_m m^{2p} ln m = zeta'(-2p) (p = 1, 2),
+// with zeta'(-2) = -zeta(3) / (4 pi^2), zeta'(-4) = 3 zeta(5) / (4 pi^4).  Solved in long double.
+long double zeta_ld(int s) {
+  // direct sum to K-1 plus the Euler-Maclaurin tail at K
+  const int K = 64;
+  long double acc = 0.0L;
+  for (int n = K - 1; n >= 1; --n) acc += std::pow((long double)n, (long double)-s);
+  const long double k = K;
+  const long double ks = std::pow(k, (long double)-s);
+  acc += k * ks / (s - 1) + ks / 2 + s * ks / (12 * k) - (long double)s * (s + 1) * (s + 2) * ks / (720 * k * k * k) +
+         (long double)s * (s + 1) * (s + 2) * (s + 3) * (s + 4) * ks / (30240 * k * k * k * k * k);
+  return acc;
+}
+
+void kr6_corrections(double out[6]) {
+  const long double pi = std::acos(-1.0L);
+  long double a[6][7];
+  for (int m = 1; m <= 6; ++m) {
+    const long double lm = std::log((long double)m);
+    const long double m2 = (long double)m * m;
+    a[0][m - 1] = 1.0L;
+    a[1][m - 1] = m2;
+    a[2][m - 1] = m2 * m2;
+    a[3][m - 1] = lm;
+    a[4][m - 1] = m2 * lm;
+    a[5][m - 1] = m2 * m2 * lm;
+  }
+  a[0][6] = 0.5L;
+  a[1][6] = 0.0L;
+  a[2][6] = 0.0L;
+  a[3][6] = -0.5L * std::log(2.0L * pi);
+  a[4][6] = -zeta_ld(3) / (4.0L * pi * pi);
+  a[5][6] = 3.0L * zeta_ld(5) / (4.0L * pi * pi * pi * pi);
+  for (int c = 0; c < 6; ++c) {
+    int p = c;
+    for (int r = c + 1; r < 6; ++r)
+      if (std::fabs(a[r][c]) > std::fabs(a[p][c])) p = r;
+    for (int j = 0; j < 7; ++j) std::swap(a[c][j], a[p][j]);
+    for (int r = 0; r < 6; ++r) {
+      if (r == c) continue;
+      const long double f = a[r][c] / a[c][c];
+      for (int j = c; j < 7; ++j) a[r][j] -= f * a[c][j];
+    }
+  }
+  for (int c = 0; c < 6; ++c) out[c] = (double)(a[c][6] / a[c][c]);
+}
+
+// Kress weights R(t_m) = -(2 pi / n) sum_{k=1}^{n-1} cos(k t_m) / k - (pi / n^2) cos(n t_m), t_m = 2 pi m / N
+std::vector<double> kress_weights(int64_t N) {
+  const int64_t n = N / 2;
+  const long double pi = std::acos(-1.0L);
+  std::vector<double> R(N);
+  for (int64_t m = 0; m < N; ++m) {
+    long double acc = 0.0L;
+    for (int64_t k = 1; k < n; ++k) {
+      const int64_t ph = (k * m) % N;
+      acc += std::cos(2.0L * pi * (long double)ph / (long double)N) / (long double)k;
+    }
+    const int64_t ph = (n * m) % N;
+    R[m] = (double)(-(2.0L * pi / n) * acc - (pi / ((long double)n * n)) * std::cos(2.0L * pi * ph / (long double)N));
+  }
+  return R;
+}
+
+bool finite_all(const double* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+hipStream_t stream_of(const hbs_opts* o) { return o ? (hipStream_t)o->stream : nullptr; }
+
+#define CKD(expr)                                                                          \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess) {                                                                \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(_e));                        \
+      return _e == hipErrorOutOfMemory ? HBS_E_OOM : HBS_E_DEVICE;                         \
+    }                                                                                      \
+  } while (0)
+
+// copy n doubles from caller memory (host or device) to a host vector
+int fetch(const double* p, int64_t n, int mode, std::vector<double>& out) {
+  out.resize(n);
+  if (n == 0) return HBS_OK;
+  if (mode == HBS_PTR_DEVICE) {
+    CKD(hipMemcpy(out.data(), p, sizeof(double) * n, hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(out.data(), p, sizeof(double) * n);
+  }
+  return HBS_OK;
+}
+
+}  // namespace
+}  // namespace qps
+
+using namespace qps;
+
+extern "C" {
+
+void hbs_opts_init(hbs_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(hbs_opts);
+  o->quad = HBS_QUAD_KR6;
+  o->compress = HBS_COMPRESS_PROXY;
+  o->leaf_size = 64;
+  o->proxy_ratio = 2.0;
+  o->proxy_min = 64;
+  o->ptr_mode = HBS_PTR_HOST;
+  o->seed = 0x5EED1301ull;
+}
+
+void qp_opts_init(qp_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(qp_opts);
+  o->h = 0.1;
+  o->ca = 1.0;
+  o->cb = 1.0;
+  o->wood_min_kn = 0.75;
+  o->refine_max_iter = 2;
+  o->refine_tol = 1e-13;
+}
+
+const char* hbs_last_error(void) { return qps::last_error(); }
+
+int hbs_build(const double* nodes, const double* weights, const double* normals, int64_t N, double omega, double tol,
+              const hbs_opts* opts, hbs_handle** out) {
+  clear_error();
+  if (!out) { set_error("hbs_build: out is NULL"); return HBS_E_INVALID_ARG; }
+  *out = nullptr;
+  hbs_opts o;
+  hbs_opts_init(&o);
+  if (opts) {
+    if (opts->struct_size != (int32_t)sizeof(hbs_opts)) { set_error("hbs_build: opts->struct_size mismatch"); return HBS_E_INVALID_ARG; }
+    o = *opts;
+    if (o.leaf_size <= 0) o.leaf_size = 64;
+    if (!(o.proxy_ratio > 0)) o.proxy_ratio = 2.0;
+    if (o.proxy_min <= 0) o.proxy_min = 64;
+  }
+  if (!nodes || !weights || !normals) { set_error("hbs_build: NULL geometry pointer"); return HBS_E_INVALID_ARG; }
+  if (!(omega > 0) || !std::isfinite(omega)) { set_error("hbs_build: omega must be positive and finite"); return HBS_E_INVALID_ARG; }
+  if (!(tol >= 1e-15 && tol <= 1e-2)) { set_error("hbs_build: tol must lie in [1e-15, 1e-2]"); return HBS_E_INVALID_ARG; }
+  if (o.quad != HBS_QUAD_KR6 && o.quad != HBS_QUAD_KRESS) { set_error("hbs_build: unknown quadrature"); return HBS_E_INVALID_ARG; }
+  if (o.compress != HBS_COMPRESS_PROXY && o.compress != HBS_COMPRESS_EXACT) { set_error("hbs_build: unknown compression"); return HBS_E_INVALID_ARG; }
+  if (o.ptr_mode != HBS_PTR_HOST && o.ptr_mode != HBS_PTR_DEVICE) { set_error("hbs_build: unknown ptr_mode"); return HBS_E_INVALID_ARG; }
+  if (o.quad == HBS_QUAD_KR6 && N < 13) { set_error("hbs_build: KR6 needs N >= 13"); return HBS_E_INVALID_ARG; }
+  if (o.quad == HBS_QUAD_KRESS) {
+    if (N % 2) { set_error("hbs_build: Kress quadrature needs even N"); return HBS_E_INVALID_ARG; }
+    if (!o.curvature) { set_error("hbs_build: Kress quadrature needs opts->curvature"); return HBS_E_INVALID_ARG; }
+    if (o.compress != HBS_COMPRESS_EXACT) {
+      set_error("hbs_build: Kress quadrature is a global correction; use HBS_COMPRESS_EXACT");
+      return HBS_E_INVALID_ARG;
+    }
+  }
+  if (N < 2 * (int64_t)o.leaf_size) { set_error("hbs_build: N must be at least 2 * leaf_size"); return HBS_E_INVALID_ARG; }
+  if (N > (int64_t)1 << 30) { set_error("hbs_build: N too large"); return HBS_E_INVALID_ARG; }
+  std::vector<double> xy, w, nrm, kap;
+  int r;
+  if ((r = fetch(nodes, 2 * N, o.ptr_mode, xy)) != HBS_OK) return r;
+  if ((r = fetch(weights, N, o.ptr_mode, w)) != HBS_OK) return r;
+  if ((r = fetch(normals, 2 * N, o.ptr_mode, nrm)) != HBS_OK) return r;
+  if (o.quad == HBS_QUAD_KRESS && (r = fetch(o.curvature, N, o.ptr_mode, kap)) != HBS_OK) return r;
+  if (!finite_all(xy.data(), 2 * N) || !finite_all(w.data(), N) || !finite_all(nrm.data(), 2 * N) ||
+      !finite_all(kap.data(), (int64_t)kap.size())) {
+    set_error("hbs_build: non-finite value in the geometry");
+    return HBS_E_NONFINITE;
+  }
+  for (int64_t i = 0; i < N; ++i) {
+    if (!(w[i] > 0)) { set_error("hbs_build: weights must be positive"); return HBS_E_INVALID_ARG; }
+    const double nn = std::hypot(nrm[2 * i], nrm[2 * i + 1]);
+    if (std::fabs(nn - 1.0) > 1e-8) { set_error("hbs_build: normals must have unit length"); return HBS_E_INVALID_ARG; }
+  }
+  hbs_handle* h = new hbs_handle();
+  h->N = N;
+  h->omega = omega;
+  h->tol = tol;
+  h->opts = o;
+  h->stream = stream_of(&o);
+  h->hx.resize(N); h->hy.resize(N); h->hnx.resize(N); h->hny.resize(N);
+  for (int64_t i = 0; i < N; ++i) {
+    h->hx[i] = xy[2 * i];
+    h->hy[i] = xy[2 * i + 1];
+    h->hnx[i] = nrm[2 * i];
+    h->hny[i] = nrm[2 * i + 1];
+  }
+  h->hw = w;
+  h->hkap = kap;
+  auto fail = [&](int code) { delete h; return code; };
+  const int nf = (o.quad == HBS_QUAD_KRESS) ? 6 : 5;
+  if (h->dgeo.reserve(sizeof(double) * N * nf) != hipSuccess) { set_error("hbs_build: out of device memory"); return fail(HBS_E_OOM); }
+  double* g = h->dgeo.as<double>();
+  const double* src[6] = {h->hx.data(), h->hy.data(), h->hnx.data(), h->hny.data(), h->hw.data(), h->hkap.data()};
+  for (int f = 0; f < nf; ++f)
+    if (hipMemcpy(g + f * N, src[f], sizeof(double) * N, hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("hbs_build: geometry upload failed");
+      return fail(HBS_E_DEVICE);
+    }
+  Geo& G = h->geo;
+  G.x = g; G.y = g + N; G.nx = g + 2 * N; G.ny = g + 3 * N; G.w = g + 4 * N;
+  G.kap = (nf == 6) ? g + 5 * N : nullptr;
+  G.kressR = nullptr;
+  G.N = (int)N;
+  G.quad = o.quad;
+  G.omega = omega;
+  kr6_corrections(G.g);
+  if (o.quad == HBS_QUAD_KRESS) {
+    std::vector<double> R = kress_weights(N);
+    if (h->dkressR.reserve(sizeof(double) * N) != hipSuccess ||
+        hipMemcpy(h->dkressR.p, R.data(), sizeof(double) * N, hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("hbs_build: Kress table upload failed");
+      return fail(HBS_E_DEVICE);
+    }
+    G.kressR = h->dkressR.as<double>();
+  }
+  int rc = qps::build(h);
+  if (rc != HBS_OK) return fail(rc);
+  *out = h;
+  return HBS_OK;
+}
+
+static int apply_common(hbs_handle* h, const double* in, int64_t nrhs, double* outp, bool inverse, int refine) {
+  clear_error();
+  if (!h || !in || !outp || nrhs < 0) { set_error("hbs_apply: bad arguments"); return HBS_E_INVALID_ARG; }
+  if (nrhs == 0) return HBS_OK;
+  if (in == outp) { set_error("hbs_apply: rhs and out may not alias"); return HBS_E_INVALID_ARG; }
+  hipStream_t st = h->stream;
+  const int64_t N = h->N;
+  const size_t bytes = sizeof(cplx) * N * nrhs;
+  const cplx* B;
+  cplx* X;
+  DevBuf sb, sx;
+  if (h->opts.ptr_mode == HBS_PTR_HOST) {
+    if (!finite_all(in, 2 * N * nrhs)) { set_error("hbs_apply: non-finite right-hand side"); return HBS_E_NONFINITE; }
+    CKD(sb.reserve(bytes));
+    CKD(sx.reserve(bytes));
+    CKD(hipMemcpyAsync(sb.p, in, bytes, hipMemcpyHostToDevice, st));
+    B = sb.as<cplx>();
+    X = sx.as<cplx>();
+  } else {
+    B = reinterpret_cast<const cplx*>(in);
+    X = reinterpret_cast<cplx*>(outp);
+  }
+  int rc = qps::apply_factors(h, inverse, B, N, X, N, nrhs);
+  if (rc != HBS_OK) return rc;
+  if (inverse && refine > 0) {
+    // x <- x + A^{-1}(b - A x) with the compressed forward operator
+    DevBuf rb, zb;
+    CKD(rb.reserve(bytes));
+    CKD(zb.reserve(bytes));
+    for (int it = 0; it < refine; ++it) {
+      rc = qps::apply_factors(h, false, X, N, rb.as<cplx>(), N, nrhs);
+      if (rc != HBS_OK) return rc;
+      CKD(launch_axpby(N, (int)nrhs, mkc(1, 0), B, N, mkc(-1, 0), rb.as<cplx>(), N, st));
+      rc = qps::apply_factors(h, true, rb.as<cplx>(), N, zb.as<cplx>(), N, nrhs);
+      if (rc != HBS_OK) return rc;
+      CKD(launch_axpby(N, (int)nrhs, mkc(1, 0), zb.as<cplx>(), N, mkc(1, 0), X, N, st));
+    }
+  }
+  if (h->opts.ptr_mode == HBS_PTR_HOST) {
+    CKD(hipMemcpyAsync(outp, X, bytes, hipMemcpyDeviceToHost, st));
+  }
+  CKD(hipStreamSynchronize(st));
+  return HBS_OK;
+}
+
+int hbs_apply(hbs_handle* h, const double* rhs, int64_t nrhs, double* out, int32_t refine) {
+  return apply_common(h, rhs, nrhs, out, true, refine);
+}
+
+int hbs_forward(hbs_handle* h, const double* x, int64_t nrhs, double* out) {
+  return apply_common(h, x, nrhs, out, false, 0);
+}
+
+static int qp_common(hbs_handle* h, double period, const double* thetas, int64_t n, const qp_opts* opts, bool check,
+                     double are, double aim, double* eta, double* xi, double* bragg, int32_t* nlo, int32_t* nm, double* flux) {
+  clear_error();
+  if (!h || !thetas || !eta || n <= 0) { set_error("qp_solve: bad arguments"); return HBS_E_INVALID_ARG; }
+  qp_opts o;
+  qp_opts_init(&o);
+  if (opts) {
+    if (opts->struct_size != (int32_t)sizeof(qp_opts)) { set_error("qp_solve: opts->struct_size mismatch"); return HBS_E_INVALID_ARG; }
+    o = *opts;
+  }
+  if (!(period > 0) || !std::isfinite(period)) { set_error("qp_solve: period must be positive"); return HBS_E_INVALID_ARG; }
+  std::vector<double> th;
+  int r = fetch(thetas, n, h->opts.ptr_mode, th);
+  if (r != HBS_OK) return r;
+  for (double t : th) {
+    if (!std::isfinite(t)) { set_error("qp_solve: non-finite angle"); return HBS_E_NONFINITE; }
+    if (!(t > -M_PI && t < 0)) { set_error("qp_solve: angles must lie in (-pi, 0)"); return HBS_E_INVALID_ARG; }
+  }
+  if (check) {
+    for (double t : th) {
+      const double ph = h->omega * period * std::cos(t);
+      if (std::hypot(std::cos(ph) - are, std::sin(ph) - aim) > 1e-12) {
+        set_error("qp_solve: alpha does not match exp(i omega d cos theta)");
+        return HBS_E_ALPHA_MISMATCH;
+      }
+    }
+  }
+  const int M = qps::qp_contour_M(h, period, &o);
+  if (M <= 0) return HBS_E_INVALID_ARG;
+  const int maxm = qps::qp_max_modes_impl(h->omega, period);
+  hipStream_t st = h->stream;
+  const int64_t N = h->N;
+  DevBuf de, dx, db;
+  cplx *pe, *px = nullptr, *pb = nullptr;
+  const bool host = h->opts.ptr_mode == HBS_PTR_HOST;
+  if (host) {
+    CKD(de.reserve(sizeof(cplx) * N * n));
+    pe = de.as<cplx>();
+    if (xi) { CKD(dx.reserve(sizeof(cplx) * 2 * M * n)); px = dx.as<cplx>(); }
+    if (bragg) { CKD(db.reserve(sizeof(cplx) * 2 * maxm * n)); pb = db.as<cplx>(); }
+  } else {
+    pe = reinterpret_cast<cplx*>(eta);
+    px = reinterpret_cast<cplx*>(xi);
+    pb = reinterpret_cast<cplx*>(bragg);
+  }
+  r = qps::qp_solve_impl(h, period, th, &o, pe, px, pb, nlo, nm, flux);
+  if (r != HBS_OK) return r;
+  if (host) {
+    CKD(hipMemcpyAsync(eta, pe, sizeof(cplx) * N * n, hipMemcpyDeviceToHost, st));
+    if (xi) CKD(hipMemcpyAsync(xi, px, sizeof(cplx) * 2 * M * n, hipMemcpyDeviceToHost, st));
+    if (bragg) CKD(hipMemcpyAsync(bragg, pb, sizeof(cplx) * 2 * maxm * n, hipMemcpyDeviceToHost, st));
+  }
+  CKD(hipStreamSynchronize(st));
+  return HBS_OK;
+}
+
+int qp_solve(hbs_handle* h, double period, double alpha_re, double alpha_im, const double* thetas, int64_t q,
+             const qp_opts* opts, double* eta, double* xi, double* bragg, int32_t* nlo_out, int32_t* n_modes_out,
+             double* flux_err) {
+  return qp_common(h, period, thetas, q, opts, true, alpha_re, alpha_im, eta, xi, bragg, nlo_out, n_modes_out, flux_err);
+}
+
+int qp_solve_many(hbs_handle* h, double period, const double* thetas, int64_t n, const qp_opts* opts, double* eta,
+                  double* xi, double* bragg, int32_t* nlo_out, int32_t* n_modes_out, double* flux_err) {
+  return qp_common(h, period, thetas, n, opts, false, 0, 0, eta, xi, bragg, nlo_out, n_modes_out, flux_err);
+}
+
+int32_t qp_contour_size(const hbs_handle* h, double period, const qp_opts* opts) {
+  if (!h) return -1;
+  qp_opts o;
+  qp_opts_init(&o);
+  if (opts) o = *opts;
+  return qps::qp_contour_M(h, period, &o);
+}
+
+int32_t qp_max_modes(double omega, double period) { return qps::qp_max_modes_impl(omega, period); }
+
+int hbs_stats(const hbs_handle* h, hbs_stats_t* s) {
+  if (!h || !s) { set_error("hbs_stats: NULL"); return HBS_E_INVALID_ARG; }
+  *s = h->stats;
+  s->struct_size = sizeof(hbs_stats_t);
+  s->levels = h->L;
+  s->N = h->N;
+  s->root_size = h->nroot;
+  int mr = 0;
+  for (int l = 1; l <= h->L; ++l)
+    for (int k : h->lv[l].k) mr = std::max(mr, k);
+  s->max_rank = mr;
+  s->factor_bytes = h->factor_bytes;
+  s->build_seconds = h->build_seconds;
+  return HBS_OK;
+}
+
+void hbs_free(hbs_handle* h) { delete h; }
+
+int qps_hankel01(const double* x, int64_t n, double* out, int32_t ptr_mode) {
+  clear_error();
+  if (!x || !out || n < 0) { set_error("qps_hankel01: bad arguments"); return HBS_E_INVALID_ARG; }
+  if (n == 0) return HBS_OK;
+  if (ptr_mode == HBS_PTR_HOST) {
+    for (int64_t i = 0; i < n; ++i)
+      if (!(x[i] > 0) || !std::isfinite(x[i])) { set_error("qps_hankel01: x must be positive and finite"); return HBS_E_INVALID_ARG; }
+    DevBuf dx, dout;
+    CKD(dx.reserve(sizeof(double) * n));
+    CKD(dout.reserve(sizeof(cplx) * 2 * n));
+    CKD(hipMemcpy(dx.p, x, sizeof(double) * n, hipMemcpyHostToDevice));
+    CKD(launch_hankel(dx.as<double>(), n, dout.as<cplx>(), nullptr));
+    CKD(hipMemcpy(out, dout.p, sizeof(cplx) * 2 * n, hipMemcpyDeviceToHost));
+  } else {
+    CKD(launch_hankel(x, n, reinterpret_cast<cplx*>(out), nullptr));
+    CKD(hipDeviceSynchronize());
+  }
+  return HBS_OK;
+}
+
+int qps_kr6_corrections(double out[6]) {
+  if (!out) return HBS_E_INVALID_ARG;
+  kr6_corrections(out);
+  return HBS_OK;
+}
+
+int qps_matrix_entries(hbs_handle* h, const int32_t* rows, const int32_t* cols, int64_t n, double* out) {
+  clear_error();
+  if (!h || !rows || !cols || !out || n < 0) { set_error("qps_matrix_entries: bad arguments"); return HBS_E_INVALID_ARG; }
+  if (n == 0) return HBS_OK;
+  for (int64_t i = 0; i < n; ++i)
+    if (rows[i] < 0 || rows[i] >= h->N || cols[i] < 0 || cols[i] >= h->N) {
+      set_error("qps_matrix_entries: index out of range");
+      return HBS_E_INVALID_ARG;
+    }
+  DevBuf dr, dc, dout;
+  CKD(dr.reserve(sizeof(int) * n));
+  CKD(dc.reserve(sizeof(int) * n));
+  CKD(dout.reserve(sizeof(cplx) * n));
+  CKD(hipMemcpy(dr.p, rows, sizeof(int) * n, hipMemcpyHostToDevice));
+  CKD(hipMemcpy(dc.p, cols, sizeof(int) * n, hipMemcpyHostToDevice));
+  CKD(launch_entries(h->geo, dr.as<int>(), dc.as<int>(), n, dout.as<cplx>(), h->stream));
+  CKD(hipStreamSynchronize(h->stream));
+  CKD(hipMemcpy(out, dout.p, sizeof(cplx) * n, hipMemcpyDeviceToHost));
+  return HBS_OK;
+}
+
+int qps_zgemm(const double* A, const double* B, double* C, int32_t m, int32_t n, int32_t k, int32_t nbatch, int32_t transA,
+              int32_t accumulate, int32_t ptr_mode) {
+  clear_error();
+  if (!A || !B || !C || m <= 0 || n <= 0 || k < 0 || nbatch <= 0) { set_error("qps_zgemm: bad arguments"); return HBS_E_INVALID_ARG; }
+  const size_t sa = (size_t)m * k, sb = (size_t)k * n, sc = (size_t)m * n;
+  DevBuf da, dbb, dc, arena;
+  const cplx *pa, *pb;
+  cplx* pc;
+  if (ptr_mode == HBS_PTR_HOST) {
+    CKD(da.reserve(sizeof(cplx) * sa * nbatch + 16));
+    CKD(dbb.reserve(sizeof(cplx) * sb * nbatch + 16));
+    CKD(dc.reserve(sizeof(cplx) * sc * nbatch));
+    if (sa) CKD(hipMemcpy(da.p, A, sizeof(cplx) * sa * nbatch, hipMemcpyHostToDevice));
+    if (sb) CKD(hipMemcpy(dbb.p, B, sizeof(cplx) * sb * nbatch, hipMemcpyHostToDevice));
+    CKD(hipMemcpy(dc.p, C, sizeof(cplx) * sc * nbatch, hipMemcpyHostToDevice));
+    pa = da.as<cplx>(); pb = dbb.as<cplx>(); pc = dc.as<cplx>();
+  } else {
+    pa = reinterpret_cast<const cplx*>(A); pb = reinterpret_cast<const cplx*>(B); pc = reinterpret_cast<cplx*>(C);
+  }
+  std::vector<GemmDesc> v;
+  for (int b = 0; b < nbatch; ++b) {
+    GemmDesc g;
+    g.A = pa + sa * b; g.B = pb + sb * b; g.C = pc + sc * b;
+    g.m = m; g.n = n; g.k = k;
+    g.lda = transA ? k : m; g.ldb = k; g.ldc = m;
+    g.transA = transA; g.pad = 0;
+    g.alpha = mkc(1, 0);
+    g.beta = accumulate ? mkc(1, 0) : mkc(0, 0);
+    v.push_back(g);
+  }
+  CKD(gemm_batched(arena, v, nullptr));
+  CKD(hipDeviceSynchronize());
+  if (ptr_mode == HBS_PTR_HOST) CKD(hipMemcpy(C, pc, sizeof(cplx) * sc * nbatch, hipMemcpyDeviceToHost));
+  return HBS_OK;
+}
+
+int qps_zinv(double* A, int32_t n, int32_t nbatch, int32_t ptr_mode) {
+  clear_error();
+  if (!A || n <= 0 || nbatch <= 0) { set_error("qps_zinv: bad arguments"); return HBS_E_INVALID_ARG; }
+  const size_t sz = (size_t)n * n;
+  DevBuf da, arena, work;
+  cplx* pa;
+  if (ptr_mode == HBS_PTR_HOST) {
+    CKD(da.reserve(sizeof(cplx) * sz * nbatch));
+    CKD(hipMemcpy(da.p, A, sizeof(cplx) * sz * nbatch, hipMemcpyHostToDevice));
+    pa = da.as<cplx>();
+  } else {
+    pa = reinterpret_cast<cplx*>(A);
+  }
+  std::vector<InvDesc> v;
+  for (int b = 0; b < nbatch; ++b) v.push_back({pa + sz * b, n, n});
+  bool sing = false;
+  CKD(inv_batched(arena, work, v, nullptr, &sing));
+  if (ptr_mode == HBS_PTR_HOST) CKD(hipMemcpy(A, pa, sizeof(cplx) * sz * nbatch, hipMemcpyDeviceToHost));
+  if (sing) { set_error("qps_zinv: singular matrix"); return HBS_E_SINGULAR; }
+  return HBS_OK;
+}
+
+int qps_profile_enable(int32_t on) {
+  profile_enable(on != 0);
+  return HBS_OK;
+}
+
+int qps_profile_read(const char* family, double* ms, int64_t* launches, double* flops, double* bytes) {
+  if (!family || !ms || !launches || !flops || !bytes) return HBS_E_INVALID_ARG;
+  if (!profile_read(family, ms, launches, flops, bytes)) { set_error("qps_profile_read: event query failed"); return HBS_E_DEVICE; }
+  return HBS_OK;
+}
+
+}  // extern "C"

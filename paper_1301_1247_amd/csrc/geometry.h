@@ -1,0 +1,80 @@
+// Entries of the Nystrom matrix A = I/2 + D - i omega S (Sec. 2.2 below Eq. 2.15).
+#pragma once
+#include "hankel.h"
+#include "internal.h"
+
+#define QPS_PI 3.14159265358979323846264338327950288
+#define QPS_EULER 0.577215664901532860606512090082402431
+
+// Kernel K(x, y, n_y) = dG/dn_y - i omega G with G = (i/4) H0(omega |x - y|) (Eqs. 2.7-2.9):
+//   K = (i omega / 4) H1(omega r) n_y.(x - y)/r + (omega / 4) H0(omega r).
+__device__ inline cplx helm_kernel(double omega, double dx, double dy, double nx, double ny) {
+  const double r = sqrt(dx * dx + dy * dy);
+  cplx h0, h1;
+  hankel01(omega * r, h0, h1);
+  const double nd = (nx * dx + ny * dy) / r;
+  const double q = 0.25 * omega;
+  return mkc(q * (h0.x - h1.y * nd), q * (h0.y + h1.x * nd));
+}
+
+// Kapur-Rokhlin discretization (Sec. 2.3): A_ij = delta_ij/2 + R_{(i-j) mod N} K(y_i, y_j, n_j) w_j,
+// R_0 = 0, R_m = R_{N-m} = 1 + g_m (1 <= m <= 6), 1 otherwise.
+__device__ inline cplx a_entry_kr6(const Geo& G, int i, int j) {
+  if (i == j) return mkc(0.5, 0.0);
+  cplx K = helm_kernel(G.omega, G.x[i] - G.x[j], G.y[i] - G.y[j], G.nx[j], G.ny[j]);
+  int m = i - j;
+  if (m < 0) m += G.N;
+  double R = 1.0;
+  if (m <= 6) R += G.g[m - 1];
+  else if (m >= G.N - 6) R += G.g[G.N - m - 1];
+  return cscale(K, R * G.w[j]);
+}
+
+// Kress' spectral log-split discretization, N = 2n nodes (Colton & Kress, Sec. 3.5), with
+// speed s_j = N w_j / (2 pi) and z'(t_j) = s_j (-n_y, n_x):
+//   M = (i/4) H0 s_j,  L = (i omega/4) H1 s_j nd,  M1 = -J0 s_j / (4 pi),  L1 = -omega J1 s_j nd / (4 pi),
+//   M2 = M - M1 ln(4 sin^2((t_i - t_j)/2)), L2 = L - L1 ln(...), and on the diagonal
+//   M1 = -s/(4 pi), L1 = 0, M2 = [i/4 - C_E/(2 pi) - ln(omega s / 2)/(2 pi)] s, L2 = -kappa s / (4 pi);
+//   A_ij = delta_ij/2 + Rk_{(i-j)} (L1 - i omega M1) + (pi / n) (L2 - i omega M2).
+__device__ inline cplx a_entry_kress(const Geo& G, int i, int j) {
+  const int N = G.N;
+  const double pin = QPS_PI / (0.5 * N);
+  const double s = G.w[j] * N / (2.0 * QPS_PI);
+  int m = i - j;
+  if (m < 0) m += N;
+  const double Rk = G.kressR[m];
+  const double om = G.omega;
+  if (i == j) {
+    // -i om M1 = i om s/(4pi)
+    cplx t1 = mkc(0.0, om * s / (4.0 * QPS_PI));
+    double m2r = (-QPS_EULER / (2.0 * QPS_PI) - log(0.5 * om * s) / (2.0 * QPS_PI)) * s;
+    double m2i = 0.25 * s;
+    double l2 = -G.kap[j] * s / (4.0 * QPS_PI);
+    // L2 - i om M2 = (l2 + om m2i) - i om m2r
+    cplx t2 = mkc(l2 + om * m2i, -om * m2r);
+    return mkc(0.5 + Rk * t1.x + pin * t2.x, Rk * t1.y + pin * t2.y);
+  }
+  const double dx = G.x[i] - G.x[j], dy = G.y[i] - G.y[j];
+  const double r = sqrt(dx * dx + dy * dy);
+  cplx h0, h1;
+  hankel01(om * r, h0, h1);
+  const double nd = (G.nx[j] * dx + G.ny[j] * dy) / r;
+  // M = (i/4) h0 s ; L = (i om/4) h1 s nd
+  const cplx M = mkc(-0.25 * h0.y * s, 0.25 * h0.x * s);
+  const cplx L = mkc(-0.25 * om * h1.y * s * nd, 0.25 * om * h1.x * s * nd);
+  const double M1 = -h0.x * s / (4.0 * QPS_PI);
+  const double L1 = -om * h1.x * s * nd / (4.0 * QPS_PI);
+  const double t = 2.0 * QPS_PI * (double)m / (double)N;
+  const double sh = sin(0.5 * t);
+  const double lg = log(4.0 * sh * sh);
+  const cplx M2 = mkc(M.x - M1 * lg, M.y);
+  const cplx L2 = mkc(L.x - L1 * lg, L.y);
+  // R (L1 - i om M1) + (pi/n)(L2 - i om M2); M1, L1 real
+  const cplx a = mkc(Rk * L1, -Rk * om * M1);
+  const cplx b = mkc(L2.x + om * M2.y, L2.y - om * M2.x);
+  return mkc(a.x + pin * b.x, a.y + pin * b.y);
+}
+
+__device__ inline cplx a_entry(const Geo& G, int i, int j) {
+  return G.quad == HBS_QUAD_KRESS ? a_entry_kress(G, i, j) : a_entry_kr6(G, i, j);
+}

@@ -1,0 +1,540 @@
+// Recursive skeletonization (Sec. 4) of the Nystrom matrix on the GPU, and the application of
+// its telescoping factorizations.
+//
+// Tree: level l has 2^l boxes of contiguous node ranges (curve order); leaves at level L.
+// Per level, for every box (all boxes of a level batched into one launch per step):
+//   1. D = A(I, I) at the leaves, or [[Dh_a, A(J_a, J_b)], [A(J_b, J_a), Dh_b]] above (Eq. 4.8):
+//      the diagonal block of the reduced matrix on the active set I = J_a u J_b.
+//   2. W^T = [A(I, near)^T | A(near, I) | proxy columns] (Sec. 3.2 proxy idea applied per box),
+//      sketched to 2n+8 rows with a complex Rademacher matrix when longer.
+//   3. Interpolative decomposition (Def. 3.1) by column-pivoted QR: skeleton J, P = Pi [I; T^T].
+//   4. With U = V = P (one joint skeleton for rows and columns), Eqs. 4.4-4.7:
+//      Dh = (P^T D^{-1} P)^{-1}, E = D^{-1} P Dh, F^T = Dh P^T D^{-1}, G = D^{-1} - E P^T D^{-1}.
+// The root holds [[Dh_1, A(J_1, J_2)], [A(J_2, J_1), Dh_2]], inverted densely.
+// The forward operator of Eq. 4.8 uses the same skeletons: P, the leaf blocks A(I, I), the
+// sibling couplings and the root coupling.
+#include "hbs.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace qps {
+
+namespace {
+
+struct LaunchRec {
+  size_t off;
+  int cnt;
+  int max_tiles;
+  double flops;
+};
+
+int tiles_of(const GemmDesc& g) { return ((g.m + 63) / 64) * ((g.n + 63) / 64); }
+
+GemmDesc gd(const cplx* A, int lda, int transA, const cplx* B, int ldb, cplx* C, int ldc, int m, int n, int k,
+            cplx alpha = mkc(1, 0), cplx beta = mkc(0, 0)) {
+  GemmDesc g;
+  g.A = A; g.B = B; g.C = C;
+  g.m = m; g.n = n; g.k = k;
+  g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+  g.transA = transA; g.pad = 0;
+  g.alpha = alpha; g.beta = beta;
+  return g;
+}
+
+#define CK(expr)                                                                                  \
+  do {                                                                                            \
+    hipError_t _e = (expr);                                                                       \
+    if (_e != hipSuccess) {                                                                       \
+      set_error(std::string("hbs_build: ") + #expr + ": " + hipGetErrorString(_e));               \
+      return _e == hipErrorOutOfMemory ? HBS_E_OOM : HBS_E_DEVICE;                                \
+    }                                                                                             \
+  } while (0)
+
+template <class T>
+hipError_t up_sync(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+  hipError_t e = upload(b, v, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+}  // namespace
+
+int build(hbs_handle* h) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = h->stream;
+  const int64_t N = h->N;
+  const int leaf = h->opts.leaf_size;
+  int L = (int)std::ceil(std::log2((double)N / (double)leaf));
+  if (L < 1) L = 1;
+  while ((N >> L) < 2 && L > 1) --L;
+  h->L = L;
+  h->lv.clear();
+  h->lv.resize(L + 1);
+  const bool exact = h->opts.compress == HBS_COMPRESS_EXACT;
+  const double ratio = h->opts.proxy_ratio;
+  const int pmin = h->opts.proxy_min;
+  const double om = h->omega;
+
+  // box ranges and bounding circles of the original points
+  for (int l = 1; l <= L; ++l) {
+    Level& V = h->lv[l];
+    V.nb = 1 << l;
+    V.lo.resize(V.nb);
+    V.hi.resize(V.nb);
+    V.cx.resize(V.nb);
+    V.cy.resize(V.nb);
+    V.rad.resize(V.nb);
+    for (int b = 0; b < V.nb; ++b) {
+      int lo = (int)((int64_t)b * N / V.nb), hi = (int)((int64_t)(b + 1) * N / V.nb);
+      V.lo[b] = lo;
+      V.hi[b] = hi;
+      double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+      for (int i = lo; i < hi; ++i) {
+        x0 = std::min(x0, h->hx[i]); x1 = std::max(x1, h->hx[i]);
+        y0 = std::min(y0, h->hy[i]); y1 = std::max(y1, h->hy[i]);
+      }
+      double cx = 0.5 * (x0 + x1), cy = 0.5 * (y0 + y1), r = 0.0;
+      for (int i = lo; i < hi; ++i) r = std::max(r, std::hypot(h->hx[i] - cx, h->hy[i] - cy));
+      V.cx[b] = cx;
+      V.cy[b] = cy;
+      V.rad[b] = r;
+    }
+  }
+
+  DevBuf dnear, wt, zb, kout, tmpY, tmpZt;
+  DevBuf& arena = h->arena;
+  h->factor_bytes = 0;
+  std::memset(h->stats.ranks_per_level_max, 0, sizeof(h->stats.ranks_per_level_max));
+  std::memset(h->stats.ranks_per_level_mean, 0, sizeof(h->stats.ranks_per_level_mean));
+
+  for (int l = L; l >= 1; --l) {
+    Level& V = h->lv[l];
+    const int nb = V.nb;
+    V.n.assign(nb, 0);
+    V.aoff.assign(nb + 1, 0);
+    if (l == L) {
+      for (int b = 0; b < nb; ++b) V.n[b] = V.hi[b] - V.lo[b];
+      V.hact.resize(N);
+      for (int64_t i = 0; i < N; ++i) V.hact[i] = (int)i;
+    } else {
+      Level& C = h->lv[l + 1];
+      for (int b = 0; b < nb; ++b) V.n[b] = C.k[2 * b] + C.k[2 * b + 1];
+      V.hact = C.hskel;
+    }
+    for (int b = 0; b < nb; ++b) V.aoff[b + 1] = V.aoff[b] + V.n[b];
+    V.ntot = V.aoff[nb];
+    for (int b = 0; b < nb; ++b)
+      if (V.n[b] > 2048) {
+        set_error("hbs_build: a box's active set exceeds 2048 points (raise tol or the leaf count)");
+        return HBS_E_INVALID_ARG;
+      }
+    CK(V.act.reserve(sizeof(int) * V.ntot));
+    CK(hipMemcpyAsync(V.act.p, V.hact.data(), sizeof(int) * V.ntot, hipMemcpyHostToDevice, st));
+    const int* dact = V.act.as<int>();
+
+    // ---- diagonal blocks D (into G, inverted in place later) and forward blocks Df
+    V.oG.assign(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) V.oG[b + 1] = V.oG[b] + (int64_t)V.n[b] * V.n[b];
+    CK(V.G.reserve(sizeof(cplx) * V.oG[nb]));
+    CK(V.Df.reserve(sizeof(cplx) * V.oG[nb]));
+    cplx* dG = V.G.as<cplx>();
+    cplx* dDf = V.Df.as<cplx>();
+    {
+      std::vector<BlockDesc> bd;
+      std::vector<CopyDesc> cz, cp, cd;
+      int maxe = 0;
+      for (int b = 0; b < nb; ++b) {
+        const int n = V.n[b];
+        maxe = std::max(maxe, n * n);
+        if (l == L) {
+          bd.push_back({dact + V.aoff[b], dact + V.aoff[b], dG + V.oG[b], n, n, n, 0});
+          cp.push_back({dG + V.oG[b], dDf + V.oG[b], n, n, n, n});
+        } else {
+          Level& C = h->lv[l + 1];
+          const int a = 2 * b, c = 2 * b + 1;
+          const int ka = C.k[a], kc = C.k[c];
+          const int* sa = C.skel.as<int>() + C.soff[a];
+          const int* sc = C.skel.as<int>() + C.soff[c];
+          cz.push_back({nullptr, dDf + V.oG[b], n, n, n, n});
+          bd.push_back({sa, sc, dDf + V.oG[b] + (int64_t)ka * n, ka, kc, n, 0});
+          bd.push_back({sc, sa, dDf + V.oG[b] + ka, kc, ka, n, 0});
+          cp.push_back({dDf + V.oG[b], dG + V.oG[b], n, n, n, n});
+          cd.push_back({C.Dh.as<cplx>() + C.oDh[a], dG + V.oG[b], ka, ka, ka, n});
+          cd.push_back({C.Dh.as<cplx>() + C.oDh[c], dG + V.oG[b] + (int64_t)ka * n + ka, kc, kc, kc, n});
+        }
+      }
+      if (!cz.empty()) {
+        CK(up_sync(arena, cz, st));
+        CK(launch_copy(arena.as<CopyDesc>(), (int)cz.size(), maxe, st));
+      }
+      {
+        int maxb = 0;
+        for (auto& d : bd) maxb = std::max(maxb, d.nr * d.nc);
+        CK(up_sync(arena, bd, st));
+        ProfScope ps("assemble", st, 0.0, 0.0);
+        CK(launch_eval_blocks(h->geo, arena.as<BlockDesc>(), (int)bd.size(), maxb, st));
+      }
+      CK(up_sync(arena, cp, st));
+      CK(launch_copy(arena.as<CopyDesc>(), (int)cp.size(), maxe, st));
+      if (!cd.empty()) {
+        int maxc = 0;
+        for (auto& d : cd) maxc = std::max(maxc, d.nr * d.nc);
+        CK(up_sync(arena, cd, st));
+        CK(launch_copy(arena.as<CopyDesc>(), (int)cd.size(), maxc, st));
+      }
+    }
+
+    // ---- compression matrices
+    std::vector<int> nnear(nb), np(nb), m(nb), s(nb);
+    std::vector<int64_t> noff(nb + 1, 0), woff(nb + 1, 0), zoff(nb + 1, 0);
+    std::vector<int> hnear;
+    for (int b = 0; b < nb; ++b) {
+      const double Rp = ratio * V.rad[b];
+      int cnt = 0, total_other = 0;
+      const size_t start = hnear.size();
+      for (int c = 0; c < nb; ++c) {
+        if (c == b) continue;
+        total_other += V.n[c];
+        const int dd = ((c - b) % nb + nb) % nb;
+        const bool adj = (dd == 1 || dd == nb - 1);
+        const bool nr = exact || adj || std::hypot(V.cx[c] - V.cx[b], V.cy[c] - V.cy[b]) < Rp + V.rad[c];
+        if (nr) {
+          for (int i = 0; i < V.n[c]; ++i) hnear.push_back(V.hact[V.aoff[c] + i]);
+          cnt += V.n[c];
+        }
+      }
+      (void)start;
+      nnear[b] = cnt;
+      const bool full = (cnt == total_other);
+      np[b] = full ? 0 : std::max(pmin, (int)std::ceil(1.5 * om * Rp) + 50);
+      m[b] = 2 * cnt + 3 * np[b];
+      s[b] = (m[b] > 2 * V.n[b] + 8) ? 2 * V.n[b] + 8 : m[b];
+      noff[b + 1] = noff[b] + cnt;
+      woff[b + 1] = woff[b] + (int64_t)m[b] * V.n[b];
+      zoff[b + 1] = zoff[b] + ((s[b] < m[b]) ? (int64_t)s[b] * V.n[b] : 0);
+    }
+    CK(dnear.reserve(sizeof(int) * std::max<int64_t>(1, noff[nb])));
+    if (noff[nb] > 0)
+      CK(hipMemcpyAsync(dnear.p, hnear.data(), sizeof(int) * noff[nb], hipMemcpyHostToDevice, st));
+    CK(wt.reserve(sizeof(cplx) * std::max<int64_t>(1, woff[nb])));
+    CK(zb.reserve(sizeof(cplx) * std::max<int64_t>(1, zoff[nb])));
+    cplx* dwt = wt.as<cplx>();
+    cplx* dz = zb.as<cplx>();
+    const int* dn = dnear.as<int>();
+    {
+      std::vector<BlockDesc> bd;
+      int maxb = 0;
+      for (int b = 0; b < nb; ++b) {
+        if (nnear[b] == 0) continue;
+        const int n = V.n[b];
+        bd.push_back({dn + noff[b], dact + V.aoff[b], dwt + woff[b], nnear[b], n, m[b], 1});
+        bd.push_back({dn + noff[b], dact + V.aoff[b], dwt + woff[b] + nnear[b], nnear[b], n, m[b], 0});
+        maxb = std::max(maxb, nnear[b] * n);
+      }
+      if (!bd.empty()) {
+        CK(up_sync(arena, bd, st));
+        ProfScope ps("assemble", st, 0.0, 0.0);
+        CK(launch_eval_blocks(h->geo, arena.as<BlockDesc>(), (int)bd.size(), maxb, st));
+      }
+      std::vector<ProxyDesc> pd;
+      int maxp = 0;
+      for (int b = 0; b < nb; ++b) {
+        if (np[b] == 0) continue;
+        pd.push_back({dact + V.aoff[b], dwt + woff[b], V.n[b], m[b], 2 * nnear[b], np[b], V.cx[b], V.cy[b],
+                      ratio * V.rad[b]});
+        maxp = std::max(maxp, np[b] * V.n[b]);
+      }
+      if (!pd.empty()) {
+        CK(up_sync(arena, pd, st));
+        ProfScope ps("assemble", st, 0.0, 0.0);
+        CK(launch_proxy(h->geo, arena.as<ProxyDesc>(), (int)pd.size(), maxp, st));
+      }
+      std::vector<SketchDesc> sd;
+      int maxs = 0, maxn = 0;
+      for (int b = 0; b < nb; ++b) {
+        if (s[b] >= m[b]) continue;
+        sd.push_back({dwt + woff[b], dz + zoff[b], m[b], V.n[b], s[b], b + (l << 24)});
+        maxs = std::max(maxs, s[b]);
+        maxn = std::max(maxn, V.n[b]);
+      }
+      if (!sd.empty()) {
+        double fl = 0;
+        for (auto& x : sd) fl += 8.0 * x.s * (double)x.m * x.n;
+        CK(up_sync(arena, sd, st));
+        ProfScope ps("sketch", st, fl, 0.0);
+        CK(launch_sketch(arena.as<SketchDesc>(), (int)sd.size(), maxs, maxn, h->opts.seed, st));
+      }
+    }
+    // ---- interpolative decompositions
+    std::vector<int> hperm(V.ntot);
+    DevBuf dperm;
+    CK(dperm.reserve(sizeof(int) * V.ntot));
+    CK(kout.reserve(sizeof(int) * nb));
+    std::vector<cplx*> zptr(nb);
+    {
+      std::vector<CpqrDesc> qd;
+      double fl = 0;
+      for (int b = 0; b < nb; ++b) {
+        zptr[b] = (s[b] < m[b]) ? dz + zoff[b] : dwt + woff[b];
+        qd.push_back({zptr[b], dperm.as<int>() + V.aoff[b], s[b], V.n[b]});
+        fl += 8.0 * 2.0 * s[b] * (double)V.n[b] * V.n[b];
+      }
+      CK(up_sync(arena, qd, st));
+      ProfScope ps("cpqr", st, fl, 0.0);
+      CK(launch_cpqr(arena.as<CpqrDesc>(), nb, h->tol, kout.as<int>(), st));
+    }
+    V.k.assign(nb, 0);
+    CK(hipMemcpyAsync(V.k.data(), kout.p, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(hperm.data(), dperm.p, sizeof(int) * V.ntot, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    V.soff.assign(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) V.soff[b + 1] = V.soff[b] + V.k[b];
+    V.ktot = V.soff[nb];
+    V.hskel.resize(V.ktot);
+    int kmax = 0;
+    double ksum = 0;
+    for (int b = 0; b < nb; ++b) {
+      for (int j = 0; j < V.k[b]; ++j) V.hskel[V.soff[b] + j] = V.hact[V.aoff[b] + hperm[V.aoff[b] + j]];
+      kmax = std::max(kmax, V.k[b]);
+      ksum += V.k[b];
+    }
+    if (l < 32) {
+      h->stats.ranks_per_level_max[l] = kmax;
+      h->stats.ranks_per_level_mean[l] = ksum / nb;
+    }
+    CK(V.skel.reserve(sizeof(int) * std::max<int64_t>(1, V.ktot)));
+    CK(hipMemcpyAsync(V.skel.p, V.hskel.data(), sizeof(int) * V.ktot, hipMemcpyHostToDevice, st));
+
+    // ---- factors
+    V.oP.assign(nb + 1, 0);
+    V.oDh.assign(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) {
+      V.oP[b + 1] = V.oP[b] + (int64_t)V.n[b] * V.k[b];
+      V.oDh[b + 1] = V.oDh[b] + (int64_t)V.k[b] * V.k[b];
+    }
+    V.oE = V.oP;
+    V.oFt = V.oP;
+    CK(V.P.reserve(sizeof(cplx) * V.oP[nb]));
+    CK(V.E.reserve(sizeof(cplx) * V.oP[nb]));
+    CK(V.Ft.reserve(sizeof(cplx) * V.oP[nb]));
+    CK(V.Dh.reserve(sizeof(cplx) * V.oDh[nb]));
+    CK(tmpY.reserve(sizeof(cplx) * V.oP[nb]));
+    CK(tmpZt.reserve(sizeof(cplx) * V.oP[nb]));
+    cplx* dP = V.P.as<cplx>();
+    {
+      std::vector<PDesc> pd;
+      int maxe = 0;
+      for (int b = 0; b < nb; ++b) {
+        pd.push_back({zptr[b], dperm.as<int>() + V.aoff[b], dP + V.oP[b], V.n[b], V.k[b], s[b]});
+        maxe = std::max(maxe, V.n[b] * V.k[b]);
+      }
+      CK(up_sync(arena, pd, st));
+      CK(launch_buildP(arena.as<PDesc>(), nb, maxe, st));
+    }
+    bool sing = false;
+    {
+      std::vector<InvDesc> iv;
+      for (int b = 0; b < nb; ++b) iv.push_back({dG + V.oG[b], V.n[b], V.n[b]});
+      CK(inv_batched(arena, h->work, iv, st, &sing));
+      if (sing) {
+        set_error("hbs_build: singular diagonal block at level " + std::to_string(l));
+        return HBS_E_SINGULAR;
+      }
+    }
+    cplx* Y = tmpY.as<cplx>();
+    cplx* Zt = tmpZt.as<cplx>();
+    cplx* Dh = V.Dh.as<cplx>();
+    cplx* E = V.E.as<cplx>();
+    cplx* Ft = V.Ft.as<cplx>();
+    {
+      std::vector<GemmDesc> g1, g2;
+      for (int b = 0; b < nb; ++b) {
+        const int n = V.n[b], k = V.k[b];
+        const cplx* Di = dG + V.oG[b];
+        // Y = D^{-1} P  (n x k)
+        g1.push_back(gd(Di, n, 0, dP + V.oP[b], n, Y + V.oP[b], n, n, k, n));
+        // Zt = P^T D^{-1}  (k x n)
+        g1.push_back(gd(dP + V.oP[b], n, 1, Di, n, Zt + V.oP[b], k, k, n, n));
+      }
+      CK(gemm_batched(arena, g1, st));
+      CK(hipStreamSynchronize(st));
+      for (int b = 0; b < nb; ++b) {
+        const int n = V.n[b], k = V.k[b];
+        // S = Zt P (k x k) -> Dh
+        g2.push_back(gd(Zt + V.oP[b], k, 0, dP + V.oP[b], n, Dh + V.oDh[b], k, k, k, n));
+      }
+      CK(gemm_batched(arena, g2, st));
+      CK(hipStreamSynchronize(st));
+      std::vector<InvDesc> iv;
+      for (int b = 0; b < nb; ++b) iv.push_back({Dh + V.oDh[b], V.k[b], V.k[b]});
+      CK(inv_batched(arena, h->work, iv, st, &sing));
+      if (sing) {
+        set_error("hbs_build: singular reduced block at level " + std::to_string(l));
+        return HBS_E_SINGULAR;
+      }
+      std::vector<GemmDesc> g3, g4;
+      for (int b = 0; b < nb; ++b) {
+        const int n = V.n[b], k = V.k[b];
+        // E = Y Dh (n x k); Ft = Dh Zt (k x n)
+        g3.push_back(gd(Y + V.oP[b], n, 0, Dh + V.oDh[b], k, E + V.oP[b], n, n, k, k));
+        g3.push_back(gd(Dh + V.oDh[b], k, 0, Zt + V.oP[b], k, Ft + V.oP[b], k, k, n, k));
+      }
+      CK(gemm_batched(arena, g3, st));
+      CK(hipStreamSynchronize(st));
+      for (int b = 0; b < nb; ++b) {
+        const int n = V.n[b], k = V.k[b];
+        // G = D^{-1} - E Zt  (in place)
+        g4.push_back(gd(E + V.oP[b], n, 0, Zt + V.oP[b], k, dG + V.oG[b], n, n, n, k, mkc(-1, 0), mkc(1, 0)));
+      }
+      CK(gemm_batched(arena, g4, st));
+      CK(hipStreamSynchronize(st));
+    }
+    if (l < L) h->lv[l + 1].Dh.release();
+    h->factor_bytes += (int64_t)sizeof(cplx) * (3 * V.oP[nb] + 2 * V.oG[nb]);
+  }
+
+  // ---- root
+  {
+    Level& V = h->lv[1];
+    const int ka = V.k[0], kc = V.k[1];
+    const int n = ka + kc;
+    h->nroot = n;
+    CK(h->Rfwd.reserve(sizeof(cplx) * n * n));
+    CK(h->Rinv.reserve(sizeof(cplx) * n * n));
+    cplx* Rf = h->Rfwd.as<cplx>();
+    cplx* Ri = h->Rinv.as<cplx>();
+    const int* sa = V.skel.as<int>();
+    const int* sc = V.skel.as<int>() + V.soff[1];
+    std::vector<CopyDesc> cz = {{nullptr, Rf, n, n, n, n}};
+    CK(up_sync(arena, cz, st));
+    CK(launch_copy(arena.as<CopyDesc>(), 1, n * n, st));
+    std::vector<BlockDesc> bd = {{sa, sc, Rf + (int64_t)ka * n, ka, kc, n, 0}, {sc, sa, Rf + ka, kc, ka, n, 0}};
+    CK(up_sync(arena, bd, st));
+    CK(launch_eval_blocks(h->geo, arena.as<BlockDesc>(), 2, std::max(ka * kc, 1), st));
+    std::vector<CopyDesc> cp = {{Rf, Ri, n, n, n, n}};
+    CK(up_sync(arena, cp, st));
+    CK(launch_copy(arena.as<CopyDesc>(), 1, n * n, st));
+    std::vector<CopyDesc> cd = {{V.Dh.as<cplx>() + V.oDh[0], Ri, ka, ka, ka, n},
+                                {V.Dh.as<cplx>() + V.oDh[1], Ri + (int64_t)ka * n + ka, kc, kc, kc, n}};
+    CK(up_sync(arena, cd, st));
+    CK(launch_copy(arena.as<CopyDesc>(), 2, std::max(ka * ka, kc * kc), st));
+    bool sing = false;
+    std::vector<InvDesc> iv = {{Ri, n, n}};
+    CK(inv_batched(arena, h->work, iv, st, &sing));
+    if (sing) {
+      set_error("hbs_build: singular root matrix");
+      return HBS_E_SINGULAR;
+    }
+    V.Dh.release();
+    h->factor_bytes += (int64_t)sizeof(cplx) * 2 * n * n;
+  }
+  CK(hipStreamSynchronize(st));
+  h->work.release();
+  auto t1 = std::chrono::steady_clock::now();
+  h->build_seconds = std::chrono::duration<double>(t1 - t0).count();
+  return HBS_OK;
+}
+
+#undef CK
+#define CK(expr)                                                                                  \
+  do {                                                                                            \
+    hipError_t _e = (expr);                                                                       \
+    if (_e != hipSuccess) {                                                                       \
+      set_error(std::string("hbs apply: ") + #expr + ": " + hipGetErrorString(_e));               \
+      return _e == hipErrorOutOfMemory ? HBS_E_OOM : HBS_E_DEVICE;                                \
+    }                                                                                             \
+  } while (0)
+
+int apply_factors(hbs_handle* h, bool inv, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r) {
+  if (r <= 0) return HBS_OK;
+  hipStream_t st = h->stream;
+  const int L = h->L;
+  auto& lv = h->lv;
+  // workspace: up[l] (l = 0..L-1) holds lv[l+1].ktot rows; x ping-pong of max ntot (l < L); root result
+  std::vector<int64_t> upoff(L + 1, 0);
+  for (int l = 0; l < L; ++l) upoff[l + 1] = upoff[l] + lv[l + 1].ktot * r;
+  int64_t xmax = 1;
+  for (int l = 1; l < L; ++l) xmax = std::max<int64_t>(xmax, lv[l].ntot);
+  CK(h->ab_up.reserve(sizeof(cplx) * std::max<int64_t>(1, upoff[L])));
+  CK(h->ab_x0.reserve(sizeof(cplx) * xmax * r));
+  CK(h->ab_x1.reserve(sizeof(cplx) * xmax * r));
+  CK(h->ab_root.reserve(sizeof(cplx) * h->nroot * r));
+  cplx* up = h->ab_up.as<cplx>();
+  cplx* xr = h->ab_root.as<cplx>();
+  auto upbuf = [&](int l) { return up + upoff[l]; };  // rows lv[l+1].ktot = lv[l].ntot
+  auto xbuf = [&](int l) { return (l & 1) ? h->ab_x1.as<cplx>() : h->ab_x0.as<cplx>(); };
+  const int rr = (int)r;
+
+  std::vector<GemmDesc> all;
+  std::vector<LaunchRec> recs;
+  auto close = [&](size_t start) {
+    LaunchRec rec{start, (int)(all.size() - start), 0, 0.0};
+    for (size_t i = start; i < all.size(); ++i) {
+      rec.max_tiles = std::max(rec.max_tiles, tiles_of(all[i]));
+      rec.flops += 8.0 * all[i].m * (double)all[i].n * all[i].k;
+    }
+    if (rec.cnt > 0) recs.push_back(rec);
+  };
+  // upward pass
+  for (int l = L; l >= 1; --l) {
+    Level& V = lv[l];
+    const cplx* src = (l == L) ? B : upbuf(l);
+    const int64_t lds = (l == L) ? ldb : V.ntot;
+    cplx* dst = upbuf(l - 1);
+    const int ldd = (int)V.ktot;
+    size_t st0 = all.size();
+    for (int b = 0; b < V.nb; ++b) {
+      const int n = V.n[b], k = V.k[b];
+      if (inv)
+        all.push_back(gd(V.Ft.as<cplx>() + V.oFt[b], k, 0, src + V.aoff[b], (int)lds, dst + V.soff[b], ldd, k, rr, n));
+      else
+        all.push_back(gd(V.P.as<cplx>() + V.oP[b], n, 1, src + V.aoff[b], (int)lds, dst + V.soff[b], ldd, k, rr, n));
+    }
+    close(st0);
+  }
+  {
+    size_t st0 = all.size();
+    const cplx* R = inv ? h->Rinv.as<cplx>() : h->Rfwd.as<cplx>();
+    all.push_back(gd(R, h->nroot, 0, upbuf(0), h->nroot, xr, h->nroot, h->nroot, rr, h->nroot));
+    close(st0);
+  }
+  for (int l = 1; l <= L; ++l) {
+    Level& V = lv[l];
+    const cplx* xin = (l == 1) ? xr : xbuf(l - 1);
+    const int ldxin = (int)V.ktot;
+    cplx* out = (l == L) ? X : xbuf(l);
+    const int64_t ldo = (l == L) ? ldx : V.ntot;
+    const cplx* src = (l == L) ? B : upbuf(l);
+    const int64_t lds = (l == L) ? ldb : V.ntot;
+    size_t st0 = all.size();
+    for (int b = 0; b < V.nb; ++b) {
+      const int n = V.n[b], k = V.k[b];
+      const cplx* Dn = inv ? V.E.as<cplx>() + V.oE[b] : V.P.as<cplx>() + V.oP[b];
+      all.push_back(gd(Dn, n, 0, xin + V.soff[b], ldxin, out + V.aoff[b], (int)ldo, n, rr, k));
+    }
+    close(st0);
+    st0 = all.size();
+    for (int b = 0; b < V.nb; ++b) {
+      const int n = V.n[b];
+      const cplx* Dg = inv ? V.G.as<cplx>() + V.oG[b] : V.Df.as<cplx>() + V.oG[b];
+      all.push_back(gd(Dg, n, 0, src + V.aoff[b], (int)lds, out + V.aoff[b], (int)ldo, n, rr, n, mkc(1, 0), mkc(1, 0)));
+    }
+    close(st0);
+  }
+  CK(upload(h->arena, all, st));
+  const GemmDesc* dd = h->arena.as<GemmDesc>();
+  double fl = 0;
+  for (auto& rc : recs) fl += rc.flops;
+  ProfScope ps("apply", st, fl, 0.0);
+  for (auto& rc : recs) {
+    ProfScope ps2("zgemm", st, rc.flops, 0.0);
+    CK(launch_zgemm(dd + rc.off, rc.cnt, rc.max_tiles, st));
+  }
+  CK(hipStreamSynchronize(st));
+  return HBS_OK;
+}
+
+}  // namespace qps

@@ -1,0 +1,55 @@
+// The solver handle: geometry, tree, per-level skeletonization factors, periodizing cache.
+#pragma once
+#include "internal.h"
+
+#include <memory>
+#include <vector>
+
+namespace qps {
+
+struct Level {
+  int nb = 0;
+  std::vector<int> n, k;
+  std::vector<int64_t> aoff, soff;  // offsets of active / skeleton lists (prefix sums of n / k)
+  int64_t ntot = 0, ktot = 0;
+  std::vector<int> hact, hskel;     // host copies of the index lists (global node indices)
+  DevBuf act, skel;
+  // factors (element offsets into the buffers, per box)
+  DevBuf P, E, Ft, G, Df, Dh;
+  std::vector<int64_t> oP, oE, oFt, oG, oDh;
+  // bounding circles of the boxes' original points
+  std::vector<double> cx, cy, rad;
+  std::vector<int> lo, hi;          // original index range
+};
+
+}  // namespace qps
+
+struct hbs_handle {
+  int64_t N = 0;
+  double omega = 0, tol = 0;
+  hbs_opts opts{};
+  hipStream_t stream = nullptr;
+  int L = 0;
+  std::vector<double> hx, hy, hnx, hny, hw, hkap;
+  qps::DevBuf dgeo, dkressR;
+  Geo geo{};
+  std::vector<qps::Level> lv;  // lv[1..L]
+  int nroot = 0;
+  qps::DevBuf Rinv, Rfwd;
+  qps::DevBuf arena, work, scratch;
+  qps::DevBuf ab_up, ab_x0, ab_x1, ab_root;  // apply workspaces
+  hbs_stats_t stats{};
+  int64_t factor_bytes = 0;
+  double build_seconds = 0;
+};
+
+namespace qps {
+// apply the telescoping factorization: inverse (F^T, E, G, root inverse) or forward (P^T, P, D, root coupling)
+int apply_factors(hbs_handle* h, bool inverse, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r);
+int build(hbs_handle* h);
+int qp_max_modes_impl(double om, double period);
+struct QPPlan;
+int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, const qp_opts* o, cplx* eta_out,
+                  cplx* xi_out, cplx* bragg_out, int32_t* nlo_out, int32_t* nm_out, double* flux_out);
+int qp_contour_M(const hbs_handle* h, double period, const qp_opts* o);
+}  // namespace qps

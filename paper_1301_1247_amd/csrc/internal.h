@@ -1,0 +1,134 @@
+// Host-side declarations shared by the library's translation units: device-side
+// descriptor structs and kernel launchers.
+#pragma once
+#include "qps_common.h"
+#include "../../include/qpscatter.h"
+#include <vector>
+
+// Geometry of the discretized curve (structure of arrays, device pointers) and the
+// quadrature data needed to evaluate entries of A = I/2 + D - i omega S.
+struct Geo {
+  const double *x, *y, *nx, *ny, *w;
+  const double* kap;     // Kress: signed curvature
+  const double* kressR;  // Kress: log weights indexed by (i - j) mod N
+  int N;
+  int quad;
+  double omega;
+  double g[6];           // Kapur-Rokhlin corrections, R_m = 1 + g_m
+};
+
+// A batch entry of the block evaluator: out[r + c*ld] = A(rows[r], cols[c]), or
+// A(cols[c], rows[r]) when trans != 0.  Index lists hold global node indices.
+struct BlockDesc {
+  const int* rows;
+  const int* cols;
+  cplx* out;
+  int nr, nc, ld, trans;
+};
+
+// Proxy part of the compression matrix of one box: rows [row0, row0 + 3 np) of W^T
+// (m x n, ld = m) for the n active points `act`.
+struct ProxyDesc {
+  const int* act;
+  cplx* wt;
+  int n, m, row0, np;
+  double cx, cy, R;
+};
+
+// Sketch Z (s x n, ld s) = Omega (s x m) * W^T (m x n, ld m), Omega complex Rademacher.
+struct SketchDesc {
+  const cplx* wt;
+  cplx* z;
+  int m, n, s, box;
+};
+
+// Column-pivoted QR of Z (s x n, ld s) in place: on exit perm[0:n] holds the column order,
+// the leading k x k block the triangular factor and Z[0:k, k:n] the interpolation matrix
+// T = R11^{-1} R12.
+struct CpqrDesc {
+  cplx* z;
+  int* perm;
+  int s, n;
+};
+
+// Batched GEMM entry: C = alpha * op(A) * B + beta * C, op(A) = A (m x k) or A^T (A is k x m).
+struct GemmDesc {
+  const cplx* A;
+  const cplx* B;
+  cplx* C;
+  int m, n, k, lda, ldb, ldc, transA, pad;
+  cplx alpha, beta;
+};
+
+// Square matrix to be inverted in place.
+struct InvDesc {
+  cplx* a;
+  int n, ld;
+};
+
+// Interpolation matrix P (n x k, ld n) from the pivots and T = Z[0:k, k:n] (ld s).
+struct PDesc {
+  const cplx* z;
+  const int* perm;
+  cplx* P;
+  int n, k, s;
+};
+
+// Sub-matrix copy dst[r + c*ldd] = src[r + c*lds] (nr x nc), or zero-fill when src == nullptr.
+struct CopyDesc {
+  const cplx* src;
+  cplx* dst;
+  int nr, nc, lds, ldd;
+};
+
+namespace qps {
+
+// device buffer that grows on demand
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t reserve(size_t b);
+  void release();
+  ~DevBuf() { release(); }
+  template <class T> T* as() { return static_cast<T*>(p); }
+};
+
+// upload a descriptor array into a growing device arena
+template <class T>
+hipError_t upload(DevBuf& buf, const std::vector<T>& v, hipStream_t s) {
+  size_t b = v.size() * sizeof(T);
+  if (b == 0) return hipSuccess;
+  hipError_t e = buf.reserve(b);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(buf.p, v.data(), b, hipMemcpyHostToDevice, s);
+}
+
+// profiling of kernel families with HIP events
+struct ProfScope {
+  const char* fam;
+  hipStream_t s;
+  double flops, bytes;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ProfScope(const char* fam, hipStream_t s, double flops, double bytes);
+  ~ProfScope();
+};
+
+// launchers (device code in kernels_build.hip / gemm.hip / kernels_qp.hip)
+hipError_t launch_eval_blocks(const Geo& g, const BlockDesc* d, int nd, int max_elems, hipStream_t s);
+hipError_t launch_proxy(const Geo& g, const ProxyDesc* d, int nd, int max_elems, hipStream_t s);
+hipError_t launch_sketch(const SketchDesc* d, int nd, int max_s, int max_n, uint64_t seed, hipStream_t s);
+hipError_t launch_cpqr(const CpqrDesc* d, int nd, double tol, int* k_out, hipStream_t s);
+hipError_t launch_buildP(const PDesc* d, int nd, int max_elems, hipStream_t s);
+hipError_t launch_copy(const CopyDesc* d, int nd, int max_elems, hipStream_t s);
+hipError_t launch_gather_idx(const int* src, const int* idx, int* dst, int64_t n, hipStream_t s);
+hipError_t launch_zgemm(const GemmDesc* d, int nd, int max_tiles, hipStream_t s);
+// blocked Gauss-Jordan inversion; tbuf: nd * 32 * max_n complex; ipiv: nd * max_n ints; info: nd ints
+hipError_t launch_zinv(const InvDesc* d, int nd, int max_n, cplx* tbuf, int* ipiv, int* info, hipStream_t s);
+hipError_t launch_hankel(const double* x, int64_t n, cplx* out, hipStream_t s);
+hipError_t launch_entries(const Geo& g, const int* rows, const int* cols, int64_t n, cplx* out, hipStream_t s);
+
+// gemm helper: build descriptors on the host, upload, launch
+hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDesc>& v, hipStream_t s);
+hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDesc>& v, hipStream_t s, bool* singular);
+
+}  // namespace qps

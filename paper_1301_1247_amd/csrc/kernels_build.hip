@@ -1,0 +1,505 @@
+// Device kernels of the recursive-skeletonization build (Sec. 4): block assembly of the
+// Nystrom matrix, proxy-circle compression matrices (Sec. 3.2), sketching, column-pivoted QR
+// interpolative decomposition (Def. 3.1), and batched Gauss-Jordan inversion.
+#include "geometry.h"
+
+namespace {
+
+constexpr int NT = 256;  // threads per workgroup (4 wavefronts)
+
+// ---------------------------------------------------------------- block evaluation
+__global__ __launch_bounds__(NT) void k_eval_blocks(Geo G, const BlockDesc* __restrict__ descs) {
+  const BlockDesc d = descs[blockIdx.y];
+  const int total = d.nr * d.nc;
+  for (int e = blockIdx.x * NT + threadIdx.x; e < total; e += gridDim.x * NT) {
+    const int r = e % d.nr, c = e / d.nr;
+    const int gr = d.rows[r], gc = d.cols[c];
+    d.out[r + (size_t)c * d.ld] = d.trans ? a_entry(G, gc, gr) : a_entry(G, gr, gc);
+  }
+}
+
+// Proxy rows of W^T for one box.  For proxy p_l = c + R (cos th_l, sin th_l) with outward
+// normal nu_l and active point x_i (normal n_i, weight w_i), with wp = 2 pi R / np:
+//   row0 + l          G(x_i, p_l) wp                         (incoming fields, single layer)
+//   row0 + np + l     [dG/dnu_l - i omega G](x_i, p_l) wp      (incoming fields, double layer)
+//   row0 + 2 np + l   K(p_l, x_i, n_i) w_i sqrt(wp)          (outgoing field of x_i on the circle)
+__global__ __launch_bounds__(NT) void k_proxy(Geo G, const ProxyDesc* __restrict__ descs) {
+  const ProxyDesc d = descs[blockIdx.y];
+  const int total = d.np * d.n;
+  const double wp = 2.0 * QPS_PI * d.R / d.np;
+  const double swp = sqrt(wp);
+  const double q = 0.25 * G.omega;
+  for (int e = blockIdx.x * NT + threadIdx.x; e < total; e += gridDim.x * NT) {
+    const int l = e % d.np, i = e / d.np;
+    double sn, cs;
+    sincos(2.0 * QPS_PI * l / d.np, &sn, &cs);
+    const double px = d.cx + d.R * cs, py = d.cy + d.R * sn;
+    const int gi = d.act[i];
+    const double dx = G.x[gi] - px, dy = G.y[gi] - py;  // x_i - p_l
+    const double r = sqrt(dx * dx + dy * dy);
+    cplx h0, h1;
+    hankel01(G.omega * r, h0, h1);
+    // G = (i/4) h0
+    const cplx gv = mkc(-0.25 * h0.y, 0.25 * h0.x);
+    // K(x_i, p_l, nu_l): n = nu_l, x - y = (dx, dy)
+    const double nd1 = (cs * dx + sn * dy) / r;
+    const cplx k1 = mkc(q * (h0.x - h1.y * nd1), q * (h0.y + h1.x * nd1));
+    // K(p_l, x_i, n_i): x - y = -(dx, dy)
+    const double nd2 = -(G.nx[gi] * dx + G.ny[gi] * dy) / r;
+    const cplx k2 = mkc(q * (h0.x - h1.y * nd2), q * (h0.y + h1.x * nd2));
+    cplx* col = d.wt + (size_t)i * d.m + d.row0;
+    col[l] = cscale(gv, wp);
+    col[d.np + l] = cscale(k1, wp);
+    col[2 * d.np + l] = cscale(k2, G.w[gi] * swp);
+  }
+}
+
+// complex Rademacher entries (+-1 +- i)/sqrt(2) from a counter-based hash
+__device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Z = Omega * W^T, tiles of 32 (sketch rows) x 32 (columns) per workgroup.
+__global__ __launch_bounds__(NT) void k_sketch(const SketchDesc* __restrict__ descs, uint64_t seed) {
+  const SketchDesc d = descs[blockIdx.z];
+  const int q0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
+  if (q0 >= d.s || i0 >= d.n) return;
+  __shared__ cplx Ws[32][33];
+  __shared__ float Om[32][33][2];
+  const int tid = threadIdx.x;
+  const int tq = tid % 32, ti = tid / 32;  // each thread: row q0+tq, columns i0+ti+8*c
+  cplx acc[4] = {mkc(0, 0), mkc(0, 0), mkc(0, 0), mkc(0, 0)};
+  const uint64_t bseed = mix64(seed ^ (0x9E3779B97F4A7C15ull * (uint64_t)(d.box + 1)));
+  for (int r0 = 0; r0 < d.m; r0 += 32) {
+    for (int e = tid; e < 32 * 32; e += NT) {
+      const int rr = e % 32, ii = e / 32;
+      const int gr = r0 + rr, gi = i0 + ii;
+      Ws[rr][ii] = (gr < d.m && gi < d.n) ? d.wt[gr + (size_t)gi * d.m] : mkc(0, 0);
+      const int qq = e / 32, r2 = e % 32;
+      const uint64_t h = mix64(bseed + 0xD1B54A32D192ED03ull * (uint64_t)(q0 + qq) +
+                               0x8CB92BA72F3D8DD7ull * (uint64_t)(r0 + r2));
+      Om[qq][r2][0] = (h & 1) ? 0.70710678118654752f : -0.70710678118654752f;
+      Om[qq][r2][1] = (h & 2) ? 0.70710678118654752f : -0.70710678118654752f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < 32; ++rr) {
+      const cplx o = mkc((double)Om[tq][rr][0], (double)Om[tq][rr][1]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = cfma(o, Ws[rr][ti + 8 * c], acc[c]);
+    }
+    __syncthreads();
+  }
+  const int q = q0 + tq;
+  if (q < d.s) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + ti + 8 * c;
+      if (i < d.n) d.z[q + (size_t)i * d.s] = acc[c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- CPQR / ID
+// One workgroup per box.  Householder QR with column pivoting on Z (s x n, in place, global
+// memory).  Column norms of the trailing rows are recomputed exactly in every update pass.
+// Rank: the first p with |R_pp| <= tol |R_00| (at least 1).
+constexpr int CPQR_MAXN = 2048;
+constexpr int CPQR_MAXS = 4608;
+__global__ __launch_bounds__(NT) void k_cpqr(const CpqrDesc* __restrict__ descs, double tol, int* __restrict__ k_out) {
+  const CpqrDesc d = descs[blockIdx.x];
+  const int s = d.s, n = d.n;
+  cplx* Z = d.z;
+  __shared__ double cn[CPQR_MAXN];
+  __shared__ int perm[CPQR_MAXN];
+  __shared__ cplx v[CPQR_MAXS];
+  __shared__ double red_v[NT / 64];
+  __shared__ int red_i[NT / 64];
+  __shared__ double sh_tau, sh_r00;
+  __shared__ int sh_piv, sh_stop;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nw = NT / 64;
+  for (int j = tid; j < n; j += NT) perm[j] = j;
+  for (int j = wv; j < n; j += nw) {
+    double a = 0.0;
+    for (int i = lane; i < s; i += 64) a += cabs2(Z[i + (size_t)j * s]);
+    a = wave_sum(a);
+    if (lane == 0) cn[j] = a;
+  }
+  __syncthreads();
+  const int pmax = min(s, n);
+  int k = pmax;
+  for (int p = 0; p < pmax; ++p) {
+    // pivot: argmax over j in [p, n)
+    double bv = -1.0;
+    int bi = n;
+    for (int j = p + tid; j < n; j += NT) {
+      const double c = cn[j];
+      if (c > bv || (c == bv && j < bi)) { bv = c; bi = j; }
+    }
+    wave_argmax(bv, bi);
+    if (lane == 0) { red_v[wv] = bv; red_i[wv] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = red_v[0];
+      int bj = red_i[0];
+      for (int w = 1; w < nw; ++w)
+        if (red_v[w] > b || (red_v[w] == b && red_i[w] < bj)) { b = red_v[w]; bj = red_i[w]; }
+      const double nr = sqrt(fmax(b, 0.0));
+      if (p == 0) sh_r00 = nr;
+      sh_stop = (p > 0 && nr <= tol * sh_r00) || (p == 0 && nr == 0.0);
+      sh_piv = bj;
+    }
+    __syncthreads();
+    if (sh_stop) { k = (p == 0) ? 1 : p; break; }
+    const int jp = sh_piv;
+    if (jp != p) {
+      for (int i = tid; i < s; i += NT) {
+        cplx t = Z[i + (size_t)p * s];
+        Z[i + (size_t)p * s] = Z[i + (size_t)jp * s];
+        Z[i + (size_t)jp * s] = t;
+      }
+      if (tid == 0) {
+        double t = cn[p]; cn[p] = cn[jp]; cn[jp] = t;
+        int ti = perm[p]; perm[p] = perm[jp]; perm[jp] = ti;
+      }
+    }
+    __syncthreads();
+    // Householder vector of x = Z[p:s, p]
+    for (int i = p + tid; i < s; i += NT) v[i] = Z[i + (size_t)p * s];
+    __syncthreads();
+    if (wv == 0) {
+      double a = 0.0;
+      for (int i = p + lane; i < s; i += 64) a += cabs2(v[i]);
+      a = wave_sum(a);
+      if (lane == 0) {
+        const double xn = sqrt(a);
+        const cplx x0 = v[p];
+        const double ax0 = sqrt(cabs2(x0));
+        cplx alpha = (ax0 > 0.0) ? cscale(x0, -xn / ax0) : mkc(-xn, 0.0);
+        const cplx v0 = csub(x0, alpha);
+        const double vn2 = a - ax0 * ax0 + cabs2(v0);
+        v[p] = v0;
+        sh_tau = (vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+        Z[p + (size_t)p * s] = alpha;
+      }
+    }
+    __syncthreads();
+    const double tau = sh_tau;
+    // apply H = I - tau v v^* to columns j > p; recompute trailing norms
+    for (int j = p + 1 + wv; j < n; j += nw) {
+      cplx* col = Z + (size_t)j * s;
+      cplx w = mkc(0, 0);
+      for (int i = p + lane; i < s; i += 64) w = cadd(w, cmul(cconj(v[i]), col[i]));
+      w = wave_csum(w);
+      w = cscale(w, tau);
+      double a = 0.0;
+      for (int i = p + lane; i < s; i += 64) {
+        cplx z = csub(col[i], cmul(w, v[i]));
+        col[i] = z;
+        if (i > p) a += cabs2(z);
+      }
+      a = wave_sum(a);
+      if (lane == 0) cn[j] = a;
+    }
+    __syncthreads();
+  }
+  // T = R11^{-1} R12 in place in Z[0:k, k:n], column-oriented back substitution
+  for (int i = k - 1; i >= 0; --i) {
+    const cplx zii = Z[i + (size_t)i * s];
+    const cplx rinv = cabs2(zii) > 0.0 ? cinv(zii) : mkc(0.0, 0.0);
+    for (int j = k + tid; j < n; j += NT) {
+      cplx* col = Z + (size_t)j * s;
+      col[i] = cmul(col[i], rinv);
+    }
+    __syncthreads();
+    const int cnt = (n - k) * i;
+    for (int e = tid; e < cnt; e += NT) {
+      const int l = e % i, j = k + e / i;
+      cplx* col = Z + (size_t)j * s;
+      col[l] = csub(col[l], cmul(Z[l + (size_t)i * s], col[i]));
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < n; j += NT) d.perm[j] = perm[j];
+  if (tid == 0) k_out[blockIdx.x] = k;
+}
+
+// P (n x k): P[perm[j], j] = 1 (j < k), P[perm[k + i], j] = T[j, i]
+__global__ __launch_bounds__(NT) void k_buildP(const PDesc* __restrict__ descs) {
+  const PDesc d = descs[blockIdx.y];
+  const int total = d.n * d.k;
+  for (int e = blockIdx.x * NT + threadIdx.x; e < total; e += gridDim.x * NT) {
+    const int r = e % d.n, j = e / d.n;  // r: position in pivot order
+    const int row = d.perm[r];
+    cplx v;
+    if (r < d.k) v = mkc(r == j ? 1.0 : 0.0, 0.0);
+    else v = d.z[j + (size_t)r * d.s];
+    d.P[row + (size_t)j * d.n] = v;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_copy(const CopyDesc* __restrict__ descs) {
+  const CopyDesc d = descs[blockIdx.y];
+  const int total = d.nr * d.nc;
+  for (int e = blockIdx.x * NT + threadIdx.x; e < total; e += gridDim.x * NT) {
+    const int r = e % d.nr, c = e / d.nr;
+    d.dst[r + (size_t)c * d.ldd] = d.src ? d.src[r + (size_t)c * d.lds] : mkc(0, 0);
+  }
+}
+
+__global__ void k_gather_idx(const int* __restrict__ src, const int* __restrict__ idx, int* __restrict__ dst, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) dst[e] = src[idx[e]];
+}
+
+// ---------------------------------------------------------------- blocked Gauss-Jordan
+constexpr int GJ_NB = 32;
+
+// Sweep the pivots of panel columns [c0, c0+nb) within the panel (one workgroup per matrix).
+__global__ __launch_bounds__(NT) void k_gj_panel(const InvDesc* __restrict__ descs, int c0, int* __restrict__ ipiv_all,
+                                                 int maxn, int* __restrict__ info) {
+  const InvDesc d = descs[blockIdx.x];
+  const int n = d.n;
+  if (c0 >= n) return;
+  const int c1 = min(c0 + GJ_NB, n);
+  const int ld = d.ld;
+  cplx* A = d.a;
+  int* ipiv = ipiv_all + (size_t)blockIdx.x * maxn;
+  __shared__ double red_v[NT / 64];
+  __shared__ int red_i[NT / 64];
+  __shared__ int sh_piv;
+  __shared__ cplx sh_d;
+  __shared__ cplx rowp[GJ_NB];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int w = c1 - c0;
+  for (int p = c0; p < c1; ++p) {
+    double bv = -1.0;
+    int bi = n;
+    for (int i = p + tid; i < n; i += NT) {
+      const double a = cabs2(A[i + (size_t)p * ld]);
+      if (a > bv || (a == bv && i < bi)) { bv = a; bi = i; }
+    }
+    wave_argmax(bv, bi);
+    if (lane == 0) { red_v[wv] = bv; red_i[wv] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = red_v[0];
+      int bj = red_i[0];
+      for (int q = 1; q < NT / 64; ++q)
+        if (red_v[q] > b || (red_v[q] == b && red_i[q] < bj)) { b = red_v[q]; bj = red_i[q]; }
+      if (!(b > 0.0)) { info[blockIdx.x] = p + 1; bj = p; }
+      sh_piv = bj;
+      ipiv[p] = bj;
+    }
+    __syncthreads();
+    const int r = sh_piv;
+    if (r != p) {
+      for (int j = c0 + tid; j < c1; j += NT) {
+        cplx t = A[p + (size_t)j * ld];
+        A[p + (size_t)j * ld] = A[r + (size_t)j * ld];
+        A[r + (size_t)j * ld] = t;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const cplx app = A[p + (size_t)p * ld];
+      sh_d = (cabs2(app) > 0.0) ? cinv(app) : mkc(0.0, 0.0);
+    }
+    __syncthreads();
+    const cplx dd = sh_d;
+    // scaled pivot row (panel columns)
+    for (int j = c0 + tid; j < c1; j += NT) {
+      cplx v = (j == p) ? dd : cmul(A[p + (size_t)j * ld], dd);
+      rowp[j - c0] = v;
+      A[p + (size_t)j * ld] = v;
+    }
+    __syncthreads();
+    // eliminate column p from all other rows (panel columns other than p) ...
+    const int total = n * w;
+    for (int e = tid; e < total; e += NT) {
+      const int i = e % n, jj = e / n;
+      const int j = c0 + jj;
+      if (i == p || j == p) continue;
+      const cplx f = A[i + (size_t)p * ld];
+      A[i + (size_t)j * ld] = csub(A[i + (size_t)j * ld], cmul(f, rowp[jj]));
+    }
+    __syncthreads();
+    // ... then replace column p by the corresponding column of the inverse
+    for (int i = tid; i < n; i += NT) {
+      if (i == p) continue;
+      const cplx f = A[i + (size_t)p * ld];
+      A[i + (size_t)p * ld] = cmul(mkc(-f.x, -f.y), dd);
+    }
+    __syncthreads();
+  }
+}
+
+// For columns outside the panel: apply the panel's row swaps, save the pivot rows to T.
+__global__ __launch_bounds__(NT) void k_gj_swapsave(const InvDesc* __restrict__ descs, int c0, const int* __restrict__ ipiv_all,
+                                                    int maxn, cplx* __restrict__ tbuf) {
+  const InvDesc d = descs[blockIdx.y];
+  const int n = d.n;
+  if (c0 >= n) return;
+  const int c1 = min(c0 + GJ_NB, n);
+  const int ld = d.ld;
+  const int* ipiv = ipiv_all + (size_t)blockIdx.y * maxn;
+  cplx* T = tbuf + (size_t)blockIdx.y * GJ_NB * maxn;
+  for (int j = blockIdx.x * NT + threadIdx.x; j < n; j += gridDim.x * NT) {
+    if (j >= c0 && j < c1) continue;
+    cplx* col = d.a + (size_t)j * ld;
+    for (int p = c0; p < c1; ++p) {
+      const int r = ipiv[p];
+      if (r != p) { cplx t = col[p]; col[p] = col[r]; col[r] = t; }
+    }
+    for (int p = c0; p < c1; ++p) T[(p - c0) + (size_t)j * GJ_NB] = col[p];
+  }
+}
+
+// A[:, j] = mask(A[:, j]) + A[:, c0:c1] T[:, j]  for j outside the panel (mask zeroes rows c0:c1).
+__global__ __launch_bounds__(NT) void k_gj_update(const InvDesc* __restrict__ descs, int c0, int maxn, const cplx* __restrict__ tbuf) {
+  const InvDesc d = descs[blockIdx.z];
+  const int n = d.n;
+  if (c0 >= n) return;
+  const int c1 = min(c0 + GJ_NB, n);
+  const int w = c1 - c0;
+  const int ld = d.ld;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 16;
+  if (i0 >= n || j0 >= n) return;
+  const cplx* T = tbuf + (size_t)blockIdx.z * GJ_NB * maxn;
+  __shared__ cplx Ap[GJ_NB][65];
+  __shared__ cplx Ts[GJ_NB][17];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * GJ_NB; e += NT) {
+    const int ii = e % 64, pp = e / 64;
+    const int i = i0 + ii;
+    Ap[pp][ii] = (i < n && pp < w) ? d.a[i + (size_t)(c0 + pp) * ld] : mkc(0, 0);
+  }
+  for (int e = tid; e < 16 * GJ_NB; e += NT) {
+    const int pp = e % GJ_NB, jj = e / GJ_NB;
+    const int j = j0 + jj;
+    Ts[pp][jj] = (j < n && pp < w) ? T[pp + (size_t)j * GJ_NB] : mkc(0, 0);
+  }
+  __syncthreads();
+  const int ii = tid % 64, jb = tid / 64;  // 4 column groups of 4
+  const int i = i0 + ii;
+  if (i >= n) return;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int jj = jb * 4 + c;
+    const int j = j0 + jj;
+    if (j >= n || (j >= c0 && j < c1)) continue;
+    cplx acc = (i >= c0 && i < c1) ? mkc(0, 0) : d.a[i + (size_t)j * ld];
+    for (int pp = 0; pp < w; ++pp) acc = cfma(Ap[pp][ii], Ts[pp][jj], acc);
+    d.a[i + (size_t)j * ld] = acc;
+  }
+}
+
+// undo the row interchanges on the columns of the inverse: for p = n-1..0 swap columns p, ipiv[p]
+__global__ __launch_bounds__(NT) void k_gj_colperm(const InvDesc* __restrict__ descs, const int* __restrict__ ipiv_all, int maxn) {
+  const InvDesc d = descs[blockIdx.y];
+  const int n = d.n;
+  const int* ipiv = ipiv_all + (size_t)blockIdx.y * maxn;
+  for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+    for (int p = n - 1; p >= 0; --p) {
+      const int r = ipiv[p];
+      if (r != p) {
+        cplx t = d.a[i + (size_t)p * d.ld];
+        d.a[i + (size_t)p * d.ld] = d.a[i + (size_t)r * d.ld];
+        d.a[i + (size_t)r * d.ld] = t;
+      }
+    }
+  }
+}
+
+__global__ void k_hankel(const double* __restrict__ x, int64_t n, cplx* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) {
+    cplx h0, h1;
+    hankel01(x[e], h0, h1);
+    out[e] = h0;
+    out[n + e] = h1;
+  }
+}
+
+__global__ void k_entries(Geo G, const int* __restrict__ rows, const int* __restrict__ cols, int64_t n, cplx* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT)
+    out[e] = a_entry(G, rows[e], cols[e]);
+}
+
+inline int grid_for(int64_t elems, int cap = 4096) {
+  int64_t g = (elems + NT - 1) / NT;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+namespace qps {
+
+hipError_t launch_eval_blocks(const Geo& g, const BlockDesc* d, int nd, int max_elems, hipStream_t s) {
+  if (nd == 0 || max_elems == 0) return hipSuccess;
+  dim3 grid(grid_for(max_elems, 256), nd);
+  hipLaunchKernelGGL(k_eval_blocks, grid, dim3(NT), 0, s, g, d);
+  return hipGetLastError();
+}
+hipError_t launch_proxy(const Geo& g, const ProxyDesc* d, int nd, int max_elems, hipStream_t s) {
+  if (nd == 0 || max_elems == 0) return hipSuccess;
+  dim3 grid(grid_for(max_elems, 256), nd);
+  hipLaunchKernelGGL(k_proxy, grid, dim3(NT), 0, s, g, d);
+  return hipGetLastError();
+}
+hipError_t launch_sketch(const SketchDesc* d, int nd, int max_s, int max_n, uint64_t seed, hipStream_t s) {
+  if (nd == 0) return hipSuccess;
+  dim3 grid((max_s + 31) / 32, (max_n + 31) / 32, nd);
+  hipLaunchKernelGGL(k_sketch, grid, dim3(NT), 0, s, d, seed);
+  return hipGetLastError();
+}
+hipError_t launch_cpqr(const CpqrDesc* d, int nd, double tol, int* k_out, hipStream_t s) {
+  if (nd == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cpqr, dim3(nd), dim3(NT), 0, s, d, tol, k_out);
+  return hipGetLastError();
+}
+hipError_t launch_buildP(const PDesc* d, int nd, int max_elems, hipStream_t s) {
+  if (nd == 0 || max_elems == 0) return hipSuccess;
+  dim3 grid(grid_for(max_elems, 256), nd);
+  hipLaunchKernelGGL(k_buildP, grid, dim3(NT), 0, s, d);
+  return hipGetLastError();
+}
+hipError_t launch_copy(const CopyDesc* d, int nd, int max_elems, hipStream_t s) {
+  if (nd == 0 || max_elems == 0) return hipSuccess;
+  dim3 grid(grid_for(max_elems, 256), nd);
+  hipLaunchKernelGGL(k_copy, grid, dim3(NT), 0, s, d);
+  return hipGetLastError();
+}
+hipError_t launch_gather_idx(const int* src, const int* idx, int* dst, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_idx, dim3(grid_for(n)), dim3(NT), 0, s, src, idx, dst, n);
+  return hipGetLastError();
+}
+hipError_t launch_zinv(const InvDesc* d, int nd, int max_n, cplx* tbuf, int* ipiv, int* info, hipStream_t s) {
+  if (nd == 0 || max_n == 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(info, 0, sizeof(int) * nd, s);
+  if (e != hipSuccess) return e;
+  for (int c0 = 0; c0 < max_n; c0 += GJ_NB) {
+    hipLaunchKernelGGL(k_gj_panel, dim3(nd), dim3(NT), 0, s, d, c0, ipiv, max_n, info);
+    hipLaunchKernelGGL(k_gj_swapsave, dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, c0, ipiv, max_n, tbuf);
+    hipLaunchKernelGGL(k_gj_update, dim3((max_n + 63) / 64, (max_n + 15) / 16, nd), dim3(NT), 0, s, d, c0, max_n,
+                       (const cplx*)tbuf);
+  }
+  hipLaunchKernelGGL(k_gj_colperm, dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, ipiv, max_n);
+  return hipGetLastError();
+}
+hipError_t launch_hankel(const double* x, int64_t n, cplx* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hankel, dim3(grid_for(n)), dim3(NT), 0, s, x, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_entries(const Geo& g, const int* rows, const int* cols, int64_t n, cplx* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_entries, dim3(grid_for(n)), dim3(NT), 0, s, g, rows, cols, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace qps

@@ -1,0 +1,326 @@
+// Device kernels of the periodizing scheme (Sec. 2.2-2.4) and the block solve (Sec. 3.1):
+// Sommerfeld-contour wall blocks B (Eq. 2.16) and C (Eq. 2.17), incident data, the Schur
+// complement S(alpha) = Q(alpha) - C(alpha) A^{-1} B(alpha) assembled from alpha-free products,
+// and Bragg amplitudes from the lattice-summed Green's function.
+#include "qp_kernels.h"
+
+namespace {
+
+constexpr int NT = 256;
+constexpr double PI = 3.14159265358979323846264338327950288;
+
+// exp(i z) for complex z
+__device__ inline cplx cexpi_c(cplx z) {
+  const double e = exp(-z.y);
+  double s, c;
+  sincos(z.x, &s, &c);
+  return mkc(e * c, e * s);
+}
+
+// Y[:, 0:4M] = [B^S_L, B^D_L, B^S_R, B^D_R] with
+//   B^S_W[i,m] = (i/2) wk_m e^{i k_m y_i} e^{i s_m |x_i - x_W|} / s_m,
+//   B^D_W[i,m] = (1/2) sign(x_i - x_W) wk_m e^{i k_m y_i} e^{i s_m |x_i - x_W|}   (Eqs. 2.12-2.13).
+__global__ __launch_bounds__(NT) void k_gen_B(QPGeo Q, cplx* __restrict__ Y, int64_t ldy) {
+  const int64_t total = (int64_t)Q.N * 4 * Q.M;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int i = (int)(e % Q.N);
+    const int col = (int)(e / Q.N);
+    const int wall = col / (2 * Q.M);          // 0 = L, 1 = R
+    const int dbl = (col / Q.M) & 1;           // 0 = single, 1 = double
+    const int m = col % Q.M;
+    const double xw = wall ? 0.5 * Q.period : -0.5 * Q.period;
+    const double dx = Q.x[i] + Q.shift - xw;
+    const cplx k = Q.k[m], s = Q.s[m], wk = Q.wk[m];
+    // i (k y + s |dx|)
+    const cplx z = mkc(k.x * Q.y[i] + s.x * fabs(dx), k.y * Q.y[i] + s.y * fabs(dx));
+    const cplx ex = cmul(wk, cexpi_c(z));
+    cplx v;
+    if (!dbl) v = cmul(mkc(0.0, 0.5), cmul(ex, cinv(s)));
+    else v = cscale(ex, dx > 0 ? 0.5 : -0.5);
+    Y[i + (size_t)col * ldy] = v;
+  }
+}
+
+// b = -exp(i (kx x + ky y)) for each angle column
+__global__ __launch_bounds__(NT) void k_gen_inc(QPGeo Q, const double* __restrict__ kx, const double* __restrict__ ky,
+                                                int nang, cplx* __restrict__ Y, int64_t ldy) {
+  const int64_t total = (int64_t)Q.N * nang;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int i = (int)(e % Q.N);
+    const int a = (int)(e / Q.N);
+    double s, c;
+    sincos(kx[a] * Q.x[i] + ky[a] * Q.y[i], &s, &c);
+    Y[i + (size_t)a * ldy] = mkc(-c, -s);
+  }
+}
+
+// C_W (2M x N): rows m (value) and M + m (x-derivative) of the wall Fourier data of the density
+// at node j on dOmega + shift e_1, with E = e^{-i k y_j} e^{i s |x_j - x_W|} / (4 pi), sigma = sign(x_j - x_W):
+//   value = [E (-sigma n_x + (k/s) n_y) + omega E / s] w_j
+//   deriv = [i E (s n_x - k sigma n_y) - i omega E sigma] w_j          (Sec. 2.2, Eq. 2.17)
+__global__ __launch_bounds__(NT) void k_gen_C(QPGeo Q, int wall, double shift, cplx* __restrict__ C) {
+  const int64_t total = (int64_t)Q.N * Q.M;
+  const double xw = wall ? 0.5 * Q.period : -0.5 * Q.period;
+  const int ldc = 2 * Q.M;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int m = (int)(e % Q.M);
+    const int j = (int)(e / Q.M);
+    const double dx = Q.x[j] + shift - xw;
+    const double sg = dx > 0 ? 1.0 : -1.0;
+    const cplx k = Q.k[m], s = Q.s[m];
+    // i(-k y + s |dx|)
+    const cplx z = mkc(-k.x * Q.y[j] + s.x * fabs(dx), -k.y * Q.y[j] + s.y * fabs(dx));
+    const cplx E = cscale(cexpi_c(z), 1.0 / (4.0 * PI));
+    const cplx is = cinv(s);
+    const double nx = Q.nx[j], ny = Q.ny[j], w = Q.w[j];
+    // value
+    cplx t = cadd(mkc(-sg * nx, 0.0), cscale(cmul(k, is), ny));
+    cplx val = cadd(cmul(E, t), cscale(cmul(E, is), Q.omega));
+    // derivative: i E (s nx - k sg ny) - i omega E sg
+    cplx u = csub(cscale(s, nx), cscale(k, sg * ny));
+    cplx der = cmul(mkc(0.0, 1.0), csub(cmul(E, u), cscale(E, Q.omega * sg)));
+    C[m + (size_t)j * ldc] = cscale(val, w);
+    C[Q.M + m + (size_t)j * ldc] = cscale(der, w);
+  }
+}
+
+// Q(alpha) entry (r, c) with E = e^{i s d}, a(+/-) = alpha +/- 1/alpha (Eq. 2.18 with the identity
+// blocks placed as the wall self-terms require):
+//   [[ i E a- /(2 s),  1 - E a+/2 ], [ -1 + E a+/2,  i E s a-/2 ]]
+__device__ inline cplx q_entry(const QPGeo& Q, cplx alpha, int r, int c) {
+  const int M = Q.M;
+  const int m = r % M;
+  if (c % M != m) return mkc(0, 0);
+  const cplx s = Q.s[m];
+  const cplx E = cexpi_c(cscale(s, Q.period));
+  const cplx ainv = cinv(alpha);
+  const cplx ap = cadd(alpha, ainv), am = csub(alpha, ainv);
+  const int br = r / M, bc = c / M;
+  if (br == 0 && bc == 0) return cmul(mkc(0.0, 0.5), cmul(cmul(E, am), cinv(s)));
+  if (br == 1 && bc == 1) return cmul(mkc(0.0, 0.5), cmul(cmul(E, am), s));
+  const cplx h = cscale(cmul(E, ap), 0.5);
+  if (br == 0) return mkc(1.0 - h.x, -h.y);
+  return mkc(h.x - 1.0, h.y);
+}
+
+// S_g = Q(alpha_g) - [C_L X_L + alpha C_L X_R - alpha^{-1} C_R X_L - C_R X_R],
+// G1 = C_L [X_L | X_R | ...], G2 = C_R [X_L | X_R | ...] (ld 2M).
+__global__ __launch_bounds__(NT) void k_form_S(QPGeo Q, const cplx* __restrict__ alphas, const cplx* __restrict__ G1,
+                                               const cplx* __restrict__ G2, cplx* __restrict__ S) {
+  const int g = blockIdx.y;
+  const int M2 = 2 * Q.M;
+  const cplx al = alphas[g];
+  const cplx ai = cinv(al);
+  const int64_t total = (int64_t)M2 * M2;
+  cplx* Sg = S + (size_t)g * total;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int r = (int)(e % M2), c = (int)(e / M2);
+    const cplx ll = G1[r + (size_t)c * M2];
+    const cplx lr = G1[r + (size_t)(M2 + c) * M2];
+    const cplx rl = G2[r + (size_t)c * M2];
+    const cplx rr = G2[r + (size_t)(M2 + c) * M2];
+    cplx cx = cadd(ll, cmul(al, lr));
+    cx = csub(cx, cmul(ai, rl));
+    cx = csub(cx, rr);
+    Sg[e] = csub(q_entry(Q, al, r, c), cx);
+  }
+}
+
+// W[:, a] = U1[:, a] - alpha_a^{-1} U2[:, a]  (optionally R - (...)), columns of 2M rows
+__global__ __launch_bounds__(NT) void k_combine_c(int M2, int nang, const cplx* __restrict__ alpha_col,
+                                                  const cplx* __restrict__ U1, int64_t ld1, const cplx* __restrict__ U2,
+                                                  int64_t ld2, const cplx* __restrict__ R, cplx* __restrict__ W) {
+  const int64_t total = (int64_t)M2 * nang;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int r = (int)(e % M2), a = (int)(e / M2);
+    const cplx ai = cinv(alpha_col[a]);
+    cplx v = csub(U1[r + (size_t)a * ld1], cmul(ai, U2[r + (size_t)a * ld2]));
+    if (R) v = csub(R[r + (size_t)a * M2], v);
+    W[e] = v;
+  }
+}
+
+// Xi_stack (4M x nang) = [xi; alpha xi]
+__global__ __launch_bounds__(NT) void k_stack(int M2, int nang, const cplx* __restrict__ alpha_col,
+                                              const cplx* __restrict__ xi, cplx* __restrict__ st) {
+  const int64_t total = (int64_t)M2 * nang;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int r = (int)(e % M2), a = (int)(e / M2);
+    const cplx v = xi[e];
+    st[r + (size_t)a * 2 * M2] = v;
+    st[M2 + r + (size_t)a * 2 * M2] = cmul(alpha_col[a], v);
+  }
+}
+
+// R2[:, a] = -(T1 - alpha^{-1} T2)[:, a] - Q(alpha_a) xi[:, a]
+__global__ __launch_bounds__(NT) void k_resid2(QPGeo Q, int nang, const cplx* __restrict__ alpha_col,
+                                               const cplx* __restrict__ T1, const cplx* __restrict__ T2,
+                                               const cplx* __restrict__ xi, cplx* __restrict__ R2) {
+  const int M = Q.M, M2 = 2 * M;
+  const int64_t total = (int64_t)M2 * nang;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int r = (int)(e % M2), a = (int)(e / M2);
+    const cplx al = alpha_col[a];
+    const cplx ai = cinv(al);
+    const cplx* x = xi + (size_t)a * M2;
+    const int m = r % M;
+    cplx qx = cadd(cmul(q_entry(Q, al, r, m), x[m]), cmul(q_entry(Q, al, r, M + m), x[M + m]));
+    cplx cv = csub(T1[e], cmul(ai, T2[e]));
+    R2[e] = mkc(-cv.x - qx.x, -cv.y - qx.y);
+  }
+}
+
+// y = a*x + b*y elementwise over n complex entries (strided columns)
+__global__ __launch_bounds__(NT) void k_axpby(int64_t rows, int cols, cplx a, const cplx* __restrict__ x, int64_t ldx,
+                                              cplx b, cplx* __restrict__ y, int64_t ldy) {
+  const int64_t total = rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int64_t r = e % rows;
+    const int64_t c = e / rows;
+    const cplx xv = x[r + c * ldx];
+    cplx* yp = y + r + c * ldy;
+    *yp = (b.x == 0.0 && b.y == 0.0) ? cmul(a, xv) : cadd(cmul(a, xv), cmul(b, *yp));
+  }
+}
+
+// column-wise squared norms (one workgroup per column)
+__global__ __launch_bounds__(NT) void k_colnorm2(int64_t rows, const cplx* __restrict__ x, int64_t ldx, double* __restrict__ out) {
+  const cplx* col = x + (size_t)blockIdx.x * ldx;
+  double a = 0.0;
+  for (int64_t r = threadIdx.x; r < rows; r += NT) a += cabs2(col[r]);
+  a = wave_sum(a);
+  __shared__ double red[NT / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Bragg amplitudes (lattice-summed Green's function), one workgroup per (mode slot, angle):
+//   c_n = pre sum_j w_j eta_j e^{-i(kap_n x_j + k_n y_j)} [-i(kap_n n_x + k_n n_y) - i omega]
+//   d_n = pre sum_j w_j eta_j e^{-i(kap_n x_j - k_n y_j)} [ i(-kap_n n_x + k_n n_y) - i omega]
+//   pre = i e^{i k_n y0} / (2 d k_n),  kap_n = kappa + 2 pi n / d, k_n = sqrt(omega^2 - kap_n^2).
+__global__ __launch_bounds__(NT) void k_bragg(QPGeo Q, const double* __restrict__ kappa, const int* __restrict__ nlo,
+                                              const int* __restrict__ nmodes, int maxmodes, const cplx* __restrict__ eta,
+                                              int64_t ldeta, double y0, cplx* __restrict__ out) {
+  const int slot = blockIdx.x, a = blockIdx.y;
+  cplx* oc = out + (size_t)a * 2 * maxmodes;
+  if (slot >= nmodes[a]) {
+    if (threadIdx.x == 0) {
+      oc[slot] = mkc(0, 0);
+      oc[maxmodes + slot] = mkc(0, 0);
+    }
+    return;
+  }
+  const double kn_x = kappa[a] + 2.0 * PI * (nlo[a] + slot) / Q.period;
+  const double kn = sqrt(fmax(Q.omega * Q.omega - kn_x * kn_x, 0.0));
+  const cplx* et = eta + (size_t)a * ldeta;
+  cplx su = mkc(0, 0), sd = mkc(0, 0);
+  for (int j = threadIdx.x; j < Q.N; j += NT) {
+    const cplx we = cscale(et[j], Q.w[j]);
+    double s1, c1, s2, c2;
+    sincos(-(kn_x * Q.x[j] + kn * Q.y[j]), &s1, &c1);
+    sincos(-(kn_x * Q.x[j] - kn * Q.y[j]), &s2, &c2);
+    const cplx fu = mkc(0.0, -(kn_x * Q.nx[j] + kn * Q.ny[j]) - Q.omega);
+    const cplx fd = mkc(0.0, (-kn_x * Q.nx[j] + kn * Q.ny[j]) - Q.omega);
+    su = cadd(su, cmul(we, cmul(mkc(c1, s1), fu)));
+    sd = cadd(sd, cmul(we, cmul(mkc(c2, s2), fd)));
+  }
+  su = wave_csum(su);
+  sd = wave_csum(sd);
+  __shared__ cplx ru[NT / 64], rd[NT / 64];
+  if ((threadIdx.x & 63) == 0) { ru[threadIdx.x >> 6] = su; rd[threadIdx.x >> 6] = sd; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cplx tu = mkc(0, 0), td = mkc(0, 0);
+    for (int w = 0; w < NT / 64; ++w) { tu = cadd(tu, ru[w]); td = cadd(td, rd[w]); }
+    double s, c;
+    sincos(kn * y0, &s, &c);
+    const cplx pre = cscale(cmul(mkc(0.0, 1.0), mkc(c, s)), 1.0 / (2.0 * Q.period * kn));
+    oc[slot] = cmul(pre, tu);
+    oc[maxmodes + slot] = cmul(pre, td);
+  }
+}
+
+// permute columns: dst[:, perm[a]] = src[:, a]
+__global__ __launch_bounds__(NT) void k_permute_cols(int64_t rows, int cols, const int* __restrict__ perm,
+                                                     const cplx* __restrict__ src, int64_t lds, cplx* __restrict__ dst,
+                                                     int64_t ldd) {
+  const int64_t total = rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int64_t r = e % rows;
+    const int a = (int)(e / rows);
+    dst[r + (size_t)perm[a] * ldd] = src[r + (size_t)a * lds];
+  }
+}
+
+inline int grid_for(int64_t elems, int cap = 8192) {
+  int64_t g = (elems + NT - 1) / NT;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+namespace qps {
+
+hipError_t launch_gen_B(const QPGeo& q, cplx* Y, int64_t ldy, hipStream_t s) {
+  hipLaunchKernelGGL(k_gen_B, dim3(grid_for((int64_t)q.N * 4 * q.M)), dim3(NT), 0, s, q, Y, ldy);
+  return hipGetLastError();
+}
+hipError_t launch_gen_inc(const QPGeo& q, const double* kx, const double* ky, int nang, cplx* Y, int64_t ldy, hipStream_t s) {
+  if (nang == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gen_inc, dim3(grid_for((int64_t)q.N * nang)), dim3(NT), 0, s, q, kx, ky, nang, Y, ldy);
+  return hipGetLastError();
+}
+hipError_t launch_gen_C(const QPGeo& q, int wall, double shift, cplx* C, hipStream_t s) {
+  hipLaunchKernelGGL(k_gen_C, dim3(grid_for((int64_t)q.N * q.M)), dim3(NT), 0, s, q, wall, shift, C);
+  return hipGetLastError();
+}
+hipError_t launch_form_S(const QPGeo& q, const cplx* alphas, int ng, const cplx* G1, const cplx* G2, cplx* S, hipStream_t s) {
+  if (ng == 0) return hipSuccess;
+  int64_t tot = (int64_t)4 * q.M * q.M;
+  hipLaunchKernelGGL(k_form_S, dim3(grid_for(tot, 4096), ng), dim3(NT), 0, s, q, alphas, G1, G2, S);
+  return hipGetLastError();
+}
+hipError_t launch_combine_c(int M2, int nang, const cplx* alpha_col, const cplx* U1, int64_t ld1, const cplx* U2, int64_t ld2,
+                            const cplx* R, cplx* W, hipStream_t s) {
+  if (nang == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_combine_c, dim3(grid_for((int64_t)M2 * nang)), dim3(NT), 0, s, M2, nang, alpha_col, U1, ld1, U2, ld2, R, W);
+  return hipGetLastError();
+}
+hipError_t launch_stack(int M2, int nang, const cplx* alpha_col, const cplx* xi, cplx* st, hipStream_t s) {
+  if (nang == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stack, dim3(grid_for((int64_t)M2 * nang)), dim3(NT), 0, s, M2, nang, alpha_col, xi, st);
+  return hipGetLastError();
+}
+hipError_t launch_resid2(const QPGeo& q, int nang, const cplx* alpha_col, const cplx* T1, const cplx* T2, const cplx* xi,
+                         cplx* R2, hipStream_t s) {
+  if (nang == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_resid2, dim3(grid_for((int64_t)2 * q.M * nang)), dim3(NT), 0, s, q, nang, alpha_col, T1, T2, xi, R2);
+  return hipGetLastError();
+}
+hipError_t launch_axpby(int64_t rows, int cols, cplx a, const cplx* x, int64_t ldx, cplx b, cplx* y, int64_t ldy, hipStream_t s) {
+  if (rows * cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(rows * cols)), dim3(NT), 0, s, rows, cols, a, x, ldx, b, y, ldy);
+  return hipGetLastError();
+}
+hipError_t launch_colnorm2(int64_t rows, int cols, const cplx* x, int64_t ldx, double* out, hipStream_t s) {
+  if (cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_colnorm2, dim3(cols), dim3(NT), 0, s, rows, x, ldx, out);
+  return hipGetLastError();
+}
+hipError_t launch_bragg(const QPGeo& q, const double* kappa, const int* nlo, const int* nmodes, int maxmodes, int nang,
+                        const cplx* eta, int64_t ldeta, double y0, cplx* out, hipStream_t s) {
+  if (nang == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bragg, dim3(maxmodes, nang), dim3(NT), 0, s, q, kappa, nlo, nmodes, maxmodes, eta, ldeta, y0, out);
+  return hipGetLastError();
+}
+hipError_t launch_permute_cols(int64_t rows, int cols, const int* perm, const cplx* src, int64_t lds, cplx* dst, int64_t ldd,
+                               hipStream_t s) {
+  if (rows * cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute_cols, dim3(grid_for(rows * cols)), dim3(NT), 0, s, rows, cols, perm, src, lds, dst, ldd);
+  return hipGetLastError();
+}
+
+}  // namespace qps

@@ -1,0 +1,29 @@
+// Declarations of the periodizing-scheme kernels (kernels_qp.hip).
+#pragma once
+#include "internal.h"
+
+// Geometry and contour data for the wall blocks (device pointers).
+struct QPGeo {
+  const double *x, *y, *nx, *ny, *w;
+  const cplx *k, *s, *wk;  // contour nodes, sqrt(omega^2 - k^2), quadrature weights
+  int N, M;
+  double omega, period, shift;
+};
+
+namespace qps {
+hipError_t launch_gen_B(const QPGeo& q, cplx* Y, int64_t ldy, hipStream_t s);
+hipError_t launch_gen_inc(const QPGeo& q, const double* kx, const double* ky, int nang, cplx* Y, int64_t ldy, hipStream_t s);
+hipError_t launch_gen_C(const QPGeo& q, int wall, double shift, cplx* C, hipStream_t s);
+hipError_t launch_form_S(const QPGeo& q, const cplx* alphas, int ng, const cplx* G1, const cplx* G2, cplx* S, hipStream_t s);
+hipError_t launch_combine_c(int M2, int nang, const cplx* alpha_col, const cplx* U1, int64_t ld1, const cplx* U2, int64_t ld2,
+                            const cplx* R, cplx* W, hipStream_t s);
+hipError_t launch_stack(int M2, int nang, const cplx* alpha_col, const cplx* xi, cplx* st, hipStream_t s);
+hipError_t launch_resid2(const QPGeo& q, int nang, const cplx* alpha_col, const cplx* T1, const cplx* T2, const cplx* xi,
+                         cplx* R2, hipStream_t s);
+hipError_t launch_axpby(int64_t rows, int cols, cplx a, const cplx* x, int64_t ldx, cplx b, cplx* y, int64_t ldy, hipStream_t s);
+hipError_t launch_colnorm2(int64_t rows, int cols, const cplx* x, int64_t ldx, double* out, hipStream_t s);
+hipError_t launch_bragg(const QPGeo& q, const double* kappa, const int* nlo, const int* nmodes, int maxmodes, int nang,
+                        const cplx* eta, int64_t ldeta, double y0, cplx* out, hipStream_t s);
+hipError_t launch_permute_cols(int64_t rows, int cols, const int* perm, const cplx* src, int64_t lds, cplx* dst, int64_t ldd,
+                               hipStream_t s);
+}  // namespace qps

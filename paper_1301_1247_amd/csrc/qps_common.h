@@ -1,0 +1,76 @@
+// Shared device/host helpers of the HIP library: complex arithmetic on double2,
+// error plumbing, wavefront reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+
+typedef double2 cplx;
+
+__host__ __device__ inline cplx mkc(double re, double im) { cplx c; c.x = re; c.y = im; return c; }
+__host__ __device__ inline cplx cadd(cplx a, cplx b) { return mkc(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cplx csub(cplx a, cplx b) { return mkc(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cplx cmul(cplx a, cplx b) { return mkc(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__host__ __device__ inline cplx cscale(cplx a, double s) { return mkc(a.x * s, a.y * s); }
+__host__ __device__ inline cplx cconj(cplx a) { return mkc(a.x, -a.y); }
+__host__ __device__ inline double cabs2(cplx a) { return a.x * a.x + a.y * a.y; }
+// a * conj(b)
+__host__ __device__ inline cplx cmulc(cplx a, cplx b) { return mkc(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+// acc + a*b
+__host__ __device__ inline cplx cfma(cplx a, cplx b, cplx acc) {
+  return mkc(fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y)));
+}
+__host__ __device__ inline cplx cinv(cplx a) {
+  // 1/a with scaling to avoid overflow for |a| large or small
+  double s = fmax(fabs(a.x), fabs(a.y));
+  double ar = a.x / s, ai = a.y / s;
+  double d = ar * ar + ai * ai;
+  return mkc(ar / (d * s), -ai / (d * s));
+}
+__device__ inline cplx cexpi(double t) {
+  double s, c;
+  sincos(t, &s, &c);
+  return mkc(c, s);
+}
+// exp(z) for complex z
+__device__ inline cplx cexp(cplx z) {
+  double e = exp(z.x);
+  double s, c;
+  sincos(z.y, &s, &c);
+  return mkc(e * c, e * s);
+}
+
+// wavefront (64 lanes) reductions
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline cplx wave_csum(cplx v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+  }
+  return v;
+}
+// arg-max of (val, idx) over a wavefront, ties resolved to the smaller index
+__device__ inline void wave_argmax(double& val, int& idx) {
+  for (int o = 32; o > 0; o >>= 1) {
+    double ov = __shfl_xor(val, o, 64);
+    int oi = __shfl_xor(idx, o, 64);
+    if (ov > val || (ov == val && oi < idx)) { val = ov; idx = oi; }
+  }
+}
+
+// host-side status plumbing
+namespace qps {
+void set_error(const std::string& msg);
+}
+
+#define QPS_HIP_CHECK(expr)                                                              \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess) {                                                              \
+      qps::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));                 \
+      return HBS_E_DEVICE;                                                               \
+    }                                                                                    \
+  } while (0)

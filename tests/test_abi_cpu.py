@@ -1,0 +1,117 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every function the
+header declares, and rejects bad input on the host before any device work."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1301_1247_amd", "libqpscatter.so")
+HDR = os.path.join(ROOT, "include", "qpscatter.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+
+
+def _declared():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", txt, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while", "return")))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("hbs_build", "hbs_apply", "qp_solve", "qp_solve_many", "hbs_free", "hbs_last_error", "hbs_stats"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(LIB)
+    for n in _declared():
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_1301_1247_amd import binding
+    assert set(_declared()) <= set(binding.EXPORTED)
+
+
+def _geom(N=256):
+    import qpinputs
+    from paper_1301_1247_amd.geometry import discretize
+    return discretize(qpinputs.star(), N)
+
+
+def _build(nodes, w, nrm, N, omega=10.0, tol=1e-10, **kw):
+    from paper_1301_1247_amd import binding as B
+    o = B.hbs_opts(**kw)
+    h = C.c_void_p()
+    rc = B._lib.hbs_build(nodes.ctypes.data, w.ctypes.data, nrm.ctypes.data, N, omega, tol, C.byref(o), C.byref(h))
+    return rc, B._lib.hbs_last_error().decode()
+
+
+def test_nonfinite_geometry_rejected_on_host():
+    nodes, w, nrm, _ = _geom()
+    nodes = nodes.copy()
+    nodes[3, 0] = np.nan
+    rc, msg = _build(nodes, w, nrm, 256)
+    assert rc == -2 and "non-finite" in msg
+
+
+def test_non_unit_normals_rejected():
+    nodes, w, nrm, _ = _geom()
+    rc, msg = _build(nodes, w, 1.5 * nrm, 256)
+    assert rc == -1 and "unit" in msg
+
+
+def test_bad_sizes_and_tolerance_rejected():
+    nodes, w, nrm, _ = _geom()
+    assert _build(nodes, w, nrm, 256, tol=1e-20)[0] == -1
+    assert _build(nodes, w, nrm, 256, omega=-1.0)[0] == -1
+    assert _build(nodes, w, nrm, 100, leaf_size=64)[0] == -1          # N < 2 leaf
+    assert _build(nodes, w, nrm, 256, quad=1)[0] == -1                # Kress without curvature
+    rc, msg = _build(nodes, w, nrm, 256, quad=1, curvature=w.ctypes.data)
+    assert rc == -1 and "EXACT" in msg                                # Kress needs exact compression
+
+
+def test_negative_weights_rejected():
+    nodes, w, nrm, _ = _geom()
+    w2 = w.copy()
+    w2[0] = -w2[0]
+    assert _build(nodes, w2, nrm, 256)[0] == -1
+
+
+def test_free_null_is_noop_and_error_is_thread_local():
+    from paper_1301_1247_amd import binding as B
+    B._lib.hbs_free(None)
+    nodes, w, nrm, _ = _geom()
+    rc, msg = _build(nodes, w, nrm, 256, tol=1.0)
+    assert rc == -1 and msg
+    import threading
+    seen = []
+    t = threading.Thread(target=lambda: seen.append(B._lib.hbs_last_error().decode()))
+    t.start()
+    t.join()
+    assert seen == [""]
+
+
+def test_max_modes_counts_propagating_orders():
+    from paper_1301_1247_amd import binding as B
+    om, d = 40.0, 2 * math.pi
+    mm = B._lib.qp_max_modes(om, d)
+    for th in np.linspace(-3.1, -0.05, 50):
+        kap = om * math.cos(th)
+        n = sum(1 for j in range(-200, 201) if abs(kap + 2 * math.pi * j / d) <= om)
+        assert n <= mm
+
+
+def test_kr6_corrections_match_oracle_derivation():
+    """Library (long double, host) and oracle (50-digit mpmath) derive the same corrections."""
+    from paper_1301_1247_amd import binding as B
+    from oracle import quadrature
+    g_lib = B.kr6_corrections()
+    g_or = quadrature.kr6_corrections()
+    assert np.abs(g_lib - g_or).max() < 1e-12 * np.abs(g_or).max()

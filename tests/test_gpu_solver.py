@@ -1,0 +1,151 @@
+"""End-to-end parity of the GPU solver with the CPU oracle, through the C ABI.
+
+Bar (floating point): relative error <= 1e-10 of every solution against the oracle's dense
+LU solution, the target stated for the solver.  The compressed inverse alone is an
+approximation to the requested tolerance amplified by the conditioning of the reduced
+systems, so bare applies are held to a looser bound and refinement recovers 1e-10.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import qpinputs
+from oracle import nystrom as ny
+from oracle import periodic as pq
+from paper_1301_1247_amd.geometry import discretize
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def wavy_small():
+    c = qpinputs.wavy(130102, 20, 0.3)
+    N, om = 2000, 40.0
+    disc = ny.Discretization(c, N)
+    A = ny.matrix(disc, om, "kr6")
+    return c, N, om, disc, A, sla.lu_factor(A)
+
+
+def test_hbs_inverse_and_forward_vs_dense(gpu_lib, wavy_small):
+    c, N, om, disc, A, lu = wavy_small
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-12)
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((N, 7)) + 1j * rng.standard_normal((N, 7))
+    Xe = sla.lu_solve(lu, B)
+    X0 = h.apply(B)
+    assert _rel(X0, Xe) < 1e-7
+    X1 = h.apply(B, refine=2)
+    assert _rel(X1, Xe) < 1e-10
+    F = h.forward(Xe)
+    assert _rel(F, A @ Xe) < 1e-10
+    # batch consistency: columns applied one at a time give the same result
+    for j in (0, 6):
+        xj = h.apply(B[:, j])
+        assert np.abs(xj - X0[:, j]).max() <= 1e-12 * np.abs(X0[:, j]).max()
+    s = h.stats()
+    assert s.levels >= 4 and 0 < s.max_rank <= 2048
+
+
+@pytest.mark.parametrize("N", [130, 131, 777])
+def test_hbs_ragged_and_minimal_sizes(gpu_lib, N):
+    c = qpinputs.star()
+    om = 10.0
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-12, leaf_size=64 if N < 200 else 50)
+    A = ny.matrix(ny.Discretization(c, N), om, "kr6")
+    b = np.exp(1j * np.arange(N) * 0.37)
+    assert _rel(h.apply(b, refine=2), np.linalg.solve(A, b)) < 1e-10
+
+
+def test_kress_exact_inverse_vs_dense(gpu_lib):
+    c = qpinputs.star()
+    N, om = 800, 10.0
+    nodes, w, nrm, kap = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-12, quad="kress", leaf_size=50, curvature=kap)
+    A = ny.matrix(ny.Discretization(c, N), om, "kress")
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal((N, 3)) + 1j * rng.standard_normal((N, 3))
+    assert _rel(h.apply(b, refine=2), np.linalg.solve(A, b)) < 1e-10
+
+
+def test_circle_closed_form_through_gpu(gpu_lib):
+    """A^{-1} e^{i n t} = e^{i n t} / lambda_n on the circle, to the quadrature's accuracy (Kress)."""
+    c = qpinputs.circle(1.0)
+    N, om = 256, 10.0
+    nodes, w, nrm, kap = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-13, quad="kress", leaf_size=32, curvature=kap)
+    t = 2 * math.pi * np.arange(N) / N
+    for n in (0, 3, 17):
+        v = np.exp(1j * n * t)
+        x = h.apply(v, refine=2)
+        assert np.abs(x - v / ny.circle_eigenvalue(om, 1.0, n)).max() < 1e-11 * np.abs(x).max()
+
+
+def _oracle_qp(curve, N, om, d, thetas, quad):
+    r = pq.solve_qp(curve, N, om, d, thetas, quad=quad)
+    return r
+
+
+def _check_qp(res, ref, nth):
+    eta, xi = res["eta"], res["xi"]
+    for a in range(nth):
+        assert _rel(eta[:, a], ref["eta"][:, a]) < 1e-10, a
+        assert _rel(xi[:, a], ref["xi"][:, a]) < 1e-10, a
+        n, kn, c, d = ref["bragg"][a]
+        maxm = res["maxmodes"]
+        nlo, nm = res["nlo"][a], res["nmodes"][a]
+        assert nlo == n[0] and nm == len(n)
+        cg = res["bragg"][:nm, a]
+        dg = res["bragg"][maxm:maxm + nm, a]
+        scale = max(np.abs(c).max(), np.abs(d).max())
+        assert np.abs(cg - c).max() < 1e-10 * scale
+        assert np.abs(dg - d).max() < 1e-10 * scale
+        assert abs(res["flux"][a] - ref["flux"][a]) < 1e-10
+
+
+def test_qp_star_kress_parity(gpu_lib):
+    wl = qpinputs.workload("star")
+    nodes, w, nrm, kap = discretize(wl.curve, wl.N)
+    h = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-12, quad="kress", leaf_size=50, curvature=kap)
+    res = h.qp_solve_many(wl.period, wl.thetas)
+    ref = _oracle_qp(wl.curve, wl.N, wl.omega, wl.period, wl.thetas, "kress")
+    assert res["M"] == len(ref["contour"].k)
+    _check_qp(res, ref, len(wl.thetas))
+    assert res["flux"][0] < 1e-12
+    st = h.stats()
+    assert st.refine_residual < 1e-12
+
+
+def test_qp_wavy_kr6_parity_shared_and_distinct_phases(gpu_lib, wavy_small):
+    c, N, om, disc, A, lu = wavy_small
+    d = 2 * math.pi
+    # two angles sharing a Bloch phase, plus two distinct ones
+    c1 = 0.3
+    c2 = c1 + 2 * math.pi / (om * d)
+    thetas = np.array([-math.acos(c1), -1.1, -math.acos(c2), -0.45])
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-12)
+    res = h.qp_solve_many(d, thetas)
+    ref = pq.solve_qp(disc, N, om, d, thetas, quad="kr6", A0=A)
+    _check_qp(res, ref, len(thetas))
+
+
+def test_qp_solve_alpha_mismatch_and_wood(gpu_lib):
+    wl = qpinputs.workload("star")
+    nodes, w, nrm, kap = discretize(wl.curve, wl.N)
+    h = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-10, quad="kress", leaf_size=50, curvature=kap)
+    with pytest.raises(gpu_lib.HBSError) as e:
+        h.qp_solve_many(wl.period, np.array([-0.6]), alpha=1.0 + 0j)
+    assert e.value.code == -8
+    # Wood's anomaly: kappa + n = +-omega for d = 2 pi, i.e. cos(theta) = (omega - 1)/omega
+    th = -math.acos((wl.omega - 1.0) / wl.omega)
+    with pytest.raises(gpu_lib.HBSError) as e:
+        h.qp_solve_many(wl.period, np.array([th]))
+    assert e.value.code == -9
