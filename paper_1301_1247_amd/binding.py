@@ -268,8 +268,8 @@ def zgemm(A, B, transA=False):
     else:
         m, k = A.shape[1], A.shape[2]
     n = B.shape[2]
-    Af = np.ascontiguousarray(np.transpose(A, (0, 2, 1)))  # column-major per batch entry
-    Bf = np.ascontiguousarray(np.transpose(B, (0, 2, 1)))
+    Af = np.array(np.transpose(A, (0, 2, 1)), order="C", copy=True)  # column-major per batch entry
+    Bf = np.array(np.transpose(B, (0, 2, 1)), order="C", copy=True)
     Cf = np.zeros((nb, n, m), dtype=np.complex128)
     _check(_lib.qps_zgemm(_ptr(Af), _ptr(Bf), _ptr(Cf), m, n, k, nb, int(transA), 0, PTR_HOST))
     return np.transpose(Cf, (0, 2, 1))
@@ -278,7 +278,7 @@ def zgemm(A, B, transA=False):
 def zinv(A):
     A = np.asarray(A, dtype=np.complex128)
     nb, n = A.shape[0], A.shape[1]
-    Af = np.ascontiguousarray(np.transpose(A, (0, 2, 1)))
+    Af = np.array(np.transpose(A, (0, 2, 1)), order="C", copy=True)
     _check(_lib.qps_zinv(_ptr(Af), n, nb, PTR_HOST))
     return np.transpose(Af, (0, 2, 1))
 

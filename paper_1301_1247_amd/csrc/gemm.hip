@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc* __restrict__ desc
     }
     __syncthreads();
   }
-  // epilogue: lane holds rows 4*(lane/16) + r, column lane%16 of each 16 x 16 block
+  // epilogue: register r of a lane holds row (lane/16) + 4r, column lane%16 of each 16 x 16 block
   const bool zero_beta = (d.beta.x == 0.0 && d.beta.y == 0.0);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc* __restrict__ desc
       if (j >= d.n) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wm * 32 + a * 16 + 4 * (lane >> 4) + r;
+        const int i = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * r;
         if (i >= d.m) continue;
         cplx v = cmul(d.alpha, mkc(accr[a][b][r], acci[a][b][r]));
         cplx* c = d.C + i + (size_t)j * d.ldc;

@@ -127,7 +127,7 @@ def test_qp_wavy_kr6_parity_shared_and_distinct_phases(gpu_lib, wavy_small):
     c, N, om, disc, A, lu = wavy_small
     d = 2 * math.pi
     # two angles sharing a Bloch phase, plus two distinct ones
-    c1 = 0.3
+    c1 = 0.31   # min_n |k_n| > 5 for both angles of the shared phase (away from Wood's anomalies)
     c2 = c1 + 2 * math.pi / (om * d)
     thetas = np.array([-math.acos(c1), -1.1, -math.acos(c2), -0.45])
     nodes, w, nrm, _ = discretize(c, N)
