@@ -441,7 +441,7 @@ int qps_zgemm(const double* A, const double* B, double* C, int32_t m, int32_t n,
   clear_error();
   if (!A || !B || !C || m <= 0 || n <= 0 || k < 0 || nbatch <= 0) { set_error("qps_zgemm: bad arguments"); return HBS_E_INVALID_ARG; }
   const size_t sa = (size_t)m * k, sb = (size_t)k * n, sc = (size_t)m * n;
-  DevBuf da, dbb, dc, arena;
+  DevBuf da, dbb, dc, arena, ws;
   const cplx *pa, *pb;
   cplx* pc;
   if (ptr_mode == HBS_PTR_HOST) {
@@ -466,7 +466,7 @@ int qps_zgemm(const double* A, const double* B, double* C, int32_t m, int32_t n,
     g.beta = accumulate ? mkc(1, 0) : mkc(0, 0);
     v.push_back(g);
   }
-  CKD(gemm_batched(arena, v, nullptr));
+  CKD(gemm_batched(arena, v, nullptr, &ws));
   CKD(hipDeviceSynchronize());
   if (ptr_mode == HBS_PTR_HOST) CKD(hipMemcpy(C, pc, sizeof(cplx) * sc * nbatch, hipMemcpyDeviceToHost));
   return HBS_OK;

@@ -8,6 +8,8 @@
 // workgroups past an entry's tile count exit.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -51,39 +53,40 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc* __restrict__ desc
     }
   const cplx* __restrict__ A = d.A;
   const cplx* __restrict__ B = d.B;
-  for (int k0 = 0; k0 < d.k; k0 += BK) {
-    // A slice: op(A)(i0 + ii, k0 + kk)
-    if (!d.transA) {
+  // register staging of one k-slice: 4 elements of op(A) and 4 of B per thread
+  cplx ra[4], rb[4];
+  auto load_slice = [&](int k0) {
 #pragma unroll
-      for (int q = 0; q < (BM * BK) / 256; ++q) {
-        const int e = tid + q * 256;
-        const int ii = e % BM, kk = e / BM;
-        const int gi = i0 + ii, gk = k0 + kk;
-        cplx v = (gi < d.m && gk < d.k) ? A[gi + (size_t)gk * d.lda] : mkc(0, 0);
-        Are[kk][ii] = v.x;
-        Aim[kk][ii] = v.y;
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < (BM * BK) / 256; ++q) {
-        const int e = tid + q * 256;
-        const int kk = e % BK, ii = e / BK;
-        const int gi = i0 + ii, gk = k0 + kk;
-        cplx v = (gi < d.m && gk < d.k) ? A[gk + (size_t)gi * d.lda] : mkc(0, 0);
-        Are[kk][ii] = v.x;
-        Aim[kk][ii] = v.y;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < (BN * BK) / 256; ++q) {
+    for (int q = 0; q < 4; ++q) {
       const int e = tid + q * 256;
-      const int kk = e % BK, jj = e / BK;
-      const int gj = j0 + jj, gk = k0 + kk;
-      cplx v = (gj < d.n && gk < d.k) ? B[gk + (size_t)gj * d.ldb] : mkc(0, 0);
-      Bre[kk][jj] = v.x;
-      Bim[kk][jj] = v.y;
+      int ii, kk;
+      if (!d.transA) { ii = e % BM; kk = e / BM; } else { kk = e % BK; ii = e / BK; }
+      const int gi = i0 + ii, gk = k0 + kk;
+      ra[q] = (gi < d.m && gk < d.k) ? (d.transA ? A[gk + (size_t)gi * d.lda] : A[gi + (size_t)gk * d.lda]) : mkc(0, 0);
+      const int kb = e % BK, jj = e / BK;
+      const int gj = j0 + jj, gkb = k0 + kb;
+      rb[q] = (gj < d.n && gkb < d.k) ? B[gkb + (size_t)gj * d.ldb] : mkc(0, 0);
     }
-    __syncthreads();
+  };
+  auto store_slice = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      int ii, kk;
+      if (!d.transA) { ii = e % BM; kk = e / BM; } else { kk = e % BK; ii = e / BK; }
+      Are[kk][ii] = ra[q].x;
+      Aim[kk][ii] = ra[q].y;
+      const int kb = e % BK, jj = e / BK;
+      Bre[kb][jj] = rb[q].x;
+      Bim[kb][jj] = rb[q].y;
+    }
+  };
+  load_slice(0);
+  store_slice();
+  __syncthreads();
+  for (int k0 = 0; k0 < d.k; k0 += BK) {
+    const bool more = k0 + BK < d.k;
+    if (more) load_slice(k0 + BK);  // in flight during the MFMAs below
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kk = ks + (lane >> 4);
@@ -100,17 +103,29 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc* __restrict__ desc
         br[b] = Bre[kk][jj];
         bi[b] = Bim[kk][jj];
       }
+      // issue order keeps 7 independent MFMAs between two updates of one accumulator
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          accr[a][b] = mfma(ar[a], br[b], accr[a][b]);
-          accr[a][b] = mfma(-ai[a], bi[b], accr[a][b]);
-          acci[a][b] = mfma(ar[a], bi[b], acci[a][b]);
-          acci[a][b] = mfma(ai[a], br[b], acci[a][b]);
-        }
+        for (int b = 0; b < 2; ++b) accr[a][b] = mfma(ar[a], br[b], accr[a][b]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acci[a][b] = mfma(ar[a], bi[b], acci[a][b]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) accr[a][b] = mfma(-ai[a], bi[b], accr[a][b]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acci[a][b] = mfma(ai[a], br[b], acci[a][b]);
     }
     __syncthreads();
+    if (more) {
+      store_slice();
+      __syncthreads();
+    }
   }
   // epilogue: register r of a lane holds row (lane/16) + 4r, column lane%16 of each 16 x 16 block
   const bool zero_beta = (d.beta.x == 0.0 && d.beta.y == 0.0);
@@ -132,6 +147,21 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc* __restrict__ desc
     }
 }
 
+// C = alpha * sum_s W_s + beta * C over S partial products (m x n, ld m each)
+__global__ __launch_bounds__(256) void k_splitk_reduce(cplx* __restrict__ C, int ldc, int m, int n,
+                                                       const cplx* __restrict__ W, int S, cplx alpha, cplx beta) {
+  const int64_t total = (int64_t)m * n;
+  for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    cplx acc = mkc(0, 0);
+    for (int q = 0; q < S; ++q) acc = cadd(acc, W[e + q * total]);
+    const int i = (int)(e % m), j = (int)(e / m);
+    cplx* c = C + i + (size_t)j * ldc;
+    cplx v = cmul(alpha, acc);
+    if (!(beta.x == 0.0 && beta.y == 0.0)) v = cadd(v, cmul(beta, *c));
+    *c = v;
+  }
+}
+
 }  // namespace
 
 namespace qps {
@@ -142,20 +172,77 @@ hipError_t launch_zgemm(const GemmDesc* d, int nd, int max_tiles, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDesc>& v, hipStream_t s) {
-  if (v.empty()) return hipSuccess;
-  int max_tiles = 0;
+static int tiles_of(const GemmDesc& g) { return ((g.m + BM - 1) / BM) * ((g.n + BN - 1) / BN); }
+
+hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDesc>& v0, hipStream_t s, DevBuf* ws) {
+  if (v0.empty()) return hipSuccess;
   double flops = 0.0, bytes = 0.0;
-  for (const auto& g : v) {
-    int t = ((g.m + BM - 1) / BM) * ((g.n + BN - 1) / BN);
-    if (t > max_tiles) max_tiles = t;
+  int64_t total_tiles = 0;
+  for (const auto& g : v0) {
     flops += 8.0 * g.m * (double)g.n * g.k;
     bytes += 16.0 * ((double)g.m * g.k + (double)g.k * g.n + 2.0 * g.m * g.n);
+    total_tiles += tiles_of(g);
   }
+  // split-K when there are too few output tiles to occupy the chip and the inner dimension is
+  // long: partial products go to a workspace and a second kernel sums them in a fixed order.
+  const int64_t target = 1024;
+  std::vector<int> split(v0.size(), 1);
+  int64_t wtot = 0;
+  for (size_t i = 0; i < v0.size(); ++i) {
+    const GemmDesc& g = v0[i];
+    if (!ws || total_tiles >= target || g.k < 4096) continue;
+    int S = (int)std::min<int64_t>(16, (target + total_tiles - 1) / total_tiles);
+    S = std::min(S, g.k / 1024);
+    if (S >= 2) {
+      split[i] = S;
+      wtot += (int64_t)S * g.m * g.n;
+    }
+  }
+  if (wtot > 0) {
+    hipError_t e = ws->reserve(sizeof(cplx) * wtot);
+    if (e != hipSuccess) return e;
+  }
+  struct Red { cplx* C; int ldc, m, n; const cplx* W; int S; cplx alpha, beta; };
+  std::vector<Red> reds;
+  std::vector<GemmDesc> v;
+  int64_t woff = 0;
+  for (size_t i = 0; i < v0.size(); ++i) {
+    const GemmDesc& g = v0[i];
+    const int S = split[i];
+    if (S == 1) {
+      v.push_back(g);
+      continue;
+    }
+    cplx* W = ws->as<cplx>() + woff;
+    woff += (int64_t)S * g.m * g.n;
+    reds.push_back({g.C, g.ldc, g.m, g.n, W, S, g.alpha, g.beta});
+    const int kc = (g.k + S - 1) / S;
+    for (int q = 0; q < S; ++q) {
+      GemmDesc h = g;
+      const int k0 = q * kc;
+      h.k = std::max(0, std::min(kc, g.k - k0));
+      h.A = g.transA ? g.A + k0 : g.A + (size_t)k0 * g.lda;
+      h.B = g.B + k0;
+      h.C = W + (int64_t)q * g.m * g.n;
+      h.ldc = g.m;
+      h.alpha = mkc(1, 0);
+      h.beta = mkc(0, 0);
+      v.push_back(h);
+    }
+  }
+  int max_tiles = 0;
+  for (const auto& g : v) max_tiles = std::max(max_tiles, tiles_of(g));
   hipError_t e = upload(arena, v, s);
   if (e != hipSuccess) return e;
   ProfScope ps("zgemm", s, flops, bytes);
-  return launch_zgemm(arena.as<GemmDesc>(), (int)v.size(), max_tiles, s);
+  e = launch_zgemm(arena.as<GemmDesc>(), (int)v.size(), max_tiles, s);
+  if (e != hipSuccess) return e;
+  for (const auto& r : reds) {
+    const int64_t tot = (int64_t)r.m * r.n;
+    const int grid = (int)std::min<int64_t>(8192, (tot + 255) / 256);
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(grid), dim3(256), 0, s, r.C, r.ldc, r.m, r.n, r.W, r.S, r.alpha, r.beta);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace qps

@@ -36,7 +36,7 @@ struct hbs_handle {
   std::vector<qps::Level> lv;  // lv[1..L]
   int nroot = 0;
   qps::DevBuf Rinv, Rfwd;
-  qps::DevBuf arena, work, scratch;
+  qps::DevBuf arena, work, scratch, splitws;
   qps::DevBuf ab_up, ab_x0, ab_x1, ab_root;  // apply workspaces
   hbs_stats_t stats{};
   int64_t factor_bytes = 0;

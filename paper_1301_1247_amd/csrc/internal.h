@@ -128,7 +128,7 @@ hipError_t launch_hankel(const double* x, int64_t n, cplx* out, hipStream_t s);
 hipError_t launch_entries(const Geo& g, const int* rows, const int* cols, int64_t n, cplx* out, hipStream_t s);
 
 // gemm helper: build descriptors on the host, upload, launch
-hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDesc>& v, hipStream_t s);
+hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDesc>& v, hipStream_t s, DevBuf* ws = nullptr);
 hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDesc>& v, hipStream_t s, bool* singular);
 
 }  // namespace qps

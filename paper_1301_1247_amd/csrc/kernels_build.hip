@@ -108,20 +108,21 @@ __global__ __launch_bounds__(NT) void k_sketch(const SketchDesc* __restrict__ de
 // Rank: the first p with |R_pp| <= tol |R_00| (at least 1).
 constexpr int CPQR_MAXN = 2048;
 constexpr int CPQR_MAXS = 4608;
-__global__ __launch_bounds__(NT) void k_cpqr(const CpqrDesc* __restrict__ descs, double tol, int* __restrict__ k_out) {
+constexpr int NTQ = 1024;
+__global__ __launch_bounds__(NTQ) void k_cpqr(const CpqrDesc* __restrict__ descs, double tol, int* __restrict__ k_out) {
   const CpqrDesc d = descs[blockIdx.x];
   const int s = d.s, n = d.n;
   cplx* Z = d.z;
   __shared__ double cn[CPQR_MAXN];
   __shared__ int perm[CPQR_MAXN];
   __shared__ cplx v[CPQR_MAXS];
-  __shared__ double red_v[NT / 64];
-  __shared__ int red_i[NT / 64];
+  __shared__ double red_v[NTQ / 64];
+  __shared__ int red_i[NTQ / 64];
   __shared__ double sh_tau, sh_r00;
   __shared__ int sh_piv, sh_stop;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int nw = NT / 64;
-  for (int j = tid; j < n; j += NT) perm[j] = j;
+  const int nw = NTQ / 64;
+  for (int j = tid; j < n; j += NTQ) perm[j] = j;
   for (int j = wv; j < n; j += nw) {
     double a = 0.0;
     for (int i = lane; i < s; i += 64) a += cabs2(Z[i + (size_t)j * s]);
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(NT) void k_cpqr(const CpqrDesc* __restrict__ descs,
     // pivot: argmax over j in [p, n)
     double bv = -1.0;
     int bi = n;
-    for (int j = p + tid; j < n; j += NT) {
+    for (int j = p + tid; j < n; j += NTQ) {
       const double c = cn[j];
       if (c > bv || (c == bv && j < bi)) { bv = c; bi = j; }
     }
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(NT) void k_cpqr(const CpqrDesc* __restrict__ descs,
     if (sh_stop) { k = (p == 0) ? 1 : p; break; }
     const int jp = sh_piv;
     if (jp != p) {
-      for (int i = tid; i < s; i += NT) {
+      for (int i = tid; i < s; i += NTQ) {
         cplx t = Z[i + (size_t)p * s];
         Z[i + (size_t)p * s] = Z[i + (size_t)jp * s];
         Z[i + (size_t)jp * s] = t;
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(NT) void k_cpqr(const CpqrDesc* __restrict__ descs,
     }
     __syncthreads();
     // Householder vector of x = Z[p:s, p]
-    for (int i = p + tid; i < s; i += NT) v[i] = Z[i + (size_t)p * s];
+    for (int i = p + tid; i < s; i += NTQ) v[i] = Z[i + (size_t)p * s];
     __syncthreads();
     if (wv == 0) {
       double a = 0.0;
@@ -210,20 +211,20 @@ __global__ __launch_bounds__(NT) void k_cpqr(const CpqrDesc* __restrict__ descs,
   for (int i = k - 1; i >= 0; --i) {
     const cplx zii = Z[i + (size_t)i * s];
     const cplx rinv = cabs2(zii) > 0.0 ? cinv(zii) : mkc(0.0, 0.0);
-    for (int j = k + tid; j < n; j += NT) {
+    for (int j = k + tid; j < n; j += NTQ) {
       cplx* col = Z + (size_t)j * s;
       col[i] = cmul(col[i], rinv);
     }
     __syncthreads();
     const int cnt = (n - k) * i;
-    for (int e = tid; e < cnt; e += NT) {
+    for (int e = tid; e < cnt; e += NTQ) {
       const int l = e % i, j = k + e / i;
       cplx* col = Z + (size_t)j * s;
       col[l] = csub(col[l], cmul(Z[l + (size_t)i * s], col[i]));
     }
     __syncthreads();
   }
-  for (int j = tid; j < n; j += NT) d.perm[j] = perm[j];
+  for (int j = tid; j < n; j += NTQ) d.perm[j] = perm[j];
   if (tid == 0) k_out[blockIdx.x] = k;
 }
 
@@ -257,9 +258,13 @@ __global__ void k_gather_idx(const int* __restrict__ src, const int* __restrict_
 // ---------------------------------------------------------------- blocked Gauss-Jordan
 constexpr int GJ_NB = 32;
 
-// Sweep the pivots of panel columns [c0, c0+nb) within the panel (one workgroup per matrix).
-__global__ __launch_bounds__(NT) void k_gj_panel(const InvDesc* __restrict__ descs, int c0, int* __restrict__ ipiv_all,
-                                                 int maxn, int* __restrict__ info) {
+// Sweep the pivots of panel columns [c0, c0+nb) within the panel (one workgroup of 1024 threads
+// per matrix).  Per pivot: arg-max search, then the pivot-row swap and scaling (one thread per
+// panel column), then the elimination with one thread per row (each thread reads its own
+// multiplier before overwriting column p, so no barrier is needed between the two).
+constexpr int NTP = 1024;
+__global__ __launch_bounds__(NTP) void k_gj_panel(const InvDesc* __restrict__ descs, int c0, int* __restrict__ ipiv_all,
+                                                  int maxn, int* __restrict__ info) {
   const InvDesc d = descs[blockIdx.x];
   const int n = d.n;
   if (c0 >= n) return;
@@ -267,69 +272,50 @@ __global__ __launch_bounds__(NT) void k_gj_panel(const InvDesc* __restrict__ des
   const int ld = d.ld;
   cplx* A = d.a;
   int* ipiv = ipiv_all + (size_t)blockIdx.x * maxn;
-  __shared__ double red_v[NT / 64];
-  __shared__ int red_i[NT / 64];
-  __shared__ int sh_piv;
-  __shared__ cplx sh_d;
+  __shared__ double red_v[NTP / 64];
+  __shared__ int red_i[NTP / 64];
   __shared__ cplx rowp[GJ_NB];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int w = c1 - c0;
   for (int p = c0; p < c1; ++p) {
     double bv = -1.0;
     int bi = n;
-    for (int i = p + tid; i < n; i += NT) {
+    for (int i = p + tid; i < n; i += NTP) {
       const double a = cabs2(A[i + (size_t)p * ld]);
       if (a > bv || (a == bv && i < bi)) { bv = a; bi = i; }
     }
     wave_argmax(bv, bi);
     if (lane == 0) { red_v[wv] = bv; red_i[wv] = bi; }
     __syncthreads();
+    double b = red_v[0];
+    int r = red_i[0];
+    for (int q = 1; q < NTP / 64; ++q)
+      if (red_v[q] > b || (red_v[q] == b && red_i[q] < r)) { b = red_v[q]; r = red_i[q]; }
+    if (!(b > 0.0)) r = p;
+    const cplx piv = A[r + (size_t)p * ld];
+    const cplx dd = (cabs2(piv) > 0.0) ? cinv(piv) : mkc(0.0, 0.0);
+    __syncthreads();  // every thread has read the pivot before rows p, r change
     if (tid == 0) {
-      double b = red_v[0];
-      int bj = red_i[0];
-      for (int q = 1; q < NT / 64; ++q)
-        if (red_v[q] > b || (red_v[q] == b && red_i[q] < bj)) { b = red_v[q]; bj = red_i[q]; }
-      if (!(b > 0.0)) { info[blockIdx.x] = p + 1; bj = p; }
-      sh_piv = bj;
-      ipiv[p] = bj;
+      ipiv[p] = r;
+      if (!(b > 0.0)) info[blockIdx.x] = p + 1;
+    }
+    // swap rows p, r in the panel and scale the new pivot row
+    for (int j = c0 + tid; j < c1; j += NTP) {
+      const cplx vr = A[r + (size_t)j * ld];
+      const cplx vp = A[p + (size_t)j * ld];
+      const cplx sc = (j == p) ? dd : cmul(vr, dd);
+      rowp[j - c0] = sc;
+      A[p + (size_t)j * ld] = sc;
+      if (r != p) A[r + (size_t)j * ld] = vp;
     }
     __syncthreads();
-    const int r = sh_piv;
-    if (r != p) {
-      for (int j = c0 + tid; j < c1; j += NT) {
-        cplx t = A[p + (size_t)j * ld];
-        A[p + (size_t)j * ld] = A[r + (size_t)j * ld];
-        A[r + (size_t)j * ld] = t;
-      }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      const cplx app = A[p + (size_t)p * ld];
-      sh_d = (cabs2(app) > 0.0) ? cinv(app) : mkc(0.0, 0.0);
-    }
-    __syncthreads();
-    const cplx dd = sh_d;
-    // scaled pivot row (panel columns)
-    for (int j = c0 + tid; j < c1; j += NT) {
-      cplx v = (j == p) ? dd : cmul(A[p + (size_t)j * ld], dd);
-      rowp[j - c0] = v;
-      A[p + (size_t)j * ld] = v;
-    }
-    __syncthreads();
-    // eliminate column p from all other rows (panel columns other than p) ...
-    const int total = n * w;
-    for (int e = tid; e < total; e += NT) {
-      const int i = e % n, jj = e / n;
-      const int j = c0 + jj;
-      if (i == p || j == p) continue;
-      const cplx f = A[i + (size_t)p * ld];
-      A[i + (size_t)j * ld] = csub(A[i + (size_t)j * ld], cmul(f, rowp[jj]));
-    }
-    __syncthreads();
-    // ... then replace column p by the corresponding column of the inverse
-    for (int i = tid; i < n; i += NT) {
+    // eliminate column p from every other row; column p becomes the inverse's column
+    for (int i = tid; i < n; i += NTP) {
       if (i == p) continue;
       const cplx f = A[i + (size_t)p * ld];
+      for (int j = c0; j < c1; ++j) {
+        if (j == p) continue;
+        A[i + (size_t)j * ld] = csub(A[i + (size_t)j * ld], cmul(f, rowp[j - c0]));
+      }
       A[i + (size_t)p * ld] = cmul(mkc(-f.x, -f.y), dd);
     }
     __syncthreads();
@@ -458,7 +444,7 @@ hipError_t launch_sketch(const SketchDesc* d, int nd, int max_s, int max_n, uint
 }
 hipError_t launch_cpqr(const CpqrDesc* d, int nd, double tol, int* k_out, hipStream_t s) {
   if (nd == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cpqr, dim3(nd), dim3(NT), 0, s, d, tol, k_out);
+  hipLaunchKernelGGL(k_cpqr, dim3(nd), dim3(NTQ), 0, s, d, tol, k_out);
   return hipGetLastError();
 }
 hipError_t launch_buildP(const PDesc* d, int nd, int max_elems, hipStream_t s) {
@@ -483,7 +469,7 @@ hipError_t launch_zinv(const InvDesc* d, int nd, int max_n, cplx* tbuf, int* ipi
   hipError_t e = hipMemsetAsync(info, 0, sizeof(int) * nd, s);
   if (e != hipSuccess) return e;
   for (int c0 = 0; c0 < max_n; c0 += GJ_NB) {
-    hipLaunchKernelGGL(k_gj_panel, dim3(nd), dim3(NT), 0, s, d, c0, ipiv, max_n, info);
+    hipLaunchKernelGGL(k_gj_panel, dim3(nd), dim3(NTP), 0, s, d, c0, ipiv, max_n, info);
     hipLaunchKernelGGL(k_gj_swapsave, dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, c0, ipiv, max_n, tbuf);
     hipLaunchKernelGGL(k_gj_update, dim3((max_n + 63) / 64, (max_n + 15) / 16, nd), dim3(NT), 0, s, d, c0, max_n,
                        (const cplx*)tbuf);

@@ -251,7 +251,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   {
     std::vector<GemmDesc> g = {gd(CL, M2, 0, X, N, G1, M2, M2, (int)W, N, one, zero),
                                gd(CRm, M2, 0, X, N, G2, M2, M2, (int)W, N, one, zero)};
-    CK(gemm_batched(h->arena, g, st));
+    CK(gemm_batched(h->arena, g, st, &h->splitws));
     CK(hipStreamSynchronize(st));
   }
   CK(launch_form_S(Q, dgal, ng, G1, G2, S, st));
@@ -272,7 +272,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     for (int gg = 0; gg < ng; ++gg)
       g.push_back(gd(S + (size_t)gg * M2 * M2, M2, 0, rhs + (size_t)goff[gg] * M2, M2, out + (size_t)goff[gg] * M2, M2, M2,
                      gcnt[gg], M2, alpha, zero));
-    CK(gemm_batched(h->arena, g, st));
+    CK(gemm_batched(h->arena, g, st, &h->splitws));
     CK(hipStreamSynchronize(st));
     return HBS_OK;
   };
@@ -282,7 +282,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   CK(launch_axpby(N, nang, one, X + (size_t)M4 * N, N, zero, eta, N, st));
   {
     std::vector<GemmDesc> g = {gd(X, N, 0, stk, M4, eta, N, N, nang, M4, mone, one)};
-    CK(gemm_batched(h->arena, g, st));
+    CK(gemm_batched(h->arena, g, st, &h->splitws));
     CK(hipStreamSynchronize(st));
   }
   // iterative refinement of the bordered system
@@ -301,7 +301,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       std::vector<GemmDesc> g = {gd(Y, N, 0, stk, M4, R1, N, N, nang, M4, mone, one),
                                  gd(CL, M2, 0, eta, N, T1, M2, M2, nang, N, one, zero),
                                  gd(CRm, M2, 0, eta, N, T2, M2, M2, nang, N, one, zero)};
-      CK(gemm_batched(h->arena, g, st));
+      CK(gemm_batched(h->arena, g, st, &h->splitws));
       CK(hipStreamSynchronize(st));
     }
     CK(launch_resid2(Q, nang, dalcol, T1, T2, xi, R2, st));
@@ -318,7 +318,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     {
       std::vector<GemmDesc> g = {gd(CL, M2, 0, Z1, N, U1, M2, M2, nang, N, one, zero),
                                  gd(CRm, M2, 0, Z1, N, U2, M2, M2, nang, N, one, zero)};
-      CK(gemm_batched(h->arena, g, st));
+      CK(gemm_batched(h->arena, g, st, &h->splitws));
       CK(hipStreamSynchronize(st));
     }
     CK(launch_combine_c(M2, nang, dalcol, U1, M2, U2, M2, R2, Wv, st));
@@ -327,7 +327,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     CK(launch_axpby(N, nang, one, Z1, N, one, eta, N, st));
     {
       std::vector<GemmDesc> g = {gd(X, N, 0, stk, M4, eta, N, N, nang, M4, mone, one)};
-      CK(gemm_batched(h->arena, g, st));
+      CK(gemm_batched(h->arena, g, st, &h->splitws));
       CK(hipStreamSynchronize(st));
     }
     CK(launch_axpby(M2, nang, one, dxi, M2, one, xi, M2, st));
