@@ -188,10 +188,13 @@ hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDesc>& v0, hipStrea
   const int64_t target = 1024;
   std::vector<int> split(v0.size(), 1);
   int64_t wtot = 0;
+  (void)total_tiles;
   for (size_t i = 0; i < v0.size(); ++i) {
     const GemmDesc& g = v0[i];
-    if (!ws || total_tiles >= target || g.k < 4096) continue;
-    int S = (int)std::min<int64_t>(16, (target + total_tiles - 1) / total_tiles);
+    // a descriptor with few tiles and a long inner dimension is the critical path of the launch
+    const int64_t tg = tiles_of(g);
+    if (!ws || tg >= target / 2 || g.k < 4096) continue;
+    int S = (int)std::min<int64_t>(16, (target + tg - 1) / tg);
     S = std::min(S, g.k / 1024);
     if (S >= 2) {
       split[i] = S;
