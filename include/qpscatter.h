@@ -58,6 +58,9 @@ typedef struct {
   const double* curvature;  /* KRESS only: signed curvature at the N nodes (ptr_mode) */
   void* stream;             /* hipStream_t, NULL = default stream */
   uint64_t seed;            /* seed of the sketching matrices of the interpolative decompositions */
+  double far_radius;        /* > 0: every skeleton also represents sources outside the circle of this
+                               radius about the obstacle's centre (needed by qp_solve with P >= 1,
+                               whose neighbour images must lie outside it); 0 = off */
 } hbs_opts;
 
 typedef struct {

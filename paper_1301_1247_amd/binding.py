@@ -37,7 +37,8 @@ class HBSError(RuntimeError):
 class HbsOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("quad", C.c_int32), ("compress", C.c_int32), ("leaf_size", C.c_int32),
                 ("proxy_ratio", C.c_double), ("proxy_min", C.c_int32), ("ptr_mode", C.c_int32),
-                ("curvature", C.c_void_p), ("stream", C.c_void_p), ("seed", C.c_uint64)]
+                ("curvature", C.c_void_p), ("stream", C.c_void_p), ("seed", C.c_uint64),
+                ("far_radius", C.c_double)]
 
 
 class QpOpts(C.Structure):
@@ -130,7 +131,8 @@ class Handle:
     """A built compressed inverse (hbs_build) with its apply / solve calls."""
 
     def __init__(self, nodes, weights, normals, omega, tol, quad="kr6", compress=None, leaf_size=64,
-                 curvature=None, device=False, stream=None, proxy_ratio=2.0, proxy_min=64, seed=0x5EED1301):
+                 curvature=None, device=False, stream=None, proxy_ratio=2.0, proxy_min=64, seed=0x5EED1301,
+                 far_radius=0.0):
         if compress is None:
             compress = "exact" if quad == "kress" else "proxy"
         self.device = bool(device)
@@ -153,7 +155,7 @@ class Handle:
         o = hbs_opts(quad=QUAD[quad], compress=COMPRESS[compress], leaf_size=int(leaf_size),
                      proxy_ratio=float(proxy_ratio), proxy_min=int(proxy_min),
                      ptr_mode=PTR_DEVICE if self.device else PTR_HOST,
-                     curvature=_ptr(curvature), stream=st, seed=int(seed))
+                     curvature=_ptr(curvature), stream=st, seed=int(seed), far_radius=float(far_radius))
         h = C.c_void_p()
         _check(_lib.hbs_build(_ptr(nodes), _ptr(weights), _ptr(normals), N, float(omega), float(tol), C.byref(o),
                               C.byref(h)))

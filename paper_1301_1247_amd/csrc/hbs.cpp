@@ -78,6 +78,28 @@ int build(hbs_handle* h) {
   const int pmin = h->opts.proxy_min;
   const double om = h->omega;
 
+  // far-field circle (neighbour images lie outside radius far_radius about the obstacle's centre)
+  {
+    double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+    for (int64_t i = 0; i < N; ++i) {
+      x0 = std::min(x0, h->hx[i]); x1 = std::max(x1, h->hx[i]);
+      y0 = std::min(y0, h->hy[i]); y1 = std::max(y1, h->hy[i]);
+    }
+    h->c0x = 0.5 * (x0 + x1);
+    h->c0y = 0.5 * (y0 + y1);
+    double r = 0;
+    for (int64_t i = 0; i < N; ++i) r = std::max(r, std::hypot(h->hx[i] - h->c0x, h->hy[i] - h->c0y));
+    h->robs = r;
+    if (h->opts.far_radius > 0 && !(h->opts.far_radius > 1.05 * r)) {
+      set_error("hbs_build: far_radius must exceed the obstacle's radius about its centre");
+      return HBS_E_INVALID_ARG;
+    }
+  }
+  const bool far_on = h->opts.far_radius > 0;
+  const double Rfar = far_on ? std::sqrt(h->robs * h->opts.far_radius) : 0.0;
+  const int npfar = far_on ? std::max(pmin, 2 * (int)std::ceil(om * Rfar + std::log(1.0 / h->tol) /
+                                                                  std::log(Rfar / h->robs)) + 8) : 0;
+
   // box ranges and bounding circles of the original points
   for (int l = 1; l <= L; ++l) {
     Level& V = h->lv[l];
@@ -188,7 +210,7 @@ int build(hbs_handle* h) {
     }
 
     // ---- compression matrices
-    std::vector<int> nnear(nb), np(nb), m(nb), s(nb);
+    std::vector<int> nnear(nb), np(nb), npf(nb), m(nb), s(nb);
     std::vector<int64_t> noff(nb + 1, 0), woff(nb + 1, 0), zoff(nb + 1, 0);
     std::vector<int> hnear;
     for (int b = 0; b < nb; ++b) {
@@ -210,7 +232,11 @@ int build(hbs_handle* h) {
       nnear[b] = cnt;
       const bool full = (cnt == total_other);
       np[b] = full ? 0 : std::max(pmin, (int)std::ceil(1.5 * om * Rp) + 50);
-      m[b] = 2 * cnt + 3 * np[b];
+      // sources beyond far_radius must be represented too: by the box's own proxies when its
+      // circle lies inside far_radius, else by proxies on the far-field circle
+      const bool inside = !full && std::hypot(V.cx[b] - h->c0x, V.cy[b] - h->c0y) + Rp < h->opts.far_radius;
+      npf[b] = (far_on && !inside) ? npfar : 0;
+      m[b] = 2 * cnt + 3 * np[b] + 3 * npf[b];
       s[b] = (m[b] > 2 * V.n[b] + 8) ? 2 * V.n[b] + 8 : m[b];
       noff[b + 1] = noff[b] + cnt;
       woff[b + 1] = woff[b] + (int64_t)m[b] * V.n[b];
@@ -246,6 +272,12 @@ int build(hbs_handle* h) {
         pd.push_back({dact + V.aoff[b], dwt + woff[b], V.n[b], m[b], 2 * nnear[b], np[b], V.cx[b], V.cy[b],
                       ratio * V.rad[b]});
         maxp = std::max(maxp, np[b] * V.n[b]);
+      }
+      for (int b = 0; b < nb; ++b) {
+        if (npf[b] == 0) continue;
+        pd.push_back({dact + V.aoff[b], dwt + woff[b], V.n[b], m[b], 2 * nnear[b] + 3 * np[b], npf[b], h->c0x, h->c0y,
+                      Rfar});
+        maxp = std::max(maxp, npf[b] * V.n[b]);
       }
       if (!pd.empty()) {
         CK(up_sync(arena, pd, st));
@@ -447,6 +479,42 @@ int build(hbs_handle* h) {
       return _e == hipErrorOutOfMemory ? HBS_E_OOM : HBS_E_DEVICE;                                \
     }                                                                                             \
   } while (0)
+
+// X (N x r) = U Z with U the nested interpolation P^(L) ... P^(1) from the root's active set
+// (the level-1 skeletons) to all nodes: the downward pass of the factorization without its
+// diagonal terms.
+int apply_interp(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx, int64_t r) {
+  if (r <= 0) return HBS_OK;
+  hipStream_t st = h->stream;
+  const int L = h->L;
+  auto& lv = h->lv;
+  int64_t xmax = 1;
+  for (int l = 1; l < L; ++l) xmax = std::max<int64_t>(xmax, lv[l].ntot);
+  CK(h->ab_x0.reserve(sizeof(cplx) * xmax * r));
+  CK(h->ab_x1.reserve(sizeof(cplx) * xmax * r));
+  auto xbuf = [&](int l) { return (l & 1) ? h->ab_x1.as<cplx>() : h->ab_x0.as<cplx>(); };
+  std::vector<GemmDesc> all;
+  std::vector<LaunchRec> recs;
+  for (int l = 1; l <= L; ++l) {
+    Level& V = lv[l];
+    const cplx* xin = (l == 1) ? Z : xbuf(l - 1);
+    const int ldxin = (l == 1) ? (int)ldz : (int)V.ktot;
+    cplx* out = (l == L) ? X : xbuf(l);
+    const int64_t ldo = (l == L) ? ldx : V.ntot;
+    LaunchRec rec{all.size(), 0, 0, 0.0};
+    for (int b = 0; b < V.nb; ++b) {
+      all.push_back(gd(V.P.as<cplx>() + V.oP[b], V.n[b], 0, xin + V.soff[b], ldxin, out + V.aoff[b], (int)ldo, V.n[b],
+                       (int)r, V.k[b]));
+      rec.max_tiles = std::max(rec.max_tiles, tiles_of(all.back()));
+    }
+    rec.cnt = (int)(all.size() - rec.off);
+    recs.push_back(rec);
+  }
+  CK(upload(h->arena, all, st));
+  for (auto& rc : recs) CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.max_tiles, st));
+  CK(hipStreamSynchronize(st));
+  return HBS_OK;
+}
 
 int apply_factors(hbs_handle* h, bool inv, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r) {
   if (r <= 0) return HBS_OK;

@@ -39,6 +39,7 @@ struct hbs_handle {
   qps::DevBuf arena, work, scratch, splitws;
   qps::DevBuf ab_up, ab_x0, ab_x1, ab_root;  // apply workspaces
   hbs_stats_t stats{};
+  double c0x = 0, c0y = 0, robs = 0;  // obstacle centre and radius about it
   int64_t factor_bytes = 0;
   double build_seconds = 0;
 };
@@ -47,6 +48,7 @@ namespace qps {
 // apply the telescoping factorization: inverse (F^T, E, G, root inverse) or forward (P^T, P, D, root coupling)
 int apply_factors(hbs_handle* h, bool inverse, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r);
 int build(hbs_handle* h);
+int apply_interp(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx, int64_t r);
 int qp_max_modes_impl(double om, double period);
 struct QPPlan;
 int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, const qp_opts* o, cplx* eta_out,

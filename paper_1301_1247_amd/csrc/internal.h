@@ -125,6 +125,7 @@ hipError_t launch_zgemm(const GemmDesc* d, int nd, int max_tiles, hipStream_t s)
 // blocked Gauss-Jordan inversion; tbuf: nd * 32 * max_n complex; ipiv: nd * max_n ints; info: nd ints
 hipError_t launch_zinv(const InvDesc* d, int nd, int max_n, cplx* tbuf, int* ipiv, int* info, hipStream_t s);
 hipError_t launch_hankel(const double* x, int64_t n, cplx* out, hipStream_t s);
+hipError_t launch_eval_shift(const Geo& g, const int* rows, int nr, double shift, cplx* out, int ld, hipStream_t s);
 hipError_t launch_entries(const Geo& g, const int* rows, const int* cols, int64_t n, cplx* out, hipStream_t s);
 
 // gemm helper: build descriptors on the host, upload, launch

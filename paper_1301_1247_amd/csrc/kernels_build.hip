@@ -399,6 +399,20 @@ __global__ __launch_bounds__(NT) void k_gj_colperm(const InvDesc* __restrict__ d
   }
 }
 
+// out[r + c*ld] = K(y_rows[r], y_c + shift e_1, n_c) w_c for every node c: rows of the plain
+// trapezoid discretization of D - i omega S from a translated copy of the curve (Sec. 2.4, A_j).
+__global__ __launch_bounds__(NT) void k_eval_shift(Geo G, const int* __restrict__ rows, int nr, double shift,
+                                                   cplx* __restrict__ out, int ld) {
+  const int64_t total = (int64_t)nr * G.N;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int r = (int)(e % nr);
+    const int c = (int)(e / nr);
+    const int gr = rows[r];
+    const cplx K = helm_kernel(G.omega, G.x[gr] - (G.x[c] + shift), G.y[gr] - G.y[c], G.nx[c], G.ny[c]);
+    out[r + (size_t)c * ld] = cscale(K, G.w[c]);
+  }
+}
+
 __global__ void k_hankel(const double* __restrict__ x, int64_t n, cplx* __restrict__ out) {
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) {
     cplx h0, h1;
@@ -475,6 +489,11 @@ hipError_t launch_zinv(const InvDesc* d, int nd, int max_n, cplx* tbuf, int* ipi
                        (const cplx*)tbuf);
   }
   hipLaunchKernelGGL(k_gj_colperm, dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, ipiv, max_n);
+  return hipGetLastError();
+}
+hipError_t launch_eval_shift(const Geo& g, const int* rows, int nr, double shift, cplx* out, int ld, hipStream_t s) {
+  if (nr == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eval_shift, dim3(grid_for((int64_t)nr * g.N, 8192)), dim3(NT), 0, s, g, rows, nr, shift, out, ld);
   return hipGetLastError();
 }
 hipError_t launch_hankel(const double* x, int64_t n, cplx* out, hipStream_t s) {

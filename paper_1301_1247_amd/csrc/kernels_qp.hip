@@ -103,40 +103,35 @@ __device__ inline cplx q_entry(const QPGeo& Q, cplx alpha, int r, int c) {
   return mkc(h.x - 1.0, h.y);
 }
 
-// S_g = Q(alpha_g) - [C_L X_L + alpha C_L X_R - alpha^{-1} C_R X_L - C_R X_R],
-// G1 = C_L [X_L | X_R | ...], G2 = C_R [X_L | X_R | ...] (ld 2M).
-__global__ __launch_bounds__(NT) void k_form_S(QPGeo Q, const cplx* __restrict__ alphas, const cplx* __restrict__ G1,
+// S_g = Q(alpha_g) - C(alpha_g) X(alpha_g) with C(alpha) = c1 C1 + c2 C2, X(alpha) = X_L + alpha X_R:
+//   S_g = Q - [c1 (G1_L + alpha G1_R) + c2 (G2_L + alpha G2_R)],  G1 = C1 [X_L | X_R | ...], G2 = C2 [...]
+// (ld 2M).  coef holds (alpha, c1, c2) per group.
+__global__ __launch_bounds__(NT) void k_form_S(QPGeo Q, const cplx* __restrict__ coef, const cplx* __restrict__ G1,
                                                const cplx* __restrict__ G2, cplx* __restrict__ S) {
   const int g = blockIdx.y;
   const int M2 = 2 * Q.M;
-  const cplx al = alphas[g];
-  const cplx ai = cinv(al);
+  const cplx al = coef[3 * g], c1 = coef[3 * g + 1], c2 = coef[3 * g + 2];
   const int64_t total = (int64_t)M2 * M2;
   cplx* Sg = S + (size_t)g * total;
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int r = (int)(e % M2), c = (int)(e / M2);
-    const cplx ll = G1[r + (size_t)c * M2];
-    const cplx lr = G1[r + (size_t)(M2 + c) * M2];
-    const cplx rl = G2[r + (size_t)c * M2];
-    const cplx rr = G2[r + (size_t)(M2 + c) * M2];
-    cplx cx = cadd(ll, cmul(al, lr));
-    cx = csub(cx, cmul(ai, rl));
-    cx = csub(cx, rr);
+    const cplx x1 = cadd(G1[r + (size_t)c * M2], cmul(al, G1[r + (size_t)(M2 + c) * M2]));
+    const cplx x2 = cadd(G2[r + (size_t)c * M2], cmul(al, G2[r + (size_t)(M2 + c) * M2]));
+    const cplx cx = cadd(cmul(c1, x1), cmul(c2, x2));
     Sg[e] = csub(q_entry(Q, al, r, c), cx);
   }
 }
 
-// W[:, a] = U1[:, a] - alpha_a^{-1} U2[:, a]  (optionally R - (...)), columns of 2M rows
-__global__ __launch_bounds__(NT) void k_combine_c(int M2, int nang, const cplx* __restrict__ alpha_col,
-                                                  const cplx* __restrict__ U1, int64_t ld1, const cplx* __restrict__ U2,
-                                                  int64_t ld2, const cplx* __restrict__ R, cplx* __restrict__ W) {
-  const int64_t total = (int64_t)M2 * nang;
+// W[:, a] = c1_a U1[:, a] + c2_a U2[:, a]  (or R - (...) when R is given), rows of length `rows`
+__global__ __launch_bounds__(NT) void k_lincomb(int rows, int ncol, const cplx* __restrict__ c1, const cplx* __restrict__ c2,
+                                                int cs, const cplx* __restrict__ U1, int64_t ld1, const cplx* __restrict__ U2,
+                                                int64_t ld2, const cplx* R, int64_t ldr, cplx* W, int64_t ldw) {
+  const int64_t total = (int64_t)rows * ncol;
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-    const int r = (int)(e % M2), a = (int)(e / M2);
-    const cplx ai = cinv(alpha_col[a]);
-    cplx v = csub(U1[r + (size_t)a * ld1], cmul(ai, U2[r + (size_t)a * ld2]));
-    if (R) v = csub(R[r + (size_t)a * M2], v);
-    W[e] = v;
+    const int r = (int)(e % rows), a = (int)(e / rows);
+    cplx v = cadd(cmul(c1[a * cs], U1[r + (size_t)a * ld1]), cmul(c2[a * cs], U2[r + (size_t)a * ld2]));
+    if (R) v = csub(R[r + (size_t)a * ldr], v);
+    W[r + (size_t)a * ldw] = v;
   }
 }
 
@@ -152,8 +147,9 @@ __global__ __launch_bounds__(NT) void k_stack(int M2, int nang, const cplx* __re
   }
 }
 
-// R2[:, a] = -(T1 - alpha^{-1} T2)[:, a] - Q(alpha_a) xi[:, a]
+// R2[:, a] = -(c1_a T1 + c2_a T2)[:, a] - Q(alpha_a) xi[:, a]
 __global__ __launch_bounds__(NT) void k_resid2(QPGeo Q, int nang, const cplx* __restrict__ alpha_col,
+                                               const cplx* __restrict__ c1, const cplx* __restrict__ c2,
                                                const cplx* __restrict__ T1, const cplx* __restrict__ T2,
                                                const cplx* __restrict__ xi, cplx* __restrict__ R2) {
   const int M = Q.M, M2 = 2 * M;
@@ -161,12 +157,25 @@ __global__ __launch_bounds__(NT) void k_resid2(QPGeo Q, int nang, const cplx* __
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int r = (int)(e % M2), a = (int)(e / M2);
     const cplx al = alpha_col[a];
-    const cplx ai = cinv(al);
     const cplx* x = xi + (size_t)a * M2;
     const int m = r % M;
     cplx qx = cadd(cmul(q_entry(Q, al, r, m), x[m]), cmul(q_entry(Q, al, r, M + m), x[M + m]));
-    cplx cv = csub(T1[e], cmul(ai, T2[e]));
+    cplx cv = cadd(cmul(c1[a], T1[e]), cmul(c2[a], T2[e]));
     R2[e] = mkc(-cv.x - qx.x, -cv.y - qx.y);
+  }
+}
+
+// A_g = I + B_g for ng square n x n blocks (ld n), B_g at B + g*bstride with column stride ldb
+__global__ __launch_bounds__(NT) void k_eye_plus(int n, int ng, const cplx* __restrict__ B, int64_t ldb, int64_t bstride,
+                                                 cplx* __restrict__ A) {
+  const int64_t total = (int64_t)n * n * ng;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int g = (int)(e / ((int64_t)n * n));
+    const int64_t q = e % ((int64_t)n * n);
+    const int r = (int)(q % n), c = (int)(q / n);
+    cplx v = B[(size_t)g * bstride + r + (size_t)c * ldb];
+    if (r == c) v.x += 1.0;
+    A[e] = v;
   }
 }
 
@@ -277,16 +286,22 @@ hipError_t launch_gen_C(const QPGeo& q, int wall, double shift, cplx* C, hipStre
   hipLaunchKernelGGL(k_gen_C, dim3(grid_for((int64_t)q.N * q.M)), dim3(NT), 0, s, q, wall, shift, C);
   return hipGetLastError();
 }
-hipError_t launch_form_S(const QPGeo& q, const cplx* alphas, int ng, const cplx* G1, const cplx* G2, cplx* S, hipStream_t s) {
+hipError_t launch_form_S(const QPGeo& q, const cplx* coef, int ng, const cplx* G1, const cplx* G2, cplx* S, hipStream_t s) {
   if (ng == 0) return hipSuccess;
   int64_t tot = (int64_t)4 * q.M * q.M;
-  hipLaunchKernelGGL(k_form_S, dim3(grid_for(tot, 4096), ng), dim3(NT), 0, s, q, alphas, G1, G2, S);
+  hipLaunchKernelGGL(k_form_S, dim3(grid_for(tot, 4096), ng), dim3(NT), 0, s, q, coef, G1, G2, S);
   return hipGetLastError();
 }
-hipError_t launch_combine_c(int M2, int nang, const cplx* alpha_col, const cplx* U1, int64_t ld1, const cplx* U2, int64_t ld2,
-                            const cplx* R, cplx* W, hipStream_t s) {
-  if (nang == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_combine_c, dim3(grid_for((int64_t)M2 * nang)), dim3(NT), 0, s, M2, nang, alpha_col, U1, ld1, U2, ld2, R, W);
+hipError_t launch_lincomb(int rows, int ncol, const cplx* c1, const cplx* c2, int cs, const cplx* U1, int64_t ld1,
+                          const cplx* U2, int64_t ld2, const cplx* R, int64_t ldr, cplx* W, int64_t ldw, hipStream_t s) {
+  if ((int64_t)rows * ncol == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lincomb, dim3(grid_for((int64_t)rows * ncol)), dim3(NT), 0, s, rows, ncol, c1, c2, cs, U1, ld1, U2,
+                     ld2, R, ldr, W, ldw);
+  return hipGetLastError();
+}
+hipError_t launch_eye_plus(int n, int ng, const cplx* B, int64_t ldb, int64_t bstride, cplx* A, hipStream_t s) {
+  if ((int64_t)n * n * ng == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eye_plus, dim3(grid_for((int64_t)n * n * ng)), dim3(NT), 0, s, n, ng, B, ldb, bstride, A);
   return hipGetLastError();
 }
 hipError_t launch_stack(int M2, int nang, const cplx* alpha_col, const cplx* xi, cplx* st, hipStream_t s) {
@@ -294,10 +309,11 @@ hipError_t launch_stack(int M2, int nang, const cplx* alpha_col, const cplx* xi,
   hipLaunchKernelGGL(k_stack, dim3(grid_for((int64_t)M2 * nang)), dim3(NT), 0, s, M2, nang, alpha_col, xi, st);
   return hipGetLastError();
 }
-hipError_t launch_resid2(const QPGeo& q, int nang, const cplx* alpha_col, const cplx* T1, const cplx* T2, const cplx* xi,
-                         cplx* R2, hipStream_t s) {
+hipError_t launch_resid2(const QPGeo& q, int nang, const cplx* alpha_col, const cplx* c1, const cplx* c2, const cplx* T1,
+                         const cplx* T2, const cplx* xi, cplx* R2, hipStream_t s) {
   if (nang == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_resid2, dim3(grid_for((int64_t)2 * q.M * nang)), dim3(NT), 0, s, q, nang, alpha_col, T1, T2, xi, R2);
+  hipLaunchKernelGGL(k_resid2, dim3(grid_for((int64_t)2 * q.M * nang)), dim3(NT), 0, s, q, nang, alpha_col, c1, c2, T1, T2,
+                     xi, R2);
   return hipGetLastError();
 }
 hipError_t launch_axpby(int64_t rows, int cols, cplx a, const cplx* x, int64_t ldx, cplx b, cplx* y, int64_t ldy, hipStream_t s) {

@@ -88,19 +88,39 @@ int qp_contour_M(const hbs_handle* h, double period, const qp_opts* o) {
 }
 
 // All outputs in "caller order"; eta/xi/bragg are device pointers here (the C ABI stages host copies).
+//
+// With P neighbour images (Sec. 2.4) the obstacle block is A~(alpha) = A + sum_{j=+-1} alpha^j A_j.  The
+// skeletons of a handle built with far_radius represent the interaction of every box with sources
+// beyond that radius, so the rows of A_j factor through the nested interpolation U of the tree:
+// A_j = U A_j(J, :) with J the root's active set.  Then A~ = A + U R(alpha), R = alpha R_1 + alpha^{-1} R_{-1},
+// and (Eq. 3.2 with the sign of its second term corrected)
+//   A~^{-1} = A^{-1} - V K R A^{-1},  V = A^{-1} U,  K(alpha) = (I + R V)^{-1}  (root-size),
+// where V joins the single application of A^{-1}.  C~(alpha) = alpha^P C_L[dOmega + P d] - alpha^{-(P+1)} C_R[dOmega - P d].
 int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, const qp_opts* o, cplx* eta_out,
                   cplx* xi_out, cplx* bragg_out, int32_t* nlo_out, int32_t* nm_out, double* flux_out) {
   hipStream_t st = h->stream;
   const int N = (int)h->N;
   const int nang = (int)th.size();
   const double om = h->omega;
-  if (o->P != 0) {
-    set_error("qp_solve: only P = 0 is supported by this build");
+  const int P = o->P;
+  if (P != 0 && P != 1) {
+    set_error("qp_solve: P must be 0 or 1");
     return HBS_E_INVALID_ARG;
+  }
+  if (P == 1) {
+    if (!(h->opts.far_radius > 0)) {
+      set_error("qp_solve: P = 1 needs a handle built with hbs_opts.far_radius > 0");
+      return HBS_E_INVALID_ARG;
+    }
+    if (!(period - h->robs > h->opts.far_radius)) {
+      set_error("qp_solve: the neighbour images come closer than far_radius to the obstacle's centre");
+      return HBS_E_INVALID_ARG;
+    }
   }
   QPPlan pl;
   CR(qp_plan(h, period, o, &pl));
   const int M = pl.M, M2 = 2 * M, M4 = 4 * M;
+  const int nr = P ? h->nroot : 0;
   const double wood = o->wood_min_kn > 0 ? o->wood_min_kn : 0.75;
   // Bloch phases, Wood's check, grouping
   std::vector<zc> al(nang);
@@ -150,42 +170,67 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     cont[M + m] = toc(s);
     cont[2 * M + m] = toc(wk);
   }
-  // per-angle data in grouped order
-  std::vector<double> kx(nang), ky(nang), kapv(nang);
-  std::vector<cplx> alcol(nang), galc(ng);
+  // per-angle data in grouped order; C~(alpha) = c1 C1 + c2 C2 with c1 = alpha^P, c2 = -alpha^{-(P+1)}
+  std::vector<double> kx(nang), ky(nang);
+  std::vector<cplx> colc(5 * nang), gcoef(3 * ng + 4 * ng);
   std::vector<int> perm(nang), nlo(nang), nm(nang);
   const int maxm = qp_max_modes_impl(om, period);
+  auto c1_of = [&](zc a) { return P ? a : zc(1.0, 0.0); };
+  auto c2_of = [&](zc a) { return -std::pow(a, -(P + 1)); };
   for (int q = 0; q < nang; ++q) {
     const int a = order[q];
+    const zc ag = galpha[grp[a]];
     kx[q] = om * std::cos(th[a]);
     ky[q] = om * std::sin(th[a]);
-    kapv[q] = kx[q];
-    alcol[q] = toc(galpha[grp[a]]);
+    colc[q] = toc(ag);                        // alpha
+    colc[nang + q] = toc(c1_of(ag));          // c1
+    colc[2 * nang + q] = toc(c2_of(ag));      // c2
+    colc[3 * nang + q] = toc(1.0 / ag);       // alpha^{-1}
+    colc[4 * nang + q] = toc(-ag);            // -alpha (for in-place subtractions)
     perm[q] = a;
     const double kap = kx[q];
     nlo[q] = (int)std::ceil((-om - kap) * period / (2 * M_PI));
     int nhi = (int)std::floor((om - kap) * period / (2 * M_PI));
     nm[q] = std::min(maxm, nhi - nlo[q] + 1);
   }
-  for (int g = 0; g < ng; ++g) galc[g] = toc(galpha[g]);
+  for (int g = 0; g < ng; ++g) {
+    const zc ag = galpha[g];
+    gcoef[3 * g] = toc(ag);
+    gcoef[3 * g + 1] = toc(c1_of(ag));
+    gcoef[3 * g + 2] = toc(c2_of(ag));
+    // per-group scalars for the neighbour terms: alpha, alpha^{-1}, alpha^2, -alpha
+    gcoef[3 * ng + 4 * g] = toc(ag);
+    gcoef[3 * ng + 4 * g + 1] = toc(1.0 / ag);
+    gcoef[3 * ng + 4 * g + 2] = toc(ag * ag);
+    gcoef[3 * ng + 4 * g + 3] = toc(-ag);
+  }
+  const cplx onec = mkc(1, 0), minus1c = mkc(-1, 0);
 
   // device workspace
-  const int64_t W = (int64_t)M4 + nang;
+  const int64_t W = (int64_t)M4 + nang + nr;
+  const int colB = M4, colU = M4 + nang;
+  const int nrr = std::max(nr, 1);
   std::vector<size_t> sizes = {
-      sizeof(cplx) * 3 * M,                 // 0 contour
-      sizeof(double) * nang * 3,            // 1 kx, ky, kappa
-      sizeof(cplx) * (nang + ng),           // 2 alpha per column, per group
-      sizeof(int) * nang * 3,               // 3 perm, nlo, nmodes
-      sizeof(cplx) * N * W,                 // 4 Y
-      sizeof(cplx) * N * W,                 // 5 X
-      sizeof(cplx) * (size_t)M2 * N * 2,    // 6 C_L, C_R
-      sizeof(cplx) * (size_t)M2 * W * 2,    // 7 G1, G2
-      sizeof(cplx) * (size_t)M2 * M2 * ng,  // 8 S
-      sizeof(cplx) * (size_t)M2 * nang * 8, // 9 xi, W, T1, T2, R2, U1, U2, dxi
-      sizeof(cplx) * (size_t)M4 * nang,     // 10 stack
-      sizeof(cplx) * (size_t)N * nang * 4,  // 11 eta, F/R1, Z1, perm staging
-      sizeof(cplx) * 2 * maxm * nang * 2,   // 12 bragg (grouped, caller order)
-      sizeof(double) * nang * 3};           // 13 norms
+      sizeof(cplx) * 3 * M,                          // 0 contour
+      sizeof(double) * nang * 3,                     // 1 kx, ky, kappa
+      sizeof(cplx) * (5 * nang + 7 * ng + 2),        // 2 column and group coefficients, constants
+      sizeof(int) * nang * 3,                        // 3 perm, nlo, nmodes
+      sizeof(cplx) * N * W,                          // 4 Y
+      sizeof(cplx) * N * W,                          // 5 X
+      sizeof(cplx) * (size_t)M2 * N * 2,             // 6 C1, C2
+      sizeof(cplx) * (size_t)M2 * W * 2,             // 7 G1, G2
+      sizeof(cplx) * (size_t)M2 * M2 * ng,           // 8 S
+      sizeof(cplx) * (size_t)M2 * nang * 8,          // 9 xi, W, T1, T2, R2, U1, U2, dxi
+      sizeof(cplx) * (size_t)M4 * nang,              // 10 stack
+      sizeof(cplx) * (size_t)N * nang * 4,           // 11 eta, R1, Z1, F
+      sizeof(cplx) * 2 * maxm * nang * 2,            // 12 bragg (grouped, caller order)
+      sizeof(double) * nang * 3,                     // 13 norms
+      sizeof(cplx) * (size_t)nr * N * 2,             // 14 R_{+1}, R_{-1}
+      sizeof(cplx) * (size_t)nr * W * 2,             // 15 R_{+1} X, R_{-1} X
+      sizeof(cplx) * (size_t)nrr * nrr * ng * 2,     // 16 K(alpha) (and I + R V)
+      sizeof(cplx) * (size_t)nrr * M2 * ng * 2,      // 17 R(alpha) X(alpha), K R X scratch
+      sizeof(cplx) * (size_t)M2 * nrr * ng,          // 18 C~ V
+      sizeof(cplx) * (size_t)nrr * nang * 4};        // 19 R b, u, y, misc (nr x nang)
   std::vector<size_t> off(sizes.size() + 1, 0);
   for (size_t i = 0; i < sizes.size(); ++i) off[i + 1] = off[i] + ((sizes[i] + 255) / 256) * 256;
   CK(h->scratch.reserve(off.back()));
@@ -194,15 +239,21 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   double* dkx = (double*)(base + off[1]);
   double* dky = dkx + nang;
   double* dkap = dky + nang;
-  cplx* dalcol = (cplx*)(base + off[2]);
-  cplx* dgal = dalcol + nang;
+  cplx* dcol = (cplx*)(base + off[2]);
+  cplx* d_al = dcol;
+  cplx* d_c1 = dcol + nang;
+  cplx* d_c2 = dcol + 2 * nang;
+  cplx* d_ainv = dcol + 3 * nang;
+  cplx* d_gco = dcol + 5 * nang;         // 3 ng: (alpha, c1, c2)
+  cplx* d_gsc = d_gco + 3 * ng;           // 4 ng: (alpha, 1/alpha, alpha^2, -alpha)
+  cplx* d_one = d_gsc + 4 * ng;           // constants 1, -1
   int* dperm = (int*)(base + off[3]);
   int* dnlo = dperm + nang;
   int* dnm = dnlo + nang;
   cplx* Y = (cplx*)(base + off[4]);
   cplx* X = (cplx*)(base + off[5]);
-  cplx* CL = (cplx*)(base + off[6]);
-  cplx* CRm = CL + (size_t)M2 * N;
+  cplx* C1 = (cplx*)(base + off[6]);
+  cplx* C2 = C1 + (size_t)M2 * N;
   cplx* G1 = (cplx*)(base + off[7]);
   cplx* G2 = G1 + (size_t)M2 * W;
   cplx* S = (cplx*)(base + off[8]);
@@ -222,13 +273,28 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   cplx* brg = (cplx*)(base + off[12]);
   cplx* brg2 = brg + (size_t)2 * maxm * nang;
   double* nrm = (double*)(base + off[13]);
+  cplx* Rp = (cplx*)(base + off[14]);
+  cplx* Rm = Rp + (size_t)nr * N;
+  cplx* RXp = (cplx*)(base + off[15]);
+  cplx* RXm = RXp + (size_t)nr * W;
+  cplx* Kg = (cplx*)(base + off[16]);
+  cplx* KVg = Kg + (size_t)nrr * nrr * ng;
+  cplx* RAX = (cplx*)(base + off[17]);
+  cplx* KRAX = RAX + (size_t)nrr * M2 * ng;
+  cplx* CV = (cplx*)(base + off[18]);
+  cplx* Rb = (cplx*)(base + off[19]);
+  cplx* uu = Rb + (size_t)nrr * nang;
+  cplx* yy = uu + (size_t)nrr * nang;
+  cplx* vv = yy + (size_t)nrr * nang;
 
+  std::vector<cplx> consts = {onec, minus1c};
   CK(hipMemcpyAsync(dcont, cont.data(), sizeof(cplx) * 3 * M, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(dkx, kx.data(), sizeof(double) * nang, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(dky, ky.data(), sizeof(double) * nang, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(dkap, kapv.data(), sizeof(double) * nang, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(dalcol, alcol.data(), sizeof(cplx) * nang, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(dgal, galc.data(), sizeof(cplx) * ng, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(dkap, kx.data(), sizeof(double) * nang, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(dcol, colc.data(), sizeof(cplx) * 5 * nang, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(d_gco, gcoef.data(), sizeof(cplx) * 7 * ng, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(d_one, consts.data(), sizeof(cplx) * 2, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(dperm, perm.data(), sizeof(int) * nang, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(dnlo, nlo.data(), sizeof(int) * nang, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(dnm, nm.data(), sizeof(int) * nang, hipMemcpyHostToDevice, st));
@@ -237,24 +303,77 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   Q.x = h->geo.x; Q.y = h->geo.y; Q.nx = h->geo.nx; Q.ny = h->geo.ny; Q.w = h->geo.w;
   Q.k = dcont; Q.s = dcont + M; Q.wk = dcont + 2 * M;
   Q.N = N; Q.M = M; Q.omega = om; Q.period = period; Q.shift = 0.0;
-  const cplx one = mkc(1, 0), zero = mkc(0, 0), mone = mkc(-1, 0);
+  const cplx zero = mkc(0, 0);
+  auto gemm = [&](const std::vector<GemmDesc>& g) -> int {
+    CK(gemm_batched(h->arena, g, st, &h->splitws));
+    CK(hipStreamSynchronize(st));
+    return HBS_OK;
+  };
   {
     ProfScope ps("assemble", st, 0.0, 0.0);
     CK(launch_gen_B(Q, Y, N, st));
-    CK(launch_gen_inc(Q, dkx, dky, nang, Y + (size_t)M4 * N, N, st));
-    CK(launch_gen_C(Q, 0, 0.0, CL, st));
-    CK(launch_gen_C(Q, 1, 0.0, CRm, st));
+    CK(launch_gen_inc(Q, dkx, dky, nang, Y + (size_t)colB * N, N, st));
+    CK(launch_gen_C(Q, 0, P * period, C1, st));
+    CK(launch_gen_C(Q, 1, -P * period, C2, st));
   }
-  // one application of A^{-1} for every alpha
+  if (P) {
+    // U (N x nr) = nested interpolation of the identity; R_{+-1} = A_{+-1}(J, :)
+    CK(h->ab_root.reserve(sizeof(cplx) * (size_t)nr * nr));
+    std::vector<cplx> eye((size_t)nr * nr, zero);
+    for (int i = 0; i < nr; ++i) eye[(size_t)i * nr + i] = onec;
+    CK(hipMemcpyAsync(h->ab_root.p, eye.data(), sizeof(cplx) * eye.size(), hipMemcpyHostToDevice, st));
+    CR(apply_interp(h, h->ab_root.as<cplx>(), nr, Y + (size_t)colU * N, N, nr));
+    const int* J = h->lv[1].skel.as<int>();
+    CK(launch_eval_shift(h->geo, J, nr, period, Rp, nr, st));
+    CK(launch_eval_shift(h->geo, J, nr, -period, Rm, nr, st));
+  }
+  // one application of A^{-1} for every alpha (and V = A^{-1} U)
   CR(apply_factors(h, true, Y, N, X, N, W));
-  // alpha-free products C_L X, C_R X
+  // alpha-free products
   {
-    std::vector<GemmDesc> g = {gd(CL, M2, 0, X, N, G1, M2, M2, (int)W, N, one, zero),
-                               gd(CRm, M2, 0, X, N, G2, M2, M2, (int)W, N, one, zero)};
-    CK(gemm_batched(h->arena, g, st, &h->splitws));
-    CK(hipStreamSynchronize(st));
+    std::vector<GemmDesc> g = {gd(C1, M2, 0, X, N, G1, M2, M2, (int)W, N, onec, zero),
+                               gd(C2, M2, 0, X, N, G2, M2, M2, (int)W, N, onec, zero)};
+    if (P) {
+      g.push_back(gd(Rp, nr, 0, X, N, RXp, nr, nr, (int)W, N, onec, zero));
+      g.push_back(gd(Rm, nr, 0, X, N, RXm, nr, nr, (int)W, N, onec, zero));
+    }
+    CR(gemm(g));
   }
-  CK(launch_form_S(Q, dgal, ng, G1, G2, S, st));
+  CK(launch_form_S(Q, d_gco, ng, G1, G2, S, st));
+  if (P) {
+    // per alpha: K = (I + R V)^{-1}, R X(alpha), C~ V;  S += C~V K R X(alpha)
+    for (int g = 0; g < ng; ++g) {
+      const cplx* sc = d_gsc + 4 * g;  // alpha, 1/alpha, alpha^2, -alpha
+      cplx* kv = KVg + (size_t)g * nr * nr;
+      CK(launch_lincomb(nr, nr, sc, sc + 1, 0, RXp + (size_t)colU * nr, nr, RXm + (size_t)colU * nr, nr, nullptr, 0, kv, nr, st));
+      cplx* rax = RAX + (size_t)g * nr * M2;
+      // R X(alpha) = alpha^2 R1 X_R + R-1 X_R + alpha R1 X_L + alpha^{-1} R-1 X_L
+      CK(launch_lincomb(nr, M2, sc + 2, d_one, 0, RXp + (size_t)M2 * nr, nr, RXm + (size_t)M2 * nr, nr, nullptr, 0, rax, nr, st));
+      std::vector<cplx> negs = {mkc(-galpha[g].real(), -galpha[g].imag()), toc(-1.0 / galpha[g])};
+      CK(hipMemcpyAsync(vv, negs.data(), sizeof(cplx) * 2, hipMemcpyHostToDevice, st));
+      CK(launch_lincomb(nr, M2, vv, vv + 1, 0, RXp, nr, RXm, nr, rax, nr, rax, nr, st));
+      CK(launch_lincomb(M2, nr, d_gco + 3 * g + 1, d_gco + 3 * g + 2, 0, G1 + (size_t)colU * M2, M2, G2 + (size_t)colU * M2,
+                        M2, nullptr, 0, CV + (size_t)g * M2 * nr, M2, st));
+      CK(hipStreamSynchronize(st));
+    }
+    CK(launch_eye_plus(nr, ng, KVg, nr, (int64_t)nr * nr, Kg, st));
+    {
+      std::vector<InvDesc> iv;
+      for (int g = 0; g < ng; ++g) iv.push_back({Kg + (size_t)g * nr * nr, nr, nr});
+      bool sing = false;
+      CK(inv_batched(h->arena, h->work, iv, st, &sing));
+      if (sing) { set_error("qp_solve: singular Woodbury capacitance matrix"); return HBS_E_SINGULAR; }
+    }
+    std::vector<GemmDesc> g1, g2;
+    for (int g = 0; g < ng; ++g)
+      g1.push_back(gd(Kg + (size_t)g * nr * nr, nr, 0, RAX + (size_t)g * nr * M2, nr, KRAX + (size_t)g * nr * M2, nr, nr, M2,
+                      nr, onec, zero));
+    CR(gemm(g1));
+    for (int g = 0; g < ng; ++g)
+      g2.push_back(gd(CV + (size_t)g * M2 * nr, M2, 0, KRAX + (size_t)g * nr * M2, nr, S + (size_t)g * M2 * M2, M2, M2, M2,
+                      nr, onec, onec));
+    CR(gemm(g2));
+  }
   {
     std::vector<InvDesc> iv;
     for (int g = 0; g < ng; ++g) iv.push_back({S + (size_t)g * M2 * M2, M2, M2});
@@ -265,46 +384,79 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       return HBS_E_SINGULAR;
     }
   }
-  // xi = -S^{-1} C(alpha) X_b
-  CK(launch_combine_c(M2, nang, dalcol, G1 + (size_t)M4 * M2, M2, G2 + (size_t)M4 * M2, M2, nullptr, Wv, st));
+  // y = K R(alpha) Z for the columns of Z (nr x nang rows-by-angle), per group
+  auto neighbour_K = [&](const cplx* RZp, const cplx* RZm, cplx* out) -> int {
+    CK(launch_lincomb(nr, nang, d_al, d_ainv, 1, RZp, nr, RZm, nr, nullptr, 0, uu, nr, st));
+    std::vector<GemmDesc> g;
+    for (int gg = 0; gg < ng; ++gg)
+      g.push_back(gd(Kg + (size_t)gg * nr * nr, nr, 0, uu + (size_t)goff[gg] * nr, nr, out + (size_t)goff[gg] * nr, nr, nr,
+                     gcnt[gg], nr, onec, zero));
+    return gemm(g);
+  };
   auto solve_S = [&](const cplx* rhs, cplx* out, cplx alpha) -> int {
     std::vector<GemmDesc> g;
     for (int gg = 0; gg < ng; ++gg)
       g.push_back(gd(S + (size_t)gg * M2 * M2, M2, 0, rhs + (size_t)goff[gg] * M2, M2, out + (size_t)goff[gg] * M2, M2, M2,
                      gcnt[gg], M2, alpha, zero));
-    CK(gemm_batched(h->arena, g, st, &h->splitws));
-    CK(hipStreamSynchronize(st));
-    return HBS_OK;
+    return gemm(g);
   };
-  CR(solve_S(Wv, xi, mone));
-  // eta = X_b - [X_L | X_R] [xi; alpha xi]
-  CK(launch_stack(M2, nang, dalcol, xi, stk, st));
-  CK(launch_axpby(N, nang, one, X + (size_t)M4 * N, N, zero, eta, N, st));
-  {
-    std::vector<GemmDesc> g = {gd(X, N, 0, stk, M4, eta, N, N, nang, M4, mone, one)};
-    CK(gemm_batched(h->arena, g, st, &h->splitws));
-    CK(hipStreamSynchronize(st));
+  const cplx* Vc = X + (size_t)colU * N;
+  // right-hand sides: C~ A~^{-1} b = C~ X_b - C~V K R X_b
+  CK(launch_lincomb(M2, nang, d_c1, d_c2, 1, G1 + (size_t)colB * M2, M2, G2 + (size_t)colB * M2, M2, nullptr, 0, Wv, M2, st));
+  if (P) {
+    CR(neighbour_K(RXp + (size_t)colB * nr, RXm + (size_t)colB * nr, yy));
+    std::vector<GemmDesc> g;
+    for (int gg = 0; gg < ng; ++gg)
+      g.push_back(gd(CV + (size_t)gg * M2 * nr, M2, 0, yy + (size_t)goff[gg] * nr, nr, Wv + (size_t)goff[gg] * M2, M2, M2,
+                     gcnt[gg], nr, minus1c, onec));
+    CR(gemm(g));
+  }
+  CR(solve_S(Wv, xi, minus1c));
+  // eta = X_b - X(alpha) xi - V K (R X_b - R X(alpha) xi)
+  CK(launch_stack(M2, nang, d_al, xi, stk, st));
+  CK(launch_axpby(N, nang, onec, X + (size_t)colB * N, N, zero, eta, N, st));
+  CR(gemm({gd(X, N, 0, stk, M4, eta, N, N, nang, M4, minus1c, onec)}));
+  // eta -= V K [R b - R X(alpha) xi], assembled in uu/yy
+  auto nb_correction = [&](const cplx* Rz, const cplx* xs, cplx sign) -> int {
+    // vv = Rz - RAX xs (per group), yy = K vv, eta += sign * V yy
+    CK(hipMemcpyAsync(vv, Rz, sizeof(cplx) * (size_t)nr * nang, hipMemcpyDeviceToDevice, st));
+    std::vector<GemmDesc> g, g2;
+    for (int gg = 0; gg < ng; ++gg)
+      g.push_back(gd(RAX + (size_t)gg * nr * M2, nr, 0, xs + (size_t)goff[gg] * M2, M2, vv + (size_t)goff[gg] * nr, nr, nr,
+                     gcnt[gg], M2, minus1c, onec));
+    CR(gemm(g));
+    for (int gg = 0; gg < ng; ++gg)
+      g2.push_back(gd(Kg + (size_t)gg * nr * nr, nr, 0, vv + (size_t)goff[gg] * nr, nr, yy + (size_t)goff[gg] * nr, nr, nr,
+                      gcnt[gg], nr, onec, zero));
+    CR(gemm(g2));
+    return gemm({gd(Vc, N, 0, yy, nr, eta, N, N, nang, nr, sign, onec)});
+  };
+  if (P) {
+    CK(launch_lincomb(nr, nang, d_al, d_ainv, 1, RXp + (size_t)colB * nr, nr, RXm + (size_t)colB * nr, nr, nullptr, 0, Rb, nr,
+                      st));
+    CR(nb_correction(Rb, xi, minus1c));
   }
   // iterative refinement of the bordered system
   int maxit = o->refine_max_iter < 0 ? 0 : (o->refine_max_iter == 0 ? 2 : o->refine_max_iter);
   const double rtol = o->refine_tol > 0 ? o->refine_tol : 1e-13;
   std::vector<double> hn(3 * nang);
-  CK(launch_colnorm2(N, nang, Y + (size_t)M4 * N, N, nrm + 2 * nang, st));
+  CK(launch_colnorm2(N, nang, Y + (size_t)colB * N, N, nrm + 2 * nang, st));
   double relres = -1;
   int iters = 0;
   for (int it = 0; it <= maxit; ++it) {
-    // R1 = b - A eta - B(alpha) xi ;  R2 = -C(alpha) eta - Q(alpha) xi
+    // R1 = b - A~ eta - B(alpha) xi ;  R2 = -C~(alpha) eta - Q(alpha) xi
     CR(apply_factors(h, false, eta, N, F, N, nang));
-    CK(launch_axpby(N, nang, one, Y + (size_t)M4 * N, N, zero, R1, N, st));
-    CK(launch_axpby(N, nang, mone, F, N, one, R1, N, st));
-    {
-      std::vector<GemmDesc> g = {gd(Y, N, 0, stk, M4, R1, N, N, nang, M4, mone, one),
-                                 gd(CL, M2, 0, eta, N, T1, M2, M2, nang, N, one, zero),
-                                 gd(CRm, M2, 0, eta, N, T2, M2, M2, nang, N, one, zero)};
-      CK(gemm_batched(h->arena, g, st, &h->splitws));
-      CK(hipStreamSynchronize(st));
+    if (P) {
+      CR(gemm({gd(Rp, nr, 0, eta, N, uu, nr, nr, nang, N, onec, zero), gd(Rm, nr, 0, eta, N, yy, nr, nr, nang, N, onec, zero)}));
+      CK(launch_lincomb(nr, nang, d_al, d_ainv, 1, uu, nr, yy, nr, nullptr, 0, vv, nr, st));
+      CR(apply_interp(h, vv, nr, Z1, N, nang));
+      CK(launch_axpby(N, nang, onec, Z1, N, onec, F, N, st));
     }
-    CK(launch_resid2(Q, nang, dalcol, T1, T2, xi, R2, st));
+    CK(launch_axpby(N, nang, onec, Y + (size_t)colB * N, N, zero, R1, N, st));
+    CK(launch_axpby(N, nang, minus1c, F, N, onec, R1, N, st));
+    CR(gemm({gd(Y, N, 0, stk, M4, R1, N, N, nang, M4, minus1c, onec), gd(C1, M2, 0, eta, N, T1, M2, M2, nang, N, onec, zero),
+             gd(C2, M2, 0, eta, N, T2, M2, M2, nang, N, onec, zero)}));
+    CK(launch_resid2(Q, nang, d_al, d_c1, d_c2, T1, T2, xi, R2, st));
     CK(launch_colnorm2(N, nang, R1, N, nrm, st));
     CK(launch_colnorm2(M2, nang, R2, M2, nrm + nang, st));
     CK(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * 3 * nang, hipMemcpyDeviceToHost, st));
@@ -313,25 +465,27 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     for (int q = 0; q < nang; ++q) relres = std::max(relres, std::sqrt((hn[q] + hn[nang + q]) / hn[2 * nang + q]));
     if (relres < rtol || it == maxit) break;
     ++iters;
-    // correction by the block solve: Z1 = A^{-1} R1; dxi = S^{-1}(R2 - C(alpha) Z1); deta = Z1 - X(alpha) dxi
+    // correction by the block solve: Z1 = A~^{-1} R1; dxi = S^{-1}(R2 - C~ Z1); deta = Z1 - X~(alpha) dxi
     CR(apply_factors(h, true, R1, N, Z1, N, nang));
-    {
-      std::vector<GemmDesc> g = {gd(CL, M2, 0, Z1, N, U1, M2, M2, nang, N, one, zero),
-                                 gd(CRm, M2, 0, Z1, N, U2, M2, M2, nang, N, one, zero)};
-      CK(gemm_batched(h->arena, g, st, &h->splitws));
-      CK(hipStreamSynchronize(st));
+    if (P) {
+      CR(gemm({gd(Rp, nr, 0, Z1, N, uu, nr, nr, nang, N, onec, zero), gd(Rm, nr, 0, Z1, N, vv, nr, nr, nang, N, onec, zero)}));
+      CK(hipMemcpyAsync(Rb, uu, sizeof(cplx) * (size_t)nr * nang, hipMemcpyDeviceToDevice, st));
+      CR(neighbour_K(Rb, vv, yy));
+      CR(gemm({gd(Vc, N, 0, yy, nr, Z1, N, N, nang, nr, minus1c, onec)}));
     }
-    CK(launch_combine_c(M2, nang, dalcol, U1, M2, U2, M2, R2, Wv, st));
-    CR(solve_S(Wv, dxi, one));
-    CK(launch_stack(M2, nang, dalcol, dxi, stk, st));
-    CK(launch_axpby(N, nang, one, Z1, N, one, eta, N, st));
-    {
-      std::vector<GemmDesc> g = {gd(X, N, 0, stk, M4, eta, N, N, nang, M4, mone, one)};
-      CK(gemm_batched(h->arena, g, st, &h->splitws));
-      CK(hipStreamSynchronize(st));
+    CR(gemm({gd(C1, M2, 0, Z1, N, U1, M2, M2, nang, N, onec, zero), gd(C2, M2, 0, Z1, N, U2, M2, M2, nang, N, onec, zero)}));
+    CK(launch_lincomb(M2, nang, d_c1, d_c2, 1, U1, M2, U2, M2, R2, M2, Wv, M2, st));
+    CR(solve_S(Wv, dxi, onec));
+    CK(launch_stack(M2, nang, d_al, dxi, stk, st));
+    CK(launch_axpby(N, nang, onec, Z1, N, onec, eta, N, st));
+    CR(gemm({gd(X, N, 0, stk, M4, eta, N, N, nang, M4, minus1c, onec)}));
+    if (P) {
+      // + V K R X(alpha) dxi  (X~(alpha) = X(alpha) - V K R X(alpha))
+      CK(hipMemsetAsync(Rb, 0, sizeof(cplx) * (size_t)nr * nang, st));
+      CR(nb_correction(Rb, dxi, minus1c));
     }
-    CK(launch_axpby(M2, nang, one, dxi, M2, one, xi, M2, st));
-    CK(launch_stack(M2, nang, dalcol, xi, stk, st));
+    CK(launch_axpby(M2, nang, onec, dxi, M2, onec, xi, M2, st));
+    CK(launch_stack(M2, nang, d_al, xi, stk, st));
   }
   h->stats.refine_iters = iters;
   h->stats.refine_residual = relres;

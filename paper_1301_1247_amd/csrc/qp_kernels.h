@@ -14,12 +14,14 @@ namespace qps {
 hipError_t launch_gen_B(const QPGeo& q, cplx* Y, int64_t ldy, hipStream_t s);
 hipError_t launch_gen_inc(const QPGeo& q, const double* kx, const double* ky, int nang, cplx* Y, int64_t ldy, hipStream_t s);
 hipError_t launch_gen_C(const QPGeo& q, int wall, double shift, cplx* C, hipStream_t s);
-hipError_t launch_form_S(const QPGeo& q, const cplx* alphas, int ng, const cplx* G1, const cplx* G2, cplx* S, hipStream_t s);
-hipError_t launch_combine_c(int M2, int nang, const cplx* alpha_col, const cplx* U1, int64_t ld1, const cplx* U2, int64_t ld2,
-                            const cplx* R, cplx* W, hipStream_t s);
+hipError_t launch_form_S(const QPGeo& q, const cplx* coef, int ng, const cplx* G1, const cplx* G2, cplx* S, hipStream_t s);
+// W[:, a] = c1[a*cs] U1[:, a] + c2[a*cs] U2[:, a], or R[:, a] - (...) when R != nullptr (W may alias R)
+hipError_t launch_lincomb(int rows, int ncol, const cplx* c1, const cplx* c2, int cs, const cplx* U1, int64_t ld1,
+                          const cplx* U2, int64_t ld2, const cplx* R, int64_t ldr, cplx* W, int64_t ldw, hipStream_t s);
+hipError_t launch_eye_plus(int n, int ng, const cplx* B, int64_t ldb, int64_t bstride, cplx* A, hipStream_t s);
 hipError_t launch_stack(int M2, int nang, const cplx* alpha_col, const cplx* xi, cplx* st, hipStream_t s);
-hipError_t launch_resid2(const QPGeo& q, int nang, const cplx* alpha_col, const cplx* T1, const cplx* T2, const cplx* xi,
-                         cplx* R2, hipStream_t s);
+hipError_t launch_resid2(const QPGeo& q, int nang, const cplx* alpha_col, const cplx* c1, const cplx* c2, const cplx* T1,
+                         const cplx* T2, const cplx* xi, cplx* R2, hipStream_t s);
 hipError_t launch_axpby(int64_t rows, int cols, cplx a, const cplx* x, int64_t ldx, cplx b, cplx* y, int64_t ldy, hipStream_t s);
 hipError_t launch_colnorm2(int64_t rows, int cols, const cplx* x, int64_t ldx, double* out, hipStream_t s);
 hipError_t launch_bragg(const QPGeo& q, const double* kappa, const int* nlo, const int* nmodes, int maxmodes, int nang,

@@ -149,3 +149,44 @@ def test_qp_solve_alpha_mismatch_and_wood(gpu_lib):
     with pytest.raises(gpu_lib.HBSError) as e:
         h.qp_solve_many(wl.period, np.array([th]))
     assert e.value.code == -9
+
+
+def _far_radius(nodes, d):
+    c = 0.5 * (nodes.max(0) + nodes.min(0))
+    robs = np.hypot(*(nodes - c).T).max()
+    return 0.9 * (d - robs)
+
+
+def test_qp_neighbour_images_P1_star_kress(gpu_lib):
+    wl = qpinputs.workload("star")
+    nodes, w, nrm, kap = discretize(wl.curve, wl.N)
+    h = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-12, quad="kress", leaf_size=50, curvature=kap,
+                       far_radius=_far_radius(nodes, wl.period))
+    res = h.qp_solve_many(wl.period, wl.thetas, P=1)
+    ref = pq.solve_qp(wl.curve, wl.N, wl.omega, wl.period, wl.thetas, quad="kress", P=1)
+    assert res["M"] == len(ref["contour"].k)
+    _check_qp(res, ref, len(wl.thetas))
+    # P = 0 and P = 1 represent the same scattered field
+    res0 = h.qp_solve_many(wl.period, wl.thetas, P=0)
+    assert _rel(res["eta"][:, 0], res0["eta"][:, 0]) < 1e-10
+
+
+def test_qp_neighbour_images_P1_wavy_kr6(gpu_lib, wavy_small):
+    c, N, om, disc, A, lu = wavy_small
+    d = 2 * math.pi
+    thetas = np.array([-1.1, -0.45, -math.acos(0.31), -math.acos(0.31 + 1 / 40)])
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-12, far_radius=_far_radius(nodes, d))
+    res = h.qp_solve_many(d, thetas, P=1)
+    ref = pq.solve_qp(disc, N, om, d, thetas, quad="kr6", P=1, A0=A)
+    _check_qp(res, ref, len(thetas))
+    assert h.stats().refine_residual < 1e-12
+
+
+def test_qp_P1_needs_far_field_skeletons(gpu_lib):
+    wl = qpinputs.workload("star")
+    nodes, w, nrm, kap = discretize(wl.curve, wl.N)
+    h = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-10, quad="kress", leaf_size=50, curvature=kap)
+    with pytest.raises(gpu_lib.HBSError) as e:
+        h.qp_solve_many(wl.period, wl.thetas, P=1)
+    assert e.value.code == -1
