@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "incident-angle solves/sec at N=1e5, rel err<=1e-10; HBS build time (s)"
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 
 
 def log(*a):
@@ -117,6 +118,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="wavy40")
     ap.add_argument("--tol", type=float, default=1e-13)
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
+                    help="fp32: complex64 inverse factors as a preconditioner, FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -156,7 +159,8 @@ def main():
     stream = torch.cuda.current_stream()
     nang = len(wl.thetas)
     kw = dict(quad=wl.quad, leaf_size=wl.leaf_size, curvature=t_kap if wl.quad == "kress" else None, device=True,
-              stream=stream.cuda_stream)
+              stream=stream.cuda_stream, precision=args.precision)
+    fam, peak = ("zgemm", FP64_PEAK_TFLOPS) if args.precision == "fp64" else ("cgemm", FP32_PEAK_TFLOPS)
 
     def step():
         h = B.Handle(t_nodes, t_w, t_nrm, wl.omega, args.tol, **kw)
@@ -178,10 +182,10 @@ def main():
             del h, res
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    prof = B.profile_read("zgemm")
+    prof = B.profile_read(fam)
     B.profile_enable(False)
     st = h.stats()
-    log(f"timed {args.steps} steps in {t:.3f} s; zgemm {prof}")
+    log(f"timed {args.steps} steps in {t:.3f} s; {fam} {prof}")
     ms = 1000.0 * t / args.steps
     value = nang * args.steps / t
     achieved = prof["flops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else 0.0
@@ -196,16 +200,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128",
+        "dtype": "c128" if args.precision == "fp64" else "c64+c128",
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: seeded obstacle, N={wl.N}, omega={wl.omega}, d=2pi, "
-                               f"{nang} angles, tol={args.tol:g}, KR6 + proxy compression",
+                               f"{nang} angles, tol={args.tol:g}, KR6 + proxy compression, {args.precision} factors",
                    "N": wl.N, "omega": wl.omega, "angles": nang, "contour_M": st.contour_M},
         "build_seconds": float(np.median(builds)),
         "levels": st.levels, "max_rank": st.max_rank, "root_size": st.root_size,
         "refine_iters": st.refine_iters, "refine_residual": st.refine_residual,
-        "roofline": {"bound": "mfma", "kernel": "k_zgemm (complex FP64 MFMA GEMM)", "achieved": achieved,
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+        "roofline": {"bound": "mfma", "kernel": ("k_zgemm (complex FP64 MFMA GEMM)" if fam == "zgemm"
+                                                 else "k_gemm<float> (complex FP32 MFMA GEMM)"),
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None, "launches": prof["launches"],
                      "avg_launch_ms": prof["ms"] / max(1, prof["launches"]),
                      "flops_per_launch": prof["flops"] / max(1, prof["launches"])},

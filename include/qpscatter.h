@@ -43,6 +43,7 @@ enum {
 enum { HBS_QUAD_KR6 = 0, HBS_QUAD_KRESS = 1 };
 enum { HBS_COMPRESS_PROXY = 0, HBS_COMPRESS_EXACT = 1 };
 enum { HBS_PTR_HOST = 0, HBS_PTR_DEVICE = 1 };
+enum { HBS_FP64 = 0, HBS_FP32_PRECOND = 1 };
 
 typedef struct hbs_handle hbs_handle;
 
@@ -61,6 +62,15 @@ typedef struct {
   double far_radius;        /* > 0: every skeleton also represents sources outside the circle of this
                                radius about the obstacle's centre (needed by qp_solve with P >= 1,
                                whose neighbour images must lie outside it); 0 = off */
+  int32_t precision;        /* HBS_FP64: inverse factors in complex128.  HBS_FP32_PRECOND: the inverse
+                               factors of the deep levels are built and applied in complex64 on FP32
+                               matrix cores and serve as a preconditioner; skeletons, the forward
+                               operator, the top levels, the root and all residuals stay FP64, and
+                               refinement (hbs_apply's `refine`, qp_solve's refine_max_iter) recovers
+                               FP64 accuracy */
+  int32_t fp64_top_levels;  /* HBS_FP32_PRECOND only: levels 1..t below the root keep complex128
+                               factors (their reduced systems are the worst conditioned), deeper
+                               levels complex64; <0 -> 0, 0 -> 3 */
 } hbs_opts;
 
 typedef struct {
@@ -72,7 +82,8 @@ typedef struct {
   double ca, cb;            /* contour k(t) = t - i ca tanh(t / cb); 0 -> 1, 1 */
   double y0;                /* Bragg reference height; 0 -> max|y| + 0.5 */
   double wood_min_kn;       /* refuse angles with min_n |k_n| below this; 0 -> 0.75 */
-  int32_t refine_max_iter;  /* iterative refinement steps of the bordered system; <0 -> 0, 0 -> 2 */
+  int32_t refine_max_iter;  /* iterative refinement steps of the bordered system; <0 -> 0,
+                               0 -> 2 (3 for a handle built with HBS_FP32_PRECOND) */
   double refine_tol;        /* stop when the relative residual is below; 0 -> 1e-13 */
 } qp_opts;
 
@@ -162,11 +173,15 @@ int qps_zgemm(const double* A, const double* B, double* C, int32_t m, int32_t n,
               int32_t nbatch, int32_t transA, int32_t accumulate, int32_t ptr_mode);
 /* In-place inversion of nbatch square n x n complex matrices (Gauss-Jordan, partial pivoting). */
 int qps_zinv(double* A, int32_t n, int32_t nbatch, int32_t ptr_mode);
+/* The complex64 variants used by HBS_FP32_PRECOND (interleaved (re, im) floats, FP32 MFMA). */
+int qps_cgemm(const float* A, const float* B, float* C, int32_t m, int32_t n, int32_t k,
+              int32_t nbatch, int32_t transA, int32_t accumulate, int32_t ptr_mode);
+int qps_cinv(float* A, int32_t n, int32_t nbatch, int32_t ptr_mode);
 
 /* Kernel-time profiling with HIP events on the handle's stream.  When enabled, each launch
  * of a kernel family is bracketed by events; qps_profile_read returns the summed time (ms),
- * launch count and summed algorithmic flops of the family ("zgemm", "cpqr", "zinv",
- * "assemble", "apply").  Enabling resets the counters. */
+ * launch count and summed algorithmic flops of the family ("zgemm", "cgemm", "zinv", "cinv",
+ * "cpqr", "sketch", "assemble", "apply", "bragg").  Enabling resets the counters. */
 int qps_profile_enable(int32_t on);
 int qps_profile_read(const char* family, double* ms, int64_t* launches, double* flops, double* bytes);
 

@@ -38,7 +38,7 @@ class HbsOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("quad", C.c_int32), ("compress", C.c_int32), ("leaf_size", C.c_int32),
                 ("proxy_ratio", C.c_double), ("proxy_min", C.c_int32), ("ptr_mode", C.c_int32),
                 ("curvature", C.c_void_p), ("stream", C.c_void_p), ("seed", C.c_uint64),
-                ("far_radius", C.c_double)]
+                ("far_radius", C.c_double), ("precision", C.c_int32), ("fp64_top_levels", C.c_int32)]
 
 
 class QpOpts(C.Structure):
@@ -74,6 +74,8 @@ _sig = {
     "qps_matrix_entries": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
     "qps_zgemm": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "qps_zinv": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32]),
+    "qps_cgemm": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "qps_cinv": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32]),
     "qps_profile_enable": (C.c_int, [C.c_int32]),
     "qps_profile_read": (C.c_int, [C.c_char_p, _P, _P, _P, _P]),
 }
@@ -132,7 +134,7 @@ class Handle:
 
     def __init__(self, nodes, weights, normals, omega, tol, quad="kr6", compress=None, leaf_size=64,
                  curvature=None, device=False, stream=None, proxy_ratio=2.0, proxy_min=64, seed=0x5EED1301,
-                 far_radius=0.0):
+                 far_radius=0.0, precision="fp64", fp64_top_levels=0):
         if compress is None:
             compress = "exact" if quad == "kress" else "proxy"
         self.device = bool(device)
@@ -155,7 +157,8 @@ class Handle:
         o = hbs_opts(quad=QUAD[quad], compress=COMPRESS[compress], leaf_size=int(leaf_size),
                      proxy_ratio=float(proxy_ratio), proxy_min=int(proxy_min),
                      ptr_mode=PTR_DEVICE if self.device else PTR_HOST,
-                     curvature=_ptr(curvature), stream=st, seed=int(seed), far_radius=float(far_radius))
+                     curvature=_ptr(curvature), stream=st, seed=int(seed), far_radius=float(far_radius),
+                     precision={"fp64": 0, "fp32": 1}[precision], fp64_top_levels=int(fp64_top_levels))
         h = C.c_void_p()
         _check(_lib.hbs_build(_ptr(nodes), _ptr(weights), _ptr(normals), N, float(omega), float(tol), C.byref(o),
                               C.byref(h)))
@@ -260,10 +263,13 @@ def kr6_corrections():
     return out
 
 
-def zgemm(A, B, transA=False):
-    """Batched C = op(A) B on the GPU: A (b, m, k) or (b, k, m) if transA, B (b, k, n); complex128."""
-    A = np.asarray(A, dtype=np.complex128)
-    B = np.asarray(B, dtype=np.complex128)
+def zgemm(A, B, transA=False, precision="fp64"):
+    """Batched C = op(A) B on the GPU: A (b, m, k) or (b, k, m) if transA, B (b, k, n).
+
+    precision "fp64": complex128 (FP64 MFMA); "fp32": complex64 (FP32 MFMA)."""
+    dt, fn = (np.complex128, _lib.qps_zgemm) if precision == "fp64" else (np.complex64, _lib.qps_cgemm)
+    A = np.asarray(A, dtype=dt)
+    B = np.asarray(B, dtype=dt)
     nb = A.shape[0]
     if transA:
         k, m = A.shape[1], A.shape[2]
@@ -272,16 +278,18 @@ def zgemm(A, B, transA=False):
     n = B.shape[2]
     Af = np.array(np.transpose(A, (0, 2, 1)), order="C", copy=True)  # column-major per batch entry
     Bf = np.array(np.transpose(B, (0, 2, 1)), order="C", copy=True)
-    Cf = np.zeros((nb, n, m), dtype=np.complex128)
-    _check(_lib.qps_zgemm(_ptr(Af), _ptr(Bf), _ptr(Cf), m, n, k, nb, int(transA), 0, PTR_HOST))
+    Cf = np.zeros((nb, n, m), dtype=dt)
+    _check(fn(_ptr(Af), _ptr(Bf), _ptr(Cf), m, n, k, nb, int(transA), 0, PTR_HOST))
     return np.transpose(Cf, (0, 2, 1))
 
 
-def zinv(A):
-    A = np.asarray(A, dtype=np.complex128)
+def zinv(A, precision="fp64"):
+    """Batched in-place Gauss-Jordan inverse on the GPU (complex128, or complex64 for "fp32")."""
+    dt, fn = (np.complex128, _lib.qps_zinv) if precision == "fp64" else (np.complex64, _lib.qps_cinv)
+    A = np.asarray(A, dtype=dt)
     nb, n = A.shape[0], A.shape[1]
     Af = np.array(np.transpose(A, (0, 2, 1)), order="C", copy=True)
-    _check(_lib.qps_zinv(_ptr(Af), n, nb, PTR_HOST))
+    _check(fn(_ptr(Af), n, nb, PTR_HOST))
     return np.transpose(Af, (0, 2, 1))
 
 

@@ -166,6 +166,7 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
   if (o.quad != HBS_QUAD_KR6 && o.quad != HBS_QUAD_KRESS) { set_error("hbs_build: unknown quadrature"); return HBS_E_INVALID_ARG; }
   if (o.compress != HBS_COMPRESS_PROXY && o.compress != HBS_COMPRESS_EXACT) { set_error("hbs_build: unknown compression"); return HBS_E_INVALID_ARG; }
   if (o.ptr_mode != HBS_PTR_HOST && o.ptr_mode != HBS_PTR_DEVICE) { set_error("hbs_build: unknown ptr_mode"); return HBS_E_INVALID_ARG; }
+  if (o.precision != HBS_FP64 && o.precision != HBS_FP32_PRECOND) { set_error("hbs_build: unknown precision"); return HBS_E_INVALID_ARG; }
   if (o.quad == HBS_QUAD_KR6 && N < 13) { set_error("hbs_build: KR6 needs N >= 13"); return HBS_E_INVALID_ARG; }
   if (o.quad == HBS_QUAD_KRESS) {
     if (N % 2) { set_error("hbs_build: Kress quadrature needs even N"); return HBS_E_INVALID_ARG; }
@@ -263,7 +264,7 @@ static int apply_common(hbs_handle* h, const double* in, int64_t nrhs, double* o
     B = reinterpret_cast<const cplx*>(in);
     X = reinterpret_cast<cplx*>(outp);
   }
-  int rc = qps::apply_factors(h, inverse, B, N, X, N, nrhs);
+  int rc = inverse ? qps::apply_inverse(h, B, N, X, N, nrhs) : qps::apply_factors(h, false, B, N, X, N, nrhs);
   if (rc != HBS_OK) return rc;
   if (inverse && refine > 0) {
     // x <- x + A^{-1}(b - A x) with the compressed forward operator
@@ -274,7 +275,7 @@ static int apply_common(hbs_handle* h, const double* in, int64_t nrhs, double* o
       rc = qps::apply_factors(h, false, X, N, rb.as<cplx>(), N, nrhs);
       if (rc != HBS_OK) return rc;
       CKD(launch_axpby(N, (int)nrhs, mkc(1, 0), B, N, mkc(-1, 0), rb.as<cplx>(), N, st));
-      rc = qps::apply_factors(h, true, rb.as<cplx>(), N, zb.as<cplx>(), N, nrhs);
+      rc = qps::apply_inverse(h, rb.as<cplx>(), N, zb.as<cplx>(), N, nrhs);
       if (rc != HBS_OK) return rc;
       CKD(launch_axpby(N, (int)nrhs, mkc(1, 0), zb.as<cplx>(), N, mkc(1, 0), X, N, st));
     }
@@ -436,63 +437,86 @@ int qps_matrix_entries(hbs_handle* h, const int32_t* rows, const int32_t* cols, 
   return HBS_OK;
 }
 
-int qps_zgemm(const double* A, const double* B, double* C, int32_t m, int32_t n, int32_t k, int32_t nbatch, int32_t transA,
-              int32_t accumulate, int32_t ptr_mode) {
+}  // extern "C"
+
+namespace {
+// shared body of the complex128 / complex64 GEMM diagnostics
+template <class R>
+int gemm_diag(const char* name, const R* A, const R* B, R* C, int32_t m, int32_t n, int32_t k, int32_t nbatch,
+              int32_t transA, int32_t accumulate, int32_t ptr_mode) {
+  typedef typename cx<R>::T T;
   clear_error();
-  if (!A || !B || !C || m <= 0 || n <= 0 || k < 0 || nbatch <= 0) { set_error("qps_zgemm: bad arguments"); return HBS_E_INVALID_ARG; }
+  if (!A || !B || !C || m <= 0 || n <= 0 || k < 0 || nbatch <= 0) { set_error(std::string(name) + ": bad arguments"); return HBS_E_INVALID_ARG; }
   const size_t sa = (size_t)m * k, sb = (size_t)k * n, sc = (size_t)m * n;
   DevBuf da, dbb, dc, arena, ws;
-  const cplx *pa, *pb;
-  cplx* pc;
+  const T *pa, *pb;
+  T* pc;
   if (ptr_mode == HBS_PTR_HOST) {
-    CKD(da.reserve(sizeof(cplx) * sa * nbatch + 16));
-    CKD(dbb.reserve(sizeof(cplx) * sb * nbatch + 16));
-    CKD(dc.reserve(sizeof(cplx) * sc * nbatch));
-    if (sa) CKD(hipMemcpy(da.p, A, sizeof(cplx) * sa * nbatch, hipMemcpyHostToDevice));
-    if (sb) CKD(hipMemcpy(dbb.p, B, sizeof(cplx) * sb * nbatch, hipMemcpyHostToDevice));
-    CKD(hipMemcpy(dc.p, C, sizeof(cplx) * sc * nbatch, hipMemcpyHostToDevice));
-    pa = da.as<cplx>(); pb = dbb.as<cplx>(); pc = dc.as<cplx>();
+    CKD(da.reserve(sizeof(T) * sa * nbatch + 16));
+    CKD(dbb.reserve(sizeof(T) * sb * nbatch + 16));
+    CKD(dc.reserve(sizeof(T) * sc * nbatch));
+    if (sa) CKD(hipMemcpy(da.p, A, sizeof(T) * sa * nbatch, hipMemcpyHostToDevice));
+    if (sb) CKD(hipMemcpy(dbb.p, B, sizeof(T) * sb * nbatch, hipMemcpyHostToDevice));
+    CKD(hipMemcpy(dc.p, C, sizeof(T) * sc * nbatch, hipMemcpyHostToDevice));
+    pa = da.as<T>(); pb = dbb.as<T>(); pc = dc.as<T>();
   } else {
-    pa = reinterpret_cast<const cplx*>(A); pb = reinterpret_cast<const cplx*>(B); pc = reinterpret_cast<cplx*>(C);
+    pa = reinterpret_cast<const T*>(A); pb = reinterpret_cast<const T*>(B); pc = reinterpret_cast<T*>(C);
   }
-  std::vector<GemmDesc> v;
+  std::vector<GemmDescT<R>> v;
   for (int b = 0; b < nbatch; ++b) {
-    GemmDesc g;
+    GemmDescT<R> g;
     g.A = pa + sa * b; g.B = pb + sb * b; g.C = pc + sc * b;
     g.m = m; g.n = n; g.k = k;
     g.lda = transA ? k : m; g.ldb = k; g.ldc = m;
     g.transA = transA; g.pad = 0;
-    g.alpha = mkc(1, 0);
-    g.beta = accumulate ? mkc(1, 0) : mkc(0, 0);
+    g.alpha = cx<R>::make(1, 0);
+    g.beta = accumulate ? cx<R>::make(1, 0) : cx<R>::make(0, 0);
     v.push_back(g);
   }
-  CKD(gemm_batched(arena, v, nullptr, &ws));
+  CKD(gemm_batched<R>(arena, v, nullptr, &ws));
   CKD(hipDeviceSynchronize());
-  if (ptr_mode == HBS_PTR_HOST) CKD(hipMemcpy(C, pc, sizeof(cplx) * sc * nbatch, hipMemcpyDeviceToHost));
+  if (ptr_mode == HBS_PTR_HOST) CKD(hipMemcpy(C, pc, sizeof(T) * sc * nbatch, hipMemcpyDeviceToHost));
   return HBS_OK;
 }
 
-int qps_zinv(double* A, int32_t n, int32_t nbatch, int32_t ptr_mode) {
+template <class R>
+int inv_diag(const char* name, R* A, int32_t n, int32_t nbatch, int32_t ptr_mode) {
+  typedef typename cx<R>::T T;
   clear_error();
-  if (!A || n <= 0 || nbatch <= 0) { set_error("qps_zinv: bad arguments"); return HBS_E_INVALID_ARG; }
+  if (!A || n <= 0 || nbatch <= 0) { set_error(std::string(name) + ": bad arguments"); return HBS_E_INVALID_ARG; }
   const size_t sz = (size_t)n * n;
   DevBuf da, arena, work;
-  cplx* pa;
+  T* pa;
   if (ptr_mode == HBS_PTR_HOST) {
-    CKD(da.reserve(sizeof(cplx) * sz * nbatch));
-    CKD(hipMemcpy(da.p, A, sizeof(cplx) * sz * nbatch, hipMemcpyHostToDevice));
-    pa = da.as<cplx>();
+    CKD(da.reserve(sizeof(T) * sz * nbatch));
+    CKD(hipMemcpy(da.p, A, sizeof(T) * sz * nbatch, hipMemcpyHostToDevice));
+    pa = da.as<T>();
   } else {
-    pa = reinterpret_cast<cplx*>(A);
+    pa = reinterpret_cast<T*>(A);
   }
-  std::vector<InvDesc> v;
+  std::vector<InvDescT<R>> v;
   for (int b = 0; b < nbatch; ++b) v.push_back({pa + sz * b, n, n});
   bool sing = false;
-  CKD(inv_batched(arena, work, v, nullptr, &sing));
-  if (ptr_mode == HBS_PTR_HOST) CKD(hipMemcpy(A, pa, sizeof(cplx) * sz * nbatch, hipMemcpyDeviceToHost));
-  if (sing) { set_error("qps_zinv: singular matrix"); return HBS_E_SINGULAR; }
+  CKD(inv_batched<R>(arena, work, v, nullptr, &sing));
+  CKD(hipDeviceSynchronize());
+  if (ptr_mode == HBS_PTR_HOST) CKD(hipMemcpy(A, pa, sizeof(T) * sz * nbatch, hipMemcpyDeviceToHost));
+  if (sing) { set_error(std::string(name) + ": singular matrix"); return HBS_E_SINGULAR; }
   return HBS_OK;
 }
+}  // namespace
+
+extern "C" {
+
+int qps_zgemm(const double* A, const double* B, double* C, int32_t m, int32_t n, int32_t k, int32_t nbatch, int32_t transA,
+              int32_t accumulate, int32_t ptr_mode) {
+  return gemm_diag<double>("qps_zgemm", A, B, C, m, n, k, nbatch, transA, accumulate, ptr_mode);
+}
+int qps_cgemm(const float* A, const float* B, float* C, int32_t m, int32_t n, int32_t k, int32_t nbatch, int32_t transA,
+              int32_t accumulate, int32_t ptr_mode) {
+  return gemm_diag<float>("qps_cgemm", A, B, C, m, n, k, nbatch, transA, accumulate, ptr_mode);
+}
+int qps_zinv(double* A, int32_t n, int32_t nbatch, int32_t ptr_mode) { return inv_diag<double>("qps_zinv", A, n, nbatch, ptr_mode); }
+int qps_cinv(float* A, int32_t n, int32_t nbatch, int32_t ptr_mode) { return inv_diag<float>("qps_cinv", A, n, nbatch, ptr_mode); }
 
 int qps_profile_enable(int32_t on) {
   profile_enable(on != 0);

@@ -1,27 +1,45 @@
-// Batched complex FP64 GEMM on CDNA4 matrix cores: C = alpha op(A) B + beta C.
+// Batched complex GEMM on CDNA4 matrix cores: C = alpha op(A) B + beta C, in complex128
+// (v_mfma_f64_16x16x4f64) or complex64 (v_mfma_f32_16x16x4f32).
 //
 // Each workgroup (4 wavefronts, 2 x 2) computes a 64 x 64 tile of one batch entry; each
-// wavefront owns a 32 x 32 sub-tile = 2 x 2 blocks of the 16 x 16 x 4 FP64 MFMA.  A complex
-// product takes four real MFMAs into two accumulators (re += ar br - ai bi, im += ar bi + ai br).
-// Operands are staged through LDS in k-slices of 16, split into real and imaginary planes.
-// Batch entries may have different shapes; grid.x covers the largest tile count and
-// workgroups past an entry's tile count exit.
+// wavefront owns a 32 x 32 sub-tile = 2 x 2 blocks of the 16 x 16 x 4 MFMA.  A complex
+// product takes four real MFMAs into two accumulators (re += ar br - ai bi, im += ar bi + ai br),
+// issued so that two updates of one accumulator are 7 MFMAs apart.  Operands are staged
+// through LDS in k-slices of 16 (real and imaginary planes); the next slice is fetched into
+// registers while the current one is multiplied.  Batch entries may have different shapes;
+// grid.x covers the largest tile count and workgroups past an entry's tile count exit.
+// Long-K entries with few output tiles are split along K into a workspace and summed in a
+// fixed order by a second kernel.
 #include "internal.h"
 
 #include <algorithm>
 
 namespace {
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
 constexpr int BM = 64, BN = 64, BK = 16, PADK = 2;
 
-__device__ inline dbl4 mfma(double a, double b, dbl4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_zgemm(const GemmDesc* __restrict__ descs) {
-  const GemmDesc d = descs[blockIdx.y];
+// 16 x 16 x 4 MFMA and its result layout (measured): register r of lane l holds column l % 16
+// and row (l / 16) + 4 r in FP64, row 4 (l / 16) + r in FP32.
+template <class R> struct mfma_t;
+template <> struct mfma_t<double> {
+  typedef dbl4 acc;
+  __device__ static acc op(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct mfma_t<float> {
+  typedef flt4 acc;
+  __device__ static acc op(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <class R>
+__global__ __launch_bounds__(256) void k_gemm(const GemmDescT<R>* __restrict__ descs) {
+  typedef typename cx<R>::T C_t;
+  typedef typename mfma_t<R>::acc acc_t;
+  const GemmDescT<R> d = descs[blockIdx.y];
   const int tm = (d.m + BM - 1) / BM, tn = (d.n + BN - 1) / BN;
   const int t = blockIdx.x;
   if (t >= tm * tn || d.k <= 0) {
@@ -31,30 +49,31 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc* __restrict__ desc
       for (int e = threadIdx.x; e < BM * BN; e += 256) {
         const int i = i0 + e % BM, j = j0 + e / BM;
         if (i < d.m && j < d.n) {
-          cplx* c = d.C + i + (size_t)j * d.ldc;
-          *c = (d.beta.x == 0.0 && d.beta.y == 0.0) ? mkc(0, 0) : cmul(d.beta, *c);
+          C_t* c = d.C + i + (size_t)j * d.ldc;
+          *c = (d.beta.x == 0 && d.beta.y == 0) ? cx<R>::make(0, 0) : cmul(d.beta, *c);
         }
       }
     }
     return;
   }
   const int i0 = (t % tm) * BM, j0 = (t / tm) * BN;
-  __shared__ double Are[BK][BM + PADK], Aim[BK][BM + PADK];
-  __shared__ double Bre[BK][BN + PADK], Bim[BK][BN + PADK];
+  __shared__ R Are[BK][BM + PADK], Aim[BK][BM + PADK];
+  __shared__ R Bre[BK][BN + PADK], Bim[BK][BN + PADK];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv & 1, wn = wv >> 1;
-  dbl4 accr[2][2], acci[2][2];
+  acc_t accr[2][2], acci[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      accr[a][b] = (dbl4){0.0, 0.0, 0.0, 0.0};
-      acci[a][b] = (dbl4){0.0, 0.0, 0.0, 0.0};
+      accr[a][b] = (acc_t){0, 0, 0, 0};
+      acci[a][b] = (acc_t){0, 0, 0, 0};
     }
-  const cplx* __restrict__ A = d.A;
-  const cplx* __restrict__ B = d.B;
+  const C_t* __restrict__ A = d.A;
+  const C_t* __restrict__ B = d.B;
+  const C_t zc = cx<R>::make(0, 0);
   // register staging of one k-slice: 4 elements of op(A) and 4 of B per thread
-  cplx ra[4], rb[4];
+  C_t ra[4], rb[4];
   auto load_slice = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -62,10 +81,10 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc* __restrict__ desc
       int ii, kk;
       if (!d.transA) { ii = e % BM; kk = e / BM; } else { kk = e % BK; ii = e / BK; }
       const int gi = i0 + ii, gk = k0 + kk;
-      ra[q] = (gi < d.m && gk < d.k) ? (d.transA ? A[gk + (size_t)gi * d.lda] : A[gi + (size_t)gk * d.lda]) : mkc(0, 0);
+      ra[q] = (gi < d.m && gk < d.k) ? (d.transA ? A[gk + (size_t)gi * d.lda] : A[gi + (size_t)gk * d.lda]) : zc;
       const int kb = e % BK, jj = e / BK;
       const int gj = j0 + jj, gkb = k0 + kb;
-      rb[q] = (gj < d.n && gkb < d.k) ? B[gkb + (size_t)gj * d.ldb] : mkc(0, 0);
+      rb[q] = (gj < d.n && gkb < d.k) ? B[gkb + (size_t)gj * d.ldb] : zc;
     }
   };
   auto store_slice = [&]() {
@@ -90,7 +109,7 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc* __restrict__ desc
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kk = ks + (lane >> 4);
-      double ar[2], ai[2], br[2], bi[2];
+      R ar[2], ai[2], br[2], bi[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const int ii = wm * 32 + a * 16 + (lane & 15);
@@ -107,19 +126,19 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc* __restrict__ desc
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) accr[a][b] = mfma(ar[a], br[b], accr[a][b]);
+        for (int b = 0; b < 2; ++b) accr[a][b] = mfma_t<R>::op(ar[a], br[b], accr[a][b]);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acci[a][b] = mfma(ar[a], bi[b], acci[a][b]);
+        for (int b = 0; b < 2; ++b) acci[a][b] = mfma_t<R>::op(ar[a], bi[b], acci[a][b]);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) accr[a][b] = mfma(-ai[a], bi[b], accr[a][b]);
+        for (int b = 0; b < 2; ++b) accr[a][b] = mfma_t<R>::op(-ai[a], bi[b], accr[a][b]);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acci[a][b] = mfma(ai[a], br[b], acci[a][b]);
+        for (int b = 0; b < 2; ++b) acci[a][b] = mfma_t<R>::op(ai[a], br[b], acci[a][b]);
     }
     __syncthreads();
     if (more) {
@@ -128,7 +147,7 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc* __restrict__ desc
     }
   }
   // epilogue: register r of a lane holds row (lane/16) + 4r, column lane%16 of each 16 x 16 block
-  const bool zero_beta = (d.beta.x == 0.0 && d.beta.y == 0.0);
+  const bool zero_beta = (d.beta.x == 0 && d.beta.y == 0);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -137,10 +156,10 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc* __restrict__ desc
       if (j >= d.n) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * r;
+        const int i = i0 + wm * 32 + a * 16 + mfma_t<R>::row(lane, r);
         if (i >= d.m) continue;
-        cplx v = cmul(d.alpha, mkc(accr[a][b][r], acci[a][b][r]));
-        cplx* c = d.C + i + (size_t)j * d.ldc;
+        C_t v = cmul(d.alpha, cx<R>::make(accr[a][b][r], acci[a][b][r]));
+        C_t* c = d.C + i + (size_t)j * d.ldc;
         if (!zero_beta) v = cadd(v, cmul(d.beta, *c));
         *c = v;
       }
@@ -148,39 +167,66 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc* __restrict__ desc
 }
 
 // C = alpha * sum_s W_s + beta * C over S partial products (m x n, ld m each)
-__global__ __launch_bounds__(256) void k_splitk_reduce(cplx* __restrict__ C, int ldc, int m, int n,
-                                                       const cplx* __restrict__ W, int S, cplx alpha, cplx beta) {
+template <class C_t>
+__global__ __launch_bounds__(256) void k_splitk_reduce(C_t* __restrict__ C, int ldc, int m, int n,
+                                                       const C_t* __restrict__ W, int S, C_t alpha, C_t beta) {
   const int64_t total = (int64_t)m * n;
   for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    cplx acc = mkc(0, 0);
-    for (int q = 0; q < S; ++q) acc = cadd(acc, W[e + q * total]);
+    C_t acc = W[e];
+    for (int q = 1; q < S; ++q) acc = cadd(acc, W[e + q * total]);
     const int i = (int)(e % m), j = (int)(e / m);
-    cplx* c = C + i + (size_t)j * ldc;
-    cplx v = cmul(alpha, acc);
-    if (!(beta.x == 0.0 && beta.y == 0.0)) v = cadd(v, cmul(beta, *c));
+    C_t* c = C + i + (size_t)j * ldc;
+    C_t v = cmul(alpha, acc);
+    if (!(beta.x == 0 && beta.y == 0)) v = cadd(v, cmul(beta, *c));
     *c = v;
   }
+}
+
+// complex128 <-> complex64
+__global__ __launch_bounds__(256) void k_cast_d2f(const cplx* __restrict__ s, cplxf* __restrict__ d, int64_t n) {
+  for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) d[e] = mkcf((float)s[e].x, (float)s[e].y);
+}
+__global__ __launch_bounds__(256) void k_cast_f2d(const cplxf* __restrict__ s, cplx* __restrict__ d, int64_t n) {
+  for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) d[e] = mkc(s[e].x, s[e].y);
 }
 
 }  // namespace
 
 namespace qps {
 
-hipError_t launch_zgemm(const GemmDesc* d, int nd, int max_tiles, hipStream_t s) {
+template <class R>
+hipError_t launch_gemm(const GemmDescT<R>* d, int nd, int max_tiles, hipStream_t s) {
   if (nd == 0 || max_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zgemm, dim3(max_tiles, nd), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_gemm<R>, dim3(max_tiles, nd), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+template hipError_t launch_gemm<double>(const GemmDesc*, int, int, hipStream_t);
+template hipError_t launch_gemm<float>(const GemmDesc32*, int, int, hipStream_t);
+
+hipError_t launch_cast_d2f(const cplx* src, cplxf* dst, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cast_d2f, dim3((int)std::min<int64_t>(8192, (n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+hipError_t launch_cast_f2d(const cplxf* src, cplx* dst, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cast_f2d, dim3((int)std::min<int64_t>(8192, (n + 255) / 256)), dim3(256), 0, s, src, dst, n);
   return hipGetLastError();
 }
 
-static int tiles_of(const GemmDesc& g) { return ((g.m + BM - 1) / BM) * ((g.n + BN - 1) / BN); }
+template <class R>
+static int tiles_of(const GemmDescT<R>& g) { return ((g.m + BM - 1) / BM) * ((g.n + BN - 1) / BN); }
 
-hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDesc>& v0, hipStream_t s, DevBuf* ws) {
+template <class R>
+hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDescT<R>>& v0, hipStream_t s, DevBuf* ws) {
+  typedef typename cx<R>::T C_t;
+  typedef GemmDescT<R> GemmDesc;
   if (v0.empty()) return hipSuccess;
   double flops = 0.0, bytes = 0.0;
   int64_t total_tiles = 0;
   for (const auto& g : v0) {
     flops += 8.0 * g.m * (double)g.n * g.k;
-    bytes += 16.0 * ((double)g.m * g.k + (double)g.k * g.n + 2.0 * g.m * g.n);
+    bytes += 2.0 * sizeof(R) * ((double)g.m * g.k + (double)g.k * g.n + 2.0 * g.m * g.n);
     total_tiles += tiles_of(g);
   }
   // split-K when there are too few output tiles to occupy the chip and the inner dimension is
@@ -202,10 +248,10 @@ hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDesc>& v0, hipStrea
     }
   }
   if (wtot > 0) {
-    hipError_t e = ws->reserve(sizeof(cplx) * wtot);
+    hipError_t e = ws->reserve(sizeof(C_t) * wtot);
     if (e != hipSuccess) return e;
   }
-  struct Red { cplx* C; int ldc, m, n; const cplx* W; int S; cplx alpha, beta; };
+  struct Red { C_t* C; int ldc, m, n; const C_t* W; int S; C_t alpha, beta; };
   std::vector<Red> reds;
   std::vector<GemmDesc> v;
   int64_t woff = 0;
@@ -216,7 +262,7 @@ hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDesc>& v0, hipStrea
       v.push_back(g);
       continue;
     }
-    cplx* W = ws->as<cplx>() + woff;
+    C_t* W = ws->as<C_t>() + woff;
     woff += (int64_t)S * g.m * g.n;
     reds.push_back({g.C, g.ldc, g.m, g.n, W, S, g.alpha, g.beta});
     const int kc = (g.k + S - 1) / S;
@@ -228,8 +274,8 @@ hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDesc>& v0, hipStrea
       h.B = g.B + k0;
       h.C = W + (int64_t)q * g.m * g.n;
       h.ldc = g.m;
-      h.alpha = mkc(1, 0);
-      h.beta = mkc(0, 0);
+      h.alpha = cx<R>::make(1, 0);
+      h.beta = cx<R>::make(0, 0);
       v.push_back(h);
     }
   }
@@ -237,15 +283,17 @@ hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDesc>& v0, hipStrea
   for (const auto& g : v) max_tiles = std::max(max_tiles, tiles_of(g));
   hipError_t e = upload(arena, v, s);
   if (e != hipSuccess) return e;
-  ProfScope ps("zgemm", s, flops, bytes);
-  e = launch_zgemm(arena.as<GemmDesc>(), (int)v.size(), max_tiles, s);
+  ProfScope ps(sizeof(R) == 8 ? "zgemm" : "cgemm", s, flops, bytes);
+  e = launch_gemm<R>(arena.as<GemmDesc>(), (int)v.size(), max_tiles, s);
   if (e != hipSuccess) return e;
   for (const auto& r : reds) {
     const int64_t tot = (int64_t)r.m * r.n;
     const int grid = (int)std::min<int64_t>(8192, (tot + 255) / 256);
-    hipLaunchKernelGGL(k_splitk_reduce, dim3(grid), dim3(256), 0, s, r.C, r.ldc, r.m, r.n, r.W, r.S, r.alpha, r.beta);
+    hipLaunchKernelGGL(k_splitk_reduce<C_t>, dim3(grid), dim3(256), 0, s, r.C, r.ldc, r.m, r.n, r.W, r.S, r.alpha, r.beta);
   }
   return hipGetLastError();
 }
+template hipError_t gemm_batched<double>(DevBuf&, const std::vector<GemmDesc>&, hipStream_t, DevBuf*);
+template hipError_t gemm_batched<float>(DevBuf&, const std::vector<GemmDesc32>&, hipStream_t, DevBuf*);
 
 }  // namespace qps

@@ -71,6 +71,12 @@ int build(hbs_handle* h) {
   if (L < 1) L = 1;
   while ((N >> L) < 2 && L > 1) --L;
   h->L = L;
+  if (h->opts.precision == HBS_FP32_PRECOND) {
+    const int t = h->opts.fp64_top_levels;
+    h->fp64_top = std::min(L, t < 0 ? 0 : (t == 0 ? 3 : t));
+  } else {
+    h->fp64_top = L;
+  }
   h->lv.clear();
   h->lv.resize(L + 1);
   const bool exact = h->opts.compress == HBS_COMPRESS_EXACT;
@@ -349,12 +355,15 @@ int build(hbs_handle* h) {
     }
     V.oE = V.oP;
     V.oFt = V.oP;
+    const bool fp32 = l > h->fp64_top;  // this level's inverse factors in complex64
     CK(V.P.reserve(sizeof(cplx) * V.oP[nb]));
-    CK(V.E.reserve(sizeof(cplx) * V.oP[nb]));
-    CK(V.Ft.reserve(sizeof(cplx) * V.oP[nb]));
-    CK(V.Dh.reserve(sizeof(cplx) * V.oDh[nb]));
-    CK(tmpY.reserve(sizeof(cplx) * V.oP[nb]));
-    CK(tmpZt.reserve(sizeof(cplx) * V.oP[nb]));
+    if (!fp32) {
+      CK(V.E.reserve(sizeof(cplx) * V.oP[nb]));
+      CK(V.Ft.reserve(sizeof(cplx) * V.oP[nb]));
+      CK(tmpY.reserve(sizeof(cplx) * V.oP[nb]));
+      CK(tmpZt.reserve(sizeof(cplx) * V.oP[nb]));
+    }
+    CK(V.Dh.reserve(sizeof(cplx) * std::max<int64_t>(1, V.oDh[nb])));
     cplx* dP = V.P.as<cplx>();
     {
       std::vector<PDesc> pd;
@@ -367,7 +376,76 @@ int build(hbs_handle* h) {
       CK(launch_buildP(arena.as<PDesc>(), nb, maxe, st));
     }
     bool sing = false;
-    {
+    if (fp32) {
+      // complex64 inverse factors from the FP64 blocks D and interpolation matrices P
+      CK(V.G32.reserve(sizeof(cplxf) * V.oG[nb]));
+      CK(V.E32.reserve(sizeof(cplxf) * V.oP[nb]));
+      CK(V.Ft32.reserve(sizeof(cplxf) * V.oP[nb]));
+      DevBuf p32, y32, z32, dh32;
+      CK(p32.reserve(sizeof(cplxf) * V.oP[nb]));
+      CK(y32.reserve(sizeof(cplxf) * V.oP[nb]));
+      CK(z32.reserve(sizeof(cplxf) * V.oP[nb]));
+      CK(dh32.reserve(sizeof(cplxf) * std::max<int64_t>(1, V.oDh[nb])));
+      cplxf* G32 = V.G32.as<cplxf>();
+      cplxf* P32 = p32.as<cplxf>();
+      cplxf* Y32 = y32.as<cplxf>();
+      cplxf* Z32 = z32.as<cplxf>();
+      cplxf* Dh32 = dh32.as<cplxf>();
+      cplxf* E32 = V.E32.as<cplxf>();
+      cplxf* F32 = V.Ft32.as<cplxf>();
+      CK(launch_cast_d2f(dG, G32, V.oG[nb], st));
+      CK(launch_cast_d2f(dP, P32, V.oP[nb], st));
+      std::vector<InvDesc32> iv;
+      for (int b = 0; b < nb; ++b) iv.push_back({G32 + V.oG[b], V.n[b], V.n[b]});
+      CK(inv_batched<float>(arena, h->work, iv, st, &sing));
+      if (sing) {
+        set_error("hbs_build: singular diagonal block at level " + std::to_string(l));
+        return HBS_E_SINGULAR;
+      }
+      const cplxf one = mkcf(1, 0), zero = mkcf(0, 0), mone = mkcf(-1, 0);
+      auto g32 = [&](const cplxf* A, int lda, int tA, const cplxf* B, int ldb, cplxf* C, int ldc, int m, int n, int k,
+                     cplxf al, cplxf be) {
+        GemmDesc32 g;
+        g.A = A; g.B = B; g.C = C; g.m = m; g.n = n; g.k = k; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+        g.transA = tA; g.pad = 0; g.alpha = al; g.beta = be;
+        return g;
+      };
+      std::vector<GemmDesc32> g1, g2, g3, g4;
+      for (int b = 0; b < nb; ++b) {
+        const int n = V.n[b], k = V.k[b];
+        g1.push_back(g32(G32 + V.oG[b], n, 0, P32 + V.oP[b], n, Y32 + V.oP[b], n, n, k, n, one, zero));
+        g1.push_back(g32(P32 + V.oP[b], n, 1, G32 + V.oG[b], n, Z32 + V.oP[b], k, k, n, n, one, zero));
+      }
+      CK(gemm_batched<float>(arena, g1, st));
+      CK(hipStreamSynchronize(st));
+      for (int b = 0; b < nb; ++b)
+        g2.push_back(g32(Z32 + V.oP[b], V.k[b], 0, P32 + V.oP[b], V.n[b], Dh32 + V.oDh[b], V.k[b], V.k[b], V.k[b], V.n[b],
+                         one, zero));
+      CK(gemm_batched<float>(arena, g2, st));
+      CK(hipStreamSynchronize(st));
+      std::vector<InvDesc32> iv2;
+      for (int b = 0; b < nb; ++b) iv2.push_back({Dh32 + V.oDh[b], V.k[b], V.k[b]});
+      CK(inv_batched<float>(arena, h->work, iv2, st, &sing));
+      if (sing) {
+        set_error("hbs_build: singular reduced block at level " + std::to_string(l));
+        return HBS_E_SINGULAR;
+      }
+      for (int b = 0; b < nb; ++b) {
+        const int n = V.n[b], k = V.k[b];
+        g3.push_back(g32(Y32 + V.oP[b], n, 0, Dh32 + V.oDh[b], k, E32 + V.oP[b], n, n, k, k, one, zero));
+        g3.push_back(g32(Dh32 + V.oDh[b], k, 0, Z32 + V.oP[b], k, F32 + V.oP[b], k, k, n, k, one, zero));
+      }
+      CK(gemm_batched<float>(arena, g3, st));
+      CK(hipStreamSynchronize(st));
+      for (int b = 0; b < nb; ++b)
+        g4.push_back(g32(E32 + V.oP[b], V.n[b], 0, Z32 + V.oP[b], V.k[b], G32 + V.oG[b], V.n[b], V.n[b], V.n[b], V.k[b],
+                         mone, one));
+      CK(gemm_batched<float>(arena, g4, st));
+      // the parent's diagonal block needs D^ in FP64
+      CK(launch_cast_f2d(Dh32, V.Dh.as<cplx>(), V.oDh[nb], st));
+      CK(hipStreamSynchronize(st));
+      V.G.release();  // D itself is not a factor in this mode
+    } else {
       std::vector<InvDesc> iv;
       for (int b = 0; b < nb; ++b) iv.push_back({dG + V.oG[b], V.n[b], V.n[b]});
       CK(inv_batched(arena, h->work, iv, st, &sing));
@@ -375,7 +453,6 @@ int build(hbs_handle* h) {
         set_error("hbs_build: singular diagonal block at level " + std::to_string(l));
         return HBS_E_SINGULAR;
       }
-    }
     cplx* Y = tmpY.as<cplx>();
     cplx* Zt = tmpZt.as<cplx>();
     cplx* Dh = V.Dh.as<cplx>();
@@ -424,8 +501,10 @@ int build(hbs_handle* h) {
       CK(gemm_batched(arena, g4, st));
       CK(hipStreamSynchronize(st));
     }
+    }
     if (l < L) h->lv[l + 1].Dh.release();
-    h->factor_bytes += (int64_t)sizeof(cplx) * (3 * V.oP[nb] + 2 * V.oG[nb]);
+    h->factor_bytes += fp32 ? (int64_t)sizeof(cplx) * (V.oP[nb] + V.oG[nb]) + (int64_t)sizeof(cplxf) * (2 * V.oP[nb] + V.oG[nb])
+                            : (int64_t)sizeof(cplx) * (3 * V.oP[nb] + 2 * V.oG[nb]);
   }
 
   // ---- root
@@ -516,93 +595,222 @@ int apply_interp(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx
   return HBS_OK;
 }
 
-int apply_factors(hbs_handle* h, bool inv, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r) {
+template <class R>
+static GemmDescT<R> gdt(const typename cx<R>::T* A, int lda, int transA, const typename cx<R>::T* B, int ldb,
+                        typename cx<R>::T* C, int ldc, int m, int n, int k, double beta) {
+  GemmDescT<R> g;
+  g.A = A; g.B = B; g.C = C;
+  g.m = m; g.n = n; g.k = k;
+  g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+  g.transA = transA; g.pad = 0;
+  g.alpha = cx<R>::make(1, 0);
+  g.beta = cx<R>::make(beta, 0);
+  return g;
+}
+
+// The telescoping factorization applied level by level: upward b^ = Up b (F^T or P^T), the root
+// (inverse or coupling), downward x = Dn x^ + Dg b (E, G or P, D_fwd).  The levels > split run in
+// complex64 on the complex64 factors (inverse only), levels 1..split and the root in complex128;
+// the vectors crossing the split are cast.  split = L: everything in complex128.
+namespace {
+struct Step {
+  int kind;  // 0: FP64 GEMM batch, 1: FP32 GEMM batch, 2: cast to complex64, 3: cast to complex128
+  size_t off;
+  int cnt, max_tiles;
+  double flops;
+  const void* src;
+  void* dst;
+  int64_t n;
+};
+}  // namespace
+
+static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r) {
   if (r <= 0) return HBS_OK;
   hipStream_t st = h->stream;
   const int L = h->L;
   auto& lv = h->lv;
-  // workspace: up[l] (l = 0..L-1) holds lv[l+1].ktot rows; x ping-pong of max ntot (l < L); root result
-  std::vector<int64_t> upoff(L + 1, 0);
-  for (int l = 0; l < L; ++l) upoff[l + 1] = upoff[l] + lv[l + 1].ktot * r;
-  int64_t xmax = 1;
-  for (int l = 1; l < L; ++l) xmax = std::max<int64_t>(xmax, lv[l].ntot);
-  CK(h->ab_up.reserve(sizeof(cplx) * std::max<int64_t>(1, upoff[L])));
-  CK(h->ab_x0.reserve(sizeof(cplx) * xmax * r));
-  CK(h->ab_x1.reserve(sizeof(cplx) * xmax * r));
-  CK(h->ab_root.reserve(sizeof(cplx) * h->nroot * r));
-  cplx* up = h->ab_up.as<cplx>();
-  cplx* xr = h->ab_root.as<cplx>();
-  auto upbuf = [&](int l) { return up + upoff[l]; };  // rows lv[l+1].ktot = lv[l].ntot
-  auto xbuf = [&](int l) { return (l & 1) ? h->ab_x1.as<cplx>() : h->ab_x0.as<cplx>(); };
+  if (!inv) split = L;
+  split = std::max(0, std::min(L, split));
+  const bool mixed = split < L;  // level L (and maybe more) in complex64
+  const int64_t N = h->N;
   const int rr = (int)r;
+  // up[j] (j = 0..L-1) = output of the upward step of level j+1, lv[j+1].ktot rows
+  std::vector<int64_t> rows_up(L);
+  for (int j = 0; j < L; ++j) rows_up[j] = lv[j + 1].ktot;
+  // complex128 up buffers hold j = 0..min(split, L-1); complex64 ones j = split..L-1
+  std::vector<int64_t> o64(L + 1, 0), o32(L + 1, 0);
+  for (int j = 0; j < L; ++j) {
+    o64[j + 1] = o64[j] + (j <= split ? rows_up[j] * r : 0);
+    o32[j + 1] = o32[j] + (j >= split ? rows_up[j] * r : 0);
+  }
+  int64_t x64max = 1, x32max = 1;
+  for (int l = 1; l < L; ++l) {
+    if (l <= split) x64max = std::max<int64_t>(x64max, lv[l].ntot);
+    else x32max = std::max<int64_t>(x32max, lv[l].ntot);
+  }
+  if (mixed) x32max = std::max<int64_t>(x32max, lv[split + 1].ktot);
+  CK(h->ab_up.reserve(sizeof(cplx) * std::max<int64_t>(1, o64[L])));
+  CK(h->ab_x0.reserve(sizeof(cplx) * x64max * r));
+  CK(h->ab_x1.reserve(sizeof(cplx) * x64max * r));
+  CK(h->ab_root.reserve(sizeof(cplx) * h->nroot * r));
+  if (mixed) {
+    CK(h->ab_in32.reserve(sizeof(cplxf) * N * r * 2));  // input and output of the complex64 leaf level
+    CK(h->ab_up32.reserve(sizeof(cplxf) * std::max<int64_t>(1, o32[L])));
+    CK(h->ab_x32a.reserve(sizeof(cplxf) * x32max * r));
+    CK(h->ab_x32b.reserve(sizeof(cplxf) * x32max * r));
+  }
+  cplx* up64 = h->ab_up.as<cplx>();
+  cplxf* up32 = mixed ? h->ab_up32.as<cplxf>() : nullptr;
+  cplx* xr = h->ab_root.as<cplx>();
+  cplxf* in32 = mixed ? h->ab_in32.as<cplxf>() : nullptr;
+  cplxf* out32 = mixed ? in32 + N * r : nullptr;
+  auto u64 = [&](int j) { return up64 + o64[j]; };
+  auto u32 = [&](int j) { return up32 + o32[j]; };
+  auto x64 = [&](int l) { return (l & 1) ? h->ab_x1.as<cplx>() : h->ab_x0.as<cplx>(); };
+  auto x32 = [&](int l) { return (l & 1) ? h->ab_x32b.as<cplxf>() : h->ab_x32a.as<cplxf>(); };
 
-  std::vector<GemmDesc> all;
-  std::vector<LaunchRec> recs;
-  auto close = [&](size_t start) {
-    LaunchRec rec{start, (int)(all.size() - start), 0, 0.0};
-    for (size_t i = start; i < all.size(); ++i) {
-      rec.max_tiles = std::max(rec.max_tiles, tiles_of(all[i]));
-      rec.flops += 8.0 * all[i].m * (double)all[i].n * all[i].k;
+  std::vector<GemmDesc> d64;
+  std::vector<GemmDesc32> d32;
+  std::vector<Step> prog;
+  auto close64 = [&](size_t s0) {
+    Step t{0, s0, (int)(d64.size() - s0), 0, 0.0, nullptr, nullptr, 0};
+    for (size_t i = s0; i < d64.size(); ++i) {
+      t.max_tiles = std::max(t.max_tiles, ((d64[i].m + 63) / 64) * ((d64[i].n + 63) / 64));
+      t.flops += 8.0 * d64[i].m * (double)d64[i].n * d64[i].k;
     }
-    if (rec.cnt > 0) recs.push_back(rec);
+    if (t.cnt > 0) prog.push_back(t);
   };
-  // upward pass
+  auto close32 = [&](size_t s0) {
+    Step t{1, s0, (int)(d32.size() - s0), 0, 0.0, nullptr, nullptr, 0};
+    for (size_t i = s0; i < d32.size(); ++i) {
+      t.max_tiles = std::max(t.max_tiles, ((d32[i].m + 63) / 64) * ((d32[i].n + 63) / 64));
+      t.flops += 8.0 * d32[i].m * (double)d32[i].n * d32[i].k;
+    }
+    if (t.cnt > 0) prog.push_back(t);
+  };
+  auto cast = [&](int kind, const void* src, void* dst, int64_t n) { prog.push_back({kind, 0, 0, 0, 0.0, src, dst, n}); };
+
+  // ---- upward
+  if (mixed) {
+    if (ldb == N) {
+      cast(2, B, in32, N * r);
+    } else {
+      for (int64_t c = 0; c < r; ++c) cast(2, B + c * ldb, in32 + c * N, N);
+    }
+  }
   for (int l = L; l >= 1; --l) {
     Level& V = lv[l];
-    const cplx* src = (l == L) ? B : upbuf(l);
-    const int64_t lds = (l == L) ? ldb : V.ntot;
-    cplx* dst = upbuf(l - 1);
-    const int ldd = (int)V.ktot;
-    size_t st0 = all.size();
-    for (int b = 0; b < V.nb; ++b) {
-      const int n = V.n[b], k = V.k[b];
-      if (inv)
-        all.push_back(gd(V.Ft.as<cplx>() + V.oFt[b], k, 0, src + V.aoff[b], (int)lds, dst + V.soff[b], ldd, k, rr, n));
-      else
-        all.push_back(gd(V.P.as<cplx>() + V.oP[b], n, 1, src + V.aoff[b], (int)lds, dst + V.soff[b], ldd, k, rr, n));
+    if (l > split) {
+      const cplxf* src = (l == L) ? in32 : u32(l);
+      const int64_t lds = (l == L) ? N : V.ntot;
+      size_t s0 = d32.size();
+      for (int b = 0; b < V.nb; ++b)
+        d32.push_back(gdt<float>(V.Ft32.as<cplxf>() + V.oFt[b], V.k[b], 0, src + V.aoff[b], (int)lds, u32(l - 1) + V.soff[b],
+                                 (int)V.ktot, V.k[b], rr, V.n[b], 0.0));
+      close32(s0);
+      if (l - 1 == split) cast(3, u32(split), u64(split), rows_up[split] * r);
+    } else {
+      const cplx* src = (l == L) ? B : u64(l);
+      const int64_t lds = (l == L) ? ldb : V.ntot;
+      size_t s0 = d64.size();
+      for (int b = 0; b < V.nb; ++b) {
+        const int n = V.n[b], k = V.k[b];
+        if (inv)
+          d64.push_back(gdt<double>(V.Ft.as<cplx>() + V.oFt[b], k, 0, src + V.aoff[b], (int)lds, u64(l - 1) + V.soff[b],
+                                    (int)V.ktot, k, rr, n, 0.0));
+        else
+          d64.push_back(gdt<double>(V.P.as<cplx>() + V.oP[b], n, 1, src + V.aoff[b], (int)lds, u64(l - 1) + V.soff[b],
+                                    (int)V.ktot, k, rr, n, 0.0));
+      }
+      close64(s0);
     }
-    close(st0);
   }
   {
-    size_t st0 = all.size();
-    const cplx* R = inv ? h->Rinv.as<cplx>() : h->Rfwd.as<cplx>();
-    all.push_back(gd(R, h->nroot, 0, upbuf(0), h->nroot, xr, h->nroot, h->nroot, rr, h->nroot));
-    close(st0);
+    size_t s0 = d64.size();
+    const cplx* Rt = inv ? h->Rinv.as<cplx>() : h->Rfwd.as<cplx>();
+    d64.push_back(gdt<double>(Rt, h->nroot, 0, u64(0), h->nroot, xr, h->nroot, h->nroot, rr, h->nroot, 0.0));
+    close64(s0);
   }
+  // ---- downward
   for (int l = 1; l <= L; ++l) {
     Level& V = lv[l];
-    const cplx* xin = (l == 1) ? xr : xbuf(l - 1);
-    const int ldxin = (int)V.ktot;
-    cplx* out = (l == L) ? X : xbuf(l);
-    const int64_t ldo = (l == L) ? ldx : V.ntot;
-    const cplx* src = (l == L) ? B : upbuf(l);
-    const int64_t lds = (l == L) ? ldb : V.ntot;
-    size_t st0 = all.size();
-    for (int b = 0; b < V.nb; ++b) {
-      const int n = V.n[b], k = V.k[b];
-      const cplx* Dn = inv ? V.E.as<cplx>() + V.oE[b] : V.P.as<cplx>() + V.oP[b];
-      all.push_back(gd(Dn, n, 0, xin + V.soff[b], ldxin, out + V.aoff[b], (int)ldo, n, rr, k));
+    if (l <= split) {
+      const cplx* xin = (l == 1) ? xr : x64(l - 1);
+      cplx* out = (l == L) ? X : x64(l);
+      const int64_t ldo = (l == L) ? ldx : V.ntot;
+      const cplx* src = (l == L) ? B : u64(l);
+      const int64_t lds = (l == L) ? ldb : V.ntot;
+      size_t s0 = d64.size();
+      for (int b = 0; b < V.nb; ++b) {
+        const int n = V.n[b], k = V.k[b];
+        const cplx* Dn = inv ? V.E.as<cplx>() + V.oE[b] : V.P.as<cplx>() + V.oP[b];
+        d64.push_back(gdt<double>(Dn, n, 0, xin + V.soff[b], (int)V.ktot, out + V.aoff[b], (int)ldo, n, rr, k, 0.0));
+      }
+      close64(s0);
+      s0 = d64.size();
+      for (int b = 0; b < V.nb; ++b) {
+        const int n = V.n[b];
+        const cplx* Dg = inv ? V.G.as<cplx>() + V.oG[b] : V.Df.as<cplx>() + V.oG[b];
+        d64.push_back(gdt<double>(Dg, n, 0, src + V.aoff[b], (int)lds, out + V.aoff[b], (int)ldo, n, rr, n, 1.0));
+      }
+      close64(s0);
+    } else {
+      // the complex64 input of level split+1 shares the buffer that level split+2 writes
+      if (l == split + 1) cast(2, (l == 1) ? xr : x64(l - 1), x32(l - 1), V.ktot * r);
+      const cplxf* xin = x32(l - 1);
+      cplxf* out = (l == L) ? out32 : x32(l);
+      const int64_t ldo = (l == L) ? N : V.ntot;
+      const cplxf* src = (l == L) ? in32 : u32(l);
+      const int64_t lds = (l == L) ? N : V.ntot;
+      size_t s0 = d32.size();
+      for (int b = 0; b < V.nb; ++b)
+        d32.push_back(gdt<float>(V.E32.as<cplxf>() + V.oE[b], V.n[b], 0, xin + V.soff[b], (int)V.ktot, out + V.aoff[b],
+                                 (int)ldo, V.n[b], rr, V.k[b], 0.0));
+      close32(s0);
+      s0 = d32.size();
+      for (int b = 0; b < V.nb; ++b)
+        d32.push_back(gdt<float>(V.G32.as<cplxf>() + V.oG[b], V.n[b], 0, src + V.aoff[b], (int)lds, out + V.aoff[b], (int)ldo,
+                                 V.n[b], rr, V.n[b], 1.0));
+      close32(s0);
     }
-    close(st0);
-    st0 = all.size();
-    for (int b = 0; b < V.nb; ++b) {
-      const int n = V.n[b];
-      const cplx* Dg = inv ? V.G.as<cplx>() + V.oG[b] : V.Df.as<cplx>() + V.oG[b];
-      all.push_back(gd(Dg, n, 0, src + V.aoff[b], (int)lds, out + V.aoff[b], (int)ldo, n, rr, n, mkc(1, 0), mkc(1, 0)));
-    }
-    close(st0);
   }
-  CK(upload(h->arena, all, st));
-  const GemmDesc* dd = h->arena.as<GemmDesc>();
+  if (mixed) {
+    if (ldx == N) {
+      cast(3, out32, X, N * r);
+    } else {
+      for (int64_t c = 0; c < r; ++c) cast(3, out32 + c * N, X + c * ldx, N);
+    }
+  }
+  CK(upload(h->arena, d64, st));
+  if (!d32.empty()) CK(upload(h->arena32, d32, st));
+  const GemmDesc* dd64 = h->arena.as<GemmDesc>();
+  const GemmDesc32* dd32 = d32.empty() ? nullptr : h->arena32.as<GemmDesc32>();
   double fl = 0;
-  for (auto& rc : recs) fl += rc.flops;
+  for (auto& t : prog) fl += t.flops;
   ProfScope ps("apply", st, fl, 0.0);
-  for (auto& rc : recs) {
-    ProfScope ps2("zgemm", st, rc.flops, 0.0);
-    CK(launch_zgemm(dd + rc.off, rc.cnt, rc.max_tiles, st));
+  for (auto& t : prog) {
+    if (t.kind == 0) {
+      ProfScope ps2("zgemm", st, t.flops, 0.0);
+      CK(launch_gemm<double>(dd64 + t.off, t.cnt, t.max_tiles, st));
+    } else if (t.kind == 1) {
+      ProfScope ps2("cgemm", st, t.flops, 0.0);
+      CK(launch_gemm<float>(dd32 + t.off, t.cnt, t.max_tiles, st));
+    } else if (t.kind == 2) {
+      CK(launch_cast_d2f(static_cast<const cplx*>(t.src), static_cast<cplxf*>(t.dst), t.n, st));
+    } else {
+      CK(launch_cast_f2d(static_cast<const cplxf*>(t.src), static_cast<cplx*>(t.dst), t.n, st));
+    }
   }
   CK(hipStreamSynchronize(st));
   return HBS_OK;
+}
+
+int apply_factors(hbs_handle* h, bool inv, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r) {
+  return apply_mixed(h, inv, inv ? h->fp64_top : h->L, B, ldb, X, ldx, r);
+}
+
+int apply_inverse(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r) {
+  return apply_mixed(h, true, h->fp64_top, B, ldb, X, ldx, r);
 }
 
 }  // namespace qps

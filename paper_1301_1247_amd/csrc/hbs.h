@@ -16,6 +16,7 @@ struct Level {
   DevBuf act, skel;
   // factors (element offsets into the buffers, per box)
   DevBuf P, E, Ft, G, Df, Dh;
+  DevBuf E32, Ft32, G32;            // complex64 inverse factors (FP32-preconditioner mode)
   std::vector<int64_t> oP, oE, oFt, oG, oDh;
   // bounding circles of the boxes' original points
   std::vector<double> cx, cy, rad;
@@ -36,8 +37,10 @@ struct hbs_handle {
   std::vector<qps::Level> lv;  // lv[1..L]
   int nroot = 0;
   qps::DevBuf Rinv, Rfwd;
-  qps::DevBuf arena, work, scratch, splitws;
-  qps::DevBuf ab_up, ab_x0, ab_x1, ab_root;  // apply workspaces
+  int fp64_top = 0;               // levels 1..fp64_top hold complex128 inverse factors, deeper ones complex64
+  qps::DevBuf arena, arena32, work, scratch, splitws, qp32;
+  qps::DevBuf ab_up, ab_x0, ab_x1, ab_root;          // apply workspaces
+  qps::DevBuf ab_in32, ab_up32, ab_x32a, ab_x32b;    // complex64 stage of a mixed-precision inverse apply
   hbs_stats_t stats{};
   double c0x = 0, c0y = 0, robs = 0;  // obstacle centre and radius about it
   int64_t factor_bytes = 0;
@@ -47,6 +50,8 @@ struct hbs_handle {
 namespace qps {
 // apply the telescoping factorization: inverse (F^T, E, G, root inverse) or forward (P^T, P, D, root coupling)
 int apply_factors(hbs_handle* h, bool inverse, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r);
+// X = A^{-1} B with whichever inverse factors the handle holds (complex64 levels run on casts)
+int apply_inverse(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r);
 int build(hbs_handle* h);
 int apply_interp(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx, int64_t r);
 int qp_max_modes_impl(double om, double period);

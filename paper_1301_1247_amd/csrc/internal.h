@@ -52,19 +52,26 @@ struct CpqrDesc {
 };
 
 // Batched GEMM entry: C = alpha * op(A) * B + beta * C, op(A) = A (m x k) or A^T (A is k x m).
-struct GemmDesc {
-  const cplx* A;
-  const cplx* B;
-  cplx* C;
+template <class R>
+struct GemmDescT {
+  typedef typename cx<R>::T C_t;
+  const C_t* A;
+  const C_t* B;
+  C_t* C;
   int m, n, k, lda, ldb, ldc, transA, pad;
-  cplx alpha, beta;
+  C_t alpha, beta;
 };
+typedef GemmDescT<double> GemmDesc;
+typedef GemmDescT<float> GemmDesc32;
 
 // Square matrix to be inverted in place.
-struct InvDesc {
-  cplx* a;
+template <class R>
+struct InvDescT {
+  typename cx<R>::T* a;
   int n, ld;
 };
+typedef InvDescT<double> InvDesc;
+typedef InvDescT<float> InvDesc32;
 
 // Interpolation matrix P (n x k, ld n) from the pivots and T = Z[0:k, k:n] (ld s).
 struct PDesc {
@@ -121,15 +128,23 @@ hipError_t launch_cpqr(const CpqrDesc* d, int nd, double tol, int* k_out, hipStr
 hipError_t launch_buildP(const PDesc* d, int nd, int max_elems, hipStream_t s);
 hipError_t launch_copy(const CopyDesc* d, int nd, int max_elems, hipStream_t s);
 hipError_t launch_gather_idx(const int* src, const int* idx, int* dst, int64_t n, hipStream_t s);
-hipError_t launch_zgemm(const GemmDesc* d, int nd, int max_tiles, hipStream_t s);
+template <class R>
+hipError_t launch_gemm(const GemmDescT<R>* d, int nd, int max_tiles, hipStream_t s);
+inline hipError_t launch_zgemm(const GemmDesc* d, int nd, int max_tiles, hipStream_t s) { return launch_gemm<double>(d, nd, max_tiles, s); }
 // blocked Gauss-Jordan inversion; tbuf: nd * 32 * max_n complex; ipiv: nd * max_n ints; info: nd ints
-hipError_t launch_zinv(const InvDesc* d, int nd, int max_n, cplx* tbuf, int* ipiv, int* info, hipStream_t s);
+template <class R>
+hipError_t launch_inv(const InvDescT<R>* d, int nd, int max_n, typename cx<R>::T* tbuf, int* ipiv, int* info, hipStream_t s);
+// precision casts of n complex values
+hipError_t launch_cast_d2f(const cplx* src, cplxf* dst, int64_t n, hipStream_t s);
+hipError_t launch_cast_f2d(const cplxf* src, cplx* dst, int64_t n, hipStream_t s);
 hipError_t launch_hankel(const double* x, int64_t n, cplx* out, hipStream_t s);
 hipError_t launch_eval_shift(const Geo& g, const int* rows, int nr, double shift, cplx* out, int ld, hipStream_t s);
 hipError_t launch_entries(const Geo& g, const int* rows, const int* cols, int64_t n, cplx* out, hipStream_t s);
 
 // gemm helper: build descriptors on the host, upload, launch
-hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDesc>& v, hipStream_t s, DevBuf* ws = nullptr);
-hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDesc>& v, hipStream_t s, bool* singular);
+template <class R>
+hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDescT<R>>& v, hipStream_t s, DevBuf* ws = nullptr);
+template <class R>
+hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R>>& v, hipStream_t s, bool* singular);
 
 }  // namespace qps

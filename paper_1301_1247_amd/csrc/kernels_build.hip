@@ -263,24 +263,26 @@ constexpr int GJ_NB = 32;
 // panel column), then the elimination with one thread per row (each thread reads its own
 // multiplier before overwriting column p, so no barrier is needed between the two).
 constexpr int NTP = 1024;
-__global__ __launch_bounds__(NTP) void k_gj_panel(const InvDesc* __restrict__ descs, int c0, int* __restrict__ ipiv_all,
+template <class R>
+__global__ __launch_bounds__(NTP) void k_gj_panel(const InvDescT<R>* __restrict__ descs, int c0, int* __restrict__ ipiv_all,
                                                   int maxn, int* __restrict__ info) {
-  const InvDesc d = descs[blockIdx.x];
+  typedef typename cx<R>::T C_t;
+  const InvDescT<R> d = descs[blockIdx.x];
   const int n = d.n;
   if (c0 >= n) return;
   const int c1 = min(c0 + GJ_NB, n);
   const int ld = d.ld;
-  cplx* A = d.a;
+  C_t* A = d.a;
   int* ipiv = ipiv_all + (size_t)blockIdx.x * maxn;
   __shared__ double red_v[NTP / 64];
   __shared__ int red_i[NTP / 64];
-  __shared__ cplx rowp[GJ_NB];
+  __shared__ C_t rowp[GJ_NB];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int p = c0; p < c1; ++p) {
     double bv = -1.0;
     int bi = n;
     for (int i = p + tid; i < n; i += NTP) {
-      const double a = cabs2(A[i + (size_t)p * ld]);
+      const double a = (double)cabs2(A[i + (size_t)p * ld]);
       if (a > bv || (a == bv && i < bi)) { bv = a; bi = i; }
     }
     wave_argmax(bv, bi);
@@ -291,8 +293,8 @@ __global__ __launch_bounds__(NTP) void k_gj_panel(const InvDesc* __restrict__ de
     for (int q = 1; q < NTP / 64; ++q)
       if (red_v[q] > b || (red_v[q] == b && red_i[q] < r)) { b = red_v[q]; r = red_i[q]; }
     if (!(b > 0.0)) r = p;
-    const cplx piv = A[r + (size_t)p * ld];
-    const cplx dd = (cabs2(piv) > 0.0) ? cinv(piv) : mkc(0.0, 0.0);
+    const C_t piv = A[r + (size_t)p * ld];
+    const C_t dd = (cabs2(piv) > 0) ? cinv(piv) : cx<R>::make(0.0, 0.0);
     __syncthreads();  // every thread has read the pivot before rows p, r change
     if (tid == 0) {
       ipiv[p] = r;
@@ -300,9 +302,9 @@ __global__ __launch_bounds__(NTP) void k_gj_panel(const InvDesc* __restrict__ de
     }
     // swap rows p, r in the panel and scale the new pivot row
     for (int j = c0 + tid; j < c1; j += NTP) {
-      const cplx vr = A[r + (size_t)j * ld];
-      const cplx vp = A[p + (size_t)j * ld];
-      const cplx sc = (j == p) ? dd : cmul(vr, dd);
+      const C_t vr = A[r + (size_t)j * ld];
+      const C_t vp = A[p + (size_t)j * ld];
+      const C_t sc = (j == p) ? dd : cmul(vr, dd);
       rowp[j - c0] = sc;
       A[p + (size_t)j * ld] = sc;
       if (r != p) A[r + (size_t)j * ld] = vp;
@@ -311,41 +313,46 @@ __global__ __launch_bounds__(NTP) void k_gj_panel(const InvDesc* __restrict__ de
     // eliminate column p from every other row; column p becomes the inverse's column
     for (int i = tid; i < n; i += NTP) {
       if (i == p) continue;
-      const cplx f = A[i + (size_t)p * ld];
+      const C_t f = A[i + (size_t)p * ld];
       for (int j = c0; j < c1; ++j) {
         if (j == p) continue;
         A[i + (size_t)j * ld] = csub(A[i + (size_t)j * ld], cmul(f, rowp[j - c0]));
       }
-      A[i + (size_t)p * ld] = cmul(mkc(-f.x, -f.y), dd);
+      A[i + (size_t)p * ld] = cmul(cx<R>::make(-f.x, -f.y), dd);
     }
     __syncthreads();
   }
 }
 
 // For columns outside the panel: apply the panel's row swaps, save the pivot rows to T.
-__global__ __launch_bounds__(NT) void k_gj_swapsave(const InvDesc* __restrict__ descs, int c0, const int* __restrict__ ipiv_all,
-                                                    int maxn, cplx* __restrict__ tbuf) {
-  const InvDesc d = descs[blockIdx.y];
+template <class R>
+__global__ __launch_bounds__(NT) void k_gj_swapsave(const InvDescT<R>* __restrict__ descs, int c0, const int* __restrict__ ipiv_all,
+                                                    int maxn, typename cx<R>::T* __restrict__ tbuf) {
+  typedef typename cx<R>::T C_t;
+  const InvDescT<R> d = descs[blockIdx.y];
   const int n = d.n;
   if (c0 >= n) return;
   const int c1 = min(c0 + GJ_NB, n);
   const int ld = d.ld;
   const int* ipiv = ipiv_all + (size_t)blockIdx.y * maxn;
-  cplx* T = tbuf + (size_t)blockIdx.y * GJ_NB * maxn;
+  C_t* T = tbuf + (size_t)blockIdx.y * GJ_NB * maxn;
   for (int j = blockIdx.x * NT + threadIdx.x; j < n; j += gridDim.x * NT) {
     if (j >= c0 && j < c1) continue;
-    cplx* col = d.a + (size_t)j * ld;
+    C_t* col = d.a + (size_t)j * ld;
     for (int p = c0; p < c1; ++p) {
       const int r = ipiv[p];
-      if (r != p) { cplx t = col[p]; col[p] = col[r]; col[r] = t; }
+      if (r != p) { C_t t = col[p]; col[p] = col[r]; col[r] = t; }
     }
     for (int p = c0; p < c1; ++p) T[(p - c0) + (size_t)j * GJ_NB] = col[p];
   }
 }
 
 // A[:, j] = mask(A[:, j]) + A[:, c0:c1] T[:, j]  for j outside the panel (mask zeroes rows c0:c1).
-__global__ __launch_bounds__(NT) void k_gj_update(const InvDesc* __restrict__ descs, int c0, int maxn, const cplx* __restrict__ tbuf) {
-  const InvDesc d = descs[blockIdx.z];
+template <class R>
+__global__ __launch_bounds__(NT) void k_gj_update(const InvDescT<R>* __restrict__ descs, int c0, int maxn,
+                                                  const typename cx<R>::T* __restrict__ tbuf) {
+  typedef typename cx<R>::T C_t;
+  const InvDescT<R> d = descs[blockIdx.z];
   const int n = d.n;
   if (c0 >= n) return;
   const int c1 = min(c0 + GJ_NB, n);
@@ -353,19 +360,19 @@ __global__ __launch_bounds__(NT) void k_gj_update(const InvDesc* __restrict__ de
   const int ld = d.ld;
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 16;
   if (i0 >= n || j0 >= n) return;
-  const cplx* T = tbuf + (size_t)blockIdx.z * GJ_NB * maxn;
-  __shared__ cplx Ap[GJ_NB][65];
-  __shared__ cplx Ts[GJ_NB][17];
+  const C_t* T = tbuf + (size_t)blockIdx.z * GJ_NB * maxn;
+  __shared__ C_t Ap[GJ_NB][65];
+  __shared__ C_t Ts[GJ_NB][17];
   const int tid = threadIdx.x;
   for (int e = tid; e < 64 * GJ_NB; e += NT) {
     const int ii = e % 64, pp = e / 64;
     const int i = i0 + ii;
-    Ap[pp][ii] = (i < n && pp < w) ? d.a[i + (size_t)(c0 + pp) * ld] : mkc(0, 0);
+    Ap[pp][ii] = (i < n && pp < w) ? d.a[i + (size_t)(c0 + pp) * ld] : cx<R>::make(0, 0);
   }
   for (int e = tid; e < 16 * GJ_NB; e += NT) {
     const int pp = e % GJ_NB, jj = e / GJ_NB;
     const int j = j0 + jj;
-    Ts[pp][jj] = (j < n && pp < w) ? T[pp + (size_t)j * GJ_NB] : mkc(0, 0);
+    Ts[pp][jj] = (j < n && pp < w) ? T[pp + (size_t)j * GJ_NB] : cx<R>::make(0, 0);
   }
   __syncthreads();
   const int ii = tid % 64, jb = tid / 64;  // 4 column groups of 4
@@ -376,22 +383,24 @@ __global__ __launch_bounds__(NT) void k_gj_update(const InvDesc* __restrict__ de
     const int jj = jb * 4 + c;
     const int j = j0 + jj;
     if (j >= n || (j >= c0 && j < c1)) continue;
-    cplx acc = (i >= c0 && i < c1) ? mkc(0, 0) : d.a[i + (size_t)j * ld];
+    C_t acc = (i >= c0 && i < c1) ? cx<R>::make(0, 0) : d.a[i + (size_t)j * ld];
     for (int pp = 0; pp < w; ++pp) acc = cfma(Ap[pp][ii], Ts[pp][jj], acc);
     d.a[i + (size_t)j * ld] = acc;
   }
 }
 
 // undo the row interchanges on the columns of the inverse: for p = n-1..0 swap columns p, ipiv[p]
-__global__ __launch_bounds__(NT) void k_gj_colperm(const InvDesc* __restrict__ descs, const int* __restrict__ ipiv_all, int maxn) {
-  const InvDesc d = descs[blockIdx.y];
+template <class R>
+__global__ __launch_bounds__(NT) void k_gj_colperm(const InvDescT<R>* __restrict__ descs, const int* __restrict__ ipiv_all, int maxn) {
+  typedef typename cx<R>::T C_t;
+  const InvDescT<R> d = descs[blockIdx.y];
   const int n = d.n;
   const int* ipiv = ipiv_all + (size_t)blockIdx.y * maxn;
   for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
     for (int p = n - 1; p >= 0; --p) {
       const int r = ipiv[p];
       if (r != p) {
-        cplx t = d.a[i + (size_t)p * d.ld];
+        C_t t = d.a[i + (size_t)p * d.ld];
         d.a[i + (size_t)p * d.ld] = d.a[i + (size_t)r * d.ld];
         d.a[i + (size_t)r * d.ld] = t;
       }
@@ -478,19 +487,22 @@ hipError_t launch_gather_idx(const int* src, const int* idx, int* dst, int64_t n
   hipLaunchKernelGGL(k_gather_idx, dim3(grid_for(n)), dim3(NT), 0, s, src, idx, dst, n);
   return hipGetLastError();
 }
-hipError_t launch_zinv(const InvDesc* d, int nd, int max_n, cplx* tbuf, int* ipiv, int* info, hipStream_t s) {
+template <class R>
+hipError_t launch_inv(const InvDescT<R>* d, int nd, int max_n, typename cx<R>::T* tbuf, int* ipiv, int* info, hipStream_t s) {
   if (nd == 0 || max_n == 0) return hipSuccess;
   hipError_t e = hipMemsetAsync(info, 0, sizeof(int) * nd, s);
   if (e != hipSuccess) return e;
   for (int c0 = 0; c0 < max_n; c0 += GJ_NB) {
-    hipLaunchKernelGGL(k_gj_panel, dim3(nd), dim3(NTP), 0, s, d, c0, ipiv, max_n, info);
-    hipLaunchKernelGGL(k_gj_swapsave, dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, c0, ipiv, max_n, tbuf);
-    hipLaunchKernelGGL(k_gj_update, dim3((max_n + 63) / 64, (max_n + 15) / 16, nd), dim3(NT), 0, s, d, c0, max_n,
-                       (const cplx*)tbuf);
+    hipLaunchKernelGGL(k_gj_panel<R>, dim3(nd), dim3(NTP), 0, s, d, c0, ipiv, max_n, info);
+    hipLaunchKernelGGL(k_gj_swapsave<R>, dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, c0, ipiv, max_n, tbuf);
+    hipLaunchKernelGGL(k_gj_update<R>, dim3((max_n + 63) / 64, (max_n + 15) / 16, nd), dim3(NT), 0, s, d, c0, max_n,
+                       (const typename cx<R>::T*)tbuf);
   }
-  hipLaunchKernelGGL(k_gj_colperm, dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, ipiv, max_n);
+  hipLaunchKernelGGL(k_gj_colperm<R>, dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, ipiv, max_n);
   return hipGetLastError();
 }
+template hipError_t launch_inv<double>(const InvDesc*, int, int, cplx*, int*, int*, hipStream_t);
+template hipError_t launch_inv<float>(const InvDesc32*, int, int, cplxf*, int*, int*, hipStream_t);
 hipError_t launch_eval_shift(const Geo& g, const int* rows, int nr, double shift, cplx* out, int ld, hipStream_t s) {
   if (nr == 0) return hipSuccess;
   hipLaunchKernelGGL(k_eval_shift, dim3(grid_for((int64_t)nr * g.N, 8192)), dim3(NT), 0, s, g, rows, nr, shift, out, ld);

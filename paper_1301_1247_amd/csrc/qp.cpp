@@ -327,10 +327,11 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     CK(launch_eval_shift(h->geo, J, nr, period, Rp, nr, st));
     CK(launch_eval_shift(h->geo, J, nr, -period, Rm, nr, st));
   }
-  // one application of A^{-1} for every alpha (and V = A^{-1} U)
-  CR(apply_factors(h, true, Y, N, X, N, W));
-  // alpha-free products
-  {
+  const bool fp32 = h->opts.precision == HBS_FP32_PRECOND;
+  if (!fp32) {
+    // one application of A^{-1} for every alpha (and V = A^{-1} U)
+    CR(apply_factors(h, true, Y, N, X, N, W));
+    // alpha-free products
     std::vector<GemmDesc> g = {gd(C1, M2, 0, X, N, G1, M2, M2, (int)W, N, onec, zero),
                                gd(C2, M2, 0, X, N, G2, M2, M2, (int)W, N, onec, zero)};
     if (P) {
@@ -338,6 +339,30 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       g.push_back(gd(Rm, nr, 0, X, N, RXm, nr, nr, (int)W, N, onec, zero));
     }
     CR(gemm(g));
+  } else {
+    // complex64 preconditioner: the big apply and the Schur products on FP32 matrix cores
+    CR(apply_inverse(h, Y, N, X, N, W));
+    CK(h->qp32.reserve(sizeof(cplxf) * ((size_t)N * W + (size_t)M2 * N * 2 + (size_t)M2 * W * 2)));
+    cplxf* X32 = h->qp32.as<cplxf>();
+    cplxf* C132 = X32 + (size_t)N * W;
+    cplxf* C232 = C132 + (size_t)M2 * N;
+    cplxf* G132 = C232 + (size_t)M2 * N;
+    cplxf* G232 = G132 + (size_t)M2 * W;
+    CK(launch_cast_d2f(X, X32, (int64_t)N * W, st));
+    CK(launch_cast_d2f(C1, C132, (int64_t)M2 * N, st));
+    CK(launch_cast_d2f(C2, C232, (int64_t)M2 * N, st));
+    auto g32 = [&](const cplxf* A, int lda, const cplxf* B, int ldb, cplxf* C, int ldc, int m, int n, int k) {
+      GemmDesc32 g;
+      g.A = A; g.B = B; g.C = C; g.m = m; g.n = n; g.k = k; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+      g.transA = 0; g.pad = 0; g.alpha = mkcf(1, 0); g.beta = mkcf(0, 0);
+      return g;
+    };
+    std::vector<GemmDesc32> g = {g32(C132, M2, X32, N, G132, M2, M2, (int)W, N), g32(C232, M2, X32, N, G232, M2, M2, (int)W, N)};
+    CK(gemm_batched<float>(h->arena, g, st, &h->splitws));
+    CK(launch_cast_f2d(G132, G1, (int64_t)M2 * W, st));
+    CK(launch_cast_f2d(G232, G2, (int64_t)M2 * W, st));
+    CK(hipStreamSynchronize(st));
+    if (P) CR(gemm({gd(Rp, nr, 0, X, N, RXp, nr, nr, (int)W, N, onec, zero), gd(Rm, nr, 0, X, N, RXm, nr, nr, (int)W, N, onec, zero)}));
   }
   CK(launch_form_S(Q, d_gco, ng, G1, G2, S, st));
   if (P) {
@@ -437,7 +462,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     CR(nb_correction(Rb, xi, minus1c));
   }
   // iterative refinement of the bordered system
-  int maxit = o->refine_max_iter < 0 ? 0 : (o->refine_max_iter == 0 ? 2 : o->refine_max_iter);
+  int maxit = o->refine_max_iter < 0 ? 0 : (o->refine_max_iter == 0 ? (fp32 ? 3 : 2) : o->refine_max_iter);
   const double rtol = o->refine_tol > 0 ? o->refine_tol : 1e-13;
   std::vector<double> hn(3 * nang);
   CK(launch_colnorm2(N, nang, Y + (size_t)colB * N, N, nrm + 2 * nang, st));

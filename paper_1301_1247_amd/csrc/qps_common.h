@@ -40,6 +40,34 @@ __device__ inline cplx cexp(cplx z) {
   return mkc(e * c, e * s);
 }
 
+// single-precision complex (complex64) helpers
+typedef float2 cplxf;
+__host__ __device__ inline cplxf mkcf(float re, float im) { cplxf c; c.x = re; c.y = im; return c; }
+__host__ __device__ inline cplxf cadd(cplxf a, cplxf b) { return mkcf(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cplxf csub(cplxf a, cplxf b) { return mkcf(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cplxf cmul(cplxf a, cplxf b) { return mkcf(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__host__ __device__ inline float cabs2(cplxf a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline cplxf cinv(cplxf a) {
+  float s = fmaxf(fabsf(a.x), fabsf(a.y));
+  float ar = a.x / s, ai = a.y / s;
+  float d = ar * ar + ai * ai;
+  return mkcf(ar / (d * s), -ai / (d * s));
+}
+__host__ __device__ inline cplxf cfma(cplxf a, cplxf b, cplxf acc) {
+  return mkcf(fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y)));
+}
+
+// precision traits: complex type and constructor for double / float
+template <class R> struct cx;
+template <> struct cx<double> {
+  typedef double2 T;
+  __host__ __device__ static T make(double re, double im) { return mkc(re, im); }
+};
+template <> struct cx<float> {
+  typedef float2 T;
+  __host__ __device__ static T make(double re, double im) { return mkcf((float)re, (float)im); }
+};
+
 // wavefront (64 lanes) reductions
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

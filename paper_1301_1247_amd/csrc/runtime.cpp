@@ -103,7 +103,9 @@ ProfScope::~ProfScope() {
 }
 
 // ------------------------------------------------------------------ batched inversion
-hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDesc>& v, hipStream_t s, bool* singular) {
+template <class R>
+hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R>>& v, hipStream_t s, bool* singular) {
+  typedef typename cx<R>::T C_t;
   *singular = false;
   if (v.empty()) return hipSuccess;
   int maxn = 0;
@@ -113,20 +115,22 @@ hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDesc>& 
     flops += 8.0 * (double)d.n * d.n * d.n;
   }
   const int nd = (int)v.size();
-  size_t tb = (size_t)nd * 32 * maxn * sizeof(cplx);
+  size_t tb = (size_t)nd * 32 * maxn * sizeof(C_t);
+  tb = (tb + 255) / 256 * 256;
   size_t ib = (size_t)nd * maxn * sizeof(int);
+  ib = (ib + 255) / 256 * 256;
   size_t fb = (size_t)nd * sizeof(int);
   hipError_t e = work.reserve(tb + ib + fb + 512);
   if (e != hipSuccess) return e;
   char* base = work.as<char>();
-  cplx* tbuf = reinterpret_cast<cplx*>(base);
+  C_t* tbuf = reinterpret_cast<C_t*>(base);
   int* ipiv = reinterpret_cast<int*>(base + tb);
   int* info = reinterpret_cast<int*>(base + tb + ib);
   e = upload(arena, v, s);
   if (e != hipSuccess) return e;
   {
-    ProfScope ps("zinv", s, flops, 0.0);
-    e = launch_zinv(arena.as<InvDesc>(), nd, maxn, tbuf, ipiv, info, s);
+    ProfScope ps(sizeof(R) == 8 ? "zinv" : "cinv", s, flops, 0.0);
+    e = launch_inv<R>(arena.as<InvDescT<R>>(), nd, maxn, tbuf, ipiv, info, s);
     if (e != hipSuccess) return e;
   }
   std::vector<int> hinfo(nd);
@@ -138,5 +142,7 @@ hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDesc>& 
     if (hinfo[i] != 0) *singular = true;
   return hipSuccess;
 }
+template hipError_t inv_batched<double>(DevBuf&, DevBuf&, const std::vector<InvDesc>&, hipStream_t, bool*);
+template hipError_t inv_batched<float>(DevBuf&, DevBuf&, const std::vector<InvDesc32>&, hipStream_t, bool*);
 
 }  // namespace qps

@@ -63,6 +63,33 @@ def test_zinv_needs_pivoting(gpu_lib):
     assert np.abs(Ai[0] @ A[0] - np.eye(3)).max() < 1e-14
 
 
+@pytest.mark.parametrize("m,n,k,trans", [(64, 64, 16, False), (37, 91, 53, False), (130, 70, 200, True),
+                                          (1, 1, 1, False), (70, 9, 20011, False)])
+def test_cgemm_complex64_matches_numpy(gpu_lib, m, n, k, trans):
+    """FP32-MFMA GEMM of the complex64 preconditioner: error of FP32 accumulation, ~eps32 sqrt(k)."""
+    rng = np.random.default_rng(m * 1000 + n + 7)
+    nb = 2
+    sh = (nb, k, m) if trans else (nb, m, k)
+    A = (rng.standard_normal(sh) + 1j * rng.standard_normal(sh)).astype(np.complex64)
+    B = (rng.standard_normal((nb, k, n)) + 1j * rng.standard_normal((nb, k, n))).astype(np.complex64)
+    C = gpu_lib.zgemm(A, B, transA=trans, precision="fp32")
+    assert C.dtype == np.complex64
+    ref = np.matmul(np.transpose(A, (0, 2, 1)).astype(complex) if trans else A.astype(complex), B.astype(complex))
+    assert np.abs(C - ref).max() < 2e-6 * math.sqrt(k) * max(1.0, math.sqrt(k))
+
+
+@pytest.mark.parametrize("n", [1, 33, 257])
+def test_cinv_complex64_matches_numpy(gpu_lib, n):
+    rng = np.random.default_rng(n + 11)
+    A = (rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n)) + 3 * np.eye(n)).astype(np.complex64)
+    Ai = gpu_lib.zinv(A, precision="fp32")
+    for b in range(2):
+        Ad = A[b].astype(complex)
+        ref = np.linalg.inv(Ad)
+        kappa = np.linalg.cond(Ad)
+        assert np.abs(Ai[b] - ref).max() < 2e-6 * kappa * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("quad,N", [("kr6", 400), ("kress", 200)])
 def test_matrix_entries_match_oracle(gpu_lib, quad, N):
     from paper_1301_1247_amd.geometry import discretize

@@ -53,6 +53,21 @@ def test_hbs_inverse_and_forward_vs_dense(gpu_lib, wavy_small):
     assert s.levels >= 4 and 0 < s.max_rank <= 2048
 
 
+def test_hbs_fp32_preconditioner_refines_to_fp64(gpu_lib, wavy_small):
+    """complex64 inverse factors as a preconditioner: the bare apply is single-precision
+    accurate, FP64 refinement against the forward operator recovers the 1e-10 bar."""
+    c, N, om, disc, A, lu = wavy_small
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-12, precision="fp32")
+    rng = np.random.default_rng(6)
+    B = rng.standard_normal((N, 5)) + 1j * rng.standard_normal((N, 5))
+    Xe = sla.lu_solve(lu, B)
+    e0 = _rel(h.apply(B), Xe)
+    assert 1e-9 < e0 < 1e-3
+    assert _rel(h.apply(B, refine=5), Xe) < 1e-10
+    assert _rel(h.forward(Xe), A @ Xe) < 1e-10
+
+
 @pytest.mark.parametrize("N", [130, 131, 777])
 def test_hbs_ragged_and_minimal_sizes(gpu_lib, N):
     c = qpinputs.star()
@@ -135,6 +150,18 @@ def test_qp_wavy_kr6_parity_shared_and_distinct_phases(gpu_lib, wavy_small):
     res = h.qp_solve_many(d, thetas)
     ref = pq.solve_qp(disc, N, om, d, thetas, quad="kr6", A0=A)
     _check_qp(res, ref, len(thetas))
+
+
+def test_qp_wavy_kr6_parity_fp32_preconditioner(gpu_lib, wavy_small):
+    c, N, om, disc, A, lu = wavy_small
+    d = 2 * math.pi
+    thetas = np.array([-math.acos(0.31), -1.1, -0.45])
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-12, precision="fp32")
+    res = h.qp_solve_many(d, thetas, refine_max_iter=6)
+    ref = pq.solve_qp(disc, N, om, d, thetas, quad="kr6", A0=A)
+    _check_qp(res, ref, len(thetas))
+    assert h.stats().refine_residual < 1e-12
 
 
 def test_qp_solve_alpha_mismatch_and_wood(gpu_lib):
