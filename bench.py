@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="wavy40")
     ap.add_argument("--tol", type=float, default=1e-13)
+    ap.add_argument("--walls", choices=("compressed", "dense"), default="compressed",
+                    help="compressed: wall blocks through the root skeletons (needs the far-field circle)")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="fp32: complex64 inverse factors as a preconditioner, FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -160,11 +162,16 @@ def main():
     nang = len(wl.thetas)
     kw = dict(quad=wl.quad, leaf_size=wl.leaf_size, curvature=t_kap if wl.quad == "kress" else None, device=True,
               stream=stream.cuda_stream, precision=args.precision)
+    if args.walls == "compressed":
+        # far-field circle about the bounding-box centre that stays inside the unit cell's walls
+        c0 = 0.5 * (nodes.max(0) + nodes.min(0))
+        kw["far_radius"] = 0.9 * (0.5 * wl.period - abs(c0[0]))
+    cw = 1 if args.walls == "compressed" else -1
     fam, peak = ("zgemm", FP64_PEAK_TFLOPS) if args.precision == "fp64" else ("cgemm", FP32_PEAK_TFLOPS)
 
     def step():
         h = B.Handle(t_nodes, t_w, t_nrm, wl.omega, args.tol, **kw)
-        res = h.qp_solve_many(wl.period, t_th)
+        res = h.qp_solve_many(wl.period, t_th, compress_walls=cw)
         return h, res
 
     for i in range(args.warmup):
@@ -203,8 +210,10 @@ def main():
         "dtype": "c128" if args.precision == "fp64" else "c64+c128",
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: seeded obstacle, N={wl.N}, omega={wl.omega}, d=2pi, "
-                               f"{nang} angles, tol={args.tol:g}, KR6 + proxy compression, {args.precision} factors",
-                   "N": wl.N, "omega": wl.omega, "angles": nang, "contour_M": st.contour_M},
+                               f"{nang} angles, tol={args.tol:g}, KR6 + proxy compression, {args.precision} factors, "
+                               f"{args.walls} walls",
+                   "N": wl.N, "omega": wl.omega, "angles": nang, "contour_M": st.contour_M,
+                   "walls": args.walls, "precision": args.precision},
         "build_seconds": float(np.median(builds)),
         "levels": st.levels, "max_rank": st.max_rank, "root_size": st.root_size,
         "refine_iters": st.refine_iters, "refine_residual": st.refine_residual,

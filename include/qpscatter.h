@@ -59,9 +59,10 @@ typedef struct {
   const double* curvature;  /* KRESS only: signed curvature at the N nodes (ptr_mode) */
   void* stream;             /* hipStream_t, NULL = default stream */
   uint64_t seed;            /* seed of the sketching matrices of the interpolative decompositions */
-  double far_radius;        /* > 0: every skeleton also represents sources outside the circle of this
-                               radius about the obstacle's centre (needed by qp_solve with P >= 1,
-                               whose neighbour images must lie outside it); 0 = off */
+  double far_radius;        /* > 0: every skeleton also represents sources and targets outside the
+                               circle of this radius about the centre of the nodes' bounding box
+                               (needed by qp_solve with P >= 1, whose neighbour images must lie
+                               outside it, and by qp_opts.compress_walls); 0 = off */
   int32_t precision;        /* HBS_FP64: inverse factors in complex128.  HBS_FP32_PRECOND: the inverse
                                factors of the deep levels are built and applied in complex64 on FP32
                                matrix cores and serve as a preconditioner; skeletons, the forward
@@ -85,6 +86,13 @@ typedef struct {
   int32_t refine_max_iter;  /* iterative refinement steps of the bordered system; <0 -> 0,
                                0 -> 2 (3 for a handle built with HBS_FP32_PRECOND) */
   double refine_tol;        /* stop when the relative residual is below; 0 -> 1e-13 */
+  int32_t compress_walls;   /* the wall blocks B (Eq. 2.16) and C (Eq. 2.17) through the root skeletons:
+                               B = U B(J, :), C = C(:, J) U^T with U the nested interpolation of the
+                               tree, valid when the handle's far_radius circle excludes the walls
+                               (far_radius <= d/2 - |c_x|, c = centre of the nodes' bounding box).
+                               Then A^{-1} is applied to root-size + q columns instead of 4M + q and
+                               no N-sized Schur product is formed.  0 = when valid, 1 = required
+                               (HBS_E_INVALID_ARG otherwise), -1 = never */
 } qp_opts;
 
 typedef struct {
@@ -100,6 +108,7 @@ typedef struct {
   int32_t refine_iters;     /* refinement iterations of the last qp_solve */
   double refine_residual;   /* relative residual after the last qp_solve */
   int32_t contour_M;        /* contour size of the last qp_solve */
+  int32_t walls_compressed; /* 1 if the last qp_solve took B and C through the root skeletons */
 } hbs_stats_t;
 
 void hbs_opts_init(hbs_opts* o);

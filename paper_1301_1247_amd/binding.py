@@ -44,14 +44,15 @@ class HbsOpts(C.Structure):
 class QpOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("P", C.c_int32), ("M", C.c_int32), ("K", C.c_double), ("h", C.c_double),
                 ("ca", C.c_double), ("cb", C.c_double), ("y0", C.c_double), ("wood_min_kn", C.c_double),
-                ("refine_max_iter", C.c_int32), ("refine_tol", C.c_double)]
+                ("refine_max_iter", C.c_int32), ("refine_tol", C.c_double), ("compress_walls", C.c_int32)]
 
 
 class HbsStats(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("levels", C.c_int32), ("N", C.c_int64), ("root_size", C.c_int32),
                 ("max_rank", C.c_int32), ("factor_bytes", C.c_int64), ("build_seconds", C.c_double),
                 ("ranks_per_level_max", C.c_int32 * 32), ("ranks_per_level_mean", C.c_double * 32),
-                ("refine_iters", C.c_int32), ("refine_residual", C.c_double), ("contour_M", C.c_int32)]
+                ("refine_iters", C.c_int32), ("refine_residual", C.c_double), ("contour_M", C.c_int32),
+                ("walls_compressed", C.c_int32)]
 
 
 _P = C.c_void_p

@@ -595,6 +595,41 @@ int apply_interp(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx
   return HBS_OK;
 }
 
+// Z (nr x r) = U^T X: the transpose of the nested interpolation, i.e. the upward pass with P^T
+// from the leaves to the root's active set (outgoing fields of X seen from beyond every proxy circle).
+int apply_interp_t(hbs_handle* h, const cplx* X, int64_t ldx, cplx* Z, int64_t ldz, int64_t r) {
+  if (r <= 0) return HBS_OK;
+  hipStream_t st = h->stream;
+  const int L = h->L;
+  auto& lv = h->lv;
+  int64_t xmax = 1;
+  for (int l = 2; l <= L; ++l) xmax = std::max<int64_t>(xmax, lv[l].ktot);
+  CK(h->ab_x0.reserve(sizeof(cplx) * xmax * r));
+  CK(h->ab_x1.reserve(sizeof(cplx) * xmax * r));
+  auto xbuf = [&](int l) { return (l & 1) ? h->ab_x1.as<cplx>() : h->ab_x0.as<cplx>(); };
+  std::vector<GemmDesc> all;
+  std::vector<LaunchRec> recs;
+  for (int l = L; l >= 1; --l) {
+    Level& V = lv[l];
+    const cplx* src = (l == L) ? X : xbuf(l);
+    const int lds = (l == L) ? (int)ldx : (int)V.ntot;
+    cplx* dst = (l == 1) ? Z : xbuf(l - 1);
+    const int ldd = (l == 1) ? (int)ldz : (int)V.ktot;
+    LaunchRec rec{all.size(), 0, 0, 0.0};
+    for (int b = 0; b < V.nb; ++b) {
+      all.push_back(gd(V.P.as<cplx>() + V.oP[b], V.n[b], 1, src + V.aoff[b], lds, dst + V.soff[b], ldd, V.k[b], (int)r,
+                       V.n[b]));
+      rec.max_tiles = std::max(rec.max_tiles, tiles_of(all.back()));
+    }
+    rec.cnt = (int)(all.size() - rec.off);
+    recs.push_back(rec);
+  }
+  CK(upload(h->arena, all, st));
+  for (auto& rc : recs) CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.max_tiles, st));
+  CK(hipStreamSynchronize(st));
+  return HBS_OK;
+}
+
 template <class R>
 static GemmDescT<R> gdt(const typename cx<R>::T* A, int lda, int transA, const typename cx<R>::T* B, int ldb,
                         typename cx<R>::T* C, int ldc, int m, int n, int k, double beta) {

@@ -54,6 +54,7 @@ int apply_factors(hbs_handle* h, bool inverse, const cplx* B, int64_t ldb, cplx*
 int apply_inverse(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r);
 int build(hbs_handle* h);
 int apply_interp(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx, int64_t r);
+int apply_interp_t(hbs_handle* h, const cplx* X, int64_t ldx, cplx* Z, int64_t ldz, int64_t r);
 int qp_max_modes_impl(double om, double period);
 struct QPPlan;
 int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, const qp_opts* o, cplx* eta_out,

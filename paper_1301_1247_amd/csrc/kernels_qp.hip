@@ -28,11 +28,12 @@ __global__ __launch_bounds__(NT) void k_gen_B(QPGeo Q, cplx* __restrict__ Y, int
     const int wall = col / (2 * Q.M);          // 0 = L, 1 = R
     const int dbl = (col / Q.M) & 1;           // 0 = single, 1 = double
     const int m = col % Q.M;
+    const int nd = Q.idx ? Q.idx[i] : i;
     const double xw = wall ? 0.5 * Q.period : -0.5 * Q.period;
-    const double dx = Q.x[i] + Q.shift - xw;
+    const double dx = Q.x[nd] + Q.shift - xw;
     const cplx k = Q.k[m], s = Q.s[m], wk = Q.wk[m];
     // i (k y + s |dx|)
-    const cplx z = mkc(k.x * Q.y[i] + s.x * fabs(dx), k.y * Q.y[i] + s.y * fabs(dx));
+    const cplx z = mkc(k.x * Q.y[nd] + s.x * fabs(dx), k.y * Q.y[nd] + s.y * fabs(dx));
     const cplx ex = cmul(wk, cexpi_c(z));
     cplx v;
     if (!dbl) v = cmul(mkc(0.0, 0.5), cmul(ex, cinv(s)));
@@ -65,14 +66,15 @@ __global__ __launch_bounds__(NT) void k_gen_C(QPGeo Q, int wall, double shift, c
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int m = (int)(e % Q.M);
     const int j = (int)(e / Q.M);
-    const double dx = Q.x[j] + shift - xw;
+    const int nd = Q.idx ? Q.idx[j] : j;
+    const double dx = Q.x[nd] + shift - xw;
     const double sg = dx > 0 ? 1.0 : -1.0;
     const cplx k = Q.k[m], s = Q.s[m];
     // i(-k y + s |dx|)
-    const cplx z = mkc(-k.x * Q.y[j] + s.x * fabs(dx), -k.y * Q.y[j] + s.y * fabs(dx));
+    const cplx z = mkc(-k.x * Q.y[nd] + s.x * fabs(dx), -k.y * Q.y[nd] + s.y * fabs(dx));
     const cplx E = cscale(cexpi_c(z), 1.0 / (4.0 * PI));
     const cplx is = cinv(s);
-    const double nx = Q.nx[j], ny = Q.ny[j], w = Q.w[j];
+    const double nx = Q.nx[nd], ny = Q.ny[nd], w = Q.w[nd];
     // value
     cplx t = cadd(mkc(-sg * nx, 0.0), cscale(cmul(k, is), ny));
     cplx val = cadd(cmul(E, t), cscale(cmul(E, is), Q.omega));

@@ -117,10 +117,18 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       return HBS_E_INVALID_ARG;
     }
   }
+  // wall blocks through the root skeletons: needs every wall outside the far-field circle
+  const bool far_ok = h->opts.far_radius > 0 && 0.5 * period - std::fabs(h->c0x) >= h->opts.far_radius;
+  if (o->compress_walls > 0 && !far_ok) {
+    set_error("qp_solve: compress_walls needs a handle whose far_radius circle excludes the walls");
+    return HBS_E_INVALID_ARG;
+  }
+  const bool cw = o->compress_walls >= 0 && far_ok;
   QPPlan pl;
   CR(qp_plan(h, period, o, &pl));
   const int M = pl.M, M2 = 2 * M, M4 = 4 * M;
-  const int nr = P ? h->nroot : 0;
+  const int nr = P ? h->nroot : 0;       // Woodbury size
+  const int nu = (P || cw) ? h->nroot : 0;  // columns of the nested interpolation U
   const double wood = o->wood_min_kn > 0 ? o->wood_min_kn : 0.75;
   // Bloch phases, Wood's check, grouping
   std::vector<zc> al(nang);
@@ -206,18 +214,23 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   }
   const cplx onec = mkc(1, 0), minus1c = mkc(-1, 0);
 
-  // device workspace
+  // device workspace.  G1, G2 and R_{+-1} X use the column layout [L | R | b | U] of width W; Y and X
+  // hold [B_L | B_R | b | U] (uncompressed walls) or [U | b] (compressed walls).
   const int64_t W = (int64_t)M4 + nang + nr;
   const int colB = M4, colU = M4 + nang;
+  const int64_t Wy = cw ? (int64_t)nu + nang : W;
+  const int ycolB = cw ? nu : M4, ycolU = cw ? 0 : M4 + nang;
+  const int64_t NC = cw ? nu : N;  // columns of C1, C2
   const int nrr = std::max(nr, 1);
+  const int nuu = std::max(nu, 1);
   std::vector<size_t> sizes = {
       sizeof(cplx) * 3 * M,                          // 0 contour
       sizeof(double) * nang * 3,                     // 1 kx, ky, kappa
       sizeof(cplx) * (5 * nang + 7 * ng + 2),        // 2 column and group coefficients, constants
       sizeof(int) * nang * 3,                        // 3 perm, nlo, nmodes
-      sizeof(cplx) * N * W,                          // 4 Y
-      sizeof(cplx) * N * W,                          // 5 X
-      sizeof(cplx) * (size_t)M2 * N * 2,             // 6 C1, C2
+      sizeof(cplx) * N * Wy,                         // 4 Y
+      sizeof(cplx) * N * Wy,                         // 5 X
+      sizeof(cplx) * (size_t)M2 * NC * 2,            // 6 C1, C2
       sizeof(cplx) * (size_t)M2 * W * 2,             // 7 G1, G2
       sizeof(cplx) * (size_t)M2 * M2 * ng,           // 8 S
       sizeof(cplx) * (size_t)M2 * nang * 8,          // 9 xi, W, T1, T2, R2, U1, U2, dxi
@@ -230,7 +243,9 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       sizeof(cplx) * (size_t)nrr * nrr * ng * 2,     // 16 K(alpha) (and I + R V)
       sizeof(cplx) * (size_t)nrr * M2 * ng * 2,      // 17 R(alpha) X(alpha), K R X scratch
       sizeof(cplx) * (size_t)M2 * nrr * ng,          // 18 C~ V
-      sizeof(cplx) * (size_t)nrr * nang * 4};        // 19 R b, u, y, misc (nr x nang)
+      sizeof(cplx) * (size_t)nrr * nang * 4,         // 19 R b, u, y, misc (nr x nang)
+      cw ? sizeof(cplx) * ((size_t)nuu * (M4 + W + Wy + 2 * nang) + (size_t)nr * Wy * 2 + (size_t)N * nang) : 0};
+                                                     // 20 B_J, X_c, U^T X, t1, t2, R_{+-1} X, U t
   std::vector<size_t> off(sizes.size() + 1, 0);
   for (size_t i = 0; i < sizes.size(); ++i) off[i + 1] = off[i] + ((sizes[i] + 255) / 256) * 256;
   CK(h->scratch.reserve(off.back()));
@@ -253,7 +268,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   cplx* Y = (cplx*)(base + off[4]);
   cplx* X = (cplx*)(base + off[5]);
   cplx* C1 = (cplx*)(base + off[6]);
-  cplx* C2 = C1 + (size_t)M2 * N;
+  cplx* C2 = C1 + (size_t)M2 * NC;
   cplx* G1 = (cplx*)(base + off[7]);
   cplx* G2 = G1 + (size_t)M2 * W;
   cplx* S = (cplx*)(base + off[8]);
@@ -286,6 +301,14 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   cplx* uu = Rb + (size_t)nrr * nang;
   cplx* yy = uu + (size_t)nrr * nang;
   cplx* vv = yy + (size_t)nrr * nang;
+  cplx* BJ = (cplx*)(base + off[20]);       // nu x 4M: [B_L | B_R](J, :)
+  cplx* Xc = BJ + (size_t)nuu * M4;         // nu x W: U^T [X_L | X_R | X_b | V]
+  cplx* Zt = Xc + (size_t)nuu * W;          // nu x Wy: U^T X
+  cplx* t1 = Zt + (size_t)nuu * Wy;         // nu x nang
+  cplx* t2 = t1 + (size_t)nuu * nang;       // nu x nang
+  cplx* RZp = t2 + (size_t)nuu * nang;      // nr x Wy
+  cplx* RZm = RZp + (size_t)nr * Wy;        // nr x Wy
+  cplx* tN = RZm + (size_t)nr * Wy;         // N x nang
 
   std::vector<cplx> consts = {onec, minus1c};
   CK(hipMemcpyAsync(dcont, cont.data(), sizeof(cplx) * 3 * M, hipMemcpyHostToDevice, st));
@@ -303,6 +326,11 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   Q.x = h->geo.x; Q.y = h->geo.y; Q.nx = h->geo.nx; Q.ny = h->geo.ny; Q.w = h->geo.w;
   Q.k = dcont; Q.s = dcont + M; Q.wk = dcont + 2 * M;
   Q.N = N; Q.M = M; Q.omega = om; Q.period = period; Q.shift = 0.0;
+  Q.idx = nullptr;
+  const int* J = h->lv[1].skel.as<int>();  // the root's active set (nroot nodes)
+  QPGeo QJ = Q;
+  QJ.idx = J;
+  QJ.N = nu;
   const cplx zero = mkc(0, 0);
   auto gemm = [&](const std::vector<GemmDesc>& g) -> int {
     CK(gemm_batched(h->arena, g, st, &h->splitws));
@@ -311,24 +339,61 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   };
   {
     ProfScope ps("assemble", st, 0.0, 0.0);
-    CK(launch_gen_B(Q, Y, N, st));
-    CK(launch_gen_inc(Q, dkx, dky, nang, Y + (size_t)colB * N, N, st));
-    CK(launch_gen_C(Q, 0, P * period, C1, st));
-    CK(launch_gen_C(Q, 1, -P * period, C2, st));
+    if (cw) {
+      // only the skeleton rows of B and the skeleton columns of C are needed
+      CK(launch_gen_B(QJ, BJ, nu, st));
+      CK(launch_gen_C(QJ, 0, P * period, C1, st));
+      CK(launch_gen_C(QJ, 1, -P * period, C2, st));
+    } else {
+      CK(launch_gen_B(Q, Y, N, st));
+      CK(launch_gen_C(Q, 0, P * period, C1, st));
+      CK(launch_gen_C(Q, 1, -P * period, C2, st));
+    }
+    CK(launch_gen_inc(Q, dkx, dky, nang, Y + (size_t)ycolB * N, N, st));
+  }
+  if (nu) {
+    // U (N x nroot) = nested interpolation of the identity
+    CK(h->ab_root.reserve(sizeof(cplx) * (size_t)nu * nu));
+    std::vector<cplx> eye((size_t)nu * nu, zero);
+    for (int i = 0; i < nu; ++i) eye[(size_t)i * nu + i] = onec;
+    CK(hipMemcpyAsync(h->ab_root.p, eye.data(), sizeof(cplx) * eye.size(), hipMemcpyHostToDevice, st));
+    CR(apply_interp(h, h->ab_root.as<cplx>(), nu, Y + (size_t)ycolU * N, N, nu));
   }
   if (P) {
-    // U (N x nr) = nested interpolation of the identity; R_{+-1} = A_{+-1}(J, :)
-    CK(h->ab_root.reserve(sizeof(cplx) * (size_t)nr * nr));
-    std::vector<cplx> eye((size_t)nr * nr, zero);
-    for (int i = 0; i < nr; ++i) eye[(size_t)i * nr + i] = onec;
-    CK(hipMemcpyAsync(h->ab_root.p, eye.data(), sizeof(cplx) * eye.size(), hipMemcpyHostToDevice, st));
-    CR(apply_interp(h, h->ab_root.as<cplx>(), nr, Y + (size_t)colU * N, N, nr));
-    const int* J = h->lv[1].skel.as<int>();
+    // R_{+-1} = A_{+-1}(J, :)
     CK(launch_eval_shift(h->geo, J, nr, period, Rp, nr, st));
     CK(launch_eval_shift(h->geo, J, nr, -period, Rm, nr, st));
   }
   const bool fp32 = h->opts.precision == HBS_FP32_PRECOND;
-  if (!fp32) {
+  if (cw) {
+    // one application of A^{-1} to [U | b]: X = [V | X_b]; then with H = U^T V,
+    //   U^T [X_L | X_R | X_b | V] = [H B_J,L | H B_J,R | U^T X_b | H]  and  G = C_J (that)
+    CR(apply_factors(h, true, Y, N, X, N, Wy));
+    CR(apply_interp_t(h, X, N, Zt, nu, Wy));
+    CR(gemm({gd(Zt, nu, 0, BJ, nu, Xc, nu, nu, M4, nu, onec, zero)}));
+    CK(hipMemcpyAsync(Xc + (size_t)colB * nu, Zt + (size_t)nu * nu, sizeof(cplx) * (size_t)nu * nang,
+                      hipMemcpyDeviceToDevice, st));
+    if (P) CK(hipMemcpyAsync(Xc + (size_t)colU * nu, Zt, sizeof(cplx) * (size_t)nu * nu, hipMemcpyDeviceToDevice, st));
+    std::vector<GemmDesc> g = {gd(C1, M2, 0, Xc, nu, G1, M2, M2, (int)W, nu, onec, zero),
+                               gd(C2, M2, 0, Xc, nu, G2, M2, M2, (int)W, nu, onec, zero)};
+    if (P) {
+      g.push_back(gd(Rp, nr, 0, X, N, RZp, nr, nr, (int)Wy, N, onec, zero));
+      g.push_back(gd(Rm, nr, 0, X, N, RZm, nr, nr, (int)Wy, N, onec, zero));
+    }
+    CR(gemm(g));
+    if (P) {
+      // R_{+-1} [X_L | X_R | X_b | V] = [(R V) B_J | R X_b | R V]
+      CR(gemm({gd(RZp, nr, 0, BJ, nu, RXp, nr, nr, M4, nu, onec, zero), gd(RZm, nr, 0, BJ, nu, RXm, nr, nr, M4, nu, onec, zero)}));
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const cplx* src = s2 ? RZm : RZp;
+        cplx* dst = s2 ? RXm : RXp;
+        CK(hipMemcpyAsync(dst + (size_t)colB * nr, src + (size_t)nu * nr, sizeof(cplx) * (size_t)nr * nang,
+                          hipMemcpyDeviceToDevice, st));
+        CK(hipMemcpyAsync(dst + (size_t)colU * nr, src, sizeof(cplx) * (size_t)nr * nu, hipMemcpyDeviceToDevice, st));
+      }
+      CK(hipStreamSynchronize(st));
+    }
+  } else if (!fp32) {
     // one application of A^{-1} for every alpha (and V = A^{-1} U)
     CR(apply_factors(h, true, Y, N, X, N, W));
     // alpha-free products
@@ -425,7 +490,27 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
                      gcnt[gg], M2, alpha, zero));
     return gemm(g);
   };
-  const cplx* Vc = X + (size_t)colU * N;
+  const cplx* Vc = X + (size_t)ycolU * N;
+  // out -= X(alpha) v for v = [xi; alpha xi] stacked (4M x nang): X_LR v, or V (B_J v) with compressed walls
+  auto sub_Xv = [&](const cplx* v, cplx* out) -> int {
+    if (!cw) return gemm({gd(X, N, 0, v, M4, out, N, N, nang, M4, minus1c, onec)});
+    CR(gemm({gd(BJ, nu, 0, v, M4, t1, nu, nu, nang, M4, onec, zero)}));
+    return gemm({gd(Vc, N, 0, t1, nu, out, N, N, nang, nu, minus1c, onec)});
+  };
+  // out -= B(alpha) xi = [B_L | B_R] v, or U (B_J v)
+  auto sub_Bv = [&](const cplx* v, cplx* out) -> int {
+    if (!cw) return gemm({gd(Y, N, 0, v, M4, out, N, N, nang, M4, minus1c, onec)});
+    CR(gemm({gd(BJ, nu, 0, v, M4, t1, nu, nu, nang, M4, onec, zero)}));
+    CR(apply_interp(h, t1, nu, tN, N, nang));
+    CK(launch_axpby(N, nang, minus1c, tN, N, onec, out, N, st));
+    return HBS_OK;
+  };
+  // T1 = C1 v, T2 = C2 v for v (N x nang); C v = C_J (U^T v) with compressed walls
+  auto C_v = [&](const cplx* v, cplx* T1o, cplx* T2o) -> int {
+    if (!cw) return gemm({gd(C1, M2, 0, v, N, T1o, M2, M2, nang, N, onec, zero), gd(C2, M2, 0, v, N, T2o, M2, M2, nang, N, onec, zero)});
+    CR(apply_interp_t(h, v, N, t2, nu, nang));
+    return gemm({gd(C1, M2, 0, t2, nu, T1o, M2, M2, nang, nu, onec, zero), gd(C2, M2, 0, t2, nu, T2o, M2, M2, nang, nu, onec, zero)});
+  };
   // right-hand sides: C~ A~^{-1} b = C~ X_b - C~V K R X_b
   CK(launch_lincomb(M2, nang, d_c1, d_c2, 1, G1 + (size_t)colB * M2, M2, G2 + (size_t)colB * M2, M2, nullptr, 0, Wv, M2, st));
   if (P) {
@@ -439,8 +524,8 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   CR(solve_S(Wv, xi, minus1c));
   // eta = X_b - X(alpha) xi - V K (R X_b - R X(alpha) xi)
   CK(launch_stack(M2, nang, d_al, xi, stk, st));
-  CK(launch_axpby(N, nang, onec, X + (size_t)colB * N, N, zero, eta, N, st));
-  CR(gemm({gd(X, N, 0, stk, M4, eta, N, N, nang, M4, minus1c, onec)}));
+  CK(launch_axpby(N, nang, onec, X + (size_t)ycolB * N, N, zero, eta, N, st));
+  CR(sub_Xv(stk, eta));
   // eta -= V K [R b - R X(alpha) xi], assembled in uu/yy
   auto nb_correction = [&](const cplx* Rz, const cplx* xs, cplx sign) -> int {
     // vv = Rz - RAX xs (per group), yy = K vv, eta += sign * V yy
@@ -465,7 +550,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   int maxit = o->refine_max_iter < 0 ? 0 : (o->refine_max_iter == 0 ? (fp32 ? 3 : 2) : o->refine_max_iter);
   const double rtol = o->refine_tol > 0 ? o->refine_tol : 1e-13;
   std::vector<double> hn(3 * nang);
-  CK(launch_colnorm2(N, nang, Y + (size_t)colB * N, N, nrm + 2 * nang, st));
+  CK(launch_colnorm2(N, nang, Y + (size_t)ycolB * N, N, nrm + 2 * nang, st));
   double relres = -1;
   int iters = 0;
   for (int it = 0; it <= maxit; ++it) {
@@ -477,10 +562,10 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       CR(apply_interp(h, vv, nr, Z1, N, nang));
       CK(launch_axpby(N, nang, onec, Z1, N, onec, F, N, st));
     }
-    CK(launch_axpby(N, nang, onec, Y + (size_t)colB * N, N, zero, R1, N, st));
+    CK(launch_axpby(N, nang, onec, Y + (size_t)ycolB * N, N, zero, R1, N, st));
     CK(launch_axpby(N, nang, minus1c, F, N, onec, R1, N, st));
-    CR(gemm({gd(Y, N, 0, stk, M4, R1, N, N, nang, M4, minus1c, onec), gd(C1, M2, 0, eta, N, T1, M2, M2, nang, N, onec, zero),
-             gd(C2, M2, 0, eta, N, T2, M2, M2, nang, N, onec, zero)}));
+    CR(sub_Bv(stk, R1));
+    CR(C_v(eta, T1, T2));
     CK(launch_resid2(Q, nang, d_al, d_c1, d_c2, T1, T2, xi, R2, st));
     CK(launch_colnorm2(N, nang, R1, N, nrm, st));
     CK(launch_colnorm2(M2, nang, R2, M2, nrm + nang, st));
@@ -498,12 +583,12 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       CR(neighbour_K(Rb, vv, yy));
       CR(gemm({gd(Vc, N, 0, yy, nr, Z1, N, N, nang, nr, minus1c, onec)}));
     }
-    CR(gemm({gd(C1, M2, 0, Z1, N, U1, M2, M2, nang, N, onec, zero), gd(C2, M2, 0, Z1, N, U2, M2, M2, nang, N, onec, zero)}));
+    CR(C_v(Z1, U1, U2));
     CK(launch_lincomb(M2, nang, d_c1, d_c2, 1, U1, M2, U2, M2, R2, M2, Wv, M2, st));
     CR(solve_S(Wv, dxi, onec));
     CK(launch_stack(M2, nang, d_al, dxi, stk, st));
     CK(launch_axpby(N, nang, onec, Z1, N, onec, eta, N, st));
-    CR(gemm({gd(X, N, 0, stk, M4, eta, N, N, nang, M4, minus1c, onec)}));
+    CR(sub_Xv(stk, eta));
     if (P) {
       // + V K R X(alpha) dxi  (X~(alpha) = X(alpha) - V K R X(alpha))
       CK(hipMemsetAsync(Rb, 0, sizeof(cplx) * (size_t)nr * nang, st));
@@ -515,6 +600,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   h->stats.refine_iters = iters;
   h->stats.refine_residual = relres;
   h->stats.contour_M = M;
+  h->stats.walls_compressed = cw ? 1 : 0;
   if (maxit > 0 && relres >= rtol && relres > 1e-8) {
     set_error("qp_solve: refinement stalled at relative residual " + std::to_string(relres));
     return HBS_E_NOT_CONVERGED;

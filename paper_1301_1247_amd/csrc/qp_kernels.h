@@ -6,6 +6,7 @@
 struct QPGeo {
   const double *x, *y, *nx, *ny, *w;
   const cplx *k, *s, *wk;  // contour nodes, sqrt(omega^2 - k^2), quadrature weights
+  const int* idx;  // nullable: row / column i of a generated block is node idx[i] (a skeleton subset)
   int N, M;
   double omega, period, shift;
 };

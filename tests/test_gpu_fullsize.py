@@ -47,7 +47,13 @@ def _dense_kr6(disc, om):
     return A
 
 
-def test_qp_wavy20_full_size_vs_dense_oracle(gpu_lib):
+def _far_walls(nodes, d):
+    c = 0.5 * (nodes.max(0) + nodes.min(0))
+    return 0.9 * (0.5 * d - abs(c[0]))
+
+
+@pytest.fixture(scope="module")
+def wavy20_ref():
     wl = qpinputs.workload("wavy20")
     N, om, d = wl.N, wl.omega, wl.period
     disc = ny.Discretization(wl.curve, N)
@@ -65,24 +71,36 @@ def test_qp_wavy20_full_size_vs_dense_oracle(gpu_lib):
         Xb = sla.lu_solve(lu, pq.incident(disc, om, t))
         xi = -np.linalg.solve(S, (CL - CR / al) @ Xb)
         ref.append(((Xb - (XL + al * XR) @ xi)[:, 0], xi[:, 0]))
+    return wl, th, ref
+
+
+@pytest.mark.parametrize("walls", ["dense", "compressed"])
+def test_qp_wavy20_full_size_vs_dense_oracle(gpu_lib, wavy20_ref, walls):
+    wl, th, ref = wavy20_ref
+    N, om, d = wl.N, wl.omega, wl.period
     nodes, w, nrm, _ = discretize(wl.curve, N)
-    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-13, leaf_size=wl.leaf_size)
-    res = h.qp_solve_many(d, th)
+    far = _far_walls(nodes, d) if walls == "compressed" else 0.0
+    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-13, leaf_size=wl.leaf_size, far_radius=far)
+    res = h.qp_solve_many(d, th, compress_walls=1 if walls == "compressed" else -1)
+    assert h.stats().walls_compressed == (walls == "compressed")
     for a, (eta, xi) in enumerate(ref):
         assert np.linalg.norm(res["eta"][:, a] - eta) / np.linalg.norm(eta) < 1e-10
         assert np.linalg.norm(res["xi"][:, a] - xi) / np.linalg.norm(xi) < 1e-10
     assert res["flux"].max() < 1e-8   # physics accuracy of the N = 1e4 discretization
 
 
-def test_qp_wavy40_full_size_sampled_residual(gpu_lib):
+@pytest.mark.parametrize("walls", ["dense", "compressed"])
+def test_qp_wavy40_full_size_sampled_residual(gpu_lib, walls):
     import torch
     wl = qpinputs.workload("wavy40")
     nodes, w, nrm, _ = discretize(wl.curve, wl.N)
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(a).to(dev)
-    h = gpu_lib.Handle(t(nodes), t(w), t(nrm), wl.omega, 1e-13, leaf_size=wl.leaf_size, device=True)
-    res = h.qp_solve_many(wl.period, t(wl.thetas))
+    far = _far_walls(nodes, wl.period) if walls == "compressed" else 0.0
+    h = gpu_lib.Handle(t(nodes), t(w), t(nrm), wl.omega, 1e-13, leaf_size=wl.leaf_size, device=True, far_radius=far)
+    res = h.qp_solve_many(wl.period, t(wl.thetas), compress_walls=1 if walls == "compressed" else -1)
     st = h.stats()
+    assert st.walls_compressed == (walls == "compressed")
     assert st.levels == 11 and st.refine_residual < 1e-12
     eta = res["eta"].T.cpu().numpy()
     xi = res["xi"].T.cpu().numpy()

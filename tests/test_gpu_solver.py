@@ -210,6 +210,59 @@ def test_qp_neighbour_images_P1_wavy_kr6(gpu_lib, wavy_small):
     assert h.stats().refine_residual < 1e-12
 
 
+def _far_walls(nodes, d):
+    """far_radius for which the walls x = +-d/2 lie outside the far-field circle."""
+    c = 0.5 * (nodes.max(0) + nodes.min(0))
+    return 0.9 * (0.5 * d - abs(c[0]))
+
+
+@pytest.mark.parametrize("P", [0, 1])
+def test_qp_wavy_kr6_parity_compressed_walls(gpu_lib, wavy_small, P):
+    """B and C through the root skeletons (B = U B(J,:), C = C(:,J) U^T): same solution as the
+    dense oracle to the 1e-10 bar, for both the plain and the neighbour-image formulation."""
+    c, N, om, disc, A, lu = wavy_small
+    d = 2 * math.pi
+    thetas = np.array([-1.1, -0.45, -math.acos(0.31), -math.acos(0.31 + 1 / 40)])
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-12, far_radius=_far_walls(nodes, d))
+    res = h.qp_solve_many(d, thetas, P=P, compress_walls=1)
+    assert h.stats().walls_compressed == 1
+    ref = pq.solve_qp(disc, N, om, d, thetas, quad="kr6", P=P, A0=A)
+    _check_qp(res, ref, len(thetas))
+    assert h.stats().refine_residual < 1e-12
+    # the uncompressed path on the same handle agrees
+    res_u = h.qp_solve_many(d, thetas, P=P, compress_walls=-1)
+    assert h.stats().walls_compressed == 0
+    assert _rel(res_u["eta"], res["eta"]) < 1e-10
+
+
+def test_qp_star_kress_compressed_walls(gpu_lib):
+    wl = qpinputs.workload("star")
+    nodes, w, nrm, kap = discretize(wl.curve, wl.N)
+    h = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-12, quad="kress", leaf_size=50, curvature=kap,
+                       far_radius=_far_walls(nodes, wl.period))
+    res = h.qp_solve_many(wl.period, wl.thetas)      # compress_walls = 0: taken when valid
+    assert h.stats().walls_compressed == 1
+    ref = _oracle_qp(wl.curve, wl.N, wl.omega, wl.period, wl.thetas, "kress")
+    _check_qp(res, ref, len(wl.thetas))
+
+
+def test_qp_compressed_walls_needs_far_circle_inside_cell(gpu_lib):
+    wl = qpinputs.workload("star")
+    nodes, w, nrm, kap = discretize(wl.curve, wl.N)
+    h = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-10, quad="kress", leaf_size=50, curvature=kap)
+    with pytest.raises(gpu_lib.HBSError) as e:
+        h.qp_solve_many(wl.period, wl.thetas, compress_walls=1)
+    assert e.value.code == -1
+    h2 = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-10, quad="kress", leaf_size=50, curvature=kap,
+                        far_radius=_far_radius(nodes, wl.period))   # reaches beyond the walls
+    with pytest.raises(gpu_lib.HBSError) as e:
+        h2.qp_solve_many(wl.period, wl.thetas, compress_walls=1)
+    assert e.value.code == -1
+    h2.qp_solve_many(wl.period, wl.thetas)            # falls back to the uncompressed walls
+    assert h2.stats().walls_compressed == 0
+
+
 def test_qp_P1_needs_far_field_skeletons(gpu_lib):
     wl = qpinputs.workload("star")
     nodes, w, nrm, kap = discretize(wl.curve, wl.N)
