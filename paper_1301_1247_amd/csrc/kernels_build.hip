@@ -324,18 +324,93 @@ __global__ __launch_bounds__(NTP) void k_gj_panel(const InvDescT<R>* __restrict_
   }
 }
 
-// For columns outside the panel: apply the panel's row swaps, save the pivot rows to T.
+// Register-resident variant for n <= 1024: thread i holds row i of the NBR-column panel, so a
+// pivot step costs two barriers and broadcasts of one row through LDS (no global traffic).
+constexpr int GJ_NBR = 16;
 template <class R>
+__global__ __launch_bounds__(NTP) void k_gj_panel_reg(const InvDescT<R>* __restrict__ descs, int c0, int* __restrict__ ipiv_all,
+                                                      int maxn, int* __restrict__ info) {
+  typedef typename cx<R>::T C_t;
+  const InvDescT<R> d = descs[blockIdx.x];
+  const int n = d.n;
+  if (c0 >= n) return;
+  const int w = min(GJ_NBR, n - c0);
+  const int ld = d.ld;
+  C_t* A = d.a;
+  int* ipiv = ipiv_all + (size_t)blockIdx.x * maxn;
+  __shared__ double red_v[NTP / 64];
+  __shared__ int red_i[NTP / 64];
+  __shared__ C_t rowp[GJ_NBR];  // the pivot row before scaling
+  __shared__ C_t rowo[GJ_NBR];  // the old row p (moves to the pivot's row)
+  const int i = threadIdx.x, lane = i & 63, wv = i >> 6;
+  const C_t zero = cx<R>::make(0.0, 0.0);
+  C_t a[GJ_NBR];
+#pragma unroll
+  for (int j = 0; j < GJ_NBR; ++j) a[j] = (i < n && j < w) ? A[i + (size_t)(c0 + j) * ld] : zero;
+#pragma unroll
+  for (int jj = 0; jj < GJ_NBR; ++jj) {
+    if (jj < w) {
+      const int p = c0 + jj;
+      double bv = (i >= p && i < n) ? (double)cabs2(a[jj]) : -1.0;
+      int bi = (i >= p && i < n) ? i : n;
+      wave_argmax(bv, bi);
+      if (lane == 0) { red_v[wv] = bv; red_i[wv] = bi; }
+      __syncthreads();
+      double b = red_v[0];
+      int r = red_i[0];
+      for (int q = 1; q < NTP / 64; ++q)
+        if (red_v[q] > b || (red_v[q] == b && red_i[q] < r)) { b = red_v[q]; r = red_i[q]; }
+      if (!(b > 0.0)) r = p;
+      if (i == r) {
+#pragma unroll
+        for (int j = 0; j < GJ_NBR; ++j) rowp[j] = a[j];
+      }
+      if (i == p) {
+#pragma unroll
+        for (int j = 0; j < GJ_NBR; ++j) rowo[j] = a[j];
+      }
+      if (i == 0) {
+        ipiv[p] = r;
+        if (!(b > 0.0)) info[blockIdx.x] = p + 1;
+      }
+      __syncthreads();
+      const C_t piv = rowp[jj];
+      const C_t dd = (cabs2(piv) > 0) ? cinv(piv) : zero;
+      if (i == p) {
+#pragma unroll
+        for (int j = 0; j < GJ_NBR; ++j) a[j] = (j == jj) ? dd : cmul(rowp[j], dd);
+      } else if (i < n) {
+        if (i == r) {
+#pragma unroll
+          for (int j = 0; j < GJ_NBR; ++j) a[j] = rowo[j];
+        }
+        const C_t f = a[jj];
+#pragma unroll
+        for (int j = 0; j < GJ_NBR; ++j)
+          if (j != jj) a[j] = csub(a[j], cmul(f, cmul(rowp[j], dd)));
+        a[jj] = cmul(cx<R>::make(-f.x, -f.y), dd);
+      }
+    }
+  }
+  if (i < n) {
+#pragma unroll
+    for (int j = 0; j < GJ_NBR; ++j)
+      if (j < w) A[i + (size_t)(c0 + j) * ld] = a[j];
+  }
+}
+
+// For columns outside the panel: apply the panel's row swaps, save the pivot rows to T.
+template <class R, int NB>
 __global__ __launch_bounds__(NT) void k_gj_swapsave(const InvDescT<R>* __restrict__ descs, int c0, const int* __restrict__ ipiv_all,
                                                     int maxn, typename cx<R>::T* __restrict__ tbuf) {
   typedef typename cx<R>::T C_t;
   const InvDescT<R> d = descs[blockIdx.y];
   const int n = d.n;
   if (c0 >= n) return;
-  const int c1 = min(c0 + GJ_NB, n);
+  const int c1 = min(c0 + NB, n);
   const int ld = d.ld;
   const int* ipiv = ipiv_all + (size_t)blockIdx.y * maxn;
-  C_t* T = tbuf + (size_t)blockIdx.y * GJ_NB * maxn;
+  C_t* T = tbuf + (size_t)blockIdx.y * NB * maxn;
   for (int j = blockIdx.x * NT + threadIdx.x; j < n; j += gridDim.x * NT) {
     if (j >= c0 && j < c1) continue;
     C_t* col = d.a + (size_t)j * ld;
@@ -343,36 +418,36 @@ __global__ __launch_bounds__(NT) void k_gj_swapsave(const InvDescT<R>* __restric
       const int r = ipiv[p];
       if (r != p) { C_t t = col[p]; col[p] = col[r]; col[r] = t; }
     }
-    for (int p = c0; p < c1; ++p) T[(p - c0) + (size_t)j * GJ_NB] = col[p];
+    for (int p = c0; p < c1; ++p) T[(p - c0) + (size_t)j * NB] = col[p];
   }
 }
 
 // A[:, j] = mask(A[:, j]) + A[:, c0:c1] T[:, j]  for j outside the panel (mask zeroes rows c0:c1).
-template <class R>
+template <class R, int NB>
 __global__ __launch_bounds__(NT) void k_gj_update(const InvDescT<R>* __restrict__ descs, int c0, int maxn,
                                                   const typename cx<R>::T* __restrict__ tbuf) {
   typedef typename cx<R>::T C_t;
   const InvDescT<R> d = descs[blockIdx.z];
   const int n = d.n;
   if (c0 >= n) return;
-  const int c1 = min(c0 + GJ_NB, n);
+  const int c1 = min(c0 + NB, n);
   const int w = c1 - c0;
   const int ld = d.ld;
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 16;
   if (i0 >= n || j0 >= n) return;
-  const C_t* T = tbuf + (size_t)blockIdx.z * GJ_NB * maxn;
-  __shared__ C_t Ap[GJ_NB][65];
-  __shared__ C_t Ts[GJ_NB][17];
+  const C_t* T = tbuf + (size_t)blockIdx.z * NB * maxn;
+  __shared__ C_t Ap[NB][65];
+  __shared__ C_t Ts[NB][17];
   const int tid = threadIdx.x;
-  for (int e = tid; e < 64 * GJ_NB; e += NT) {
+  for (int e = tid; e < 64 * NB; e += NT) {
     const int ii = e % 64, pp = e / 64;
     const int i = i0 + ii;
     Ap[pp][ii] = (i < n && pp < w) ? d.a[i + (size_t)(c0 + pp) * ld] : cx<R>::make(0, 0);
   }
-  for (int e = tid; e < 16 * GJ_NB; e += NT) {
-    const int pp = e % GJ_NB, jj = e / GJ_NB;
+  for (int e = tid; e < 16 * NB; e += NT) {
+    const int pp = e % NB, jj = e / NB;
     const int j = j0 + jj;
-    Ts[pp][jj] = (j < n && pp < w) ? T[pp + (size_t)j * GJ_NB] : cx<R>::make(0, 0);
+    Ts[pp][jj] = (j < n && pp < w) ? T[pp + (size_t)j * NB] : cx<R>::make(0, 0);
   }
   __syncthreads();
   const int ii = tid % 64, jb = tid / 64;  // 4 column groups of 4
@@ -492,11 +567,20 @@ hipError_t launch_inv(const InvDescT<R>* d, int nd, int max_n, typename cx<R>::T
   if (nd == 0 || max_n == 0) return hipSuccess;
   hipError_t e = hipMemsetAsync(info, 0, sizeof(int) * nd, s);
   if (e != hipSuccess) return e;
-  for (int c0 = 0; c0 < max_n; c0 += GJ_NB) {
-    hipLaunchKernelGGL(k_gj_panel<R>, dim3(nd), dim3(NTP), 0, s, d, c0, ipiv, max_n, info);
-    hipLaunchKernelGGL(k_gj_swapsave<R>, dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, c0, ipiv, max_n, tbuf);
-    hipLaunchKernelGGL(k_gj_update<R>, dim3((max_n + 63) / 64, (max_n + 15) / 16, nd), dim3(NT), 0, s, d, c0, max_n,
-                       (const typename cx<R>::T*)tbuf);
+  if (max_n <= NTP) {
+    for (int c0 = 0; c0 < max_n; c0 += GJ_NBR) {
+      hipLaunchKernelGGL(k_gj_panel_reg<R>, dim3(nd), dim3(NTP), 0, s, d, c0, ipiv, max_n, info);
+      hipLaunchKernelGGL((k_gj_swapsave<R, GJ_NBR>), dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, c0, ipiv, max_n, tbuf);
+      hipLaunchKernelGGL((k_gj_update<R, GJ_NBR>), dim3((max_n + 63) / 64, (max_n + 15) / 16, nd), dim3(NT), 0, s, d, c0,
+                         max_n, (const typename cx<R>::T*)tbuf);
+    }
+  } else {
+    for (int c0 = 0; c0 < max_n; c0 += GJ_NB) {
+      hipLaunchKernelGGL(k_gj_panel<R>, dim3(nd), dim3(NTP), 0, s, d, c0, ipiv, max_n, info);
+      hipLaunchKernelGGL((k_gj_swapsave<R, GJ_NB>), dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, c0, ipiv, max_n, tbuf);
+      hipLaunchKernelGGL((k_gj_update<R, GJ_NB>), dim3((max_n + 63) / 64, (max_n + 15) / 16, nd), dim3(NT), 0, s, d, c0, max_n,
+                         (const typename cx<R>::T*)tbuf);
+    }
   }
   hipLaunchKernelGGL(k_gj_colperm<R>, dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, ipiv, max_n);
   return hipGetLastError();

@@ -105,6 +105,24 @@ __device__ inline cplx q_entry(const QPGeo& Q, cplx alpha, int r, int c) {
   return mkc(h.x - 1.0, h.y);
 }
 
+// out[:, a] = Q(alpha_a)^{-1} in[:, a]: Q couples rows m and M + m only, so each contour node is a
+// 2 x 2 solve (in and out may alias).  alpha_a = alpha[a * cs].
+__global__ __launch_bounds__(NT) void k_qsolve(QPGeo Q, const cplx* __restrict__ alpha, int cs, int ncol, const cplx* in,
+                                               int64_t ldi, cplx* out, int64_t ldo) {
+  const int M = Q.M;
+  const int64_t total = (int64_t)M * ncol;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int m = (int)(e % M), a = (int)(e / M);
+    const cplx al = alpha[(size_t)a * cs];
+    const cplx q00 = q_entry(Q, al, m, m), q01 = q_entry(Q, al, m, M + m);
+    const cplx q10 = q_entry(Q, al, M + m, m), q11 = q_entry(Q, al, M + m, M + m);
+    const cplx id = cinv(csub(cmul(q00, q11), cmul(q01, q10)));
+    const cplx x0 = in[m + (size_t)a * ldi], x1 = in[M + m + (size_t)a * ldi];
+    out[m + (size_t)a * ldo] = cmul(id, csub(cmul(q11, x0), cmul(q01, x1)));
+    out[M + m + (size_t)a * ldo] = cmul(id, csub(cmul(q00, x1), cmul(q10, x0)));
+  }
+}
+
 // S_g = Q(alpha_g) - C(alpha_g) X(alpha_g) with C(alpha) = c1 C1 + c2 C2, X(alpha) = X_L + alpha X_R:
 //   S_g = Q - [c1 (G1_L + alpha G1_R) + c2 (G2_L + alpha G2_R)],  G1 = C1 [X_L | X_R | ...], G2 = C2 [...]
 // (ld 2M).  coef holds (alpha, c1, c2) per group.
@@ -299,6 +317,12 @@ hipError_t launch_lincomb(int rows, int ncol, const cplx* c1, const cplx* c2, in
   if ((int64_t)rows * ncol == 0) return hipSuccess;
   hipLaunchKernelGGL(k_lincomb, dim3(grid_for((int64_t)rows * ncol)), dim3(NT), 0, s, rows, ncol, c1, c2, cs, U1, ld1, U2,
                      ld2, R, ldr, W, ldw);
+  return hipGetLastError();
+}
+hipError_t launch_qsolve(const QPGeo& q, const cplx* alpha, int cs, int ncol, const cplx* in, int64_t ldi, cplx* out,
+                         int64_t ldo, hipStream_t s) {
+  if ((int64_t)q.M * ncol == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_qsolve, dim3(grid_for((int64_t)q.M * ncol)), dim3(NT), 0, s, q, alpha, cs, ncol, in, ldi, out, ldo);
   return hipGetLastError();
 }
 hipError_t launch_eye_plus(int n, int ng, const cplx* B, int64_t ldb, int64_t bstride, cplx* A, hipStream_t s) {

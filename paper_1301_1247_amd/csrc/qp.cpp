@@ -232,7 +232,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       sizeof(cplx) * N * Wy,                         // 5 X
       sizeof(cplx) * (size_t)M2 * NC * 2,            // 6 C1, C2
       sizeof(cplx) * (size_t)M2 * W * 2,             // 7 G1, G2
-      sizeof(cplx) * (size_t)M2 * M2 * ng,           // 8 S
+      cw ? 0 : sizeof(cplx) * (size_t)M2 * M2 * ng, // 8 S (uncompressed walls)
       sizeof(cplx) * (size_t)M2 * nang * 8,          // 9 xi, W, T1, T2, R2, U1, U2, dxi
       sizeof(cplx) * (size_t)M4 * nang,              // 10 stack
       sizeof(cplx) * (size_t)N * nang * 4,           // 11 eta, R1, Z1, F
@@ -244,8 +244,12 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       sizeof(cplx) * (size_t)nrr * M2 * ng * 2,      // 17 R(alpha) X(alpha), K R X scratch
       sizeof(cplx) * (size_t)M2 * nrr * ng,          // 18 C~ V
       sizeof(cplx) * (size_t)nrr * nang * 4,         // 19 R b, u, y, misc (nr x nang)
-      cw ? sizeof(cplx) * ((size_t)nuu * (M4 + W + Wy + 2 * nang) + (size_t)nr * Wy * 2 + (size_t)N * nang) : 0};
+      cw ? sizeof(cplx) * ((size_t)nuu * (M4 + W + Wy + 2 * nang) + (size_t)nr * Wy * 2 + (size_t)N * nang) : 0,
                                                      // 20 B_J, X_c, U^T X, t1, t2, R_{+-1} X, U t
+      cw ? sizeof(cplx) * ((size_t)ng * (2 * (size_t)nuu * M2 + 3 * (size_t)nuu * nuu) + (size_t)M2 * nuu +
+                           (size_t)M2 * nang + 2 * (size_t)nuu * nang) : 0};
+                                                     // 21 Woodbury form of S^{-1}: B_J(alpha), Q^{-1} C~ H~, K2, H~,
+                                                     //    scratch; C~_J H~; Q^{-1} r; two nu x nang
   std::vector<size_t> off(sizes.size() + 1, 0);
   for (size_t i = 0; i < sizes.size(); ++i) off[i + 1] = off[i] + ((sizes[i] + 255) / 256) * 256;
   CK(h->scratch.reserve(off.back()));
@@ -309,6 +313,15 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   cplx* RZp = t2 + (size_t)nuu * nang;      // nr x Wy
   cplx* RZm = RZp + (size_t)nr * Wy;        // nr x Wy
   cplx* tN = RZm + (size_t)nr * Wy;         // N x nang
+  cplx* BJa = (cplx*)(base + off[21]);      // per group nu x 2M: B_J,L + alpha B_J,R
+  cplx* Cq = BJa + (size_t)ng * nuu * M2;   // per group 2M x nu: Q^{-1} C~_J H~
+  cplx* K2 = Cq + (size_t)ng * nuu * M2;    // per group nu x nu: (I - B_J(alpha) Cq)^{-1}
+  cplx* Ht = K2 + (size_t)ng * nuu * nuu;   // per group nu x nu: U^T A~^{-1} U
+  cplx* Hs = Ht + (size_t)ng * nuu * nuu;   // per group nu x nu scratch
+  cplx* CH = Hs + (size_t)ng * nuu * nuu;   // 2M x nu
+  cplx* yq = CH + (size_t)M2 * nuu;         // 2M x nang
+  cplx* zq = yq + (size_t)M2 * nang;        // nu x nang
+  cplx* zq2 = zq + (size_t)nuu * nang;      // nu x nang
 
   std::vector<cplx> consts = {onec, minus1c};
   CK(hipMemcpyAsync(dcont, cont.data(), sizeof(cplx) * 3 * M, hipMemcpyHostToDevice, st));
@@ -429,7 +442,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     CK(hipStreamSynchronize(st));
     if (P) CR(gemm({gd(Rp, nr, 0, X, N, RXp, nr, nr, (int)W, N, onec, zero), gd(Rm, nr, 0, X, N, RXm, nr, nr, (int)W, N, onec, zero)}));
   }
-  CK(launch_form_S(Q, d_gco, ng, G1, G2, S, st));
+  if (!cw) CK(launch_form_S(Q, d_gco, ng, G1, G2, S, st));
   if (P) {
     // per alpha: K = (I + R V)^{-1}, R X(alpha), C~ V;  S += C~V K R X(alpha)
     for (int g = 0; g < ng; ++g) {
@@ -454,17 +467,64 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       CK(inv_batched(h->arena, h->work, iv, st, &sing));
       if (sing) { set_error("qp_solve: singular Woodbury capacitance matrix"); return HBS_E_SINGULAR; }
     }
-    std::vector<GemmDesc> g1, g2;
-    for (int g = 0; g < ng; ++g)
-      g1.push_back(gd(Kg + (size_t)g * nr * nr, nr, 0, RAX + (size_t)g * nr * M2, nr, KRAX + (size_t)g * nr * M2, nr, nr, M2,
-                      nr, onec, zero));
-    CR(gemm(g1));
-    for (int g = 0; g < ng; ++g)
-      g2.push_back(gd(CV + (size_t)g * M2 * nr, M2, 0, KRAX + (size_t)g * nr * M2, nr, S + (size_t)g * M2 * M2, M2, M2, M2,
-                      nr, onec, onec));
-    CR(gemm(g2));
+    if (!cw) {
+      std::vector<GemmDesc> g1, g2;
+      for (int g = 0; g < ng; ++g)
+        g1.push_back(gd(Kg + (size_t)g * nr * nr, nr, 0, RAX + (size_t)g * nr * M2, nr, KRAX + (size_t)g * nr * M2, nr, nr, M2,
+                        nr, onec, zero));
+      CR(gemm(g1));
+      for (int g = 0; g < ng; ++g)
+        g2.push_back(gd(CV + (size_t)g * M2 * nr, M2, 0, KRAX + (size_t)g * nr * M2, nr, S + (size_t)g * M2 * M2, M2, M2, M2,
+                        nr, onec, onec));
+      CR(gemm(g2));
+    }
   }
-  {
+  if (cw) {
+    // S(alpha) = Q - C~_J(alpha) H~(alpha) B_J(alpha) with H~ = U^T A~^{-1} U = H - H K(alpha) R(alpha) V (P = 1) or H;
+    // Woodbury around the 2 x 2-block-diagonal Q: S^{-1} = [I + Cq K2 B_J(alpha)] Q^{-1},
+    // Cq = Q^{-1} C~_J H~, K2 = (I - B_J(alpha) Cq)^{-1}  (root-size inversions only).
+    const cplx* H = Zt;  // U^T V (nu x nu)
+    for (int g = 0; g < ng; ++g) {
+      CK(launch_lincomb(nu, M2, d_one, d_gco + 3 * g, 0, BJ, nu, BJ + (size_t)M2 * nu, nu, nullptr, 0,
+                        BJa + (size_t)g * nu * M2, nu, st));
+    }
+    if (P) {
+      std::vector<GemmDesc> g1, g2;
+      for (int g = 0; g < ng; ++g)
+        g1.push_back(gd(Kg + (size_t)g * nr * nr, nr, 0, KVg + (size_t)g * nr * nr, nr, Hs + (size_t)g * nu * nu, nu, nu, nu,
+                        nr, onec, zero));
+      CR(gemm(g1));
+      for (int g = 0; g < ng; ++g) {
+        CK(hipMemcpyAsync(Ht + (size_t)g * nu * nu, H, sizeof(cplx) * (size_t)nu * nu, hipMemcpyDeviceToDevice, st));
+        g2.push_back(gd(H, nu, 0, Hs + (size_t)g * nu * nu, nu, Ht + (size_t)g * nu * nu, nu, nu, nu, nu, minus1c, onec));
+      }
+      CR(gemm(g2));
+    }
+    for (int g = 0; g < ng; ++g) {
+      const cplx* Hg = P ? Ht + (size_t)g * nu * nu : H;
+      // C~_J(alpha) = c1 C1_J + c2 C2_J (staged in Cq), then Cq = Q^{-1} C~_J H~
+      cplx* cq = Cq + (size_t)g * M2 * nu;
+      CK(launch_lincomb(M2, nu, d_gco + 3 * g + 1, d_gco + 3 * g + 2, 0, C1, M2, C2, M2, nullptr, 0, cq, M2, st));
+      CR(gemm({gd(cq, M2, 0, Hg, nu, CH, M2, M2, nu, nu, onec, zero)}));
+      CK(launch_qsolve(Q, d_gco + 3 * g, 0, nu, CH, M2, cq, M2, st));
+    }
+    {
+      std::vector<GemmDesc> g1;
+      for (int g = 0; g < ng; ++g)
+        g1.push_back(gd(BJa + (size_t)g * nu * M2, nu, 0, Cq + (size_t)g * M2 * nu, M2, Hs + (size_t)g * nu * nu, nu, nu, nu,
+                        M2, minus1c, zero));
+      CR(gemm(g1));
+      CK(launch_eye_plus(nu, ng, Hs, nu, (int64_t)nu * nu, K2, st));
+      std::vector<InvDesc> iv;
+      for (int g = 0; g < ng; ++g) iv.push_back({K2 + (size_t)g * nu * nu, nu, nu});
+      bool sing = false;
+      CK(inv_batched(h->arena, h->work, iv, st, &sing));
+      if (sing) {
+        set_error("qp_solve: singular Schur complement");
+        return HBS_E_SINGULAR;
+      }
+    }
+  } else {
     std::vector<InvDesc> iv;
     for (int g = 0; g < ng; ++g) iv.push_back({S + (size_t)g * M2 * M2, M2, M2});
     bool sing = false;
@@ -484,6 +544,24 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     return gemm(g);
   };
   auto solve_S = [&](const cplx* rhs, cplx* out, cplx alpha) -> int {
+    if (cw) {
+      // out = alpha [y + Cq K2 B_J(alpha) y],  y = Q^{-1} rhs  (per group of angles)
+      CK(launch_qsolve(Q, d_al, 1, nang, rhs, M2, yq, M2, st));
+      std::vector<GemmDesc> g1, g2, g3;
+      for (int gg = 0; gg < ng; ++gg)
+        g1.push_back(gd(BJa + (size_t)gg * nu * M2, nu, 0, yq + (size_t)goff[gg] * M2, M2, zq + (size_t)goff[gg] * nu, nu, nu,
+                        gcnt[gg], M2, onec, zero));
+      CR(gemm(g1));
+      for (int gg = 0; gg < ng; ++gg)
+        g2.push_back(gd(K2 + (size_t)gg * nu * nu, nu, 0, zq + (size_t)goff[gg] * nu, nu, zq2 + (size_t)goff[gg] * nu, nu, nu,
+                        gcnt[gg], nu, onec, zero));
+      CR(gemm(g2));
+      CK(launch_axpby(M2, nang, alpha, yq, M2, zero, out, M2, st));
+      for (int gg = 0; gg < ng; ++gg)
+        g3.push_back(gd(Cq + (size_t)gg * M2 * nu, M2, 0, zq2 + (size_t)goff[gg] * nu, nu, out + (size_t)goff[gg] * M2, M2, M2,
+                        gcnt[gg], nu, alpha, onec));
+      return gemm(g3);
+    }
     std::vector<GemmDesc> g;
     for (int gg = 0; gg < ng; ++gg)
       g.push_back(gd(S + (size_t)gg * M2 * M2, M2, 0, rhs + (size_t)goff[gg] * M2, M2, out + (size_t)goff[gg] * M2, M2, M2,

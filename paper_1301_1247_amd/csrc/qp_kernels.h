@@ -19,6 +19,9 @@ hipError_t launch_form_S(const QPGeo& q, const cplx* coef, int ng, const cplx* G
 // W[:, a] = c1[a*cs] U1[:, a] + c2[a*cs] U2[:, a], or R[:, a] - (...) when R != nullptr (W may alias R)
 hipError_t launch_lincomb(int rows, int ncol, const cplx* c1, const cplx* c2, int cs, const cplx* U1, int64_t ld1,
                           const cplx* U2, int64_t ld2, const cplx* R, int64_t ldr, cplx* W, int64_t ldw, hipStream_t s);
+// out[:, a] = Q(alpha[a cs])^{-1} in[:, a] (2M rows; may alias)
+hipError_t launch_qsolve(const QPGeo& q, const cplx* alpha, int cs, int ncol, const cplx* in, int64_t ldi, cplx* out,
+                         int64_t ldo, hipStream_t s);
 hipError_t launch_eye_plus(int n, int ng, const cplx* B, int64_t ldb, int64_t bstride, cplx* A, hipStream_t s);
 hipError_t launch_stack(int M2, int nang, const cplx* alpha_col, const cplx* xi, cplx* st, hipStream_t s);
 hipError_t launch_resid2(const QPGeo& q, int nang, const cplx* alpha_col, const cplx* c1, const cplx* c2, const cplx* T1,

@@ -46,7 +46,7 @@ def test_zgemm_matches_numpy(gpu_lib, m, n, k, trans):
     assert np.abs(C - ref).max() < 1e-13 * max(1.0, np.abs(ref).max()) * math.sqrt(k)
 
 
-@pytest.mark.parametrize("n", [1, 5, 32, 33, 100, 257])
+@pytest.mark.parametrize("n", [1, 5, 16, 17, 32, 33, 100, 257, 1024, 1030])
 def test_zinv_matches_numpy(gpu_lib, n):
     rng = np.random.default_rng(n)
     A = rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n)) + 3 * np.eye(n)
