@@ -77,6 +77,8 @@ _sig = {
     "qps_zinv": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32]),
     "qps_cgemm": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "qps_cinv": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32]),
+    "qps_pool_release": (C.c_int, []),
+    "qps_pool_cached_bytes": (C.c_int64, []),
     "qps_profile_enable": (C.c_int, [C.c_int32]),
     "qps_profile_read": (C.c_int, [C.c_char_p, _P, _P, _P, _P]),
 }
@@ -292,6 +294,15 @@ def zinv(A, precision="fp64"):
     Af = np.array(np.transpose(A, (0, 2, 1)), order="C", copy=True)
     _check(fn(_ptr(Af), n, nb, PTR_HOST))
     return np.transpose(Af, (0, 2, 1))
+
+
+def pool_release():
+    """Return the device memory cached by the library's pool (current device) to HIP."""
+    _check(_lib.qps_pool_release())
+
+
+def pool_cached_bytes():
+    return int(_lib.qps_pool_cached_bytes())
 
 
 def profile_enable(on=True):

@@ -518,6 +518,14 @@ int qps_cgemm(const float* A, const float* B, float* C, int32_t m, int32_t n, in
 int qps_zinv(double* A, int32_t n, int32_t nbatch, int32_t ptr_mode) { return inv_diag<double>("qps_zinv", A, n, nbatch, ptr_mode); }
 int qps_cinv(float* A, int32_t n, int32_t nbatch, int32_t ptr_mode) { return inv_diag<float>("qps_cinv", A, n, nbatch, ptr_mode); }
 
+int qps_pool_release(void) {
+  clear_error();
+  if (pool_release_current() != 0) { set_error("qps_pool_release: no current device"); return HBS_E_DEVICE; }
+  return HBS_OK;
+}
+
+int64_t qps_pool_cached_bytes(void) { return (int64_t)pool_cached_current(); }
+
 int qps_profile_enable(int32_t on) {
   profile_enable(on != 0);
   return HBS_OK;

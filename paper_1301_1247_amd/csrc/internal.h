@@ -91,14 +91,19 @@ struct CopyDesc {
 namespace qps {
 
 // device buffer that grows on demand
+// Device buffer drawn from the library's per-device pool (runtime.cpp); grows, never shrinks.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  int dev = 0;
   hipError_t reserve(size_t b);
   void release();
   ~DevBuf() { release(); }
   template <class T> T* as() { return static_cast<T*>(p); }
 };
+
+int pool_release_current();      // return the current device's cached blocks to the device
+size_t pool_cached_current();     // bytes cached for the current device
 
 // upload a descriptor array into a growing device arena
 template <class T>

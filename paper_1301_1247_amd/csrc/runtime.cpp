@@ -2,6 +2,7 @@
 // profiling with HIP events, and the batched inversion driver.
 #include "internal.h"
 
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <string>
@@ -14,27 +15,120 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 const char* last_error() { return g_last_error.c_str(); }
 void clear_error() { g_last_error.clear(); }
 
+// ------------------------------------------------------------------ device memory pool
+// Released buffers are kept per device and handed to later reservations of a similar size, so
+// that handles built and freed in a loop (one per frequency, or per benchmark step) do not pay
+// hipMalloc / hipFree each time.  Sizes are rounded to 1/8 of their power of two; a cached block
+// is reused for requests down to 4/5 of its size.  At most QPS_POOL_MAX_GB (default 64) GiB stay
+// cached per device; a failed hipMalloc returns the cache to the device and retries.
+namespace {
+struct Pool {
+  std::mutex mu;
+  std::map<int, std::multimap<size_t, void*>> free_blocks;
+  std::map<int, size_t> cached;
+  size_t cap = 0;
+};
+Pool& pool() {
+  static Pool* p = [] {
+    Pool* q = new Pool;  // never destroyed: no HIP calls during process teardown
+    const char* e = std::getenv("QPS_POOL_MAX_GB");
+    double gb = e ? std::atof(e) : 64.0;
+    q->cap = gb > 0 ? (size_t)(gb * 1073741824.0) : 0;
+    return q;
+  }();
+  return *p;
+}
+size_t round_size(size_t b) {
+  if (b <= ((size_t)1 << 20)) return (b + 255) & ~(size_t)255;
+  size_t p2 = 1;
+  while (p2 < b) p2 <<= 1;
+  const size_t q = p2 / 8;
+  return (b + q - 1) / q * q;
+}
+void trim_device(int dev) {
+  Pool& P = pool();
+  std::vector<void*> blocks;
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    for (auto& kv : P.free_blocks[dev]) blocks.push_back(kv.second);
+    P.free_blocks[dev].clear();
+    P.cached[dev] = 0;
+  }
+  for (void* b : blocks) (void)hipFree(b);
+}
+}  // namespace
+
 hipError_t DevBuf::reserve(size_t b) {
   if (b <= bytes) return hipSuccess;
   release();
-  size_t nb = b + b / 4 + 256;
-  hipError_t e = hipMalloc(&p, nb);
+  const size_t want = round_size(b + b / 4 + 256);
+  int d = 0;
+  hipError_t e = hipGetDevice(&d);
+  if (e != hipSuccess) return e;
+  Pool& P = pool();
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto& fl = P.free_blocks[d];
+    auto it = fl.lower_bound(want);
+    if (it != fl.end() && it->first <= want + want / 4) {
+      p = it->second;
+      bytes = it->first;
+      dev = d;
+      P.cached[d] -= it->first;
+      fl.erase(it);
+      return hipSuccess;
+    }
+  }
+  e = hipMalloc(&p, want);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    (void)hipDeviceSynchronize();
+    trim_device(d);
+    e = hipMalloc(&p, want);
+  }
   if (e != hipSuccess) {
     p = nullptr;
     bytes = 0;
     return e;
   }
-  bytes = nb;
+  bytes = want;
+  dev = d;
   return hipSuccess;
 }
+
 void DevBuf::release() {
-  // the buffer may still be read by queued kernels; hipFree must not overtake them
-  if (p) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(p);
+  if (!p) return;
+  // the buffer may still be read by queued kernels (of any stream) before it is handed on
+  (void)hipDeviceSynchronize();
+  Pool& P = pool();
+  bool keep;
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    keep = P.cached[dev] + bytes <= P.cap;
+    if (keep) {
+      P.free_blocks[dev].emplace(bytes, p);
+      P.cached[dev] += bytes;
+    }
   }
+  if (!keep) (void)hipFree(p);
   p = nullptr;
   bytes = 0;
+}
+
+int pool_release_current() {
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) return -1;
+  (void)hipDeviceSynchronize();
+  trim_device(d);
+  return 0;
+}
+
+size_t pool_cached_current() {
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) return 0;
+  Pool& P = pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  return P.cached[d];
 }
 
 // ------------------------------------------------------------------ profiling
