@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 
 namespace qps {
 
@@ -94,7 +95,11 @@ int build(hbs_handle* h) {
     h->c0x = 0.5 * (x0 + x1);
     h->c0y = 0.5 * (y0 + y1);
     double r = 0;
-    for (int64_t i = 0; i < N; ++i) r = std::max(r, std::hypot(h->hx[i] - h->c0x, h->hy[i] - h->c0y));
+    for (int64_t i = 0; i < N; ++i) {
+      const double dx = h->hx[i] - h->c0x, dy = h->hy[i] - h->c0y;
+      r = std::max(r, dx * dx + dy * dy);
+    }
+    r = std::sqrt(r);
     h->robs = r;
     if (h->opts.far_radius > 0 && !(h->opts.far_radius > 1.05 * r)) {
       set_error("hbs_build: far_radius must exceed the obstacle's radius about its centre");
@@ -106,29 +111,43 @@ int build(hbs_handle* h) {
   const int npfar = far_on ? std::max(pmin, 2 * (int)std::ceil(om * Rfar + std::log(1.0 / h->tol) /
                                                                   std::log(Rfar / h->robs)) + 8) : 0;
 
-  // box ranges and bounding circles of the original points
-  for (int l = 1; l <= L; ++l) {
-    Level& V = h->lv[l];
-    V.nb = 1 << l;
-    V.lo.resize(V.nb);
-    V.hi.resize(V.nb);
-    V.cx.resize(V.nb);
-    V.cy.resize(V.nb);
-    V.rad.resize(V.nb);
-    for (int b = 0; b < V.nb; ++b) {
-      int lo = (int)((int64_t)b * N / V.nb), hi = (int)((int64_t)(b + 1) * N / V.nb);
-      V.lo[b] = lo;
-      V.hi[b] = hi;
-      double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
-      for (int i = lo; i < hi; ++i) {
-        x0 = std::min(x0, h->hx[i]); x1 = std::max(x1, h->hx[i]);
-        y0 = std::min(y0, h->hy[i]); y1 = std::max(y1, h->hy[i]);
+  // box ranges and bounding circles of the original points (all levels in one launch)
+  {
+    std::vector<int> blo, bhi;
+    for (int l = 1; l <= L; ++l) {
+      Level& V = h->lv[l];
+      V.nb = 1 << l;
+      V.lo.resize(V.nb);
+      V.hi.resize(V.nb);
+      for (int b = 0; b < V.nb; ++b) {
+        V.lo[b] = (int)((int64_t)b * N / V.nb);
+        V.hi[b] = (int)((int64_t)(b + 1) * N / V.nb);
+        blo.push_back(V.lo[b]);
+        bhi.push_back(V.hi[b]);
       }
-      double cx = 0.5 * (x0 + x1), cy = 0.5 * (y0 + y1), r = 0.0;
-      for (int i = lo; i < hi; ++i) r = std::max(r, std::hypot(h->hx[i] - cx, h->hy[i] - cy));
-      V.cx[b] = cx;
-      V.cy[b] = cy;
-      V.rad[b] = r;
+    }
+    const int nbox = (int)blo.size();
+    DevBuf dlo, dhi, dcirc;
+    CK(dlo.reserve(sizeof(int) * nbox));
+    CK(dhi.reserve(sizeof(int) * nbox));
+    CK(dcirc.reserve(sizeof(double) * 3 * nbox));
+    CK(hipMemcpyAsync(dlo.p, blo.data(), sizeof(int) * nbox, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(dhi.p, bhi.data(), sizeof(int) * nbox, hipMemcpyHostToDevice, st));
+    CK(launch_box_circles(h->geo.x, h->geo.y, dlo.as<int>(), dhi.as<int>(), nbox, dcirc.as<double>(), st));
+    std::vector<double> circ(3 * (size_t)nbox);
+    CK(hipMemcpyAsync(circ.data(), dcirc.p, sizeof(double) * 3 * nbox, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    size_t q = 0;
+    for (int l = 1; l <= L; ++l) {
+      Level& V = h->lv[l];
+      V.cx.resize(V.nb);
+      V.cy.resize(V.nb);
+      V.rad.resize(V.nb);
+      for (int b = 0; b < V.nb; ++b, ++q) {
+        V.cx[b] = circ[3 * q];
+        V.cy[b] = circ[3 * q + 1];
+        V.rad[b] = circ[3 * q + 2];
+      }
     }
   }
 
@@ -219,22 +238,52 @@ int build(hbs_handle* h) {
     std::vector<int> nnear(nb), np(nb), npf(nb), m(nb), s(nb);
     std::vector<int64_t> noff(nb + 1, 0), woff(nb + 1, 0), zoff(nb + 1, 0);
     std::vector<int> hnear;
+    // candidate boxes from a uniform grid of box centres (cell = the largest near distance), so
+    // the near lists cost O(nb) instead of O(nb^2); exact compression takes every box
+    double maxrad = 0, gx0 = 1e300, gy0 = 1e300;
+    for (int b = 0; b < nb; ++b) {
+      maxrad = std::max(maxrad, V.rad[b]);
+      gx0 = std::min(gx0, V.cx[b]);
+      gy0 = std::min(gy0, V.cy[b]);
+    }
+    const double cell = std::max((ratio + 1.0) * maxrad, 1e-300);
+    std::map<std::pair<int64_t, int64_t>, std::vector<int>> grid;
+    auto key = [&](double x, double y) {
+      return std::make_pair((int64_t)std::floor((x - gx0) / cell), (int64_t)std::floor((y - gy0) / cell));
+    };
+    if (!exact)
+      for (int c = 0; c < nb; ++c) grid[key(V.cx[c], V.cy[c])].push_back(c);
+    std::vector<int> cand;
     for (int b = 0; b < nb; ++b) {
       const double Rp = ratio * V.rad[b];
-      int cnt = 0, total_other = 0;
-      const size_t start = hnear.size();
-      for (int c = 0; c < nb; ++c) {
+      int cnt = 0;
+      const int64_t total_other = V.ntot - V.n[b];
+      cand.clear();
+      if (exact) {
+        for (int c = 0; c < nb; ++c) cand.push_back(c);
+      } else {
+        const auto k0 = key(V.cx[b], V.cy[b]);
+        for (int64_t dx = -1; dx <= 1; ++dx)
+          for (int64_t dy = -1; dy <= 1; ++dy) {
+            auto it = grid.find(std::make_pair(k0.first + dx, k0.second + dy));
+            if (it != grid.end()) cand.insert(cand.end(), it->second.begin(), it->second.end());
+          }
+        cand.push_back((b + 1) % nb);
+        cand.push_back((b + nb - 1) % nb);
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+      }
+      for (int c : cand) {
         if (c == b) continue;
-        total_other += V.n[c];
         const int dd = ((c - b) % nb + nb) % nb;
         const bool adj = (dd == 1 || dd == nb - 1);
-        const bool nr = exact || adj || std::hypot(V.cx[c] - V.cx[b], V.cy[c] - V.cy[b]) < Rp + V.rad[c];
+        const double ex = V.cx[c] - V.cx[b], ey = V.cy[c] - V.cy[b];
+        const bool nr = exact || adj || std::sqrt(ex * ex + ey * ey) < Rp + V.rad[c];
         if (nr) {
           for (int i = 0; i < V.n[c]; ++i) hnear.push_back(V.hact[V.aoff[c] + i]);
           cnt += V.n[c];
         }
       }
-      (void)start;
       nnear[b] = cnt;
       const bool full = (cnt == total_other);
       np[b] = full ? 0 : std::max(pmin, (int)std::ceil(1.5 * om * Rp) + 50);

@@ -251,6 +251,45 @@ __global__ __launch_bounds__(NT) void k_copy(const CopyDesc* __restrict__ descs)
   }
 }
 
+// Bounding circle of the nodes lo[b] <= i < hi[b] of every box b: centre = middle of the
+// bounding box, radius = largest distance from it (out = cx, cy, r per box; one workgroup per box).
+__global__ __launch_bounds__(NT) void k_box_circles(const double* __restrict__ x, const double* __restrict__ y,
+                                                    const int* __restrict__ lo, const int* __restrict__ hi,
+                                                    double* __restrict__ out) {
+  const int b = blockIdx.x;
+  const int i0 = lo[b], i1 = hi[b];
+  __shared__ double red[4][NT / 64];
+  double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+  for (int i = i0 + threadIdx.x; i < i1; i += NT) {
+    x0 = fmin(x0, x[i]); x1 = fmax(x1, x[i]);
+    y0 = fmin(y0, y[i]); y1 = fmax(y1, y[i]);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    x0 = fmin(x0, __shfl_xor(x0, o, 64)); x1 = fmax(x1, __shfl_xor(x1, o, 64));
+    y0 = fmin(y0, __shfl_xor(y0, o, 64)); y1 = fmax(y1, __shfl_xor(y1, o, 64));
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { red[0][wv] = x0; red[1][wv] = x1; red[2][wv] = y0; red[3][wv] = y1; }
+  __syncthreads();
+  for (int q = 0; q < NT / 64; ++q) {
+    x0 = fmin(x0, red[0][q]); x1 = fmax(x1, red[1][q]);
+    y0 = fmin(y0, red[2][q]); y1 = fmax(y1, red[3][q]);
+  }
+  const double cx = 0.5 * (x0 + x1), cy = 0.5 * (y0 + y1);
+  double r = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += NT) r = fmax(r, sqrt((x[i] - cx) * (x[i] - cx) + (y[i] - cy) * (y[i] - cy)));
+  for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[0][wv] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < NT / 64; ++q) r = fmax(r, red[0][q]);
+    out[3 * b] = cx;
+    out[3 * b + 1] = cy;
+    out[3 * b + 2] = r;
+  }
+}
+
 __global__ void k_gather_idx(const int* __restrict__ src, const int* __restrict__ idx, int* __restrict__ dst, int64_t n) {
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) dst[e] = src[idx[e]];
 }
@@ -555,6 +594,12 @@ hipError_t launch_copy(const CopyDesc* d, int nd, int max_elems, hipStream_t s) 
   if (nd == 0 || max_elems == 0) return hipSuccess;
   dim3 grid(grid_for(max_elems, 256), nd);
   hipLaunchKernelGGL(k_copy, grid, dim3(NT), 0, s, d);
+  return hipGetLastError();
+}
+hipError_t launch_box_circles(const double* x, const double* y, const int* lo, const int* hi, int nbox, double* out,
+                              hipStream_t s) {
+  if (nbox == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_box_circles, dim3(nbox), dim3(NT), 0, s, x, y, lo, hi, out);
   return hipGetLastError();
 }
 hipError_t launch_gather_idx(const int* src, const int* idx, int* dst, int64_t n, hipStream_t s) {

@@ -270,6 +270,53 @@ __global__ __launch_bounds__(NT) void k_bragg(QPGeo Q, const double* __restrict_
   }
 }
 
+// Bragg basis of one Bloch-phase group: the orders shared by its angles are kap_q = kref + 2 pi (qlo + q) / d,
+// q < nq.  E (2 nq x N, col-major): row q = w_j e^{-i(kap_q x_j + k_q y_j)} [-i(kap_q n_x + k_q n_y) - i omega],
+// row nq + q = w_j e^{-i(kap_q x_j - k_q y_j)} [i(-kap_q n_x + k_q n_y) - i omega]; E eta gives the sums of k_bragg.
+__global__ __launch_bounds__(NT) void k_bragg_basis(QPGeo Q, double kref, int qlo, int nq, cplx* __restrict__ E) {
+  const int64_t rows = 2 * (int64_t)nq;
+  const int64_t total = rows * Q.N;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int r = (int)(e % rows);
+    const int j = (int)(e / rows);
+    const bool up = r < nq;
+    const int q = up ? r : r - nq;
+    const double kx = kref + 2.0 * PI * (qlo + q) / Q.period;
+    const double kn = sqrt(fmax(Q.omega * Q.omega - kx * kx, 0.0));
+    const double ky = up ? kn : -kn;
+    double sn, cs;
+    sincos(-(kx * Q.x[j] + ky * Q.y[j]), &sn, &cs);
+    const cplx f = up ? mkc(0.0, -(kx * Q.nx[j] + kn * Q.ny[j]) - Q.omega) : mkc(0.0, (-kx * Q.nx[j] + kn * Q.ny[j]) - Q.omega);
+    E[e] = cscale(cmul(mkc(cs, sn), f), Q.w[j]);
+  }
+}
+
+// out slot s of angle a (a < nang of one group) = pre(k) * Cg[slot0[a] + s, a] (c_n) and the same from
+// row nq + slot0[a] + s (d_n), pre = i e^{i k y0} / (2 d k); slots >= nmodes[a] are zero.
+__global__ __launch_bounds__(NT) void k_bragg_gather(QPGeo Q, double kref, int qlo, int nq, const int* __restrict__ slot0,
+                                                     const int* __restrict__ nmodes, int maxmodes, int nang,
+                                                     const cplx* __restrict__ Cg, double y0, cplx* __restrict__ out) {
+  const int64_t total = (int64_t)maxmodes * nang;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int sl = (int)(e % maxmodes), a = (int)(e / maxmodes);
+    cplx* oc = out + (size_t)a * 2 * maxmodes;
+    if (sl >= nmodes[a]) {
+      oc[sl] = mkc(0, 0);
+      oc[maxmodes + sl] = mkc(0, 0);
+      continue;
+    }
+    const int q = slot0[a] + sl;
+    const double kx = kref + 2.0 * PI * (qlo + q) / Q.period;
+    const double kn = sqrt(fmax(Q.omega * Q.omega - kx * kx, 0.0));
+    double sn, cs;
+    sincos(kn * y0, &sn, &cs);
+    const cplx pre = cscale(cmul(mkc(0.0, 1.0), mkc(cs, sn)), 1.0 / (2.0 * Q.period * kn));
+    const cplx* col = Cg + (size_t)a * 2 * nq;
+    oc[sl] = cmul(pre, col[q]);
+    oc[maxmodes + sl] = cmul(pre, col[nq + q]);
+  }
+}
+
 // permute columns: dst[:, perm[a]] = src[:, a]
 __global__ __launch_bounds__(NT) void k_permute_cols(int64_t rows, int cols, const int* __restrict__ perm,
                                                      const cplx* __restrict__ src, int64_t lds, cplx* __restrict__ dst,
@@ -356,6 +403,18 @@ hipError_t launch_bragg(const QPGeo& q, const double* kappa, const int* nlo, con
                         const cplx* eta, int64_t ldeta, double y0, cplx* out, hipStream_t s) {
   if (nang == 0) return hipSuccess;
   hipLaunchKernelGGL(k_bragg, dim3(maxmodes, nang), dim3(NT), 0, s, q, kappa, nlo, nmodes, maxmodes, eta, ldeta, y0, out);
+  return hipGetLastError();
+}
+hipError_t launch_bragg_basis(const QPGeo& q, double kref, int qlo, int nq, cplx* E, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bragg_basis, dim3(grid_for((int64_t)2 * nq * q.N)), dim3(NT), 0, s, q, kref, qlo, nq, E);
+  return hipGetLastError();
+}
+hipError_t launch_bragg_gather(const QPGeo& q, double kref, int qlo, int nq, const int* slot0, const int* nmodes, int maxmodes,
+                               int nang, const cplx* Cg, double y0, cplx* out, hipStream_t s) {
+  if (nang == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bragg_gather, dim3(grid_for((int64_t)maxmodes * nang)), dim3(NT), 0, s, q, kref, qlo, nq, slot0, nmodes,
+                     maxmodes, nang, Cg, y0, out);
   return hipGetLastError();
 }
 hipError_t launch_permute_cols(int64_t rows, int cols, const int* perm, const cplx* src, int64_t lds, cplx* dst, int64_t ldd,

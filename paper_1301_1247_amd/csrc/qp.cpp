@@ -686,7 +686,34 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   // Bragg amplitudes
   {
     ProfScope ps("bragg", st, 0.0, 0.0);
-    CK(launch_bragg(Q, dkap, dnlo, dnm, maxm, nang, eta, N, pl.y0, brg, st));
+    // groups of >= 4 angles share one basis of diffraction orders (a GEMM); smaller ones sum directly
+    for (int g = 0; g < ng; ++g) {
+      const int q0 = goff[g], cnt = gcnt[g];
+      if (cnt < 4) {
+        CK(launch_bragg(Q, dkap + q0, dnlo + q0, dnm + q0, maxm, cnt, eta + (size_t)q0 * N, N, pl.y0,
+                        brg + (size_t)q0 * 2 * maxm, st));
+        continue;
+      }
+      const double kref = kx[q0];
+      std::vector<int> slot0(cnt);
+      int qlo = 1 << 30, qhi = -(1 << 30);
+      for (int a = 0; a < cnt; ++a) {
+        const int mshift = (int)std::llround((kx[q0 + a] - kref) * period / (2 * M_PI));
+        slot0[a] = mshift + nlo[q0 + a];
+        qlo = std::min(qlo, slot0[a]);
+        qhi = std::max(qhi, slot0[a] + nm[q0 + a] - 1);
+      }
+      for (int a = 0; a < cnt; ++a) slot0[a] -= qlo;
+      const int nq = qhi - qlo + 1;
+      CK(h->work.reserve(sizeof(cplx) * ((size_t)2 * nq * N + (size_t)2 * nq * cnt) + sizeof(int) * cnt + 512));
+      cplx* E = h->work.as<cplx>();
+      cplx* Cg = E + (size_t)2 * nq * N;
+      int* dslot = (int*)(Cg + (size_t)2 * nq * cnt);
+      CK(hipMemcpyAsync(dslot, slot0.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, st));
+      CK(launch_bragg_basis(Q, kref, qlo, nq, E, st));
+      CR(gemm({gd(E, 2 * nq, 0, eta + (size_t)q0 * N, N, Cg, 2 * nq, 2 * nq, cnt, N, onec, zero)}));
+      CK(launch_bragg_gather(Q, kref, qlo, nq, dslot, dnm + q0, maxm, cnt, Cg, pl.y0, brg + (size_t)q0 * 2 * maxm, st));
+    }
   }
   // outputs in caller order
   CK(launch_permute_cols(N, nang, dperm, eta, N, eta_out, N, st));

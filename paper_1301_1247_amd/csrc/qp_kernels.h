@@ -30,6 +30,10 @@ hipError_t launch_axpby(int64_t rows, int cols, cplx a, const cplx* x, int64_t l
 hipError_t launch_colnorm2(int64_t rows, int cols, const cplx* x, int64_t ldx, double* out, hipStream_t s);
 hipError_t launch_bragg(const QPGeo& q, const double* kappa, const int* nlo, const int* nmodes, int maxmodes, int nang,
                         const cplx* eta, int64_t ldeta, double y0, cplx* out, hipStream_t s);
+// Bragg amplitudes of a group of angles sharing a Bloch phase through one basis matrix and a GEMM
+hipError_t launch_bragg_basis(const QPGeo& q, double kref, int qlo, int nq, cplx* E, hipStream_t s);
+hipError_t launch_bragg_gather(const QPGeo& q, double kref, int qlo, int nq, const int* slot0, const int* nmodes, int maxmodes,
+                               int nang, const cplx* Cg, double y0, cplx* out, hipStream_t s);
 hipError_t launch_permute_cols(int64_t rows, int cols, const int* perm, const cplx* src, int64_t lds, cplx* dst, int64_t ldd,
                                hipStream_t s);
 }  // namespace qps
