@@ -120,6 +120,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-13)
     ap.add_argument("--walls", choices=("compressed", "dense"), default="compressed",
                     help="compressed: wall blocks through the root skeletons (needs the far-field circle)")
+    ap.add_argument("--rank-predictor", choices=("on", "off"), default="on",
+                    help="size each box's sketch from the MLP rank prediction (off: worst case 2n + 8)")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="fp32: complex64 inverse factors as a preconditioner, FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -161,7 +163,7 @@ def main():
     stream = torch.cuda.current_stream()
     nang = len(wl.thetas)
     kw = dict(quad=wl.quad, leaf_size=wl.leaf_size, curvature=t_kap if wl.quad == "kress" else None, device=True,
-              stream=stream.cuda_stream, precision=args.precision)
+              stream=stream.cuda_stream, precision=args.precision, rank_predictor=args.rank_predictor == "on")
     if args.walls == "compressed":
         # far-field circle about the bounding-box centre that stays inside the unit cell's walls
         c0 = 0.5 * (nodes.max(0) + nodes.min(0))
@@ -213,10 +215,11 @@ def main():
                                f"{nang} angles, tol={args.tol:g}, KR6 + proxy compression, {args.precision} factors, "
                                f"{args.walls} walls",
                    "N": wl.N, "omega": wl.omega, "angles": nang, "contour_M": st.contour_M,
-                   "walls": args.walls, "precision": args.precision},
+                   "walls": args.walls, "precision": args.precision, "rank_predictor": args.rank_predictor},
         "build_seconds": float(np.median(builds)),
         "levels": st.levels, "max_rank": st.max_rank, "root_size": st.root_size,
         "refine_iters": st.refine_iters, "refine_residual": st.refine_residual,
+        "rank_fallbacks": st.rank_fallbacks, "sketch_bytes_max": st.sketch_bytes_max,
         "roofline": {"bound": "mfma", "kernel": ("k_zgemm (complex FP64 MFMA GEMM)" if fam == "zgemm"
                                                  else "k_gemm<float> (complex FP32 MFMA GEMM)"),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,

@@ -72,6 +72,13 @@ typedef struct {
   int32_t fp64_top_levels;  /* HBS_FP32_PRECOND only: levels 1..t below the root keep complex128
                                factors (their reduced systems are the worst conditioned), deeper
                                levels complex64; <0 -> 0, 0 -> 3 */
+  int32_t rank_predictor;   /* 1: size each box's sketch from the rank predicted by a small MLP
+                               (16 geometric features -> log k) instead of the worst case 2n + 8;
+                               a box whose CPQR rank reaches the sketch size is redone at full size,
+                               so ranks and skeletons stay those of the adaptive CPQR.  0 = off */
+  double rank_scale;        /* factor on the predicted rank (0 -> 1); values < 1 force the fallback */
+  const float* rank_model;  /* host pointer to qps_rank_model_size() floats (layout of qps_mlp_forward);
+                               NULL -> the library's built-in model */
 } hbs_opts;
 
 typedef struct {
@@ -109,6 +116,9 @@ typedef struct {
   double refine_residual;   /* relative residual after the last qp_solve */
   int32_t contour_M;        /* contour size of the last qp_solve */
   int32_t walls_compressed; /* 1 if the last qp_solve took B and C through the root skeletons */
+  int32_t rank_fallbacks;   /* boxes whose predicted sketch was too short (rank_predictor) */
+  int64_t sketch_bytes_max; /* largest per-level sketch buffer of the build */
+  double cpqr_work;         /* sum over boxes of sketch rows x n x k (CPQR cost measure) */
 } hbs_stats_t;
 
 void hbs_opts_init(hbs_opts* o);
@@ -171,6 +181,32 @@ const char* hbs_last_error(void);             /* thread-local; "" if none */
  * returns the cached blocks of the current device to HIP; qps_pool_cached_bytes reports them. */
 int qps_pool_release(void);
 int64_t qps_pool_cached_bytes(void);
+
+/* ------------------------------------------------------------- rank predictor -------
+ * A 16-64-64-1 tanh MLP in FP32 predicting log(rank) of a box from 16 geometric features.
+ * Parameter vector (qps_rank_model_size() floats): mu[16], sd[16] (input normalisation
+ * (x - mu) / sd), W1[64][16], b1[64], W2[64][64], b2[64], W3[64], b3.  The features of every box
+ * of a built handle, with the CPQR ranks as targets, are the training data.  All arrays are host
+ * or device pointers by ptr_mode; x is n x 16 row-major. */
+int32_t qps_rank_model_size(void);
+/* copies the built-in model into out (qps_rank_model_size() floats); HBS_E_INVALID_ARG if the
+ * library was built without one */
+int qps_rank_model_default(float* out);
+/* features (count x 16, row-major), CPQR ranks, levels and predicted ranks (0 without the
+ * predictor) of the boxes of h, leaves first; host pointers, capacity cap boxes (NULL to query
+ * *count only) */
+int qps_rank_features(const hbs_handle* h, float* feats, int32_t* ranks, int32_t* levels, float* predicted,
+                      int64_t cap, int64_t* count);
+/* y[b] = model(x[b]) (log of the rank) */
+int qps_mlp_forward(const float* params, const float* x, int64_t n, float* y, int32_t ptr_mode);
+/* pinball loss at quantile tau summed over the n samples (r = t - y: tau r if r > 0 else
+ * (tau - 1) r) and its gradient with respect to the parameters (zero for mu, sd) */
+int qps_mlp_grad(const float* params, const float* x, const float* t, int64_t n, float tau, float* grad, float* loss,
+                 int32_t ptr_mode);
+/* steps of full-batch Adam (lr; betas 0.9, 0.999) on the mean pinball loss, params updated in
+ * place (mu, sd kept); loss_hist (steps floats, nullable) receives the mean loss before each step */
+int qps_mlp_train(float* params, const float* x, const float* t, int64_t n, float tau, int32_t steps, float lr,
+                  float* loss_hist, int32_t ptr_mode);
 
 /* ---------------------------------------------------------------- diagnostics ---------
  * Unit-level access to the device kernels, used by the parity tests. */

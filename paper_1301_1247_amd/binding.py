@@ -38,7 +38,8 @@ class HbsOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("quad", C.c_int32), ("compress", C.c_int32), ("leaf_size", C.c_int32),
                 ("proxy_ratio", C.c_double), ("proxy_min", C.c_int32), ("ptr_mode", C.c_int32),
                 ("curvature", C.c_void_p), ("stream", C.c_void_p), ("seed", C.c_uint64),
-                ("far_radius", C.c_double), ("precision", C.c_int32), ("fp64_top_levels", C.c_int32)]
+                ("far_radius", C.c_double), ("precision", C.c_int32), ("fp64_top_levels", C.c_int32),
+                ("rank_predictor", C.c_int32), ("rank_scale", C.c_double), ("rank_model", C.c_void_p)]
 
 
 class QpOpts(C.Structure):
@@ -52,7 +53,8 @@ class HbsStats(C.Structure):
                 ("max_rank", C.c_int32), ("factor_bytes", C.c_int64), ("build_seconds", C.c_double),
                 ("ranks_per_level_max", C.c_int32 * 32), ("ranks_per_level_mean", C.c_double * 32),
                 ("refine_iters", C.c_int32), ("refine_residual", C.c_double), ("contour_M", C.c_int32),
-                ("walls_compressed", C.c_int32)]
+                ("walls_compressed", C.c_int32), ("rank_fallbacks", C.c_int32), ("sketch_bytes_max", C.c_int64),
+                ("cpqr_work", C.c_double)]
 
 
 _P = C.c_void_p
@@ -77,6 +79,12 @@ _sig = {
     "qps_zinv": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32]),
     "qps_cgemm": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "qps_cinv": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32]),
+    "qps_rank_model_size": (C.c_int32, []),
+    "qps_rank_model_default": (C.c_int, [_P]),
+    "qps_rank_features": (C.c_int, [_P, _P, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
+    "qps_mlp_forward": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32]),
+    "qps_mlp_grad": (C.c_int, [_P, _P, _P, C.c_int64, C.c_float, _P, _P, C.c_int32]),
+    "qps_mlp_train": (C.c_int, [_P, _P, _P, C.c_int64, C.c_float, C.c_int32, C.c_float, _P, C.c_int32]),
     "qps_pool_release": (C.c_int, []),
     "qps_pool_cached_bytes": (C.c_int64, []),
     "qps_profile_enable": (C.c_int, [C.c_int32]),
@@ -137,7 +145,8 @@ class Handle:
 
     def __init__(self, nodes, weights, normals, omega, tol, quad="kr6", compress=None, leaf_size=64,
                  curvature=None, device=False, stream=None, proxy_ratio=2.0, proxy_min=64, seed=0x5EED1301,
-                 far_radius=0.0, precision="fp64", fp64_top_levels=0):
+                 far_radius=0.0, precision="fp64", fp64_top_levels=0, rank_predictor=False, rank_scale=1.0,
+                 rank_model=None):
         if compress is None:
             compress = "exact" if quad == "kress" else "proxy"
         self.device = bool(device)
@@ -161,7 +170,12 @@ class Handle:
                      proxy_ratio=float(proxy_ratio), proxy_min=int(proxy_min),
                      ptr_mode=PTR_DEVICE if self.device else PTR_HOST,
                      curvature=_ptr(curvature), stream=st, seed=int(seed), far_radius=float(far_radius),
-                     precision={"fp64": 0, "fp32": 1}[precision], fp64_top_levels=int(fp64_top_levels))
+                     precision={"fp64": 0, "fp32": 1}[precision], fp64_top_levels=int(fp64_top_levels),
+                     rank_predictor=1 if rank_predictor else 0, rank_scale=float(rank_scale))
+        if rank_model is not None:
+            rank_model = np.ascontiguousarray(rank_model, dtype=np.float32)
+            o.rank_model = rank_model.ctypes.data
+        self._model = rank_model
         h = C.c_void_p()
         _check(_lib.hbs_build(_ptr(nodes), _ptr(weights), _ptr(normals), N, float(omega), float(tol), C.byref(o),
                               C.byref(h)))
@@ -245,6 +259,18 @@ class Handle:
         _check(_lib.hbs_stats(self._h, C.byref(s)))
         return s
 
+    def rank_features(self):
+        """(features n x 16, CPQR ranks, levels, predicted ranks) of every box, leaves first."""
+        cnt = C.c_int64()
+        _check(_lib.qps_rank_features(self._h, None, None, None, None, 0, C.byref(cnt)))
+        n = cnt.value
+        f = np.empty((n, 16), dtype=np.float32)
+        k = np.empty(n, dtype=np.int32)
+        lv = np.empty(n, dtype=np.int32)
+        pr = np.empty(n, dtype=np.float32)
+        _check(_lib.qps_rank_features(self._h, _ptr(f), _ptr(k), _ptr(lv), _ptr(pr), n, C.byref(cnt)))
+        return f, k, lv, pr
+
     def matrix_entries(self, rows, cols):
         rows = np.ascontiguousarray(rows, dtype=np.int32)
         cols = np.ascontiguousarray(cols, dtype=np.int32)
@@ -294,6 +320,45 @@ def zinv(A, precision="fp64"):
     Af = np.array(np.transpose(A, (0, 2, 1)), order="C", copy=True)
     _check(fn(_ptr(Af), n, nb, PTR_HOST))
     return np.transpose(Af, (0, 2, 1))
+
+
+def rank_model_size():
+    return int(_lib.qps_rank_model_size())
+
+
+def rank_model_default():
+    out = np.empty(rank_model_size(), dtype=np.float32)
+    _check(_lib.qps_rank_model_default(_ptr(out)))
+    return out
+
+
+def mlp_forward(params, x):
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.empty(x.shape[0], dtype=np.float32)
+    _check(_lib.qps_mlp_forward(_ptr(params), _ptr(x), x.shape[0], _ptr(y), PTR_HOST))
+    return y
+
+
+def mlp_grad(params, x, t, tau=0.9):
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    g = np.empty_like(params)
+    loss = np.zeros(1, dtype=np.float32)
+    _check(_lib.qps_mlp_grad(_ptr(params), _ptr(x), _ptr(t), x.shape[0], float(tau), _ptr(g), _ptr(loss), PTR_HOST))
+    return g, float(loss[0])
+
+
+def mlp_train(params, x, t, tau=0.9, steps=1000, lr=1e-3):
+    """Adam on the mean pinball loss; returns (new params, per-step mean loss)."""
+    p = np.array(params, dtype=np.float32, copy=True)
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    hist = np.zeros(max(1, steps), dtype=np.float32)
+    _check(_lib.qps_mlp_train(_ptr(p), _ptr(x), _ptr(t), x.shape[0], float(tau), int(steps), float(lr), _ptr(hist),
+                              PTR_HOST))
+    return p, hist[:steps]
 
 
 def pool_release():

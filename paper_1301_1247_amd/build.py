@@ -12,7 +12,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqpscatter.so")
 
-SOURCES = ["kernels_build.hip", "gemm.hip", "kernels_qp.hip", "runtime.cpp", "hbs.cpp", "qp.cpp", "capi.cpp"]
+SOURCES = ["kernels_build.hip", "gemm.hip", "kernels_qp.hip", "kernels_mlp.hip", "runtime.cpp", "hbs.cpp", "qp.cpp",
+           "capi.cpp"]
+MODEL = os.path.join(HERE, "rank_mlp_default.json")
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -28,8 +30,27 @@ def _tables():
             f.write(out)
 
 
+def _model():
+    """Embed the trained rank-predictor parameters (rank_mlp_default.json) as a C array."""
+    inc = os.path.join(CSRC, "rank_mlp_default.inc")
+    if os.path.exists(MODEL):
+        import json
+        with open(MODEL) as f:
+            params = json.load(f)["params"]
+        body = ",\n".join(", ".join(f"{float(v):.9e}f" for v in params[i:i + 8]) for i in range(0, len(params), 8))
+        text = (f"static const float kRankModelDefault[] = {{\n{body}\n}};\n"
+                f"static const int kRankModelDefaultN = {len(params)};\n")
+    else:
+        text = "static const float kRankModelDefault[1] = {0.0f};\nstatic const int kRankModelDefaultN = 0;\n"
+    old = open(inc).read() if os.path.exists(inc) else None
+    if old != text:
+        with open(inc, "w") as f:
+            f.write(text)
+
+
 def build(verbose: bool = False) -> str:
     _tables()
+    _model()
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     srcs = []
     for s in SOURCES:

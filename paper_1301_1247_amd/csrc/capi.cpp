@@ -1,6 +1,7 @@
 // C ABI of the library (include/qpscatter.h): validation, staging, handle lifecycle.
 #include "hbs.h"
 #include "qp_kernels.h"
+#include "mlp.h"
 
 #include <algorithm>
 #include <cmath>
@@ -9,6 +10,8 @@
 #include <vector>
 
 namespace qps {
+// built-in rank-predictor parameters (generated from the trained model file by the build)
+#include "rank_mlp_default.inc"
 const char* last_error();
 void clear_error();
 void profile_enable(bool on);
@@ -167,6 +170,12 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
   if (o.compress != HBS_COMPRESS_PROXY && o.compress != HBS_COMPRESS_EXACT) { set_error("hbs_build: unknown compression"); return HBS_E_INVALID_ARG; }
   if (o.ptr_mode != HBS_PTR_HOST && o.ptr_mode != HBS_PTR_DEVICE) { set_error("hbs_build: unknown ptr_mode"); return HBS_E_INVALID_ARG; }
   if (o.precision != HBS_FP64 && o.precision != HBS_FP32_PRECOND) { set_error("hbs_build: unknown precision"); return HBS_E_INVALID_ARG; }
+  if (o.rank_predictor != 0 && o.rank_predictor != 1) { set_error("hbs_build: rank_predictor must be 0 or 1"); return HBS_E_INVALID_ARG; }
+  if (o.rank_scale < 0 || !std::isfinite(o.rank_scale)) { set_error("hbs_build: rank_scale must be >= 0"); return HBS_E_INVALID_ARG; }
+  if (o.rank_predictor && !o.rank_model && kRankModelDefaultN != MLP_NPARAM) {
+    set_error("hbs_build: the library has no built-in rank model; pass hbs_opts.rank_model");
+    return HBS_E_INVALID_ARG;
+  }
   if (o.quad == HBS_QUAD_KR6 && N < 13) { set_error("hbs_build: KR6 needs N >= 13"); return HBS_E_INVALID_ARG; }
   if (o.quad == HBS_QUAD_KRESS) {
     if (N % 2) { set_error("hbs_build: Kress quadrature needs even N"); return HBS_E_INVALID_ARG; }
@@ -235,6 +244,12 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
       return fail(HBS_E_DEVICE);
     }
     G.kressR = h->dkressR.as<double>();
+  }
+  if (o.rank_predictor) {
+    const float* src = o.rank_model ? o.rank_model : kRankModelDefault;
+    h->rank_model.assign(src, src + MLP_NPARAM);
+    for (float v : h->rank_model)
+      if (!std::isfinite(v)) { set_error("hbs_build: non-finite rank model parameter"); return fail(HBS_E_NONFINITE); }
   }
   int rc = qps::build(h);
   if (rc != HBS_OK) return fail(rc);
@@ -517,6 +532,113 @@ int qps_cgemm(const float* A, const float* B, float* C, int32_t m, int32_t n, in
 }
 int qps_zinv(double* A, int32_t n, int32_t nbatch, int32_t ptr_mode) { return inv_diag<double>("qps_zinv", A, n, nbatch, ptr_mode); }
 int qps_cinv(float* A, int32_t n, int32_t nbatch, int32_t ptr_mode) { return inv_diag<float>("qps_cinv", A, n, nbatch, ptr_mode); }
+
+int32_t qps_rank_model_size(void) { return MLP_NPARAM; }
+
+int qps_rank_model_default(float* out) {
+  clear_error();
+  if (!out) { set_error("qps_rank_model_default: NULL"); return HBS_E_INVALID_ARG; }
+  if (kRankModelDefaultN != MLP_NPARAM) { set_error("qps_rank_model_default: no built-in model"); return HBS_E_INVALID_ARG; }
+  std::memcpy(out, kRankModelDefault, sizeof(float) * MLP_NPARAM);
+  return HBS_OK;
+}
+
+int qps_rank_features(const hbs_handle* h, float* feats, int32_t* ranks, int32_t* levels, float* predicted, int64_t cap,
+                      int64_t* count) {
+  clear_error();
+  if (!h || !count) { set_error("qps_rank_features: NULL"); return HBS_E_INVALID_ARG; }
+  const int64_t nbox = (int64_t)h->feat_rank.size();
+  *count = nbox;
+  if (!feats && !ranks && !levels && !predicted) return HBS_OK;
+  if (cap < nbox) { set_error("qps_rank_features: capacity too small"); return HBS_E_INVALID_ARG; }
+  if (feats) std::memcpy(feats, h->feat.data(), sizeof(float) * MLP_IN * nbox);
+  for (int64_t b = 0; b < nbox; ++b) {
+    if (ranks) ranks[b] = h->feat_rank[b];
+    if (levels) levels[b] = h->feat_level[b];
+    if (predicted) predicted[b] = h->feat_pred[b];
+  }
+  return HBS_OK;
+}
+
+namespace {
+// stage n floats of caller memory on the device (host mode) or borrow them (device mode)
+struct FStage {
+  DevBuf buf;
+  float* p = nullptr;
+  hipError_t in(const float* src, size_t n, int mode) {
+    if (mode == HBS_PTR_DEVICE) { p = const_cast<float*>(src); return hipSuccess; }
+    hipError_t e = buf.reserve(sizeof(float) * std::max<size_t>(1, n));
+    if (e != hipSuccess) return e;
+    p = buf.as<float>();
+    return src && n ? hipMemcpy(p, src, sizeof(float) * n, hipMemcpyHostToDevice) : hipSuccess;
+  }
+  hipError_t out(float* dst, size_t n, int mode) {
+    if (mode == HBS_PTR_DEVICE || !dst || !n) return hipSuccess;
+    return hipMemcpy(dst, p, sizeof(float) * n, hipMemcpyDeviceToHost);
+  }
+};
+bool mlp_args_ok(const char* name, const void* params, const void* x, int64_t n, int32_t ptr_mode) {
+  if (!params || !x || n <= 0 || (ptr_mode != HBS_PTR_HOST && ptr_mode != HBS_PTR_DEVICE)) {
+    set_error(std::string(name) + ": bad arguments");
+    return false;
+  }
+  return true;
+}
+}  // namespace
+
+int qps_mlp_forward(const float* params, const float* x, int64_t n, float* y, int32_t ptr_mode) {
+  clear_error();
+  if (!mlp_args_ok("qps_mlp_forward", params, x, n, ptr_mode) || !y) return HBS_E_INVALID_ARG;
+  FStage P, X, Y;
+  CKD(P.in(params, MLP_NPARAM, ptr_mode));
+  CKD(X.in(x, (size_t)n * MLP_IN, ptr_mode));
+  if (ptr_mode == HBS_PTR_DEVICE) Y.p = y; else CKD(Y.in(nullptr, n, HBS_PTR_HOST));
+  CKD(mlp_forward(P.p, X.p, n, Y.p, nullptr));
+  CKD(hipDeviceSynchronize());
+  CKD(Y.out(y, n, ptr_mode));
+  return HBS_OK;
+}
+
+int qps_mlp_grad(const float* params, const float* x, const float* t, int64_t n, float tau, float* grad, float* loss,
+                 int32_t ptr_mode) {
+  clear_error();
+  if (!mlp_args_ok("qps_mlp_grad", params, x, n, ptr_mode) || !t || !grad || !loss) return HBS_E_INVALID_ARG;
+  if (!(tau > 0.f && tau < 1.f)) { set_error("qps_mlp_grad: tau must lie in (0, 1)"); return HBS_E_INVALID_ARG; }
+  FStage P, X, T, G, Lo;
+  DevBuf work;
+  CKD(P.in(params, MLP_NPARAM, ptr_mode));
+  CKD(X.in(x, (size_t)n * MLP_IN, ptr_mode));
+  CKD(T.in(t, n, ptr_mode));
+  if (ptr_mode == HBS_PTR_DEVICE) { G.p = grad; Lo.p = loss; }
+  else { CKD(G.in(nullptr, MLP_NPARAM, HBS_PTR_HOST)); CKD(Lo.in(nullptr, 1, HBS_PTR_HOST)); }
+  CKD(mlp_grad(work, P.p, X.p, T.p, n, tau, G.p, Lo.p, nullptr));
+  CKD(hipDeviceSynchronize());
+  CKD(G.out(grad, MLP_NPARAM, ptr_mode));
+  CKD(Lo.out(loss, 1, ptr_mode));
+  return HBS_OK;
+}
+
+int qps_mlp_train(float* params, const float* x, const float* t, int64_t n, float tau, int32_t steps, float lr, float* loss_hist,
+                  int32_t ptr_mode) {
+  clear_error();
+  if (!mlp_args_ok("qps_mlp_train", params, x, n, ptr_mode) || !t || steps < 0 || !(lr > 0.f)) return HBS_E_INVALID_ARG;
+  if (!(tau > 0.f && tau < 1.f)) { set_error("qps_mlp_train: tau must lie in (0, 1)"); return HBS_E_INVALID_ARG; }
+  FStage P, X, T, Hh;
+  DevBuf work;
+  CKD(P.in(params, MLP_NPARAM, ptr_mode));
+  CKD(X.in(x, (size_t)n * MLP_IN, ptr_mode));
+  CKD(T.in(t, n, ptr_mode));
+  float* hist = nullptr;
+  if (loss_hist) {
+    if (ptr_mode == HBS_PTR_DEVICE) hist = loss_hist;
+    else { CKD(Hh.in(nullptr, std::max(1, steps), HBS_PTR_HOST)); hist = Hh.p; }
+  }
+  CKD(mlp_train(work, P.p, X.p, T.p, n, tau, steps, lr, hist, nullptr));
+  CKD(hipDeviceSynchronize());
+  CKD(P.out(params, MLP_NPARAM, ptr_mode));
+  if (loss_hist) CKD(Hh.out(loss_hist, steps, ptr_mode));
+  return HBS_OK;
+}
 
 int qps_pool_release(void) {
   clear_error();

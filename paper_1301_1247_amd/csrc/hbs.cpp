@@ -14,6 +14,7 @@
 // The forward operator of Eq. 4.8 uses the same skeletons: P, the leaf blocks A(I, I), the
 // sibling couplings and the root coupling.
 #include "hbs.h"
+#include "mlp.h"
 
 #include <algorithm>
 #include <chrono>
@@ -130,12 +131,12 @@ int build(hbs_handle* h) {
     DevBuf dlo, dhi, dcirc;
     CK(dlo.reserve(sizeof(int) * nbox));
     CK(dhi.reserve(sizeof(int) * nbox));
-    CK(dcirc.reserve(sizeof(double) * 3 * nbox));
+    CK(dcirc.reserve(sizeof(double) * 7 * nbox));
     CK(hipMemcpyAsync(dlo.p, blo.data(), sizeof(int) * nbox, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(dhi.p, bhi.data(), sizeof(int) * nbox, hipMemcpyHostToDevice, st));
     CK(launch_box_circles(h->geo.x, h->geo.y, dlo.as<int>(), dhi.as<int>(), nbox, dcirc.as<double>(), st));
-    std::vector<double> circ(3 * (size_t)nbox);
-    CK(hipMemcpyAsync(circ.data(), dcirc.p, sizeof(double) * 3 * nbox, hipMemcpyDeviceToHost, st));
+    std::vector<double> circ(7 * (size_t)nbox);
+    CK(hipMemcpyAsync(circ.data(), dcirc.p, sizeof(double) * 7 * nbox, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     size_t q = 0;
     for (int l = 1; l <= L; ++l) {
@@ -143,15 +144,67 @@ int build(hbs_handle* h) {
       V.cx.resize(V.nb);
       V.cy.resize(V.nb);
       V.rad.resize(V.nb);
+      V.aspect.resize(V.nb);
       for (int b = 0; b < V.nb; ++b, ++q) {
-        V.cx[b] = circ[3 * q];
-        V.cy[b] = circ[3 * q + 1];
-        V.rad[b] = circ[3 * q + 2];
+        V.cx[b] = circ[7 * q];
+        V.cy[b] = circ[7 * q + 1];
+        V.rad[b] = circ[7 * q + 2];
+        const double wx = circ[7 * q + 4] - circ[7 * q + 3], wy = circ[7 * q + 6] - circ[7 * q + 5];
+        V.aspect[b] = std::max(wx, wy) > 0 ? std::min(wx, wy) / std::max(wx, wy) : 1.0;
       }
     }
   }
 
-  DevBuf dnear, wt, zb, kout, tmpY, tmpZt;
+  // geometric features of the boxes for the rank predictor: arc length, curvature (|kappa| at
+  // the nodes, from the curvature array when given, else from the turning of the normals)
+  std::vector<double> arc(N + 1, 0.0), kabs(N);
+  for (int64_t i = 0; i < N; ++i) arc[i + 1] = arc[i] + h->hw[i];
+  for (int64_t i = 0; i < N; ++i) {
+    if (!h->hkap.empty()) {
+      kabs[i] = std::fabs(h->hkap[i]);
+    } else {
+      const int64_t a = (i + N - 1) % N, c = (i + 1) % N;
+      const double cr = h->hnx[a] * h->hny[c] - h->hny[a] * h->hnx[c];
+      const double dt = h->hnx[a] * h->hnx[c] + h->hny[a] * h->hny[c];
+      kabs[i] = std::fabs(std::atan2(cr, dt)) / (0.5 * h->hw[a] + h->hw[i] + 0.5 * h->hw[c]);
+    }
+  }
+  std::vector<std::vector<double>> kmaxb(L + 1), kmeanb(L + 1);
+  for (int l = L; l >= 1; --l) {
+    Level& V = h->lv[l];
+    kmaxb[l].assign(V.nb, 0.0);
+    kmeanb[l].assign(V.nb, 0.0);
+    for (int b = 0; b < V.nb; ++b) {
+      if (l == L) {
+        double mx = 0, sm = 0;
+        for (int i = V.lo[b]; i < V.hi[b]; ++i) { mx = std::max(mx, kabs[i]); sm += kabs[i]; }
+        kmaxb[l][b] = mx;
+        kmeanb[l][b] = sm / std::max(1, V.hi[b] - V.lo[b]);
+      } else {
+        const Level& C = h->lv[l + 1];
+        const int a = 2 * b, c = 2 * b + 1;
+        const double na = C.hi[a] - C.lo[a], nc = C.hi[c] - C.lo[c];
+        kmaxb[l][b] = std::max(kmaxb[l + 1][a], kmaxb[l + 1][c]);
+        kmeanb[l][b] = (kmeanb[l + 1][a] * na + kmeanb[l + 1][c] * nc) / std::max(1.0, na + nc);
+      }
+    }
+  }
+  const bool predict = h->opts.rank_predictor != 0;
+  const double rscale = h->opts.rank_scale > 0 ? h->opts.rank_scale : 1.0;
+  DevBuf dmodel, dfeat, dpred;
+  if (predict) {
+    CK(dmodel.reserve(sizeof(float) * MLP_NPARAM));
+    CK(hipMemcpyAsync(dmodel.p, h->rank_model.data(), sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, st));
+  }
+  h->feat.clear();
+  h->feat_rank.clear();
+  h->feat_level.clear();
+  h->feat_pred.clear();
+  h->stats.rank_fallbacks = 0;
+  h->stats.sketch_bytes_max = 0;
+  h->stats.cpqr_work = 0.0;
+
+  DevBuf dnear, wt, zb, zb2, kout, tmpY, tmpZt;
   DevBuf& arena = h->arena;
   h->factor_bytes = 0;
   std::memset(h->stats.ranks_per_level_max, 0, sizeof(h->stats.ranks_per_level_max));
@@ -254,9 +307,11 @@ int build(hbs_handle* h) {
     if (!exact)
       for (int c = 0; c < nb; ++c) grid[key(V.cx[c], V.cy[c])].push_back(c);
     std::vector<int> cand;
+    std::vector<double> mind(nb);
     for (int b = 0; b < nb; ++b) {
       const double Rp = ratio * V.rad[b];
       int cnt = 0;
+      double md = std::max(0.0, Rp - V.rad[b]);
       const int64_t total_other = V.ntot - V.n[b];
       cand.clear();
       if (exact) {
@@ -282,8 +337,10 @@ int build(hbs_handle* h) {
         if (nr) {
           for (int i = 0; i < V.n[c]; ++i) hnear.push_back(V.hact[V.aoff[c] + i]);
           cnt += V.n[c];
+          if (!adj) md = std::min(md, std::max(0.0, std::sqrt(ex * ex + ey * ey) - V.rad[c] - V.rad[b]));
         }
       }
+      mind[b] = md;
       nnear[b] = cnt;
       const bool full = (cnt == total_other);
       np[b] = full ? 0 : std::max(pmin, (int)std::ceil(1.5 * om * Rp) + 50);
@@ -295,8 +352,54 @@ int build(hbs_handle* h) {
       s[b] = (m[b] > 2 * V.n[b] + 8) ? 2 * V.n[b] + 8 : m[b];
       noff[b + 1] = noff[b] + cnt;
       woff[b + 1] = woff[b] + (int64_t)m[b] * V.n[b];
-      zoff[b + 1] = zoff[b] + ((s[b] < m[b]) ? (int64_t)s[b] * V.n[b] : 0);
     }
+    // features of every box (kept on the handle: training data for the predictor)
+    const std::vector<int> sfull = s;
+    std::vector<float> F((size_t)nb * MLP_IN);
+    for (int b = 0; b < nb; ++b) {
+      const double Rp = ratio * V.rad[b];
+      const double len = arc[V.hi[b]] - arc[V.lo[b]];
+      const double chx = h->hx[V.hi[b] - 1] - h->hx[V.lo[b]], chy = h->hy[V.hi[b] - 1] - h->hy[V.lo[b]];
+      int ksum = 0;
+      if (l < L) ksum = h->lv[l + 1].k[2 * b] + h->lv[l + 1].k[2 * b + 1];
+      float* f = &F[(size_t)b * MLP_IN];
+      f[0] = (float)std::log2((double)V.n[b]);
+      f[1] = (float)l / (float)L;
+      f[2] = (float)(om * len);
+      f[3] = (float)(om * V.rad[b]);
+      f[4] = (float)(om * Rp);
+      f[5] = (float)nnear[b] / (float)V.n[b];
+      f[6] = (float)np[b] / 100.f;
+      f[7] = (float)std::log10(h->tol);
+      f[8] = (float)(kmaxb[l][b] * V.rad[b]);
+      f[9] = (float)(kmeanb[l][b] * V.rad[b]);
+      f[10] = (float)(om * mind[b]);
+      f[11] = (float)(om / 100.0);
+      f[12] = (float)(len > 0 ? std::sqrt(chx * chx + chy * chy) / len : 1.0);
+      f[13] = (float)V.aspect[b];
+      f[14] = (float)(npf[b] > 0 ? om * Rfar : 0.0);
+      f[15] = (float)std::log2(1.0 + ksum);
+    }
+    h->feat.insert(h->feat.end(), F.begin(), F.end());
+    std::vector<float> kpred;
+    if (predict) {
+      // predicted rank -> sketch rows 1.25 k^ + 16 (at least 32, at most the full 2n + 8)
+      CK(dfeat.reserve(sizeof(float) * F.size()));
+      CK(dpred.reserve(sizeof(float) * nb));
+      CK(hipMemcpyAsync(dfeat.p, F.data(), sizeof(float) * F.size(), hipMemcpyHostToDevice, st));
+      CK(mlp_forward(dmodel.as<float>(), dfeat.as<float>(), nb, dpred.as<float>(), st));
+      kpred.resize(nb);
+      CK(hipMemcpyAsync(kpred.data(), dpred.p, sizeof(float) * nb, hipMemcpyDeviceToHost, st));
+      CK(hipStreamSynchronize(st));
+      for (int b = 0; b < nb; ++b) {
+        const double kp = std::exp(std::min(20.0, (double)kpred[b])) * rscale;
+        kpred[b] = (float)kp;
+        const int sp = (int)std::max(32.0, std::ceil(1.25 * kp) + 16.0);
+        s[b] = std::min(sfull[b], sp);
+      }
+    }
+    for (int b = 0; b < nb; ++b) zoff[b + 1] = zoff[b] + ((s[b] < m[b]) ? (int64_t)s[b] * V.n[b] : 0);
+    h->stats.sketch_bytes_max = std::max<int64_t>(h->stats.sketch_bytes_max, (int64_t)sizeof(cplx) * zoff[nb]);
     CK(dnear.reserve(sizeof(int) * std::max<int64_t>(1, noff[nb])));
     if (noff[nb] > 0)
       CK(hipMemcpyAsync(dnear.p, hnear.data(), sizeof(int) * noff[nb], hipMemcpyHostToDevice, st));
@@ -375,8 +478,58 @@ int build(hbs_handle* h) {
     }
     V.k.assign(nb, 0);
     CK(hipMemcpyAsync(V.k.data(), kout.p, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (predict) {
+      // a sketch that was too short for the box's rank reveals no gap: redo it at full size
+      std::vector<int> redo;
+      for (int b = 0; b < nb; ++b)
+        if (s[b] < sfull[b] && V.k[b] >= s[b] - 8) redo.push_back(b);
+      if (!redo.empty()) {
+        h->stats.rank_fallbacks += (int)redo.size();
+        std::vector<int64_t> z2off(redo.size() + 1, 0);
+        for (size_t r = 0; r < redo.size(); ++r) {
+          const int b = redo[r];
+          s[b] = sfull[b];
+          z2off[r + 1] = z2off[r] + ((s[b] < m[b]) ? (int64_t)s[b] * V.n[b] : 0);
+        }
+        CK(zb2.reserve(sizeof(cplx) * std::max<int64_t>(1, z2off.back())));
+        std::vector<SketchDesc> sd;
+        int maxs = 0, maxn = 0;
+        for (size_t r = 0; r < redo.size(); ++r) {
+          const int b = redo[r];
+          if (s[b] >= m[b]) continue;
+          sd.push_back({dwt + woff[b], zb2.as<cplx>() + z2off[r], m[b], V.n[b], s[b], b + (l << 24)});
+          maxs = std::max(maxs, s[b]);
+          maxn = std::max(maxn, V.n[b]);
+        }
+        if (!sd.empty()) {
+          CK(up_sync(arena, sd, st));
+          CK(launch_sketch(arena.as<SketchDesc>(), (int)sd.size(), maxs, maxn, h->opts.seed, st));
+        }
+        std::vector<CpqrDesc> qd;
+        for (size_t r = 0; r < redo.size(); ++r) {
+          const int b = redo[r];
+          zptr[b] = (s[b] < m[b]) ? zb2.as<cplx>() + z2off[r] : dwt + woff[b];
+          qd.push_back({zptr[b], dperm.as<int>() + V.aoff[b], s[b], V.n[b]});
+        }
+        CK(up_sync(arena, qd, st));
+        CK(kout.reserve(sizeof(int) * nb + sizeof(int) * redo.size()));
+        int* k2 = kout.as<int>() + nb;
+        CK(launch_cpqr(arena.as<CpqrDesc>(), (int)qd.size(), h->tol, k2, st));
+        std::vector<int> hk2(redo.size());
+        CK(hipMemcpyAsync(hk2.data(), k2, sizeof(int) * redo.size(), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        for (size_t r = 0; r < redo.size(); ++r) V.k[redo[r]] = hk2[r];
+      }
+    }
     CK(hipMemcpyAsync(hperm.data(), dperm.p, sizeof(int) * V.ntot, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
+    for (int b = 0; b < nb; ++b) {
+      h->feat_rank.push_back(V.k[b]);
+      h->feat_level.push_back(l);
+      h->feat_pred.push_back(predict ? kpred[b] : 0.f);
+      h->stats.cpqr_work += (double)s[b] * V.n[b] * V.k[b];
+    }
     V.soff.assign(nb + 1, 0);
     for (int b = 0; b < nb; ++b) V.soff[b + 1] = V.soff[b] + V.k[b];
     V.ktot = V.soff[nb];

@@ -19,7 +19,7 @@ struct Level {
   DevBuf E32, Ft32, G32;            // complex64 inverse factors (FP32-preconditioner mode)
   std::vector<int64_t> oP, oE, oFt, oG, oDh;
   // bounding circles of the boxes' original points
-  std::vector<double> cx, cy, rad;
+  std::vector<double> cx, cy, rad, aspect;
   std::vector<int> lo, hi;          // original index range
 };
 
@@ -38,6 +38,10 @@ struct hbs_handle {
   int nroot = 0;
   qps::DevBuf Rinv, Rfwd;
   int fp64_top = 0;               // levels 1..fp64_top hold complex128 inverse factors, deeper ones complex64
+  std::vector<float> rank_model;  // rank-predictor parameters (when hbs_opts.rank_predictor)
+  // per box of every level (leaves first): predictor features, CPQR rank, level, predicted rank
+  std::vector<float> feat, feat_pred;
+  std::vector<int> feat_rank, feat_level;
   qps::DevBuf arena, arena32, work, scratch, splitws, qp32;
   qps::DevBuf ab_up, ab_x0, ab_x1, ab_root;          // apply workspaces
   qps::DevBuf ab_in32, ab_up32, ab_x32a, ab_x32b;    // complex64 stage of a mixed-precision inverse apply

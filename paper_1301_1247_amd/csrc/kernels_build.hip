@@ -252,7 +252,8 @@ __global__ __launch_bounds__(NT) void k_copy(const CopyDesc* __restrict__ descs)
 }
 
 // Bounding circle of the nodes lo[b] <= i < hi[b] of every box b: centre = middle of the
-// bounding box, radius = largest distance from it (out = cx, cy, r per box; one workgroup per box).
+// bounding box, radius = largest distance from it (out = cx, cy, r, x0, x1, y0, y1 per box; one
+// workgroup per box).
 __global__ __launch_bounds__(NT) void k_box_circles(const double* __restrict__ x, const double* __restrict__ y,
                                                     const int* __restrict__ lo, const int* __restrict__ hi,
                                                     double* __restrict__ out) {
@@ -284,9 +285,13 @@ __global__ __launch_bounds__(NT) void k_box_circles(const double* __restrict__ x
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int q = 1; q < NT / 64; ++q) r = fmax(r, red[0][q]);
-    out[3 * b] = cx;
-    out[3 * b + 1] = cy;
-    out[3 * b + 2] = r;
+    out[7 * b] = cx;
+    out[7 * b + 1] = cy;
+    out[7 * b + 2] = r;
+    out[7 * b + 3] = x0;
+    out[7 * b + 4] = x1;
+    out[7 * b + 5] = y0;
+    out[7 * b + 6] = y1;
   }
 }
 

@@ -130,6 +130,27 @@ def shared_phase_angles(omega: float, period: float, n_phase: int = 4, per_phase
     return np.array(out)
 
 
+def rank_training_set(n: int = 64, seed: int = 4242):
+    """Seeded obstacles for fitting and checking the rank predictor (64 by default).
+
+    Per obstacle, drawn in this order from ``numpy.random.default_rng(seed)``: K ~ U{4..40}
+    harmonics, roughness cmax ~ U(0.05, 0.3), N log-uniform in [2e3, 5e4] (rounded to a multiple
+    of 64), omega ~ U(10, 80), tol from {1e-10, 1e-12, 1e-13}, a shape seed; the far-field circle
+    is requested for every other obstacle.  Returns a list of dicts (curve, N, omega, tol, far).
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        K = int(rng.integers(4, 41))
+        cmax = float(rng.uniform(0.05, 0.3))
+        N = int(round(math.exp(rng.uniform(math.log(2e3), math.log(5e4))) / 64.0)) * 64
+        omega = float(rng.uniform(10.0, 80.0))
+        tol = float([1e-10, 1e-12, 1e-13][int(rng.integers(0, 3))])
+        shape_seed = int(rng.integers(0, 2 ** 31))
+        out.append({"curve": wavy(shape_seed, K, cmax), "N": N, "omega": omega, "tol": tol, "far": i % 2 == 1})
+    return out
+
+
 @dataclass
 class Workload:
     name: str
