@@ -79,6 +79,11 @@ typedef struct {
   double rank_scale;        /* factor on the predicted rank (0 -> 1); values < 1 force the fallback */
   const float* rank_model;  /* host pointer to qps_rank_model_size() floats (layout of qps_mlp_forward);
                                NULL -> the library's built-in model */
+  int32_t root_level;       /* 1: the root holds the skeletons of the two level-1 boxes (Sec. 4);
+                               2: level 1 is left uncompressed (P = I) and the root holds the
+                               level-2 skeletons; 0 (default): 2 when the rank predictor expects
+                               the level-1 decomposition to keep >= 60% of its points and the root
+                               stays within 1024 points, else 1 */
 } hbs_opts;
 
 typedef struct {
@@ -119,6 +124,7 @@ typedef struct {
   int32_t rank_fallbacks;   /* boxes whose predicted sketch was too short (rank_predictor) */
   int64_t sketch_bytes_max; /* largest per-level sketch buffer of the build */
   double cpqr_work;         /* sum over boxes of sketch rows x n x k (CPQR cost measure) */
+  int32_t root_level;       /* 1 or 2 (see hbs_opts.root_level) */
 } hbs_stats_t;
 
 void hbs_opts_init(hbs_opts* o);

@@ -398,15 +398,33 @@ int build(hbs_handle* h) {
         s[b] = std::min(sfull[b], sp);
       }
     }
+    // The top level is left uncompressed (P = I, root over the level-2 skeletons) when its
+    // interpolative decomposition would keep most points anyway: requested by root_level = 2, or
+    // chosen when the predicted ranks reach 0.6 n and the root stays within 1024 points.
+    bool ident = false;
+    if (l == 1 && L >= 2 && l <= h->fp64_top) {
+      if (h->opts.root_level == 2) {
+        ident = true;
+      } else if (h->opts.root_level == 0 && predict && V.ntot <= 1024) {
+        ident = true;
+        for (int b = 0; b < nb; ++b) ident = ident && kpred[b] >= 0.6 * V.n[b];
+      }
+    }
+    h->top_identity = ident;
+    if (ident)
+      for (int b = 0; b < nb; ++b) s[b] = m[b];  // no sketch
     for (int b = 0; b < nb; ++b) zoff[b + 1] = zoff[b] + ((s[b] < m[b]) ? (int64_t)s[b] * V.n[b] : 0);
     h->stats.sketch_bytes_max = std::max<int64_t>(h->stats.sketch_bytes_max, (int64_t)sizeof(cplx) * zoff[nb]);
+    cplx* dwt = nullptr;
+    cplx* dz = nullptr;
+    if (!ident) {
     CK(dnear.reserve(sizeof(int) * std::max<int64_t>(1, noff[nb])));
     if (noff[nb] > 0)
       CK(hipMemcpyAsync(dnear.p, hnear.data(), sizeof(int) * noff[nb], hipMemcpyHostToDevice, st));
     CK(wt.reserve(sizeof(cplx) * std::max<int64_t>(1, woff[nb])));
     CK(zb.reserve(sizeof(cplx) * std::max<int64_t>(1, zoff[nb])));
-    cplx* dwt = wt.as<cplx>();
-    cplx* dz = zb.as<cplx>();
+    dwt = wt.as<cplx>();
+    dz = zb.as<cplx>();
     const int* dn = dnear.as<int>();
     {
       std::vector<BlockDesc> bd;
@@ -458,13 +476,22 @@ int build(hbs_handle* h) {
         CK(launch_sketch(arena.as<SketchDesc>(), (int)sd.size(), maxs, maxn, h->opts.seed, st));
       }
     }
+    }
     // ---- interpolative decompositions
     std::vector<int> hperm(V.ntot);
     DevBuf dperm;
     CK(dperm.reserve(sizeof(int) * V.ntot));
     CK(kout.reserve(sizeof(int) * nb));
-    std::vector<cplx*> zptr(nb);
-    {
+    std::vector<cplx*> zptr(nb, nullptr);
+    if (ident) {
+      std::vector<int> idp(V.ntot);
+      for (int b = 0; b < nb; ++b)
+        for (int j = 0; j < V.n[b]; ++j) idp[V.aoff[b] + j] = j;
+      std::vector<int> kk(V.n.begin(), V.n.end());
+      CK(hipMemcpyAsync(dperm.p, idp.data(), sizeof(int) * V.ntot, hipMemcpyHostToDevice, st));
+      CK(hipMemcpyAsync(kout.p, kk.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+      CK(hipStreamSynchronize(st));
+    } else {
       std::vector<CpqrDesc> qd;
       double fl = 0;
       for (int b = 0; b < nb; ++b) {
@@ -479,7 +506,7 @@ int build(hbs_handle* h) {
     V.k.assign(nb, 0);
     CK(hipMemcpyAsync(V.k.data(), kout.p, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
-    if (predict) {
+    if (predict && !ident) {
       // a sketch that was too short for the box's rank reveals no gap: redo it at full size
       std::vector<int> redo;
       for (int b = 0; b < nb; ++b)
@@ -528,7 +555,7 @@ int build(hbs_handle* h) {
       h->feat_rank.push_back(V.k[b]);
       h->feat_level.push_back(l);
       h->feat_pred.push_back(predict ? kpred[b] : 0.f);
-      h->stats.cpqr_work += (double)s[b] * V.n[b] * V.k[b];
+      if (!ident) h->stats.cpqr_work += (double)s[b] * V.n[b] * V.k[b];
     }
     V.soff.assign(nb + 1, 0);
     for (int b = 0; b < nb; ++b) V.soff[b + 1] = V.soff[b] + V.k[b];
@@ -647,6 +674,23 @@ int build(hbs_handle* h) {
       CK(launch_cast_f2d(Dh32, V.Dh.as<cplx>(), V.oDh[nb], st));
       CK(hipStreamSynchronize(st));
       V.G.release();  // D itself is not a factor in this mode
+    } else if (ident) {
+      // P = I: the reduced block is D itself, E = F^T = I and G = D^{-1} - D^{-1} = 0
+      CK(hipMemcpyAsync(V.Dh.p, dG, sizeof(cplx) * V.oG[nb], hipMemcpyDeviceToDevice, st));
+      std::vector<CopyDesc> ce, cz;
+      int maxe = 0;
+      for (int b = 0; b < nb; ++b) {
+        const int n = V.n[b];
+        ce.push_back({nullptr, V.E.as<cplx>() + V.oP[b], n, n, n, n});
+        ce.push_back({nullptr, V.Ft.as<cplx>() + V.oP[b], n, n, n, n});
+        cz.push_back({nullptr, dG + V.oG[b], n, n, n, n});
+        maxe = std::max(maxe, n * n);
+      }
+      CK(up_sync(arena, ce, st));
+      CK(launch_eye(arena.as<CopyDesc>(), (int)ce.size(), maxe, st));
+      CK(up_sync(arena, cz, st));
+      CK(launch_copy(arena.as<CopyDesc>(), (int)cz.size(), maxe, st));
+      CK(hipStreamSynchronize(st));
     } else {
       std::vector<InvDesc> iv;
       for (int b = 0; b < nb; ++b) iv.push_back({dG + V.oG[b], V.n[b], V.n[b]});

@@ -38,6 +38,7 @@ struct hbs_handle {
   int nroot = 0;
   qps::DevBuf Rinv, Rfwd;
   int fp64_top = 0;               // levels 1..fp64_top hold complex128 inverse factors, deeper ones complex64
+  bool top_identity = false;      // level 1 left uncompressed (root over the level-2 skeletons)
   std::vector<float> rank_model;  // rank-predictor parameters (when hbs_opts.rank_predictor)
   // per box of every level (leaves first): predictor features, CPQR rank, level, predicted rank
   std::vector<float> feat, feat_pred;

@@ -132,6 +132,7 @@ hipError_t launch_sketch(const SketchDesc* d, int nd, int max_s, int max_n, uint
 hipError_t launch_cpqr(const CpqrDesc* d, int nd, double tol, int* k_out, hipStream_t s);
 hipError_t launch_buildP(const PDesc* d, int nd, int max_elems, hipStream_t s);
 hipError_t launch_copy(const CopyDesc* d, int nd, int max_elems, hipStream_t s);
+hipError_t launch_eye(const CopyDesc* d, int nd, int max_elems, hipStream_t s);  // dst = I (nr x nc)
 hipError_t launch_box_circles(const double* x, const double* y, const int* lo, const int* hi, int nbox, double* out,
                               hipStream_t s);
 hipError_t launch_gather_idx(const int* src, const int* idx, int* dst, int64_t n, hipStream_t s);

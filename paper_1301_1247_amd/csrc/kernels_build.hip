@@ -295,6 +295,16 @@ __global__ __launch_bounds__(NT) void k_box_circles(const double* __restrict__ x
   }
 }
 
+// identity blocks: dst[r + c ldd] = (r == c) for r < nr, c < nc
+__global__ __launch_bounds__(NT) void k_eye(const CopyDesc* __restrict__ descs) {
+  const CopyDesc d = descs[blockIdx.y];
+  const int total = d.nr * d.nc;
+  for (int e = blockIdx.x * NT + threadIdx.x; e < total; e += gridDim.x * NT) {
+    const int r = e % d.nr, c = e / d.nr;
+    d.dst[r + (size_t)c * d.ldd] = mkc(r == c ? 1.0 : 0.0, 0.0);
+  }
+}
+
 __global__ void k_gather_idx(const int* __restrict__ src, const int* __restrict__ idx, int* __restrict__ dst, int64_t n) {
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) dst[e] = src[idx[e]];
 }
@@ -599,6 +609,11 @@ hipError_t launch_copy(const CopyDesc* d, int nd, int max_elems, hipStream_t s) 
   if (nd == 0 || max_elems == 0) return hipSuccess;
   dim3 grid(grid_for(max_elems, 256), nd);
   hipLaunchKernelGGL(k_copy, grid, dim3(NT), 0, s, d);
+  return hipGetLastError();
+}
+hipError_t launch_eye(const CopyDesc* d, int nd, int max_elems, hipStream_t s) {
+  if (nd == 0 || max_elems == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eye, dim3(grid_for(max_elems, 256), nd), dim3(NT), 0, s, d);
   return hipGetLastError();
 }
 hipError_t launch_box_circles(const double* x, const double* y, const int* lo, const int* hi, int nbox, double* out,

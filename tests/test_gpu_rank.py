@@ -92,10 +92,13 @@ def test_predictor_with_oversized_prediction_reproduces_the_worst_case_build(gpu
     d["b3"] = 20.0
     big = rm.pack(d).astype(np.float32)
     h0 = gpu_lib.Handle(nodes, w, nrm, om, 1e-12)
-    h1 = gpu_lib.Handle(nodes, w, nrm, om, 1e-12, rank_predictor=True, rank_model=big)
+    h1 = gpu_lib.Handle(nodes, w, nrm, om, 1e-12, rank_predictor=True, rank_model=big, root_level=1)
     assert np.array_equal(h0.rank_features()[1], h1.rank_features()[1])
     assert h1.stats().rank_fallbacks == 0
     assert h1.stats().sketch_bytes_max == h0.stats().sketch_bytes_max
+    # with the level-1 ranks predicted at n, the automatic choice leaves level 1 uncompressed
+    h2 = gpu_lib.Handle(nodes, w, nrm, om, 1e-12, rank_predictor=True, rank_model=big)
+    assert h2.stats().root_level == 2 and h0.stats().root_level == 1
 
 
 def test_predicted_sketches_keep_the_accuracy(gpu_lib, wavy_case):

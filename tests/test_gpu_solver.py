@@ -236,6 +236,31 @@ def test_qp_wavy_kr6_parity_compressed_walls(gpu_lib, wavy_small, P):
     assert _rel(res_u["eta"], res["eta"]) < 1e-10
 
 
+@pytest.mark.parametrize("P", [0, 1])
+def test_root_over_level2_skeletons(gpu_lib, wavy_small, P):
+    """root_level = 2: level 1 left uncompressed (P = I), the root holds the level-2 skeletons;
+    the compressed inverse, the forward operator and the quasi-periodic solve keep the 1e-10 bar."""
+    c, N, om, disc, A, lu = wavy_small
+    d = 2 * math.pi
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-12, far_radius=_far_walls(nodes, d), root_level=2)
+    h1 = gpu_lib.Handle(nodes, w, nrm, om, 1e-12, far_radius=_far_walls(nodes, d), root_level=1)
+    st, st1 = h.stats(), h1.stats()
+    assert st.root_level == 2 and st1.root_level == 1
+    k, lv = h.rank_features()[1], h.rank_features()[2]
+    k1 = h1.rank_features()[1]
+    assert st.root_size == k1[lv == 2].sum() and st1.root_size == k1[lv == 1].sum()
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal((N, 2)) + 1j * rng.standard_normal((N, 2))
+    xe = sla.lu_solve(lu, b)
+    assert _rel(h.apply(b, refine=2), xe) < 1e-10
+    assert _rel(h.forward(xe), A @ xe) < 1e-10
+    thetas = np.array([-1.1, -math.acos(0.31), -math.acos(0.31 + 1 / 40)])
+    res = h.qp_solve_many(d, thetas, P=P, compress_walls=1)
+    ref = pq.solve_qp(disc, N, om, d, thetas, quad="kr6", P=P, A0=A)
+    _check_qp(res, ref, len(thetas))
+
+
 def test_qp_star_kress_compressed_walls(gpu_lib):
     wl = qpinputs.workload("star")
     nodes, w, nrm, kap = discretize(wl.curve, wl.N)
