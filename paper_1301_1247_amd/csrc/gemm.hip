@@ -240,7 +240,7 @@ hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDescT<R>>& v0, hipS
     // a descriptor with few tiles and a long inner dimension is the critical path of the launch
     const int64_t tg = tiles_of(g);
     if (!ws || tg >= target / 2 || g.k < 4096) continue;
-    int S = (int)std::min<int64_t>(16, (target + tg - 1) / tg);
+    int S = (int)std::min<int64_t>(64, (target + tg - 1) / tg);
     S = std::min(S, g.k / 1024);
     if (S >= 2) {
       split[i] = S;

@@ -841,6 +841,50 @@ int apply_interp(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx
   return HBS_OK;
 }
 
+// X (N x r) = E_L ... E_1 Z: the downward pass of the inverse with E only.  Since F^T P = I and
+// G P = 0 for every box (Dh = (P^T D^{-1} P)^{-1}), A^{-1} U = E_L ... E_1 R^{-1} and U^T A^{-1} U
+// = R^{-1}: this gives V = A^{-1} U from Z = R^{-1} without forming U.  complex128 levels only.
+int apply_down_E(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx, int64_t r) {
+  if (r <= 0) return HBS_OK;
+  if (h->fp64_top < h->L) {
+    set_error("hbs apply: E-only downward pass needs complex128 factors on every level");
+    return HBS_E_INVALID_ARG;
+  }
+  hipStream_t st = h->stream;
+  const int L = h->L;
+  auto& lv = h->lv;
+  int64_t xmax = 1;
+  for (int l = 1; l < L; ++l) xmax = std::max<int64_t>(xmax, lv[l].ntot);
+  CK(h->ab_x0.reserve(sizeof(cplx) * xmax * r));
+  CK(h->ab_x1.reserve(sizeof(cplx) * xmax * r));
+  auto xbuf = [&](int l) { return (l & 1) ? h->ab_x1.as<cplx>() : h->ab_x0.as<cplx>(); };
+  std::vector<GemmDesc> all;
+  std::vector<LaunchRec> recs;
+  for (int l = 1; l <= L; ++l) {
+    Level& V = lv[l];
+    const cplx* xin = (l == 1) ? Z : xbuf(l - 1);
+    const int ldxin = (l == 1) ? (int)ldz : (int)V.ktot;
+    cplx* out = (l == L) ? X : xbuf(l);
+    const int64_t ldo = (l == L) ? ldx : V.ntot;
+    LaunchRec rec{all.size(), 0, 0, 0.0};
+    for (int b = 0; b < V.nb; ++b) {
+      all.push_back(gd(V.E.as<cplx>() + V.oE[b], V.n[b], 0, xin + V.soff[b], ldxin, out + V.aoff[b], (int)ldo, V.n[b],
+                       (int)r, V.k[b]));
+      rec.max_tiles = std::max(rec.max_tiles, tiles_of(all.back()));
+      rec.flops += 8.0 * V.n[b] * (double)r * V.k[b];
+    }
+    rec.cnt = (int)(all.size() - rec.off);
+    recs.push_back(rec);
+  }
+  CK(upload(h->arena, all, st));
+  for (auto& rc : recs) {
+    ProfScope ps("zgemm", st, rc.flops, 0.0);
+    CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.max_tiles, st));
+  }
+  CK(hipStreamSynchronize(st));
+  return HBS_OK;
+}
+
 // Z (nr x r) = U^T X: the transpose of the nested interpolation, i.e. the upward pass with P^T
 // from the leaves to the root's active set (outgoing fields of X seen from beyond every proxy circle).
 int apply_interp_t(hbs_handle* h, const cplx* X, int64_t ldx, cplx* Z, int64_t ldz, int64_t r) {
@@ -1092,6 +1136,21 @@ int apply_factors(hbs_handle* h, bool inv, const cplx* B, int64_t ldb, cplx* X, 
 
 int apply_inverse(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r) {
   return apply_mixed(h, true, h->fp64_top, B, ldb, X, ldx, r);
+}
+
+int apply_inverse_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r, cplx* root, int64_t ldr) {
+  int rc = apply_mixed(h, true, h->fp64_top, B, ldb, X, ldx, r);
+  if (rc != HBS_OK || r <= 0) return rc;
+  // the root solution of the apply (still in the root workspace) is U^T A^{-1} B
+  const int64_t n = h->nroot;
+  if (ldr == n) {
+    CK(hipMemcpyAsync(root, h->ab_root.p, sizeof(cplx) * n * r, hipMemcpyDeviceToDevice, h->stream));
+  } else {
+    CK(hipMemcpy2DAsync(root, sizeof(cplx) * ldr, h->ab_root.p, sizeof(cplx) * n, sizeof(cplx) * n, r,
+                        hipMemcpyDeviceToDevice, h->stream));
+  }
+  CK(hipStreamSynchronize(h->stream));
+  return HBS_OK;
 }
 
 }  // namespace qps

@@ -60,6 +60,10 @@ int apply_inverse(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ld
 int build(hbs_handle* h);
 int apply_interp(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx, int64_t r);
 int apply_interp_t(hbs_handle* h, const cplx* X, int64_t ldx, cplx* Z, int64_t ldz, int64_t r);
+// X = E_L ... E_1 Z (complex128 levels only): A^{-1} U from Z = R^{-1}
+int apply_down_E(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx, int64_t r);
+// X = A^{-1} B and root (nroot x r) = U^T A^{-1} B, the root solution of the same apply
+int apply_inverse_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r, cplx* root, int64_t ldr);
 int qp_max_modes_impl(double om, double period);
 struct QPPlan;
 int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, const qp_opts* o, cplx* eta_out,

@@ -380,10 +380,75 @@ __global__ __launch_bounds__(NTP) void k_gj_panel(const InvDescT<R>* __restrict_
 
 // Register-resident variant for n <= 1024: thread i holds row i of the NBR-column panel, so a
 // pivot step costs two barriers and broadcasts of one row through LDS (no global traffic).
+// The pivot steps are instantiated per column (template recursion) so that every access to
+// the row array has a constant index and the row stays in registers.
 constexpr int GJ_NBR = 16;
+constexpr int NTP_REG = 1024;
+
 template <class R>
-__global__ __launch_bounds__(NTP) void k_gj_panel_reg(const InvDescT<R>* __restrict__ descs, int c0, int* __restrict__ ipiv_all,
-                                                      int maxn, int* __restrict__ info) {
+struct GjShared {
+  double red_v[NTP_REG / 64];
+  int red_i[NTP_REG / 64];
+  typename cx<R>::T rowp[GJ_NBR];  // the pivot row before scaling
+  typename cx<R>::T rowo[GJ_NBR];  // the old row p (moves to the pivot's row)
+};
+
+template <class R, int JJ>
+__device__ __forceinline__ void gj_pivot_steps(typename cx<R>::T (&a)[GJ_NBR], GjShared<R>& sh, int c0, int w, int n,
+                                               int* __restrict__ ipiv, int* __restrict__ info) {
+  typedef typename cx<R>::T C_t;
+  if (JJ < w) {
+    const int i = threadIdx.x, lane = i & 63, wv = i >> 6;
+    const C_t zero = cx<R>::make(0.0, 0.0);
+    const int p = c0 + JJ;
+    double bv = (i >= p && i < n) ? (double)cabs2(a[JJ]) : -1.0;
+    int bi = (i >= p && i < n) ? i : n;
+    wave_argmax(bv, bi);
+    if (lane == 0) { sh.red_v[wv] = bv; sh.red_i[wv] = bi; }
+    __syncthreads();
+    double b = sh.red_v[0];
+    int r = sh.red_i[0];
+#pragma unroll
+    for (int q = 1; q < NTP_REG / 64; ++q)
+      if (sh.red_v[q] > b || (sh.red_v[q] == b && sh.red_i[q] < r)) { b = sh.red_v[q]; r = sh.red_i[q]; }
+    if (!(b > 0.0)) r = p;
+    if (i == r) {
+#pragma unroll
+      for (int j = 0; j < GJ_NBR; ++j) sh.rowp[j] = a[j];
+    }
+    if (i == p) {
+#pragma unroll
+      for (int j = 0; j < GJ_NBR; ++j) sh.rowo[j] = a[j];
+    }
+    if (i == 0) {
+      ipiv[p] = r;
+      if (!(b > 0.0)) info[blockIdx.x] = p + 1;
+    }
+    __syncthreads();
+    const C_t piv = sh.rowp[JJ];
+    const C_t dd = (cabs2(piv) > 0) ? cinv(piv) : zero;
+    if (i == p) {
+#pragma unroll
+      for (int j = 0; j < GJ_NBR; ++j) a[j] = (j == JJ) ? dd : cmul(sh.rowp[j], dd);
+    } else if (i < n) {
+      if (i == r) {
+#pragma unroll
+        for (int j = 0; j < GJ_NBR; ++j) a[j] = sh.rowo[j];
+      }
+      const C_t f = a[JJ];
+      const C_t fd = cmul(f, dd);
+#pragma unroll
+      for (int j = 0; j < GJ_NBR; ++j)
+        if (j != JJ) a[j] = csub(a[j], cmul(fd, sh.rowp[j]));
+      a[JJ] = cx<R>::make(-fd.x, -fd.y);
+    }
+    if constexpr (JJ + 1 < GJ_NBR) gj_pivot_steps<R, JJ + 1>(a, sh, c0, w, n, ipiv, info);
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(NTP_REG) void k_gj_panel_reg(const InvDescT<R>* __restrict__ descs, int c0, int* __restrict__ ipiv_all,
+                                                          int maxn, int* __restrict__ info) {
   typedef typename cx<R>::T C_t;
   const InvDescT<R> d = descs[blockIdx.x];
   const int n = d.n;
@@ -392,60 +457,13 @@ __global__ __launch_bounds__(NTP) void k_gj_panel_reg(const InvDescT<R>* __restr
   const int ld = d.ld;
   C_t* A = d.a;
   int* ipiv = ipiv_all + (size_t)blockIdx.x * maxn;
-  __shared__ double red_v[NTP / 64];
-  __shared__ int red_i[NTP / 64];
-  __shared__ C_t rowp[GJ_NBR];  // the pivot row before scaling
-  __shared__ C_t rowo[GJ_NBR];  // the old row p (moves to the pivot's row)
-  const int i = threadIdx.x, lane = i & 63, wv = i >> 6;
+  __shared__ GjShared<R> sh;
+  const int i = threadIdx.x;
   const C_t zero = cx<R>::make(0.0, 0.0);
   C_t a[GJ_NBR];
 #pragma unroll
   for (int j = 0; j < GJ_NBR; ++j) a[j] = (i < n && j < w) ? A[i + (size_t)(c0 + j) * ld] : zero;
-#pragma unroll
-  for (int jj = 0; jj < GJ_NBR; ++jj) {
-    if (jj < w) {
-      const int p = c0 + jj;
-      double bv = (i >= p && i < n) ? (double)cabs2(a[jj]) : -1.0;
-      int bi = (i >= p && i < n) ? i : n;
-      wave_argmax(bv, bi);
-      if (lane == 0) { red_v[wv] = bv; red_i[wv] = bi; }
-      __syncthreads();
-      double b = red_v[0];
-      int r = red_i[0];
-      for (int q = 1; q < NTP / 64; ++q)
-        if (red_v[q] > b || (red_v[q] == b && red_i[q] < r)) { b = red_v[q]; r = red_i[q]; }
-      if (!(b > 0.0)) r = p;
-      if (i == r) {
-#pragma unroll
-        for (int j = 0; j < GJ_NBR; ++j) rowp[j] = a[j];
-      }
-      if (i == p) {
-#pragma unroll
-        for (int j = 0; j < GJ_NBR; ++j) rowo[j] = a[j];
-      }
-      if (i == 0) {
-        ipiv[p] = r;
-        if (!(b > 0.0)) info[blockIdx.x] = p + 1;
-      }
-      __syncthreads();
-      const C_t piv = rowp[jj];
-      const C_t dd = (cabs2(piv) > 0) ? cinv(piv) : zero;
-      if (i == p) {
-#pragma unroll
-        for (int j = 0; j < GJ_NBR; ++j) a[j] = (j == jj) ? dd : cmul(rowp[j], dd);
-      } else if (i < n) {
-        if (i == r) {
-#pragma unroll
-          for (int j = 0; j < GJ_NBR; ++j) a[j] = rowo[j];
-        }
-        const C_t f = a[jj];
-#pragma unroll
-        for (int j = 0; j < GJ_NBR; ++j)
-          if (j != jj) a[j] = csub(a[j], cmul(f, cmul(rowp[j], dd)));
-        a[jj] = cmul(cx<R>::make(-f.x, -f.y), dd);
-      }
-    }
-  }
+  gj_pivot_steps<R, 0>(a, sh, c0, w, n, ipiv, info);
   if (i < n) {
 #pragma unroll
     for (int j = 0; j < GJ_NBR; ++j)
@@ -632,9 +650,9 @@ hipError_t launch_inv(const InvDescT<R>* d, int nd, int max_n, typename cx<R>::T
   if (nd == 0 || max_n == 0) return hipSuccess;
   hipError_t e = hipMemsetAsync(info, 0, sizeof(int) * nd, s);
   if (e != hipSuccess) return e;
-  if (max_n <= NTP) {
+  if (max_n <= NTP_REG) {
     for (int c0 = 0; c0 < max_n; c0 += GJ_NBR) {
-      hipLaunchKernelGGL(k_gj_panel_reg<R>, dim3(nd), dim3(NTP), 0, s, d, c0, ipiv, max_n, info);
+      hipLaunchKernelGGL(k_gj_panel_reg<R>, dim3(nd), dim3(NTP_REG), 0, s, d, c0, ipiv, max_n, info);
       hipLaunchKernelGGL((k_gj_swapsave<R, GJ_NBR>), dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, c0, ipiv, max_n, tbuf);
       hipLaunchKernelGGL((k_gj_update<R, GJ_NBR>), dim3((max_n + 63) / 64, (max_n + 15) / 16, nd), dim3(NT), 0, s, d, c0,
                          max_n, (const typename cx<R>::T*)tbuf);

@@ -364,7 +364,10 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     }
     CK(launch_gen_inc(Q, dkx, dky, nang, Y + (size_t)ycolB * N, N, st));
   }
-  if (nu) {
+  // compressed walls on complex128 factors: V = A^{-1} U and U^T A^{-1} [U | b] come from the
+  // root inverse and the E-only downward pass, without forming U (F^T P = I, G P = 0, P^T E = I)
+  const bool fastU = cw && h->fp64_top >= h->L;
+  if (nu && !fastU) {
     // U (N x nroot) = nested interpolation of the identity
     CK(h->ab_root.reserve(sizeof(cplx) * (size_t)nu * nu));
     std::vector<cplx> eye((size_t)nu * nu, zero);
@@ -381,8 +384,14 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   if (cw) {
     // one application of A^{-1} to [U | b]: X = [V | X_b]; then with H = U^T V,
     //   U^T [X_L | X_R | X_b | V] = [H B_J,L | H B_J,R | U^T X_b | H]  and  G = C_J (that)
-    CR(apply_factors(h, true, Y, N, X, N, Wy));
-    CR(apply_interp_t(h, X, N, Zt, nu, Wy));
+    if (fastU) {
+      CR(apply_inverse_root(h, Y + (size_t)ycolB * N, N, X + (size_t)ycolB * N, N, nang, Zt + (size_t)nu * nu, nu));
+      CK(hipMemcpyAsync(Zt, h->Rinv.p, sizeof(cplx) * (size_t)nu * nu, hipMemcpyDeviceToDevice, st));
+      CR(apply_down_E(h, Zt, nu, X + (size_t)ycolU * N, N, nu));
+    } else {
+      CR(apply_factors(h, true, Y, N, X, N, Wy));
+      CR(apply_interp_t(h, X, N, Zt, nu, Wy));
+    }
     CR(gemm({gd(Zt, nu, 0, BJ, nu, Xc, nu, nu, M4, nu, onec, zero)}));
     CK(hipMemcpyAsync(Xc + (size_t)colB * nu, Zt + (size_t)nu * nu, sizeof(cplx) * (size_t)nu * nang,
                       hipMemcpyDeviceToDevice, st));
@@ -686,7 +695,37 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   // Bragg amplitudes
   {
     ProfScope ps("bragg", st, 0.0, 0.0);
-    // groups of >= 4 angles share one basis of diffraction orders (a GEMM); smaller ones sum directly
+    // groups of >= 4 angles share one basis of diffraction orders (one batched GEMM for all such
+    // groups); smaller groups sum directly
+    struct BG { int q0, cnt, qlo, nq; double kref; size_t eoff, coff, soff; };
+    std::vector<BG> bg;
+    std::vector<int> slots;
+    size_t etot = 0, ctot = 0;
+    // bases of at most ~4 GiB at a time
+    const size_t ecap = ((size_t)4 << 30) / sizeof(cplx);
+    auto flush = [&]() -> int {
+      if (bg.empty()) return HBS_OK;
+      CK(h->work.reserve(sizeof(cplx) * (etot + ctot) + sizeof(int) * slots.size() + 512));
+      cplx* E = h->work.as<cplx>();
+      cplx* Cg = E + etot;
+      int* dslot = (int*)(Cg + ctot);
+      CK(hipMemcpyAsync(dslot, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice, st));
+      std::vector<GemmDesc> g;
+      for (const BG& b : bg) {
+        CK(launch_bragg_basis(Q, b.kref, b.qlo, b.nq, E + b.eoff, st));
+        g.push_back(gd(E + b.eoff, 2 * b.nq, 0, eta + (size_t)b.q0 * N, N, Cg + b.coff, 2 * b.nq, 2 * b.nq, b.cnt, N, onec,
+                       zero));
+      }
+      CR(gemm(g));
+      for (const BG& b : bg)
+        CK(launch_bragg_gather(Q, b.kref, b.qlo, b.nq, dslot + b.soff, dnm + b.q0, maxm, b.cnt, Cg + b.coff, pl.y0,
+                               brg + (size_t)b.q0 * 2 * maxm, st));
+      CK(hipStreamSynchronize(st));
+      bg.clear();
+      slots.clear();
+      etot = ctot = 0;
+      return HBS_OK;
+    };
     for (int g = 0; g < ng; ++g) {
       const int q0 = goff[g], cnt = gcnt[g];
       if (cnt < 4) {
@@ -694,26 +733,26 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
                         brg + (size_t)q0 * 2 * maxm, st));
         continue;
       }
-      const double kref = kx[q0];
-      std::vector<int> slot0(cnt);
-      int qlo = 1 << 30, qhi = -(1 << 30);
+      BG b{q0, cnt, 1 << 30, 0, kx[q0], 0, 0, 0};
+      std::vector<int> sl(cnt);
+      int qhi = -(1 << 30);
       for (int a = 0; a < cnt; ++a) {
-        const int mshift = (int)std::llround((kx[q0 + a] - kref) * period / (2 * M_PI));
-        slot0[a] = mshift + nlo[q0 + a];
-        qlo = std::min(qlo, slot0[a]);
-        qhi = std::max(qhi, slot0[a] + nm[q0 + a] - 1);
+        const int mshift = (int)std::llround((kx[q0 + a] - b.kref) * period / (2 * M_PI));
+        sl[a] = mshift + nlo[q0 + a];
+        b.qlo = std::min(b.qlo, sl[a]);
+        qhi = std::max(qhi, sl[a] + nm[q0 + a] - 1);
       }
-      for (int a = 0; a < cnt; ++a) slot0[a] -= qlo;
-      const int nq = qhi - qlo + 1;
-      CK(h->work.reserve(sizeof(cplx) * ((size_t)2 * nq * N + (size_t)2 * nq * cnt) + sizeof(int) * cnt + 512));
-      cplx* E = h->work.as<cplx>();
-      cplx* Cg = E + (size_t)2 * nq * N;
-      int* dslot = (int*)(Cg + (size_t)2 * nq * cnt);
-      CK(hipMemcpyAsync(dslot, slot0.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, st));
-      CK(launch_bragg_basis(Q, kref, qlo, nq, E, st));
-      CR(gemm({gd(E, 2 * nq, 0, eta + (size_t)q0 * N, N, Cg, 2 * nq, 2 * nq, cnt, N, onec, zero)}));
-      CK(launch_bragg_gather(Q, kref, qlo, nq, dslot, dnm + q0, maxm, cnt, Cg, pl.y0, brg + (size_t)q0 * 2 * maxm, st));
+      b.nq = qhi - b.qlo + 1;
+      if (etot + (size_t)2 * b.nq * N > ecap) CR(flush());
+      b.soff = slots.size();
+      for (int a = 0; a < cnt; ++a) slots.push_back(sl[a] - b.qlo);
+      b.eoff = etot;
+      b.coff = ctot;
+      etot += (size_t)2 * b.nq * N;
+      ctot += (size_t)2 * b.nq * cnt;
+      bg.push_back(b);
     }
+    CR(flush());
   }
   // outputs in caller order
   CK(launch_permute_cols(N, nang, dperm, eta, N, eta_out, N, st));
