@@ -30,6 +30,30 @@ FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_gemm_wavy40_N1e5_traffic.txt")
+GEMM_SRC = os.path.join(HERE, "paper_1301_1247_amd", "csrc", "gemm.hip")
+
+
+def measured_traffic():
+    """HBM bytes per k_gemm<double> launch from the committed rocprofv3 counter runs (FETCH_SIZE and
+    WRITE_SIZE per dispatch, KiB, scaled by the factors a plain copy of known size gives), or None
+    when the GEMM source has changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(GEMM_SRC, "rb").read()).hexdigest()
+    if kv.get("source_sha256") != sha:
+        return None
+    return 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["fetch_factor"]) +
+                     float(kv["write_kib_per_launch"]) * float(kv["write_factor"]))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -223,7 +247,8 @@ def main():
         "roofline": {"bound": "mfma", "kernel": ("k_zgemm (complex FP64 MFMA GEMM)" if fam == "zgemm"
                                                  else "k_gemm<float> (complex FP32 MFMA GEMM)"),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "launches": prof["launches"],
+                     "traffic": measured_traffic() if fam == "zgemm" and wl.name == "wavy40" else None,
+                     "traffic_unit": "bytes per launch", "launches": prof["launches"],
                      "avg_launch_ms": prof["ms"] / max(1, prof["launches"]),
                      "flops_per_launch": prof["flops"] / max(1, prof["launches"])},
     }

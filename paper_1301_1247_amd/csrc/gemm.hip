@@ -283,9 +283,11 @@ hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDescT<R>>& v0, hipS
   for (const auto& g : v) max_tiles = std::max(max_tiles, tiles_of(g));
   hipError_t e = upload(arena, v, s);
   if (e != hipSuccess) return e;
-  ProfScope ps(sizeof(R) == 8 ? "zgemm" : "cgemm", s, flops, bytes);
-  e = launch_gemm<R>(arena.as<GemmDesc>(), (int)v.size(), max_tiles, s);
-  if (e != hipSuccess) return e;
+  {
+    ProfScope ps(sizeof(R) == 8 ? "zgemm" : "cgemm", s, flops, bytes);
+    e = launch_gemm<R>(arena.as<GemmDesc>(), (int)v.size(), max_tiles, s);
+    if (e != hipSuccess) return e;
+  }
   for (const auto& r : reds) {
     const int64_t tot = (int64_t)r.m * r.n;
     const int grid = (int)std::min<int64_t>(8192, (tot + 255) / 256);

@@ -831,12 +831,16 @@ int apply_interp(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx
       all.push_back(gd(V.P.as<cplx>() + V.oP[b], V.n[b], 0, xin + V.soff[b], ldxin, out + V.aoff[b], (int)ldo, V.n[b],
                        (int)r, V.k[b]));
       rec.max_tiles = std::max(rec.max_tiles, tiles_of(all.back()));
+      rec.flops += 8.0 * V.n[b] * (double)r * V.k[b];
     }
     rec.cnt = (int)(all.size() - rec.off);
     recs.push_back(rec);
   }
   CK(upload(h->arena, all, st));
-  for (auto& rc : recs) CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.max_tiles, st));
+  for (auto& rc : recs) {
+    ProfScope ps("zgemm", st, rc.flops, 0.0);
+    CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.max_tiles, st));
+  }
   CK(hipStreamSynchronize(st));
   return HBS_OK;
 }
@@ -910,12 +914,16 @@ int apply_interp_t(hbs_handle* h, const cplx* X, int64_t ldx, cplx* Z, int64_t l
       all.push_back(gd(V.P.as<cplx>() + V.oP[b], V.n[b], 1, src + V.aoff[b], lds, dst + V.soff[b], ldd, V.k[b], (int)r,
                        V.n[b]));
       rec.max_tiles = std::max(rec.max_tiles, tiles_of(all.back()));
+      rec.flops += 8.0 * V.n[b] * (double)r * V.k[b];
     }
     rec.cnt = (int)(all.size() - rec.off);
     recs.push_back(rec);
   }
   CK(upload(h->arena, all, st));
-  for (auto& rc : recs) CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.max_tiles, st));
+  for (auto& rc : recs) {
+    ProfScope ps("zgemm", st, rc.flops, 0.0);
+    CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.max_tiles, st));
+  }
   CK(hipStreamSynchronize(st));
   return HBS_OK;
 }
