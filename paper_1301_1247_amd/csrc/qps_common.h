@@ -80,13 +80,39 @@ __device__ inline cplx wave_csum(cplx v) {
   }
   return v;
 }
-// arg-max of (val, idx) over a wavefront, ties resolved to the smaller index
+// Wavefront max / min of an unsigned value with DPP moves (quad swaps, half-row and row
+// mirrors, row broadcasts 15 and 31), result read from lane 63: no LDS round trips.
+__device__ inline unsigned wave_umax(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ inline unsigned wave_umin(unsigned v) {
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// arg-max of (val, idx) over a wavefront, ties resolved to the smaller index; values <= 0
+// (including the -1 of lanes without a candidate) compare as 0.  The bit pattern of a
+// non-negative double orders like the value, so the max is taken on its high then low word.
+// Every lane receives the result.
 __device__ inline void wave_argmax(double& val, int& idx) {
-  for (int o = 32; o > 0; o >>= 1) {
-    double ov = __shfl_xor(val, o, 64);
-    int oi = __shfl_xor(idx, o, 64);
-    if (ov > val || (ov == val && oi < idx)) { val = ov; idx = oi; }
-  }
+  const unsigned long long bits = val > 0.0 ? (unsigned long long)__double_as_longlong(val) : 0ull;
+  const unsigned hi = (unsigned)(bits >> 32), lo = (unsigned)bits;
+  const unsigned mh = wave_umax(hi);
+  const unsigned ml = wave_umax(hi == mh ? lo : 0u);
+  const unsigned mi = wave_umin((hi == mh && lo == ml) ? (unsigned)idx : 0xFFFFFFFFu);
+  val = __longlong_as_double((long long)(((unsigned long long)mh << 32) | ml));
+  idx = (int)mi;
 }
 
 // host-side status plumbing
