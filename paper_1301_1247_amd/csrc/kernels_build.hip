@@ -379,7 +379,8 @@ __global__ __launch_bounds__(NTP) void k_gj_panel(const InvDescT<R>* __restrict_
 }
 
 // Register-resident variant for n <= 1024: thread i holds row i of the NBR-column panel, so a
-// pivot step costs two barriers and broadcasts of one row through LDS (no global traffic).
+// pivot step costs two barriers and broadcasts of one row through LDS (no global traffic).  The
+// workgroup has as many whole wavefronts as the largest matrix of the batch has rows.
 // The pivot steps are instantiated per column (template recursion) so that every access to
 // the row array has a constant index and the row stays in registers.
 constexpr int GJ_NBR = 16;
@@ -408,8 +409,8 @@ __device__ __forceinline__ void gj_pivot_steps(typename cx<R>::T (&a)[GJ_NBR], G
     __syncthreads();
     double b = sh.red_v[0];
     int r = sh.red_i[0];
-#pragma unroll
-    for (int q = 1; q < NTP_REG / 64; ++q)
+    const int nwv = blockDim.x >> 6;
+    for (int q = 1; q < nwv; ++q)
       if (sh.red_v[q] > b || (sh.red_v[q] == b && sh.red_i[q] < r)) { b = sh.red_v[q]; r = sh.red_i[q]; }
     if (!(b > 0.0)) r = p;
     if (i == r) {
@@ -651,8 +652,10 @@ hipError_t launch_inv(const InvDescT<R>* d, int nd, int max_n, typename cx<R>::T
   hipError_t e = hipMemsetAsync(info, 0, sizeof(int) * nd, s);
   if (e != hipSuccess) return e;
   if (max_n <= NTP_REG) {
+    // one thread per row, in whole wavefronts: small matrices get small workgroups
+    const int nthr = std::min(NTP_REG, (max_n + 63) / 64 * 64);
     for (int c0 = 0; c0 < max_n; c0 += GJ_NBR) {
-      hipLaunchKernelGGL(k_gj_panel_reg<R>, dim3(nd), dim3(NTP_REG), 0, s, d, c0, ipiv, max_n, info);
+      hipLaunchKernelGGL(k_gj_panel_reg<R>, dim3(nd), dim3(nthr), 0, s, d, c0, ipiv, max_n, info);
       hipLaunchKernelGGL((k_gj_swapsave<R, GJ_NBR>), dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, c0, ipiv, max_n, tbuf);
       hipLaunchKernelGGL((k_gj_update<R, GJ_NBR>), dim3((max_n + 63) / 64, (max_n + 15) / 16, nd), dim3(NT), 0, s, d, c0,
                          max_n, (const typename cx<R>::T*)tbuf);
