@@ -68,18 +68,29 @@ template <> struct cx<float> {
   __host__ __device__ static T make(double re, double im) { return mkcf((float)re, (float)im); }
 };
 
-// wavefront (64 lanes) reductions
+// wavefront (64 lanes) reductions with DPP moves; every lane must be active, every lane gets the
+// result.  A DPP move of a double moves its two 32-bit halves; lanes a row mask leaves out take
+// the move's old value 0, so the partial sums of rows 0 and 2 are not counted twice.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 __device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<0xB1, 0xF>(v);   // quad_perm 1,0,3,2
+  v += dpp_d<0x4E, 0xF>(v);   // quad_perm 2,3,0,1
+  v += dpp_d<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_d<0x140, 0xF>(v);  // row_mirror
+  v += dpp_d<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp_d<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-__device__ inline cplx wave_csum(cplx v) {
-  for (int o = 32; o > 0; o >>= 1) {
-    v.x += __shfl_xor(v.x, o, 64);
-    v.y += __shfl_xor(v.y, o, 64);
-  }
-  return v;
-}
+__device__ inline cplx wave_csum(cplx v) { return mkc(wave_sum(v.x), wave_sum(v.y)); }
 // Wavefront max / min of an unsigned value with DPP moves (quad swaps, half-row and row
 // mirrors, row broadcasts 15 and 31), result read from lane 63: no LDS round trips.
 __device__ inline unsigned wave_umax(unsigned v) {
