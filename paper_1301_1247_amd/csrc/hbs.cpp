@@ -55,11 +55,12 @@ GemmDesc gd(const cplx* A, int lda, int transA, const cplx* B, int ldb, cplx* C,
     }                                                                                             \
   } while (0)
 
+// Descriptor upload into the arena.  The copy from pageable host memory is staged before the call
+// returns and is ordered on the stream after the kernels that read the previous contents, so no
+// host synchronisation is needed between consecutive uploads and launches.
 template <class T>
 hipError_t up_sync(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
-  hipError_t e = upload(b, v, s);
-  if (e != hipSuccess) return e;
-  return hipStreamSynchronize(s);
+  return upload(b, v, s);
 }
 
 }  // namespace
@@ -646,12 +647,10 @@ int build(hbs_handle* h) {
         g1.push_back(g32(P32 + V.oP[b], n, 1, G32 + V.oG[b], n, Z32 + V.oP[b], k, k, n, n, one, zero));
       }
       CK(gemm_batched<float>(arena, g1, st));
-      CK(hipStreamSynchronize(st));
       for (int b = 0; b < nb; ++b)
         g2.push_back(g32(Z32 + V.oP[b], V.k[b], 0, P32 + V.oP[b], V.n[b], Dh32 + V.oDh[b], V.k[b], V.k[b], V.k[b], V.n[b],
                          one, zero));
       CK(gemm_batched<float>(arena, g2, st));
-      CK(hipStreamSynchronize(st));
       std::vector<InvDesc32> iv2;
       for (int b = 0; b < nb; ++b) iv2.push_back({Dh32 + V.oDh[b], V.k[b], V.k[b]});
       CK(inv_batched<float>(arena, h->work, iv2, st, &sing));
@@ -665,14 +664,12 @@ int build(hbs_handle* h) {
         g3.push_back(g32(Dh32 + V.oDh[b], k, 0, Z32 + V.oP[b], k, F32 + V.oP[b], k, k, n, k, one, zero));
       }
       CK(gemm_batched<float>(arena, g3, st));
-      CK(hipStreamSynchronize(st));
       for (int b = 0; b < nb; ++b)
         g4.push_back(g32(E32 + V.oP[b], V.n[b], 0, Z32 + V.oP[b], V.k[b], G32 + V.oG[b], V.n[b], V.n[b], V.n[b], V.k[b],
                          mone, one));
       CK(gemm_batched<float>(arena, g4, st));
       // the parent's diagonal block needs D^ in FP64
       CK(launch_cast_f2d(Dh32, V.Dh.as<cplx>(), V.oDh[nb], st));
-      CK(hipStreamSynchronize(st));
       V.G.release();  // D itself is not a factor in this mode
     } else if (ident) {
       // P = I: the reduced block is D itself, E = F^T = I and G = D^{-1} - D^{-1} = 0
@@ -690,7 +687,6 @@ int build(hbs_handle* h) {
       CK(launch_eye(arena.as<CopyDesc>(), (int)ce.size(), maxe, st));
       CK(up_sync(arena, cz, st));
       CK(launch_copy(arena.as<CopyDesc>(), (int)cz.size(), maxe, st));
-      CK(hipStreamSynchronize(st));
     } else {
       std::vector<InvDesc> iv;
       for (int b = 0; b < nb; ++b) iv.push_back({dG + V.oG[b], V.n[b], V.n[b]});
@@ -715,14 +711,12 @@ int build(hbs_handle* h) {
         g1.push_back(gd(dP + V.oP[b], n, 1, Di, n, Zt + V.oP[b], k, k, n, n));
       }
       CK(gemm_batched(arena, g1, st));
-      CK(hipStreamSynchronize(st));
       for (int b = 0; b < nb; ++b) {
         const int n = V.n[b], k = V.k[b];
         // S = Zt P (k x k) -> Dh
         g2.push_back(gd(Zt + V.oP[b], k, 0, dP + V.oP[b], n, Dh + V.oDh[b], k, k, k, n));
       }
       CK(gemm_batched(arena, g2, st));
-      CK(hipStreamSynchronize(st));
       std::vector<InvDesc> iv;
       for (int b = 0; b < nb; ++b) iv.push_back({Dh + V.oDh[b], V.k[b], V.k[b]});
       CK(inv_batched(arena, h->work, iv, st, &sing));
@@ -738,14 +732,12 @@ int build(hbs_handle* h) {
         g3.push_back(gd(Dh + V.oDh[b], k, 0, Zt + V.oP[b], k, Ft + V.oP[b], k, k, n, k));
       }
       CK(gemm_batched(arena, g3, st));
-      CK(hipStreamSynchronize(st));
       for (int b = 0; b < nb; ++b) {
         const int n = V.n[b], k = V.k[b];
         // G = D^{-1} - E Zt  (in place)
         g4.push_back(gd(E + V.oP[b], n, 0, Zt + V.oP[b], k, dG + V.oG[b], n, n, n, k, mkc(-1, 0), mkc(1, 0)));
       }
       CK(gemm_batched(arena, g4, st));
-      CK(hipStreamSynchronize(st));
     }
     }
     if (l < L) h->lv[l + 1].Dh.release();

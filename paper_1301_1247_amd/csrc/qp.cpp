@@ -345,9 +345,10 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   QJ.idx = J;
   QJ.N = nu;
   const cplx zero = mkc(0, 0);
+  // batched GEMMs are stream-ordered with the surrounding kernels; the host waits only where it
+  // reads results back
   auto gemm = [&](const std::vector<GemmDesc>& g) -> int {
     CK(gemm_batched(h->arena, g, st, &h->splitws));
-    CK(hipStreamSynchronize(st));
     return HBS_OK;
   };
   {
