@@ -84,6 +84,10 @@ typedef struct {
                                level-2 skeletons; 0 (default): 2 when the rank predictor expects
                                the level-1 decomposition to keep >= 60% of its points and the root
                                stays within 1024 points, else 1 */
+  int32_t graph;            /* 1: each application of the factorization (hbs_apply, hbs_forward and the
+                               applies inside qp_solve) is captured into a HIP graph on a private
+                               stream and replayed while a later call uses the same operands and
+                               workspaces (up to 4 captured operand sets per handle); 0 = off */
 } hbs_opts;
 
 typedef struct {
@@ -125,6 +129,8 @@ typedef struct {
   int64_t sketch_bytes_max; /* largest per-level sketch buffer of the build */
   double cpqr_work;         /* sum over boxes of sketch rows x n x k (CPQR cost measure) */
   int32_t root_level;       /* 1 or 2 (see hbs_opts.root_level) */
+  int64_t graph_captures;   /* applies captured into HIP graphs (hbs_opts.graph) */
+  int64_t graph_replays;    /* applies served by replaying a captured graph */
 } hbs_stats_t;
 
 void hbs_opts_init(hbs_opts* o);

@@ -171,6 +171,7 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
   if (o.ptr_mode != HBS_PTR_HOST && o.ptr_mode != HBS_PTR_DEVICE) { set_error("hbs_build: unknown ptr_mode"); return HBS_E_INVALID_ARG; }
   if (o.precision != HBS_FP64 && o.precision != HBS_FP32_PRECOND) { set_error("hbs_build: unknown precision"); return HBS_E_INVALID_ARG; }
   if (o.rank_predictor != 0 && o.rank_predictor != 1) { set_error("hbs_build: rank_predictor must be 0 or 1"); return HBS_E_INVALID_ARG; }
+  if (o.graph != 0 && o.graph != 1) { set_error("hbs_build: graph must be 0 or 1"); return HBS_E_INVALID_ARG; }
   if (o.root_level < 0 || o.root_level > 2) { set_error("hbs_build: root_level must be 0, 1 or 2"); return HBS_E_INVALID_ARG; }
   if (o.rank_scale < 0 || !std::isfinite(o.rank_scale)) { set_error("hbs_build: rank_scale must be >= 0"); return HBS_E_INVALID_ARG; }
   if (o.rank_predictor && !o.rank_model && kRankModelDefaultN != MLP_NPARAM) {
@@ -402,6 +403,8 @@ int hbs_stats(const hbs_handle* h, hbs_stats_t* s) {
   s->factor_bytes = h->factor_bytes;
   s->build_seconds = h->build_seconds;
   s->root_level = h->top_identity ? 2 : 1;
+  s->graph_captures = h->graph_captures;
+  s->graph_replays = h->graph_replays;
   return HBS_OK;
 }
 

@@ -1106,25 +1106,78 @@ static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_
       for (int64_t c = 0; c < r; ++c) cast(3, out32 + c * N, X + c * ldx, N);
     }
   }
-  CK(upload(h->arena, d64, st));
-  if (!d32.empty()) CK(upload(h->arena32, d32, st));
-  const GemmDesc* dd64 = h->arena.as<GemmDesc>();
-  const GemmDesc32* dd32 = d32.empty() ? nullptr : h->arena32.as<GemmDesc32>();
   double fl = 0;
   for (auto& t : prog) fl += t.flops;
-  ProfScope ps("apply", st, fl, 0.0);
-  for (auto& t : prog) {
-    if (t.kind == 0) {
-      ProfScope ps2("zgemm", st, t.flops, 0.0);
-      CK(launch_gemm<double>(dd64 + t.off, t.cnt, t.max_tiles, st));
-    } else if (t.kind == 1) {
-      ProfScope ps2("cgemm", st, t.flops, 0.0);
-      CK(launch_gemm<float>(dd32 + t.off, t.cnt, t.max_tiles, st));
-    } else if (t.kind == 2) {
-      CK(launch_cast_d2f(static_cast<const cplx*>(t.src), static_cast<cplxf*>(t.dst), t.n, st));
-    } else {
-      CK(launch_cast_f2d(static_cast<const cplxf*>(t.src), static_cast<cplx*>(t.dst), t.n, st));
+  // issue the program on stream s (profiled per launch unless it is being captured)
+  auto issue = [&](const GemmDesc* dd64, const GemmDesc32* dd32, hipStream_t s, bool prof) -> hipError_t {
+    for (auto& t : prog) {
+      hipError_t e;
+      if (t.kind == 0) {
+        ProfScope ps2(prof ? "zgemm" : nullptr, s, t.flops, 0.0);
+        e = launch_gemm<double>(dd64 + t.off, t.cnt, t.max_tiles, s);
+      } else if (t.kind == 1) {
+        ProfScope ps2(prof ? "cgemm" : nullptr, s, t.flops, 0.0);
+        e = launch_gemm<float>(dd32 + t.off, t.cnt, t.max_tiles, s);
+      } else if (t.kind == 2) {
+        e = launch_cast_d2f(static_cast<const cplx*>(t.src), static_cast<cplxf*>(t.dst), t.n, s);
+      } else {
+        e = launch_cast_f2d(static_cast<const cplxf*>(t.src), static_cast<cplx*>(t.dst), t.n, s);
+      }
+      if (e != hipSuccess) return e;
     }
+    return hipSuccess;
+  };
+  if (h->opts.graph) {
+    // capture once per operand set on a private stream (kernels only: the descriptors live in the
+    // graph's own buffers, uploaded before the capture), then replay on the handle's stream
+    const void* ws[8] = {h->ab_up.p, h->ab_x0.p, h->ab_x1.p, h->ab_root.p, h->ab_in32.p, h->ab_up32.p, h->ab_x32a.p,
+                         h->ab_x32b.p};
+    ApplyGraph* g = nullptr;
+    for (auto& c : h->graphs)
+      if (c->inv == inv && c->split == split && c->B == B && c->ldb == ldb && c->X == X && c->ldx == ldx && c->r == r &&
+          std::equal(ws, ws + 8, c->ws))
+        g = c.get();
+    if (!g) {
+      if (!h->cap_stream) CK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+      if (h->graphs.size() >= 4) h->graphs.erase(h->graphs.begin());
+      h->graphs.emplace_back(new ApplyGraph);
+      g = h->graphs.back().get();
+      g->inv = inv; g->split = split; g->B = B; g->ldb = ldb; g->X = X; g->ldx = ldx; g->r = r;
+      std::copy(ws, ws + 8, g->ws);
+      CK(upload(g->d64, d64, st));
+      if (!d32.empty()) CK(upload(g->d32, d32, st));
+      CK(hipStreamSynchronize(st));
+      hipGraph_t graph = nullptr;
+      CK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+      const hipError_t ie = issue(g->d64.as<GemmDesc>(), d32.empty() ? nullptr : g->d32.as<GemmDesc32>(), h->cap_stream, false);
+      const hipError_t ce = hipStreamEndCapture(h->cap_stream, &graph);
+      if (ie != hipSuccess || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        h->graphs.pop_back();
+        CK(ie != hipSuccess ? ie : ce);
+      }
+      const hipError_t xe = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (xe != hipSuccess) {
+        h->graphs.pop_back();
+        CK(xe);
+      }
+      ++h->graph_captures;
+    } else {
+      ++h->graph_replays;
+    }
+    {
+      ProfScope ps("apply", st, fl, 0.0);
+      CK(hipGraphLaunch(g->exec, st));
+    }
+    CK(hipStreamSynchronize(st));
+    return HBS_OK;
+  }
+  CK(upload(h->arena, d64, st));
+  if (!d32.empty()) CK(upload(h->arena32, d32, st));
+  {
+    ProfScope ps("apply", st, fl, 0.0);
+    CK(issue(h->arena.as<GemmDesc>(), d32.empty() ? nullptr : h->arena32.as<GemmDesc32>(), st, true));
   }
   CK(hipStreamSynchronize(st));
   return HBS_OK;
@@ -1154,3 +1207,9 @@ int apply_inverse_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64
 }
 
 }  // namespace qps
+
+hbs_handle::~hbs_handle() {
+  for (auto& g : graphs)
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+}

@@ -25,7 +25,21 @@ struct Level {
 
 }  // namespace qps
 
+// A captured application of the telescoping factorization (HIP graph), replayed while the call
+// uses the same operands and the apply workspaces have not moved.
+struct ApplyGraph {
+  bool inv = false;
+  int split = 0;
+  const void* B = nullptr;
+  void* X = nullptr;
+  int64_t ldb = 0, ldx = 0, r = 0;
+  const void* ws[8] = {};
+  hipGraphExec_t exec = nullptr;
+  qps::DevBuf d64, d32;  // the graph's own descriptor arrays
+};
+
 struct hbs_handle {
+  ~hbs_handle();
   int64_t N = 0;
   double omega = 0, tol = 0;
   hbs_opts opts{};
@@ -46,6 +60,9 @@ struct hbs_handle {
   qps::DevBuf arena, arena32, work, scratch, splitws, qp32;
   qps::DevBuf ab_up, ab_x0, ab_x1, ab_root;          // apply workspaces
   qps::DevBuf ab_in32, ab_up32, ab_x32a, ab_x32b;    // complex64 stage of a mixed-precision inverse apply
+  std::vector<std::unique_ptr<ApplyGraph>> graphs;   // hbs_opts.graph: captured applies (at most 4)
+  hipStream_t cap_stream = nullptr;                 // private stream the applies are captured on
+  int64_t graph_captures = 0, graph_replays = 0;
   hbs_stats_t stats{};
   double c0x = 0, c0y = 0, robs = 0;  // obstacle centre and radius about it
   int64_t factor_bytes = 0;

@@ -178,7 +178,7 @@ bool profile_read(const std::string& fam, double* ms, int64_t* launches, double*
 }
 
 ProfScope::ProfScope(const char* f, hipStream_t st, double fl, double by) : fam(f), s(st), flops(fl), bytes(by) {
-  if (!g_prof_on) return;
+  if (!g_prof_on || !f) return;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     e0 = e1 = nullptr;
     return;

@@ -295,3 +295,38 @@ def test_qp_P1_needs_far_field_skeletons(gpu_lib):
     with pytest.raises(gpu_lib.HBSError) as e:
         h.qp_solve_many(wl.period, wl.thetas, P=1)
     assert e.value.code == -1
+
+
+def test_graph_captured_applies_replay_exactly(gpu_lib, wavy_small):
+    """hbs_opts.graph: the apply is captured into a HIP graph and replayed; every replay, with
+    eager work of other handles in between, gives the result of the uncaptured apply."""
+    import torch
+    c, N, om, disc, A, lu = wavy_small
+    nodes, w, nrm, _ = discretize(c, N)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(a).to(dev)
+    hg = gpu_lib.Handle(t(nodes), t(w), t(nrm), om, 1e-12, device=True, graph=True)
+    h0 = gpu_lib.Handle(t(nodes), t(w), t(nrm), om, 1e-12, device=True)
+    rng = np.random.default_rng(9)
+    b = torch.from_numpy(rng.standard_normal((3, N)) + 1j * rng.standard_normal((3, N))).to(dev)
+    out = torch.empty_like(b)
+    ref = h0.apply(b)
+    for it in range(4):
+        for inverse in (True, False):
+            fn = gpu_lib._lib.hbs_apply if inverse else gpu_lib._lib.hbs_forward
+            args = (hg._h, gpu_lib._ptr(b), 3, gpu_lib._ptr(out)) + ((0,) if inverse else ())
+            assert fn(*args) == 0
+            torch.cuda.synchronize()
+            expect = ref if inverse else h0.forward(b)
+            assert torch.equal(out, expect), (it, inverse)
+        h0.apply(b[:1])   # eager work between the replays
+    st = hg.stats()
+    assert st.graph_captures == 2 and st.graph_replays == 6
+    # refinement inside qp_solve replays its forward and inverse applies
+    d = 2 * math.pi
+    thetas = np.array([-1.1, -0.45])
+    kw = dict(refine_max_iter=3, refine_tol=1e-300)
+    r1 = hg.qp_solve_many(d, t(thetas), **kw)
+    r0 = h0.qp_solve_many(d, t(thetas), **kw)
+    assert torch.equal(r1["eta"], r0["eta"])
+    assert hg.stats().graph_replays > 6
