@@ -501,8 +501,10 @@ int build(hbs_handle* h) {
         fl += 8.0 * 2.0 * s[b] * (double)V.n[b] * V.n[b];
       }
       CK(up_sync(arena, qd, st));
+      int ms = 0, mn = 0;
+      for (const auto& q : qd) { ms = std::max(ms, q.s); mn = std::max(mn, q.n); }
       ProfScope ps("cpqr", st, fl, 0.0);
-      CK(launch_cpqr(arena.as<CpqrDesc>(), nb, h->tol, kout.as<int>(), st));
+      CK(launch_cpqr(arena.as<CpqrDesc>(), nb, ms, mn, h->tol, kout.as<int>(), st));
     }
     V.k.assign(nb, 0);
     CK(hipMemcpyAsync(V.k.data(), kout.p, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
@@ -543,7 +545,9 @@ int build(hbs_handle* h) {
         CK(up_sync(arena, qd, st));
         CK(kout.reserve(sizeof(int) * nb + sizeof(int) * redo.size()));
         int* k2 = kout.as<int>() + nb;
-        CK(launch_cpqr(arena.as<CpqrDesc>(), (int)qd.size(), h->tol, k2, st));
+        int ms = 0, mn = 0;
+        for (const auto& q : qd) { ms = std::max(ms, q.s); mn = std::max(mn, q.n); }
+        CK(launch_cpqr(arena.as<CpqrDesc>(), (int)qd.size(), ms, mn, h->tol, k2, st));
         std::vector<int> hk2(redo.size());
         CK(hipMemcpyAsync(hk2.data(), k2, sizeof(int) * redo.size(), hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));

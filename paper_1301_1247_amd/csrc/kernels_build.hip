@@ -106,20 +106,21 @@ __global__ __launch_bounds__(NT) void k_sketch(const SketchDesc* __restrict__ de
 // One workgroup per box.  Householder QR with column pivoting on Z (s x n, in place, global
 // memory).  Column norms of the trailing rows are recomputed exactly in every update pass.
 // Rank: the first p with |R_pp| <= tol |R_00| (at least 1).
+// Two instantiations: 1024 threads with room for s <= 4608, n <= 2048 (few, large boxes), and
+// 256 threads with s <= 512, n <= 256 (many small boxes: several workgroups per CU hide the
+// memory latency of the column updates).
 constexpr int CPQR_MAXN = 2048;
 constexpr int CPQR_MAXS = 4608;
-constexpr int NTQ = 1024;
+template <int NTQ, int MAXS, int MAXN>
 __global__ __launch_bounds__(NTQ) void k_cpqr(const CpqrDesc* __restrict__ descs, double tol, int* __restrict__ k_out) {
   const CpqrDesc d = descs[blockIdx.x];
   const int s = d.s, n = d.n;
   cplx* Z = d.z;
-  __shared__ double cn[CPQR_MAXN];
-  __shared__ int perm[CPQR_MAXN];
-  __shared__ cplx v[CPQR_MAXS];
+  __shared__ double cn[MAXN];
+  __shared__ int perm[MAXN];
+  __shared__ cplx v[MAXS];
   __shared__ double red_v[NTQ / 64];
   __shared__ int red_i[NTQ / 64];
-  __shared__ double sh_tau, sh_r00;
-  __shared__ int sh_piv, sh_stop;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nw = NTQ / 64;
   for (int j = tid; j < n; j += NTQ) perm[j] = j;
@@ -132,8 +133,9 @@ __global__ __launch_bounds__(NTQ) void k_cpqr(const CpqrDesc* __restrict__ descs
   __syncthreads();
   const int pmax = min(s, n);
   int k = pmax;
+  double r00 = 0.0;
   for (int p = 0; p < pmax; ++p) {
-    // pivot: argmax over j in [p, n)
+    // pivot: argmax over j in [p, n), then every thread reduces the wavefronts' candidates
     double bv = -1.0;
     int bi = n;
     for (int j = p + tid; j < n; j += NTQ) {
@@ -143,86 +145,98 @@ __global__ __launch_bounds__(NTQ) void k_cpqr(const CpqrDesc* __restrict__ descs
     wave_argmax(bv, bi);
     if (lane == 0) { red_v[wv] = bv; red_i[wv] = bi; }
     __syncthreads();
-    if (tid == 0) {
-      double b = red_v[0];
-      int bj = red_i[0];
-      for (int w = 1; w < nw; ++w)
-        if (red_v[w] > b || (red_v[w] == b && red_i[w] < bj)) { b = red_v[w]; bj = red_i[w]; }
-      const double nr = sqrt(fmax(b, 0.0));
-      if (p == 0) sh_r00 = nr;
-      sh_stop = (p > 0 && nr <= tol * sh_r00) || (p == 0 && nr == 0.0);
-      sh_piv = bj;
+    double b = red_v[0];
+    int jp = red_i[0];
+    for (int w = 1; w < nw; ++w)
+      if (red_v[w] > b || (red_v[w] == b && red_i[w] < jp)) { b = red_v[w]; jp = red_i[w]; }
+    const double nr = sqrt(fmax(b, 0.0));
+    if (p == 0) r00 = nr;
+    if ((p > 0 && nr <= tol * r00) || (p == 0 && nr == 0.0)) { k = (p == 0) ? 1 : p; break; }
+    // swap columns p and jp, and stage the new column p (rows p..s-1) in LDS
+    for (int i = tid; i < s; i += NTQ) {
+      const cplx zp = Z[i + (size_t)p * s];
+      const cplx zj = Z[i + (size_t)jp * s];
+      if (jp != p) Z[i + (size_t)jp * s] = zp;
+      Z[i + (size_t)p * s] = zj;
+      if (i >= p) v[i] = zj;
+    }
+    if (tid == 0 && jp != p) {
+      double t = cn[p]; cn[p] = cn[jp]; cn[jp] = t;
+      int ti = perm[p]; perm[p] = perm[jp]; perm[jp] = ti;
     }
     __syncthreads();
-    if (sh_stop) { k = (p == 0) ? 1 : p; break; }
-    const int jp = sh_piv;
-    if (jp != p) {
-      for (int i = tid; i < s; i += NTQ) {
-        cplx t = Z[i + (size_t)p * s];
-        Z[i + (size_t)p * s] = Z[i + (size_t)jp * s];
-        Z[i + (size_t)jp * s] = t;
-      }
-      if (tid == 0) {
-        double t = cn[p]; cn[p] = cn[jp]; cn[jp] = t;
-        int ti = perm[p]; perm[p] = perm[jp]; perm[jp] = ti;
-      }
-    }
-    __syncthreads();
-    // Householder vector of x = Z[p:s, p]
-    for (int i = p + tid; i < s; i += NTQ) v[i] = Z[i + (size_t)p * s];
-    __syncthreads();
-    if (wv == 0) {
-      double a = 0.0;
-      for (int i = p + lane; i < s; i += 64) a += cabs2(v[i]);
-      a = wave_sum(a);
-      if (lane == 0) {
-        const double xn = sqrt(a);
-        const cplx x0 = v[p];
-        const double ax0 = sqrt(cabs2(x0));
-        cplx alpha = (ax0 > 0.0) ? cscale(x0, -xn / ax0) : mkc(-xn, 0.0);
-        const cplx v0 = csub(x0, alpha);
-        const double vn2 = a - ax0 * ax0 + cabs2(v0);
-        v[p] = v0;
-        sh_tau = (vn2 > 0.0) ? 2.0 / vn2 : 0.0;
-        Z[p + (size_t)p * s] = alpha;
-      }
-    }
-    __syncthreads();
-    const double tau = sh_tau;
-    // apply H = I - tau v v^* to columns j > p; recompute trailing norms
-    for (int j = p + 1 + wv; j < n; j += nw) {
-      cplx* col = Z + (size_t)j * s;
+    // Householder vector of x = Z[p:s, p] (every wavefront forms the same reduction)
+    double a = 0.0;
+    for (int i = p + lane; i < s; i += 64) a += cabs2(v[i]);
+    a = wave_sum(a);
+    const double xn = sqrt(a);
+    const cplx x0 = v[p];
+    const double ax0 = sqrt(cabs2(x0));
+    const cplx alpha = (ax0 > 0.0) ? cscale(x0, -xn / ax0) : mkc(-xn, 0.0);
+    const cplx v0 = csub(x0, alpha);
+    const double vn2 = a - ax0 * ax0 + cabs2(v0);
+    const double tau = (vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+    if (tid == 0) Z[p + (size_t)p * s] = alpha;
+    // apply H = I - tau v v^* to columns j > p (v[p] replaced by v0 in registers) and recompute
+    // the trailing norms.  Each 16-lane row of a wavefront takes one column, so one reduction
+    // instruction serves four columns.
+    const int sub = lane >> 4, rl = lane & 15;
+    for (int j0 = p + 1 + 4 * wv; j0 < n; j0 += 4 * nw) {
+      const int j = j0 + sub;
+      const bool act = j < n;
+      cplx* col = Z + (size_t)(act ? j : p) * s;
       cplx w = mkc(0, 0);
-      for (int i = p + lane; i < s; i += 64) w = cadd(w, cmul(cconj(v[i]), col[i]));
-      w = wave_csum(w);
-      w = cscale(w, tau);
-      double a = 0.0;
-      for (int i = p + lane; i < s; i += 64) {
-        cplx z = csub(col[i], cmul(w, v[i]));
-        col[i] = z;
-        if (i > p) a += cabs2(z);
-      }
-      a = wave_sum(a);
-      if (lane == 0) cn[j] = a;
+      if (act)
+        for (int i = p + rl; i < s; i += 16) w = cadd(w, cmul(cconj(i == p ? v0 : v[i]), col[i]));
+      w = cscale(row16_csum(w), tau);
+      double an = 0.0;
+      if (act)
+        for (int i = p + rl; i < s; i += 16) {
+          const cplx z = csub(col[i], cmul(w, i == p ? v0 : v[i]));
+          col[i] = z;
+          if (i > p) an += cabs2(z);
+        }
+      an = row16_sum(an);
+      if (act && rl == 0) cn[j] = an;
     }
     __syncthreads();
   }
-  // T = R11^{-1} R12 in place in Z[0:k, k:n], column-oriented back substitution
-  for (int i = k - 1; i >= 0; --i) {
-    const cplx zii = Z[i + (size_t)i * s];
-    const cplx rinv = cabs2(zii) > 0.0 ? cinv(zii) : mkc(0.0, 0.0);
-    for (int j = k + tid; j < n; j += NTQ) {
+  // T = R11^{-1} R12 in place in Z[0:k, k:n], by blocks of 64 rows from the bottom: the diagonal
+  // block is solved by one wavefront per column with the right-hand side in registers (the
+  // solved entry is broadcast with readlane), then the rows above are updated by all threads.
+  for (int i1 = k; i1 > 0; i1 -= 64) {
+    const int i0 = max(0, i1 - 64);
+    for (int j = k + wv; j < n; j += nw) {
       cplx* col = Z + (size_t)j * s;
-      col[i] = cmul(col[i], rinv);
+      const int l = i0 + lane;
+      cplx t = (l < i1) ? col[l] : mkc(0, 0);
+      for (int i = i1 - 1; i >= i0; --i) {
+        const int li = i - i0;
+        if (lane == li) {
+          const cplx zii = Z[i + (size_t)i * s];
+          t = cabs2(zii) > 0.0 ? cmul(t, cinv(zii)) : mkc(0, 0);
+        }
+        const long long bx = __double_as_longlong(t.x), by = __double_as_longlong(t.y);
+        const int xlo = __builtin_amdgcn_readlane((int)(bx & 0xffffffff), li), xhi = __builtin_amdgcn_readlane((int)(bx >> 32), li);
+        const int ylo = __builtin_amdgcn_readlane((int)(by & 0xffffffff), li), yhi = __builtin_amdgcn_readlane((int)(by >> 32), li);
+        const cplx ti = mkc(__longlong_as_double(((long long)xhi << 32) | (unsigned)xlo),
+                            __longlong_as_double(((long long)yhi << 32) | (unsigned)ylo));
+        if (lane < li) t = csub(t, cmul(Z[l + (size_t)i * s], ti));
+      }
+      if (l < i1) col[l] = t;
     }
     __syncthreads();
-    const int cnt = (n - k) * i;
-    for (int e = tid; e < cnt; e += NTQ) {
-      const int l = e % i, j = k + e / i;
-      cplx* col = Z + (size_t)j * s;
-      col[l] = csub(col[l], cmul(Z[l + (size_t)i * s], col[i]));
+    if (i0 > 0) {
+      const int rows = i0, cols = n - k;
+      for (int e = tid; e < rows * cols; e += NTQ) {
+        const int r = e % rows, j = k + e / rows;
+        cplx* col = Z + (size_t)j * s;
+        cplx acc = col[r];
+        for (int i = i0; i < i1; ++i) acc = csub(acc, cmul(Z[r + (size_t)i * s], col[i]));
+        col[r] = acc;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   for (int j = tid; j < n; j += NTQ) d.perm[j] = perm[j];
   if (tid == 0) k_out[blockIdx.x] = k;
@@ -613,9 +627,12 @@ hipError_t launch_sketch(const SketchDesc* d, int nd, int max_s, int max_n, uint
   hipLaunchKernelGGL(k_sketch, grid, dim3(NT), 0, s, d, seed);
   return hipGetLastError();
 }
-hipError_t launch_cpqr(const CpqrDesc* d, int nd, double tol, int* k_out, hipStream_t s) {
+hipError_t launch_cpqr(const CpqrDesc* d, int nd, int max_s, int max_n, double tol, int* k_out, hipStream_t s) {
   if (nd == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cpqr, dim3(nd), dim3(NTQ), 0, s, d, tol, k_out);
+  if (nd >= 256 && max_s <= 512 && max_n <= 256)
+    hipLaunchKernelGGL((k_cpqr<256, 512, 256>), dim3(nd), dim3(256), 0, s, d, tol, k_out);
+  else
+    hipLaunchKernelGGL((k_cpqr<1024, CPQR_MAXS, CPQR_MAXN>), dim3(nd), dim3(1024), 0, s, d, tol, k_out);
   return hipGetLastError();
 }
 hipError_t launch_buildP(const PDesc* d, int nd, int max_elems, hipStream_t s) {

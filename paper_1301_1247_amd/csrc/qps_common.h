@@ -91,6 +91,15 @@ __device__ inline double wave_sum(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 __device__ inline cplx wave_csum(cplx v) { return mkc(wave_sum(v.x), wave_sum(v.y)); }
+// sum over each 16-lane row of the wavefront (every lane of the row gets its row's sum)
+__device__ inline double row16_sum(double v) {
+  v += dpp_d<0xB1, 0xF>(v);
+  v += dpp_d<0x4E, 0xF>(v);
+  v += dpp_d<0x141, 0xF>(v);
+  v += dpp_d<0x140, 0xF>(v);
+  return v;
+}
+__device__ inline cplx row16_csum(cplx v) { return mkc(row16_sum(v.x), row16_sum(v.y)); }
 // Wavefront max / min of an unsigned value with DPP moves (quad swaps, half-row and row
 // mirrors, row broadcasts 15 and 31), result read from lane 63: no LDS round trips.
 __device__ inline unsigned wave_umax(unsigned v) {
