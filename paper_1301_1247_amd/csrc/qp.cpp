@@ -388,17 +388,21 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     if (fastU) {
       CR(apply_inverse_root(h, Y + (size_t)ycolB * N, N, X + (size_t)ycolB * N, N, nang, Zt + (size_t)nu * nu, nu));
       CK(hipMemcpyAsync(Zt, h->Rinv.p, sizeof(cplx) * (size_t)nu * nu, hipMemcpyDeviceToDevice, st));
-      CR(apply_down_E(h, Zt, nu, X + (size_t)ycolU * N, N, nu));
+      // V itself is needed only with neighbour images; without them X(alpha) xi = V (B_J v) is
+      // applied as E_L ... E_1 (R^{-1} B_J v) where needed
+      if (P) CR(apply_down_E(h, Zt, nu, X + (size_t)ycolU * N, N, nu));
     } else {
       CR(apply_factors(h, true, Y, N, X, N, Wy));
       CR(apply_interp_t(h, X, N, Zt, nu, Wy));
     }
-    CR(gemm({gd(Zt, nu, 0, BJ, nu, Xc, nu, nu, M4, nu, onec, zero)}));
+    // the Woodbury form of S^{-1} uses only the b (and U) columns of C [X_L | X_R | X_b | V]:
+    // G[:, b | U] = C_J [U^T X_b | H]
     CK(hipMemcpyAsync(Xc + (size_t)colB * nu, Zt + (size_t)nu * nu, sizeof(cplx) * (size_t)nu * nang,
                       hipMemcpyDeviceToDevice, st));
     if (P) CK(hipMemcpyAsync(Xc + (size_t)colU * nu, Zt, sizeof(cplx) * (size_t)nu * nu, hipMemcpyDeviceToDevice, st));
-    std::vector<GemmDesc> g = {gd(C1, M2, 0, Xc, nu, G1, M2, M2, (int)W, nu, onec, zero),
-                               gd(C2, M2, 0, Xc, nu, G2, M2, M2, (int)W, nu, onec, zero)};
+    const int wbu = nang + nr;
+    std::vector<GemmDesc> g = {gd(C1, M2, 0, Xc + (size_t)colB * nu, nu, G1 + (size_t)colB * M2, M2, M2, wbu, nu, onec, zero),
+                               gd(C2, M2, 0, Xc + (size_t)colB * nu, nu, G2 + (size_t)colB * M2, M2, M2, wbu, nu, onec, zero)};
     if (P) {
       g.push_back(gd(Rp, nr, 0, X, N, RZp, nr, nr, (int)Wy, N, onec, zero));
       g.push_back(gd(Rm, nr, 0, X, N, RZm, nr, nr, (int)Wy, N, onec, zero));
@@ -583,6 +587,13 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   auto sub_Xv = [&](const cplx* v, cplx* out) -> int {
     if (!cw) return gemm({gd(X, N, 0, v, M4, out, N, N, nang, M4, minus1c, onec)});
     CR(gemm({gd(BJ, nu, 0, v, M4, t1, nu, nu, nang, M4, onec, zero)}));
+    if (fastU && !P) {
+      // V t1 = E_L ... E_1 (R^{-1} t1)
+      CR(gemm({gd(Zt, nu, 0, t1, nu, t2, nu, nu, nang, nu, onec, zero)}));
+      CR(apply_down_E(h, t2, nu, tN, N, nang));
+      CK(launch_axpby(N, nang, minus1c, tN, N, onec, out, N, st));
+      return HBS_OK;
+    }
     return gemm({gd(Vc, N, 0, t1, nu, out, N, N, nang, nu, minus1c, onec)});
   };
   // out -= B(alpha) xi = [B_L | B_R] v, or U (B_J v)
