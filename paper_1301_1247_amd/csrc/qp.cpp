@@ -246,7 +246,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       sizeof(cplx) * (size_t)nrr * nang * 4,         // 19 R b, u, y, misc (nr x nang)
       cw ? sizeof(cplx) * ((size_t)nuu * (M4 + W + Wy + 2 * nang) + (size_t)nr * Wy * 2 + (size_t)N * nang) : 0,
                                                      // 20 B_J, X_c, U^T X, t1, t2, R_{+-1} X, U t
-      cw ? sizeof(cplx) * ((size_t)ng * (2 * (size_t)nuu * M2 + 3 * (size_t)nuu * nuu) + (size_t)M2 * nuu +
+      cw ? sizeof(cplx) * ((size_t)ng * (2 * (size_t)nuu * M2 + 3 * (size_t)nuu * nuu) + 3 * (size_t)M2 * nuu +
                            (size_t)M2 * nang + 2 * (size_t)nuu * nang) : 0};
                                                      // 21 Woodbury form of S^{-1}: B_J(alpha), Q^{-1} C~ H~, K2, H~,
                                                      //    scratch; C~_J H~; Q^{-1} r; two nu x nang
@@ -319,7 +319,9 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   cplx* Ht = K2 + (size_t)ng * nuu * nuu;   // per group nu x nu: U^T A~^{-1} U
   cplx* Hs = Ht + (size_t)ng * nuu * nuu;   // per group nu x nu scratch
   cplx* CH = Hs + (size_t)ng * nuu * nuu;   // 2M x nu
-  cplx* yq = CH + (size_t)M2 * nuu;         // 2M x nang
+  cplx* C1H = CH + (size_t)M2 * nuu;        // 2M x nu: C1_J H (shared by the phases when P = 0)
+  cplx* C2H = C1H + (size_t)M2 * nuu;       // 2M x nu: C2_J H
+  cplx* yq = C2H + (size_t)M2 * nuu;        // 2M x nang
   cplx* zq = yq + (size_t)M2 * nang;        // nu x nang
   cplx* zq2 = zq + (size_t)nuu * nang;      // nu x nang
 
@@ -514,13 +516,23 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       }
       CR(gemm(g2));
     }
-    for (int g = 0; g < ng; ++g) {
-      const cplx* Hg = P ? Ht + (size_t)g * nu * nu : H;
-      // C~_J(alpha) = c1 C1_J + c2 C2_J (staged in Cq), then Cq = Q^{-1} C~_J H~
-      cplx* cq = Cq + (size_t)g * M2 * nu;
-      CK(launch_lincomb(M2, nu, d_gco + 3 * g + 1, d_gco + 3 * g + 2, 0, C1, M2, C2, M2, nullptr, 0, cq, M2, st));
-      CR(gemm({gd(cq, M2, 0, Hg, nu, CH, M2, M2, nu, nu, onec, zero)}));
-      CK(launch_qsolve(Q, d_gco + 3 * g, 0, nu, CH, M2, cq, M2, st));
+    if (!P) {
+      // H~ = H for every phase: C~_J H = c1 (C1_J H) + c2 (C2_J H)
+      CR(gemm({gd(C1, M2, 0, H, nu, C1H, M2, M2, nu, nu, onec, zero), gd(C2, M2, 0, H, nu, C2H, M2, M2, nu, nu, onec, zero)}));
+      for (int g = 0; g < ng; ++g) {
+        cplx* cq = Cq + (size_t)g * M2 * nu;
+        CK(launch_lincomb(M2, nu, d_gco + 3 * g + 1, d_gco + 3 * g + 2, 0, C1H, M2, C2H, M2, nullptr, 0, CH, M2, st));
+        CK(launch_qsolve(Q, d_gco + 3 * g, 0, nu, CH, M2, cq, M2, st));
+      }
+    } else {
+      for (int g = 0; g < ng; ++g) {
+        const cplx* Hg = Ht + (size_t)g * nu * nu;
+        // C~_J(alpha) = c1 C1_J + c2 C2_J (staged in Cq), then Cq = Q^{-1} C~_J H~
+        cplx* cq = Cq + (size_t)g * M2 * nu;
+        CK(launch_lincomb(M2, nu, d_gco + 3 * g + 1, d_gco + 3 * g + 2, 0, C1, M2, C2, M2, nullptr, 0, cq, M2, st));
+        CR(gemm({gd(cq, M2, 0, Hg, nu, CH, M2, M2, nu, nu, onec, zero)}));
+        CK(launch_qsolve(Q, d_gco + 3 * g, 0, nu, CH, M2, cq, M2, st));
+      }
     }
     {
       std::vector<GemmDesc> g1;
