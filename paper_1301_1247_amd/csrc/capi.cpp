@@ -151,6 +151,7 @@ const char* hbs_last_error(void) { return qps::last_error(); }
 
 int hbs_build(const double* nodes, const double* weights, const double* normals, int64_t N, double omega, double tol,
               const hbs_opts* opts, hbs_handle** out) {
+  PoolQuiesce pq_;  // retired device buffers become reusable once the call is done
   clear_error();
   if (!out) { set_error("hbs_build: out is NULL"); return HBS_E_INVALID_ARG; }
   *out = nullptr;
@@ -305,10 +306,12 @@ static int apply_common(hbs_handle* h, const double* in, int64_t nrhs, double* o
 }
 
 int hbs_apply(hbs_handle* h, const double* rhs, int64_t nrhs, double* out, int32_t refine) {
+  PoolQuiesce pq_;  // retired device buffers become reusable once the call is done
   return apply_common(h, rhs, nrhs, out, true, refine);
 }
 
 int hbs_forward(hbs_handle* h, const double* x, int64_t nrhs, double* out) {
+  PoolQuiesce pq_;  // retired device buffers become reusable once the call is done
   return apply_common(h, x, nrhs, out, false, 0);
 }
 
@@ -371,11 +374,13 @@ static int qp_common(hbs_handle* h, double period, const double* thetas, int64_t
 int qp_solve(hbs_handle* h, double period, double alpha_re, double alpha_im, const double* thetas, int64_t q,
              const qp_opts* opts, double* eta, double* xi, double* bragg, int32_t* nlo_out, int32_t* n_modes_out,
              double* flux_err) {
+  PoolQuiesce pq_;  // retired device buffers become reusable once the call is done
   return qp_common(h, period, thetas, q, opts, true, alpha_re, alpha_im, eta, xi, bragg, nlo_out, n_modes_out, flux_err);
 }
 
 int qp_solve_many(hbs_handle* h, double period, const double* thetas, int64_t n, const qp_opts* opts, double* eta,
                   double* xi, double* bragg, int32_t* nlo_out, int32_t* n_modes_out, double* flux_err) {
+  PoolQuiesce pq_;  // retired device buffers become reusable once the call is done
   return qp_common(h, period, thetas, n, opts, false, 0, 0, eta, xi, bragg, nlo_out, n_modes_out, flux_err);
 }
 
@@ -408,9 +413,13 @@ int hbs_stats(const hbs_handle* h, hbs_stats_t* s) {
   return HBS_OK;
 }
 
-void hbs_free(hbs_handle* h) { delete h; }
+void hbs_free(hbs_handle* h) {
+  PoolQuiesce pq_;
+  delete h;
+}
 
 int qps_hankel01(const double* x, int64_t n, double* out, int32_t ptr_mode) {
+  PoolQuiesce pq_;  // retired device buffers become reusable once the call is done
   clear_error();
   if (!x || !out || n < 0) { set_error("qps_hankel01: bad arguments"); return HBS_E_INVALID_ARG; }
   if (n == 0) return HBS_OK;
@@ -437,6 +446,7 @@ int qps_kr6_corrections(double out[6]) {
 }
 
 int qps_matrix_entries(hbs_handle* h, const int32_t* rows, const int32_t* cols, int64_t n, double* out) {
+  PoolQuiesce pq_;  // retired device buffers become reusable once the call is done
   clear_error();
   if (!h || !rows || !cols || !out || n < 0) { set_error("qps_matrix_entries: bad arguments"); return HBS_E_INVALID_ARG; }
   if (n == 0) return HBS_OK;
@@ -464,6 +474,7 @@ namespace {
 template <class R>
 int gemm_diag(const char* name, const R* A, const R* B, R* C, int32_t m, int32_t n, int32_t k, int32_t nbatch,
               int32_t transA, int32_t accumulate, int32_t ptr_mode) {
+  PoolQuiesce pq_;  // retired device buffers become reusable once the call is done
   typedef typename cx<R>::T T;
   clear_error();
   if (!A || !B || !C || m <= 0 || n <= 0 || k < 0 || nbatch <= 0) { set_error(std::string(name) + ": bad arguments"); return HBS_E_INVALID_ARG; }
@@ -501,6 +512,7 @@ int gemm_diag(const char* name, const R* A, const R* B, R* C, int32_t m, int32_t
 
 template <class R>
 int inv_diag(const char* name, R* A, int32_t n, int32_t nbatch, int32_t ptr_mode) {
+  PoolQuiesce pq_;  // retired device buffers become reusable once the call is done
   typedef typename cx<R>::T T;
   clear_error();
   if (!A || n <= 0 || nbatch <= 0) { set_error(std::string(name) + ": bad arguments"); return HBS_E_INVALID_ARG; }
@@ -592,6 +604,7 @@ bool mlp_args_ok(const char* name, const void* params, const void* x, int64_t n,
 }  // namespace
 
 int qps_mlp_forward(const float* params, const float* x, int64_t n, float* y, int32_t ptr_mode) {
+  PoolQuiesce pq_;  // retired device buffers become reusable once the call is done
   clear_error();
   if (!mlp_args_ok("qps_mlp_forward", params, x, n, ptr_mode) || !y) return HBS_E_INVALID_ARG;
   FStage P, X, Y;
@@ -606,6 +619,7 @@ int qps_mlp_forward(const float* params, const float* x, int64_t n, float* y, in
 
 int qps_mlp_grad(const float* params, const float* x, const float* t, int64_t n, float tau, float* grad, float* loss,
                  int32_t ptr_mode) {
+  PoolQuiesce pq_;  // retired device buffers become reusable once the call is done
   clear_error();
   if (!mlp_args_ok("qps_mlp_grad", params, x, n, ptr_mode) || !t || !grad || !loss) return HBS_E_INVALID_ARG;
   if (!(tau > 0.f && tau < 1.f)) { set_error("qps_mlp_grad: tau must lie in (0, 1)"); return HBS_E_INVALID_ARG; }
@@ -625,6 +639,7 @@ int qps_mlp_grad(const float* params, const float* x, const float* t, int64_t n,
 
 int qps_mlp_train(float* params, const float* x, const float* t, int64_t n, float tau, int32_t steps, float lr, float* loss_hist,
                   int32_t ptr_mode) {
+  PoolQuiesce pq_;  // retired device buffers become reusable once the call is done
   clear_error();
   if (!mlp_args_ok("qps_mlp_train", params, x, n, ptr_mode) || !t || steps < 0 || !(lr > 0.f)) return HBS_E_INVALID_ARG;
   if (!(tau > 0.f && tau < 1.f)) { set_error("qps_mlp_train: tau must lie in (0, 1)"); return HBS_E_INVALID_ARG; }

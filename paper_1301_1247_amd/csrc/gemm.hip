@@ -217,6 +217,31 @@ hipError_t launch_cast_f2d(const cplxf* src, cplx* dst, int64_t n, hipStream_t s
 template <class R>
 static int tiles_of(const GemmDescT<R>& g) { return ((g.m + BM - 1) / BM) * ((g.n + BN - 1) / BN); }
 
+// split-K when there are too few output tiles to occupy the chip and the inner dimension is
+// long: partial products go to a workspace and a second kernel sums them in a fixed order.  A
+// descriptor with few tiles and a long inner dimension is the critical path of its launch.
+template <class R>
+static int split_of(const GemmDescT<R>& g) {
+  const int64_t target = 1024;
+  const int64_t tg = tiles_of(g);
+  if (tg >= target / 2 || g.k < 4096) return 1;
+  int S = (int)std::min<int64_t>(64, (target + tg - 1) / tg);
+  S = std::min(S, g.k / 1024);
+  return S >= 2 ? S : 1;
+}
+
+template <class R>
+void gemm_batched_needs(const std::vector<GemmDescT<R>>& v, size_t* arena_bytes, size_t* ws_bytes) {
+  size_t nd = 0, w = 0;
+  for (const auto& g : v) {
+    const int S = split_of(g);
+    nd += S;
+    if (S > 1) w += (size_t)S * g.m * g.n;
+  }
+  *arena_bytes = nd * sizeof(GemmDescT<R>);
+  *ws_bytes = w * sizeof(typename cx<R>::T);
+}
+
 template <class R>
 hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDescT<R>>& v0, hipStream_t s, DevBuf* ws) {
   typedef typename cx<R>::T C_t;
@@ -229,23 +254,12 @@ hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDescT<R>>& v0, hipS
     bytes += 2.0 * sizeof(R) * ((double)g.m * g.k + (double)g.k * g.n + 2.0 * g.m * g.n);
     total_tiles += tiles_of(g);
   }
-  // split-K when there are too few output tiles to occupy the chip and the inner dimension is
-  // long: partial products go to a workspace and a second kernel sums them in a fixed order.
-  const int64_t target = 1024;
+  (void)total_tiles;
   std::vector<int> split(v0.size(), 1);
   int64_t wtot = 0;
-  (void)total_tiles;
   for (size_t i = 0; i < v0.size(); ++i) {
-    const GemmDesc& g = v0[i];
-    // a descriptor with few tiles and a long inner dimension is the critical path of the launch
-    const int64_t tg = tiles_of(g);
-    if (!ws || tg >= target / 2 || g.k < 4096) continue;
-    int S = (int)std::min<int64_t>(64, (target + tg - 1) / tg);
-    S = std::min(S, g.k / 1024);
-    if (S >= 2) {
-      split[i] = S;
-      wtot += (int64_t)S * g.m * g.n;
-    }
+    split[i] = ws ? split_of(v0[i]) : 1;
+    if (split[i] > 1) wtot += (int64_t)split[i] * v0[i].m * v0[i].n;
   }
   if (wtot > 0) {
     hipError_t e = ws->reserve(sizeof(C_t) * wtot);
@@ -295,6 +309,8 @@ hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDescT<R>>& v0, hipS
   }
   return hipGetLastError();
 }
+template void gemm_batched_needs<double>(const std::vector<GemmDesc>&, size_t*, size_t*);
+template void gemm_batched_needs<float>(const std::vector<GemmDesc32>&, size_t*, size_t*);
 template hipError_t gemm_batched<double>(DevBuf&, const std::vector<GemmDesc>&, hipStream_t, DevBuf*);
 template hipError_t gemm_batched<float>(DevBuf&, const std::vector<GemmDesc32>&, hipStream_t, DevBuf*);
 

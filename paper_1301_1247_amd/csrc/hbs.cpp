@@ -953,7 +953,8 @@ struct Step {
 };
 }  // namespace
 
-static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r) {
+static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r,
+                       bool sync = true) {
   if (r <= 0) return HBS_OK;
   hipStream_t st = h->stream;
   const int L = h->L;
@@ -1174,7 +1175,7 @@ static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_
       ProfScope ps("apply", st, fl, 0.0);
       CK(hipGraphLaunch(g->exec, st));
     }
-    CK(hipStreamSynchronize(st));
+    if (sync) CK(hipStreamSynchronize(st));
     return HBS_OK;
   }
   CK(upload(h->arena, d64, st));
@@ -1183,7 +1184,7 @@ static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_
     ProfScope ps("apply", st, fl, 0.0);
     CK(issue(h->arena.as<GemmDesc>(), d32.empty() ? nullptr : h->arena32.as<GemmDesc32>(), st, true));
   }
-  CK(hipStreamSynchronize(st));
+  if (sync) CK(hipStreamSynchronize(st));
   return HBS_OK;
 }
 
@@ -1195,8 +1196,9 @@ int apply_inverse(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ld
   return apply_mixed(h, true, h->fp64_top, B, ldb, X, ldx, r);
 }
 
-int apply_inverse_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r, cplx* root, int64_t ldr) {
-  int rc = apply_mixed(h, true, h->fp64_top, B, ldb, X, ldx, r);
+int apply_inverse_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r, cplx* root, int64_t ldr,
+                       bool sync) {
+  int rc = apply_mixed(h, true, h->fp64_top, B, ldb, X, ldx, r, sync);
   if (rc != HBS_OK || r <= 0) return rc;
   // the root solution of the apply (still in the root workspace) is U^T A^{-1} B
   const int64_t n = h->nroot;
@@ -1206,7 +1208,15 @@ int apply_inverse_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64
     CK(hipMemcpy2DAsync(root, sizeof(cplx) * ldr, h->ab_root.p, sizeof(cplx) * n, sizeof(cplx) * n, r,
                         hipMemcpyDeviceToDevice, h->stream));
   }
-  CK(hipStreamSynchronize(h->stream));
+  if (sync) CK(hipStreamSynchronize(h->stream));
+  return HBS_OK;
+}
+
+int side_stream_init(hbs_handle* h) {
+  if (h->side_stream) return HBS_OK;
+  // default priority, like every other stream of the library
+  CK(hipStreamCreateWithFlags(&h->side_stream, hipStreamNonBlocking));
+  for (auto& e : h->side_ev) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return HBS_OK;
 }
 
@@ -1216,4 +1226,7 @@ hbs_handle::~hbs_handle() {
   for (auto& g : graphs)
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  for (auto e : side_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (side_stream) (void)hipStreamDestroy(side_stream);
 }

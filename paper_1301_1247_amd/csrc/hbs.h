@@ -62,6 +62,11 @@ struct hbs_handle {
   qps::DevBuf ab_in32, ab_up32, ab_x32a, ab_x32b;    // complex64 stage of a mixed-precision inverse apply
   std::vector<std::unique_ptr<ApplyGraph>> graphs;   // hbs_opts.graph: captured applies (at most 4)
   hipStream_t cap_stream = nullptr;                 // private stream the applies are captured on
+  // second stream for work that does not depend on a concurrent apply, with its own descriptor
+  // arena and workspaces; side_ev: [ready on the main stream, done on the side stream]
+  hipStream_t side_stream = nullptr;
+  hipEvent_t side_ev[2] = {nullptr, nullptr};
+  qps::DevBuf arena_s, splitws_s, work_s;
   int64_t graph_captures = 0, graph_replays = 0;
   hbs_stats_t stats{};
   double c0x = 0, c0y = 0, robs = 0;  // obstacle centre and radius about it
@@ -80,7 +85,11 @@ int apply_interp_t(hbs_handle* h, const cplx* X, int64_t ldx, cplx* Z, int64_t l
 // X = E_L ... E_1 Z (complex128 levels only): A^{-1} U from Z = R^{-1}
 int apply_down_E(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx, int64_t r);
 // X = A^{-1} B and root (nroot x r) = U^T A^{-1} B, the root solution of the same apply
-int apply_inverse_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r, cplx* root, int64_t ldr);
+// (sync = false leaves the work stream-ordered on the handle's stream without waiting for it)
+int apply_inverse_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r, cplx* root, int64_t ldr,
+                       bool sync = true);
+// create the side stream and its two events on first use
+int side_stream_init(hbs_handle* h);
 int qp_max_modes_impl(double om, double period);
 struct QPPlan;
 int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, const qp_opts* o, cplx* eta_out,

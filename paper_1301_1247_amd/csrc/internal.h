@@ -103,6 +103,11 @@ struct DevBuf {
 };
 
 int pool_release_current();      // return the current device's cached blocks to the device
+void pool_quiesce_current();      // make retired blocks reusable (one device sync if any are pending)
+// at the end of every library call that may release device buffers
+struct PoolQuiesce {
+  ~PoolQuiesce() { pool_quiesce_current(); }
+};
 size_t pool_cached_current();     // bytes cached for the current device
 
 // upload a descriptor array into a growing device arena
@@ -154,5 +159,15 @@ template <class R>
 hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDescT<R>>& v, hipStream_t s, DevBuf* ws = nullptr);
 template <class R>
 hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R>>& v, hipStream_t s, bool* singular);
+// the same without waiting: *dinfo receives the device address of the nd singularity flags (in
+// work, valid once stream s has passed this point and until work is used again)
+template <class R>
+hipError_t inv_batched_async(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R>>& v, hipStream_t s, int** dinfo);
+// bytes that gemm_batched / inv_batched reserve in their arena and workspace for a descriptor set
+// (reserving them beforehand keeps those calls from touching the pool while other streams run)
+template <class R>
+void gemm_batched_needs(const std::vector<GemmDescT<R>>& v, size_t* arena_bytes, size_t* ws_bytes);
+template <class R>
+void inv_batched_needs(const std::vector<InvDescT<R>>& v, size_t* arena_bytes, size_t* work_bytes);
 
 }  // namespace qps

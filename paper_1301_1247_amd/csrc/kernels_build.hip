@@ -392,9 +392,15 @@ __global__ __launch_bounds__(NTP) void k_gj_panel(const InvDescT<R>* __restrict_
   }
 }
 
-// Register-resident variant for n <= 1024: thread i holds row i of the NBR-column panel, so a
-// pivot step costs two barriers and broadcasts of one row through LDS (no global traffic).  The
-// workgroup has as many whole wavefronts as the largest matrix of the batch has rows.
+// Register-resident variant for n <= 1024: thread i holds row i of the NBR-column panel, and a
+// pivot step costs one barrier.  Before it, every wavefront publishes its best candidate (a key
+// holding |a|^2 with the row index in its low 11 bits, so one 64-bit max finds the pivot, ties
+// going to the smaller row) together with that candidate's whole row, and the thread of row p
+// publishes row p; after it, every thread picks the winning wavefront and reads the pivot row
+// from LDS.  The LDS slots alternate between two buffers from step to step: a wavefront can be
+// at most one step ahead of another.  Dropping the 11 low mantissa bits of |a|^2 only lets
+// candidates within a relative 2^-41 of each other count as equal.
+// The workgroup has as many whole wavefronts as the largest matrix of the batch has rows.
 // The pivot steps are instantiated per column (template recursion) so that every access to
 // the row array has a constant index and the row stays in registers.
 constexpr int GJ_NBR = 16;
@@ -402,87 +408,143 @@ constexpr int NTP_REG = 1024;
 
 template <class R>
 struct GjShared {
-  double red_v[NTP_REG / 64];
-  int red_i[NTP_REG / 64];
-  typename cx<R>::T rowp[GJ_NBR];  // the pivot row before scaling
-  typename cx<R>::T rowo[GJ_NBR];  // the old row p (moves to the pivot's row)
+  unsigned long long key[2][NTP_REG / 64];
+  typename cx<R>::T cand[2][NTP_REG / 64][GJ_NBR];  // each wavefront's candidate pivot row
+  typename cx<R>::T rowo[2][GJ_NBR];                 // row p before the step
 };
 
 template <class R, int JJ>
 __device__ __forceinline__ void gj_pivot_steps(typename cx<R>::T (&a)[GJ_NBR], GjShared<R>& sh, int c0, int w, int n,
-                                               int* __restrict__ ipiv, int* __restrict__ info) {
+                                               int* __restrict__ ipiv, int* __restrict__ info_m) {
   typedef typename cx<R>::T C_t;
   if (JJ < w) {
+    constexpr int buf = JJ & 1;
     const int i = threadIdx.x, lane = i & 63, wv = i >> 6;
     const C_t zero = cx<R>::make(0.0, 0.0);
     const int p = c0 + JJ;
-    double bv = (i >= p && i < n) ? (double)cabs2(a[JJ]) : -1.0;
-    int bi = (i >= p && i < n) ? i : n;
-    wave_argmax(bv, bi);
-    if (lane == 0) { sh.red_v[wv] = bv; sh.red_i[wv] = bi; }
-    __syncthreads();
-    double b = sh.red_v[0];
-    int r = sh.red_i[0];
-    const int nwv = blockDim.x >> 6;
-    for (int q = 1; q < nwv; ++q)
-      if (sh.red_v[q] > b || (sh.red_v[q] == b && sh.red_i[q] < r)) { b = sh.red_v[q]; r = sh.red_i[q]; }
-    if (!(b > 0.0)) r = p;
-    if (i == r) {
-#pragma unroll
-      for (int j = 0; j < GJ_NBR; ++j) sh.rowp[j] = a[j];
+    unsigned long long key = 0;
+    if (i >= p && i < n) {
+      const double v = (double)cabs2(a[JJ]);
+      key = ((unsigned long long)__double_as_longlong(v) & ~0x7FFull) | (unsigned long long)(0x7FF - i);
     }
+    const unsigned long long wk = wave_umax64(key);
+    if (wk != 0 && key == wk) {
+#pragma unroll
+      for (int j = 0; j < GJ_NBR; ++j) sh.cand[buf][wv][j] = a[j];
+    }
+    if (lane == 0) sh.key[buf][wv] = wk;
     if (i == p) {
 #pragma unroll
-      for (int j = 0; j < GJ_NBR; ++j) sh.rowo[j] = a[j];
-    }
-    if (i == 0) {
-      ipiv[p] = r;
-      if (!(b > 0.0)) info[blockIdx.x] = p + 1;
+      for (int j = 0; j < GJ_NBR; ++j) sh.rowo[buf][j] = a[j];
     }
     __syncthreads();
-    const C_t piv = sh.rowp[JJ];
+    unsigned long long best = sh.key[buf][0];
+    const int nwv = blockDim.x >> 6;
+    for (int q = 1; q < nwv; ++q) {
+      const unsigned long long kq = sh.key[buf][q];
+      best = kq > best ? kq : best;
+    }
+    const bool ok = (best >> 11) != 0;  // a nonzero pivot exists
+    const int r = ok ? 0x7FF - (int)(best & 0x7FF) : p;
+    const C_t* prow = ok ? sh.cand[buf][r >> 6] : sh.rowo[buf];
+    if (i == 0) {
+      ipiv[p] = r;
+      if (!ok) *info_m = p + 1;
+    }
+    const C_t piv = prow[JJ];
     const C_t dd = (cabs2(piv) > 0) ? cinv(piv) : zero;
     if (i == p) {
 #pragma unroll
-      for (int j = 0; j < GJ_NBR; ++j) a[j] = (j == JJ) ? dd : cmul(sh.rowp[j], dd);
+      for (int j = 0; j < GJ_NBR; ++j) a[j] = (j == JJ) ? dd : cmul(prow[j], dd);
     } else if (i < n) {
       if (i == r) {
 #pragma unroll
-        for (int j = 0; j < GJ_NBR; ++j) a[j] = sh.rowo[j];
+        for (int j = 0; j < GJ_NBR; ++j) a[j] = sh.rowo[buf][j];
       }
       const C_t f = a[JJ];
       const C_t fd = cmul(f, dd);
 #pragma unroll
       for (int j = 0; j < GJ_NBR; ++j)
-        if (j != JJ) a[j] = csub(a[j], cmul(fd, sh.rowp[j]));
+        if (j != JJ) a[j] = csub(a[j], cmul(fd, prow[j]));
       a[JJ] = cx<R>::make(-fd.x, -fd.y);
     }
-    if constexpr (JJ + 1 < GJ_NBR) gj_pivot_steps<R, JJ + 1>(a, sh, c0, w, n, ipiv, info);
+    if constexpr (JJ + 1 < GJ_NBR) gj_pivot_steps<R, JJ + 1>(a, sh, c0, w, n, ipiv, info_m);
   }
 }
 
+// Applies panel [cp, cp + wp) of the register Gauss-Jordan inversion to the 16-column strip at cs,
+// for the calling thread's row i, into a[]: the panel's row interchanges as one gather
+// (sigma(i) = s_1(s_2(... s_wp(i))) for the interchanges s_t in the order they were made), then
+// strip = mask(strip) + A[:, panel] T with T the interchanged strip's pivot rows cp.. and mask
+// zeroing those rows.  The whole workgroup calls it (two barriers); one workgroup owns the strip.
 template <class R>
-__global__ __launch_bounds__(NTP_REG) void k_gj_panel_reg(const InvDescT<R>* __restrict__ descs, int c0, int* __restrict__ ipiv_all,
-                                                          int maxn, int* __restrict__ info) {
+__device__ __forceinline__ void gj_strip_update(const InvDescT<R>& d, int n, int cp, int cs, int ws, const int* __restrict__ ipiv,
+                                                typename cx<R>::T (&a)[GJ_NBR], typename cx<R>::T (*T)[GJ_NBR], int* sp) {
   typedef typename cx<R>::T C_t;
-  const InvDescT<R> d = descs[blockIdx.x];
-  const int n = d.n;
-  if (c0 >= n) return;
-  const int w = min(GJ_NBR, n - c0);
-  const int ld = d.ld;
-  C_t* A = d.a;
-  int* ipiv = ipiv_all + (size_t)blockIdx.x * maxn;
-  __shared__ GjShared<R> sh;
   const int i = threadIdx.x;
-  const C_t zero = cx<R>::make(0.0, 0.0);
-  C_t a[GJ_NBR];
+  const int wp = min(GJ_NBR, n - cp);
+  const int ld = d.ld;
+  if (i < wp) sp[i] = ipiv[cp + i];
+  __syncthreads();
+  int src = i;
+  for (int t = wp - 1; t >= 0; --t) {
+    const int p = cp + t, r = sp[t];
+    src = (src == p) ? r : (src == r ? p : src);
+  }
 #pragma unroll
-  for (int j = 0; j < GJ_NBR; ++j) a[j] = (i < n && j < w) ? A[i + (size_t)(c0 + j) * ld] : zero;
-  gj_pivot_steps<R, 0>(a, sh, c0, w, n, ipiv, info);
+  for (int j = 0; j < GJ_NBR; ++j) a[j] = (i < n && j < ws) ? d.a[src + (size_t)(cs + j) * ld] : cx<R>::make(0.0, 0.0);
+  if (i >= cp && i < cp + wp) {
+#pragma unroll
+    for (int j = 0; j < GJ_NBR; ++j) {
+      T[i - cp][j] = a[j];
+      a[j] = cx<R>::make(0.0, 0.0);
+    }
+  }
+  // the strip is permuted in place: every gather load has landed before any row is stored
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (i < n) {
+    for (int q = 0; q < wp; ++q) {
+      const C_t f = d.a[i + (size_t)(cp + q) * ld];
+#pragma unroll
+      for (int j = 0; j < GJ_NBR; ++j) a[j] = cfma(f, T[q][j], a[j]);
+    }
+  }
+}
+
+// One step of the register Gauss-Jordan inversion with look-ahead: workgroup x = 0 brings the
+// strip of panel c0 up to date with panel cp and factors it in registers; workgroups x >= 1 each
+// apply panel cp to one other 16-column strip (all of its rows).  Launched for c0 = 0, 16, ...
+// up to and including the first c0 >= n (then only the updates run); cp = c0 - 16.
+template <class R>
+__global__ __launch_bounds__(NTP_REG) void k_gj_step(const InvDescT<R>* __restrict__ descs, int cp, int c0, int* __restrict__ ipiv_all,
+                                                     int maxn, int* __restrict__ info) {
+  typedef typename cx<R>::T C_t;
+  const InvDescT<R> d = descs[blockIdx.y];
+  const int n = d.n;
+  const bool panel = blockIdx.x == 0;
+  const int cs = panel ? c0 : GJ_NBR * (int)(blockIdx.x - 1);
+  if (cs >= n) return;
+  if (!panel && (cp < 0 || cp >= n || cs == cp || cs == c0)) return;
+  int* ipiv = ipiv_all + (size_t)blockIdx.y * maxn;
+  __shared__ GjShared<R> sh;
+  __shared__ C_t T[GJ_NBR][GJ_NBR];
+  __shared__ int sp[GJ_NBR];
+  const int i = threadIdx.x;
+  const int ld = d.ld;
+  const int ws = min(GJ_NBR, n - cs);
+  C_t a[GJ_NBR];
+  if (cp >= 0) {
+    gj_strip_update<R>(d, n, cp, cs, ws, ipiv, a, T, sp);
+  } else {
+#pragma unroll
+    for (int j = 0; j < GJ_NBR; ++j) a[j] = (i < n && j < ws) ? d.a[i + (size_t)(cs + j) * ld] : cx<R>::make(0.0, 0.0);
+  }
+  if (panel) gj_pivot_steps<R, 0>(a, sh, c0, ws, n, ipiv, info + blockIdx.y);
   if (i < n) {
 #pragma unroll
     for (int j = 0; j < GJ_NBR; ++j)
-      if (j < w) A[i + (size_t)(c0 + j) * ld] = a[j];
+      if (j < ws) d.a[i + (size_t)(cs + j) * ld] = a[j];
   }
 }
 
@@ -669,14 +731,12 @@ hipError_t launch_inv(const InvDescT<R>* d, int nd, int max_n, typename cx<R>::T
   hipError_t e = hipMemsetAsync(info, 0, sizeof(int) * nd, s);
   if (e != hipSuccess) return e;
   if (max_n <= NTP_REG) {
-    // one thread per row, in whole wavefronts: small matrices get small workgroups
+    // one thread per row, in whole wavefronts: small matrices get small workgroups; one launch per
+    // panel (the previous panel's update runs beside the factorization)
     const int nthr = std::min(NTP_REG, (max_n + 63) / 64 * 64);
-    for (int c0 = 0; c0 < max_n; c0 += GJ_NBR) {
-      hipLaunchKernelGGL(k_gj_panel_reg<R>, dim3(nd), dim3(nthr), 0, s, d, c0, ipiv, max_n, info);
-      hipLaunchKernelGGL((k_gj_swapsave<R, GJ_NBR>), dim3(grid_for(max_n, 64), nd), dim3(NT), 0, s, d, c0, ipiv, max_n, tbuf);
-      hipLaunchKernelGGL((k_gj_update<R, GJ_NBR>), dim3((max_n + 63) / 64, (max_n + 15) / 16, nd), dim3(NT), 0, s, d, c0,
-                         max_n, (const typename cx<R>::T*)tbuf);
-    }
+    const int np = (max_n + GJ_NBR - 1) / GJ_NBR;
+    for (int k = 0; k <= np; ++k)
+      hipLaunchKernelGGL(k_gj_step<R>, dim3(1 + np, nd), dim3(nthr), 0, s, d, GJ_NBR * (k - 1), GJ_NBR * k, ipiv, max_n, info);
   } else {
     for (int c0 = 0; c0 < max_n; c0 += GJ_NB) {
       hipLaunchKernelGGL(k_gj_panel<R>, dim3(nd), dim3(NTP), 0, s, d, c0, ipiv, max_n, info);

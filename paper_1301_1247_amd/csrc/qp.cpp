@@ -353,6 +353,97 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     CK(gemm_batched(h->arena, g, st, &h->splitws));
     return HBS_OK;
   };
+  // the side stream (when used) is joined before returning, also on error paths
+  struct SideJoin {
+    hipStream_t s = nullptr;
+    ~SideJoin() {
+      if (s) (void)hipStreamSynchronize(s);
+    }
+  } side_join;
+  // S(alpha) = Q - C~_J(alpha) H~(alpha) B_J(alpha) with H~ = U^T A~^{-1} U = H - H K(alpha) R(alpha) V (P = 1) or H;
+  // Woodbury around the 2 x 2-block-diagonal Q: S^{-1} = [I + Cq K2 B_J(alpha)] Q^{-1},
+  // Cq = Q^{-1} C~_J H~, K2 = (I - B_J(alpha) Cq)^{-1}  (root-size inversions only).
+  // Issued on stream s with its own descriptor arena and workspaces.
+  // dinfo: leave the singularity check to the caller (device flags in wk) instead of waiting
+  auto woodbury = [&](hipStream_t s, DevBuf& ar, DevBuf& ws, DevBuf& wk, int** dinfo) -> int {
+    const cplx* H = Zt;  // U^T V (nu x nu)
+    // every descriptor set first, so that the arena and workspaces are reserved before any launch
+    std::vector<GemmDesc> gp1, gp2, gch, gbc;
+    std::vector<std::vector<GemmDesc>> gcq(P ? ng : 0);
+    std::vector<InvDesc> iv;
+    for (int g = 0; g < ng; ++g) {
+      if (P) {
+        gp1.push_back(gd(Kg + (size_t)g * nr * nr, nr, 0, KVg + (size_t)g * nr * nr, nr, Hs + (size_t)g * nu * nu, nu, nu, nu,
+                         nr, onec, zero));
+        gp2.push_back(gd(H, nu, 0, Hs + (size_t)g * nu * nu, nu, Ht + (size_t)g * nu * nu, nu, nu, nu, nu, minus1c, onec));
+        gcq[g] = {gd(Cq + (size_t)g * M2 * nu, M2, 0, Ht + (size_t)g * nu * nu, nu, CH, M2, M2, nu, nu, onec, zero)};
+      }
+      gbc.push_back(gd(BJa + (size_t)g * nu * M2, nu, 0, Cq + (size_t)g * M2 * nu, M2, Hs + (size_t)g * nu * nu, nu, nu, nu, M2,
+                       minus1c, zero));
+      iv.push_back({K2 + (size_t)g * nu * nu, nu, nu});
+    }
+    if (!P) gch = {gd(C1, M2, 0, H, nu, C1H, M2, M2, nu, nu, onec, zero), gd(C2, M2, 0, H, nu, C2H, M2, M2, nu, nu, onec, zero)};
+    {
+      size_t amax = 0, wmax = 0, a, w;
+      auto need = [&](const std::vector<GemmDesc>& v) {
+        gemm_batched_needs(v, &a, &w);
+        amax = std::max(amax, a);
+        wmax = std::max(wmax, w);
+      };
+      need(gp1);
+      need(gp2);
+      need(gch);
+      need(gbc);
+      for (const auto& v : gcq) need(v);
+      size_t wi;
+      inv_batched_needs(iv, &a, &wi);
+      CK(ar.reserve(std::max(amax, a)));
+      if (wmax) CK(ws.reserve(wmax));
+      CK(wk.reserve(wi));
+    }
+    auto gemm_s = [&](const std::vector<GemmDesc>& g) -> int {
+      CK(gemm_batched(ar, g, s, &ws));
+      return HBS_OK;
+    };
+    for (int g = 0; g < ng; ++g) {
+      CK(launch_lincomb(nu, M2, d_one, d_gco + 3 * g, 0, BJ, nu, BJ + (size_t)M2 * nu, nu, nullptr, 0,
+                        BJa + (size_t)g * nu * M2, nu, s));
+    }
+    if (P) {
+      CR(gemm_s(gp1));
+      for (int g = 0; g < ng; ++g)
+        CK(hipMemcpyAsync(Ht + (size_t)g * nu * nu, H, sizeof(cplx) * (size_t)nu * nu, hipMemcpyDeviceToDevice, s));
+      CR(gemm_s(gp2));
+      for (int g = 0; g < ng; ++g) {
+        // C~_J(alpha) = c1 C1_J + c2 C2_J (staged in Cq), then Cq = Q^{-1} C~_J H~
+        cplx* cq = Cq + (size_t)g * M2 * nu;
+        CK(launch_lincomb(M2, nu, d_gco + 3 * g + 1, d_gco + 3 * g + 2, 0, C1, M2, C2, M2, nullptr, 0, cq, M2, s));
+        CR(gemm_s(gcq[g]));
+        CK(launch_qsolve(Q, d_gco + 3 * g, 0, nu, CH, M2, cq, M2, s));
+      }
+    } else {
+      // H~ = H for every phase: C~_J H = c1 (C1_J H) + c2 (C2_J H)
+      CR(gemm_s(gch));
+      for (int g = 0; g < ng; ++g) {
+        cplx* cq = Cq + (size_t)g * M2 * nu;
+        CK(launch_lincomb(M2, nu, d_gco + 3 * g + 1, d_gco + 3 * g + 2, 0, C1H, M2, C2H, M2, nullptr, 0, CH, M2, s));
+        CK(launch_qsolve(Q, d_gco + 3 * g, 0, nu, CH, M2, cq, M2, s));
+      }
+    }
+    CR(gemm_s(gbc));
+    CK(launch_eye_plus(nu, ng, Hs, nu, (int64_t)nu * nu, K2, s));
+    if (dinfo) {
+      CK(inv_batched_async(ar, wk, iv, s, dinfo));
+      return HBS_OK;
+    }
+    bool sing = false;
+    CK(inv_batched(ar, wk, iv, s, &sing));
+    if (sing) {
+      set_error("qp_solve: singular Schur complement");
+      return HBS_E_SINGULAR;
+    }
+    return HBS_OK;
+  };
   {
     ProfScope ps("assemble", st, 0.0, 0.0);
     if (cw) {
@@ -370,6 +461,10 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   // compressed walls on complex128 factors: V = A^{-1} U and U^T A^{-1} [U | b] come from the
   // root inverse and the E-only downward pass, without forming U (F^T P = I, G P = 0, P^T E = I)
   const bool fastU = cw && h->fp64_top >= h->L;
+  // without neighbour images the Woodbury factors need only R^{-1}, B_J and C_J: they are formed on
+  // the side stream while the main stream applies A^{-1} to the incident fields
+  const bool overlap = fastU && !P;
+  int* side_dinfo = nullptr;  // the side stream's singularity flags (device)
   if (nu && !fastU) {
     // U (N x nroot) = nested interpolation of the identity
     CK(h->ab_root.reserve(sizeof(cplx) * (size_t)nu * nu));
@@ -388,8 +483,18 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     // one application of A^{-1} to [U | b]: X = [V | X_b]; then with H = U^T V,
     //   U^T [X_L | X_R | X_b | V] = [H B_J,L | H B_J,R | U^T X_b | H]  and  G = C_J (that)
     if (fastU) {
-      CR(apply_inverse_root(h, Y + (size_t)ycolB * N, N, X + (size_t)ycolB * N, N, nang, Zt + (size_t)nu * nu, nu));
       CK(hipMemcpyAsync(Zt, h->Rinv.p, sizeof(cplx) * (size_t)nu * nu, hipMemcpyDeviceToDevice, st));
+      if (overlap) {
+        // the side stream waits for R^{-1} and the wall blocks and forms the Woodbury factors while
+        // the main stream applies A^{-1}; the main stream waits for them before the first solve with S
+        CR(side_stream_init(h));
+        CK(hipEventRecord(h->side_ev[0], st));
+        side_join.s = h->side_stream;
+        CK(hipStreamWaitEvent(h->side_stream, h->side_ev[0], 0));
+        CR(woodbury(h->side_stream, h->arena_s, h->splitws_s, h->work_s, &side_dinfo));
+        CK(hipEventRecord(h->side_ev[1], h->side_stream));
+      }
+      CR(apply_inverse_root(h, Y + (size_t)ycolB * N, N, X + (size_t)ycolB * N, N, nang, Zt + (size_t)nu * nu, nu, !overlap));
       // V itself is needed only with neighbour images; without them X(alpha) xi = V (B_J v) is
       // applied as E_L ... E_1 (R^{-1} B_J v) where needed
       if (P) CR(apply_down_E(h, Zt, nu, X + (size_t)ycolU * N, N, nu));
@@ -496,60 +601,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     }
   }
   if (cw) {
-    // S(alpha) = Q - C~_J(alpha) H~(alpha) B_J(alpha) with H~ = U^T A~^{-1} U = H - H K(alpha) R(alpha) V (P = 1) or H;
-    // Woodbury around the 2 x 2-block-diagonal Q: S^{-1} = [I + Cq K2 B_J(alpha)] Q^{-1},
-    // Cq = Q^{-1} C~_J H~, K2 = (I - B_J(alpha) Cq)^{-1}  (root-size inversions only).
-    const cplx* H = Zt;  // U^T V (nu x nu)
-    for (int g = 0; g < ng; ++g) {
-      CK(launch_lincomb(nu, M2, d_one, d_gco + 3 * g, 0, BJ, nu, BJ + (size_t)M2 * nu, nu, nullptr, 0,
-                        BJa + (size_t)g * nu * M2, nu, st));
-    }
-    if (P) {
-      std::vector<GemmDesc> g1, g2;
-      for (int g = 0; g < ng; ++g)
-        g1.push_back(gd(Kg + (size_t)g * nr * nr, nr, 0, KVg + (size_t)g * nr * nr, nr, Hs + (size_t)g * nu * nu, nu, nu, nu,
-                        nr, onec, zero));
-      CR(gemm(g1));
-      for (int g = 0; g < ng; ++g) {
-        CK(hipMemcpyAsync(Ht + (size_t)g * nu * nu, H, sizeof(cplx) * (size_t)nu * nu, hipMemcpyDeviceToDevice, st));
-        g2.push_back(gd(H, nu, 0, Hs + (size_t)g * nu * nu, nu, Ht + (size_t)g * nu * nu, nu, nu, nu, nu, minus1c, onec));
-      }
-      CR(gemm(g2));
-    }
-    if (!P) {
-      // H~ = H for every phase: C~_J H = c1 (C1_J H) + c2 (C2_J H)
-      CR(gemm({gd(C1, M2, 0, H, nu, C1H, M2, M2, nu, nu, onec, zero), gd(C2, M2, 0, H, nu, C2H, M2, M2, nu, nu, onec, zero)}));
-      for (int g = 0; g < ng; ++g) {
-        cplx* cq = Cq + (size_t)g * M2 * nu;
-        CK(launch_lincomb(M2, nu, d_gco + 3 * g + 1, d_gco + 3 * g + 2, 0, C1H, M2, C2H, M2, nullptr, 0, CH, M2, st));
-        CK(launch_qsolve(Q, d_gco + 3 * g, 0, nu, CH, M2, cq, M2, st));
-      }
-    } else {
-      for (int g = 0; g < ng; ++g) {
-        const cplx* Hg = Ht + (size_t)g * nu * nu;
-        // C~_J(alpha) = c1 C1_J + c2 C2_J (staged in Cq), then Cq = Q^{-1} C~_J H~
-        cplx* cq = Cq + (size_t)g * M2 * nu;
-        CK(launch_lincomb(M2, nu, d_gco + 3 * g + 1, d_gco + 3 * g + 2, 0, C1, M2, C2, M2, nullptr, 0, cq, M2, st));
-        CR(gemm({gd(cq, M2, 0, Hg, nu, CH, M2, M2, nu, nu, onec, zero)}));
-        CK(launch_qsolve(Q, d_gco + 3 * g, 0, nu, CH, M2, cq, M2, st));
-      }
-    }
-    {
-      std::vector<GemmDesc> g1;
-      for (int g = 0; g < ng; ++g)
-        g1.push_back(gd(BJa + (size_t)g * nu * M2, nu, 0, Cq + (size_t)g * M2 * nu, M2, Hs + (size_t)g * nu * nu, nu, nu, nu,
-                        M2, minus1c, zero));
-      CR(gemm(g1));
-      CK(launch_eye_plus(nu, ng, Hs, nu, (int64_t)nu * nu, K2, st));
-      std::vector<InvDesc> iv;
-      for (int g = 0; g < ng; ++g) iv.push_back({K2 + (size_t)g * nu * nu, nu, nu});
-      bool sing = false;
-      CK(inv_batched(h->arena, h->work, iv, st, &sing));
-      if (sing) {
-        set_error("qp_solve: singular Schur complement");
-        return HBS_E_SINGULAR;
-      }
-    }
+    if (!overlap) CR(woodbury(st, h->arena, h->splitws, h->work, nullptr));
   } else {
     std::vector<InvDesc> iv;
     for (int g = 0; g < ng; ++g) iv.push_back({S + (size_t)g * M2 * M2, M2, M2});
@@ -632,6 +684,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
                      gcnt[gg], nr, minus1c, onec));
     CR(gemm(g));
   }
+  if (overlap) CK(hipStreamWaitEvent(st, h->side_ev[1], 0));
   CR(solve_S(Wv, xi, minus1c));
   // eta = X_b - X(alpha) xi - V K (R X_b - R X(alpha) xi)
   CK(launch_stack(M2, nang, d_al, xi, stk, st));
@@ -681,7 +734,15 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     CK(launch_colnorm2(N, nang, R1, N, nrm, st));
     CK(launch_colnorm2(M2, nang, R2, M2, nrm + nang, st));
     CK(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * 3 * nang, hipMemcpyDeviceToHost, st));
+    std::vector<int> sinfo(side_dinfo && it == 0 ? ng : 0);
+    // the main stream has waited for the side stream's inversion: its flags are final
+    if (!sinfo.empty()) CK(hipMemcpyAsync(sinfo.data(), side_dinfo, sizeof(int) * ng, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
+    for (int f : sinfo)
+      if (f != 0) {
+        set_error("qp_solve: singular Schur complement");
+        return HBS_E_SINGULAR;
+      }
     relres = 0;
     for (int q = 0; q < nang; ++q) relres = std::max(relres, std::sqrt((hn[q] + hn[nang + q]) / hn[2 * nang + q]));
     if (relres < rtol || it == maxit) break;

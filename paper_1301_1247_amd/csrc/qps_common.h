@@ -121,6 +121,27 @@ __device__ inline unsigned wave_umin(unsigned v) {
   return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// Wavefront max of a 64-bit unsigned key: each DPP stage moves both halves, lanes outside the row
+// mask keep their own key.  Every lane receives the result (from lane 63).
+template <int CTRL, int ROWS>
+__device__ inline unsigned long long dpp_keep_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)v, (int)(unsigned)v, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(v >> 32), (int)(unsigned)(v >> 32), CTRL, ROWS, 0xF, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ inline unsigned long long wave_umax64(unsigned long long v) {
+  unsigned long long o;
+  o = dpp_keep_u64<0xB1, 0xF>(v);  v = o > v ? o : v;  // quad_perm 1,0,3,2
+  o = dpp_keep_u64<0x4E, 0xF>(v);  v = o > v ? o : v;  // quad_perm 2,3,0,1
+  o = dpp_keep_u64<0x141, 0xF>(v); v = o > v ? o : v;  // row_half_mirror
+  o = dpp_keep_u64<0x140, 0xF>(v); v = o > v ? o : v;  // row_mirror
+  o = dpp_keep_u64<0x142, 0xA>(v); v = o > v ? o : v;  // row_bcast:15
+  o = dpp_keep_u64<0x143, 0xC>(v); v = o > v ? o : v;  // row_bcast:31
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 // arg-max of (val, idx) over a wavefront, ties resolved to the smaller index; values <= 0
 // (including the -1 of lanes without a candidate) compare as 0.  The bit pattern of a
 // non-negative double orders like the value, so the max is taken on its high then low word.

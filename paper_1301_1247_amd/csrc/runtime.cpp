@@ -2,6 +2,7 @@
 // profiling with HIP events, and the batched inversion driver.
 #include "internal.h"
 
+#include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -21,10 +22,15 @@ void clear_error() { g_last_error.clear(); }
 // hipMalloc / hipFree each time.  Sizes are rounded to 1/8 of their power of two; a cached block
 // is reused for requests down to 4/5 of its size.  At most QPS_POOL_MAX_GB (default 64) GiB stay
 // cached per device; a failed hipMalloc returns the cache to the device and retries.
+// A released block may still be read or written by queued work on any stream, so it is only
+// retired: it joins the free list at the next quiescent point (the end of a library call, after
+// one device synchronisation when blocks are pending, or an out-of-memory retry).  Within a call
+// no block is ever handed out twice, and releasing never waits for the device.
 namespace {
 struct Pool {
   std::mutex mu;
   std::map<int, std::multimap<size_t, void*>> free_blocks;
+  std::map<int, std::vector<std::pair<size_t, void*>>> retired;
   std::map<int, size_t> cached;
   size_t cap = 0;
 };
@@ -44,6 +50,25 @@ size_t round_size(size_t b) {
   while (p2 < b) p2 <<= 1;
   const size_t q = p2 / 8;
   return (b + q - 1) / q * q;
+}
+// retired blocks of device dev (the caller has synchronised it) to the free list, or back to the
+// device beyond the cap
+void flush_retired(int dev) {
+  Pool& P = pool();
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    for (auto& kv : P.retired[dev]) {
+      if (P.cached[dev] + kv.first <= P.cap) {
+        P.free_blocks[dev].emplace(kv.first, kv.second);
+        P.cached[dev] += kv.first;
+      } else {
+        drop.push_back(kv.second);
+      }
+    }
+    P.retired[dev].clear();
+  }
+  for (void* b : drop) (void)hipFree(b);
 }
 void trim_device(int dev) {
   Pool& P = pool();
@@ -83,6 +108,7 @@ hipError_t DevBuf::reserve(size_t b) {
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
     (void)hipDeviceSynchronize();
+    flush_retired(d);
     trim_device(d);
     e = hipMalloc(&p, want);
   }
@@ -98,27 +124,32 @@ hipError_t DevBuf::reserve(size_t b) {
 
 void DevBuf::release() {
   if (!p) return;
-  // the buffer may still be read by queued kernels (of any stream) before it is handed on
-  (void)hipDeviceSynchronize();
   Pool& P = pool();
-  bool keep;
   {
     std::lock_guard<std::mutex> lk(P.mu);
-    keep = P.cached[dev] + bytes <= P.cap;
-    if (keep) {
-      P.free_blocks[dev].emplace(bytes, p);
-      P.cached[dev] += bytes;
-    }
+    P.retired[dev].emplace_back(bytes, p);
   }
-  if (!keep) (void)hipFree(p);
   p = nullptr;
   bytes = 0;
+}
+
+void pool_quiesce_current() {
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) return;
+  Pool& P = pool();
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    if (P.retired[d].empty()) return;
+  }
+  (void)hipDeviceSynchronize();
+  flush_retired(d);
 }
 
 int pool_release_current() {
   int d = 0;
   if (hipGetDevice(&d) != hipSuccess) return -1;
   (void)hipDeviceSynchronize();
+  flush_retired(d);
   trim_device(d);
   return 0;
 }
@@ -197,11 +228,28 @@ ProfScope::~ProfScope() {
 }
 
 // ------------------------------------------------------------------ batched inversion
+// workspace of a batched inversion: panel rows (nd * 32 * maxn), pivots (nd * maxn), info (nd)
 template <class R>
-hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R>>& v, hipStream_t s, bool* singular) {
+static void inv_layout(int nd, int maxn, size_t* tb, size_t* ib, size_t* fb) {
+  *tb = ((size_t)nd * 32 * maxn * sizeof(typename cx<R>::T) + 255) / 256 * 256;
+  *ib = ((size_t)nd * maxn * sizeof(int) + 255) / 256 * 256;
+  *fb = (size_t)nd * sizeof(int);
+}
+
+template <class R>
+void inv_batched_needs(const std::vector<InvDescT<R>>& v, size_t* arena_bytes, size_t* work_bytes) {
+  int maxn = 0;
+  for (const auto& d : v) maxn = std::max(maxn, d.n);
+  size_t tb, ib, fb;
+  inv_layout<R>((int)v.size(), maxn, &tb, &ib, &fb);
+  *arena_bytes = v.size() * sizeof(InvDescT<R>);
+  *work_bytes = v.empty() ? 0 : tb + ib + fb + 512;
+}
+
+// launches the inversion; *dinfo receives the device address of the nd singularity flags
+template <class R>
+static hipError_t inv_launch(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R>>& v, hipStream_t s, int** dinfo) {
   typedef typename cx<R>::T C_t;
-  *singular = false;
-  if (v.empty()) return hipSuccess;
   int maxn = 0;
   double flops = 0.0;
   for (const auto& d : v) {
@@ -209,11 +257,8 @@ hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R
     flops += 8.0 * (double)d.n * d.n * d.n;
   }
   const int nd = (int)v.size();
-  size_t tb = (size_t)nd * 32 * maxn * sizeof(C_t);
-  tb = (tb + 255) / 256 * 256;
-  size_t ib = (size_t)nd * maxn * sizeof(int);
-  ib = (ib + 255) / 256 * 256;
-  size_t fb = (size_t)nd * sizeof(int);
+  size_t tb, ib, fb;
+  inv_layout<R>(nd, maxn, &tb, &ib, &fb);
   hipError_t e = work.reserve(tb + ib + fb + 512);
   if (e != hipSuccess) return e;
   char* base = work.as<char>();
@@ -227,8 +272,20 @@ hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R
     e = launch_inv<R>(arena.as<InvDescT<R>>(), nd, maxn, tbuf, ipiv, info, s);
     if (e != hipSuccess) return e;
   }
+  *dinfo = info;
+  return hipSuccess;
+}
+
+template <class R>
+hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R>>& v, hipStream_t s, bool* singular) {
+  *singular = false;
+  if (v.empty()) return hipSuccess;
+  int* info = nullptr;
+  hipError_t e = inv_launch<R>(arena, work, v, s, &info);
+  if (e != hipSuccess) return e;
+  const int nd = (int)v.size();
   std::vector<int> hinfo(nd);
-  e = hipMemcpyAsync(hinfo.data(), info, fb, hipMemcpyDeviceToHost, s);
+  e = hipMemcpyAsync(hinfo.data(), info, sizeof(int) * nd, hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return e;
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
@@ -236,7 +293,17 @@ hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R
     if (hinfo[i] != 0) *singular = true;
   return hipSuccess;
 }
+
+template <class R>
+hipError_t inv_batched_async(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R>>& v, hipStream_t s, int** dinfo) {
+  *dinfo = nullptr;
+  if (v.empty()) return hipSuccess;
+  return inv_launch<R>(arena, work, v, s, dinfo);
+}
+template void inv_batched_needs<double>(const std::vector<InvDesc>&, size_t*, size_t*);
+template void inv_batched_needs<float>(const std::vector<InvDesc32>&, size_t*, size_t*);
 template hipError_t inv_batched<double>(DevBuf&, DevBuf&, const std::vector<InvDesc>&, hipStream_t, bool*);
 template hipError_t inv_batched<float>(DevBuf&, DevBuf&, const std::vector<InvDesc32>&, hipStream_t, bool*);
+template hipError_t inv_batched_async<double>(DevBuf&, DevBuf&, const std::vector<InvDesc>&, hipStream_t, int**);
 
 }  // namespace qps
