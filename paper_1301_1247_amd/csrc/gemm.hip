@@ -59,8 +59,15 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDescT<R>* __restrict__ d
   const int i0 = (t % tm) * BM, j0 = (t / tm) * BN;
   __shared__ R Are[BK][BM + PADK], Aim[BK][BM + PADK];
   __shared__ R Bre[BK][BN + PADK], Bim[BK][BN + PADK];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform
   const int wm = wv & 1, wn = wv >> 1;
+  // 16 x 16 blocks wholly outside C and k-steps past K take no MFMAs (ragged boxes of a batch
+  // would otherwise pad every product to whole 64 x 64 x 16 tiles)
+  const bool rv0 = i0 + wm * 32 < d.m, rv1 = i0 + wm * 32 + 16 < d.m;
+  const bool cv0 = j0 + wn * 32 < d.n, cv1 = j0 + wn * 32 + 16 < d.n;
+  const bool a00 = rv0 && cv0, a01 = rv0 && cv1, a10 = rv1 && cv0, a11 = rv1 && cv1;
+#define QPS_ACT(a, b) ((a) ? ((b) ? a11 : a10) : ((b) ? a01 : a00))
   acc_t accr[2][2], acci[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -106,8 +113,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDescT<R>* __restrict__ d
   for (int k0 = 0; k0 < d.k; k0 += BK) {
     const bool more = k0 + BK < d.k;
     if (more) load_slice(k0 + BK);  // in flight during the MFMAs below
+    const int kv = d.k - k0;
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
+      if (ks >= kv) break;
       const int kk = ks + (lane >> 4);
       R ar[2], ai[2], br[2], bi[2];
 #pragma unroll
@@ -126,19 +135,23 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDescT<R>* __restrict__ d
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) accr[a][b] = mfma_t<R>::op(ar[a], br[b], accr[a][b]);
+        for (int b = 0; b < 2; ++b)
+          if (QPS_ACT(a, b)) accr[a][b] = mfma_t<R>::op(ar[a], br[b], accr[a][b]);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acci[a][b] = mfma_t<R>::op(ar[a], bi[b], acci[a][b]);
+        for (int b = 0; b < 2; ++b)
+          if (QPS_ACT(a, b)) acci[a][b] = mfma_t<R>::op(ar[a], bi[b], acci[a][b]);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) accr[a][b] = mfma_t<R>::op(-ai[a], bi[b], accr[a][b]);
+        for (int b = 0; b < 2; ++b)
+          if (QPS_ACT(a, b)) accr[a][b] = mfma_t<R>::op(-ai[a], bi[b], accr[a][b]);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acci[a][b] = mfma_t<R>::op(ai[a], br[b], acci[a][b]);
+        for (int b = 0; b < 2; ++b)
+          if (QPS_ACT(a, b)) acci[a][b] = mfma_t<R>::op(ai[a], br[b], acci[a][b]);
     }
     __syncthreads();
     if (more) {
@@ -146,6 +159,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDescT<R>* __restrict__ d
       __syncthreads();
     }
   }
+#undef QPS_ACT
   // epilogue: register r of a lane holds row (lane/16) + 4r, column lane%16 of each 16 x 16 block
   const bool zero_beta = (d.beta.x == 0 && d.beta.y == 0);
 #pragma unroll
