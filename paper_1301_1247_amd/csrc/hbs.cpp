@@ -207,6 +207,22 @@ int build(hbs_handle* h) {
 
   DevBuf dnear, wt, zb, zb2, kout, tmpY, tmpZt;
   DevBuf& arena = h->arena;
+  // singularity flags of every batched inversion of the build (two per box and level, the root),
+  // read once after the final synchronisation so that the host never waits on an inversion
+  int64_t nflag = 1;
+  for (int l = 1; l <= L; ++l) nflag += 2 * (int64_t)h->lv[l].nb;
+  DevBuf dflags;
+  CK(dflags.reserve(sizeof(int) * nflag));
+  CK(hipMemsetAsync(dflags.p, 0, sizeof(int) * nflag, st));
+  struct FlagRange { int64_t off; int cnt, level; const char* what; };
+  std::vector<FlagRange> franges;
+  int64_t foff = 0;
+  auto flags_for = [&](int cnt, int level, const char* what) {
+    int* p = dflags.as<int>() + foff;
+    franges.push_back({foff, cnt, level, what});
+    foff += cnt;
+    return p;
+  };
   h->factor_bytes = 0;
   std::memset(h->stats.ranks_per_level_max, 0, sizeof(h->stats.ranks_per_level_max));
   std::memset(h->stats.ranks_per_level_mean, 0, sizeof(h->stats.ranks_per_level_mean));
@@ -508,7 +524,9 @@ int build(hbs_handle* h) {
     }
     V.k.assign(nb, 0);
     CK(hipMemcpyAsync(V.k.data(), kout.p, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(hperm.data(), dperm.p, sizeof(int) * V.ntot, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
+    bool perm_stale = false;  // a redone box rewrites its part of the permutation
     if (predict && !ident) {
       // a sketch that was too short for the box's rank reveals no gap: redo it at full size
       std::vector<int> redo;
@@ -552,10 +570,13 @@ int build(hbs_handle* h) {
         CK(hipMemcpyAsync(hk2.data(), k2, sizeof(int) * redo.size(), hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));
         for (size_t r = 0; r < redo.size(); ++r) V.k[redo[r]] = hk2[r];
+        perm_stale = true;
       }
     }
-    CK(hipMemcpyAsync(hperm.data(), dperm.p, sizeof(int) * V.ntot, hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
+    if (perm_stale) {
+      CK(hipMemcpyAsync(hperm.data(), dperm.p, sizeof(int) * V.ntot, hipMemcpyDeviceToHost, st));
+      CK(hipStreamSynchronize(st));
+    }
     for (int b = 0; b < nb; ++b) {
       h->feat_rank.push_back(V.k[b]);
       h->feat_level.push_back(l);
@@ -609,7 +630,6 @@ int build(hbs_handle* h) {
       CK(up_sync(arena, pd, st));
       CK(launch_buildP(arena.as<PDesc>(), nb, maxe, st));
     }
-    bool sing = false;
     if (fp32) {
       // complex64 inverse factors from the FP64 blocks D and interpolation matrices P
       CK(V.G32.reserve(sizeof(cplxf) * V.oG[nb]));
@@ -631,11 +651,7 @@ int build(hbs_handle* h) {
       CK(launch_cast_d2f(dP, P32, V.oP[nb], st));
       std::vector<InvDesc32> iv;
       for (int b = 0; b < nb; ++b) iv.push_back({G32 + V.oG[b], V.n[b], V.n[b]});
-      CK(inv_batched<float>(arena, h->work, iv, st, &sing));
-      if (sing) {
-        set_error("hbs_build: singular diagonal block at level " + std::to_string(l));
-        return HBS_E_SINGULAR;
-      }
+      CK(inv_batched_flags<float>(arena, h->work, iv, st, flags_for(nb, l, "diagonal block")));
       const cplxf one = mkcf(1, 0), zero = mkcf(0, 0), mone = mkcf(-1, 0);
       auto g32 = [&](const cplxf* A, int lda, int tA, const cplxf* B, int ldb, cplxf* C, int ldc, int m, int n, int k,
                      cplxf al, cplxf be) {
@@ -657,11 +673,7 @@ int build(hbs_handle* h) {
       CK(gemm_batched<float>(arena, g2, st));
       std::vector<InvDesc32> iv2;
       for (int b = 0; b < nb; ++b) iv2.push_back({Dh32 + V.oDh[b], V.k[b], V.k[b]});
-      CK(inv_batched<float>(arena, h->work, iv2, st, &sing));
-      if (sing) {
-        set_error("hbs_build: singular reduced block at level " + std::to_string(l));
-        return HBS_E_SINGULAR;
-      }
+      CK(inv_batched_flags<float>(arena, h->work, iv2, st, flags_for(nb, l, "reduced block")));
       for (int b = 0; b < nb; ++b) {
         const int n = V.n[b], k = V.k[b];
         g3.push_back(g32(Y32 + V.oP[b], n, 0, Dh32 + V.oDh[b], k, E32 + V.oP[b], n, n, k, k, one, zero));
@@ -694,11 +706,7 @@ int build(hbs_handle* h) {
     } else {
       std::vector<InvDesc> iv;
       for (int b = 0; b < nb; ++b) iv.push_back({dG + V.oG[b], V.n[b], V.n[b]});
-      CK(inv_batched(arena, h->work, iv, st, &sing));
-      if (sing) {
-        set_error("hbs_build: singular diagonal block at level " + std::to_string(l));
-        return HBS_E_SINGULAR;
-      }
+      CK(inv_batched_flags(arena, h->work, iv, st, flags_for(nb, l, "diagonal block")));
     cplx* Y = tmpY.as<cplx>();
     cplx* Zt = tmpZt.as<cplx>();
     cplx* Dh = V.Dh.as<cplx>();
@@ -723,11 +731,7 @@ int build(hbs_handle* h) {
       CK(gemm_batched(arena, g2, st));
       std::vector<InvDesc> iv;
       for (int b = 0; b < nb; ++b) iv.push_back({Dh + V.oDh[b], V.k[b], V.k[b]});
-      CK(inv_batched(arena, h->work, iv, st, &sing));
-      if (sing) {
-        set_error("hbs_build: singular reduced block at level " + std::to_string(l));
-        return HBS_E_SINGULAR;
-      }
+      CK(inv_batched_flags(arena, h->work, iv, st, flags_for(nb, l, "reduced block")));
       std::vector<GemmDesc> g3, g4;
       for (int b = 0; b < nb; ++b) {
         const int n = V.n[b], k = V.k[b];
@@ -774,17 +778,21 @@ int build(hbs_handle* h) {
                                 {V.Dh.as<cplx>() + V.oDh[1], Ri + (int64_t)ka * n + ka, kc, kc, kc, n}};
     CK(up_sync(arena, cd, st));
     CK(launch_copy(arena.as<CopyDesc>(), 2, std::max(ka * ka, kc * kc), st));
-    bool sing = false;
     std::vector<InvDesc> iv = {{Ri, n, n}};
-    CK(inv_batched(arena, h->work, iv, st, &sing));
-    if (sing) {
-      set_error("hbs_build: singular root matrix");
-      return HBS_E_SINGULAR;
-    }
+    CK(inv_batched_flags(arena, h->work, iv, st, flags_for(1, 0, "root matrix")));
     V.Dh.release();
     h->factor_bytes += (int64_t)sizeof(cplx) * 2 * n * n;
   }
+  std::vector<int> hflags(foff);
+  if (foff > 0) CK(hipMemcpyAsync(hflags.data(), dflags.p, sizeof(int) * foff, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
+  for (const auto& fr : franges)
+    for (int b = 0; b < fr.cnt; ++b)
+      if (hflags[fr.off + b] != 0) {
+        set_error(std::string("hbs_build: singular ") + fr.what +
+                  (fr.level > 0 ? " at level " + std::to_string(fr.level) + ", box " + std::to_string(b) : ""));
+        return HBS_E_SINGULAR;
+      }
   h->work.release();
   auto t1 = std::chrono::steady_clock::now();
   h->build_seconds = std::chrono::duration<double>(t1 - t0).count();

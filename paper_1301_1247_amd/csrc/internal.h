@@ -163,6 +163,9 @@ hipError_t inv_batched(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R
 // work, valid once stream s has passed this point and until work is used again)
 template <class R>
 hipError_t inv_batched_async(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R>>& v, hipStream_t s, int** dinfo);
+// the same with the nd flags written to dflags (device memory of the caller), nothing waited for
+template <class R>
+hipError_t inv_batched_flags(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R>>& v, hipStream_t s, int* dflags);
 // bytes that gemm_batched / inv_batched reserve in their arena and workspace for a descriptor set
 // (reserving them beforehand keeps those calls from touching the pool while other streams run)
 template <class R>

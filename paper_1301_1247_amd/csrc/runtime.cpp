@@ -246,9 +246,11 @@ void inv_batched_needs(const std::vector<InvDescT<R>>& v, size_t* arena_bytes, s
   *work_bytes = v.empty() ? 0 : tb + ib + fb + 512;
 }
 
-// launches the inversion; *dinfo receives the device address of the nd singularity flags
+// launches the inversion; the nd singularity flags go to info_dst (device) when given, else into
+// work; *dinfo receives their address
 template <class R>
-static hipError_t inv_launch(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R>>& v, hipStream_t s, int** dinfo) {
+static hipError_t inv_launch(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R>>& v, hipStream_t s, int** dinfo,
+                             int* info_dst = nullptr) {
   typedef typename cx<R>::T C_t;
   int maxn = 0;
   double flops = 0.0;
@@ -264,7 +266,7 @@ static hipError_t inv_launch(DevBuf& arena, DevBuf& work, const std::vector<InvD
   char* base = work.as<char>();
   C_t* tbuf = reinterpret_cast<C_t*>(base);
   int* ipiv = reinterpret_cast<int*>(base + tb);
-  int* info = reinterpret_cast<int*>(base + tb + ib);
+  int* info = info_dst ? info_dst : reinterpret_cast<int*>(base + tb + ib);
   e = upload(arena, v, s);
   if (e != hipSuccess) return e;
   {
@@ -300,10 +302,19 @@ hipError_t inv_batched_async(DevBuf& arena, DevBuf& work, const std::vector<InvD
   if (v.empty()) return hipSuccess;
   return inv_launch<R>(arena, work, v, s, dinfo);
 }
+
+template <class R>
+hipError_t inv_batched_flags(DevBuf& arena, DevBuf& work, const std::vector<InvDescT<R>>& v, hipStream_t s, int* dflags) {
+  if (v.empty()) return hipSuccess;
+  int* info = nullptr;
+  return inv_launch<R>(arena, work, v, s, &info, dflags);
+}
 template void inv_batched_needs<double>(const std::vector<InvDesc>&, size_t*, size_t*);
 template void inv_batched_needs<float>(const std::vector<InvDesc32>&, size_t*, size_t*);
 template hipError_t inv_batched<double>(DevBuf&, DevBuf&, const std::vector<InvDesc>&, hipStream_t, bool*);
 template hipError_t inv_batched<float>(DevBuf&, DevBuf&, const std::vector<InvDesc32>&, hipStream_t, bool*);
 template hipError_t inv_batched_async<double>(DevBuf&, DevBuf&, const std::vector<InvDesc>&, hipStream_t, int**);
+template hipError_t inv_batched_flags<double>(DevBuf&, DevBuf&, const std::vector<InvDesc>&, hipStream_t, int*);
+template hipError_t inv_batched_flags<float>(DevBuf&, DevBuf&, const std::vector<InvDesc32>&, hipStream_t, int*);
 
 }  // namespace qps

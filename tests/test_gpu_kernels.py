@@ -33,6 +33,17 @@ def test_hankel_seams_continuous(gpu_lib):
     assert np.abs(h1 - hankel1(1, x)).max() < 5e-15
 
 
+@pytest.mark.parametrize("n", [3, 40, 1030])
+def test_zinv_reports_singular(gpu_lib, n):
+    # a zero column in the second matrix of the batch: no nonzero pivot exists at that step
+    rng = np.random.default_rng(n + 5)
+    A = rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n)) + 3 * np.eye(n)
+    A[1][:, n // 2] = 0.0
+    with pytest.raises(gpu_lib.HBSError) as ei:
+        gpu_lib.zinv(A)
+    assert ei.value.code == -6
+
+
 @pytest.mark.parametrize("m,n,k,trans", [(64, 64, 16, False), (37, 91, 53, False), (130, 70, 200, True),
                                           (1, 1, 1, False), (65, 129, 3, True),
                                           (70, 9, 20011, False), (33, 5, 9000, True)])  # split-K cases
