@@ -430,6 +430,19 @@ int build(hbs_handle* h) {
     h->top_identity = ident;
     if (ident)
       for (int b = 0; b < nb; ++b) s[b] = m[b];  // no sketch
+    // complex128 levels: the diagonal blocks D are inverted on the side stream while the main
+    // stream compresses (W, sketch, column-pivoted QR); the factors wait for the inverse
+    const bool dinv_side = !ident && l <= h->fp64_top;
+    if (dinv_side) {
+      const int rc = side_stream_init(h);
+      if (rc != HBS_OK) return rc;
+      CK(hipEventRecord(h->side_ev[0], st));
+      CK(hipStreamWaitEvent(h->side_stream, h->side_ev[0], 0));
+      std::vector<InvDesc> iv;
+      for (int b = 0; b < nb; ++b) iv.push_back({dG + V.oG[b], V.n[b], V.n[b]});
+      CK(inv_batched_flags(h->arena_s, h->work_s, iv, h->side_stream, flags_for(nb, l, "diagonal block")));
+      CK(hipEventRecord(h->side_ev[1], h->side_stream));
+    }
     for (int b = 0; b < nb; ++b) zoff[b + 1] = zoff[b] + ((s[b] < m[b]) ? (int64_t)s[b] * V.n[b] : 0);
     h->stats.sketch_bytes_max = std::max<int64_t>(h->stats.sketch_bytes_max, (int64_t)sizeof(cplx) * zoff[nb]);
     cplx* dwt = nullptr;
@@ -704,9 +717,7 @@ int build(hbs_handle* h) {
       CK(up_sync(arena, cz, st));
       CK(launch_copy(arena.as<CopyDesc>(), (int)cz.size(), maxe, st));
     } else {
-      std::vector<InvDesc> iv;
-      for (int b = 0; b < nb; ++b) iv.push_back({dG + V.oG[b], V.n[b], V.n[b]});
-      CK(inv_batched_flags(arena, h->work, iv, st, flags_for(nb, l, "diagonal block")));
+      CK(hipStreamWaitEvent(st, h->side_ev[1], 0));
     cplx* Y = tmpY.as<cplx>();
     cplx* Zt = tmpZt.as<cplx>();
     cplx* Dh = V.Dh.as<cplx>();
