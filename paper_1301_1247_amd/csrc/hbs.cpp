@@ -207,6 +207,19 @@ int build(hbs_handle* h) {
 
   DevBuf dnear, wt, zb, zb2, kout, tmpY, tmpZt;
   DevBuf& arena = h->arena;
+  // Two chains per level: the compression (W, sketch, column-pivoted QR, P) on the main stream,
+  // and the factors (diagonal blocks, their inverses, the products with P, the reduced blocks) on
+  // the side stream, which trails.  A level's compression needs only its children's skeletons, so
+  // the main stream never waits for the side stream; the side stream waits for the active set
+  // of each level (event 0) and for its P (event 1).
+  {
+    const int rc = side_stream_init(h);
+    if (rc != HBS_OK) return rc;
+  }
+  hipStream_t sf = h->side_stream;
+  DevBuf& arena_f = h->arena_s;
+  DevBuf& work_f = h->work_s;
+  hipEvent_t ev_act = h->side_ev[0], ev_P = h->side_ev[1];
   // singularity flags of every batched inversion of the build (two per box and level, the root),
   // read once after the final synchronisation so that the host never waits on an inversion
   int64_t nflag = 1;
@@ -251,6 +264,8 @@ int build(hbs_handle* h) {
     CK(V.act.reserve(sizeof(int) * V.ntot));
     CK(hipMemcpyAsync(V.act.p, V.hact.data(), sizeof(int) * V.ntot, hipMemcpyHostToDevice, st));
     const int* dact = V.act.as<int>();
+    CK(hipEventRecord(ev_act, st));
+    CK(hipStreamWaitEvent(sf, ev_act, 0));
 
     // ---- diagonal blocks D (into G, inverted in place later) and forward blocks Df
     V.oG.assign(nb + 1, 0);
@@ -284,23 +299,23 @@ int build(hbs_handle* h) {
         }
       }
       if (!cz.empty()) {
-        CK(up_sync(arena, cz, st));
-        CK(launch_copy(arena.as<CopyDesc>(), (int)cz.size(), maxe, st));
+        CK(up_sync(arena_f, cz, sf));
+        CK(launch_copy(arena_f.as<CopyDesc>(), (int)cz.size(), maxe, sf));
       }
       {
         int maxb = 0;
         for (auto& d : bd) maxb = std::max(maxb, d.nr * d.nc);
-        CK(up_sync(arena, bd, st));
-        ProfScope ps("assemble", st, 0.0, 0.0);
-        CK(launch_eval_blocks(h->geo, arena.as<BlockDesc>(), (int)bd.size(), maxb, st));
+        CK(up_sync(arena_f, bd, sf));
+        ProfScope ps("assemble", sf, 0.0, 0.0);
+        CK(launch_eval_blocks(h->geo, arena_f.as<BlockDesc>(), (int)bd.size(), maxb, sf));
       }
-      CK(up_sync(arena, cp, st));
-      CK(launch_copy(arena.as<CopyDesc>(), (int)cp.size(), maxe, st));
+      CK(up_sync(arena_f, cp, sf));
+      CK(launch_copy(arena_f.as<CopyDesc>(), (int)cp.size(), maxe, sf));
       if (!cd.empty()) {
         int maxc = 0;
         for (auto& d : cd) maxc = std::max(maxc, d.nr * d.nc);
-        CK(up_sync(arena, cd, st));
-        CK(launch_copy(arena.as<CopyDesc>(), (int)cd.size(), maxc, st));
+        CK(up_sync(arena_f, cd, sf));
+        CK(launch_copy(arena_f.as<CopyDesc>(), (int)cd.size(), maxc, sf));
       }
     }
 
@@ -430,18 +445,12 @@ int build(hbs_handle* h) {
     h->top_identity = ident;
     if (ident)
       for (int b = 0; b < nb; ++b) s[b] = m[b];  // no sketch
-    // complex128 levels: the diagonal blocks D are inverted on the side stream while the main
-    // stream compresses (W, sketch, column-pivoted QR); the factors wait for the inverse
-    const bool dinv_side = !ident && l <= h->fp64_top;
-    if (dinv_side) {
-      const int rc = side_stream_init(h);
-      if (rc != HBS_OK) return rc;
-      CK(hipEventRecord(h->side_ev[0], st));
-      CK(hipStreamWaitEvent(h->side_stream, h->side_ev[0], 0));
+    // complex128 levels: the diagonal blocks D are inverted on the side stream (after their
+    // assembly there) while the main stream compresses the level
+    if (!ident && l <= h->fp64_top) {
       std::vector<InvDesc> iv;
       for (int b = 0; b < nb; ++b) iv.push_back({dG + V.oG[b], V.n[b], V.n[b]});
-      CK(inv_batched_flags(h->arena_s, h->work_s, iv, h->side_stream, flags_for(nb, l, "diagonal block")));
-      CK(hipEventRecord(h->side_ev[1], h->side_stream));
+      CK(inv_batched_flags(arena_f, work_f, iv, sf, flags_for(nb, l, "diagonal block")));
     }
     for (int b = 0; b < nb; ++b) zoff[b + 1] = zoff[b] + ((s[b] < m[b]) ? (int64_t)s[b] * V.n[b] : 0);
     h->stats.sketch_bytes_max = std::max<int64_t>(h->stats.sketch_bytes_max, (int64_t)sizeof(cplx) * zoff[nb]);
@@ -643,6 +652,8 @@ int build(hbs_handle* h) {
       CK(up_sync(arena, pd, st));
       CK(launch_buildP(arena.as<PDesc>(), nb, maxe, st));
     }
+    CK(hipEventRecord(ev_P, st));
+    CK(hipStreamWaitEvent(sf, ev_P, 0));
     if (fp32) {
       // complex64 inverse factors from the FP64 blocks D and interpolation matrices P
       CK(V.G32.reserve(sizeof(cplxf) * V.oG[nb]));
@@ -660,11 +671,11 @@ int build(hbs_handle* h) {
       cplxf* Dh32 = dh32.as<cplxf>();
       cplxf* E32 = V.E32.as<cplxf>();
       cplxf* F32 = V.Ft32.as<cplxf>();
-      CK(launch_cast_d2f(dG, G32, V.oG[nb], st));
-      CK(launch_cast_d2f(dP, P32, V.oP[nb], st));
+      CK(launch_cast_d2f(dG, G32, V.oG[nb], sf));
+      CK(launch_cast_d2f(dP, P32, V.oP[nb], sf));
       std::vector<InvDesc32> iv;
       for (int b = 0; b < nb; ++b) iv.push_back({G32 + V.oG[b], V.n[b], V.n[b]});
-      CK(inv_batched_flags<float>(arena, h->work, iv, st, flags_for(nb, l, "diagonal block")));
+      CK(inv_batched_flags<float>(arena_f, work_f, iv, sf, flags_for(nb, l, "diagonal block")));
       const cplxf one = mkcf(1, 0), zero = mkcf(0, 0), mone = mkcf(-1, 0);
       auto g32 = [&](const cplxf* A, int lda, int tA, const cplxf* B, int ldb, cplxf* C, int ldc, int m, int n, int k,
                      cplxf al, cplxf be) {
@@ -679,30 +690,30 @@ int build(hbs_handle* h) {
         g1.push_back(g32(G32 + V.oG[b], n, 0, P32 + V.oP[b], n, Y32 + V.oP[b], n, n, k, n, one, zero));
         g1.push_back(g32(P32 + V.oP[b], n, 1, G32 + V.oG[b], n, Z32 + V.oP[b], k, k, n, n, one, zero));
       }
-      CK(gemm_batched<float>(arena, g1, st));
+      CK(gemm_batched<float>(arena_f, g1, sf));
       for (int b = 0; b < nb; ++b)
         g2.push_back(g32(Z32 + V.oP[b], V.k[b], 0, P32 + V.oP[b], V.n[b], Dh32 + V.oDh[b], V.k[b], V.k[b], V.k[b], V.n[b],
                          one, zero));
-      CK(gemm_batched<float>(arena, g2, st));
+      CK(gemm_batched<float>(arena_f, g2, sf));
       std::vector<InvDesc32> iv2;
       for (int b = 0; b < nb; ++b) iv2.push_back({Dh32 + V.oDh[b], V.k[b], V.k[b]});
-      CK(inv_batched_flags<float>(arena, h->work, iv2, st, flags_for(nb, l, "reduced block")));
+      CK(inv_batched_flags<float>(arena_f, work_f, iv2, sf, flags_for(nb, l, "reduced block")));
       for (int b = 0; b < nb; ++b) {
         const int n = V.n[b], k = V.k[b];
         g3.push_back(g32(Y32 + V.oP[b], n, 0, Dh32 + V.oDh[b], k, E32 + V.oP[b], n, n, k, k, one, zero));
         g3.push_back(g32(Dh32 + V.oDh[b], k, 0, Z32 + V.oP[b], k, F32 + V.oP[b], k, k, n, k, one, zero));
       }
-      CK(gemm_batched<float>(arena, g3, st));
+      CK(gemm_batched<float>(arena_f, g3, sf));
       for (int b = 0; b < nb; ++b)
         g4.push_back(g32(E32 + V.oP[b], V.n[b], 0, Z32 + V.oP[b], V.k[b], G32 + V.oG[b], V.n[b], V.n[b], V.n[b], V.k[b],
                          mone, one));
-      CK(gemm_batched<float>(arena, g4, st));
+      CK(gemm_batched<float>(arena_f, g4, sf));
       // the parent's diagonal block needs D^ in FP64
-      CK(launch_cast_f2d(Dh32, V.Dh.as<cplx>(), V.oDh[nb], st));
+      CK(launch_cast_f2d(Dh32, V.Dh.as<cplx>(), V.oDh[nb], sf));
       V.G.release();  // D itself is not a factor in this mode
     } else if (ident) {
       // P = I: the reduced block is D itself, E = F^T = I and G = D^{-1} - D^{-1} = 0
-      CK(hipMemcpyAsync(V.Dh.p, dG, sizeof(cplx) * V.oG[nb], hipMemcpyDeviceToDevice, st));
+      CK(hipMemcpyAsync(V.Dh.p, dG, sizeof(cplx) * V.oG[nb], hipMemcpyDeviceToDevice, sf));
       std::vector<CopyDesc> ce, cz;
       int maxe = 0;
       for (int b = 0; b < nb; ++b) {
@@ -712,12 +723,11 @@ int build(hbs_handle* h) {
         cz.push_back({nullptr, dG + V.oG[b], n, n, n, n});
         maxe = std::max(maxe, n * n);
       }
-      CK(up_sync(arena, ce, st));
-      CK(launch_eye(arena.as<CopyDesc>(), (int)ce.size(), maxe, st));
-      CK(up_sync(arena, cz, st));
-      CK(launch_copy(arena.as<CopyDesc>(), (int)cz.size(), maxe, st));
+      CK(up_sync(arena_f, ce, sf));
+      CK(launch_eye(arena_f.as<CopyDesc>(), (int)ce.size(), maxe, sf));
+      CK(up_sync(arena_f, cz, sf));
+      CK(launch_copy(arena_f.as<CopyDesc>(), (int)cz.size(), maxe, sf));
     } else {
-      CK(hipStreamWaitEvent(st, h->side_ev[1], 0));
     cplx* Y = tmpY.as<cplx>();
     cplx* Zt = tmpZt.as<cplx>();
     cplx* Dh = V.Dh.as<cplx>();
@@ -733,16 +743,16 @@ int build(hbs_handle* h) {
         // Zt = P^T D^{-1}  (k x n)
         g1.push_back(gd(dP + V.oP[b], n, 1, Di, n, Zt + V.oP[b], k, k, n, n));
       }
-      CK(gemm_batched(arena, g1, st));
+      CK(gemm_batched(arena_f, g1, sf));
       for (int b = 0; b < nb; ++b) {
         const int n = V.n[b], k = V.k[b];
         // S = Zt P (k x k) -> Dh
         g2.push_back(gd(Zt + V.oP[b], k, 0, dP + V.oP[b], n, Dh + V.oDh[b], k, k, k, n));
       }
-      CK(gemm_batched(arena, g2, st));
+      CK(gemm_batched(arena_f, g2, sf));
       std::vector<InvDesc> iv;
       for (int b = 0; b < nb; ++b) iv.push_back({Dh + V.oDh[b], V.k[b], V.k[b]});
-      CK(inv_batched_flags(arena, h->work, iv, st, flags_for(nb, l, "reduced block")));
+      CK(inv_batched_flags(arena_f, work_f, iv, sf, flags_for(nb, l, "reduced block")));
       std::vector<GemmDesc> g3, g4;
       for (int b = 0; b < nb; ++b) {
         const int n = V.n[b], k = V.k[b];
@@ -750,13 +760,13 @@ int build(hbs_handle* h) {
         g3.push_back(gd(Y + V.oP[b], n, 0, Dh + V.oDh[b], k, E + V.oP[b], n, n, k, k));
         g3.push_back(gd(Dh + V.oDh[b], k, 0, Zt + V.oP[b], k, Ft + V.oP[b], k, k, n, k));
       }
-      CK(gemm_batched(arena, g3, st));
+      CK(gemm_batched(arena_f, g3, sf));
       for (int b = 0; b < nb; ++b) {
         const int n = V.n[b], k = V.k[b];
         // G = D^{-1} - E Zt  (in place)
         g4.push_back(gd(E + V.oP[b], n, 0, Zt + V.oP[b], k, dG + V.oG[b], n, n, n, k, mkc(-1, 0), mkc(1, 0)));
       }
-      CK(gemm_batched(arena, g4, st));
+      CK(gemm_batched(arena_f, g4, sf));
     }
     }
     if (l < L) h->lv[l + 1].Dh.release();
@@ -764,7 +774,9 @@ int build(hbs_handle* h) {
                             : (int64_t)sizeof(cplx) * (3 * V.oP[nb] + 2 * V.oG[nb]);
   }
 
-  // ---- root
+  // ---- root (side stream: it needs level 1's reduced blocks; the skeletons came from the main stream)
+  CK(hipEventRecord(ev_act, st));
+  CK(hipStreamWaitEvent(sf, ev_act, 0));
   {
     Level& V = h->lv[1];
     const int ka = V.k[0], kc = V.k[1];
@@ -777,25 +789,26 @@ int build(hbs_handle* h) {
     const int* sa = V.skel.as<int>();
     const int* sc = V.skel.as<int>() + V.soff[1];
     std::vector<CopyDesc> cz = {{nullptr, Rf, n, n, n, n}};
-    CK(up_sync(arena, cz, st));
-    CK(launch_copy(arena.as<CopyDesc>(), 1, n * n, st));
+    CK(up_sync(arena_f, cz, sf));
+    CK(launch_copy(arena_f.as<CopyDesc>(), 1, n * n, sf));
     std::vector<BlockDesc> bd = {{sa, sc, Rf + (int64_t)ka * n, ka, kc, n, 0}, {sc, sa, Rf + ka, kc, ka, n, 0}};
-    CK(up_sync(arena, bd, st));
-    CK(launch_eval_blocks(h->geo, arena.as<BlockDesc>(), 2, std::max(ka * kc, 1), st));
+    CK(up_sync(arena_f, bd, sf));
+    CK(launch_eval_blocks(h->geo, arena_f.as<BlockDesc>(), 2, std::max(ka * kc, 1), sf));
     std::vector<CopyDesc> cp = {{Rf, Ri, n, n, n, n}};
-    CK(up_sync(arena, cp, st));
-    CK(launch_copy(arena.as<CopyDesc>(), 1, n * n, st));
+    CK(up_sync(arena_f, cp, sf));
+    CK(launch_copy(arena_f.as<CopyDesc>(), 1, n * n, sf));
     std::vector<CopyDesc> cd = {{V.Dh.as<cplx>() + V.oDh[0], Ri, ka, ka, ka, n},
                                 {V.Dh.as<cplx>() + V.oDh[1], Ri + (int64_t)ka * n + ka, kc, kc, kc, n}};
-    CK(up_sync(arena, cd, st));
-    CK(launch_copy(arena.as<CopyDesc>(), 2, std::max(ka * ka, kc * kc), st));
+    CK(up_sync(arena_f, cd, sf));
+    CK(launch_copy(arena_f.as<CopyDesc>(), 2, std::max(ka * ka, kc * kc), sf));
     std::vector<InvDesc> iv = {{Ri, n, n}};
-    CK(inv_batched_flags(arena, h->work, iv, st, flags_for(1, 0, "root matrix")));
+    CK(inv_batched_flags(arena_f, work_f, iv, sf, flags_for(1, 0, "root matrix")));
     V.Dh.release();
     h->factor_bytes += (int64_t)sizeof(cplx) * 2 * n * n;
   }
   std::vector<int> hflags(foff);
-  if (foff > 0) CK(hipMemcpyAsync(hflags.data(), dflags.p, sizeof(int) * foff, hipMemcpyDeviceToHost, st));
+  if (foff > 0) CK(hipMemcpyAsync(hflags.data(), dflags.p, sizeof(int) * foff, hipMemcpyDeviceToHost, sf));
+  CK(hipStreamSynchronize(sf));
   CK(hipStreamSynchronize(st));
   for (const auto& fr : franges)
     for (int b = 0; b < fr.cnt; ++b)
