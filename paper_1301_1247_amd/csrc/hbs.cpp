@@ -20,7 +20,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
-#include <map>
+#include <unordered_map>
 
 namespace qps {
 
@@ -332,12 +332,39 @@ int build(hbs_handle* h) {
       gy0 = std::min(gy0, V.cy[b]);
     }
     const double cell = std::max((ratio + 1.0) * maxrad, 1e-300);
-    std::map<std::pair<int64_t, int64_t>, std::vector<int>> grid;
-    auto key = [&](double x, double y) {
-      return std::make_pair((int64_t)std::floor((x - gx0) / cell), (int64_t)std::floor((y - gy0) / cell));
+    // cells of side `cell` holding linked lists of box centres: a dense array of list heads, or a
+    // hash of the occupied cells when the obstacle spans very many cells
+    double gx1 = -1e300, gy1 = -1e300;
+    for (int b = 0; b < nb; ++b) {
+      gx1 = std::max(gx1, V.cx[b]);
+      gy1 = std::max(gy1, V.cy[b]);
+    }
+    // a cell grid beyond 1e9 cells per side (degenerate, tiny boxes) takes every box as a candidate
+    const double fcx = (gx1 - gx0) / cell, fcy = (gy1 - gy0) / cell;
+    const bool allc = exact || !(fcx < 1e9 && fcy < 1e9);
+    const int64_t ncx = allc ? 1 : (int64_t)std::floor(fcx) + 1;
+    const int64_t ncy = allc ? 1 : (int64_t)std::floor(fcy) + 1;
+    const bool dense = !allc && ncx * ncy <= ((int64_t)1 << 23);
+    std::vector<int> cell_head(dense ? ncx * ncy : 0, -1), cell_next(nb, -1);
+    std::unordered_map<int64_t, int> cell_hash;
+    auto head = [&](int64_t c) -> int& { return dense ? cell_head[c] : cell_hash.emplace(c, -1).first->second; };
+    auto head_find = [&](int64_t c) -> int {
+      if (dense) return cell_head[c];
+      auto it = cell_hash.find(c);
+      return it == cell_hash.end() ? -1 : it->second;
     };
-    if (!exact)
-      for (int c = 0; c < nb; ++c) grid[key(V.cx[c], V.cy[c])].push_back(c);
+    auto cell_of = [&](double x, double y, int64_t* ix, int64_t* iy) {
+      *ix = std::min<int64_t>(ncx - 1, std::max<int64_t>(0, (int64_t)std::floor((x - gx0) / cell)));
+      *iy = std::min<int64_t>(ncy - 1, std::max<int64_t>(0, (int64_t)std::floor((y - gy0) / cell)));
+    };
+    if (!allc)
+      for (int c = nb - 1; c >= 0; --c) {
+        int64_t ix, iy;
+        cell_of(V.cx[c], V.cy[c], &ix, &iy);
+        int& hd = head(ix + ncx * iy);
+        cell_next[c] = hd;
+        hd = c;
+      }
     std::vector<int> cand;
     std::vector<double> mind(nb);
     for (int b = 0; b < nb; ++b) {
@@ -346,15 +373,14 @@ int build(hbs_handle* h) {
       double md = std::max(0.0, Rp - V.rad[b]);
       const int64_t total_other = V.ntot - V.n[b];
       cand.clear();
-      if (exact) {
+      if (allc) {
         for (int c = 0; c < nb; ++c) cand.push_back(c);
       } else {
-        const auto k0 = key(V.cx[b], V.cy[b]);
-        for (int64_t dx = -1; dx <= 1; ++dx)
-          for (int64_t dy = -1; dy <= 1; ++dy) {
-            auto it = grid.find(std::make_pair(k0.first + dx, k0.second + dy));
-            if (it != grid.end()) cand.insert(cand.end(), it->second.begin(), it->second.end());
-          }
+        int64_t ix, iy;
+        cell_of(V.cx[b], V.cy[b], &ix, &iy);
+        for (int64_t jy = std::max<int64_t>(0, iy - 1); jy <= std::min<int64_t>(ncy - 1, iy + 1); ++jy)
+          for (int64_t jx = std::max<int64_t>(0, ix - 1); jx <= std::min<int64_t>(ncx - 1, ix + 1); ++jx)
+            for (int c = head_find(jx + ncx * jy); c >= 0; c = cell_next[c]) cand.push_back(c);
         cand.push_back((b + 1) % nb);
         cand.push_back((b + nb - 1) % nb);
         std::sort(cand.begin(), cand.end());
@@ -367,7 +393,7 @@ int build(hbs_handle* h) {
         const double ex = V.cx[c] - V.cx[b], ey = V.cy[c] - V.cy[b];
         const bool nr = exact || adj || std::sqrt(ex * ex + ey * ey) < Rp + V.rad[c];
         if (nr) {
-          for (int i = 0; i < V.n[c]; ++i) hnear.push_back(V.hact[V.aoff[c] + i]);
+          hnear.insert(hnear.end(), V.hact.begin() + V.aoff[c], V.hact.begin() + V.aoff[c] + V.n[c]);
           cnt += V.n[c];
           if (!adj) md = std::min(md, std::max(0.0, std::sqrt(ex * ex + ey * ey) - V.rad[c] - V.rad[b]));
         }
@@ -869,7 +895,7 @@ int apply_interp(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx
     ProfScope ps("zgemm", st, rc.flops, 0.0);
     CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.max_tiles, st));
   }
-  CK(hipStreamSynchronize(st));
+  // stream-ordered: the caller's later work on the handle's stream sees the result
   return HBS_OK;
 }
 
@@ -913,7 +939,7 @@ int apply_down_E(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx
     ProfScope ps("zgemm", st, rc.flops, 0.0);
     CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.max_tiles, st));
   }
-  CK(hipStreamSynchronize(st));
+  // stream-ordered: the caller's later work on the handle's stream sees the result
   return HBS_OK;
 }
 
@@ -952,7 +978,7 @@ int apply_interp_t(hbs_handle* h, const cplx* X, int64_t ldx, cplx* Z, int64_t l
     ProfScope ps("zgemm", st, rc.flops, 0.0);
     CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.max_tiles, st));
   }
-  CK(hipStreamSynchronize(st));
+  // stream-ordered: the caller's later work on the handle's stream sees the result
   return HBS_OK;
 }
 
@@ -985,8 +1011,12 @@ struct Step {
 };
 }  // namespace
 
+// phase 0: the whole apply; 1: the upward pass and the root product only; 2: the downward pass
+// only, from root_set (nroot x r) when given, else from the root workspace as phase 1 left it (the
+// upward results of the same B stay in the handle's workspace between the two calls)
 static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r,
-                       bool sync = true) {
+                       bool sync = true, const cplx* root_add = nullptr, cplx* root_up = nullptr, int phase = 0,
+                       const cplx* root_set = nullptr) {
   if (r <= 0) return HBS_OK;
   hipStream_t st = h->stream;
   const int L = h->L;
@@ -1090,9 +1120,10 @@ static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_
   {
     size_t s0 = d64.size();
     const cplx* Rt = inv ? h->Rinv.as<cplx>() : h->Rfwd.as<cplx>();
-    d64.push_back(gdt<double>(Rt, h->nroot, 0, u64(0), h->nroot, xr, h->nroot, h->nroot, rr, h->nroot, 0.0));
+    d64.push_back(gdt<double>(Rt, h->nroot, 0, u64(0), h->nroot, xr, h->nroot, h->nroot, rr, h->nroot, root_add ? 1.0 : 0.0));
     close64(s0);
   }
+  const size_t down_begin = prog.size();
   // ---- downward
   for (int l = 1; l <= L; ++l) {
     Level& V = lv[l];
@@ -1146,8 +1177,14 @@ static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_
   double fl = 0;
   for (auto& t : prog) fl += t.flops;
   // issue the program on stream s (profiled per launch unless it is being captured)
+  if (phase != 0 && mixed) {
+    set_error("hbs apply: a split apply needs complex128 factors on every level");
+    return HBS_E_INVALID_ARG;
+  }
+  const size_t p0 = phase == 2 ? down_begin : 0, p1 = phase == 1 ? down_begin : prog.size();
   auto issue = [&](const GemmDesc* dd64, const GemmDesc32* dd32, hipStream_t s, bool prof) -> hipError_t {
-    for (auto& t : prog) {
+    for (size_t ti = p0; ti < p1; ++ti) {
+      const Step& t = prog[ti];
       hipError_t e;
       if (t.kind == 0) {
         ProfScope ps2(prof ? "zgemm" : nullptr, s, t.flops, 0.0);
@@ -1164,6 +1201,14 @@ static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_
     }
     return hipSuccess;
   };
+  const int64_t nroot = h->nroot;
+  if (root_add) CK(hipMemcpyAsync(xr, root_add, sizeof(cplx) * nroot * r, hipMemcpyDeviceToDevice, st));
+  if (phase == 2 && root_set) CK(hipMemcpyAsync(xr, root_set, sizeof(cplx) * nroot * r, hipMemcpyDeviceToDevice, st));
+  auto copy_root_up = [&]() -> hipError_t {
+    // the upward result at the root (u64(0), nroot x r) is not touched by the downward pass
+    if (!root_up) return hipSuccess;
+    return hipMemcpyAsync(root_up, u64(0), sizeof(cplx) * nroot * r, hipMemcpyDeviceToDevice, st);
+  };
   if (h->opts.graph) {
     // capture once per operand set on a private stream (kernels only: the descriptors live in the
     // graph's own buffers, uploaded before the capture), then replay on the handle's stream
@@ -1171,15 +1216,18 @@ static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_
                          h->ab_x32b.p};
     ApplyGraph* g = nullptr;
     for (auto& c : h->graphs)
-      if (c->inv == inv && c->split == split && c->B == B && c->ldb == ldb && c->X == X && c->ldx == ldx && c->r == r &&
-          std::equal(ws, ws + 8, c->ws))
+      if (c->inv == inv && c->root_acc == (root_add != nullptr) && c->phase == phase && c->split == split && c->B == B &&
+          c->ldb == ldb &&
+          c->X == X && c->ldx == ldx && c->r == r && std::equal(ws, ws + 8, c->ws))
         g = c.get();
     if (!g) {
       if (!h->cap_stream) CK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
       if (h->graphs.size() >= 4) h->graphs.erase(h->graphs.begin());
       h->graphs.emplace_back(new ApplyGraph);
       g = h->graphs.back().get();
-      g->inv = inv; g->split = split; g->B = B; g->ldb = ldb; g->X = X; g->ldx = ldx; g->r = r;
+      g->inv = inv; g->root_acc = root_add != nullptr; g->phase = phase; g->split = split; g->B = B; g->ldb = ldb; g->X = X;
+      g->ldx = ldx;
+      g->r = r;
       std::copy(ws, ws + 8, g->ws);
       CK(upload(g->d64, d64, st));
       if (!d32.empty()) CK(upload(g->d32, d32, st));
@@ -1207,6 +1255,7 @@ static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_
       ProfScope ps("apply", st, fl, 0.0);
       CK(hipGraphLaunch(g->exec, st));
     }
+    CK(copy_root_up());
     if (sync) CK(hipStreamSynchronize(st));
     return HBS_OK;
   }
@@ -1216,8 +1265,27 @@ static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_
     ProfScope ps("apply", st, fl, 0.0);
     CK(issue(h->arena.as<GemmDesc>(), d32.empty() ? nullptr : h->arena32.as<GemmDesc32>(), st, true));
   }
+  CK(copy_root_up());
   if (sync) CK(hipStreamSynchronize(st));
   return HBS_OK;
+}
+
+int apply_forward_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r, const cplx* root_add,
+                       cplx* root_up) {
+  return apply_mixed(h, false, h->L, B, ldb, X, ldx, r, false, root_add, root_up);
+}
+
+int apply_inverse_up(hbs_handle* h, const cplx* B, int64_t ldb, int64_t r, cplx* root, int64_t ldr) {
+  int rc = apply_mixed(h, true, h->fp64_top, B, ldb, nullptr, 0, r, false, nullptr, nullptr, 1);
+  if (rc != HBS_OK || r <= 0) return rc;
+  const int64_t n = h->nroot;
+  CK(hipMemcpy2DAsync(root, sizeof(cplx) * ldr, h->ab_root.p, sizeof(cplx) * n, sizeof(cplx) * n, r, hipMemcpyDeviceToDevice,
+                      h->stream));
+  return HBS_OK;
+}
+
+int apply_inverse_down(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r, const cplx* root_in) {
+  return apply_mixed(h, true, h->fp64_top, B, ldb, X, ldx, r, false, nullptr, nullptr, 2, root_in);
 }
 
 int apply_factors(hbs_handle* h, bool inv, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r) {

@@ -29,6 +29,8 @@ struct Level {
 // uses the same operands and the apply workspaces have not moved.
 struct ApplyGraph {
   bool inv = false;
+  bool root_acc = false;  // the root product accumulates (beta = 1)
+  int phase = 0;          // whole apply, upward + root only, or downward only
   int split = 0;
   const void* B = nullptr;
   void* X = nullptr;
@@ -85,6 +87,17 @@ int apply_interp_t(hbs_handle* h, const cplx* X, int64_t ldx, cplx* Z, int64_t l
 // X = E_L ... E_1 Z (complex128 levels only): A^{-1} U from Z = R^{-1}
 int apply_down_E(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx, int64_t r);
 // X = A^{-1} B and root (nroot x r) = U^T A^{-1} B, the root solution of the same apply
+// X = A B (compressed forward operator) with root_add (nroot x r, or null) added to the root's
+// downward input, so that X = A B + U root_add, and root_up (nroot x r, or null) = U^T B, the
+// upward result at the root (U: the nested interpolation).  Stream-ordered, no host wait.
+int apply_forward_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r, const cplx* root_add,
+                       cplx* root_up);
+// A^{-1} B in two calls (complex128 factors only): the upward pass and the root product, with the
+// root solution U^T A^{-1} B (nroot x r) copied to root; later the downward pass from root_in
+// (nroot x r, ld nroot) instead of that root solution, writing X.  The upward results of B stay
+// in the handle's apply workspace in between: no other apply may run on the handle meanwhile.
+int apply_inverse_up(hbs_handle* h, const cplx* B, int64_t ldb, int64_t r, cplx* root, int64_t ldr);
+int apply_inverse_down(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r, const cplx* root_in);
 // (sync = false leaves the work stream-ordered on the handle's stream without waiting for it)
 int apply_inverse_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r, cplx* root, int64_t ldr,
                        bool sync = true);

@@ -494,7 +494,12 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
         CR(woodbury(h->side_stream, h->arena_s, h->splitws_s, h->work_s, &side_dinfo));
         CK(hipEventRecord(h->side_ev[1], h->side_stream));
       }
-      CR(apply_inverse_root(h, Y + (size_t)ycolB * N, N, X + (size_t)ycolB * N, N, nang, Zt + (size_t)nu * nu, nu, !overlap));
+      if (overlap) {
+        // only the upward pass and the root now: eta comes from one downward pass once xi is known
+        CR(apply_inverse_up(h, Y + (size_t)ycolB * N, N, nang, Zt + (size_t)nu * nu, nu));
+      } else {
+        CR(apply_inverse_root(h, Y + (size_t)ycolB * N, N, X + (size_t)ycolB * N, N, nang, Zt + (size_t)nu * nu, nu));
+      }
       // V itself is needed only with neighbour images; without them X(alpha) xi = V (B_J v) is
       // applied as E_L ... E_1 (R^{-1} B_J v) where needed
       if (P) CR(apply_down_E(h, Zt, nu, X + (size_t)ycolU * N, N, nu));
@@ -688,8 +693,17 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   CR(solve_S(Wv, xi, minus1c));
   // eta = X_b - X(alpha) xi - V K (R X_b - R X(alpha) xi)
   CK(launch_stack(M2, nang, d_al, xi, stk, st));
-  CK(launch_axpby(N, nang, onec, X + (size_t)ycolB * N, N, zero, eta, N, st));
-  CR(sub_Xv(stk, eta));
+  if (overlap) {
+    // eta = A^{-1} b - A^{-1} U (B_J v): one downward pass from the root vector
+    // U^T A^{-1} b - R^{-1} B_J v (the upward results of b are still in the apply workspace)
+    CR(gemm({gd(BJ, nu, 0, stk, M4, t1, nu, nu, nang, M4, onec, zero)}));
+    CR(gemm({gd(Zt, nu, 0, t1, nu, t2, nu, nu, nang, nu, onec, zero)}));
+    CK(launch_axpby(nu, nang, onec, Zt + (size_t)nu * nu, nu, minus1c, t2, nu, st));
+    CR(apply_inverse_down(h, Y + (size_t)ycolB * N, N, eta, N, nang, t2));
+  } else {
+    CK(launch_axpby(N, nang, onec, X + (size_t)ycolB * N, N, zero, eta, N, st));
+    CR(sub_Xv(stk, eta));
+  }
   // eta -= V K [R b - R X(alpha) xi], assembled in uu/yy
   auto nb_correction = [&](const cplx* Rz, const cplx* xs, cplx sign) -> int {
     // vv = Rz - RAX xs (per group), yy = K vv, eta += sign * V yy
@@ -719,17 +733,32 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   int iters = 0;
   for (int it = 0; it <= maxit; ++it) {
     // R1 = b - A~ eta - B(alpha) xi ;  R2 = -C~(alpha) eta - Q(alpha) xi
-    CR(apply_factors(h, false, eta, N, F, N, nang));
-    if (P) {
-      CR(gemm({gd(Rp, nr, 0, eta, N, uu, nr, nr, nang, N, onec, zero), gd(Rm, nr, 0, eta, N, yy, nr, nr, nang, N, onec, zero)}));
-      CK(launch_lincomb(nr, nang, d_al, d_ainv, 1, uu, nr, yy, nr, nullptr, 0, vv, nr, st));
-      CR(apply_interp(h, vv, nr, Z1, N, nang));
-      CK(launch_axpby(N, nang, onec, Z1, N, onec, F, N, st));
+    if (cw) {
+      // every U-term enters at the root of one forward apply: F = A eta + U (B_J v [+ R(alpha) eta]),
+      // and the same apply's upward result at the root is U^T eta (C eta = C_J U^T eta)
+      CR(gemm({gd(BJ, nu, 0, stk, M4, t1, nu, nu, nang, M4, onec, zero)}));
+      if (P) {
+        CR(gemm({gd(Rp, nr, 0, eta, N, uu, nr, nr, nang, N, onec, zero), gd(Rm, nr, 0, eta, N, yy, nr, nr, nang, N, onec, zero)}));
+        CK(launch_lincomb(nr, nang, d_al, d_ainv, 1, uu, nr, yy, nr, nullptr, 0, vv, nr, st));
+        CK(launch_axpby(nr, nang, onec, vv, nr, onec, t1, nu, st));
+      }
+      CR(apply_forward_root(h, eta, N, F, N, nang, t1, t2));
+      CK(launch_axpby(N, nang, onec, Y + (size_t)ycolB * N, N, zero, R1, N, st));
+      CK(launch_axpby(N, nang, minus1c, F, N, onec, R1, N, st));
+      CR(gemm({gd(C1, M2, 0, t2, nu, T1, M2, M2, nang, nu, onec, zero), gd(C2, M2, 0, t2, nu, T2, M2, M2, nang, nu, onec, zero)}));
+    } else {
+      CR(apply_factors(h, false, eta, N, F, N, nang));
+      if (P) {
+        CR(gemm({gd(Rp, nr, 0, eta, N, uu, nr, nr, nang, N, onec, zero), gd(Rm, nr, 0, eta, N, yy, nr, nr, nang, N, onec, zero)}));
+        CK(launch_lincomb(nr, nang, d_al, d_ainv, 1, uu, nr, yy, nr, nullptr, 0, vv, nr, st));
+        CR(apply_interp(h, vv, nr, Z1, N, nang));
+        CK(launch_axpby(N, nang, onec, Z1, N, onec, F, N, st));
+      }
+      CK(launch_axpby(N, nang, onec, Y + (size_t)ycolB * N, N, zero, R1, N, st));
+      CK(launch_axpby(N, nang, minus1c, F, N, onec, R1, N, st));
+      CR(sub_Bv(stk, R1));
+      CR(C_v(eta, T1, T2));
     }
-    CK(launch_axpby(N, nang, onec, Y + (size_t)ycolB * N, N, zero, R1, N, st));
-    CK(launch_axpby(N, nang, minus1c, F, N, onec, R1, N, st));
-    CR(sub_Bv(stk, R1));
-    CR(C_v(eta, T1, T2));
     CK(launch_resid2(Q, nang, d_al, d_c1, d_c2, T1, T2, xi, R2, st));
     CK(launch_colnorm2(N, nang, R1, N, nrm, st));
     CK(launch_colnorm2(M2, nang, R2, M2, nrm + nang, st));
