@@ -393,7 +393,7 @@ __global__ __launch_bounds__(NTP) void k_gj_panel(const InvDescT<R>* __restrict_
 }
 
 // Register-resident variant for n <= 1024: thread i holds row i of the NBR-column panel, and a
-// pivot step costs one barrier.  Before it, every wavefront publishes its best candidate (a key
+// pivot step costs one barrier and two LDS reads per wavefront.  Before it, every wavefront publishes its best candidate (a key
 // holding |a|^2 with the row index in its low 11 bits, so one 64-bit max finds the pivot, ties
 // going to the smaller row) together with that candidate's whole row, and the thread of row p
 // publishes row p; after it, every thread picks the winning wavefront and reads the pivot row
@@ -438,12 +438,10 @@ __device__ __forceinline__ void gj_pivot_steps(typename cx<R>::T (&a)[GJ_NBR], G
       for (int j = 0; j < GJ_NBR; ++j) sh.rowo[buf][j] = a[j];
     }
     __syncthreads();
-    unsigned long long best = sh.key[buf][0];
+    // the wavefronts' keys: one LDS read per lane and a wavefront max; the pivot row: one LDS read
+    // by lanes 0..15 and lane broadcasts (wavefront-uniform values, no per-lane LDS traffic)
     const int nwv = blockDim.x >> 6;
-    for (int q = 1; q < nwv; ++q) {
-      const unsigned long long kq = sh.key[buf][q];
-      best = kq > best ? kq : best;
-    }
+    const unsigned long long best = wave_umax64(lane < nwv ? sh.key[buf][lane] : 0ull);
     const bool ok = (best >> 11) != 0;  // a nonzero pivot exists
     const int r = ok ? 0x7FF - (int)(best & 0x7FF) : p;
     const C_t* prow = ok ? sh.cand[buf][r >> 6] : sh.rowo[buf];
@@ -451,11 +449,15 @@ __device__ __forceinline__ void gj_pivot_steps(typename cx<R>::T (&a)[GJ_NBR], G
       ipiv[p] = r;
       if (!ok) *info_m = p + 1;
     }
-    const C_t piv = prow[JJ];
+    const C_t pl = lane < GJ_NBR ? prow[lane] : zero;
+    C_t pr[GJ_NBR];
+#pragma unroll
+    for (int j = 0; j < GJ_NBR; ++j) pr[j] = lane_bcast(pl, j);
+    const C_t piv = pr[JJ];
     const C_t dd = (cabs2(piv) > 0) ? cinv(piv) : zero;
     if (i == p) {
 #pragma unroll
-      for (int j = 0; j < GJ_NBR; ++j) a[j] = (j == JJ) ? dd : cmul(prow[j], dd);
+      for (int j = 0; j < GJ_NBR; ++j) a[j] = (j == JJ) ? dd : cmul(pr[j], dd);
     } else if (i < n) {
       if (i == r) {
 #pragma unroll
@@ -465,7 +467,7 @@ __device__ __forceinline__ void gj_pivot_steps(typename cx<R>::T (&a)[GJ_NBR], G
       const C_t fd = cmul(f, dd);
 #pragma unroll
       for (int j = 0; j < GJ_NBR; ++j)
-        if (j != JJ) a[j] = csub(a[j], cmul(fd, prow[j]));
+        if (j != JJ) a[j] = csub(a[j], cmul(fd, pr[j]));
       a[JJ] = cx<R>::make(-fd.x, -fd.y);
     }
     if constexpr (JJ + 1 < GJ_NBR) gj_pivot_steps<R, JJ + 1>(a, sh, c0, w, n, ipiv, info_m);

@@ -142,6 +142,19 @@ __device__ inline unsigned long long wave_umax64(unsigned long long v) {
   return ((unsigned long long)hi << 32) | lo;
 }
 
+// the value of lane j of a wavefront, for every lane (the result is wavefront-uniform)
+__device__ __forceinline__ cplx lane_bcast(cplx v, int j) {
+  const long long bx = __double_as_longlong(v.x), by = __double_as_longlong(v.y);
+  const int xl = __builtin_amdgcn_readlane((int)bx, j), xh = __builtin_amdgcn_readlane((int)(bx >> 32), j);
+  const int yl = __builtin_amdgcn_readlane((int)by, j), yh = __builtin_amdgcn_readlane((int)(by >> 32), j);
+  return mkc(__longlong_as_double(((long long)xh << 32) | (unsigned)xl),
+             __longlong_as_double(((long long)yh << 32) | (unsigned)yl));
+}
+__device__ __forceinline__ cplxf lane_bcast(cplxf v, int j) {
+  return mkcf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), j)),
+              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), j)));
+}
+
 // arg-max of (val, idx) over a wavefront, ties resolved to the smaller index; values <= 0
 // (including the -1 of lanes without a candidate) compare as 0.  The bit pattern of a
 // non-negative double orders like the value, so the max is taken on its high then low word.
