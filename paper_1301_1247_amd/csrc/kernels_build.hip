@@ -111,7 +111,9 @@ __global__ __launch_bounds__(NT) void k_sketch(const SketchDesc* __restrict__ de
 // memory latency of the column updates).
 constexpr int CPQR_MAXN = 2048;
 constexpr int CPQR_MAXS = 4608;
-template <int NTQ, int MAXS, int MAXN>
+// RC > 0: while the trailing rows fit in RC per lane (16 lanes per column), a column's rows are
+// loaded into registers in one burst, so its inner product and update wait for memory once.
+template <int NTQ, int MAXS, int MAXN, int RC>
 __global__ __launch_bounds__(NTQ) void k_cpqr(const CpqrDesc* __restrict__ descs, double tol, int* __restrict__ k_out) {
   const CpqrDesc d = descs[blockIdx.x];
   const int s = d.s, n = d.n;
@@ -181,23 +183,56 @@ __global__ __launch_bounds__(NTQ) void k_cpqr(const CpqrDesc* __restrict__ descs
     // the trailing norms.  Each 16-lane row of a wavefront takes one column, so one reduction
     // instruction serves four columns.
     const int sub = lane >> 4, rl = lane & 15;
-    for (int j0 = p + 1 + 4 * wv; j0 < n; j0 += 4 * nw) {
-      const int j = j0 + sub;
-      const bool act = j < n;
-      cplx* col = Z + (size_t)(act ? j : p) * s;
-      cplx w = mkc(0, 0);
-      if (act)
-        for (int i = p + rl; i < s; i += 16) w = cadd(w, cmul(cconj(i == p ? v0 : v[i]), col[i]));
-      w = cscale(row16_csum(w), tau);
-      double an = 0.0;
-      if (act)
-        for (int i = p + rl; i < s; i += 16) {
-          const cplx z = csub(col[i], cmul(w, i == p ? v0 : v[i]));
-          col[i] = z;
-          if (i > p) an += cabs2(z);
+    if (RC > 0 && s - p <= 16 * RC) {
+      for (int j0 = p + 1 + 4 * wv; j0 < n; j0 += 4 * nw) {
+        const int j = j0 + sub;
+        const bool act = j < n;
+        cplx* col = Z + (size_t)(act ? j : p) * s;
+        cplx c[RC > 0 ? RC : 1];
+#pragma unroll
+        for (int t = 0; t < RC; ++t) {
+          const int i = p + rl + 16 * t;
+          c[t] = (act && i < s) ? col[i] : mkc(0, 0);
         }
-      an = row16_sum(an);
-      if (act && rl == 0) cn[j] = an;
+        cplx w = mkc(0, 0);
+#pragma unroll
+        for (int t = 0; t < RC; ++t) {
+          const int i = p + rl + 16 * t;
+          if (i < s) w = cadd(w, cmul(cconj(i == p ? v0 : v[i]), c[t]));
+        }
+        w = cscale(row16_csum(w), tau);
+        double an = 0.0;
+#pragma unroll
+        for (int t = 0; t < RC; ++t) {
+          const int i = p + rl + 16 * t;
+          if (act && i < s) {
+            const cplx z = csub(c[t], cmul(w, i == p ? v0 : v[i]));
+            col[i] = z;
+            if (i > p) an += cabs2(z);
+          }
+        }
+        an = row16_sum(an);
+        if (act && rl == 0) cn[j] = an;
+      }
+    } else {
+      for (int j0 = p + 1 + 4 * wv; j0 < n; j0 += 4 * nw) {
+        const int j = j0 + sub;
+        const bool act = j < n;
+        cplx* col = Z + (size_t)(act ? j : p) * s;
+        cplx w = mkc(0, 0);
+        if (act)
+          for (int i = p + rl; i < s; i += 16) w = cadd(w, cmul(cconj(i == p ? v0 : v[i]), col[i]));
+        w = cscale(row16_csum(w), tau);
+        double an = 0.0;
+        if (act)
+          for (int i = p + rl; i < s; i += 16) {
+            const cplx z = csub(col[i], cmul(w, i == p ? v0 : v[i]));
+            col[i] = z;
+            if (i > p) an += cabs2(z);
+          }
+        an = row16_sum(an);
+        if (act && rl == 0) cn[j] = an;
+      }
     }
     __syncthreads();
   }
@@ -694,9 +729,9 @@ hipError_t launch_sketch(const SketchDesc* d, int nd, int max_s, int max_n, uint
 hipError_t launch_cpqr(const CpqrDesc* d, int nd, int max_s, int max_n, double tol, int* k_out, hipStream_t s) {
   if (nd == 0) return hipSuccess;
   if (nd >= 256 && max_s <= 512 && max_n <= 256)
-    hipLaunchKernelGGL((k_cpqr<256, 512, 256>), dim3(nd), dim3(256), 0, s, d, tol, k_out);
+    hipLaunchKernelGGL((k_cpqr<256, 512, 256, 0>), dim3(nd), dim3(256), 0, s, d, tol, k_out);
   else
-    hipLaunchKernelGGL((k_cpqr<1024, CPQR_MAXS, CPQR_MAXN>), dim3(nd), dim3(1024), 0, s, d, tol, k_out);
+    hipLaunchKernelGGL((k_cpqr<1024, CPQR_MAXS, CPQR_MAXN, 18>), dim3(nd), dim3(1024), 0, s, d, tol, k_out);
   return hipGetLastError();
 }
 hipError_t launch_buildP(const PDesc* d, int nd, int max_elems, hipStream_t s) {
