@@ -113,7 +113,9 @@ int build(hbs_handle* h) {
   const int npfar = far_on ? std::max(pmin, 2 * (int)std::ceil(om * Rfar + std::log(1.0 / h->tol) /
                                                                   std::log(Rfar / h->robs)) + 8) : 0;
 
-  // box ranges and bounding circles of the original points (all levels in one launch)
+  // box ranges, bounding circles and the predictor's geometric features (max and mean |curvature|,
+  // arc length) of the original points, all levels in one launch
+  std::vector<std::vector<double>> kmaxb(L + 1), kmeanb(L + 1), arcb(L + 1);
   {
     std::vector<int> blo, bhi;
     for (int l = 1; l <= L; ++l) {
@@ -132,12 +134,12 @@ int build(hbs_handle* h) {
     DevBuf dlo, dhi, dcirc;
     CK(dlo.reserve(sizeof(int) * nbox));
     CK(dhi.reserve(sizeof(int) * nbox));
-    CK(dcirc.reserve(sizeof(double) * 7 * nbox));
+    CK(dcirc.reserve(sizeof(double) * 10 * nbox));
     CK(hipMemcpyAsync(dlo.p, blo.data(), sizeof(int) * nbox, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(dhi.p, bhi.data(), sizeof(int) * nbox, hipMemcpyHostToDevice, st));
-    CK(launch_box_circles(h->geo.x, h->geo.y, dlo.as<int>(), dhi.as<int>(), nbox, dcirc.as<double>(), st));
-    std::vector<double> circ(7 * (size_t)nbox);
-    CK(hipMemcpyAsync(circ.data(), dcirc.p, sizeof(double) * 7 * nbox, hipMemcpyDeviceToHost, st));
+    CK(launch_box_circles(h->geo, dlo.as<int>(), dhi.as<int>(), nbox, dcirc.as<double>(), st));
+    std::vector<double> circ(10 * (size_t)nbox);
+    CK(hipMemcpyAsync(circ.data(), dcirc.p, sizeof(double) * 10 * nbox, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     size_t q = 0;
     for (int l = 1; l <= L; ++l) {
@@ -146,50 +148,23 @@ int build(hbs_handle* h) {
       V.cy.resize(V.nb);
       V.rad.resize(V.nb);
       V.aspect.resize(V.nb);
+      kmaxb[l].resize(V.nb);
+      kmeanb[l].resize(V.nb);
+      arcb[l].resize(V.nb);
       for (int b = 0; b < V.nb; ++b, ++q) {
-        V.cx[b] = circ[7 * q];
-        V.cy[b] = circ[7 * q + 1];
-        V.rad[b] = circ[7 * q + 2];
-        const double wx = circ[7 * q + 4] - circ[7 * q + 3], wy = circ[7 * q + 6] - circ[7 * q + 5];
+        const double* c = &circ[10 * q];
+        V.cx[b] = c[0];
+        V.cy[b] = c[1];
+        V.rad[b] = c[2];
+        const double wx = c[4] - c[3], wy = c[6] - c[5];
         V.aspect[b] = std::max(wx, wy) > 0 ? std::min(wx, wy) / std::max(wx, wy) : 1.0;
+        kmaxb[l][b] = c[7];
+        kmeanb[l][b] = c[8];
+        arcb[l][b] = c[9];
       }
     }
   }
 
-  // geometric features of the boxes for the rank predictor: arc length, curvature (|kappa| at
-  // the nodes, from the curvature array when given, else from the turning of the normals)
-  std::vector<double> arc(N + 1, 0.0), kabs(N);
-  for (int64_t i = 0; i < N; ++i) arc[i + 1] = arc[i] + h->hw[i];
-  for (int64_t i = 0; i < N; ++i) {
-    if (!h->hkap.empty()) {
-      kabs[i] = std::fabs(h->hkap[i]);
-    } else {
-      const int64_t a = (i + N - 1) % N, c = (i + 1) % N;
-      const double cr = h->hnx[a] * h->hny[c] - h->hny[a] * h->hnx[c];
-      const double dt = h->hnx[a] * h->hnx[c] + h->hny[a] * h->hny[c];
-      kabs[i] = std::fabs(std::atan2(cr, dt)) / (0.5 * h->hw[a] + h->hw[i] + 0.5 * h->hw[c]);
-    }
-  }
-  std::vector<std::vector<double>> kmaxb(L + 1), kmeanb(L + 1);
-  for (int l = L; l >= 1; --l) {
-    Level& V = h->lv[l];
-    kmaxb[l].assign(V.nb, 0.0);
-    kmeanb[l].assign(V.nb, 0.0);
-    for (int b = 0; b < V.nb; ++b) {
-      if (l == L) {
-        double mx = 0, sm = 0;
-        for (int i = V.lo[b]; i < V.hi[b]; ++i) { mx = std::max(mx, kabs[i]); sm += kabs[i]; }
-        kmaxb[l][b] = mx;
-        kmeanb[l][b] = sm / std::max(1, V.hi[b] - V.lo[b]);
-      } else {
-        const Level& C = h->lv[l + 1];
-        const int a = 2 * b, c = 2 * b + 1;
-        const double na = C.hi[a] - C.lo[a], nc = C.hi[c] - C.lo[c];
-        kmaxb[l][b] = std::max(kmaxb[l + 1][a], kmaxb[l + 1][c]);
-        kmeanb[l][b] = (kmeanb[l + 1][a] * na + kmeanb[l + 1][c] * nc) / std::max(1.0, na + nc);
-      }
-    }
-  }
   const bool predict = h->opts.rank_predictor != 0;
   const double rscale = h->opts.rank_scale > 0 ? h->opts.rank_scale : 1.0;
   DevBuf dmodel, dfeat, dpred;
@@ -416,7 +391,7 @@ int build(hbs_handle* h) {
     std::vector<float> F((size_t)nb * MLP_IN);
     for (int b = 0; b < nb; ++b) {
       const double Rp = ratio * V.rad[b];
-      const double len = arc[V.hi[b]] - arc[V.lo[b]];
+      const double len = arcb[l][b];
       const double chx = h->hx[V.hi[b] - 1] - h->hx[V.lo[b]], chy = h->hy[V.hi[b] - 1] - h->hy[V.lo[b]];
       int ksum = 0;
       if (l < L) ksum = h->lv[l + 1].k[2 * b] + h->lv[l + 1].k[2 * b + 1];

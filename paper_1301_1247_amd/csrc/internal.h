@@ -138,8 +138,8 @@ hipError_t launch_cpqr(const CpqrDesc* d, int nd, int max_s, int max_n, double t
 hipError_t launch_buildP(const PDesc* d, int nd, int max_elems, hipStream_t s);
 hipError_t launch_copy(const CopyDesc* d, int nd, int max_elems, hipStream_t s);
 hipError_t launch_eye(const CopyDesc* d, int nd, int max_elems, hipStream_t s);  // dst = I (nr x nc)
-hipError_t launch_box_circles(const double* x, const double* y, const int* lo, const int* hi, int nbox, double* out,
-                              hipStream_t s);
+// per box: centre, radius, bounding box, max and mean |curvature|, arc length (10 doubles)
+hipError_t launch_box_circles(const Geo& g, const int* lo, const int* hi, int nbox, double* out, hipStream_t s);
 hipError_t launch_gather_idx(const int* src, const int* idx, int* dst, int64_t n, hipStream_t s);
 template <class R>
 hipError_t launch_gemm(const GemmDescT<R>* d, int nd, int max_tiles, hipStream_t s);

@@ -301,29 +301,56 @@ __global__ __launch_bounds__(NT) void k_copy(const CopyDesc* __restrict__ descs)
 }
 
 // Bounding circle of the nodes lo[b] <= i < hi[b] of every box b: centre = middle of the
-// bounding box, radius = largest distance from it (out = cx, cy, r, x0, x1, y0, y1 per box; one
-// workgroup per box).
-__global__ __launch_bounds__(NT) void k_box_circles(const double* __restrict__ x, const double* __restrict__ y,
-                                                    const int* __restrict__ lo, const int* __restrict__ hi,
+// Per box [lo, hi) of the original nodes (one workgroup per box, every level in one launch):
+// bounding box, radius = largest distance from its centre, and the features of the rank
+// predictor: max and mean |curvature| over the nodes (|kappa_i| when the curvature is given,
+// else the turning angle of the normals between the neighbours i-1, i+1 over the arc length
+// between them) and the box's arc length (sum of the weights).
+// out = cx, cy, r, x0, x1, y0, y1, max|kappa|, mean|kappa|, arc length (BOX_OUT per box).
+constexpr int BOX_OUT = 10;
+__global__ __launch_bounds__(NT) void k_box_circles(Geo G, const int* __restrict__ lo, const int* __restrict__ hi,
                                                     double* __restrict__ out) {
   const int b = blockIdx.x;
-  const int i0 = lo[b], i1 = hi[b];
-  __shared__ double red[4][NT / 64];
-  double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+  const int i0 = lo[b], i1 = hi[b], N = G.N;
+  const double* __restrict__ x = G.x;
+  const double* __restrict__ y = G.y;
+  __shared__ double red[7][NT / 64];
+  double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300, km = 0.0, ks = 0.0, al = 0.0;
   for (int i = i0 + threadIdx.x; i < i1; i += NT) {
     x0 = fmin(x0, x[i]); x1 = fmax(x1, x[i]);
     y0 = fmin(y0, y[i]); y1 = fmax(y1, y[i]);
+    double k;
+    if (G.kap) {
+      k = fabs(G.kap[i]);
+    } else {
+      const int a = (i + N - 1) % N, c = (i + 1) % N;
+      const double cr = G.nx[a] * G.ny[c] - G.ny[a] * G.nx[c];
+      const double dt = G.nx[a] * G.nx[c] + G.ny[a] * G.ny[c];
+      k = fabs(atan2(cr, dt)) / (0.5 * G.w[a] + G.w[i] + 0.5 * G.w[c]);
+    }
+    km = fmax(km, k);
+    ks += k;
+    al += G.w[i];
   }
   for (int o = 32; o > 0; o >>= 1) {
     x0 = fmin(x0, __shfl_xor(x0, o, 64)); x1 = fmax(x1, __shfl_xor(x1, o, 64));
     y0 = fmin(y0, __shfl_xor(y0, o, 64)); y1 = fmax(y1, __shfl_xor(y1, o, 64));
+    km = fmax(km, __shfl_xor(km, o, 64));
+    ks += __shfl_xor(ks, o, 64);
+    al += __shfl_xor(al, o, 64);
   }
   const int wv = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) { red[0][wv] = x0; red[1][wv] = x1; red[2][wv] = y0; red[3][wv] = y1; }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wv] = x0; red[1][wv] = x1; red[2][wv] = y0; red[3][wv] = y1;
+    red[4][wv] = km; red[5][wv] = ks; red[6][wv] = al;
+  }
   __syncthreads();
-  for (int q = 0; q < NT / 64; ++q) {
+  x0 = red[0][0]; x1 = red[1][0]; y0 = red[2][0]; y1 = red[3][0];
+  km = red[4][0]; ks = red[5][0]; al = red[6][0];
+  for (int q = 1; q < NT / 64; ++q) {
     x0 = fmin(x0, red[0][q]); x1 = fmax(x1, red[1][q]);
     y0 = fmin(y0, red[2][q]); y1 = fmax(y1, red[3][q]);
+    km = fmax(km, red[4][q]); ks += red[5][q]; al += red[6][q];
   }
   const double cx = 0.5 * (x0 + x1), cy = 0.5 * (y0 + y1);
   double r = 0.0;
@@ -334,13 +361,12 @@ __global__ __launch_bounds__(NT) void k_box_circles(const double* __restrict__ x
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int q = 1; q < NT / 64; ++q) r = fmax(r, red[0][q]);
-    out[7 * b] = cx;
-    out[7 * b + 1] = cy;
-    out[7 * b + 2] = r;
-    out[7 * b + 3] = x0;
-    out[7 * b + 4] = x1;
-    out[7 * b + 5] = y0;
-    out[7 * b + 6] = y1;
+    double* o = out + (size_t)BOX_OUT * b;
+    o[0] = cx; o[1] = cy; o[2] = r;
+    o[3] = x0; o[4] = x1; o[5] = y0; o[6] = y1;
+    o[7] = km;
+    o[8] = ks / (double)max(1, i1 - i0);
+    o[9] = al;
   }
 }
 
@@ -751,10 +777,9 @@ hipError_t launch_eye(const CopyDesc* d, int nd, int max_elems, hipStream_t s) {
   hipLaunchKernelGGL(k_eye, dim3(grid_for(max_elems, 256), nd), dim3(NT), 0, s, d);
   return hipGetLastError();
 }
-hipError_t launch_box_circles(const double* x, const double* y, const int* lo, const int* hi, int nbox, double* out,
-                              hipStream_t s) {
+hipError_t launch_box_circles(const Geo& g, const int* lo, const int* hi, int nbox, double* out, hipStream_t s) {
   if (nbox == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_box_circles, dim3(nbox), dim3(NT), 0, s, x, y, lo, hi, out);
+  hipLaunchKernelGGL(k_box_circles, dim3(nbox), dim3(NT), 0, s, g, lo, hi, out);
   return hipGetLastError();
 }
 hipError_t launch_gather_idx(const int* src, const int* idx, int* dst, int64_t n, hipStream_t s) {

@@ -75,6 +75,32 @@ def test_rank_features_of_a_build(gpu_lib, wavy_case):
     assert np.all(f[leaves, 15] == 0)                              # no children below the leaves
 
 
+def test_rank_features_geometry_matches_numpy(gpu_lib, wavy_case):
+    """Arc length and max / mean |curvature| of every box (computed on the GPU for all levels in one
+    launch) against numpy on the node data: the turning angle of the normals between a node's two
+    neighbours over the arc length between them."""
+    c, N, om, _ = wavy_case
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-12)
+    f, _, lv, _ = h.rank_features()
+    a, cn = np.roll(np.arange(N), 1), np.roll(np.arange(N), -1)
+    cr = nrm[a, 0] * nrm[cn, 1] - nrm[a, 1] * nrm[cn, 0]
+    dt = nrm[a, 0] * nrm[cn, 0] + nrm[a, 1] * nrm[cn, 1]
+    kabs = np.abs(np.arctan2(cr, dt)) / (0.5 * w[a] + w + 0.5 * w[cn])
+    L = h.stats().levels
+    row = 0
+    for l in range(L, 0, -1):
+        nb = 2 ** l
+        for b in range(nb):
+            lo, hi = b * N // nb, (b + 1) * N // nb
+            rad = f[row, 3] / om
+            assert f[row, 2] == pytest.approx(om * w[lo:hi].sum(), rel=1e-5)
+            assert f[row, 8] == pytest.approx(kabs[lo:hi].max() * rad, rel=1e-5, abs=1e-6)
+            assert f[row, 9] == pytest.approx(kabs[lo:hi].mean() * rad, rel=1e-5, abs=1e-6)
+            row += 1
+    assert row == len(lv)
+
+
 def _default_model(gpu_lib):
     try:
         return gpu_lib.rank_model_default()
