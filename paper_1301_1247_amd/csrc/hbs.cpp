@@ -211,6 +211,135 @@ int build(hbs_handle* h) {
     foff += cnt;
     return p;
   };
+  // The side-stream part of level lf's factor phase (it needs lf's P: event 1).  Enqueued one level
+  // late, after the next level's predictor round trip, so that the large products of the side
+  // stream do not share the GPU with the main stream's short critical kernels at that moment.
+  auto factor_chain = [&](int lf) -> int {
+    Level& V = h->lv[lf];
+    const int l = lf, nb = V.nb;
+    const bool fp32 = lf > h->fp64_top;
+    const bool ident = lf == 1 && h->top_identity;
+    cplx* dG = V.G.as<cplx>();
+    cplx* dP = V.P.as<cplx>();
+    CK(hipStreamWaitEvent(sf, ev_P, 0));
+      if (fp32) {
+        // complex64 inverse factors from the FP64 blocks D and interpolation matrices P
+        CK(V.G32.reserve(sizeof(cplxf) * V.oG[nb]));
+        CK(V.E32.reserve(sizeof(cplxf) * V.oP[nb]));
+        CK(V.Ft32.reserve(sizeof(cplxf) * V.oP[nb]));
+        DevBuf p32, y32, z32, dh32;
+        CK(p32.reserve(sizeof(cplxf) * V.oP[nb]));
+        CK(y32.reserve(sizeof(cplxf) * V.oP[nb]));
+        CK(z32.reserve(sizeof(cplxf) * V.oP[nb]));
+        CK(dh32.reserve(sizeof(cplxf) * std::max<int64_t>(1, V.oDh[nb])));
+        cplxf* G32 = V.G32.as<cplxf>();
+        cplxf* P32 = p32.as<cplxf>();
+        cplxf* Y32 = y32.as<cplxf>();
+        cplxf* Z32 = z32.as<cplxf>();
+        cplxf* Dh32 = dh32.as<cplxf>();
+        cplxf* E32 = V.E32.as<cplxf>();
+        cplxf* F32 = V.Ft32.as<cplxf>();
+        CK(launch_cast_d2f(dG, G32, V.oG[nb], sf));
+        CK(launch_cast_d2f(dP, P32, V.oP[nb], sf));
+        std::vector<InvDesc32> iv;
+        for (int b = 0; b < nb; ++b) iv.push_back({G32 + V.oG[b], V.n[b], V.n[b]});
+        CK(inv_batched_flags<float>(arena_f, work_f, iv, sf, flags_for(nb, l, "diagonal block")));
+        const cplxf one = mkcf(1, 0), zero = mkcf(0, 0), mone = mkcf(-1, 0);
+        auto g32 = [&](const cplxf* A, int lda, int tA, const cplxf* B, int ldb, cplxf* C, int ldc, int m, int n, int k,
+                       cplxf al, cplxf be) {
+          GemmDesc32 g;
+          g.A = A; g.B = B; g.C = C; g.m = m; g.n = n; g.k = k; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+          g.transA = tA; g.pad = 0; g.alpha = al; g.beta = be;
+          return g;
+        };
+        std::vector<GemmDesc32> g1, g2, g3, g4;
+        for (int b = 0; b < nb; ++b) {
+          const int n = V.n[b], k = V.k[b];
+          g1.push_back(g32(G32 + V.oG[b], n, 0, P32 + V.oP[b], n, Y32 + V.oP[b], n, n, k, n, one, zero));
+          g1.push_back(g32(P32 + V.oP[b], n, 1, G32 + V.oG[b], n, Z32 + V.oP[b], k, k, n, n, one, zero));
+        }
+        CK(gemm_batched<float>(arena_f, g1, sf));
+        for (int b = 0; b < nb; ++b)
+          g2.push_back(g32(Z32 + V.oP[b], V.k[b], 0, P32 + V.oP[b], V.n[b], Dh32 + V.oDh[b], V.k[b], V.k[b], V.k[b], V.n[b],
+                           one, zero));
+        CK(gemm_batched<float>(arena_f, g2, sf));
+        std::vector<InvDesc32> iv2;
+        for (int b = 0; b < nb; ++b) iv2.push_back({Dh32 + V.oDh[b], V.k[b], V.k[b]});
+        CK(inv_batched_flags<float>(arena_f, work_f, iv2, sf, flags_for(nb, l, "reduced block")));
+        for (int b = 0; b < nb; ++b) {
+          const int n = V.n[b], k = V.k[b];
+          g3.push_back(g32(Y32 + V.oP[b], n, 0, Dh32 + V.oDh[b], k, E32 + V.oP[b], n, n, k, k, one, zero));
+          g3.push_back(g32(Dh32 + V.oDh[b], k, 0, Z32 + V.oP[b], k, F32 + V.oP[b], k, k, n, k, one, zero));
+        }
+        CK(gemm_batched<float>(arena_f, g3, sf));
+        for (int b = 0; b < nb; ++b)
+          g4.push_back(g32(E32 + V.oP[b], V.n[b], 0, Z32 + V.oP[b], V.k[b], G32 + V.oG[b], V.n[b], V.n[b], V.n[b], V.k[b],
+                           mone, one));
+        CK(gemm_batched<float>(arena_f, g4, sf));
+        // the parent's diagonal block needs D^ in FP64
+        CK(launch_cast_f2d(Dh32, V.Dh.as<cplx>(), V.oDh[nb], sf));
+        V.G.release();  // D itself is not a factor in this mode
+      } else if (ident) {
+        // P = I: the reduced block is D itself, E = F^T = I and G = D^{-1} - D^{-1} = 0
+        CK(hipMemcpyAsync(V.Dh.p, dG, sizeof(cplx) * V.oG[nb], hipMemcpyDeviceToDevice, sf));
+        std::vector<CopyDesc> ce, cz;
+        int maxe = 0;
+        for (int b = 0; b < nb; ++b) {
+          const int n = V.n[b];
+          ce.push_back({nullptr, V.E.as<cplx>() + V.oP[b], n, n, n, n});
+          ce.push_back({nullptr, V.Ft.as<cplx>() + V.oP[b], n, n, n, n});
+          cz.push_back({nullptr, dG + V.oG[b], n, n, n, n});
+          maxe = std::max(maxe, n * n);
+        }
+        CK(up_sync(arena_f, ce, sf));
+        CK(launch_eye(arena_f.as<CopyDesc>(), (int)ce.size(), maxe, sf));
+        CK(up_sync(arena_f, cz, sf));
+        CK(launch_copy(arena_f.as<CopyDesc>(), (int)cz.size(), maxe, sf));
+      } else {
+      cplx* Y = tmpY.as<cplx>();
+      cplx* Zt = tmpZt.as<cplx>();
+      cplx* Dh = V.Dh.as<cplx>();
+      cplx* E = V.E.as<cplx>();
+      cplx* Ft = V.Ft.as<cplx>();
+      {
+        std::vector<GemmDesc> g1, g2;
+        for (int b = 0; b < nb; ++b) {
+          const int n = V.n[b], k = V.k[b];
+          const cplx* Di = dG + V.oG[b];
+          // Y = D^{-1} P  (n x k)
+          g1.push_back(gd(Di, n, 0, dP + V.oP[b], n, Y + V.oP[b], n, n, k, n));
+          // Zt = P^T D^{-1}  (k x n)
+          g1.push_back(gd(dP + V.oP[b], n, 1, Di, n, Zt + V.oP[b], k, k, n, n));
+        }
+        CK(gemm_batched(arena_f, g1, sf));
+        for (int b = 0; b < nb; ++b) {
+          const int n = V.n[b], k = V.k[b];
+          // S = Zt P (k x k) -> Dh
+          g2.push_back(gd(Zt + V.oP[b], k, 0, dP + V.oP[b], n, Dh + V.oDh[b], k, k, k, n));
+        }
+        CK(gemm_batched(arena_f, g2, sf));
+        std::vector<InvDesc> iv;
+        for (int b = 0; b < nb; ++b) iv.push_back({Dh + V.oDh[b], V.k[b], V.k[b]});
+        CK(inv_batched_flags(arena_f, work_f, iv, sf, flags_for(nb, l, "reduced block")));
+        std::vector<GemmDesc> g3, g4;
+        for (int b = 0; b < nb; ++b) {
+          const int n = V.n[b], k = V.k[b];
+          // E = Y Dh (n x k); Ft = Dh Zt (k x n)
+          g3.push_back(gd(Y + V.oP[b], n, 0, Dh + V.oDh[b], k, E + V.oP[b], n, n, k, k));
+          g3.push_back(gd(Dh + V.oDh[b], k, 0, Zt + V.oP[b], k, Ft + V.oP[b], k, k, n, k));
+        }
+        CK(gemm_batched(arena_f, g3, sf));
+        for (int b = 0; b < nb; ++b) {
+          const int n = V.n[b], k = V.k[b];
+          // G = D^{-1} - E Zt  (in place)
+          g4.push_back(gd(E + V.oP[b], n, 0, Zt + V.oP[b], k, dG + V.oG[b], n, n, n, k, mkc(-1, 0), mkc(1, 0)));
+        }
+        CK(gemm_batched(arena_f, g4, sf));
+      }
+      }
+    return HBS_OK;
+  };
+  int pending = 0;  // the level whose factor chain is still to be enqueued
   h->factor_bytes = 0;
   std::memset(h->stats.ranks_per_level_max, 0, sizeof(h->stats.ranks_per_level_max));
   std::memset(h->stats.ranks_per_level_mean, 0, sizeof(h->stats.ranks_per_level_mean));
@@ -241,58 +370,6 @@ int build(hbs_handle* h) {
     const int* dact = V.act.as<int>();
     CK(hipEventRecord(ev_act, st));
     CK(hipStreamWaitEvent(sf, ev_act, 0));
-
-    // ---- diagonal blocks D (into G, inverted in place later) and forward blocks Df
-    V.oG.assign(nb + 1, 0);
-    for (int b = 0; b < nb; ++b) V.oG[b + 1] = V.oG[b] + (int64_t)V.n[b] * V.n[b];
-    CK(V.G.reserve(sizeof(cplx) * V.oG[nb]));
-    CK(V.Df.reserve(sizeof(cplx) * V.oG[nb]));
-    cplx* dG = V.G.as<cplx>();
-    cplx* dDf = V.Df.as<cplx>();
-    {
-      std::vector<BlockDesc> bd;
-      std::vector<CopyDesc> cz, cp, cd;
-      int maxe = 0;
-      for (int b = 0; b < nb; ++b) {
-        const int n = V.n[b];
-        maxe = std::max(maxe, n * n);
-        if (l == L) {
-          bd.push_back({dact + V.aoff[b], dact + V.aoff[b], dG + V.oG[b], n, n, n, 0});
-          cp.push_back({dG + V.oG[b], dDf + V.oG[b], n, n, n, n});
-        } else {
-          Level& C = h->lv[l + 1];
-          const int a = 2 * b, c = 2 * b + 1;
-          const int ka = C.k[a], kc = C.k[c];
-          const int* sa = C.skel.as<int>() + C.soff[a];
-          const int* sc = C.skel.as<int>() + C.soff[c];
-          cz.push_back({nullptr, dDf + V.oG[b], n, n, n, n});
-          bd.push_back({sa, sc, dDf + V.oG[b] + (int64_t)ka * n, ka, kc, n, 0});
-          bd.push_back({sc, sa, dDf + V.oG[b] + ka, kc, ka, n, 0});
-          cp.push_back({dDf + V.oG[b], dG + V.oG[b], n, n, n, n});
-          cd.push_back({C.Dh.as<cplx>() + C.oDh[a], dG + V.oG[b], ka, ka, ka, n});
-          cd.push_back({C.Dh.as<cplx>() + C.oDh[c], dG + V.oG[b] + (int64_t)ka * n + ka, kc, kc, kc, n});
-        }
-      }
-      if (!cz.empty()) {
-        CK(up_sync(arena_f, cz, sf));
-        CK(launch_copy(arena_f.as<CopyDesc>(), (int)cz.size(), maxe, sf));
-      }
-      {
-        int maxb = 0;
-        for (auto& d : bd) maxb = std::max(maxb, d.nr * d.nc);
-        CK(up_sync(arena_f, bd, sf));
-        ProfScope ps("assemble", sf, 0.0, 0.0);
-        CK(launch_eval_blocks(h->geo, arena_f.as<BlockDesc>(), (int)bd.size(), maxb, sf));
-      }
-      CK(up_sync(arena_f, cp, sf));
-      CK(launch_copy(arena_f.as<CopyDesc>(), (int)cp.size(), maxe, sf));
-      if (!cd.empty()) {
-        int maxc = 0;
-        for (auto& d : cd) maxc = std::max(maxc, d.nr * d.nc);
-        CK(up_sync(arena_f, cd, sf));
-        CK(launch_copy(arena_f.as<CopyDesc>(), (int)cd.size(), maxc, sf));
-      }
-    }
 
     // ---- compression matrices
     std::vector<int> nnear(nb), np(nb), npf(nb), m(nb), s(nb);
@@ -446,6 +523,65 @@ int build(hbs_handle* h) {
     h->top_identity = ident;
     if (ident)
       for (int b = 0; b < nb; ++b) s[b] = m[b];  // no sketch
+    // the side stream: the children's factor chain (their reduced blocks D^ enter this level's
+    // diagonal blocks), then this level's diagonal blocks and their inverses
+    if (pending) {
+      const int rc = factor_chain(pending);
+      if (rc != HBS_OK) return rc;
+      pending = 0;
+    }
+    // ---- diagonal blocks D (into G, inverted in place later) and forward blocks Df
+    V.oG.assign(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) V.oG[b + 1] = V.oG[b] + (int64_t)V.n[b] * V.n[b];
+    CK(V.G.reserve(sizeof(cplx) * V.oG[nb]));
+    CK(V.Df.reserve(sizeof(cplx) * V.oG[nb]));
+    cplx* dG = V.G.as<cplx>();
+    cplx* dDf = V.Df.as<cplx>();
+    {
+      std::vector<BlockDesc> bd;
+      std::vector<CopyDesc> cz, cp, cd;
+      int maxe = 0;
+      for (int b = 0; b < nb; ++b) {
+        const int n = V.n[b];
+        maxe = std::max(maxe, n * n);
+        if (l == L) {
+          bd.push_back({dact + V.aoff[b], dact + V.aoff[b], dG + V.oG[b], n, n, n, 0});
+          cp.push_back({dG + V.oG[b], dDf + V.oG[b], n, n, n, n});
+        } else {
+          Level& C = h->lv[l + 1];
+          const int a = 2 * b, c = 2 * b + 1;
+          const int ka = C.k[a], kc = C.k[c];
+          const int* sa = C.skel.as<int>() + C.soff[a];
+          const int* sc = C.skel.as<int>() + C.soff[c];
+          cz.push_back({nullptr, dDf + V.oG[b], n, n, n, n});
+          bd.push_back({sa, sc, dDf + V.oG[b] + (int64_t)ka * n, ka, kc, n, 0});
+          bd.push_back({sc, sa, dDf + V.oG[b] + ka, kc, ka, n, 0});
+          cp.push_back({dDf + V.oG[b], dG + V.oG[b], n, n, n, n});
+          cd.push_back({C.Dh.as<cplx>() + C.oDh[a], dG + V.oG[b], ka, ka, ka, n});
+          cd.push_back({C.Dh.as<cplx>() + C.oDh[c], dG + V.oG[b] + (int64_t)ka * n + ka, kc, kc, kc, n});
+        }
+      }
+      if (!cz.empty()) {
+        CK(up_sync(arena_f, cz, sf));
+        CK(launch_copy(arena_f.as<CopyDesc>(), (int)cz.size(), maxe, sf));
+      }
+      {
+        int maxb = 0;
+        for (auto& d : bd) maxb = std::max(maxb, d.nr * d.nc);
+        CK(up_sync(arena_f, bd, sf));
+        ProfScope ps("assemble", sf, 0.0, 0.0);
+        CK(launch_eval_blocks(h->geo, arena_f.as<BlockDesc>(), (int)bd.size(), maxb, sf));
+      }
+      CK(up_sync(arena_f, cp, sf));
+      CK(launch_copy(arena_f.as<CopyDesc>(), (int)cp.size(), maxe, sf));
+      if (!cd.empty()) {
+        int maxc = 0;
+        for (auto& d : cd) maxc = std::max(maxc, d.nr * d.nc);
+        CK(up_sync(arena_f, cd, sf));
+        CK(launch_copy(arena_f.as<CopyDesc>(), (int)cd.size(), maxc, sf));
+      }
+    }
+
     // complex128 levels: the diagonal blocks D are inverted on the side stream (after their
     // assembly there) while the main stream compresses the level
     if (!ident && l <= h->fp64_top) {
@@ -654,127 +790,17 @@ int build(hbs_handle* h) {
       CK(launch_buildP(arena.as<PDesc>(), nb, maxe, st));
     }
     CK(hipEventRecord(ev_P, st));
-    CK(hipStreamWaitEvent(sf, ev_P, 0));
-    if (fp32) {
-      // complex64 inverse factors from the FP64 blocks D and interpolation matrices P
-      CK(V.G32.reserve(sizeof(cplxf) * V.oG[nb]));
-      CK(V.E32.reserve(sizeof(cplxf) * V.oP[nb]));
-      CK(V.Ft32.reserve(sizeof(cplxf) * V.oP[nb]));
-      DevBuf p32, y32, z32, dh32;
-      CK(p32.reserve(sizeof(cplxf) * V.oP[nb]));
-      CK(y32.reserve(sizeof(cplxf) * V.oP[nb]));
-      CK(z32.reserve(sizeof(cplxf) * V.oP[nb]));
-      CK(dh32.reserve(sizeof(cplxf) * std::max<int64_t>(1, V.oDh[nb])));
-      cplxf* G32 = V.G32.as<cplxf>();
-      cplxf* P32 = p32.as<cplxf>();
-      cplxf* Y32 = y32.as<cplxf>();
-      cplxf* Z32 = z32.as<cplxf>();
-      cplxf* Dh32 = dh32.as<cplxf>();
-      cplxf* E32 = V.E32.as<cplxf>();
-      cplxf* F32 = V.Ft32.as<cplxf>();
-      CK(launch_cast_d2f(dG, G32, V.oG[nb], sf));
-      CK(launch_cast_d2f(dP, P32, V.oP[nb], sf));
-      std::vector<InvDesc32> iv;
-      for (int b = 0; b < nb; ++b) iv.push_back({G32 + V.oG[b], V.n[b], V.n[b]});
-      CK(inv_batched_flags<float>(arena_f, work_f, iv, sf, flags_for(nb, l, "diagonal block")));
-      const cplxf one = mkcf(1, 0), zero = mkcf(0, 0), mone = mkcf(-1, 0);
-      auto g32 = [&](const cplxf* A, int lda, int tA, const cplxf* B, int ldb, cplxf* C, int ldc, int m, int n, int k,
-                     cplxf al, cplxf be) {
-        GemmDesc32 g;
-        g.A = A; g.B = B; g.C = C; g.m = m; g.n = n; g.k = k; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
-        g.transA = tA; g.pad = 0; g.alpha = al; g.beta = be;
-        return g;
-      };
-      std::vector<GemmDesc32> g1, g2, g3, g4;
-      for (int b = 0; b < nb; ++b) {
-        const int n = V.n[b], k = V.k[b];
-        g1.push_back(g32(G32 + V.oG[b], n, 0, P32 + V.oP[b], n, Y32 + V.oP[b], n, n, k, n, one, zero));
-        g1.push_back(g32(P32 + V.oP[b], n, 1, G32 + V.oG[b], n, Z32 + V.oP[b], k, k, n, n, one, zero));
-      }
-      CK(gemm_batched<float>(arena_f, g1, sf));
-      for (int b = 0; b < nb; ++b)
-        g2.push_back(g32(Z32 + V.oP[b], V.k[b], 0, P32 + V.oP[b], V.n[b], Dh32 + V.oDh[b], V.k[b], V.k[b], V.k[b], V.n[b],
-                         one, zero));
-      CK(gemm_batched<float>(arena_f, g2, sf));
-      std::vector<InvDesc32> iv2;
-      for (int b = 0; b < nb; ++b) iv2.push_back({Dh32 + V.oDh[b], V.k[b], V.k[b]});
-      CK(inv_batched_flags<float>(arena_f, work_f, iv2, sf, flags_for(nb, l, "reduced block")));
-      for (int b = 0; b < nb; ++b) {
-        const int n = V.n[b], k = V.k[b];
-        g3.push_back(g32(Y32 + V.oP[b], n, 0, Dh32 + V.oDh[b], k, E32 + V.oP[b], n, n, k, k, one, zero));
-        g3.push_back(g32(Dh32 + V.oDh[b], k, 0, Z32 + V.oP[b], k, F32 + V.oP[b], k, k, n, k, one, zero));
-      }
-      CK(gemm_batched<float>(arena_f, g3, sf));
-      for (int b = 0; b < nb; ++b)
-        g4.push_back(g32(E32 + V.oP[b], V.n[b], 0, Z32 + V.oP[b], V.k[b], G32 + V.oG[b], V.n[b], V.n[b], V.n[b], V.k[b],
-                         mone, one));
-      CK(gemm_batched<float>(arena_f, g4, sf));
-      // the parent's diagonal block needs D^ in FP64
-      CK(launch_cast_f2d(Dh32, V.Dh.as<cplx>(), V.oDh[nb], sf));
-      V.G.release();  // D itself is not a factor in this mode
-    } else if (ident) {
-      // P = I: the reduced block is D itself, E = F^T = I and G = D^{-1} - D^{-1} = 0
-      CK(hipMemcpyAsync(V.Dh.p, dG, sizeof(cplx) * V.oG[nb], hipMemcpyDeviceToDevice, sf));
-      std::vector<CopyDesc> ce, cz;
-      int maxe = 0;
-      for (int b = 0; b < nb; ++b) {
-        const int n = V.n[b];
-        ce.push_back({nullptr, V.E.as<cplx>() + V.oP[b], n, n, n, n});
-        ce.push_back({nullptr, V.Ft.as<cplx>() + V.oP[b], n, n, n, n});
-        cz.push_back({nullptr, dG + V.oG[b], n, n, n, n});
-        maxe = std::max(maxe, n * n);
-      }
-      CK(up_sync(arena_f, ce, sf));
-      CK(launch_eye(arena_f.as<CopyDesc>(), (int)ce.size(), maxe, sf));
-      CK(up_sync(arena_f, cz, sf));
-      CK(launch_copy(arena_f.as<CopyDesc>(), (int)cz.size(), maxe, sf));
-    } else {
-    cplx* Y = tmpY.as<cplx>();
-    cplx* Zt = tmpZt.as<cplx>();
-    cplx* Dh = V.Dh.as<cplx>();
-    cplx* E = V.E.as<cplx>();
-    cplx* Ft = V.Ft.as<cplx>();
-    {
-      std::vector<GemmDesc> g1, g2;
-      for (int b = 0; b < nb; ++b) {
-        const int n = V.n[b], k = V.k[b];
-        const cplx* Di = dG + V.oG[b];
-        // Y = D^{-1} P  (n x k)
-        g1.push_back(gd(Di, n, 0, dP + V.oP[b], n, Y + V.oP[b], n, n, k, n));
-        // Zt = P^T D^{-1}  (k x n)
-        g1.push_back(gd(dP + V.oP[b], n, 1, Di, n, Zt + V.oP[b], k, k, n, n));
-      }
-      CK(gemm_batched(arena_f, g1, sf));
-      for (int b = 0; b < nb; ++b) {
-        const int n = V.n[b], k = V.k[b];
-        // S = Zt P (k x k) -> Dh
-        g2.push_back(gd(Zt + V.oP[b], k, 0, dP + V.oP[b], n, Dh + V.oDh[b], k, k, k, n));
-      }
-      CK(gemm_batched(arena_f, g2, sf));
-      std::vector<InvDesc> iv;
-      for (int b = 0; b < nb; ++b) iv.push_back({Dh + V.oDh[b], V.k[b], V.k[b]});
-      CK(inv_batched_flags(arena_f, work_f, iv, sf, flags_for(nb, l, "reduced block")));
-      std::vector<GemmDesc> g3, g4;
-      for (int b = 0; b < nb; ++b) {
-        const int n = V.n[b], k = V.k[b];
-        // E = Y Dh (n x k); Ft = Dh Zt (k x n)
-        g3.push_back(gd(Y + V.oP[b], n, 0, Dh + V.oDh[b], k, E + V.oP[b], n, n, k, k));
-        g3.push_back(gd(Dh + V.oDh[b], k, 0, Zt + V.oP[b], k, Ft + V.oP[b], k, k, n, k));
-      }
-      CK(gemm_batched(arena_f, g3, sf));
-      for (int b = 0; b < nb; ++b) {
-        const int n = V.n[b], k = V.k[b];
-        // G = D^{-1} - E Zt  (in place)
-        g4.push_back(gd(E + V.oP[b], n, 0, Zt + V.oP[b], k, dG + V.oG[b], n, n, n, k, mkc(-1, 0), mkc(1, 0)));
-      }
-      CK(gemm_batched(arena_f, g4, sf));
-    }
-    }
+    pending = l;  // its factor chain is enqueued after the next level's predictor
     if (l < L) h->lv[l + 1].Dh.release();
     h->factor_bytes += fp32 ? (int64_t)sizeof(cplx) * (V.oP[nb] + V.oG[nb]) + (int64_t)sizeof(cplxf) * (2 * V.oP[nb] + V.oG[nb])
                             : (int64_t)sizeof(cplx) * (3 * V.oP[nb] + 2 * V.oG[nb]);
   }
 
+  if (pending) {
+    const int rc = factor_chain(pending);
+    if (rc != HBS_OK) return rc;
+    pending = 0;
+  }
   // ---- root (side stream: it needs level 1's reduced blocks; the skeletons came from the main stream)
   CK(hipEventRecord(ev_act, st));
   CK(hipStreamWaitEvent(sf, ev_act, 0));
