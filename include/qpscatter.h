@@ -248,6 +248,35 @@ int qps_cinv(float* A, int32_t n, int32_t nbatch, int32_t ptr_mode);
 int qps_profile_enable(int32_t on);
 int qps_profile_read(const char* family, double* ms, int64_t* launches, double* flops, double* bytes);
 
+/* Tile configurations of the batched complex GEMM that carries every block product of the
+ * factorization and its application (the per-level products of the telescoping factorization,
+ * Sec. 3, and the Schur products of the periodizing step, Sec. 4).  Configuration c:
+ * 0 = 64 x 64 output tiles (2 x 2 wavefronts), 1 = 32 x 32 (one wavefront), 2 = 64 x 32 (2 x 1),
+ * 3 = 32 x 64 (1 x 2).  Each launch picks one from its shape class through a tuning table; all
+ * configurations give bitwise equal results, so the table affects run time only.
+ *
+ * qps_gemm_class: the class key of a launch (complex64 != 0 for the complex64 kernel; the largest
+ *   m, n, k of its entries and the entry count; all >= 0).  Key = prec << 24 | ceil(log2 m) << 18
+ *   | ceil(log2 n) << 12 | ceil(log2 k) << 6 | ceil(log2 count), each ceil(log2) of max(x, 1).
+ * qps_gemm_tune_lookup: *cfg = the table's configuration for key, or -1 (configuration 0 is used).
+ * qps_gemm_tune_set: replace the table by n (key, cfg) pairs (host arrays; cfg outside 0..3 is
+ *   an error); n = 0 empties it, n < 0 restores the built-in table.  Launches planned afterwards
+ *   use the new table (captured apply graphs keep the configuration they were captured with).
+ * qps_gemm_tune_get: copy up to cap entries (keys ascending) into keys/cfgs (may be NULL when
+ *   cap = 0); *n = the table size.
+ * qps_gemm_tune_begin: start a sweep: every launch uses configuration cfg, and each class's
+ *   launches outside graph capture are timed with HIP events.  qps_gemm_tune_end: wait for
+ *   the timed launches, return up to cap classes (keys ascending) with their summed ms and
+ *   launch counts, *n = the number of classes timed, and end the sweep (table lookups again).
+ *   One sweep at a time per process; calls from other threads during a sweep are forced too. */
+#define QPS_GEMM_CONFIGS 4
+int qps_gemm_class(int32_t complex64, int64_t max_m, int64_t max_n, int64_t max_k, int64_t count, int32_t* key);
+int qps_gemm_tune_lookup(int32_t key, int32_t* cfg);
+int qps_gemm_tune_set(const int32_t* keys, const int32_t* cfgs, int32_t n);
+int qps_gemm_tune_get(int32_t* keys, int32_t* cfgs, int32_t cap, int32_t* n);
+int qps_gemm_tune_begin(int32_t cfg);
+int qps_gemm_tune_end(int32_t* keys, double* ms, int64_t* launches, int32_t cap, int32_t* n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -91,6 +91,12 @@ _sig = {
     "qps_pool_cached_bytes": (C.c_int64, []),
     "qps_profile_enable": (C.c_int, [C.c_int32]),
     "qps_profile_read": (C.c_int, [C.c_char_p, _P, _P, _P, _P]),
+    "qps_gemm_class": (C.c_int, [C.c_int32, C.c_int64, C.c_int64, C.c_int64, C.c_int64, _P]),
+    "qps_gemm_tune_lookup": (C.c_int, [C.c_int32, _P]),
+    "qps_gemm_tune_set": (C.c_int, [_P, _P, C.c_int32]),
+    "qps_gemm_tune_get": (C.c_int, [_P, _P, C.c_int32, _P]),
+    "qps_gemm_tune_begin": (C.c_int, [C.c_int32]),
+    "qps_gemm_tune_end": (C.c_int, [_P, _P, _P, C.c_int32, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -384,3 +390,61 @@ def profile_read(family):
     by = C.c_double()
     _check(_lib.qps_profile_read(family.encode(), C.byref(ms), C.byref(la), C.byref(fl), C.byref(by)))
     return dict(ms=ms.value, launches=la.value, flops=fl.value, bytes=by.value)
+
+
+GEMM_CONFIGS = {0: (64, 64), 1: (32, 32), 2: (64, 32), 3: (32, 64)}  # output tile (rows, cols) per config
+
+
+def gemm_class(max_m, max_n, max_k, count, complex64=False):
+    """Shape-class key of a batched GEMM launch (largest m, n, k of its entries, entry count)."""
+    key = C.c_int32()
+    _check(_lib.qps_gemm_class(1 if complex64 else 0, int(max_m), int(max_n), int(max_k), int(count), C.byref(key)))
+    return key.value
+
+
+def gemm_class_fields(key):
+    """(complex64, ceil log2 m, n, k, count) of a class key."""
+    return (key >> 24) & 1, (key >> 18) & 63, (key >> 12) & 63, (key >> 6) & 63, key & 63
+
+
+def gemm_tune_lookup(key):
+    """The tuning table's configuration for a class key, or -1 (configuration 0 is used)."""
+    cfg = C.c_int32()
+    _check(_lib.qps_gemm_tune_lookup(int(key), C.byref(cfg)))
+    return cfg.value
+
+
+def gemm_tune_set(table):
+    """Replace the tuning table by {key: cfg}; None restores the built-in table."""
+    if table is None:
+        _check(_lib.qps_gemm_tune_set(None, None, -1))
+        return
+    keys = np.ascontiguousarray(list(table.keys()), dtype=np.int32)
+    cfgs = np.ascontiguousarray([table[k] for k in table], dtype=np.int32)
+    _check(_lib.qps_gemm_tune_set(_ptr(keys) if len(keys) else None, _ptr(cfgs) if len(cfgs) else None, len(keys)))
+
+
+def gemm_tune_get():
+    """The active tuning table as {key: cfg}."""
+    n = C.c_int32()
+    _check(_lib.qps_gemm_tune_get(None, None, 0, C.byref(n)))
+    keys = np.zeros(max(1, n.value), dtype=np.int32)
+    cfgs = np.zeros(max(1, n.value), dtype=np.int32)
+    _check(_lib.qps_gemm_tune_get(_ptr(keys), _ptr(cfgs), n.value, C.byref(n)))
+    return {int(k): int(c) for k, c in zip(keys[: n.value], cfgs[: n.value])}
+
+
+def gemm_tune_begin(cfg):
+    """Start a sweep: every GEMM launch uses configuration cfg and is timed per shape class."""
+    _check(_lib.qps_gemm_tune_begin(int(cfg)))
+
+
+def gemm_tune_end(cap=4096):
+    """End the sweep: {key: (ms, launches)} of the classes timed since gemm_tune_begin."""
+    keys = np.zeros(cap, dtype=np.int32)
+    ms = np.zeros(cap, dtype=np.float64)
+    la = np.zeros(cap, dtype=np.int64)
+    n = C.c_int32()
+    _check(_lib.qps_gemm_tune_end(_ptr(keys), _ptr(ms), _ptr(la), cap, C.byref(n)))
+    m = min(n.value, cap)
+    return {int(keys[i]): (float(ms[i]), int(la[i])) for i in range(m)}

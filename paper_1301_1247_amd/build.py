@@ -12,9 +12,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqpscatter.so")
 
-SOURCES = ["kernels_build.hip", "gemm.hip", "kernels_qp.hip", "kernels_mlp.hip", "runtime.cpp", "hbs.cpp", "qp.cpp",
-           "capi.cpp"]
+SOURCES = ["kernels_build.hip", "gemm.hip", "gemm_tune.cpp", "kernels_qp.hip", "kernels_mlp.hip", "runtime.cpp",
+           "hbs.cpp", "qp.cpp", "capi.cpp"]
 MODEL = os.path.join(HERE, "rank_mlp_default.json")
+TUNE = os.path.join(HERE, "gemm_tune_default.json")
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -48,9 +49,30 @@ def _model():
             f.write(text)
 
 
+def _tune_table():
+    """Embed the GEMM tile tuning table (gemm_tune_default.json, written by tune_gemm.py) as a C array."""
+    inc = os.path.join(CSRC, "gemm_tune_default.inc")
+    pairs = []
+    if os.path.exists(TUNE):
+        import json
+        with open(TUNE) as f:
+            pairs = [(int(e["key"]), int(e["cfg"])) for e in json.load(f)["table"]]
+    if pairs:
+        body = ",\n".join(f"{k}, {c}" for k, c in pairs)
+        text = (f"static const int kGemmTuneDefault[] = {{\n{body}\n}};\n"
+                f"static const int kGemmTuneDefaultN = {len(pairs)};\n")
+    else:
+        text = "static const int kGemmTuneDefault[2] = {0, 0};\nstatic const int kGemmTuneDefaultN = 0;\n"
+    old = open(inc).read() if os.path.exists(inc) else None
+    if old != text:
+        with open(inc, "w") as f:
+            f.write(text)
+
+
 def build(verbose: bool = False) -> str:
     _tables()
     _model()
+    _tune_table()
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     srcs = []
     for s in SOURCES:

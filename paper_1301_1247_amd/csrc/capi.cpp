@@ -679,4 +679,58 @@ int qps_profile_read(const char* family, double* ms, int64_t* launches, double* 
   return HBS_OK;
 }
 
+int qps_gemm_class(int32_t complex64, int64_t max_m, int64_t max_n, int64_t max_k, int64_t count, int32_t* key) {
+  clear_error();
+  if (!key || max_m < 0 || max_n < 0 || max_k < 0 || count < 0) {
+    set_error("qps_gemm_class: sizes must be >= 0 and key non-null");
+    return HBS_E_INVALID_ARG;
+  }
+  *key = gemm_class_key(complex64 ? 1 : 0, max_m, max_n, max_k, count);
+  return HBS_OK;
+}
+
+int qps_gemm_tune_lookup(int32_t key, int32_t* cfg) {
+  clear_error();
+  if (!cfg) { set_error("qps_gemm_tune_lookup: cfg is null"); return HBS_E_INVALID_ARG; }
+  *cfg = gemm_tune_lookup(key);
+  return HBS_OK;
+}
+
+int qps_gemm_tune_set(const int32_t* keys, const int32_t* cfgs, int32_t n) {
+  clear_error();
+  if (n > 0 && (!keys || !cfgs)) { set_error("qps_gemm_tune_set: null table"); return HBS_E_INVALID_ARG; }
+  for (int32_t i = 0; i < n; ++i)
+    if (cfgs[i] < 0 || cfgs[i] >= kGemmConfigs) {
+      set_error("qps_gemm_tune_set: configuration out of range");
+      return HBS_E_INVALID_ARG;
+    }
+  gemm_tune_set(keys, cfgs, n);
+  return HBS_OK;
+}
+
+int qps_gemm_tune_get(int32_t* keys, int32_t* cfgs, int32_t cap, int32_t* n) {
+  clear_error();
+  if (!n || cap < 0 || (cap > 0 && (!keys || !cfgs))) { set_error("qps_gemm_tune_get: bad arguments"); return HBS_E_INVALID_ARG; }
+  *n = gemm_tune_get(keys, cfgs, cap);
+  return HBS_OK;
+}
+
+int qps_gemm_tune_begin(int32_t cfg) {
+  clear_error();
+  if (!gemm_tune_begin(cfg)) { set_error("qps_gemm_tune_begin: configuration out of range"); return HBS_E_INVALID_ARG; }
+  return HBS_OK;
+}
+
+int qps_gemm_tune_end(int32_t* keys, double* ms, int64_t* launches, int32_t cap, int32_t* n) {
+  clear_error();
+  if (!n || cap < 0 || (cap > 0 && (!keys || !ms || !launches))) {
+    set_error("qps_gemm_tune_end: bad arguments");
+    return HBS_E_INVALID_ARG;
+  }
+  bool ok = true;
+  *n = gemm_tune_end(keys, ms, launches, cap, &ok);
+  if (!ok) { set_error("qps_gemm_tune_end: event query failed"); return HBS_E_DEVICE; }
+  return HBS_OK;
+}
+
 }  // extern "C"

@@ -1,22 +1,23 @@
 // Batched complex GEMM on CDNA4 matrix cores: C = alpha op(A) B + beta C, in complex128
 // (v_mfma_f64_16x16x4f64) or complex64 (v_mfma_f32_16x16x4f32).
 //
-// Each workgroup (4 wavefronts, 2 x 2) computes a 64 x 64 tile of one batch entry; each
-// wavefront owns a 32 x 32 sub-tile = 2 x 2 blocks of the 16 x 16 x 4 MFMA.  A complex
-// product takes four real MFMAs into two accumulators (re += ar br - ai bi, im += ar bi + ai br),
-// issued so that two updates of one accumulator are 7 MFMAs apart.  Operands are staged
-// through LDS in k-slices of 16 (real and imaginary planes); the next slice is fetched into
-// registers while the current one is multiplied.  Batch entries may have different shapes;
-// grid.x covers the largest tile count and workgroups past an entry's tile count exit.
-// Long-K entries with few output tiles are split along K into a workspace and summed in a
-// fixed order by a second kernel.
+// A workgroup of WM x WN wavefronts computes a (32 WM) x (32 WN) tile of one batch entry; each
+// wavefront owns a 32 x 32 sub-tile = 2 x 2 blocks of the 16 x 16 x 4 MFMA.  A complex product
+// takes four real MFMAs into two accumulators (re += ar br - ai bi, im += ar bi + ai br), issued
+// so that two updates of one accumulator are 7 MFMAs apart.  Operands are staged through LDS in
+// k-slices of 16 (real and imaginary planes); the next slice is fetched into registers while the
+// current one is multiplied.  Batch entries may have different shapes; grid.x covers the largest
+// tile count and workgroups past an entry's tile count exit.  Every tile configuration runs the
+// same MFMA sequence for a given element of C, so the configurations give bitwise equal results
+// and the choice among them (gemm_tune.cpp) affects only the time.  Long-K entries with few
+// output tiles are split along K into a workspace and summed in a fixed order by a second kernel.
 #include "internal.h"
 
 #include <algorithm>
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, PADK = 2;
+constexpr int BK = 16, PADK = 2;
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
@@ -35,8 +36,29 @@ template <> struct mfma_t<float> {
   __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+// load of one complex element through a global-address-space pointer (descriptor pointers are
+// generic; flat loads would also count against the LDS wait counter and hold up the LDS reads
+// behind the prefetch of the next slice)
 template <class R>
-__global__ __launch_bounds__(256) void k_gemm(const GemmDescT<R>* __restrict__ descs) {
+__device__ __forceinline__ typename cx<R>::T gload(const typename cx<R>::T* p) {
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *(const __attribute__((address_space(1))) v2*)p;
+  return cx<R>::make(v.x, v.y);
+}
+
+template <class R>
+__device__ __forceinline__ void gstore(typename cx<R>::T* p, typename cx<R>::T v) {
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  v2 w;
+  w.x = v.x;
+  w.y = v.y;
+  *(__attribute__((address_space(1))) v2*)p = w;
+}
+
+template <class R, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm(const GemmDescT<R>* __restrict__ descs) {
+  constexpr int BM = 32 * WM, BN = 32 * WN, NT = 64 * WM * WN;
+  constexpr int QA = BM * BK / NT, QB = BK * BN / NT;  // slice elements of op(A) and B per thread
   typedef typename cx<R>::T C_t;
   typedef typename mfma_t<R>::acc acc_t;
   const GemmDescT<R> d = descs[blockIdx.y];
@@ -46,11 +68,11 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDescT<R>* __restrict__ d
     // k == 0: C = beta C
     if (t < tm * tn && d.k <= 0) {
       const int i0 = (t % tm) * BM, j0 = (t / tm) * BN;
-      for (int e = threadIdx.x; e < BM * BN; e += 256) {
+      for (int e = threadIdx.x; e < BM * BN; e += NT) {
         const int i = i0 + e % BM, j = j0 + e / BM;
         if (i < d.m && j < d.n) {
           C_t* c = d.C + i + (size_t)j * d.ldc;
-          *c = (d.beta.x == 0 && d.beta.y == 0) ? cx<R>::make(0, 0) : cmul(d.beta, *c);
+          gstore<R>(c, (d.beta.x == 0 && d.beta.y == 0) ? cx<R>::make(0, 0) : cmul(d.beta, gload<R>(c)));
         }
       }
     }
@@ -61,7 +83,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDescT<R>* __restrict__ d
   __shared__ R Bre[BK][BN + PADK], Bim[BK][BN + PADK];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform
-  const int wm = wv & 1, wn = wv >> 1;
+  const int wm = wv % WM, wn = wv / WM;
   // 16 x 16 blocks wholly outside C and k-steps past K take no MFMAs (ragged boxes of a batch
   // would otherwise pad every product to whole 64 x 64 x 16 tiles)
   const bool rv0 = i0 + wm * 32 < d.m, rv1 = i0 + wm * 32 + 16 < d.m;
@@ -78,30 +100,42 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDescT<R>* __restrict__ d
     }
   const C_t* __restrict__ A = d.A;
   const C_t* __restrict__ B = d.B;
-  const C_t zc = cx<R>::make(0, 0);
-  // register staging of one k-slice: 4 elements of op(A) and 4 of B per thread
-  C_t ra[4], rb[4];
+  // register staging of one k-slice: QA elements of op(A) and QB of B per thread
+  C_t ra[QA], rb[QB];
   auto load_slice = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + q * 256;
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * NT;
       int ii, kk;
       if (!d.transA) { ii = e % BM; kk = e / BM; } else { kk = e % BK; ii = e / BK; }
       const int gi = i0 + ii, gk = k0 + kk;
-      ra[q] = (gi < d.m && gk < d.k) ? (d.transA ? A[gk + (size_t)gi * d.lda] : A[gi + (size_t)gk * d.lda]) : zc;
+      // a value select (a select of addresses with a local zero would make these flat loads)
+      const bool in = gi < d.m && gk < d.k;
+      const size_t off = d.transA ? gk + (size_t)gi * d.lda : gi + (size_t)gk * d.lda;
+      ra[q] = cx<R>::make(0, 0);
+      if (in) ra[q] = gload<R>(A + off);
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * NT;
       const int kb = e % BK, jj = e / BK;
       const int gj = j0 + jj, gkb = k0 + kb;
-      rb[q] = (gj < d.n && gkb < d.k) ? B[gkb + (size_t)gj * d.ldb] : zc;
+      rb[q] = cx<R>::make(0, 0);
+      if (gj < d.n && gkb < d.k) rb[q] = gload<R>(B + gkb + (size_t)gj * d.ldb);
     }
   };
   auto store_slice = [&]() {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + q * 256;
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * NT;
       int ii, kk;
       if (!d.transA) { ii = e % BM; kk = e / BM; } else { kk = e % BK; ii = e / BK; }
       Are[kk][ii] = ra[q].x;
       Aim[kk][ii] = ra[q].y;
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * NT;
       const int kb = e % BK, jj = e / BK;
       Bre[kb][jj] = rb[q].x;
       Bim[kb][jj] = rb[q].y;
@@ -174,8 +208,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDescT<R>* __restrict__ d
         if (i >= d.m) continue;
         C_t v = cmul(d.alpha, cx<R>::make(accr[a][b][r], acci[a][b][r]));
         C_t* c = d.C + i + (size_t)j * d.ldc;
-        if (!zero_beta) v = cadd(v, cmul(d.beta, *c));
-        *c = v;
+        if (!zero_beta) v = cadd(v, cmul(d.beta, gload<R>(c)));
+        gstore<R>(c, v);
       }
     }
 }
@@ -209,13 +243,21 @@ __global__ __launch_bounds__(256) void k_cast_f2d(const cplxf* __restrict__ s, c
 namespace qps {
 
 template <class R>
-hipError_t launch_gemm(const GemmDescT<R>* d, int nd, int max_tiles, hipStream_t s) {
-  if (nd == 0 || max_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm<R>, dim3(max_tiles, nd), dim3(256), 0, s, d);
+hipError_t launch_gemm(const GemmDescT<R>* d, int nd, const GemmPlan& p, hipStream_t s) {
+  if (nd == 0 || p.tiles == 0) return hipSuccess;
+  const dim3 grid(p.tiles, nd);
+  GemmTuneTimer tt(p, s);
+  switch (p.cfg) {
+    case 0: hipLaunchKernelGGL((k_gemm<R, 2, 2>), grid, dim3(256), 0, s, d); break;
+    case 1: hipLaunchKernelGGL((k_gemm<R, 1, 1>), grid, dim3(64), 0, s, d); break;
+    case 2: hipLaunchKernelGGL((k_gemm<R, 2, 1>), grid, dim3(128), 0, s, d); break;
+    case 3: hipLaunchKernelGGL((k_gemm<R, 1, 2>), grid, dim3(128), 0, s, d); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
-template hipError_t launch_gemm<double>(const GemmDesc*, int, int, hipStream_t);
-template hipError_t launch_gemm<float>(const GemmDesc32*, int, int, hipStream_t);
+template hipError_t launch_gemm<double>(const GemmDesc*, int, const GemmPlan&, hipStream_t);
+template hipError_t launch_gemm<float>(const GemmDesc32*, int, const GemmPlan&, hipStream_t);
 
 hipError_t launch_cast_d2f(const cplx* src, cplxf* dst, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
@@ -229,7 +271,7 @@ hipError_t launch_cast_f2d(const cplxf* src, cplx* dst, int64_t n, hipStream_t s
 }
 
 template <class R>
-static int tiles_of(const GemmDescT<R>& g) { return ((g.m + BM - 1) / BM) * ((g.n + BN - 1) / BN); }
+static int tiles_of(const GemmDescT<R>& g) { return ((g.m + 63) / 64) * ((g.n + 63) / 64); }
 
 // split-K when there are too few output tiles to occupy the chip and the inner dimension is
 // long: partial products go to a workspace and a second kernel sums them in a fixed order.  A
@@ -307,13 +349,12 @@ hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDescT<R>>& v0, hipS
       v.push_back(h);
     }
   }
-  int max_tiles = 0;
-  for (const auto& g : v) max_tiles = std::max(max_tiles, tiles_of(g));
+  const GemmPlan plan = gemm_plan(v.data(), v.size());
   hipError_t e = upload(arena, v, s);
   if (e != hipSuccess) return e;
   {
     ProfScope ps(sizeof(R) == 8 ? "zgemm" : "cgemm", s, flops, bytes);
-    e = launch_gemm<R>(arena.as<GemmDesc>(), (int)v.size(), max_tiles, s);
+    e = launch_gemm<R>(arena.as<GemmDesc>(), (int)v.size(), plan, s);
     if (e != hipSuccess) return e;
   }
   for (const auto& r : reds) {

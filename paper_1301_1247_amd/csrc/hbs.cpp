@@ -29,11 +29,9 @@ namespace {
 struct LaunchRec {
   size_t off;
   int cnt;
-  int max_tiles;
+  GemmPlan plan;
   double flops;
 };
-
-int tiles_of(const GemmDesc& g) { return ((g.m + 63) / 64) * ((g.n + 63) / 64); }
 
 GemmDesc gd(const cplx* A, int lda, int transA, const cplx* B, int ldb, cplx* C, int ldc, int m, int n, int k,
             cplx alpha = mkc(1, 0), cplx beta = mkc(0, 0)) {
@@ -881,20 +879,20 @@ int apply_interp(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx
     const int ldxin = (l == 1) ? (int)ldz : (int)V.ktot;
     cplx* out = (l == L) ? X : xbuf(l);
     const int64_t ldo = (l == L) ? ldx : V.ntot;
-    LaunchRec rec{all.size(), 0, 0, 0.0};
+    LaunchRec rec{all.size(), 0, GemmPlan{0, 0, 0}, 0.0};
     for (int b = 0; b < V.nb; ++b) {
       all.push_back(gd(V.P.as<cplx>() + V.oP[b], V.n[b], 0, xin + V.soff[b], ldxin, out + V.aoff[b], (int)ldo, V.n[b],
                        (int)r, V.k[b]));
-      rec.max_tiles = std::max(rec.max_tiles, tiles_of(all.back()));
       rec.flops += 8.0 * V.n[b] * (double)r * V.k[b];
     }
     rec.cnt = (int)(all.size() - rec.off);
+    rec.plan = gemm_plan(all.data() + rec.off, rec.cnt);
     recs.push_back(rec);
   }
   CK(upload(h->arena, all, st));
   for (auto& rc : recs) {
     ProfScope ps("zgemm", st, rc.flops, 0.0);
-    CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.max_tiles, st));
+    CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.plan, st));
   }
   // stream-ordered: the caller's later work on the handle's stream sees the result
   return HBS_OK;
@@ -925,20 +923,20 @@ int apply_down_E(hbs_handle* h, const cplx* Z, int64_t ldz, cplx* X, int64_t ldx
     const int ldxin = (l == 1) ? (int)ldz : (int)V.ktot;
     cplx* out = (l == L) ? X : xbuf(l);
     const int64_t ldo = (l == L) ? ldx : V.ntot;
-    LaunchRec rec{all.size(), 0, 0, 0.0};
+    LaunchRec rec{all.size(), 0, GemmPlan{0, 0, 0}, 0.0};
     for (int b = 0; b < V.nb; ++b) {
       all.push_back(gd(V.E.as<cplx>() + V.oE[b], V.n[b], 0, xin + V.soff[b], ldxin, out + V.aoff[b], (int)ldo, V.n[b],
                        (int)r, V.k[b]));
-      rec.max_tiles = std::max(rec.max_tiles, tiles_of(all.back()));
       rec.flops += 8.0 * V.n[b] * (double)r * V.k[b];
     }
     rec.cnt = (int)(all.size() - rec.off);
+    rec.plan = gemm_plan(all.data() + rec.off, rec.cnt);
     recs.push_back(rec);
   }
   CK(upload(h->arena, all, st));
   for (auto& rc : recs) {
     ProfScope ps("zgemm", st, rc.flops, 0.0);
-    CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.max_tiles, st));
+    CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.plan, st));
   }
   // stream-ordered: the caller's later work on the handle's stream sees the result
   return HBS_OK;
@@ -964,20 +962,20 @@ int apply_interp_t(hbs_handle* h, const cplx* X, int64_t ldx, cplx* Z, int64_t l
     const int lds = (l == L) ? (int)ldx : (int)V.ntot;
     cplx* dst = (l == 1) ? Z : xbuf(l - 1);
     const int ldd = (l == 1) ? (int)ldz : (int)V.ktot;
-    LaunchRec rec{all.size(), 0, 0, 0.0};
+    LaunchRec rec{all.size(), 0, GemmPlan{0, 0, 0}, 0.0};
     for (int b = 0; b < V.nb; ++b) {
       all.push_back(gd(V.P.as<cplx>() + V.oP[b], V.n[b], 1, src + V.aoff[b], lds, dst + V.soff[b], ldd, V.k[b], (int)r,
                        V.n[b]));
-      rec.max_tiles = std::max(rec.max_tiles, tiles_of(all.back()));
       rec.flops += 8.0 * V.n[b] * (double)r * V.k[b];
     }
     rec.cnt = (int)(all.size() - rec.off);
+    rec.plan = gemm_plan(all.data() + rec.off, rec.cnt);
     recs.push_back(rec);
   }
   CK(upload(h->arena, all, st));
   for (auto& rc : recs) {
     ProfScope ps("zgemm", st, rc.flops, 0.0);
-    CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.max_tiles, st));
+    CK(launch_zgemm(h->arena.as<GemmDesc>() + rc.off, rc.cnt, rc.plan, st));
   }
   // stream-ordered: the caller's later work on the handle's stream sees the result
   return HBS_OK;
@@ -1004,7 +1002,8 @@ namespace {
 struct Step {
   int kind;  // 0: FP64 GEMM batch, 1: FP32 GEMM batch, 2: cast to complex64, 3: cast to complex128
   size_t off;
-  int cnt, max_tiles;
+  int cnt;
+  GemmPlan plan;
   double flops;
   const void* src;
   void* dst;
@@ -1066,22 +1065,18 @@ static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_
   std::vector<GemmDesc32> d32;
   std::vector<Step> prog;
   auto close64 = [&](size_t s0) {
-    Step t{0, s0, (int)(d64.size() - s0), 0, 0.0, nullptr, nullptr, 0};
-    for (size_t i = s0; i < d64.size(); ++i) {
-      t.max_tiles = std::max(t.max_tiles, ((d64[i].m + 63) / 64) * ((d64[i].n + 63) / 64));
-      t.flops += 8.0 * d64[i].m * (double)d64[i].n * d64[i].k;
-    }
+    Step t{0, s0, (int)(d64.size() - s0), gemm_plan(d64.data() + s0, d64.size() - s0), 0.0, nullptr, nullptr, 0};
+    for (size_t i = s0; i < d64.size(); ++i) t.flops += 8.0 * d64[i].m * (double)d64[i].n * d64[i].k;
     if (t.cnt > 0) prog.push_back(t);
   };
   auto close32 = [&](size_t s0) {
-    Step t{1, s0, (int)(d32.size() - s0), 0, 0.0, nullptr, nullptr, 0};
-    for (size_t i = s0; i < d32.size(); ++i) {
-      t.max_tiles = std::max(t.max_tiles, ((d32[i].m + 63) / 64) * ((d32[i].n + 63) / 64));
-      t.flops += 8.0 * d32[i].m * (double)d32[i].n * d32[i].k;
-    }
+    Step t{1, s0, (int)(d32.size() - s0), gemm_plan(d32.data() + s0, d32.size() - s0), 0.0, nullptr, nullptr, 0};
+    for (size_t i = s0; i < d32.size(); ++i) t.flops += 8.0 * d32[i].m * (double)d32[i].n * d32[i].k;
     if (t.cnt > 0) prog.push_back(t);
   };
-  auto cast = [&](int kind, const void* src, void* dst, int64_t n) { prog.push_back({kind, 0, 0, 0, 0.0, src, dst, n}); };
+  auto cast = [&](int kind, const void* src, void* dst, int64_t n) {
+    prog.push_back({kind, 0, 0, GemmPlan{0, 0, 0}, 0.0, src, dst, n});
+  };
 
   // ---- upward
   if (mixed) {
@@ -1189,10 +1184,10 @@ static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_
       hipError_t e;
       if (t.kind == 0) {
         ProfScope ps2(prof ? "zgemm" : nullptr, s, t.flops, 0.0);
-        e = launch_gemm<double>(dd64 + t.off, t.cnt, t.max_tiles, s);
+        e = launch_gemm<double>(dd64 + t.off, t.cnt, t.plan, s);
       } else if (t.kind == 1) {
         ProfScope ps2(prof ? "cgemm" : nullptr, s, t.flops, 0.0);
-        e = launch_gemm<float>(dd32 + t.off, t.cnt, t.max_tiles, s);
+        e = launch_gemm<float>(dd32 + t.off, t.cnt, t.plan, s);
       } else if (t.kind == 2) {
         e = launch_cast_d2f(static_cast<const cplx*>(t.src), static_cast<cplxf*>(t.dst), t.n, s);
       } else {

@@ -141,9 +141,38 @@ hipError_t launch_eye(const CopyDesc* d, int nd, int max_elems, hipStream_t s); 
 // per box: centre, radius, bounding box, max and mean |curvature|, arc length (10 doubles)
 hipError_t launch_box_circles(const Geo& g, const int* lo, const int* hi, int nbox, double* out, hipStream_t s);
 hipError_t launch_gather_idx(const int* src, const int* idx, int* dst, int64_t n, hipStream_t s);
+// Launch plan of one batched GEMM: tile configuration (cfg: 0 = 64 x 64 tiles of 2 x 2 wavefronts,
+// 1 = 32 x 32 of one, 2 = 64 x 32 of 2 x 1, 3 = 32 x 64 of 1 x 2), grid width (tiles of the largest
+// entry) and shape class.  Every configuration gives bitwise equal results.
+constexpr int kGemmConfigs = 4;
+struct GemmPlan {
+  int cfg, tiles, key;
+};
+// shape class of a batch: precision (0 complex128, 1 complex64) and ceil(log2) of the largest m,
+// n, k and of the entry count, packed as prec << 24 | m << 18 | n << 12 | k << 6 | count
+int gemm_class_key(int prec, int64_t max_m, int64_t max_n, int64_t max_k, int64_t nd);
+// the configuration of a class: the forced one while a tuning sweep runs, else the tuning table's
+// entry, else 0
+int gemm_config_of(int key);
 template <class R>
-hipError_t launch_gemm(const GemmDescT<R>* d, int nd, int max_tiles, hipStream_t s);
-inline hipError_t launch_zgemm(const GemmDesc* d, int nd, int max_tiles, hipStream_t s) { return launch_gemm<double>(d, nd, max_tiles, s); }
+GemmPlan gemm_plan(const GemmDescT<R>* v, size_t nd);
+// tuning table and sweeps (gemm_tune.cpp)
+int gemm_tune_lookup(int key);                                  // table entry or -1
+void gemm_tune_set(const int* keys, const int* cfgs, int n);    // n < 0: the built-in table
+int gemm_tune_get(int* keys, int* cfgs, int cap);               // entries copied (cap may be 0), returns the count
+bool gemm_tune_begin(int cfg);                                  // force cfg on every launch and time each class
+int gemm_tune_end(int* keys, double* ms, int64_t* launches, int cap, bool* ok);  // classes timed; ends the sweep
+// times one launch per class while a sweep runs (not while the stream is being captured)
+struct GemmTuneTimer {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int key = 0;
+  hipStream_t s = nullptr;
+  GemmTuneTimer(const GemmPlan& p, hipStream_t st);
+  ~GemmTuneTimer();
+};
+template <class R>
+hipError_t launch_gemm(const GemmDescT<R>* d, int nd, const GemmPlan& p, hipStream_t s);
+inline hipError_t launch_zgemm(const GemmDesc* d, int nd, const GemmPlan& p, hipStream_t s) { return launch_gemm<double>(d, nd, p, s); }
 // blocked Gauss-Jordan inversion; tbuf: nd * 32 * max_n complex; ipiv: nd * max_n ints; info: nd ints
 template <class R>
 hipError_t launch_inv(const InvDescT<R>* d, int nd, int max_n, typename cx<R>::T* tbuf, int* ipiv, int* info, hipStream_t s);

@@ -115,3 +115,52 @@ def test_kr6_corrections_match_oracle_derivation():
     g_lib = B.kr6_corrections()
     g_or = quadrature.kr6_corrections()
     assert np.abs(g_lib - g_or).max() < 1e-12 * np.abs(g_or).max()
+
+
+# ---------------------------------------------------------------- GEMM tile tuning table (host logic)
+
+def _clog2(x):
+    x = max(1, int(x))
+    return (x - 1).bit_length()
+
+
+@pytest.mark.parametrize("c64,m,n,k,cnt", [(0, 1, 1, 1, 1), (0, 64, 64, 16, 1), (0, 65, 200, 97, 1024),
+                                           (1, 808, 200, 808, 1), (0, 0, 0, 0, 0), (1, 4097, 3, 20011, 7)])
+def test_gemm_class_key_packing(c64, m, n, k, cnt):
+    from paper_1301_1247_amd import binding as B
+    key = B.gemm_class(m, n, k, cnt, complex64=bool(c64))
+    assert key == (c64 << 24 | _clog2(m) << 18 | _clog2(n) << 12 | _clog2(k) << 6 | _clog2(cnt))
+    assert B.gemm_class_fields(key) == (c64, _clog2(m), _clog2(n), _clog2(k), _clog2(cnt))
+
+
+def test_gemm_tune_table_roundtrip_and_builtin():
+    import json
+    from paper_1301_1247_amd import binding as B
+    builtin = B.gemm_tune_get()
+    path = os.path.join(ROOT, "paper_1301_1247_amd", "gemm_tune_default.json")
+    if os.path.exists(path):
+        want = {int(e["key"]): int(e["cfg"]) for e in json.load(open(path))["table"]}
+        assert builtin == want  # the library embeds the committed table
+    try:
+        k1, k2 = B.gemm_class(100, 200, 50, 1000), B.gemm_class(808, 200, 808, 1, complex64=True)
+        B.gemm_tune_set({k1: 1, k2: 3})
+        assert B.gemm_tune_get() == {k1: 1, k2: 3}
+        assert B.gemm_tune_lookup(k1) == 1 and B.gemm_tune_lookup(k2) == 3
+        assert B.gemm_tune_lookup(k1 + 1) == -1
+        with pytest.raises(B.HBSError):
+            B.gemm_tune_set({k1: 4})
+        assert B.gemm_tune_get() == {k1: 1, k2: 3}  # a rejected table leaves the active one
+        B.gemm_tune_set({})
+        assert B.gemm_tune_get() == {}
+    finally:
+        B.gemm_tune_set(None)
+    assert B.gemm_tune_get() == builtin
+
+
+def test_gemm_tune_sweep_bounds():
+    from paper_1301_1247_amd import binding as B
+    for bad in (-1, 4):
+        with pytest.raises(B.HBSError):
+            B.gemm_tune_begin(bad)
+    B.gemm_tune_begin(2)
+    assert B.gemm_tune_end() == {}  # nothing launched: no classes timed
