@@ -33,12 +33,14 @@ FP32_PEAK_TFLOPS = 157.3
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_gemm_wavy40_N1e5_traffic.txt")
 GEMM_SRC = os.path.join(HERE, "paper_1301_1247_amd", "csrc", "gemm.hip")
+GEMM_TABLE = os.path.join(HERE, "paper_1301_1247_amd", "gemm_tune_default.json")
 
 
 def measured_traffic():
-    """HBM bytes per k_gemm<double> launch from the committed rocprofv3 counter runs (FETCH_SIZE and
-    WRITE_SIZE per dispatch, KiB, scaled by the factors a plain copy of known size gives), or None
-    when the GEMM source has changed since the counters were taken."""
+    """HBM bytes per complex128 GEMM launch (k_gemm<double, *, *>, every tile configuration) from the
+    committed rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE per dispatch, KiB, scaled by the
+    factors a plain copy of known size gives), or None when the GEMM source or its tuning table
+    has changed since the counters were taken."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -49,6 +51,10 @@ def measured_traffic():
             kv[k.strip()] = v.strip()
     sha = hashlib.sha256(open(GEMM_SRC, "rb").read()).hexdigest()
     if kv.get("source_sha256") != sha:
+        return None
+    # the tile configurations (and so the operand re-reads) follow the embedded tuning table
+    tsha = hashlib.sha256(open(GEMM_TABLE, "rb").read()).hexdigest() if os.path.exists(GEMM_TABLE) else "none"
+    if kv.get("table_sha256") != tsha:
         return None
     return 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["fetch_factor"]) +
                      float(kv["write_kib_per_launch"]) * float(kv["write_factor"]))
@@ -244,7 +250,7 @@ def main():
         "levels": st.levels, "max_rank": st.max_rank, "root_size": st.root_size,
         "refine_iters": st.refine_iters, "refine_residual": st.refine_residual,
         "rank_fallbacks": st.rank_fallbacks, "sketch_bytes_max": st.sketch_bytes_max,
-        "roofline": {"bound": "mfma", "kernel": ("k_zgemm (complex FP64 MFMA GEMM)" if fam == "zgemm"
+        "roofline": {"bound": "mfma", "kernel": ("k_gemm<double, *, *> (complex FP64 MFMA GEMM, tuned tiles)" if fam == "zgemm"
                                                  else "k_gemm<float> (complex FP32 MFMA GEMM)"),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic() if fam == "zgemm" and wl.name == "wavy40" else None,
