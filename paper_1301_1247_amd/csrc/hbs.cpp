@@ -521,72 +521,6 @@ int build(hbs_handle* h) {
     h->top_identity = ident;
     if (ident)
       for (int b = 0; b < nb; ++b) s[b] = m[b];  // no sketch
-    // the side stream: the children's factor chain (their reduced blocks D^ enter this level's
-    // diagonal blocks), then this level's diagonal blocks and their inverses
-    if (pending) {
-      const int rc = factor_chain(pending);
-      if (rc != HBS_OK) return rc;
-      pending = 0;
-    }
-    // ---- diagonal blocks D (into G, inverted in place later) and forward blocks Df
-    V.oG.assign(nb + 1, 0);
-    for (int b = 0; b < nb; ++b) V.oG[b + 1] = V.oG[b] + (int64_t)V.n[b] * V.n[b];
-    CK(V.G.reserve(sizeof(cplx) * V.oG[nb]));
-    CK(V.Df.reserve(sizeof(cplx) * V.oG[nb]));
-    cplx* dG = V.G.as<cplx>();
-    cplx* dDf = V.Df.as<cplx>();
-    {
-      std::vector<BlockDesc> bd;
-      std::vector<CopyDesc> cz, cp, cd;
-      int maxe = 0;
-      for (int b = 0; b < nb; ++b) {
-        const int n = V.n[b];
-        maxe = std::max(maxe, n * n);
-        if (l == L) {
-          bd.push_back({dact + V.aoff[b], dact + V.aoff[b], dG + V.oG[b], n, n, n, 0});
-          cp.push_back({dG + V.oG[b], dDf + V.oG[b], n, n, n, n});
-        } else {
-          Level& C = h->lv[l + 1];
-          const int a = 2 * b, c = 2 * b + 1;
-          const int ka = C.k[a], kc = C.k[c];
-          const int* sa = C.skel.as<int>() + C.soff[a];
-          const int* sc = C.skel.as<int>() + C.soff[c];
-          cz.push_back({nullptr, dDf + V.oG[b], n, n, n, n});
-          bd.push_back({sa, sc, dDf + V.oG[b] + (int64_t)ka * n, ka, kc, n, 0});
-          bd.push_back({sc, sa, dDf + V.oG[b] + ka, kc, ka, n, 0});
-          cp.push_back({dDf + V.oG[b], dG + V.oG[b], n, n, n, n});
-          cd.push_back({C.Dh.as<cplx>() + C.oDh[a], dG + V.oG[b], ka, ka, ka, n});
-          cd.push_back({C.Dh.as<cplx>() + C.oDh[c], dG + V.oG[b] + (int64_t)ka * n + ka, kc, kc, kc, n});
-        }
-      }
-      if (!cz.empty()) {
-        CK(up_sync(arena_f, cz, sf));
-        CK(launch_copy(arena_f.as<CopyDesc>(), (int)cz.size(), maxe, sf));
-      }
-      {
-        int maxb = 0;
-        for (auto& d : bd) maxb = std::max(maxb, d.nr * d.nc);
-        CK(up_sync(arena_f, bd, sf));
-        ProfScope ps("assemble", sf, 0.0, 0.0);
-        CK(launch_eval_blocks(h->geo, arena_f.as<BlockDesc>(), (int)bd.size(), maxb, sf));
-      }
-      CK(up_sync(arena_f, cp, sf));
-      CK(launch_copy(arena_f.as<CopyDesc>(), (int)cp.size(), maxe, sf));
-      if (!cd.empty()) {
-        int maxc = 0;
-        for (auto& d : cd) maxc = std::max(maxc, d.nr * d.nc);
-        CK(up_sync(arena_f, cd, sf));
-        CK(launch_copy(arena_f.as<CopyDesc>(), (int)cd.size(), maxc, sf));
-      }
-    }
-
-    // complex128 levels: the diagonal blocks D are inverted on the side stream (after their
-    // assembly there) while the main stream compresses the level
-    if (!ident && l <= h->fp64_top) {
-      std::vector<InvDesc> iv;
-      for (int b = 0; b < nb; ++b) iv.push_back({dG + V.oG[b], V.n[b], V.n[b]});
-      CK(inv_batched_flags(arena_f, work_f, iv, sf, flags_for(nb, l, "diagonal block")));
-    }
     for (int b = 0; b < nb; ++b) zoff[b + 1] = zoff[b] + ((s[b] < m[b]) ? (int64_t)s[b] * V.n[b] : 0);
     h->stats.sketch_bytes_max = std::max<int64_t>(h->stats.sketch_bytes_max, (int64_t)sizeof(cplx) * zoff[nb]);
     cplx* dwt = nullptr;
@@ -678,6 +612,74 @@ int build(hbs_handle* h) {
       for (const auto& q : qd) { ms = std::max(ms, q.s); mn = std::max(mn, q.n); }
       ProfScope ps("cpqr", st, fl, 0.0);
       CK(launch_cpqr(arena.as<CpqrDesc>(), nb, ms, mn, h->tol, kout.as<int>(), st));
+    }
+    // the side stream: the children's factor chain (their reduced blocks D^ enter this level's
+    // diagonal blocks), then this level's diagonal blocks and their inverses.  Enqueued after the
+    // level's compression kernels, so that the host builds these launches while the GPU
+    // compresses and the main stream's kernels reach the GPU first.
+    if (pending) {
+      const int rc = factor_chain(pending);
+      if (rc != HBS_OK) return rc;
+      pending = 0;
+    }
+    // ---- diagonal blocks D (into G, inverted in place later) and forward blocks Df
+    V.oG.assign(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) V.oG[b + 1] = V.oG[b] + (int64_t)V.n[b] * V.n[b];
+    CK(V.G.reserve(sizeof(cplx) * V.oG[nb]));
+    CK(V.Df.reserve(sizeof(cplx) * V.oG[nb]));
+    cplx* dG = V.G.as<cplx>();
+    cplx* dDf = V.Df.as<cplx>();
+    {
+      std::vector<BlockDesc> bd;
+      std::vector<CopyDesc> cz, cp, cd;
+      int maxe = 0;
+      for (int b = 0; b < nb; ++b) {
+        const int n = V.n[b];
+        maxe = std::max(maxe, n * n);
+        if (l == L) {
+          bd.push_back({dact + V.aoff[b], dact + V.aoff[b], dG + V.oG[b], n, n, n, 0});
+          cp.push_back({dG + V.oG[b], dDf + V.oG[b], n, n, n, n});
+        } else {
+          Level& C = h->lv[l + 1];
+          const int a = 2 * b, c = 2 * b + 1;
+          const int ka = C.k[a], kc = C.k[c];
+          const int* sa = C.skel.as<int>() + C.soff[a];
+          const int* sc = C.skel.as<int>() + C.soff[c];
+          cz.push_back({nullptr, dDf + V.oG[b], n, n, n, n});
+          bd.push_back({sa, sc, dDf + V.oG[b] + (int64_t)ka * n, ka, kc, n, 0});
+          bd.push_back({sc, sa, dDf + V.oG[b] + ka, kc, ka, n, 0});
+          cp.push_back({dDf + V.oG[b], dG + V.oG[b], n, n, n, n});
+          cd.push_back({C.Dh.as<cplx>() + C.oDh[a], dG + V.oG[b], ka, ka, ka, n});
+          cd.push_back({C.Dh.as<cplx>() + C.oDh[c], dG + V.oG[b] + (int64_t)ka * n + ka, kc, kc, kc, n});
+        }
+      }
+      if (!cz.empty()) {
+        CK(up_sync(arena_f, cz, sf));
+        CK(launch_copy(arena_f.as<CopyDesc>(), (int)cz.size(), maxe, sf));
+      }
+      {
+        int maxb = 0;
+        for (auto& d : bd) maxb = std::max(maxb, d.nr * d.nc);
+        CK(up_sync(arena_f, bd, sf));
+        ProfScope ps("assemble", sf, 0.0, 0.0);
+        CK(launch_eval_blocks(h->geo, arena_f.as<BlockDesc>(), (int)bd.size(), maxb, sf));
+      }
+      CK(up_sync(arena_f, cp, sf));
+      CK(launch_copy(arena_f.as<CopyDesc>(), (int)cp.size(), maxe, sf));
+      if (!cd.empty()) {
+        int maxc = 0;
+        for (auto& d : cd) maxc = std::max(maxc, d.nr * d.nc);
+        CK(up_sync(arena_f, cd, sf));
+        CK(launch_copy(arena_f.as<CopyDesc>(), (int)cd.size(), maxc, sf));
+      }
+    }
+
+    // complex128 levels: the diagonal blocks D are inverted on the side stream (after their
+    // assembly there) while the main stream compresses the level
+    if (!ident && l <= h->fp64_top) {
+      std::vector<InvDesc> iv;
+      for (int b = 0; b < nb; ++b) iv.push_back({dG + V.oG[b], V.n[b], V.n[b]});
+      CK(inv_batched_flags(arena_f, work_f, iv, sf, flags_for(nb, l, "diagonal block")));
     }
     V.k.assign(nb, 0);
     CK(hipMemcpyAsync(V.k.data(), kout.p, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
