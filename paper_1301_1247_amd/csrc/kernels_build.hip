@@ -474,6 +474,18 @@ struct GjShared {
   typename cx<R>::T rowo[2][GJ_NBR];                 // row p before the step
 };
 
+// 1/a for the pivot, scaled against overflow as in cinv but with two divisions instead of four
+// (the inverse is on the dependent chain of every pivot step); 0 for a = 0
+template <class R>
+__device__ __forceinline__ typename cx<R>::T gj_recip(typename cx<R>::T a) {
+  const R sc = fmax(fabs(a.x), fabs(a.y));
+  if (!(sc > 0)) return cx<R>::make(0.0, 0.0);
+  const R is = R(1) / sc;
+  const R ar = a.x * is, ai = a.y * is;
+  const R q = is / (ar * ar + ai * ai);
+  return cx<R>::make(ar * q, -ai * q);
+}
+
 template <class R, int JJ>
 __device__ __forceinline__ void gj_pivot_steps(typename cx<R>::T (&a)[GJ_NBR], GjShared<R>& sh, int c0, int w, int n,
                                                int* __restrict__ ipiv, int* __restrict__ info_m) {
@@ -514,8 +526,7 @@ __device__ __forceinline__ void gj_pivot_steps(typename cx<R>::T (&a)[GJ_NBR], G
     C_t pr[GJ_NBR];
 #pragma unroll
     for (int j = 0; j < GJ_NBR; ++j) pr[j] = lane_bcast(pl, j);
-    const C_t piv = pr[JJ];
-    const C_t dd = (cabs2(piv) > 0) ? cinv(piv) : zero;
+    const C_t dd = gj_recip<R>(pr[JJ]);
     if (i == p) {
 #pragma unroll
       for (int j = 0; j < GJ_NBR; ++j) a[j] = (j == JJ) ? dd : cmul(pr[j], dd);
@@ -524,12 +535,12 @@ __device__ __forceinline__ void gj_pivot_steps(typename cx<R>::T (&a)[GJ_NBR], G
 #pragma unroll
         for (int j = 0; j < GJ_NBR; ++j) a[j] = sh.rowo[buf][j];
       }
-      const C_t f = a[JJ];
-      const C_t fd = cmul(f, dd);
+      const C_t fd = cmul(a[JJ], dd);
+      const C_t nfd = cx<R>::make(-fd.x, -fd.y);
 #pragma unroll
       for (int j = 0; j < GJ_NBR; ++j)
-        if (j != JJ) a[j] = csub(a[j], cmul(fd, pr[j]));
-      a[JJ] = cx<R>::make(-fd.x, -fd.y);
+        if (j != JJ) a[j] = cfma(nfd, pr[j], a[j]);  // four FMAs per entry
+      a[JJ] = nfd;
     }
     if constexpr (JJ + 1 < GJ_NBR) gj_pivot_steps<R, JJ + 1>(a, sh, c0, w, n, ipiv, info_m);
   }
