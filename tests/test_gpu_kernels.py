@@ -33,7 +33,7 @@ def test_hankel_seams_continuous(gpu_lib):
     assert np.abs(h1 - hankel1(1, x)).max() < 5e-15
 
 
-@pytest.mark.parametrize("n", [3, 40, 1030])
+@pytest.mark.parametrize("n", [3, 40, 600, 1030])
 def test_zinv_reports_singular(gpu_lib, n):
     # a zero column in the second matrix of the batch: no nonzero pivot exists at that step
     rng = np.random.default_rng(n + 5)
@@ -57,7 +57,8 @@ def test_zgemm_matches_numpy(gpu_lib, m, n, k, trans):
     assert np.abs(C - ref).max() < 1e-13 * max(1.0, np.abs(ref).max()) * math.sqrt(k)
 
 
-@pytest.mark.parametrize("n", [1, 5, 16, 17, 32, 33, 100, 257, 1024, 1030])
+# 300, 513, 808: ragged last wavefronts at the sizes of the root and Schur inversions
+@pytest.mark.parametrize("n", [1, 5, 16, 17, 32, 33, 100, 257, 300, 513, 808, 1024, 1030])
 def test_zinv_matches_numpy(gpu_lib, n):
     rng = np.random.default_rng(n)
     A = rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n)) + 3 * np.eye(n)
@@ -89,7 +90,7 @@ def test_cgemm_complex64_matches_numpy(gpu_lib, m, n, k, trans):
     assert np.abs(C - ref).max() < 2e-6 * math.sqrt(k) * max(1.0, math.sqrt(k))
 
 
-@pytest.mark.parametrize("n", [1, 33, 257])
+@pytest.mark.parametrize("n", [1, 33, 257, 600])
 def test_cinv_complex64_matches_numpy(gpu_lib, n):
     rng = np.random.default_rng(n + 11)
     A = (rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n)) + 3 * np.eye(n)).astype(np.complex64)
