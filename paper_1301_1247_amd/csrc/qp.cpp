@@ -689,6 +689,49 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
                      gcnt[gg], nr, minus1c, onec));
     CR(gemm(g));
   }
+  // Bragg groups of >= 4 angles share one basis of diffraction orders (rows qlo .. qlo + nq - 1
+  // relative to the group's first angle).  The bases depend only on the nodes and the orders:
+  // when they all fit one buffer they are computed here, where the main stream would otherwise
+  // wait for the side stream's Woodbury factors.
+  const size_t bragg_ecap = ((size_t)4 << 30) / sizeof(cplx);
+  auto bragg_orders = [&](int g, int* qlo, int* nq, std::vector<int>* sl) {
+    const int q0 = goff[g], cnt = gcnt[g];
+    int lo = 1 << 30, hi = -(1 << 30);
+    if (sl) sl->assign(cnt, 0);
+    for (int a = 0; a < cnt; ++a) {
+      const int mshift = (int)std::llround((kx[q0 + a] - kx[q0]) * period / (2 * M_PI));
+      const int s0 = mshift + nlo[q0 + a];
+      if (sl) (*sl)[a] = s0;
+      lo = std::min(lo, s0);
+      hi = std::max(hi, s0 + nm[q0 + a] - 1);
+    }
+    *qlo = lo;
+    *nq = hi - lo + 1;
+  };
+  DevBuf bragg_pre;
+  bool bragg_early = false;
+  {
+    size_t et = 0;
+    for (int g = 0; g < ng; ++g)
+      if (gcnt[g] >= 4) {
+        int qlo, nq;
+        bragg_orders(g, &qlo, &nq, nullptr);
+        et += (size_t)2 * nq * N;
+      }
+    if (et > 0 && et <= bragg_ecap) {
+      CK(bragg_pre.reserve(sizeof(cplx) * et));
+      size_t eoff = 0;
+      ProfScope ps("bragg", st, 0.0, 0.0);
+      for (int g = 0; g < ng; ++g)
+        if (gcnt[g] >= 4) {
+          int qlo, nq;
+          bragg_orders(g, &qlo, &nq, nullptr);
+          CK(launch_bragg_basis(Q, kx[goff[g]], qlo, nq, bragg_pre.as<cplx>() + eoff, st));
+          eoff += (size_t)2 * nq * N;
+        }
+      bragg_early = true;
+    }
+  }
   if (overlap) CK(hipStreamWaitEvent(st, h->side_ev[1], 0));
   CR(solve_S(Wv, xi, minus1c));
   // eta = X_b - X(alpha) xi - V K (R X_b - R X(alpha) xi)
@@ -816,17 +859,20 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     std::vector<int> slots;
     size_t etot = 0, ctot = 0;
     // bases of at most ~4 GiB at a time
-    const size_t ecap = ((size_t)4 << 30) / sizeof(cplx);
+    const size_t ecap = bragg_ecap;
     auto flush = [&]() -> int {
       if (bg.empty()) return HBS_OK;
-      CK(h->work.reserve(sizeof(cplx) * (etot + ctot) + sizeof(int) * slots.size() + 512));
-      cplx* E = h->work.as<cplx>();
-      cplx* Cg = E + etot;
+      // with the bases computed early (one buffer, so this is the only flush) only the
+      // coefficients and slots go to the work buffer
+      const size_t ewk = bragg_early ? 0 : etot;
+      CK(h->work.reserve(sizeof(cplx) * (ewk + ctot) + sizeof(int) * slots.size() + 512));
+      cplx* E = bragg_early ? bragg_pre.as<cplx>() : h->work.as<cplx>();
+      cplx* Cg = h->work.as<cplx>() + ewk;
       int* dslot = (int*)(Cg + ctot);
       CK(hipMemcpyAsync(dslot, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice, st));
       std::vector<GemmDesc> g;
       for (const BG& b : bg) {
-        CK(launch_bragg_basis(Q, b.kref, b.qlo, b.nq, E + b.eoff, st));
+        if (!bragg_early) CK(launch_bragg_basis(Q, b.kref, b.qlo, b.nq, E + b.eoff, st));
         g.push_back(gd(E + b.eoff, 2 * b.nq, 0, eta + (size_t)b.q0 * N, N, Cg + b.coff, 2 * b.nq, 2 * b.nq, b.cnt, N, onec,
                        zero));
       }
@@ -847,16 +893,9 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
                         brg + (size_t)q0 * 2 * maxm, st));
         continue;
       }
-      BG b{q0, cnt, 1 << 30, 0, kx[q0], 0, 0, 0};
-      std::vector<int> sl(cnt);
-      int qhi = -(1 << 30);
-      for (int a = 0; a < cnt; ++a) {
-        const int mshift = (int)std::llround((kx[q0 + a] - b.kref) * period / (2 * M_PI));
-        sl[a] = mshift + nlo[q0 + a];
-        b.qlo = std::min(b.qlo, sl[a]);
-        qhi = std::max(qhi, sl[a] + nm[q0 + a] - 1);
-      }
-      b.nq = qhi - b.qlo + 1;
+      BG b{q0, cnt, 0, 0, kx[q0], 0, 0, 0};
+      std::vector<int> sl;
+      bragg_orders(g, &b.qlo, &b.nq, &sl);
       if (etot + (size_t)2 * b.nq * N > ecap) CR(flush());
       b.soff = slots.size();
       for (int a = 0; a < cnt; ++a) slots.push_back(sl[a] - b.qlo);

@@ -152,6 +152,26 @@ def test_qp_wavy_kr6_parity_shared_and_distinct_phases(gpu_lib, wavy_small):
     _check_qp(res, ref, len(thetas))
 
 
+@pytest.mark.parametrize("walls", ["dense", "compressed"])
+def test_qp_wavy_kr6_parity_bragg_group_basis(gpu_lib, wavy_small, walls):
+    """Five angles on one Bloch phase take the shared basis of diffraction orders (groups of four
+    or more: one batched product for all their Bragg amplitudes), a sixth angle the direct sums."""
+    c, N, om, disc, A, lu = wavy_small
+    d = 2 * math.pi
+    c1 = 0.31  # the shared phase keeps the diffraction orders of c1, away from Wood's anomalies
+    thetas = np.array([-math.acos(c1 + m * 2 * math.pi / (om * d)) for m in range(5)] + [-0.45])
+    nodes, w, nrm, _ = discretize(c, N)
+    kw = {}
+    if walls == "compressed":
+        c0 = 0.5 * (nodes.max(0) + nodes.min(0))
+        kw["far_radius"] = 0.9 * (0.5 * d - abs(c0[0]))
+    h = gpu_lib.Handle(nodes, w, nrm, om, 1e-12, **kw)
+    res = h.qp_solve_many(d, thetas, compress_walls=1 if walls == "compressed" else -1)
+    assert h.stats().walls_compressed == (walls == "compressed")
+    ref = pq.solve_qp(disc, N, om, d, thetas, quad="kr6", A0=A)
+    _check_qp(res, ref, len(thetas))
+
+
 def test_qp_wavy_kr6_parity_fp32_preconditioner(gpu_lib, wavy_small):
     c, N, om, disc, A, lu = wavy_small
     d = 2 * math.pi
