@@ -275,22 +275,39 @@ static int tiles_of(const GemmDescT<R>& g) { return ((g.m + 63) / 64) * ((g.n + 
 
 // split-K when there are too few output tiles to occupy the chip and the inner dimension is
 // long: partial products go to a workspace and a second kernel sums them in a fixed order.  A
-// descriptor with few tiles and a long inner dimension is the critical path of its launch.
+// descriptor with few tiles and a long inner dimension is the critical path of its launch (K >=
+// 4096: up to ~1024 workgroups per descriptor, parts of >= 1024); a launch whose descriptors
+// together have fewer output tiles than the chip has CUs, with 512 <= K < 4096, is split to ~512
+// workgroups in parts of >= 128 (at most 8).  The decision depends on the shapes only, never on
+// the tile configuration.
 template <class R>
-static int split_of(const GemmDescT<R>& g) {
-  const int64_t target = 1024;
+static int64_t launch_tiles(const std::vector<GemmDescT<R>>& v) {
+  int64_t t = 0;
+  for (const auto& g : v) t += tiles_of(g);
+  return t;
+}
+template <class R>
+static int split_of(const GemmDescT<R>& g, int64_t lt) {
   const int64_t tg = tiles_of(g);
-  if (tg >= target / 2 || g.k < 4096) return 1;
-  int S = (int)std::min<int64_t>(64, (target + tg - 1) / tg);
-  S = std::min(S, g.k / 1024);
+  int S = 1;
+  if (g.k >= 4096) {
+    const int64_t target = 1024;
+    if (tg >= target / 2) return 1;
+    S = (int)std::min<int64_t>(64, (target + tg - 1) / tg);
+    S = std::min(S, g.k / 1024);
+  } else if (g.k >= 512 && lt < 256) {
+    S = (int)std::min<int64_t>(8, (512 + lt - 1) / lt);
+    S = std::min(S, g.k / 128);
+  }
   return S >= 2 ? S : 1;
 }
 
 template <class R>
 void gemm_batched_needs(const std::vector<GemmDescT<R>>& v, size_t* arena_bytes, size_t* ws_bytes) {
   size_t nd = 0, w = 0;
+  const int64_t lt = launch_tiles(v);
   for (const auto& g : v) {
-    const int S = split_of(g);
+    const int S = split_of(g, lt);
     nd += S;
     if (S > 1) w += (size_t)S * g.m * g.n;
   }
@@ -304,17 +321,15 @@ hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDescT<R>>& v0, hipS
   typedef GemmDescT<R> GemmDesc;
   if (v0.empty()) return hipSuccess;
   double flops = 0.0, bytes = 0.0;
-  int64_t total_tiles = 0;
   for (const auto& g : v0) {
     flops += 8.0 * g.m * (double)g.n * g.k;
     bytes += 2.0 * sizeof(R) * ((double)g.m * g.k + (double)g.k * g.n + 2.0 * g.m * g.n);
-    total_tiles += tiles_of(g);
   }
-  (void)total_tiles;
   std::vector<int> split(v0.size(), 1);
   int64_t wtot = 0;
+  const int64_t lt = launch_tiles(v0);
   for (size_t i = 0; i < v0.size(); ++i) {
-    split[i] = ws ? split_of(v0[i]) : 1;
+    split[i] = ws ? split_of(v0[i], lt) : 1;
     if (split[i] > 1) wtot += (int64_t)split[i] * v0[i].m * v0[i].n;
   }
   if (wtot > 0) {

@@ -46,7 +46,9 @@ def test_zinv_reports_singular(gpu_lib, n):
 
 @pytest.mark.parametrize("m,n,k,trans", [(64, 64, 16, False), (37, 91, 53, False), (130, 70, 200, True),
                                           (1, 1, 1, False), (65, 129, 3, True),
-                                          (70, 9, 20011, False), (33, 5, 9000, True)])  # split-K cases
+                                          (70, 9, 20011, False), (33, 5, 9000, True),  # split-K, long K
+                                          (808, 50, 808, False), (600, 130, 1000, True),  # split-K, few tiles
+                                          (100, 100, 512, False)])
 def test_zgemm_matches_numpy(gpu_lib, m, n, k, trans):
     rng = np.random.default_rng(m * 1000 + n)
     nb = 3
