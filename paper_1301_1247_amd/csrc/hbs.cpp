@@ -342,6 +342,7 @@ int build(hbs_handle* h) {
   std::memset(h->stats.ranks_per_level_max, 0, sizeof(h->stats.ranks_per_level_max));
   std::memset(h->stats.ranks_per_level_mean, 0, sizeof(h->stats.ranks_per_level_mean));
 
+  DevBuf cpqrws;  // workspace of the one-launch-per-pivot QR of the top levels
   for (int l = L; l >= 1; --l) {
     Level& V = h->lv[l];
     const int nb = V.nb;
@@ -611,7 +612,7 @@ int build(hbs_handle* h) {
       int ms = 0, mn = 0;
       for (const auto& q : qd) { ms = std::max(ms, q.s); mn = std::max(mn, q.n); }
       ProfScope ps("cpqr", st, fl, 0.0);
-      CK(launch_cpqr(arena.as<CpqrDesc>(), nb, ms, mn, h->tol, kout.as<int>(), st));
+      CK(launch_cpqr(arena.as<CpqrDesc>(), nb, ms, mn, h->tol, kout.as<int>(), st, &cpqrws));
     }
     // the side stream: the children's factor chain (their reduced blocks D^ enter this level's
     // diagonal blocks), then this level's diagonal blocks and their inverses.  Enqueued after the
@@ -724,7 +725,7 @@ int build(hbs_handle* h) {
         int* k2 = kout.as<int>() + nb;
         int ms = 0, mn = 0;
         for (const auto& q : qd) { ms = std::max(ms, q.s); mn = std::max(mn, q.n); }
-        CK(launch_cpqr(arena.as<CpqrDesc>(), (int)qd.size(), ms, mn, h->tol, k2, st));
+        CK(launch_cpqr(arena.as<CpqrDesc>(), (int)qd.size(), ms, mn, h->tol, k2, st, &cpqrws));
         std::vector<int> hk2(redo.size());
         CK(hipMemcpyAsync(hk2.data(), k2, sizeof(int) * redo.size(), hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));

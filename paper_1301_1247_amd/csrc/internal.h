@@ -134,7 +134,9 @@ struct ProfScope {
 hipError_t launch_eval_blocks(const Geo& g, const BlockDesc* d, int nd, int max_elems, hipStream_t s);
 hipError_t launch_proxy(const Geo& g, const ProxyDesc* d, int nd, int max_elems, hipStream_t s);
 hipError_t launch_sketch(const SketchDesc* d, int nd, int max_s, int max_n, uint64_t seed, hipStream_t s);
-hipError_t launch_cpqr(const CpqrDesc* d, int nd, int max_s, int max_n, double tol, int* k_out, hipStream_t s);
+// ws: workspace for the few-large-boxes path (one launch per pivot step); nullptr: one workgroup per box
+hipError_t launch_cpqr(const CpqrDesc* d, int nd, int max_s, int max_n, double tol, int* k_out, hipStream_t s,
+                       DevBuf* ws = nullptr);
 hipError_t launch_buildP(const PDesc* d, int nd, int max_elems, hipStream_t s);
 hipError_t launch_copy(const CopyDesc* d, int nd, int max_elems, hipStream_t s);
 hipError_t launch_eye(const CopyDesc* d, int nd, int max_elems, hipStream_t s);  // dst = I (nr x nc)

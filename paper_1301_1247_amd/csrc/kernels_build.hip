@@ -103,6 +103,51 @@ __global__ __launch_bounds__(NT) void k_sketch(const SketchDesc* __restrict__ de
 }
 
 // ---------------------------------------------------------------- CPQR / ID
+// T = R11^{-1} R12 in place in Z[0:k, k:n] (Z: s x n, ld s), by blocks of 64 rows from the bottom:
+// the diagonal block is solved by one wavefront per column with the right-hand side in registers
+// (the solved entry is broadcast with readlane), then the rows above are updated by all threads.
+// Called by the whole workgroup.
+template <int NTQ>
+__device__ void cpqr_tsolve(cplx* Z, int s, int n, int k) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nw = NTQ / 64;
+  for (int i1 = k; i1 > 0; i1 -= 64) {
+    const int i0 = max(0, i1 - 64);
+    for (int j = k + wv; j < n; j += nw) {
+      cplx* col = Z + (size_t)j * s;
+      const int l = i0 + lane;
+      cplx t = (l < i1) ? col[l] : mkc(0, 0);
+      for (int i = i1 - 1; i >= i0; --i) {
+        const int li = i - i0;
+        if (lane == li) {
+          const cplx zii = Z[i + (size_t)i * s];
+          t = cabs2(zii) > 0.0 ? cmul(t, cinv(zii)) : mkc(0, 0);
+        }
+        const long long bx = __double_as_longlong(t.x), by = __double_as_longlong(t.y);
+        const int xlo = __builtin_amdgcn_readlane((int)(bx & 0xffffffff), li), xhi = __builtin_amdgcn_readlane((int)(bx >> 32), li);
+        const int ylo = __builtin_amdgcn_readlane((int)(by & 0xffffffff), li), yhi = __builtin_amdgcn_readlane((int)(by >> 32), li);
+        const cplx ti = mkc(__longlong_as_double(((long long)xhi << 32) | (unsigned)xlo),
+                            __longlong_as_double(((long long)yhi << 32) | (unsigned)ylo));
+        if (lane < li) t = csub(t, cmul(Z[l + (size_t)i * s], ti));
+      }
+      if (l < i1) col[l] = t;
+    }
+    __syncthreads();
+    if (i0 > 0) {
+      const int rows = i0, cols = n - k;
+      for (int e = tid; e < rows * cols; e += NTQ) {
+        const int r = e % rows, j = k + e / rows;
+        cplx* col = Z + (size_t)j * s;
+        cplx acc = col[r];
+        for (int i = i0; i < i1; ++i) acc = csub(acc, cmul(Z[r + (size_t)i * s], col[i]));
+        col[r] = acc;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+
 // One workgroup per box.  Householder QR with column pivoting on Z (s x n, in place, global
 // memory).  Column norms of the trailing rows are recomputed exactly in every update pass.
 // Rank: the first p with |R_pp| <= tol |R_00| (at least 1).
@@ -236,45 +281,181 @@ __global__ __launch_bounds__(NTQ) void k_cpqr(const CpqrDesc* __restrict__ descs
     }
     __syncthreads();
   }
-  // T = R11^{-1} R12 in place in Z[0:k, k:n], by blocks of 64 rows from the bottom: the diagonal
-  // block is solved by one wavefront per column with the right-hand side in registers (the
-  // solved entry is broadcast with readlane), then the rows above are updated by all threads.
-  for (int i1 = k; i1 > 0; i1 -= 64) {
-    const int i0 = max(0, i1 - 64);
-    for (int j = k + wv; j < n; j += nw) {
-      cplx* col = Z + (size_t)j * s;
-      const int l = i0 + lane;
-      cplx t = (l < i1) ? col[l] : mkc(0, 0);
-      for (int i = i1 - 1; i >= i0; --i) {
-        const int li = i - i0;
-        if (lane == li) {
-          const cplx zii = Z[i + (size_t)i * s];
-          t = cabs2(zii) > 0.0 ? cmul(t, cinv(zii)) : mkc(0, 0);
-        }
-        const long long bx = __double_as_longlong(t.x), by = __double_as_longlong(t.y);
-        const int xlo = __builtin_amdgcn_readlane((int)(bx & 0xffffffff), li), xhi = __builtin_amdgcn_readlane((int)(bx >> 32), li);
-        const int ylo = __builtin_amdgcn_readlane((int)(by & 0xffffffff), li), yhi = __builtin_amdgcn_readlane((int)(by >> 32), li);
-        const cplx ti = mkc(__longlong_as_double(((long long)xhi << 32) | (unsigned)xlo),
-                            __longlong_as_double(((long long)yhi << 32) | (unsigned)ylo));
-        if (lane < li) t = csub(t, cmul(Z[l + (size_t)i * s], ti));
-      }
-      if (l < i1) col[l] = t;
-    }
-    __syncthreads();
-    if (i0 > 0) {
-      const int rows = i0, cols = n - k;
-      for (int e = tid; e < rows * cols; e += NTQ) {
-        const int r = e % rows, j = k + e / rows;
-        cplx* col = Z + (size_t)j * s;
-        cplx acc = col[r];
-        for (int i = i0; i < i1; ++i) acc = csub(acc, cmul(Z[r + (size_t)i * s], col[i]));
-        col[r] = acc;
-      }
-      __syncthreads();
-    }
-  }
+  cpqr_tsolve<NTQ>(Z, s, n, k);
   for (int j = tid; j < n; j += NTQ) d.perm[j] = perm[j];
   if (tid == 0) k_out[blockIdx.x] = k;
+}
+
+// ---- column-pivoted QR of a few large boxes: one launch per pivot step
+// The one-workgroup kernel streams a box's whole trailing matrix through one CU at every pivot;
+// at the top levels (a handful of boxes) that leaves most of the chip idle and bounds a step by
+// one CU's bandwidth.  Here each pivot step is one launch, and each box's columns are spread over
+// workgroups of 16 columns: every workgroup finds the pivot from the column norms the previous
+// launch left, forms the same Householder vector from the pivot column (same data, same
+// arithmetic, hence the same bits in every workgroup), and applies it to its own 16 columns.
+// Columns do not move: a logical-to-physical column map and the norms are double-buffered
+// between launches (launch p reads buffer p & 1 and writes the other, for the columns after p),
+// and the pivot's physical column and R's diagonal entry are recorded per step.  A gather puts
+// the columns in pivot order into a second buffer, T = R11^{-1} R12 is formed there, and the
+// result is copied back.  The termination rule and the outputs are those of k_cpqr.
+constexpr int CPQRM_MAXS = 1024;
+struct CpqrmState {
+  int done, k, np, pad;  // np: pivot steps carried out (columns in pivot order)
+  double r00, pad2;
+};
+struct CpqrmWs {
+  int *pcA, *pcB, *fin;
+  double *cnA, *cnB;
+  cplx* alph;
+  CpqrmState* st;
+  cplx* W2;
+  int maxn;
+  int64_t zstride;
+};
+
+__global__ __launch_bounds__(256) void k_cpqrm_init(const CpqrDesc* __restrict__ descs, CpqrmWs W) {
+  const CpqrDesc d = descs[blockIdx.y];
+  const int b = blockIdx.y, s = d.s, n = d.n;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, sub = lane >> 4, rl = lane & 15;
+  const int j = 16 * blockIdx.x + 4 * wv + sub;
+  double a = 0.0;
+  if (j < n)
+    for (int i = rl; i < s; i += 16) a += cabs2(d.z[i + (size_t)j * s]);
+  a = row16_sum(a);
+  if (j < n && rl == 0) {
+    W.cnA[(size_t)b * W.maxn + j] = a;
+    W.pcA[(size_t)b * W.maxn + j] = j;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int pmax = min(s, n);
+    CpqrmState st0;
+    st0.done = 0; st0.k = pmax; st0.np = pmax; st0.pad = 0; st0.r00 = 0.0; st0.pad2 = 0.0;
+    W.st[b] = st0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cpqrm_step(const CpqrDesc* __restrict__ descs, CpqrmWs W, int p, double tol) {
+  const CpqrDesc d = descs[blockIdx.y];
+  const int b = blockIdx.y, s = d.s, n = d.n;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (p >= min(s, n)) return;
+  CpqrmState* S = W.st + b;
+  if (S->done) return;
+  const int slot0 = p + 1 + 16 * (int)blockIdx.x;
+  if (blockIdx.x != 0 && slot0 >= n) return;
+  const size_t o = (size_t)b * W.maxn;
+  const int* pcO = ((p & 1) ? W.pcB : W.pcA) + o;
+  const double* cnO = ((p & 1) ? W.cnB : W.cnA) + o;
+  int* pcN = ((p & 1) ? W.pcA : W.pcB) + o;
+  double* cnN = ((p & 1) ? W.cnA : W.cnB) + o;
+  __shared__ double rv[4];
+  __shared__ int ri[4];
+  __shared__ cplx v[CPQRM_MAXS];
+  // pivot: the largest remaining norm (ties: the smaller position)
+  double bv = -1.0;
+  int bi = n;
+  for (int j = p + tid; j < n; j += 256) {
+    const double c = cnO[j];
+    if (c > bv || (c == bv && j < bi)) { bv = c; bi = j; }
+  }
+  wave_argmax(bv, bi);
+  if (lane == 0) { rv[wv] = bv; ri[wv] = bi; }
+  __syncthreads();
+  double bb = rv[0];
+  int jp = ri[0];
+  for (int w = 1; w < 4; ++w)
+    if (rv[w] > bb || (rv[w] == bb && ri[w] < jp)) { bb = rv[w]; jp = ri[w]; }
+  const double nr = sqrt(fmax(bb, 0.0));
+  const double r00 = (p == 0) ? nr : S->r00;
+  if ((p > 0 && nr <= tol * r00) || (p == 0 && nr == 0.0)) {
+    if (blockIdx.x == 0 && tid == 0) {
+      S->k = (p == 0) ? 1 : p;
+      S->np = p;
+      S->done = 1;
+    }
+    return;
+  }
+  const int ph = pcO[jp];  // the pivot's physical column (read only in this launch)
+  const int pq = pcO[p];   // the column that moves to position jp
+  const cplx* zc = d.z + (size_t)ph * s;
+  for (int i = p + tid; i < s; i += 256) v[i - p] = zc[i];
+  __syncthreads();
+  // Householder vector of x = Z[p:s, ph] (every wavefront forms the same reduction)
+  double a = 0.0;
+  for (int i = lane; i < s - p; i += 64) a += cabs2(v[i]);
+  a = wave_sum(a);
+  const double xn = sqrt(a);
+  const cplx x0 = v[0];
+  const double ax0 = sqrt(cabs2(x0));
+  const cplx alpha = (ax0 > 0.0) ? cscale(x0, -xn / ax0) : mkc(-xn, 0.0);
+  const cplx v0 = csub(x0, alpha);
+  const double vn2 = a - ax0 * ax0 + cabs2(v0);
+  const double tau = (vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+  if (blockIdx.x == 0 && tid == 0) {
+    W.fin[o + p] = ph;
+    W.alph[o + p] = alpha;
+    if (p == 0) S->r00 = nr;
+  }
+  // this workgroup's columns: 16 lanes per column, 4 columns per wavefront
+  const int sub = lane >> 4, rl = lane & 15;
+  const int j = slot0 + 4 * wv + sub;
+  const bool act = j < n;
+  const int phys = act ? ((j == jp) ? pq : pcO[j]) : ph;
+  cplx* col = d.z + (size_t)phys * s;
+  cplx w = mkc(0, 0);
+  if (act)
+    for (int i = p + rl; i < s; i += 16) w = cadd(w, cmul(cconj(i == p ? v0 : v[i - p]), col[i]));
+  w = cscale(row16_csum(w), tau);
+  double an = 0.0;
+  if (act)
+    for (int i = p + rl; i < s; i += 16) {
+      const cplx z = csub(col[i], cmul(w, i == p ? v0 : v[i - p]));
+      col[i] = z;
+      if (i > p) an += cabs2(z);
+    }
+  an = row16_sum(an);
+  if (act && rl == 0) {
+    cnN[j] = an;
+    pcN[j] = phys;
+  }
+}
+
+// columns in pivot order into W2 (R's diagonal from the recorded steps), the permutation, the rank
+__global__ __launch_bounds__(256) void k_cpqrm_gather(const CpqrDesc* __restrict__ descs, CpqrmWs W, int* __restrict__ k_out) {
+  const CpqrDesc d = descs[blockIdx.y];
+  const int b = blockIdx.y, s = d.s, n = d.n, j = blockIdx.x;
+  if (j >= n) return;
+  const CpqrmState S = W.st[b];
+  const int pmax = min(s, n);
+  const int k = S.done ? S.k : pmax, np = S.done ? S.np : pmax;
+  const size_t o = (size_t)b * W.maxn;
+  const int* pcF = ((np & 1) ? W.pcB : W.pcA) + o;
+  const int phys = (j < np) ? W.fin[o + j] : pcF[j];
+  const cplx* src = d.z + (size_t)phys * s;
+  cplx* dst = W.W2 + (size_t)b * W.zstride + (size_t)j * s;
+  const cplx al = (j < np) ? W.alph[o + j] : mkc(0, 0);
+  for (int i = threadIdx.x; i < s; i += 256) {
+    cplx val = src[i];
+    if (j < np && i == j) val = al;
+    dst[i] = val;
+  }
+  if (threadIdx.x == 0) {
+    d.perm[j] = phys;
+    if (j == 0) k_out[b] = k;
+  }
+}
+
+// T = R11^{-1} R12 in W2, then W2 back into Z
+__global__ __launch_bounds__(1024) void k_cpqrm_tsolve(const CpqrDesc* __restrict__ descs, CpqrmWs W) {
+  const CpqrDesc d = descs[blockIdx.x];
+  const int b = blockIdx.x, s = d.s, n = d.n;
+  const CpqrmState S = W.st[b];
+  const int k = S.done ? S.k : min(s, n);
+  cplx* Z2 = W.W2 + (size_t)b * W.zstride;
+  cpqr_tsolve<1024>(Z2, s, n, k);
+  __syncthreads();
+  const int64_t tot = (int64_t)s * n;
+  for (int64_t e = threadIdx.x; e < tot; e += 1024) d.z[e] = Z2[e];
 }
 
 // P (n x k): P[perm[j], j] = 1 (j < k), P[perm[k + i], j] = T[j, i]
@@ -763,8 +944,38 @@ hipError_t launch_sketch(const SketchDesc* d, int nd, int max_s, int max_n, uint
   hipLaunchKernelGGL(k_sketch, grid, dim3(NT), 0, s, d, seed);
   return hipGetLastError();
 }
-hipError_t launch_cpqr(const CpqrDesc* d, int nd, int max_s, int max_n, double tol, int* k_out, hipStream_t s) {
+hipError_t launch_cpqr(const CpqrDesc* d, int nd, int max_s, int max_n, double tol, int* k_out, hipStream_t s, DevBuf* ws) {
   if (nd == 0) return hipSuccess;
+  if (ws && nd <= 16 && max_s <= CPQRM_MAXS && max_n <= CPQR_MAXN && max_s >= 1 && max_n >= 2) {
+    // a few large boxes: one launch per pivot step over workgroups of 16 columns
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t ni = (size_t)nd * max_n;
+    const int64_t zs = (int64_t)max_s * max_n;
+    const size_t bst = al(sizeof(CpqrmState) * nd), bi = al(sizeof(int) * ni), bd = al(sizeof(double) * ni),
+                 bc = al(sizeof(cplx) * ni), bw = al(sizeof(cplx) * (size_t)nd * zs);
+    hipError_t e = ws->reserve(bst + 3 * bi + 2 * bd + bc + bw);
+    if (e != hipSuccess) return e;
+    char* base = ws->as<char>();
+    CpqrmWs W;
+    W.st = (CpqrmState*)base;
+    W.pcA = (int*)(base + bst);
+    W.pcB = (int*)(base + bst + bi);
+    W.fin = (int*)(base + bst + 2 * bi);
+    W.cnA = (double*)(base + bst + 3 * bi);
+    W.cnB = (double*)(base + bst + 3 * bi + bd);
+    W.alph = (cplx*)(base + bst + 3 * bi + 2 * bd);
+    W.W2 = (cplx*)(base + bst + 3 * bi + 2 * bd + bc);
+    W.maxn = max_n;
+    W.zstride = zs;
+    const int ncg = (max_n + 15) / 16;
+    hipLaunchKernelGGL(k_cpqrm_init, dim3(ncg, nd), dim3(256), 0, s, d, W);
+    const int pmax = std::min(max_s, max_n);
+    const int nwg = (max_n - 1 + 15) / 16;
+    for (int p = 0; p < pmax; ++p) hipLaunchKernelGGL(k_cpqrm_step, dim3(nwg, nd), dim3(256), 0, s, d, W, p, tol);
+    hipLaunchKernelGGL(k_cpqrm_gather, dim3(max_n, nd), dim3(256), 0, s, d, W, k_out);
+    hipLaunchKernelGGL(k_cpqrm_tsolve, dim3(nd), dim3(1024), 0, s, d, W);
+    return hipGetLastError();
+  }
   if (nd >= 256 && max_s <= 512 && max_n <= 256)
     hipLaunchKernelGGL((k_cpqr<256, 512, 256, 0>), dim3(nd), dim3(256), 0, s, d, tol, k_out);
   else
