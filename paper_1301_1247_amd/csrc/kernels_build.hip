@@ -946,8 +946,11 @@ hipError_t launch_sketch(const SketchDesc* d, int nd, int max_s, int max_n, uint
 }
 hipError_t launch_cpqr(const CpqrDesc* d, int nd, int max_s, int max_n, double tol, int* k_out, hipStream_t s, DevBuf* ws) {
   if (nd == 0) return hipSuccess;
-  if (ws && nd <= 16 && max_s <= CPQRM_MAXS && max_n <= CPQR_MAXN && max_s >= 1 && max_n >= 2) {
-    // a few large boxes: one launch per pivot step over workgroups of 16 columns
+  // a few large boxes: one launch per pivot step over workgroups of 16 columns.  A launch costs
+  // about as much as a pivot step of the one-workgroup kernel on a 200 x 200 sketch, whose steps
+  // grow with s n (the trailing matrix through one CU): the launches pay from there on.
+  if (ws && nd <= 16 && max_s <= CPQRM_MAXS && max_n <= CPQR_MAXN && max_s >= 1 && max_n >= 2 &&
+      (int64_t)max_s * max_n >= 40000) {
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t ni = (size_t)nd * max_n;
     const int64_t zs = (int64_t)max_s * max_n;
