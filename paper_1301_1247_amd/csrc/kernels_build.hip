@@ -106,13 +106,29 @@ __global__ __launch_bounds__(NT) void k_sketch(const SketchDesc* __restrict__ de
 // T = R11^{-1} R12 in place in Z[0:k, k:n] (Z: s x n, ld s), by blocks of 64 rows from the bottom:
 // the diagonal block is solved by one wavefront per column with the right-hand side in registers
 // (the solved entry is broadcast with readlane), then the rows above are updated by all threads.
-// Called by the whole workgroup.
+// With lds (room for 64 x 65 + 64 complex values), the block of R11 and the inverses of its
+// diagonal are staged there first, so the serial steps wait on LDS instead of on global memory
+// (same arithmetic, same results).  Called by the whole workgroup.
+constexpr int CPQR_TS_LDS = 64 * 65 + 64;
 template <int NTQ>
-__device__ void cpqr_tsolve(cplx* Z, int s, int n, int k) {
+__device__ void cpqr_tsolve(cplx* Z, int s, int n, int k, cplx* lds) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nw = NTQ / 64;
   for (int i1 = k; i1 > 0; i1 -= 64) {
     const int i0 = max(0, i1 - 64);
+    const int nbk = i1 - i0;
+    if (lds) {
+      for (int e = tid; e < nbk * nbk; e += NTQ) {
+        const int r = e % nbk, c = e / nbk;
+        lds[r * 65 + c] = Z[(i0 + r) + (size_t)(i0 + c) * s];
+      }
+      __syncthreads();
+      for (int r = tid; r < nbk; r += NTQ) {
+        const cplx zii = lds[r * 65 + r];
+        lds[64 * 65 + r] = cabs2(zii) > 0.0 ? cinv(zii) : mkc(0, 0);
+      }
+      __syncthreads();
+    }
     for (int j = k + wv; j < n; j += nw) {
       cplx* col = Z + (size_t)j * s;
       const int l = i0 + lane;
@@ -120,15 +136,22 @@ __device__ void cpqr_tsolve(cplx* Z, int s, int n, int k) {
       for (int i = i1 - 1; i >= i0; --i) {
         const int li = i - i0;
         if (lane == li) {
-          const cplx zii = Z[i + (size_t)i * s];
-          t = cabs2(zii) > 0.0 ? cmul(t, cinv(zii)) : mkc(0, 0);
+          if (lds) {
+            t = cmul(t, lds[64 * 65 + li]);
+          } else {
+            const cplx zii = Z[i + (size_t)i * s];
+            t = cabs2(zii) > 0.0 ? cmul(t, cinv(zii)) : mkc(0, 0);
+          }
         }
         const long long bx = __double_as_longlong(t.x), by = __double_as_longlong(t.y);
         const int xlo = __builtin_amdgcn_readlane((int)(bx & 0xffffffff), li), xhi = __builtin_amdgcn_readlane((int)(bx >> 32), li);
         const int ylo = __builtin_amdgcn_readlane((int)(by & 0xffffffff), li), yhi = __builtin_amdgcn_readlane((int)(by >> 32), li);
         const cplx ti = mkc(__longlong_as_double(((long long)xhi << 32) | (unsigned)xlo),
                             __longlong_as_double(((long long)yhi << 32) | (unsigned)ylo));
-        if (lane < li) t = csub(t, cmul(Z[l + (size_t)i * s], ti));
+        if (lane < li) {
+          const cplx zl = lds ? lds[lane * 65 + li] : Z[l + (size_t)i * s];
+          t = csub(t, cmul(zl, ti));
+        }
       }
       if (l < i1) col[l] = t;
     }
@@ -139,6 +162,7 @@ __device__ void cpqr_tsolve(cplx* Z, int s, int n, int k) {
         const int r = e % rows, j = k + e / rows;
         cplx* col = Z + (size_t)j * s;
         cplx acc = col[r];
+#pragma unroll 8
         for (int i = i0; i < i1; ++i) acc = csub(acc, cmul(Z[r + (size_t)i * s], col[i]));
         col[r] = acc;
       }
@@ -146,7 +170,6 @@ __device__ void cpqr_tsolve(cplx* Z, int s, int n, int k) {
     }
   }
 }
-
 
 // One workgroup per box.  Householder QR with column pivoting on Z (s x n, in place, global
 // memory).  Column norms of the trailing rows are recomputed exactly in every update pass.
@@ -281,7 +304,8 @@ __global__ __launch_bounds__(NTQ) void k_cpqr(const CpqrDesc* __restrict__ descs
     }
     __syncthreads();
   }
-  cpqr_tsolve<NTQ>(Z, s, n, k);
+  __syncthreads();  // v is reused as the staging area of the triangular solve
+  cpqr_tsolve<NTQ>(Z, s, n, k, MAXS >= CPQR_TS_LDS ? v : nullptr);
   for (int j = tid; j < n; j += NTQ) d.perm[j] = perm[j];
   if (tid == 0) k_out[blockIdx.x] = k;
 }
@@ -452,7 +476,8 @@ __global__ __launch_bounds__(1024) void k_cpqrm_tsolve(const CpqrDesc* __restric
   const CpqrmState S = W.st[b];
   const int k = S.done ? S.k : min(s, n);
   cplx* Z2 = W.W2 + (size_t)b * W.zstride;
-  cpqr_tsolve<1024>(Z2, s, n, k);
+  __shared__ cplx stage[CPQR_TS_LDS];
+  cpqr_tsolve<1024>(Z2, s, n, k, stage);
   __syncthreads();
   const int64_t tot = (int64_t)s * n;
   for (int64_t e = threadIdx.x; e < tot; e += 1024) d.z[e] = Z2[e];
