@@ -106,26 +106,31 @@ __global__ __launch_bounds__(NT) void k_sketch(const SketchDesc* __restrict__ de
 // T = R11^{-1} R12 in place in Z[0:k, k:n] (Z: s x n, ld s), by blocks of 64 rows from the bottom:
 // the diagonal block is solved by one wavefront per column with the right-hand side in registers
 // (the solved entry is broadcast with readlane), then the rows above are updated by all threads.
-// With lds (room for 64 x 65 + 64 complex values), the block of R11 and the inverses of its
-// diagonal are staged there first, so the serial steps wait on LDS instead of on global memory
-// (same arithmetic, same results).  Called by the whole workgroup.
-constexpr int CPQR_TS_LDS = 64 * 65 + 64;
-template <int NTQ>
+// With lds (room for BH (BH + 1) + BH complex values), the blocks are BH rows high and each block
+// of R11 and the inverses of its diagonal are staged there first, so the serial steps wait on
+// LDS instead of on global memory (same arithmetic, same results).  Called by the whole
+// workgroup.
+template <int BH>
+constexpr int cpqr_ts_lds() { return BH * (BH + 1) + BH; }
+constexpr int CPQR_TS_LDS = cpqr_ts_lds<64>();
+template <int NTQ, int BH = 64>
 __device__ void cpqr_tsolve(cplx* Z, int s, int n, int k, cplx* lds) {
+  static_assert(BH >= 1 && BH <= 64, "one lane per row of a block");
+  constexpr int LD = BH + 1;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nw = NTQ / 64;
-  for (int i1 = k; i1 > 0; i1 -= 64) {
-    const int i0 = max(0, i1 - 64);
+  for (int i1 = k; i1 > 0; i1 -= BH) {
+    const int i0 = max(0, i1 - BH);
     const int nbk = i1 - i0;
     if (lds) {
       for (int e = tid; e < nbk * nbk; e += NTQ) {
         const int r = e % nbk, c = e / nbk;
-        lds[r * 65 + c] = Z[(i0 + r) + (size_t)(i0 + c) * s];
+        lds[r * LD + c] = Z[(i0 + r) + (size_t)(i0 + c) * s];
       }
       __syncthreads();
       for (int r = tid; r < nbk; r += NTQ) {
-        const cplx zii = lds[r * 65 + r];
-        lds[64 * 65 + r] = cabs2(zii) > 0.0 ? cinv(zii) : mkc(0, 0);
+        const cplx zii = lds[r * LD + r];
+        lds[BH * LD + r] = cabs2(zii) > 0.0 ? cinv(zii) : mkc(0, 0);
       }
       __syncthreads();
     }
@@ -137,7 +142,7 @@ __device__ void cpqr_tsolve(cplx* Z, int s, int n, int k, cplx* lds) {
         const int li = i - i0;
         if (lane == li) {
           if (lds) {
-            t = cmul(t, lds[64 * 65 + li]);
+            t = cmul(t, lds[BH * LD + li]);
           } else {
             const cplx zii = Z[i + (size_t)i * s];
             t = cabs2(zii) > 0.0 ? cmul(t, cinv(zii)) : mkc(0, 0);
@@ -149,7 +154,7 @@ __device__ void cpqr_tsolve(cplx* Z, int s, int n, int k, cplx* lds) {
         const cplx ti = mkc(__longlong_as_double(((long long)xhi << 32) | (unsigned)xlo),
                             __longlong_as_double(((long long)yhi << 32) | (unsigned)ylo));
         if (lane < li) {
-          const cplx zl = lds ? lds[lane * 65 + li] : Z[l + (size_t)i * s];
+          const cplx zl = lds ? lds[lane * LD + li] : Z[l + (size_t)i * s];
           t = csub(t, cmul(zl, ti));
         }
       }
@@ -305,7 +310,11 @@ __global__ __launch_bounds__(NTQ) void k_cpqr(const CpqrDesc* __restrict__ descs
     __syncthreads();
   }
   __syncthreads();  // v is reused as the staging area of the triangular solve
-  cpqr_tsolve<NTQ>(Z, s, n, k, MAXS >= CPQR_TS_LDS ? v : nullptr);
+  if constexpr (MAXS >= cpqr_ts_lds<64>())
+    cpqr_tsolve<NTQ, 64>(Z, s, n, k, v);
+  else
+    cpqr_tsolve<NTQ, 16>(Z, s, n, k, v);
+  static_assert(MAXS >= cpqr_ts_lds<16>(), "pivot vector too small to stage the triangular solve");
   for (int j = tid; j < n; j += NTQ) d.perm[j] = perm[j];
   if (tid == 0) k_out[blockIdx.x] = k;
 }
