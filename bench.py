@@ -144,8 +144,8 @@ class _Sub:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="wavy40")
     ap.add_argument("--tol", type=float, default=1e-13)
     ap.add_argument("--walls", choices=("compressed", "dense"), default="compressed",
