@@ -164,3 +164,20 @@ def test_gemm_tune_sweep_bounds():
             B.gemm_tune_begin(bad)
     B.gemm_tune_begin(2)
     assert B.gemm_tune_end() == {}  # nothing launched: no classes timed
+
+
+def test_gemm_tune_choose_keeps_default_within_margin():
+    """The sweep's rule: a class leaves 64 x 64 tiles only for a configuration more than the
+    margin faster; classes missing under configuration 0 keep it."""
+    from paper_1301_1247_amd.tune_gemm import choose
+    times = {0: {1: (10.0, 3), 2: (5.0, 3), 3: (1.0, 1)},
+             1: {1: (9.0, 3), 2: (4.9, 3), 3: (2.0, 1)},
+             2: {1: (9.8, 3), 2: (4.0, 3)},
+             3: {1: (11.0, 3), 2: (6.0, 3), 4: (0.5, 1)}}
+    table, rows = choose(times, margin=0.03)
+    assert table == {1: 1, 2: 2}          # 10% and 20% faster; class 3: 64 x 64 is fastest
+    assert 4 not in table                 # never timed with 64 x 64: stays on the default
+    assert [r["key"] for r in rows] == [1, 2, 3, 4]
+    assert rows[0]["ms"] == {"0": 10.0, "1": 9.0, "2": 9.8, "3": 11.0}
+    table_strict, _ = choose(times, margin=0.15)
+    assert table_strict == {2: 2}
