@@ -166,6 +166,16 @@ int build(hbs_handle* h) {
   const bool predict = h->opts.rank_predictor != 0;
   const double rscale = h->opts.rank_scale > 0 ? h->opts.rank_scale : 1.0;
   DevBuf dmodel, dfeat, dpred;
+  // predictions land in pinned host memory behind an event, so the host can build and launch a
+  // level's block and proxy evaluation (which do not depend on them) before it waits
+  struct PredHost {
+    float* p = nullptr;
+    hipEvent_t ev = nullptr;
+    ~PredHost() {
+      if (p) (void)hipHostFree(p);
+      if (ev) (void)hipEventDestroy(ev);
+    }
+  } ph;
   if (predict) {
     CK(dmodel.reserve(sizeof(float) * MLP_NPARAM));
     CK(hipMemcpyAsync(dmodel.p, h->rank_model.data(), sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, st));
@@ -491,21 +501,35 @@ int build(hbs_handle* h) {
     }
     h->feat.insert(h->feat.end(), F.begin(), F.end());
     std::vector<float> kpred;
+    // level 1 decides on the predictions whether it is compressed at all: it waits for them first
+    const bool early_pred = predict && l != 1;
     if (predict) {
-      // predicted rank -> sketch rows 1.25 k^ + 16 (at least 32, at most the full 2n + 8)
       CK(dfeat.reserve(sizeof(float) * F.size()));
       CK(dpred.reserve(sizeof(float) * nb));
       CK(hipMemcpyAsync(dfeat.p, F.data(), sizeof(float) * F.size(), hipMemcpyHostToDevice, st));
       CK(mlp_forward(dmodel.as<float>(), dfeat.as<float>(), nb, dpred.as<float>(), st));
+      if (!ph.p) {
+        CK(hipHostMalloc((void**)&ph.p, sizeof(float) * std::max(1, h->lv[L].nb), hipHostMallocDefault));
+        CK(hipEventCreateWithFlags(&ph.ev, hipEventDisableTiming));
+      }
+      CK(hipMemcpyAsync(ph.p, dpred.p, sizeof(float) * nb, hipMemcpyDeviceToHost, st));
+      CK(hipEventRecord(ph.ev, st));
+    }
+    // predicted rank -> sketch rows 1.25 k^ + 16 (at least 32, at most the full 2n + 8)
+    auto take_pred = [&]() -> int {
+      CK(hipEventSynchronize(ph.ev));
       kpred.resize(nb);
-      CK(hipMemcpyAsync(kpred.data(), dpred.p, sizeof(float) * nb, hipMemcpyDeviceToHost, st));
-      CK(hipStreamSynchronize(st));
       for (int b = 0; b < nb; ++b) {
-        const double kp = std::exp(std::min(20.0, (double)kpred[b])) * rscale;
+        const double kp = std::exp(std::min(20.0, (double)ph.p[b])) * rscale;
         kpred[b] = (float)kp;
         const int sp = (int)std::max(32.0, std::ceil(1.25 * kp) + 16.0);
         s[b] = std::min(sfull[b], sp);
       }
+      return HBS_OK;
+    };
+    if (predict && !early_pred) {
+      const int rc = take_pred();
+      if (rc != HBS_OK) return rc;
     }
     // The top level is left uncompressed (P = I, root over the level-2 skeletons) when its
     // interpolative decomposition would keep most points anyway: requested by root_level = 2, or
@@ -522,8 +546,11 @@ int build(hbs_handle* h) {
     h->top_identity = ident;
     if (ident)
       for (int b = 0; b < nb; ++b) s[b] = m[b];  // no sketch
-    for (int b = 0; b < nb; ++b) zoff[b + 1] = zoff[b] + ((s[b] < m[b]) ? (int64_t)s[b] * V.n[b] : 0);
-    h->stats.sketch_bytes_max = std::max<int64_t>(h->stats.sketch_bytes_max, (int64_t)sizeof(cplx) * zoff[nb]);
+    auto size_sketches = [&]() {
+      for (int b = 0; b < nb; ++b) zoff[b + 1] = zoff[b] + ((s[b] < m[b]) ? (int64_t)s[b] * V.n[b] : 0);
+      h->stats.sketch_bytes_max = std::max<int64_t>(h->stats.sketch_bytes_max, (int64_t)sizeof(cplx) * zoff[nb]);
+    };
+    if (!early_pred) size_sketches();
     cplx* dwt = nullptr;
     cplx* dz = nullptr;
     if (!ident) {
@@ -531,9 +558,7 @@ int build(hbs_handle* h) {
     if (noff[nb] > 0)
       CK(hipMemcpyAsync(dnear.p, hnear.data(), sizeof(int) * noff[nb], hipMemcpyHostToDevice, st));
     CK(wt.reserve(sizeof(cplx) * std::max<int64_t>(1, woff[nb])));
-    CK(zb.reserve(sizeof(cplx) * std::max<int64_t>(1, zoff[nb])));
     dwt = wt.as<cplx>();
-    dz = zb.as<cplx>();
     const int* dn = dnear.as<int>();
     {
       std::vector<BlockDesc> bd;
@@ -569,6 +594,14 @@ int build(hbs_handle* h) {
         ProfScope ps("assemble", st, 0.0, 0.0);
         CK(launch_proxy(h->geo, arena.as<ProxyDesc>(), (int)pd.size(), maxp, st));
       }
+      // the sketch sizes need the predictions
+      if (early_pred) {
+        const int rc = take_pred();
+        if (rc != HBS_OK) return rc;
+        size_sketches();
+      }
+      CK(zb.reserve(sizeof(cplx) * std::max<int64_t>(1, zoff[nb])));
+      dz = zb.as<cplx>();
       std::vector<SketchDesc> sd;
       int maxs = 0, maxn = 0;
       for (int b = 0; b < nb; ++b) {
