@@ -367,20 +367,38 @@ __global__ __launch_bounds__(256) void k_cpqrm_init(const CpqrDesc* __restrict__
   }
 }
 
+constexpr int CPQRM_RC = 24;  // rows per lane of a column held in registers (16 lanes per column)
 __global__ __launch_bounds__(256) void k_cpqrm_step(const CpqrDesc* __restrict__ descs, CpqrmWs W, int p, double tol) {
   const CpqrDesc d = descs[blockIdx.y];
   const int b = blockIdx.y, s = d.s, n = d.n;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (p >= min(s, n)) return;
-  CpqrmState* S = W.st + b;
-  if (S->done) return;
   const int slot0 = p + 1 + 16 * (int)blockIdx.x;
   if (blockIdx.x != 0 && slot0 >= n) return;
+  CpqrmState* S = W.st + b;
   const size_t o = (size_t)b * W.maxn;
   const int* pcO = ((p & 1) ? W.pcB : W.pcA) + o;
   const double* cnO = ((p & 1) ? W.cnB : W.cnA) + o;
   int* pcN = ((p & 1) ? W.pcA : W.pcB) + o;
   double* cnN = ((p & 1) ? W.cnA : W.cnB) + o;
+  // this workgroup's columns (16 lanes per column, 4 per wavefront): their rows p.. are loaded
+  // now, beside the pivot search, unless the column is the one that moves to position jp
+  const int sub = lane >> 4, rl = lane & 15;
+  const int j = slot0 + 4 * wv + sub;
+  const bool act = j < n;
+  const bool reg = s - p <= 16 * CPQRM_RC;
+  // (clamped: a box that stopped at step 0 never wrote the second map buffer; it returns below,
+  // but the prefetch must stay inside Z)
+  int phys = act ? min(max(pcO[j], 0), n - 1) : 0;
+  cplx c[CPQRM_RC];
+  if (reg) {
+#pragma unroll
+    for (int t = 0; t < CPQRM_RC; ++t) {
+      const int i = p + rl + 16 * t;
+      c[t] = (act && i < s) ? d.z[i + (size_t)phys * s] : mkc(0, 0);
+    }
+  }
+  if (S->done) return;
   __shared__ double rv[4];
   __shared__ int ri[4];
   __shared__ cplx v[CPQRM_MAXS];
@@ -429,23 +447,47 @@ __global__ __launch_bounds__(256) void k_cpqrm_step(const CpqrDesc* __restrict__
     W.alph[o + p] = alpha;
     if (p == 0) S->r00 = nr;
   }
-  // this workgroup's columns: 16 lanes per column, 4 columns per wavefront
-  const int sub = lane >> 4, rl = lane & 15;
-  const int j = slot0 + 4 * wv + sub;
-  const bool act = j < n;
-  const int phys = act ? ((j == jp) ? pq : pcO[j]) : ph;
-  cplx* col = d.z + (size_t)phys * s;
-  cplx w = mkc(0, 0);
-  if (act)
-    for (int i = p + rl; i < s; i += 16) w = cadd(w, cmul(cconj(i == p ? v0 : v[i - p]), col[i]));
-  w = cscale(row16_csum(w), tau);
-  double an = 0.0;
-  if (act)
-    for (int i = p + rl; i < s; i += 16) {
-      const cplx z = csub(col[i], cmul(w, i == p ? v0 : v[i - p]));
-      col[i] = z;
-      if (i > p) an += cabs2(z);
+  // the column at position jp is the one that was at position p
+  if (act && j == jp) {
+    phys = pq;
+    if (reg) {
+#pragma unroll
+      for (int t = 0; t < CPQRM_RC; ++t) {
+        const int i = p + rl + 16 * t;
+        c[t] = (i < s) ? d.z[i + (size_t)phys * s] : mkc(0, 0);
+      }
     }
+  }
+  cplx* col = d.z + (size_t)(act ? phys : ph) * s;
+  cplx w = mkc(0, 0);
+  double an = 0.0;
+  if (reg) {
+#pragma unroll
+    for (int t = 0; t < CPQRM_RC; ++t) {
+      const int i = p + rl + 16 * t;
+      if (act && i < s) w = cadd(w, cmul(cconj(i == p ? v0 : v[i - p]), c[t]));
+    }
+    w = cscale(row16_csum(w), tau);
+#pragma unroll
+    for (int t = 0; t < CPQRM_RC; ++t) {
+      const int i = p + rl + 16 * t;
+      if (act && i < s) {
+        const cplx z = csub(c[t], cmul(w, i == p ? v0 : v[i - p]));
+        col[i] = z;
+        if (i > p) an += cabs2(z);
+      }
+    }
+  } else {
+    if (act)
+      for (int i = p + rl; i < s; i += 16) w = cadd(w, cmul(cconj(i == p ? v0 : v[i - p]), col[i]));
+    w = cscale(row16_csum(w), tau);
+    if (act)
+      for (int i = p + rl; i < s; i += 16) {
+        const cplx z = csub(col[i], cmul(w, i == p ? v0 : v[i - p]));
+        col[i] = z;
+        if (i > p) an += cabs2(z);
+      }
+  }
   an = row16_sum(an);
   if (act && rl == 0) {
     cnN[j] = an;
