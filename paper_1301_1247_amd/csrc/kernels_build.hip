@@ -731,15 +731,34 @@ struct GjShared {
   typename cx<R>::T rowo[2][GJ_NBR];                 // row p before the step
 };
 
-// 1/a for the pivot, scaled against overflow as in cinv but with two divisions instead of four
-// (the inverse is on the dependent chain of every pivot step); 0 for a = 0
+// 1/x from the hardware reciprocal refined by Newton steps (r <- r + r (1 - x r)); x normal
+__device__ __forceinline__ double gj_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float gj_rcp(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// 1/a for the pivot, scaled against overflow as in cinv (the inverse is on the dependent chain of
+// every pivot step, so it takes reciprocals refined by Newton steps instead of divisions; the
+// scaled modulus lies in [1, 2]); 0 for a = 0.  Pivots of extreme scale take the divisions.
 template <class R>
 __device__ __forceinline__ typename cx<R>::T gj_recip(typename cx<R>::T a) {
   const R sc = fmax(fabs(a.x), fabs(a.y));
   if (!(sc > 0)) return cx<R>::make(0.0, 0.0);
-  const R is = R(1) / sc;
+  constexpr R lo = sizeof(R) == 8 ? R(1e-300) : R(1e-35), hi = sizeof(R) == 8 ? R(1e300) : R(1e35);
+  if (sc < lo || sc > hi) {
+    const R is = R(1) / sc;
+    const R ar = a.x * is, ai = a.y * is;
+    const R q = is / (ar * ar + ai * ai);
+    return cx<R>::make(ar * q, -ai * q);
+  }
+  const R is = gj_rcp(sc);
   const R ar = a.x * is, ai = a.y * is;
-  const R q = is / (ar * ar + ai * ai);
+  const R q = is * gj_rcp(ar * ar + ai * ai);
   return cx<R>::make(ar * q, -ai * q);
 }
 
