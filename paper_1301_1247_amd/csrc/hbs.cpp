@@ -172,6 +172,7 @@ int build(hbs_handle* h) {
     float* p = nullptr;
     hipEvent_t ev = nullptr;
     ~PredHost() {
+      if (ev) (void)hipEventSynchronize(ev);  // a copy into p may still be in flight after an error
       if (p) (void)hipHostFree(p);
       if (ev) (void)hipEventDestroy(ev);
     }
