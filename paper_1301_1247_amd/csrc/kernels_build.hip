@@ -8,7 +8,7 @@ namespace {
 constexpr int NT = 256;  // threads per workgroup (4 wavefronts)
 
 // ---------------------------------------------------------------- block evaluation
-__global__ __launch_bounds__(NT) void k_eval_blocks(Geo G, const BlockDesc* __restrict__ descs) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_blocks(Geo G, const BlockDesc* __restrict__ descs) {
   const BlockDesc d = descs[blockIdx.y];
   const int total = d.nr * d.nc;
   for (int e = blockIdx.x * NT + threadIdx.x; e < total; e += gridDim.x * NT) {
