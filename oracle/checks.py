@@ -1,0 +1,74 @@
+"""Checks of a computed solution at sizes where the dense oracle does not fit (oracle side).
+
+TEST INFRASTRUCTURE ONLY (like the rest of ``oracle/``).
+
+At N = 1e5 the dense Nystrom matrix needs 160 GB, so a solution (eta, xi) of the bordered
+system of Eq. 2.19 is judged by sampled rows of its residual
+
+    r1 = A~ eta + B xi - b     (rows of the obstacle block: Sec. 2.2, discretized as in Sec. 2.3)
+    r2 = C eta + Q xi          (every wall row: Eqs. 2.17-2.18 on the Sommerfeld contour)
+
+with exact dense rows of A (``nystrom.matrix_kr6_rows``), B and b on the sampled nodes and all of
+C and Q (accumulated over node chunks), and by the energy balance of Remark 6.1.  The residual is
+relative to |b|, with the sampled obstacle rows scaled up to all N rows; it is a residual of the
+bordered system, not a forward error.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import nystrom
+from . import periodic
+
+
+class RowSubset:
+    """The nodes ``rows`` of a discretization (for B, b and C restricted to them)."""
+
+    def __init__(self, disc: nystrom.Discretization, rows):
+        rows = np.asarray(rows)
+        self.x = disc.x[rows]
+        self.nrm = disc.nrm[rows]
+        self.w = disc.w[rows]
+
+
+def bordered_residual(curve, N, omega, period, thetas, eta, xi, flux=None, n_rows=48, n_ang=8, chunk=4000,
+                      seed=7, angles=None):
+    """Sampled relative residual of the bordered system (P = 0, KR6 quadrature) for the solutions
+    eta (N x n) and xi (2M x n) of the angles ``thetas`` (n), M from the default contour.
+
+    n_rows obstacle rows and n_ang angles are drawn from rng(seed) (or ``angles`` given).
+    Returns dict(sampled_rel_residual = max over the sampled angles of
+    sqrt(|r1|^2 N / n_rows + |r2|^2) / |b|, flux_err_max over every angle when ``flux`` is given,
+    rows_sampled, angles_sampled)."""
+    disc = nystrom.Discretization(curve, N)
+    ct = periodic.default_contour(disc, omega, period)
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(N, n_rows, replace=False))
+    angs = np.asarray(angles) if angles is not None else rng.choice(len(thetas), n_ang, replace=False)
+    Arows = nystrom.matrix_kr6_rows(disc, omega, rows)
+    sub = RowSubset(disc, rows)
+    BL, BR = periodic.wall_B(sub, omega, period, ct)
+    eta_s = eta[:, angs]
+    CLe = 0
+    CRe = 0
+    for c0 in range(0, N, chunk):
+        sl = np.arange(c0, min(N, c0 + chunk))
+        CL, CR = periodic.wall_C(RowSubset(disc, sl), omega, period, ct)
+        CLe = CLe + CL @ eta_s[sl]
+        CRe = CRe + CR @ eta_s[sl]
+    worst = 0.0
+    for q, a in enumerate(angs):
+        th = thetas[a]
+        al = periodic.bloch_phase(omega, period, th)
+        x = xi[:, a]
+        b = periodic.incident(sub, omega, th)[:, 0]
+        r1 = Arows @ eta_s[:, q] + (BL + al * BR) @ x - b
+        r2 = CLe[:, q] - CRe[:, q] / al + periodic.wall_Q(omega, period, al, ct) @ x
+        bn = np.linalg.norm(periodic.incident(disc, omega, th))
+        worst = max(worst, math.sqrt(np.sum(np.abs(r1) ** 2) * N / n_rows + np.sum(np.abs(r2) ** 2)) / bn)
+    out = {"sampled_rel_residual": float(worst), "rows_sampled": int(n_rows), "angles_sampled": int(len(angs))}
+    if flux is not None:
+        out["flux_err_max"] = float(np.max(flux))
+    return out

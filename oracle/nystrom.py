@@ -72,6 +72,21 @@ def matrix_kr6(disc: Discretization, omega: float) -> np.ndarray:
     return A
 
 
+def matrix_kr6_rows(disc: Discretization, omega: float, rows) -> np.ndarray:
+    """Rows ``rows`` of the Kapur-Rokhlin matrix of ``matrix_kr6`` (Sec. 2.3), evaluated without
+    forming the other rows: A[r, j] = delta_rj/2 + R_{(r-j) mod N} K(y_r, y_j, n_j) w_j."""
+    N = disc.N
+    rows = np.asarray(rows, dtype=np.int64).reshape(-1)
+    R = quadrature.kr6_band(N)
+    idx = np.arange(N)
+    K = kernel(omega, disc.x[rows], disc.x, disc.nrm)
+    same = rows[:, None] == idx[None, :]
+    K[same] = 0.0
+    A = R[(rows[:, None] - idx[None, :]) % N] * K * disc.w[None, :]
+    A[np.arange(len(rows)), rows] += 0.5
+    return A
+
+
 def matrix_kress(disc: Discretization, omega: float) -> np.ndarray:
     """A with Kress' spectral log-split quadrature (Colton & Kress, Sec. 3.5), N = 2n.
 

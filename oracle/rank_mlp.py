@@ -95,3 +95,45 @@ def init(x, seed=0):
                  "W1": rng.standard_normal((N_H, N_IN)) / np.sqrt(N_IN), "b1": np.zeros(N_H),
                  "W2": rng.standard_normal((N_H, N_H)) / np.sqrt(N_H), "b2": np.zeros(N_H),
                  "W3": rng.standard_normal(N_H) / np.sqrt(N_H), "b3": np.zeros(1)})
+
+
+# ---------------------------------------------------------------- training (Adam)
+# Adam (Kingma & Ba, "Adam: a method for stochastic optimization", 2015, Algorithm 1) with the
+# constants the predictor is trained with.  Only the weights and biases are trained: the input
+# normalisation mu, sd (the first 32 entries of the parameter vector) stays fixed.
+ADAM_BETA1 = 0.9
+ADAM_BETA2 = 0.999
+ADAM_EPS = 1e-8
+N_FIXED = 2 * N_IN
+
+
+def adam_step(p, g, m, v, step, lr):
+    """One Adam update of the trainable entries p[N_FIXED:] for gradient g at step number
+    ``step`` (1 for the first update).  Returns new (p, m, v); the inputs are not modified.
+
+      m <- b1 m + (1 - b1) g,   v <- b2 v + (1 - b2) g^2
+      p <- p - lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps)
+    """
+    p = np.array(p, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    m = ADAM_BETA1 * np.asarray(m, dtype=np.float64) + (1.0 - ADAM_BETA1) * g
+    v = ADAM_BETA2 * np.asarray(v, dtype=np.float64) + (1.0 - ADAM_BETA2) * g * g
+    mhat = m / (1.0 - ADAM_BETA1 ** step)
+    vhat = v / (1.0 - ADAM_BETA2 ** step)
+    p[N_FIXED:] -= lr * mhat[N_FIXED:] / (np.sqrt(vhat[N_FIXED:]) + ADAM_EPS)
+    return p, m, v
+
+
+def train(p, x, t, tau, steps, lr):
+    """Full-batch Adam on the mean pinball loss (the summed loss of ``loss`` divided by the
+    sample count), starting from zero moments.  Returns the final parameters and the mean loss
+    before each step."""
+    n = len(t)
+    p = np.array(p, dtype=np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    hist = []
+    for it in range(1, steps + 1):
+        hist.append(loss(p, x, t, tau) / n)
+        p, m, v = adam_step(p, grad(p, x, t, tau) / n, m, v, it, lr)
+    return p, np.array(hist)

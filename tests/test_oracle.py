@@ -209,3 +209,46 @@ def test_planted_missing_end_correction_fails_circle(monkeypatch):
     A = ny.matrix(d, 10.0, "kr6")
     v = np.ones(d.N)
     assert np.abs(A @ v - ny.circle_eigenvalue(10.0, 1.0, 0) * v).max() > 1e-3
+
+
+# ---------------------------------------------------------------- row blocks and the residual checker
+
+def test_kr6_rows_equal_full_matrix_rows():
+    c = qpinputs.wavy(130102, 20, 0.3)
+    disc = ny.Discretization(c, 400)
+    A = ny.matrix_kr6(disc, 40.0)
+    rows = np.array([0, 1, 7, 199, 398, 399])
+    assert np.array_equal(ny.matrix_kr6_rows(disc, 40.0, rows), A[rows])
+
+
+@pytest.fixture(scope="module")
+def wavy_kr6_qp():
+    """A KR6 solution at N = 600 of a rough obstacle, for the residual checker."""
+    from oracle import checks  # noqa: F401
+    c = qpinputs.wavy(130103, 40, 0.2)
+    N, om, d = 600, 12.0, 2 * math.pi
+    th = np.array([-0.7, -1.1, -1.3])
+    r = pq.solve_qp(c, N, om, d, th, quad="kr6")
+    return c, N, om, d, th, r
+
+
+def test_residual_checker_small_for_the_exact_solution(wavy_kr6_qp):
+    from oracle import checks
+    c, N, om, d, th, r = wavy_kr6_qp
+    v = checks.bordered_residual(c, N, om, d, th, r["eta"], r["xi"], r["flux"], n_rows=40, n_ang=3, chunk=250)
+    assert v["sampled_rel_residual"] < 1e-12
+    assert v["angles_sampled"] == 3
+
+
+def test_residual_checker_sees_planted_errors(wavy_kr6_qp):
+    """A perturbation of one obstacle density value or of one wall density value shows in the
+    sampled residual at about its own size (all wall rows are checked; the obstacle column of a
+    perturbed node reaches every row through the kernel)."""
+    from oracle import checks
+    c, N, om, d, th, r = wavy_kr6_qp
+    scale = np.linalg.norm(pq.incident(ny.Discretization(c, N), om, th[0]))
+    for which in ("eta", "xi"):
+        eta, xi = r["eta"].copy(), r["xi"].copy()
+        (eta if which == "eta" else xi)[17, :] += 1e-6 * scale
+        v = checks.bordered_residual(c, N, om, d, th, eta, xi, n_rows=40, n_ang=3, chunk=250)
+        assert v["sampled_rel_residual"] > 1e-9, which
