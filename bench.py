@@ -90,55 +90,12 @@ def cpu_baseline(wl, n_sample=2000, q_sample=2):
                       f"to N={wl.N}, M={Mf}"}
 
 
-def verify(wl, res, n_rows=48, n_ang=6, chunk=4000):
-    """Sampled rows of the bordered-system residual [A B; C Q][eta; xi] - [b; 0] with the oracle's
-    kernels (exact dense rows of A and B; all rows of C and Q, accumulated over node chunks),
-    relative to |b|, plus the flux error of every angle."""
-    import numpy as np
-    from oracle import nystrom as ny
-    from oracle import periodic as pq
-    from oracle import quadrature as qd
-
-    disc = ny.Discretization(wl.curve, wl.N)
-    ct = pq.default_contour(disc, wl.omega, wl.period)
-    rng = np.random.default_rng(7)
-    rows = np.sort(rng.choice(wl.N, n_rows, replace=False))
-    angs = rng.choice(len(wl.thetas), n_ang, replace=False)
-    R = qd.kr6_band(wl.N)
-    K = ny.kernel(wl.omega, disc.x[rows], disc.x, disc.nrm)
-    idx = np.arange(wl.N)
-    Arows = R[(rows[:, None] - idx[None, :]) % wl.N] * np.where(rows[:, None] == idx[None, :], 0, K) * disc.w[None, :]
-    Arows[np.arange(n_rows), rows] += 0.5
-    BL, BR = pq.wall_B(_Sub(disc, rows), wl.omega, wl.period, ct)
-    eta = res["eta"][:, angs]
-    CLe = 0
-    CRe = 0
-    for c0 in range(0, wl.N, chunk):
-        sl = np.arange(c0, min(wl.N, c0 + chunk))
-        CL, CR = pq.wall_C(_Sub(disc, sl), wl.omega, wl.period, ct)
-        CLe = CLe + CL @ eta[sl]
-        CRe = CRe + CR @ eta[sl]
-    worst = 0.0
-    for q, a in enumerate(angs):
-        th = wl.thetas[a]
-        al = pq.bloch_phase(wl.omega, wl.period, th)
-        xi = res["xi"][:, a]
-        b = pq.incident(_Sub(disc, rows), wl.omega, th)[:, 0]
-        r1 = Arows @ eta[:, q] + (BL + al * BR) @ xi - b
-        r2 = CLe[:, q] - CRe[:, q] / al + pq.wall_Q(wl.omega, wl.period, al, ct) @ xi
-        bn = np.linalg.norm(pq.incident(disc, wl.omega, th))
-        worst = max(worst, math.sqrt(np.sum(np.abs(r1) ** 2) * wl.N / n_rows + np.sum(np.abs(r2) ** 2)) / bn)
-    return {"sampled_rel_residual": worst, "flux_err_max": float(np.max(res["flux"])),
-            "rows_sampled": n_rows, "angles_sampled": n_ang}
-
-
-class _Sub:
-    """Row subset of a discretization (for evaluating B and b on sampled nodes)."""
-
-    def __init__(self, disc, rows):
-        self.x = disc.x[rows]
-        self.nrm = disc.nrm[rows]
-        self.w = disc.w[rows]
+def verify(wl, res, n_rows=48, n_ang=8):
+    """Sampled rows of the bordered-system residual of the timed solution, by the oracle's
+    checker (exact dense rows of A and B, all rows of C and Q), plus the flux error of every angle."""
+    from oracle import checks
+    return checks.bordered_residual(wl.curve, wl.N, wl.omega, wl.period, wl.thetas, res["eta"], res["xi"],
+                                    res["flux"], n_rows=n_rows, n_ang=n_ang)
 
 
 def main():
@@ -156,18 +113,7 @@ def main():
                     help="fp32: complex64 inverse factors as a preconditioner, FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
-    ap.add_argument("--copy-probe", type=int, default=0,
-                    help="only run a plain device copy of this many bytes (calibrates HBM byte counters)")
     args = ap.parse_args()
-    if args.copy_probe:
-        import torch
-        src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 3}), flush=True)
-        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the sharding design is described in DESIGN.md", file=sys.stderr)

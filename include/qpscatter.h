@@ -88,6 +88,11 @@ typedef struct {
                                applies inside qp_solve) is captured into a HIP graph on a private
                                stream and replayed while a later call uses the same operands and
                                workspaces (up to 4 captured operand sets per handle); 0 = off */
+  uint64_t mem_limit;       /* > 0: largest number of device bytes the handle may hold at once, its
+                               factors and the workspaces of the calls made on it together (buffers
+                               are counted at the size requested from the library's pool); a call
+                               that would exceed it fails with HBS_E_OOM before allocating, and
+                               hbs_last_error names the limit.  0 = no limit */
 } hbs_opts;
 
 typedef struct {
@@ -98,7 +103,8 @@ typedef struct {
   double h;                 /* contour spacing; 0 -> 0.1 */
   double ca, cb;            /* contour k(t) = t - i ca tanh(t / cb); 0 -> 1, 1 */
   double y0;                /* Bragg reference height; 0 -> max|y| + 0.5 */
-  double wood_min_kn;       /* refuse angles with min_n |k_n| below this; 0 -> 0.75 */
+  double wood_min_kn;       /* angles with min_n |k_n| below this are within reach of a Wood's
+                               anomaly (the undisplaced contour loses accuracy there); 0 -> 0.75 */
   int32_t refine_max_iter;  /* iterative refinement steps of the bordered system; <0 -> 0,
                                0 -> 2 (3 for a handle built with HBS_FP32_PRECOND) */
   double refine_tol;        /* stop when the relative residual is below; 0 -> 1e-13 */
@@ -109,6 +115,19 @@ typedef struct {
                                Then A^{-1} is applied to root-size + q columns instead of 4M + q and
                                no N-sized Schur product is formed.  0 = when valid, 1 = required
                                (HBS_E_INVALID_ARG otherwise), -1 = never */
+  int32_t wood;             /* angles within wood_min_kn of a Wood's anomaly (Sec. 2.4, second
+                               improvement): 0 = solve them on the Sommerfeld contour displaced to cross
+                               the real axis at wood_shift, with one added Rayleigh-Bloch wave and one
+                               no-incoming-radiation row per order whose pole the contour crossed (the
+                               angles of each Bloch phase in one extra pass); -1 = refuse (HBS_E_WOOD).
+                               Their xi holds the densities at the displaced contour's nodes */
+  double wood_shift;        /* real-axis crossing of the displaced contour; 0 -> chosen per Bloch phase
+                               in [0.25, 3] to keep every pole +-k_n farthest from the real axis of the
+                               contour's parameter t */
+  int32_t wood_samples;     /* samples on y = -y0 of the radiation rows' Fourier coefficients; 0 -> the
+                               smallest count >= 64 whose aliases of the propagating orders decay by
+                               e^-37 between y = -y0 and the obstacle:
+                               (omega + sqrt(omega^2 + (37 / (y0 - max|y|))^2)) d / (2 pi) */
 } qp_opts;
 
 typedef struct {
@@ -131,6 +150,10 @@ typedef struct {
   int32_t root_level;       /* 1 or 2 (see hbs_opts.root_level) */
   int64_t graph_captures;   /* applies captured into HIP graphs (hbs_opts.graph) */
   int64_t graph_replays;    /* applies served by replaying a captured graph */
+  int64_t device_bytes_peak;/* largest device bytes held at once by the handle and its calls */
+  int32_t wood_angles;      /* angles of the last qp_solve solved on a displaced contour */
+  int32_t wood_orders;      /* Rayleigh-Bloch waves added for them (summed over Bloch phases) */
+  double wood_shift;        /* real-axis crossing of the last displaced contour (0 = none) */
 } hbs_stats_t;
 
 void hbs_opts_init(hbs_opts* o);
@@ -165,10 +188,10 @@ int hbs_forward(hbs_handle* h, const double* x, int64_t nrhs, double* out);
  * refinement of the bordered system.
  *   eta      N x q complex   obstacle densities (required)
  *   xi       2M x q complex  wall densities [mu; nu] (nullable)
- *   bragg    2 x n_modes x q complex: c_n then d_n for n = nlo..nlo+n_modes-1 (nullable); the
- *            propagating orders of each angle, n_modes_out[q] and nlo_out[q] tell the range
- *   flux_err q doubles, energy-balance error of Remark 6.1 (nullable)
- * bragg must hold 2 * qp_max_modes(omega, d) * q complex values. */
+ *   bragg    (2 mx) x q complex, mx = qp_max_modes(omega, d) (nullable): for angle a, rows
+ *            0..n_modes_out[a]-1 hold c_n (Eq. 2.5) and rows mx..mx+n_modes_out[a]-1 hold d_n
+ *            (Eq. 2.6) of the propagating orders n = nlo_out[a], nlo_out[a]+1, ...; other rows unset
+ *   flux_err q doubles, energy-balance error of Remark 6.1 (nullable) */
 int qp_solve(hbs_handle* h, double period, double alpha_re, double alpha_im, const double* thetas,
              int64_t q, const qp_opts* opts, double* eta, double* xi, double* bragg,
              int32_t* nlo_out, int32_t* n_modes_out, double* flux_err);
@@ -250,7 +273,7 @@ int qps_profile_read(const char* family, double* ms, int64_t* launches, double* 
 
 /* Tile configurations of the batched complex GEMM that carries every block product of the
  * factorization and its application (the per-level products of the telescoping factorization,
- * Sec. 3, and the Schur products of the periodizing step, Sec. 4).  Configuration c:
+ * Sec. 4, and the Schur products of the block solve of the periodizing step, Sec. 3).  Configuration c:
  * 0 = 64 x 64 output tiles (2 x 2 wavefronts), 1 = 32 x 32 (one wavefront), 2 = 64 x 32 (2 x 1),
  * 3 = 32 x 64 (1 x 2).  Each launch picks one from its shape class through a tuning table; all
  * configurations give bitwise equal results, so the table affects run time only.

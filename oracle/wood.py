@@ -29,8 +29,10 @@ Readings (the paper gives the idea, not the formulas):
   is U_n(y) = A+ e^{i k_n y} + A- e^{-i k_n y}; the up-going (incoming from below, or growing
   downward) part A+ vanishes iff i k_n U_n(-y0) + U_n'(-y0) = 0.  U_n and U_n' are taken, as in
   Remark 2.3, from samples of the representation and of its y-derivative at ns equispaced points
-  x_l = -d/2 + (l + 1/2) d / ns on y = -y0 and a discrete Fourier transform.  At an exact anomaly
-  (k_n = 0) the row states U_n'(-y0) = 0 (no linearly growing term).
+  x_l = -d/2 + (l + 1/2) d / ns on y = -y0 and a discrete Fourier transform, with ns large enough
+  that the aliases of every propagating order decay by e^-37 between the line and the obstacle
+  (``default_samples``).  At an exact anomaly (k_n = 0) the row states U_n'(-y0) = 0 (no linearly
+  growing term).
 * Choice of delta: the value in [0.25, 3] (step 0.05) that keeps every pole +-k_n of the angle's
   orders farthest from the real axis of the contour's parameter plane (the trapezoid rule in t loses
   about exp(-2 pi dist / h)); the displaced contour's t-range is that of the undisplaced one (the
@@ -146,6 +148,14 @@ def sample_points(period, ns, y):
     return np.stack([xl, np.full(ns, y)], axis=1)
 
 
+def default_samples(disc, omega, period, y0):
+    """Samples of the radiation rows' Fourier coefficients: at least 64, and enough that the alias
+    kappa_n + 2 pi ns / d of every propagating order decays by e^-37 over the gap g between y = -y0
+    and the obstacle: 2 pi ns / d - omega >= sqrt(omega^2 + (37 / g)^2)."""
+    g = y0 - float(np.max(np.abs(disc.x[:, 1])))
+    return max(64, int(math.ceil((omega + math.sqrt(omega ** 2 + (37.0 / g) ** 2)) * period / (2 * math.pi))))
+
+
 def radiation_rows(disc, omega, period, alpha, ct, crossed, y0, ns=64, P=0):
     """Rows (c x N for eta, c x 2M for xi) of the radiation conditions of the crossed orders:
     row . [eta; xi] = i k_n U_n(-y0) + U_n'(-y0) of the representation of Eq. 2.14 (Eq. 2.20 with P
@@ -185,7 +195,7 @@ def radiation_of_waves(crossed, y0):
     return np.diag([2j * kn * np.exp(-1j * kn * y0) for (n, kx, kn) in crossed]).astype(complex)
 
 
-def solve_wood(disc, omega, period, theta, P=0, quad="kr6", h=0.1, a=1.0, b=1.0, delta=None, ns=64, A0=None,
+def solve_wood(disc, omega, period, theta, P=0, quad="kr6", h=0.1, a=1.0, b=1.0, delta=None, ns=None, A0=None,
                crossed=None, y0=None):
     """Dense LU of the bordered system on the displaced contour with the added waves and radiation
     rows: [[A~, B, Phi], [C~, Q, 0], [R_eta, R_xi, R_phi]] [eta; xi; a] = [b; 0; 0]."""
@@ -199,6 +209,8 @@ def solve_wood(disc, omega, period, theta, P=0, quad="kr6", h=0.1, a=1.0, b=1.0,
         crossed = crossed_orders(omega, period, theta, delta, a, b)
     if y0 is None:
         y0 = periodic.default_y0(disc)
+    if ns is None:
+        ns = default_samples(disc, omega, period, y0)
     sysm = periodic.assemble(disc, omega, period, al, ct, P=P, quad=quad, A0=A0)
     Phi = plane_waves(disc, crossed)
     Re, Rx = radiation_rows(disc, omega, period, al, ct, crossed, y0, ns, P)

@@ -40,13 +40,14 @@ class HbsOpts(C.Structure):
                 ("curvature", C.c_void_p), ("stream", C.c_void_p), ("seed", C.c_uint64),
                 ("far_radius", C.c_double), ("precision", C.c_int32), ("fp64_top_levels", C.c_int32),
                 ("rank_predictor", C.c_int32), ("rank_scale", C.c_double), ("rank_model", C.c_void_p),
-                ("root_level", C.c_int32), ("graph", C.c_int32)]
+                ("root_level", C.c_int32), ("graph", C.c_int32), ("mem_limit", C.c_uint64)]
 
 
 class QpOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("P", C.c_int32), ("M", C.c_int32), ("K", C.c_double), ("h", C.c_double),
                 ("ca", C.c_double), ("cb", C.c_double), ("y0", C.c_double), ("wood_min_kn", C.c_double),
-                ("refine_max_iter", C.c_int32), ("refine_tol", C.c_double), ("compress_walls", C.c_int32)]
+                ("refine_max_iter", C.c_int32), ("refine_tol", C.c_double), ("compress_walls", C.c_int32),
+                ("wood", C.c_int32), ("wood_shift", C.c_double), ("wood_samples", C.c_int32)]
 
 
 class HbsStats(C.Structure):
@@ -56,7 +57,8 @@ class HbsStats(C.Structure):
                 ("refine_iters", C.c_int32), ("refine_residual", C.c_double), ("contour_M", C.c_int32),
                 ("walls_compressed", C.c_int32), ("rank_fallbacks", C.c_int32), ("sketch_bytes_max", C.c_int64),
                 ("cpqr_work", C.c_double), ("root_level", C.c_int32), ("graph_captures", C.c_int64),
-                ("graph_replays", C.c_int64)]
+                ("graph_replays", C.c_int64), ("device_bytes_peak", C.c_int64), ("wood_angles", C.c_int32),
+                ("wood_orders", C.c_int32), ("wood_shift", C.c_double)]
 
 
 _P = C.c_void_p
@@ -154,7 +156,7 @@ class Handle:
     def __init__(self, nodes, weights, normals, omega, tol, quad="kr6", compress=None, leaf_size=64,
                  curvature=None, device=False, stream=None, proxy_ratio=2.0, proxy_min=64, seed=0x5EED1301,
                  far_radius=0.0, precision="fp64", fp64_top_levels=0, rank_predictor=False, rank_scale=1.0,
-                 rank_model=None, root_level=0, graph=False):
+                 rank_model=None, root_level=0, graph=False, mem_limit=0):
         if compress is None:
             compress = "exact" if quad == "kress" else "proxy"
         self.device = bool(device)
@@ -180,7 +182,7 @@ class Handle:
                      curvature=_ptr(curvature), stream=st, seed=int(seed), far_radius=float(far_radius),
                      precision={"fp64": 0, "fp32": 1}[precision], fp64_top_levels=int(fp64_top_levels),
                      rank_predictor=1 if rank_predictor else 0, rank_scale=float(rank_scale),
-                     root_level=int(root_level), graph=1 if graph else 0)
+                     root_level=int(root_level), graph=1 if graph else 0, mem_limit=int(mem_limit))
         if rank_model is not None:
             rank_model = np.ascontiguousarray(rank_model, dtype=np.float32)
             o.rank_model = rank_model.ctypes.data
@@ -193,9 +195,11 @@ class Handle:
     def __del__(self):
         self.free()
 
-    def free(self):
+    def free(self, _free=_lib.hbs_free):
+        # the library function is bound at definition time: at interpreter shutdown the module's
+        # globals may already be cleared when the last handles are collected
         if getattr(self, "_h", None) is not None and self._h.value:
-            _lib.hbs_free(self._h)
+            _free(self._h)
             self._h = None
 
     # -- apply / forward

@@ -120,6 +120,18 @@ int fetch(const double* p, int64_t n, int mode, std::vector<double>& out) {
 
 using namespace qps;
 
+// A call that failed for want of memory because the handle's mem_limit refused a reservation
+// says so (the HIP error text alone would suggest the device ran out).
+static int budget_status(hbs_handle* h, int code) {
+  if (code == HBS_E_OOM && h && h->budget.refused > 0) {
+    set_error("mem_limit of " + std::to_string(h->budget.limit) + " device bytes exceeded: " +
+              std::to_string(h->budget.used) + " held, " + std::to_string(h->budget.refused) + " more requested (" +
+              last_error() + ")");
+  }
+  if (h) h->budget.refused = 0;
+  return code;
+}
+
 extern "C" {
 
 void hbs_opts_init(hbs_opts* o) {
@@ -207,6 +219,8 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
     if (std::fabs(nn - 1.0) > 1e-8) { set_error("hbs_build: normals must have unit length"); return HBS_E_INVALID_ARG; }
   }
   hbs_handle* h = new hbs_handle();
+  h->budget.limit = (size_t)o.mem_limit;
+  BudgetScope bscope(&h->budget);
   h->N = N;
   h->omega = omega;
   h->tol = tol;
@@ -221,7 +235,11 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
   }
   h->hw = w;
   h->hkap = kap;
-  auto fail = [&](int code) { delete h; return code; };
+  auto fail = [&](int code) {
+    code = budget_status(h, code);
+    delete h;
+    return code;
+  };
   const int nf = (o.quad == HBS_QUAD_KRESS) ? 6 : 5;
   if (h->dgeo.reserve(sizeof(double) * N * nf) != hipSuccess) { set_error("hbs_build: out of device memory"); return fail(HBS_E_OOM); }
   double* g = h->dgeo.as<double>();
@@ -260,9 +278,14 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
   return HBS_OK;
 }
 
+static int apply_common_(hbs_handle* h, const double* in, int64_t nrhs, double* outp, bool inverse, int refine);
 static int apply_common(hbs_handle* h, const double* in, int64_t nrhs, double* outp, bool inverse, int refine) {
   clear_error();
   if (!h || !in || !outp || nrhs < 0) { set_error("hbs_apply: bad arguments"); return HBS_E_INVALID_ARG; }
+  BudgetScope bscope(&h->budget);
+  return budget_status(h, apply_common_(h, in, nrhs, outp, inverse, refine));
+}
+static int apply_common_(hbs_handle* h, const double* in, int64_t nrhs, double* outp, bool inverse, int refine) {
   if (nrhs == 0) return HBS_OK;
   if (in == outp) { set_error("hbs_apply: rhs and out may not alias"); return HBS_E_INVALID_ARG; }
   hipStream_t st = h->stream;
@@ -315,10 +338,17 @@ int hbs_forward(hbs_handle* h, const double* x, int64_t nrhs, double* out) {
   return apply_common(h, x, nrhs, out, false, 0);
 }
 
+static int qp_common_(hbs_handle* h, double period, const double* thetas, int64_t n, const qp_opts* opts, bool check,
+                      double are, double aim, double* eta, double* xi, double* bragg, int32_t* nlo, int32_t* nm, double* flux);
 static int qp_common(hbs_handle* h, double period, const double* thetas, int64_t n, const qp_opts* opts, bool check,
                      double are, double aim, double* eta, double* xi, double* bragg, int32_t* nlo, int32_t* nm, double* flux) {
   clear_error();
   if (!h || !thetas || !eta || n <= 0) { set_error("qp_solve: bad arguments"); return HBS_E_INVALID_ARG; }
+  BudgetScope bscope(&h->budget);
+  return budget_status(h, qp_common_(h, period, thetas, n, opts, check, are, aim, eta, xi, bragg, nlo, nm, flux));
+}
+static int qp_common_(hbs_handle* h, double period, const double* thetas, int64_t n, const qp_opts* opts, bool check,
+                      double are, double aim, double* eta, double* xi, double* bragg, int32_t* nlo, int32_t* nm, double* flux) {
   qp_opts o;
   qp_opts_init(&o);
   if (opts) {
@@ -326,6 +356,12 @@ static int qp_common(hbs_handle* h, double period, const double* thetas, int64_t
     o = *opts;
   }
   if (!(period > 0) || !std::isfinite(period)) { set_error("qp_solve: period must be positive"); return HBS_E_INVALID_ARG; }
+  if (o.wood != 0 && o.wood != -1) { set_error("qp_solve: wood must be 0 or -1"); return HBS_E_INVALID_ARG; }
+  if (!(o.wood_shift >= 0) || !(o.wood_shift < h->omega)) {
+    set_error("qp_solve: wood_shift must lie in [0, omega)");
+    return HBS_E_INVALID_ARG;
+  }
+  if (o.wood_samples < 0 || o.wood_samples > 8192) { set_error("qp_solve: wood_samples must lie in [0, 8192]"); return HBS_E_INVALID_ARG; }
   std::vector<double> th;
   int r = fetch(thetas, n, h->opts.ptr_mode, th);
   if (r != HBS_OK) return r;
@@ -410,6 +446,7 @@ int hbs_stats(const hbs_handle* h, hbs_stats_t* s) {
   s->root_level = h->top_identity ? 2 : 1;
   s->graph_captures = h->graph_captures;
   s->graph_replays = h->graph_replays;
+  s->device_bytes_peak = (int64_t)h->budget.peak;
   return HBS_OK;
 }
 

@@ -1,5 +1,6 @@
 // The solver handle: geometry, tree, per-level skeletonization factors, periodizing cache.
 #pragma once
+#include <complex>
 #include "internal.h"
 
 #include <memory>
@@ -42,6 +43,8 @@ struct ApplyGraph {
 
 struct hbs_handle {
   ~hbs_handle();
+  // declared first, so destroyed after every buffer charged to it
+  qps::MemBudget budget;
   int64_t N = 0;
   double omega = 0, tol = 0;
   hbs_opts opts{};
@@ -105,6 +108,16 @@ int apply_inverse_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64
 int side_stream_init(hbs_handle* h);
 int qp_max_modes_impl(double om, double period);
 struct QPPlan;
+// Columns of the Wood's-anomaly scheme (Sec. 2.4): plane waves -exp(i (kx x + ky y)), ky complex, sharing
+// the Bloch phase alpha, on the contour displaced to cross the real axis at delta.
+struct QPCols {
+  double delta = 0.0;
+  std::complex<double> alpha{1.0, 0.0};
+  std::vector<double> kx;
+  std::vector<std::complex<double>> ky;
+};
+int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, const qp_opts* o, const QPCols* cols,
+                  cplx* eta_out, cplx* xi_out, cplx* bragg_out, int32_t* nlo_out, int32_t* nm_out, double* flux_out);
 int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, const qp_opts* o, cplx* eta_out,
                   cplx* xi_out, cplx* bragg_out, int32_t* nlo_out, int32_t* nm_out, double* flux_out);
 int qp_contour_M(const hbs_handle* h, double period, const qp_opts* o);

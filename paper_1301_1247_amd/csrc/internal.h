@@ -90,15 +90,33 @@ struct CopyDesc {
 
 namespace qps {
 
-// device buffer that grows on demand
+// Device-memory budget of a handle (hbs_opts.mem_limit): every buffer reserved while the budget
+// is current on the calling thread is charged to it until released; a reservation that would take
+// the charged bytes above the limit fails with hipErrorOutOfMemory before any allocation.
+struct MemBudget {
+  size_t limit = 0;      // 0 = no limit
+  size_t used = 0;       // bytes of the live buffers charged to the budget
+  size_t peak = 0;
+  size_t refused = 0;    // size of the last refused reservation (0 = none)
+};
+MemBudget*& current_budget();
+struct BudgetScope {
+  MemBudget* prev;
+  explicit BudgetScope(MemBudget* b) : prev(current_budget()) { current_budget() = b; }
+  ~BudgetScope() { current_budget() = prev; }
+};
+
 // Device buffer drawn from the library's per-device pool (runtime.cpp); grows, never shrinks.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   int dev = 0;
+  MemBudget* budget = nullptr;  // the budget this buffer is charged to
+  size_t charged = 0;           // bytes charged (the size asked of the pool)
   hipError_t reserve(size_t b);
   void release();
   ~DevBuf() { release(); }
+  hipError_t reserve_pool(size_t want);  // a block of exactly `want` bytes from the pool
   template <class T> T* as() { return static_cast<T*>(p); }
 };
 

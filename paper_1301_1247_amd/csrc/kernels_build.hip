@@ -376,6 +376,8 @@ __global__ __launch_bounds__(256) void k_cpqrm_step(const CpqrDesc* __restrict__
   const int slot0 = p + 1 + 16 * (int)blockIdx.x;
   if (blockIdx.x != 0 && slot0 >= n) return;
   CpqrmState* S = W.st + b;
+  // a box whose rank is found costs its remaining launches nothing but this read
+  if (S->done) return;
   const size_t o = (size_t)b * W.maxn;
   const int* pcO = ((p & 1) ? W.pcB : W.pcA) + o;
   const double* cnO = ((p & 1) ? W.cnB : W.cnA) + o;
@@ -398,7 +400,6 @@ __global__ __launch_bounds__(256) void k_cpqrm_step(const CpqrDesc* __restrict__
       c[t] = (act && i < s) ? d.z[i + (size_t)phys * s] : mkc(0, 0);
     }
   }
-  if (S->done) return;
   __shared__ double rv[4];
   __shared__ int ri[4];
   __shared__ cplx v[CPQRM_MAXS];

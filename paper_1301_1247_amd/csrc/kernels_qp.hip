@@ -2,6 +2,7 @@
 // Sommerfeld-contour wall blocks B (Eq. 2.16) and C (Eq. 2.17), incident data, the Schur
 // complement S(alpha) = Q(alpha) - C(alpha) A^{-1} B(alpha) assembled from alpha-free products,
 // and Bragg amplitudes from the lattice-summed Green's function.
+#include "hankel.h"
 #include "qp_kernels.h"
 
 namespace {
@@ -42,16 +43,18 @@ __global__ __launch_bounds__(NT) void k_gen_B(QPGeo Q, cplx* __restrict__ Y, int
   }
 }
 
-// b = -exp(i (kx x + ky y)) for each angle column
+// b = -exp(i (kx x + ky y)) for each column; ky may be complex (ky_im nullable): the Rayleigh-Bloch
+// waves of evanescent orders that the Wood's-anomaly scheme adds as extra right-hand sides
 __global__ __launch_bounds__(NT) void k_gen_inc(QPGeo Q, const double* __restrict__ kx, const double* __restrict__ ky,
-                                                int nang, cplx* __restrict__ Y, int64_t ldy) {
+                                                const double* __restrict__ ky_im, int nang, cplx* __restrict__ Y, int64_t ldy) {
   const int64_t total = (int64_t)Q.N * nang;
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int i = (int)(e % Q.N);
     const int a = (int)(e / Q.N);
     double s, c;
     sincos(kx[a] * Q.x[i] + ky[a] * Q.y[i], &s, &c);
-    Y[i + (size_t)a * ldy] = mkc(-c, -s);
+    const double amp = ky_im ? -exp(-ky_im[a] * Q.y[i]) : -1.0;
+    Y[i + (size_t)a * ldy] = mkc(amp * c, amp * s);
   }
 }
 
@@ -239,6 +242,88 @@ __global__ __launch_bounds__(NT_NORM) void k_colnorm2(int64_t rows, const cplx* 
   }
 }
 
+// ---- radiation rows of the Wood's-anomaly scheme (Sec. 2.4, second improvement)
+// For each listed order m (kappa_m, k_m) the row of the condition "no up-going part of order m below
+// the obstacle": row . [eta; xi] = i k_m U_m(-y0) + U_m'(-y0), where U_m is the discrete Fourier
+// coefficient of order m of the representation (Eq. 2.14, Eq. 2.20 with P images) sampled at
+// x_l = -d/2 + (l + 1/2) d / ns on the line y = -y0 (Remark 2.3), U_m' that of its y-derivative.
+//
+// Obstacle part, one thread per (node i, order m):
+//   R[m + i ldr] = w_i sum_{j=-P..P} alpha^j (1/ns) sum_l e^{-i kappa_m x_l} [i k_m K + dK/dy](p_l; y_i + j d e_1, n_i)
+// with K = (i omega/4) H1(omega r) n.D/r + (omega/4) H0(omega r), D = p - y, and its derivative in the
+// target's second coordinate (H1' = H0 - H1/z):
+//   dK/dy = (i omega/4) [(omega H1'(omega r)/r - H1/r^2)(D_2/r) n.D + H1 n_2/r] - (omega^2/4) H1 D_2/r.
+__global__ __launch_bounds__(NT) void k_rad_rows_eta(QPGeo Q, const RadOrder* __restrict__ ord, int ns, int P, cplx alpha,
+                                                     double y0, cplx* __restrict__ R, int64_t ldr) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  const int m = blockIdx.y;
+  if (i >= Q.N) return;
+  const RadOrder o = ord[m];
+  const cplx ikm = mkc(-o.kn.y, o.kn.x);
+  const double nx = Q.nx[i], ny = Q.ny[i];
+  const double q = 0.25 * Q.omega;
+  cplx acc = mkc(0, 0);
+  cplx aj = mkc(1, 0);
+  for (int j = 0; j < P; ++j) aj = cmul(aj, cinv(alpha));  // alpha^{-P}
+  for (int j = -P; j <= P; ++j) {
+    const double sx = Q.x[i] + j * Q.period, sy = Q.y[i];
+    cplx part = mkc(0, 0);
+    for (int l = 0; l < ns; ++l) {
+      const double xl = -0.5 * Q.period + (l + 0.5) * Q.period / ns;
+      const double dx = xl - sx, dy = -y0 - sy;
+      const double r = sqrt(dx * dx + dy * dy);
+      const double z = Q.omega * r;
+      cplx h0, h1;
+      hankel01(z, h0, h1);
+      const double nd = nx * dx + ny * dy;
+      // K = q (H0 + i H1 nd / r)
+      const cplx K = cscale(cadd(h0, cmul(mkc(0, 1), cscale(h1, nd / r))), q);
+      // dK/dy = i q [(omega H1'/r - H1/r^2)(dy/r) nd + H1 ny / r] - q omega H1 dy / r
+      const cplx dh1 = csub(h0, cscale(h1, 1.0 / z));
+      const cplx br = cadd(cscale(csub(cscale(dh1, Q.omega / r), cscale(h1, 1.0 / (r * r))), dy * nd / r), cscale(h1, ny / r));
+      const cplx dK = csub(cmul(mkc(0, q), br), cscale(h1, q * Q.omega * dy / r));
+      double s, c;
+      sincos(-o.kap * xl, &s, &c);
+      part = cadd(part, cmul(mkc(c, s), cadd(cmul(ikm, K), dK)));
+    }
+    acc = cadd(acc, cmul(aj, part));
+    aj = cmul(aj, alpha);
+  }
+  R[m + (size_t)i * ldr] = cscale(acc, Q.w[i] / ns);
+}
+
+// Wall part, one thread per (contour column k in [0, 2M), order m): the Fourier wall potentials
+// (Eqs. 2.12-2.13) of mu (k < M) and nu (k >= M) on both walls, L with factor 1 and R with alpha,
+// sampled on y = -y0; d/dy multiplies node kk's term by i k_kk:
+//   mu:  (i/2) wk e^{-i kk y0} [e^{i s (x_l + d/2)} + alpha e^{i s (d/2 - x_l)}] / s
+//   nu:  (1/2) wk e^{-i kk y0} [e^{i s (x_l + d/2)} - alpha e^{i s (d/2 - x_l)}]
+__global__ __launch_bounds__(NT) void k_rad_rows_xi(QPGeo Q, const RadOrder* __restrict__ ord, int ns, cplx alpha, double y0,
+                                                    cplx* __restrict__ R, int64_t ldr) {
+  const int col = blockIdx.x * NT + threadIdx.x;
+  const int m = blockIdx.y;
+  if (col >= 2 * Q.M) return;
+  const RadOrder o = ord[m];
+  const int kk = col % Q.M;
+  const bool dbl = col >= Q.M;
+  const cplx k = Q.k[kk], sq = Q.s[kk], wk = Q.wk[kk];
+  // i k_m + i k
+  const cplx fac = mkc(-(o.kn.y + k.y), o.kn.x + k.x);
+  // wk e^{-i k y0}
+  const cplx base = cmul(wk, cexpi_c(mkc(-k.x * y0, -k.y * y0)));
+  cplx acc = mkc(0, 0);
+  for (int l = 0; l < ns; ++l) {
+    const double xl = -0.5 * Q.period + (l + 0.5) * Q.period / ns;
+    const cplx eL = cexpi_c(cscale(sq, xl + 0.5 * Q.period));
+    const cplx eR = cmul(alpha, cexpi_c(cscale(sq, 0.5 * Q.period - xl)));
+    double s, c;
+    sincos(-o.kap * xl, &s, &c);
+    acc = cadd(acc, cmul(mkc(c, s), dbl ? csub(eL, eR) : cadd(eL, eR)));
+  }
+  cplx v = cmul(cmul(base, fac), acc);
+  v = dbl ? cscale(v, 0.5) : cmul(mkc(0.0, 0.5), cmul(v, cinv(sq)));
+  R[m + (size_t)col * ldr] = cscale(v, 1.0 / ns);
+}
+
 // Bragg amplitudes (lattice-summed Green's function), one workgroup per (mode slot, angle):
 //   c_n = pre sum_j w_j eta_j e^{-i(kap_n x_j + k_n y_j)} [-i(kap_n n_x + k_n n_y) - i omega]
 //   d_n = pre sum_j w_j eta_j e^{-i(kap_n x_j - k_n y_j)} [ i(-kap_n n_x + k_n n_y) - i omega]
@@ -359,9 +444,10 @@ hipError_t launch_gen_B(const QPGeo& q, cplx* Y, int64_t ldy, hipStream_t s) {
   hipLaunchKernelGGL(k_gen_B, dim3(grid_for((int64_t)q.N * 4 * q.M)), dim3(NT), 0, s, q, Y, ldy);
   return hipGetLastError();
 }
-hipError_t launch_gen_inc(const QPGeo& q, const double* kx, const double* ky, int nang, cplx* Y, int64_t ldy, hipStream_t s) {
+hipError_t launch_gen_inc(const QPGeo& q, const double* kx, const double* ky, const double* ky_im, int nang, cplx* Y,
+                          int64_t ldy, hipStream_t s) {
   if (nang == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gen_inc, dim3(grid_for((int64_t)q.N * nang)), dim3(NT), 0, s, q, kx, ky, nang, Y, ldy);
+  hipLaunchKernelGGL(k_gen_inc, dim3(grid_for((int64_t)q.N * nang)), dim3(NT), 0, s, q, kx, ky, ky_im, nang, Y, ldy);
   return hipGetLastError();
 }
 hipError_t launch_gen_C(const QPGeo& q, int wall, double shift, cplx* C, hipStream_t s) {
@@ -432,6 +518,14 @@ hipError_t launch_bragg_gather(const QPGeo& q, double kref, int qlo, int nq, con
                      maxmodes, nang, Cg, y0, out);
   return hipGetLastError();
 }
+hipError_t launch_rad_rows(const QPGeo& q, const RadOrder* ord, int c, int ns, int P, cplx alpha, double y0, cplx* Reta,
+                           cplx* Rxi, hipStream_t s) {
+  if (c == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rad_rows_eta, dim3((q.N + NT - 1) / NT, c), dim3(NT), 0, s, q, ord, ns, P, alpha, y0, Reta, (int64_t)c);
+  hipLaunchKernelGGL(k_rad_rows_xi, dim3((2 * q.M + NT - 1) / NT, c), dim3(NT), 0, s, q, ord, ns, alpha, y0, Rxi, (int64_t)c);
+  return hipGetLastError();
+}
+
 hipError_t launch_permute_cols(int64_t rows, int cols, const int* perm, const cplx* src, int64_t lds, cplx* dst, int64_t ldd,
                                hipStream_t s) {
   if (rows * cols == 0) return hipSuccess;

@@ -81,6 +81,16 @@ int qp_plan(const hbs_handle* h, double period, const qp_opts* o, QPPlan* p) {
   return HBS_OK;
 }
 
+int qp_plan_y0(const hbs_handle* h, double period, const qp_opts* o, double* K, double* y0, int* M) {
+  QPPlan p;
+  const int rc = qp_plan(h, period, o, &p);
+  if (rc != HBS_OK) return rc;
+  *K = p.K;
+  *y0 = p.y0;
+  *M = p.M;
+  return HBS_OK;
+}
+
 int qp_contour_M(const hbs_handle* h, double period, const qp_opts* o) {
   QPPlan p;
   if (qp_plan(h, period, o, &p) != HBS_OK) return -1;
@@ -96,11 +106,15 @@ int qp_contour_M(const hbs_handle* h, double period, const qp_opts* o) {
 // and (Eq. 3.2 with the sign of its second term corrected)
 //   A~^{-1} = A^{-1} - V K R A^{-1},  V = A^{-1} U,  K(alpha) = (I + R V)^{-1}  (root-size),
 // where V joins the single application of A^{-1}.  C~(alpha) = alpha^P C_L[dOmega + P d] - alpha^{-(P+1)} C_R[dOmega - P d].
-int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, const qp_opts* o, cplx* eta_out,
-                  cplx* xi_out, cplx* bragg_out, int32_t* nlo_out, int32_t* nm_out, double* flux_out) {
+//
+// cols (nullable): the columns are not incident angles but the given plane waves
+// -exp(i (kx x + ky y)) (ky complex), all with the Bloch phase cols->alpha, solved on the contour
+// whose real-axis crossing is displaced to cols->delta (the Wood's-anomaly scheme); th is ignored.
+int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, const qp_opts* o, const QPCols* cols,
+                  cplx* eta_out, cplx* xi_out, cplx* bragg_out, int32_t* nlo_out, int32_t* nm_out, double* flux_out) {
   hipStream_t st = h->stream;
   const int N = (int)h->N;
-  const int nang = (int)th.size();
+  const int nang = cols ? (int)cols->kx.size() : (int)th.size();
   const double om = h->omega;
   const int P = o->P;
   if (P != 0 && P != 1) {
@@ -132,7 +146,8 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   const double wood = o->wood_min_kn > 0 ? o->wood_min_kn : 0.75;
   // Bloch phases, Wood's check, grouping
   std::vector<zc> al(nang);
-  for (int a = 0; a < nang; ++a) {
+  for (int a = 0; a < nang && cols; ++a) al[a] = cols->alpha;
+  for (int a = 0; a < nang && !cols; ++a) {
     const double kap = om * std::cos(th[a]);
     al[a] = std::exp(zc(0.0, kap * period));
     double mn = 1e300;
@@ -147,11 +162,14 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       return HBS_E_WOOD;
     }
   }
+  // Angles share a group (and its alpha in the alpha-dependent blocks) only when their Bloch phases
+  // agree to the rounding of omega d cos(theta): a few ulps of a phase of size omega d.
+  const double gtol = 32.0 * 2.220446049250313e-16 * std::max(1.0, om * period);
   std::vector<int> grp(nang, -1);
   std::vector<zc> galpha;
   for (int a = 0; a < nang; ++a) {
     for (size_t g = 0; g < galpha.size(); ++g)
-      if (std::abs(al[a] - galpha[g]) <= 1e-10) { grp[a] = (int)g; break; }
+      if (std::abs(al[a] - galpha[g]) <= gtol) { grp[a] = (int)g; break; }
     if (grp[a] < 0) {
       grp[a] = (int)galpha.size();
       galpha.push_back(al[a]);
@@ -168,10 +186,12 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   }
   // contour (Sec. 2.3): k(t) = t - i ca tanh(t/cb), trapezoid in t
   std::vector<cplx> cont(3 * M);
+  // (displaced: k(t) = t - i ca tanh((t - delta)/cb), crossing the real axis at delta)
+  const double cdel = cols ? cols->delta : 0.0;
   for (int m = 0; m < M; ++m) {
     const double t = -pl.K + (m + 0.5) * pl.h;
-    const zc k(t, -pl.ca * std::tanh(t / pl.cb));
-    const double sech = 1.0 / std::cosh(t / pl.cb);
+    const zc k(t, -pl.ca * std::tanh((t - cdel) / pl.cb));
+    const double sech = 1.0 / std::cosh((t - cdel) / pl.cb);
     const zc wk = pl.h * zc(1.0, -(pl.ca / pl.cb) * sech * sech);
     const zc s = std::sqrt(om * om - k * k);
     cont[m] = toc(k);
@@ -179,7 +199,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
     cont[2 * M + m] = toc(wk);
   }
   // per-angle data in grouped order; C~(alpha) = c1 C1 + c2 C2 with c1 = alpha^P, c2 = -alpha^{-(P+1)}
-  std::vector<double> kx(nang), ky(nang);
+  std::vector<double> kx(nang), ky(nang), kyi(nang, 0.0);
   std::vector<cplx> colc(5 * nang), gcoef(3 * ng + 4 * ng);
   std::vector<int> perm(nang), nlo(nang), nm(nang);
   const int maxm = qp_max_modes_impl(om, period);
@@ -188,8 +208,9 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   for (int q = 0; q < nang; ++q) {
     const int a = order[q];
     const zc ag = galpha[grp[a]];
-    kx[q] = om * std::cos(th[a]);
-    ky[q] = om * std::sin(th[a]);
+    kx[q] = cols ? cols->kx[a] : om * std::cos(th[a]);
+    ky[q] = cols ? cols->ky[a].real() : om * std::sin(th[a]);
+    kyi[q] = cols ? cols->ky[a].imag() : 0.0;
     colc[q] = toc(ag);                        // alpha
     colc[nang + q] = toc(c1_of(ag));          // c1
     colc[2 * nang + q] = toc(c2_of(ag));      // c2
@@ -225,7 +246,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   const int nuu = std::max(nu, 1);
   std::vector<size_t> sizes = {
       sizeof(cplx) * 3 * M,                          // 0 contour
-      sizeof(double) * nang * 3,                     // 1 kx, ky, kappa
+      sizeof(double) * nang * 4,                     // 1 kx, ky, kappa, Im ky
       sizeof(cplx) * (5 * nang + 7 * ng + 2),        // 2 column and group coefficients, constants
       sizeof(int) * nang * 3,                        // 3 perm, nlo, nmodes
       sizeof(cplx) * N * Wy,                         // 4 Y
@@ -258,6 +279,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   double* dkx = (double*)(base + off[1]);
   double* dky = dkx + nang;
   double* dkap = dky + nang;
+  double* dkyi = cols ? dkap + nang : nullptr;
   cplx* dcol = (cplx*)(base + off[2]);
   cplx* d_al = dcol;
   cplx* d_c1 = dcol + nang;
@@ -330,6 +352,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   CK(hipMemcpyAsync(dkx, kx.data(), sizeof(double) * nang, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(dky, ky.data(), sizeof(double) * nang, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(dkap, kx.data(), sizeof(double) * nang, hipMemcpyHostToDevice, st));
+  if (dkyi) CK(hipMemcpyAsync(dkyi, kyi.data(), sizeof(double) * nang, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(dcol, colc.data(), sizeof(cplx) * 5 * nang, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(d_gco, gcoef.data(), sizeof(cplx) * 7 * ng, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(d_one, consts.data(), sizeof(cplx) * 2, hipMemcpyHostToDevice, st));
@@ -456,7 +479,7 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
       CK(launch_gen_C(Q, 0, P * period, C1, st));
       CK(launch_gen_C(Q, 1, -P * period, C2, st));
     }
-    CK(launch_gen_inc(Q, dkx, dky, nang, Y + (size_t)ycolB * N, N, st));
+    CK(launch_gen_inc(Q, dkx, dky, dkyi, nang, Y + (size_t)ycolB * N, N, st));
   }
   // compressed walls on complex128 factors: V = A^{-1} U and U^T A^{-1} [U | b] come from the
   // root inverse and the E-only downward pass, without forming U (F^T P = I, G P = 0, P^T E = I)

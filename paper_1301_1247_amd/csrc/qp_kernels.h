@@ -11,9 +11,21 @@ struct QPGeo {
   double omega, period, shift;
 };
 
+// An order of the Wood's-anomaly radiation rows: kappa_m = kappa + 2 pi m / d and k_m (complex).
+struct RadOrder {
+  double kap;
+  double pad;
+  cplx kn;
+};
+
 namespace qps {
+// Rows (c x N and c x 2M, column-major, leading dimension c) of the radiation conditions of the
+// orders ord[0..c) for the representation with P images and Bloch phase alpha, from ns samples on y = -y0
+hipError_t launch_rad_rows(const QPGeo& q, const RadOrder* ord, int c, int ns, int P, cplx alpha, double y0, cplx* Reta,
+                           cplx* Rxi, hipStream_t s);
 hipError_t launch_gen_B(const QPGeo& q, cplx* Y, int64_t ldy, hipStream_t s);
-hipError_t launch_gen_inc(const QPGeo& q, const double* kx, const double* ky, int nang, cplx* Y, int64_t ldy, hipStream_t s);
+hipError_t launch_gen_inc(const QPGeo& q, const double* kx, const double* ky, const double* ky_im, int nang, cplx* Y,
+                          int64_t ldy, hipStream_t s);
 hipError_t launch_gen_C(const QPGeo& q, int wall, double shift, cplx* C, hipStream_t s);
 hipError_t launch_form_S(const QPGeo& q, const cplx* coef, int ng, const cplx* G1, const cplx* G2, cplx* S, hipStream_t s);
 // W[:, a] = c1[a*cs] U1[:, a] + c2[a*cs] U2[:, a], or R[:, a] - (...) when R != nullptr (W may alias R)

@@ -83,10 +83,31 @@ void trim_device(int dev) {
 }
 }  // namespace
 
+MemBudget*& current_budget() {
+  static thread_local MemBudget* b = nullptr;
+  return b;
+}
+
 hipError_t DevBuf::reserve(size_t b) {
   if (b <= bytes) return hipSuccess;
   release();
   const size_t want = round_size(b + b / 4 + 256);
+  MemBudget* mb = current_budget();
+  if (mb && mb->limit > 0 && mb->used + want > mb->limit) {
+    mb->refused = want;
+    return hipErrorOutOfMemory;
+  }
+  hipError_t e0 = reserve_pool(want);
+  if (e0 == hipSuccess && mb) {
+    budget = mb;
+    charged = want;
+    mb->used += want;
+    mb->peak = std::max(mb->peak, mb->used);
+  }
+  return e0;
+}
+
+hipError_t DevBuf::reserve_pool(size_t want) {
   int d = 0;
   hipError_t e = hipGetDevice(&d);
   if (e != hipSuccess) return e;
@@ -124,6 +145,11 @@ hipError_t DevBuf::reserve(size_t b) {
 
 void DevBuf::release() {
   if (!p) return;
+  if (budget) {
+    budget->used -= charged;
+    budget = nullptr;
+    charged = 0;
+  }
   Pool& P = pool();
   {
     std::lock_guard<std::mutex> lk(P.mu);

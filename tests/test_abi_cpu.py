@@ -181,3 +181,22 @@ def test_gemm_tune_choose_keeps_default_within_margin():
     assert rows[0]["ms"] == {"0": 10.0, "1": 9.0, "2": 9.8, "3": 11.0}
     table_strict, _ = choose(times, margin=0.15)
     assert table_strict == {2: 2}
+
+
+def test_mem_limit_refused_before_any_device_allocation():
+    """hbs_opts.mem_limit is checked on the host: a budget smaller than the geometry upload fails
+    with HBS_E_OOM and an error text naming the limit, without touching the device (this runs on
+    a host with no GPU)."""
+    nodes, w, nrm, _ = _geom()
+    rc, msg = _build(nodes, w, nrm, 256, mem_limit=4096)
+    assert rc == -3, (rc, msg)
+    assert "mem_limit of 4096 device bytes exceeded" in msg
+
+
+def test_opts_struct_size_matches_binding():
+    from paper_1301_1247_amd import binding as B
+    o = B.hbs_opts()
+    assert o.struct_size == C.sizeof(B.HbsOpts)
+    assert o.mem_limit == 0
+    q = B.qp_opts()
+    assert q.struct_size == C.sizeof(B.QpOpts)

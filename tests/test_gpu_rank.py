@@ -157,3 +157,42 @@ def test_under_predicted_sketches_fall_back(gpu_lib, wavy_case):
     b = rng.standard_normal(N) + 1j * rng.standard_normal(N)
     xe = sla.lu_solve(lu, b)
     assert np.linalg.norm(h.apply(b, refine=2) - xe) / np.linalg.norm(xe) < 1e-10
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3])
+def test_mlp_adam_steps_match_oracle(gpu_lib, steps):
+    """qps_mlp_train against the oracle's Adam (mean pinball loss, zero initial moments), entry by
+    entry.  Data with targets away from the predictions (no sample near the loss's kink).  An
+    entry whose oracle gradient comes within 1e-4 of zero at some step is held to the bound
+    lr * steps that any Adam step obeys (its sign is decided by rounding there); every other
+    entry to 1e-2 lr + float rounding of the parameter."""
+    rng = np.random.default_rng(11)
+    n = 500
+    x = (rng.standard_normal((n, 16)) * 1.5 + 0.5).astype(np.float32)
+    p0 = rm.init(x.astype(float), 4).astype(np.float32)
+    y = rm.forward(p0.astype(float), x.astype(float))
+    t = (y + np.where(rng.random(n) < 0.5, -1.0, 1.0) * rng.uniform(0.5, 2.0, n)).astype(np.float32)
+    lr = 1e-3
+    p_gpu, hist = gpu_lib.mlp_train(p0, x, t, tau=0.9, steps=steps, lr=lr)
+    xd, td = x.astype(float), t.astype(float)
+    p_ref, hist_ref = rm.train(p0.astype(float), xd, td, 0.9, steps, lr)
+    # the oracle's gradients along its own path, for the near-zero mask
+    pp = p0.astype(float)
+    m = np.zeros_like(pp)
+    v = np.zeros_like(pp)
+    gmin = np.full(pp.size, np.inf)
+    for it in range(1, steps + 1):
+        g = rm.grad(pp, xd, td, 0.9) / n
+        gmin = np.minimum(gmin, np.abs(g))
+        pp, m, v = rm.adam_step(pp, g, m, v, it, lr)
+    assert np.array_equal(pp, p_ref)
+    assert np.abs(hist - hist_ref).max() <= 1e-5 * np.abs(hist_ref).max()
+    assert np.array_equal(p_gpu[:32], p0[:32])
+    d = np.abs(p_gpu.astype(float) - p_ref)
+    # float32 gradients sum 500 samples (absolute error ~1e-7): an entry of |g| > 1e-4 is off by
+    # < 1e-3 relative, which moves a later Adam step (m / sqrt(v)) by about that fraction of lr;
+    # a wrong moment rate or bias correction moves it by O(lr)
+    firm = gmin > 1e-4
+    assert firm[32:].mean() > 0.8
+    assert d[firm].max() <= 1e-2 * lr + 4e-7 * np.abs(p_ref[firm]).max()
+    assert d.max() <= lr * steps * 1.001 + 1e-6

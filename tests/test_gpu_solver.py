@@ -194,7 +194,7 @@ def test_qp_solve_alpha_mismatch_and_wood(gpu_lib):
     # Wood's anomaly: kappa + n = +-omega for d = 2 pi, i.e. cos(theta) = (omega - 1)/omega
     th = -math.acos((wl.omega - 1.0) / wl.omega)
     with pytest.raises(gpu_lib.HBSError) as e:
-        h.qp_solve_many(wl.period, np.array([th]))
+        h.qp_solve_many(wl.period, np.array([th]), wood=-1)
     assert e.value.code == -9
 
 
