@@ -1,23 +1,29 @@
 """Benchmark: incident-angle solves per second of the full hot path on one MI355X.
 
 One step = hbs_build (recursive skeletonization of the N x N Nystrom matrix) + qp_solve_many
-over every incident angle of the workload (one application of A^{-1} to [B_L | B_R | b...],
-alpha-free Schur products, per-alpha Schur inversions, refinement, Bragg amplitudes), with the
-geometry already resident in HBM.  value = angles per second over the timed steps.
+over every incident angle of the workload (one application of A^{-1} to the wall and incident
+columns, the Schur step per Bloch phase, refinement check, Bragg amplitudes), with the geometry
+already resident in HBM.  value = angles per second over the timed steps.
 
-Default workload "wavy40": seeded 40-harmonic obstacle, N = 1e5, omega = 60, d = 2 pi,
-200 angles on 4 shared Bloch phases.
+Default workload "wavy40": seeded 40-harmonic obstacle, N = 1e5, omega = 60, d = 2 pi, 200 angles
+on 4 shared Bloch phases, rank predictor on, complex128.
 
-Also reported: the roofline of the dominant kernel (the complex FP64 MFMA GEMM) from HIP events
-on the library's stream, the oracle timed on the host cores on a bounded sample, and a
-verification of the timed solution (sampled residual rows of the bordered system evaluated by
-the oracle's kernels, and the energy balance).
+Also reported on the same JSON line:
+* kernel_families: summed HIP-event time per kernel family over the timed steps (events recorded on
+  the stream each launch is issued on), its share, and the achieved rate against the family's
+  roofline; `roofline` is the family with the largest time, `rooflines` every family above 5%;
+* variants: the same workload without the rank predictor and with the complex64 preconditioner;
+* c5: the 64-obstacle batch with a predictor trained on 48 obstacles, held-out rate with and without
+  the predictor;
+* verify: sampled residual rows of the bordered system of the timed solution (oracle checker, CPU)
+  and the energy balance; a failed check voids `value`;
+* cpu_baseline: the oracle (dense Nystrom + LU) timed on the host cores on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -26,76 +32,221 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "incident-angle solves/sec at N=1e5, rel err<=1e-10; HBS build time (s)"
-FP64_PEAK_TFLOPS = 78.6
-FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK = 78.6      # TFLOP/s: FP64 MFMA and FP64 vector (MI355X, dense)
+FP32_MFMA_PEAK = 157.3
+CSRC = os.path.join(ROOT, "paper_1301_1247_amd", "csrc")
 
-
-HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_gemm_wavy40_N1e5_traffic.txt")
-GEMM_SRC = os.path.join(HERE, "paper_1301_1247_amd", "csrc", "gemm.hip")
-GEMM_TABLE = os.path.join(HERE, "paper_1301_1247_amd", "gemm_tune_default.json")
-
-
-def measured_traffic():
-    """HBM bytes per complex128 GEMM launch (k_gemm<double, *, *>, every tile configuration) from the
-    committed rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE per dispatch, KiB, scaled by the
-    factors a plain copy of known size gives), or None when the GEMM source or its tuning table
-    has changed since the counters were taken."""
-    import hashlib
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    kv = {}
-    for line in open(TRAFFIC_FILE):
-        if "=" in line and not line.lstrip().startswith("#"):
-            k, v = line.split("=", 1)
-            kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(GEMM_SRC, "rb").read()).hexdigest()
-    if kv.get("source_sha256") != sha:
-        return None
-    # the tile configurations (and so the operand re-reads) follow the embedded tuning table
-    tsha = hashlib.sha256(open(GEMM_TABLE, "rb").read()).hexdigest() if os.path.exists(GEMM_TABLE) else "none"
-    if kv.get("table_sha256") != tsha:
-        return None
-    return 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["fetch_factor"]) +
-                     float(kv["write_kib_per_launch"]) * float(kv["write_factor"]))
+# kernel family -> (kernels, bound, peak TFLOP/s, source whose counters the traffic file belongs to)
+FAMILIES = {
+    "zgemm": ("k_gemm<double, *, *>", "mfma", FP64_PEAK, "gemm.hip"),
+    "zinv": ("k_gj_step<double>", "alu", FP64_PEAK, "kernels_build.hip"),
+    "cpqr": ("k_cpqr<*>, k_cpqrm_*", "alu", FP64_PEAK, "kernels_build.hip"),
+    "sketch": ("k_sketch", "alu", FP64_PEAK, "kernels_build.hip"),
+    "assemble": ("k_eval_blocks, k_proxy, k_gen_B, k_gen_C", "alu", FP64_PEAK, "kernels_build.hip"),
+    "bragg": ("k_bragg_basis, k_bragg", "alu", FP64_PEAK, "kernels_qp.hip"),
+    "cgemm": ("k_gemm<float, *, *>", "mfma", FP32_MFMA_PEAK, "gemm.hip"),
+    "cinv": ("k_gj_step<float>", "alu", 157.3, "kernels_build.hip"),
+}
+WORK = {
+    "zgemm": "8 m n k flops per complex product",
+    "cgemm": "8 m n k flops per complex product",
+    "zinv": "8 n^3 flops per n x n Gauss-Jordan inversion, over its 16-column panel launches",
+    "cinv": "8 n^3 flops per n x n Gauss-Jordan inversion",
+    "cpqr": "16 s n k flops per box (s x n sketch, rank k)",
+    "sketch": "8 s m n flops per box (s sketch rows, m x n compression matrix)",
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, n_sample=2000, q_sample=2):
-    """The oracle (dense Nystrom + bordered LU per angle) on a bounded sample of the workload:
-    the same obstacle, frequency, period and first angles at N = n_sample; the per-angle time is
-    scaled to the workload's N by the O((N + 2M)^3) cost of the dense LU that dominates it."""
-    import numpy as np
+def measured_traffic(family, workload):
+    """HBM bytes per launch of the family's kernel from the committed rocprofv3 counter runs
+    (profiles/<family>_<workload>_traffic.txt: FETCH_SIZE and WRITE_SIZE per dispatch, KiB, scaled
+    by the factors a plain copy of known size gives), or None when the kernel's source has changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{family}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(CSRC, FAMILIES[family][3])
+    if kv.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["fetch_factor"]) +
+                     float(kv["write_kib_per_launch"]) * float(kv["write_factor"]))
+
+
+def cpu_baseline(wl, n_sample=4000, q_sample=4):
+    """The oracle, as it stands, on a bounded sample of the workload: the same obstacle, frequency,
+    period and one angle of each Bloch phase, at N = n_sample (dense Nystrom assembly, then for every
+    angle the bordered system by one LU of A and the Schur complement of Eq. 3.1).  The rate is the
+    one measured at that N; the cube-law estimate at the workload's N is given beside it, labelled."""
     from threadpoolctl import threadpool_info
     from oracle import nystrom as ny
     from oracle import periodic as pq
 
     disc = ny.Discretization(wl.curve, n_sample)
-    th = wl.thetas[:q_sample]
+    per = len(wl.thetas) // 4
+    th = wl.thetas[::per][:q_sample]
     t0 = time.perf_counter()
-    r = pq.solve_qp(disc, n_sample, wl.omega, wl.period, th, quad=wl.quad)
+    r = pq.solve_qp(disc, n_sample, wl.omega, wl.period, th, quad=wl.quad, method="schur")
     t = time.perf_counter() - t0
     Ms = len(r["contour"].k)
-    dfull = ny.Discretization(wl.curve, 2000)  # only for the contour size of the workload
-    Mf = len(pq.default_contour(dfull, wl.omega, wl.period).k)
-    scale = ((wl.N + 2 * Mf) / (n_sample + 2 * Ms)) ** 3
-    per_angle_full = t / q_sample * scale
     threads = sum(x.get("num_threads", 0) for x in threadpool_info() if x.get("user_api") == "blas") or os.cpu_count()
-    return {"value": 1.0 / per_angle_full, "unit": "angles/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"N={n_sample}, {q_sample} angles of the same workload in {t:.1f} s "
-                      f"({q_sample / t:.3g} angles/s at that N); scaled by ((N+2M)/(Ns+2Ms))^3 = {scale:.3g} "
-                      f"to N={wl.N}, M={Mf}"}
+    est = (q_sample / t) / (((wl.N + 2 * Ms) / (n_sample + 2 * Ms)) ** 3)
+    return {"value": q_sample / t, "unit": "angles/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{wl.name} obstacle, omega={wl.omega}, d=2pi at N={n_sample} (the workload has N={wl.N}), "
+                      f"{q_sample} angles (one per Bloch phase), dense assembly + one LU and Schur solve per angle: "
+                      f"{t:.1f} s measured",
+            "estimate_at_workload_N": {"value": est, "unit": "angles/s",
+                                       "how": "measured rate scaled by ((N+2M)/(Ns+2M))^3 (dense LU cost); "
+                                              "an estimate, not a measurement"}}
 
 
 def verify(wl, res, n_rows=48, n_ang=8):
-    """Sampled rows of the bordered-system residual of the timed solution, by the oracle's
-    checker (exact dense rows of A and B, all rows of C and Q), plus the flux error of every angle."""
+    """Sampled rows of the bordered-system residual of the timed solution, by the oracle's checker
+    (exact dense rows of A and B, all rows of C and Q), plus the flux error of every angle."""
     from oracle import checks
-    return checks.bordered_residual(wl.curve, wl.N, wl.omega, wl.period, wl.thetas, res["eta"], res["xi"],
-                                    res["flux"], n_rows=n_rows, n_ang=n_ang)
+    v = checks.bordered_residual(wl.curve, wl.N, wl.omega, wl.period, wl.thetas, res["eta"], res["xi"],
+                                 res["flux"], n_rows=n_rows, n_ang=n_ang)
+    v["kind"] = "sampled residual of the bordered system (Eq. 2.19) relative to |b|, not a forward error"
+    v["ok"] = bool(v["sampled_rel_residual"] <= 1e-10 and v["flux_err_max"] <= 1e-8)
+    return v
+
+
+def family_table(B, steps, cpqr_flops_step):
+    """Per kernel family: summed event time, launches, algorithmic flops, rate and roofline fraction."""
+    fams = {}
+    for fam in FAMILIES:
+        p = B.profile_read(fam)
+        if p["launches"] == 0:
+            continue
+        flops = p["flops"]
+        if fam == "cpqr":
+            flops = cpqr_flops_step * steps
+        if fam in ("assemble", "bragg"):
+            flops = 0.0
+        kernels, bound, peak, _ = FAMILIES[fam]
+        ach = flops / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 and flops > 0 else None
+        fams[fam] = {"kernels": kernels, "ms_per_step": p["ms"] / steps, "launches_per_step": p["launches"] / steps,
+                     "avg_launch_ms": p["ms"] / p["launches"], "flops_per_launch": flops / p["launches"] if flops else None,
+                     "achieved": ach, "peak": peak, "unit": "TFLOP/s", "bound": bound,
+                     "frac": ach / peak if ach is not None else None, "work": WORK.get(fam)}
+    tot = sum(f["ms_per_step"] for f in fams.values())
+    for f in fams.values():
+        f["share"] = f["ms_per_step"] / tot if tot > 0 else 0.0
+    return fams
+
+
+def run_steps(B, torch, wl, t_nodes, t_w, t_nrm, t_th, kw, tol, cw, steps, warmup, profile=False):
+    def step():
+        h = B.Handle(t_nodes, t_w, t_nrm, wl.omega, tol, **kw)
+        res = h.qp_solve_many(wl.period, t_th, compress_walls=cw)
+        return h, res
+
+    for i in range(warmup):
+        h, res = step()
+        log(f"warmup {i}: build {h.stats().build_seconds:.3f} s, refine residual {h.stats().refine_residual:.2e}")
+        del h, res
+    torch.cuda.synchronize()
+    if profile:
+        B.profile_enable(True)
+    builds = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        h, res = step()
+        builds.append(h.stats().build_seconds)
+        if i < steps - 1:
+            del h, res
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    return h, res, t, builds
+
+
+def host_solution(res):
+    return {"eta": res["eta"].T.cpu().numpy(), "xi": res["xi"].T.cpu().numpy(), "flux": res["flux"]}
+
+
+def c5_batch(B, torch, steps=3):
+    """The 64-obstacle batch: even obstacles from the 20-harmonic family (a_k ~ U(0, 0.3/k)), odd ones
+    from the 40-harmonic family (a_k ~ U(0, 0.2/k)); N = rng.integers(2000, 50001) rounded to even,
+    omega ~ U[10, 80], seeds 1301500 + i, 50 angles each away from Wood's anomalies.  A predictor is
+    trained on the features and CPQR ranks of obstacles i < 48 (built without it) on the GPU; the
+    16 held out are then built and solved with and without it, angles/s over the held-out set."""
+    import numpy as np
+    import qpinputs
+    from paper_1301_1247_amd import train_rank_mlp as tr
+    from paper_1301_1247_amd.geometry import discretize
+
+    members = qpinputs.c5_batch()
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    geo = []
+    for m in members:
+        nodes, w, nrm, _ = discretize(m["curve"], m["N"])
+        c0 = 0.5 * (nodes.max(0) + nodes.min(0))
+        far = 0.9 * (0.5 * m["period"] - abs(c0[0]))
+        geo.append((t(nodes), t(w), t(nrm), t(m["thetas"]), far))
+    # training data: every box of the 48 training obstacles, built without the predictor
+    feats, ranks = [], []
+    t0 = time.perf_counter()
+    for m, g in zip(members[:48], geo[:48]):
+        h = B.Handle(g[0], g[1], g[2], m["omega"], m["tol"], device=True, far_radius=g[4])
+        f, k, lv, _ = h.rank_features()
+        feats.append(f)
+        ranks.append(k)
+        del h
+    x = np.concatenate(feats)
+    y = np.log(np.maximum(np.concatenate(ranks), 1)).astype(np.float32)
+    p0 = tr.initial_params(x, seed=1301)
+    p1, hist = B.mlp_train(p0, x, y, tau=0.9, steps=3000, lr=3e-3)
+    t_train = time.perf_counter() - t0
+    held = list(zip(members[48:], geo[48:]))
+
+    def rate(predictor):
+        nang = 0
+        fallbacks = 0
+        flux = 0.0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            for m, g in held:
+                h = B.Handle(g[0], g[1], g[2], m["omega"], m["tol"], device=True, far_radius=g[4],
+                             rank_predictor=predictor, rank_model=p1 if predictor else None)
+                r = h.qp_solve_many(m["period"], g[3], compress_walls=1)
+                nang += len(m["thetas"])
+                fallbacks += h.stats().rank_fallbacks
+                flux = max(flux, float(np.max(r["flux"])))
+                del h, r
+        torch.cuda.synchronize()
+        return nang / (time.perf_counter() - t1), fallbacks / steps, flux
+
+    rate(True)   # warm-up
+    rate(False)
+    on, fb, flux_on = rate(True)
+    off, _, flux_off = rate(False)
+    cov, ratio = [], []
+    for m, g in held:
+        h = B.Handle(g[0], g[1], g[2], m["omega"], m["tol"], device=True, far_radius=g[4], rank_predictor=True,
+                     rank_model=p1)
+        f, k, lv, pr = h.rank_features()
+        top = lv > 1
+        cov.append(float((pr[top] >= k[top]).mean()))
+        ratio.append(float(np.mean(pr[top] / np.maximum(k[top], 1))))
+        del h
+    return {"obstacles": len(members), "train": 48, "held_out": len(held), "angles_each": 50,
+            "angles_per_s_predictor": on, "angles_per_s_no_predictor": off, "speedup": on / off,
+            "rank_fallbacks_per_pass": fb, "held_out_rank_coverage": float(np.mean(cov)),
+            "held_out_mean_predicted_over_actual": float(np.mean(ratio)),
+            "train_boxes": int(len(y)), "train_seconds_incl_builds": t_train,
+            "train_loss_first_last": [float(hist[0]), float(hist[-1])],
+            "flux_err_max": max(flux_on, flux_off),
+            "note": "flux of the low-N / high-omega members measures their discretization, not the solver"}
 
 
 def main():
@@ -113,6 +264,8 @@ def main():
                     help="fp32: complex64 inverse factors as a preconditioner, FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the no-predictor and fp32 rates")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 64-obstacle batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -138,42 +291,38 @@ def main():
     t_th = torch.from_numpy(wl.thetas).to(dev)
     stream = torch.cuda.current_stream()
     nang = len(wl.thetas)
-    kw = dict(quad=wl.quad, leaf_size=wl.leaf_size, curvature=t_kap if wl.quad == "kress" else None, device=True,
-              stream=stream.cuda_stream, precision=args.precision, rank_predictor=args.rank_predictor == "on")
+    base_kw = dict(quad=wl.quad, leaf_size=wl.leaf_size, curvature=t_kap if wl.quad == "kress" else None, device=True,
+                   stream=stream.cuda_stream)
     if args.walls == "compressed":
         # far-field circle about the bounding-box centre that stays inside the unit cell's walls
         c0 = 0.5 * (nodes.max(0) + nodes.min(0))
-        kw["far_radius"] = 0.9 * (0.5 * wl.period - abs(c0[0]))
+        base_kw["far_radius"] = 0.9 * (0.5 * wl.period - abs(c0[0]))
     cw = 1 if args.walls == "compressed" else -1
-    fam, peak = ("zgemm", FP64_PEAK_TFLOPS) if args.precision == "fp64" else ("cgemm", FP32_PEAK_TFLOPS)
+    kw = dict(base_kw, precision=args.precision, rank_predictor=args.rank_predictor == "on")
 
-    def step():
-        h = B.Handle(t_nodes, t_w, t_nrm, wl.omega, args.tol, **kw)
-        res = h.qp_solve_many(wl.period, t_th, compress_walls=cw)
-        return h, res
-
-    for i in range(args.warmup):
-        h, res = step()
-        log(f"warmup {i}: build {h.stats().build_seconds:.3f} s, refine residual {h.stats().refine_residual:.2e}")
-        del h, res
-    torch.cuda.synchronize()
-    B.profile_enable(True)
-    builds = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        h, res = step()
-        builds.append(h.stats().build_seconds)
-        if i < args.steps - 1:
-            del h, res
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    prof = B.profile_read(fam)
-    B.profile_enable(False)
+    h, res, t, builds = run_steps(B, torch, wl, t_nodes, t_w, t_nrm, t_th, kw, args.tol, cw, args.steps, args.warmup,
+                                  profile=True)
     st = h.stats()
-    log(f"timed {args.steps} steps in {t:.3f} s; {fam} {prof}")
+    fams = family_table(B, args.steps, 16.0 * st.cpqr_work)
+    B.profile_enable(False)
+    log(f"timed {args.steps} steps in {t:.3f} s")
     ms = 1000.0 * t / args.steps
     value = nang * args.steps / t
-    achieved = prof["flops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else 0.0
+    # the dominant family and every family above 5% of the summed kernel time
+    dom = max(fams, key=lambda f: fams[f]["ms_per_step"])
+    rl = {}
+    for fam, f in sorted(fams.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+        if f["share"] >= 0.05 and f["achieved"] is not None:
+            rl[fam] = {"kernel": f["kernels"], "bound": f["bound"], "achieved": f["achieved"], "peak": f["peak"],
+                       "unit": "TFLOP/s", "frac": f["frac"], "share": f["share"], "avg_launch_ms": f["avg_launch_ms"],
+                       "flops_per_launch": f["flops_per_launch"], "work": f["work"]}
+    d = fams[dom]
+    roofline = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": "TFLOP/s",
+                "frac": d["frac"], "traffic": measured_traffic(dom, wl.name) if wl.name == "wavy40" else None,
+                "kernel": d["kernels"], "family": dom, "share_of_kernel_time": d["share"],
+                "avg_launch_ms": d["avg_launch_ms"], "flops_per_launch": d["flops_per_launch"],
+                "launches_per_step": d["launches_per_step"], "work": d["work"],
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}
     out = {
         "metric": METRIC,
         "value": value,
@@ -189,25 +338,41 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: seeded obstacle, N={wl.N}, omega={wl.omega}, d=2pi, "
                                f"{nang} angles, tol={args.tol:g}, KR6 + proxy compression, {args.precision} factors, "
-                               f"{args.walls} walls",
+                               f"{args.walls} walls, rank predictor {args.rank_predictor}",
                    "N": wl.N, "omega": wl.omega, "angles": nang, "contour_M": st.contour_M,
                    "walls": args.walls, "precision": args.precision, "rank_predictor": args.rank_predictor},
         "build_seconds": float(np.median(builds)),
-        "levels": st.levels, "max_rank": st.max_rank, "root_size": st.root_size,
+        "levels": st.levels, "max_rank": st.max_rank, "root_size": st.root_size, "root_level": st.root_level,
         "refine_iters": st.refine_iters, "refine_residual": st.refine_residual,
         "rank_fallbacks": st.rank_fallbacks, "sketch_bytes_max": st.sketch_bytes_max,
-        "roofline": {"bound": "mfma", "kernel": ("k_gemm<double, *, *> (complex FP64 MFMA GEMM, tuned tiles)" if fam == "zgemm"
-                                                 else "k_gemm<float> (complex FP32 MFMA GEMM)"),
-                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic() if fam == "zgemm" and wl.name == "wavy40" else None,
-                     "traffic_unit": "bytes per launch", "launches": prof["launches"],
-                     "avg_launch_ms": prof["ms"] / max(1, prof["launches"]),
-                     "flops_per_launch": prof["flops"] / max(1, prof["launches"])},
+        "roofline": roofline,
+        "rooflines": rl,
+        "kernel_families": fams,
     }
     if not args.no_verify:
-        res_h = {"eta": res["eta"].T.cpu().numpy(), "xi": res["xi"].T.cpu().numpy(), "flux": res["flux"]}
-        out["verify"] = verify(wl, res_h)
+        out["verify"] = verify(wl, host_solution(res))
+        if not out["verify"]["ok"]:
+            out["invalid"] = "the timed solution failed the residual / energy check: value withheld"
+            out["value"] = None
     del h, res
+    if not args.no_variants and args.precision == "fp64" and args.rank_predictor == "on":
+        variants = {}
+        for name, vkw in (("no_rank_predictor", dict(kw, rank_predictor=False)),
+                          ("fp32_preconditioner", dict(kw, precision="fp32"))):
+            hv, rv, tv, bv = run_steps(B, torch, wl, t_nodes, t_w, t_nrm, t_th, vkw, args.tol, cw, 3, 1)
+            sv = hv.stats()
+            vr = {"value": nang * 3 / tv, "unit": "angles/s", "ms_per_step": 1000.0 * tv / 3,
+                  "build_seconds": float(np.median(bv)), "refine_iters": sv.refine_iters,
+                  "refine_residual": sv.refine_residual, "root_level": sv.root_level}
+            if not args.no_verify:
+                vr["verify"] = verify(wl, host_solution(rv))
+                if not vr["verify"]["ok"]:
+                    vr["value"] = None
+            variants[name] = vr
+            del hv, rv
+        out["variants"] = variants
+    if not args.no_c5 and args.workload == "wavy40":
+        out["c5"] = c5_batch(B, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

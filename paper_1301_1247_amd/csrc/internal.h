@@ -139,12 +139,15 @@ hipError_t upload(DevBuf& buf, const std::vector<T>& v, hipStream_t s) {
 }
 
 // profiling of kernel families with HIP events
+// One event pair brackets the work issued in the scope; `launches` is the number of kernel
+// launches of the family it holds (the average launch duration is the summed time over them).
 struct ProfScope {
   const char* fam;
   hipStream_t s;
   double flops, bytes;
+  int launches;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  ProfScope(const char* fam, hipStream_t s, double flops, double bytes);
+  ProfScope(const char* fam, hipStream_t s, double flops, double bytes, int launches = 1);
   ~ProfScope();
 };
 

@@ -234,7 +234,8 @@ bool profile_read(const std::string& fam, double* ms, int64_t* launches, double*
   return true;
 }
 
-ProfScope::ProfScope(const char* f, hipStream_t st, double fl, double by) : fam(f), s(st), flops(fl), bytes(by) {
+ProfScope::ProfScope(const char* f, hipStream_t st, double fl, double by, int nl)
+    : fam(f), s(st), flops(fl), bytes(by), launches(nl) {
   if (!g_prof_on || !f) return;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     e0 = e1 = nullptr;
@@ -250,7 +251,7 @@ ProfScope::~ProfScope() {
   r.ev.emplace_back(e0, e1);
   r.flops += flops;
   r.bytes += bytes;
-  r.launches += 1;
+  r.launches += launches;
 }
 
 // ------------------------------------------------------------------ batched inversion
@@ -296,7 +297,10 @@ static hipError_t inv_launch(DevBuf& arena, DevBuf& work, const std::vector<InvD
   e = upload(arena, v, s);
   if (e != hipSuccess) return e;
   {
-    ProfScope ps(sizeof(R) == 8 ? "zinv" : "cinv", s, flops, 0.0);
+    // launches of the elimination kernel: one per 16-column panel plus one (n <= 1024), else three
+    // per 32-column panel
+    const int nlaunch = maxn <= 1024 ? (maxn + 15) / 16 + 1 : 3 * ((maxn + 31) / 32);
+    ProfScope ps(sizeof(R) == 8 ? "zinv" : "cinv", s, flops, 0.0, nlaunch);
     e = launch_inv<R>(arena.as<InvDescT<R>>(), nd, maxn, tbuf, ipiv, info, s);
     if (e != hipSuccess) return e;
   }

@@ -63,6 +63,9 @@ def init_params(x, seed=0):
     return p
 
 
+initial_params = init_params
+
+
 def coverage(params, x, k, margin=8.0):
     """Fraction of boxes whose rank stays below the predicted sketch (1.25 k^ + 16) minus the margin."""
     kp = np.exp(B.mlp_forward(params, x).astype(np.float64))

@@ -151,6 +151,25 @@ def rank_training_set(n: int = 64, seed: int = 4242):
     return out
 
 
+def c5_batch(n: int = 64, seed0: int = 1301500):
+    """The 64-obstacle batch of the learned-rank workload.  Obstacle i, from
+    ``numpy.random.default_rng(seed0 + i)`` in this order: N = integers(2000, 50001) rounded down to
+    even, omega = uniform(10, 80); the shape is ``wavy(seed0 + i, 20, 0.3)`` for even i (the
+    20-harmonic family) and ``wavy(seed0 + i, 40, 0.2)`` for odd i (the 40-harmonic family); 50
+    angles from ``random_angles(seed0 + i + 1, 50, omega, 2 pi)``; ID tolerance 1e-12.
+    Returns a list of dicts (curve, N, omega, period, thetas, tol)."""
+    out = []
+    for i in range(n):
+        s = seed0 + i
+        rng = np.random.default_rng(s)
+        N = int(rng.integers(2000, 50001)) // 2 * 2
+        omega = float(rng.uniform(10.0, 80.0))
+        K, cmax = (20, 0.3) if i % 2 == 0 else (40, 0.2)
+        out.append({"curve": wavy(s, K, cmax), "N": N, "omega": omega, "period": TWO_PI,
+                    "thetas": random_angles(s + 1, 50, omega, TWO_PI), "tol": 1e-12})
+    return out
+
+
 @dataclass
 class Workload:
     name: str
