@@ -177,6 +177,19 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
  *   rhs, out: N x nrhs complex (may not alias). */
 int hbs_apply(hbs_handle* h, const double* rhs, int64_t nrhs, double* out, int32_t refine);
 
+/* hbs_apply for callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same result as hbs_apply(h, rhs, nrhs, out, refine)
+ * (the same kernels), but every workspace of the call is carved from a static per-device scratch
+ * array of 64 MiB (each GPU holds it from the first such call on it until the process ends) and the
+ * call makes no hipMalloc / hipFree.  The handle must be built with HBS_PTR_DEVICE; rhs and out are
+ * device pointers (N x nrhs complex, may not alias); refine in [0, 16]; graph capture of the handle
+ * (hbs_opts.graph) is not used for this call.  Returns HBS_E_OOM, before any GPU work when the level,
+ * root and refinement buffers alone are too large, when the workspaces of nrhs columns exceed the
+ * scratch (about 5-8 MB per column at N = 1e5).  All calls on one GPU share its scratch, which keeps the
+ * last call's contents (every workspace is written before it is read): calls that overlap on one GPU
+ * (other threads, other streams) race and must be serialised by the caller. */
+int hbs_apply_noalloc(hbs_handle* h, const double* rhs, int64_t nrhs, double* out, int32_t refine);
+
 /* out = A x with the compressed forward operator (the telescoping factorization of Eq. 4.8
  * built from the same skeletons); relative accuracy ~ tol.  x, out: N x nrhs complex. */
 int hbs_forward(hbs_handle* h, const double* x, int64_t nrhs, double* out);

@@ -68,6 +68,7 @@ _sig = {
     "hbs_build": (C.c_int, [_P, _P, _P, C.c_int64, C.c_double, C.c_double, C.POINTER(HbsOpts), C.POINTER(_P)]),
     "hbs_apply": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32]),
     "hbs_forward": (C.c_int, [_P, _P, C.c_int64, _P]),
+    "hbs_apply_noalloc": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32]),
     "qp_solve": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, _P, C.c_int64, C.POINTER(QpOpts), _P, _P, _P, _P,
                            _P, _P]),
     "qp_solve_many": (C.c_int, [_P, C.c_double, _P, C.c_int64, C.POINTER(QpOpts), _P, _P, _P, _P, _P, _P]),
@@ -219,6 +220,16 @@ class Handle:
         out = np.empty_like(b)
         _check(_lib.hbs_apply(self._h, _ptr(b), b.shape[1], _ptr(out), int(refine)))
         return out[:, 0] if np.ndim(rhs) == 1 else out
+
+    def apply_noalloc(self, rhs, refine=0, out=None):
+        """hbs_apply_noalloc: device handles only; rhs torch (r, N) complex128 (column-major N x r)."""
+        if not self.device:
+            raise ValueError("apply_noalloc needs a handle built with device=True")
+        r = rhs.shape[0] if rhs.dim() == 2 else 1
+        if out is None:
+            out = self._torch.empty_like(rhs)
+        _check(_lib.hbs_apply_noalloc(self._h, _ptr(rhs), r, _ptr(out), int(refine)))
+        return out
 
     def forward(self, x):
         if self.device:

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqpscatter.so")
 
 SOURCES = ["kernels_build.hip", "gemm.hip", "gemm_tune.cpp", "kernels_qp.hip", "kernels_mlp.hip", "runtime.cpp",
-           "hbs.cpp", "qp.cpp", "wood.cpp", "capi.cpp"]
+           "hbs.cpp", "qp.cpp", "wood.cpp", "capi.cpp", "noalloc.cpp"]
 MODEL = os.path.join(HERE, "rank_mlp_default.json")
 TUNE = os.path.join(HERE, "gemm_tune_default.json")
 

@@ -106,6 +106,23 @@ struct BudgetScope {
   ~BudgetScope() { current_budget() = prev; }
 };
 
+// A caller-provided device region that buffers are carved from instead of the pool while a
+// BumpScope is active on the calling thread (the entry point that allocates nothing): a
+// reservation takes the next aligned piece, release gives nothing back, and a reservation beyond
+// the region fails with hipErrorOutOfMemory.
+struct BumpArena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  size_t refused = 0;  // size of the first refused reservation (0 = none)
+};
+BumpArena*& current_bump();
+struct BumpScope {
+  BumpArena* prev;
+  explicit BumpScope(BumpArena* b) : prev(current_bump()) { current_bump() = b; }
+  ~BumpScope() { current_bump() = prev; }
+};
+
 // Device buffer drawn from the library's per-device pool (runtime.cpp); grows, never shrinks.
 struct DevBuf {
   void* p = nullptr;
@@ -113,6 +130,7 @@ struct DevBuf {
   int dev = 0;
   MemBudget* budget = nullptr;  // the budget this buffer is charged to
   size_t charged = 0;           // bytes charged (the size asked of the pool)
+  bool borrowed = false;        // carved from a BumpArena: never returned to the pool
   hipError_t reserve(size_t b);
   void release();
   ~DevBuf() { release(); }

@@ -88,9 +88,26 @@ MemBudget*& current_budget() {
   return b;
 }
 
+BumpArena*& current_bump() {
+  static thread_local BumpArena* b = nullptr;
+  return b;
+}
+
 hipError_t DevBuf::reserve(size_t b) {
   if (b <= bytes) return hipSuccess;
   release();
+  if (BumpArena* ba = current_bump()) {
+    const size_t want = (b + 255) & ~(size_t)255;
+    if (ba->used + want > ba->cap) {
+      if (!ba->refused) ba->refused = want;
+      return hipErrorOutOfMemory;
+    }
+    p = ba->base + ba->used;
+    ba->used += want;
+    bytes = want;
+    borrowed = true;
+    return hipSuccess;
+  }
   const size_t want = round_size(b + b / 4 + 256);
   MemBudget* mb = current_budget();
   if (mb && mb->limit > 0 && mb->used + want > mb->limit) {
@@ -145,6 +162,12 @@ hipError_t DevBuf::reserve_pool(size_t want) {
 
 void DevBuf::release() {
   if (!p) return;
+  if (borrowed) {
+    p = nullptr;
+    bytes = 0;
+    borrowed = false;
+    return;
+  }
   if (budget) {
     budget->used -= charged;
     budget = nullptr;
