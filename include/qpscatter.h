@@ -40,7 +40,7 @@ enum {
   HBS_E_WOOD = -9           /* an angle is within qp_opts.wood_min_kn of a Wood's anomaly */
 };
 
-enum { HBS_QUAD_KR6 = 0, HBS_QUAD_KRESS = 1 };
+enum { HBS_QUAD_KR6 = 0, HBS_QUAD_KRESS = 1, HBS_QUAD_ALPERT = 2 };
 enum { HBS_COMPRESS_PROXY = 0, HBS_COMPRESS_EXACT = 1 };
 enum { HBS_PTR_HOST = 0, HBS_PTR_DEVICE = 1 };
 enum { HBS_FP64 = 0, HBS_FP32_PRECOND = 1 };
@@ -49,7 +49,12 @@ typedef struct hbs_handle hbs_handle;
 
 typedef struct {
   int32_t struct_size;      /* sizeof(hbs_opts); set by hbs_opts_init */
-  int32_t quad;             /* HBS_QUAD_KR6 (Sec. 2.3) or HBS_QUAD_KRESS (needs curvature) */
+  int32_t quad;             /* HBS_QUAD_KR6 (Sec. 2.3), HBS_QUAD_KRESS (needs curvature) or
+                               HBS_QUAD_ALPERT (Alpert's hybrid Gauss-trapezoidal correction, the
+                               alternative Sec. 2.3 names: 5 off-grid nodes on each side of the target,
+                               grid nodes closer than 6 left out, order about 11; the off-grid density
+                               and position are 12-point Lagrange interpolants of the node arrays, the
+                               normal and speed come from the interpolant's derivative) */
   int32_t compress;         /* HBS_COMPRESS_PROXY (proxy circles) or HBS_COMPRESS_EXACT
                                (true off-diagonal blocks; required with KRESS, O(N^2)) */
   int32_t leaf_size;        /* max points per leaf box; 0 -> 64 */
@@ -264,6 +269,11 @@ int qps_hankel01(const double* x, int64_t n, double* out, int32_t ptr_mode);
 /* The symmetric Kapur-Rokhlin 6th-order corrections g_1..g_6 (R_m = 1 + g_m, Sec. 2.3) as
  * derived by the library (host, long double). */
 int qps_kr6_corrections(double out[6]);
+/* Nodes x[m] (ascending, in (0, a)) and weights w[m] of Alpert's correction with m off-grid nodes
+ * per side and the grid nodes closer than a left out, as the library derives them (Newton's method in
+ * long double on the conditions of the generalized Euler-Maclaurin expansion, Sec. 2.3's named
+ * alternative to Kapur-Rokhlin); m in [1, 8], a in [1, 12]; HBS_E_NOT_CONVERGED if Newton fails. */
+int qps_alpert_rule(int32_t m, int32_t a, double* x, double* w);
 /* Entries A(rows[t], cols[t]) of the Nystrom matrix of the handle, evaluated on the GPU. */
 int qps_matrix_entries(hbs_handle* h, const int32_t* rows, const int32_t* cols, int64_t n, double* out);
 /* Batched complex GEMM C_b = A_b B_b (+ C_b if accumulate) on the GPU with the library's

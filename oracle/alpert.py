@@ -25,7 +25,7 @@ Off-grid values: the density at t_i + u h (u = +-x_j) is the Lagrange interpolan
 values at offsets floor(u) - NL/2 + 1 .. floor(u) + NL/2 (NL = 12), so A gains the entries
 A[i, i + o] += h w_j K(y_i, z(t_i + u h), n(t_i + u h)) |z'(t_i + u h)| L_o(u); the geometry there
 is the curve's own (this oracle evaluates the analytic curve; the GPU library interpolates its node
-arrays with the same stencil, an O(h^12) difference).
+positions with the same stencil and differentiates the interpolant for the normal and the speed).
 """
 from __future__ import annotations
 

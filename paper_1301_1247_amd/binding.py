@@ -23,7 +23,7 @@ _lib = C.CDLL(LIB_PATH)
 HBS_OK = 0
 ERRORS = {-1: "INVALID_ARG", -2: "NONFINITE", -3: "OOM", -4: "DEVICE", -6: "SINGULAR", -7: "NOT_CONVERGED",
           -8: "ALPHA_MISMATCH", -9: "WOOD"}
-QUAD = {"kr6": 0, "kress": 1}
+QUAD = {"kr6": 0, "kress": 1, "alpert": 2}
 COMPRESS = {"proxy": 0, "exact": 1}
 PTR_HOST, PTR_DEVICE = 0, 1
 
@@ -79,6 +79,7 @@ _sig = {
     "hbs_last_error": (C.c_char_p, []),
     "qps_hankel01": (C.c_int, [_P, C.c_int64, _P, C.c_int32]),
     "qps_kr6_corrections": (C.c_int, [_P]),
+    "qps_alpert_rule": (C.c_int, [C.c_int32, C.c_int32, _P, _P]),
     "qps_matrix_entries": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
     "qps_zgemm": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "qps_zinv": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32]),
@@ -308,6 +309,14 @@ def hankel01(x):
     out = np.empty(2 * x.shape[0], dtype=np.complex128)
     _check(_lib.qps_hankel01(_ptr(x), x.shape[0], _ptr(out), PTR_HOST))
     return out[: x.shape[0]], out[x.shape[0]:]
+
+
+def alpert_rule(m=5, a=6):
+    """Nodes and weights of the library's Alpert correction (derived on the host)."""
+    x = np.zeros(m)
+    w = np.zeros(m)
+    _check(_lib.qps_alpert_rule(int(m), int(a), _ptr(x), _ptr(w)))
+    return x, w
 
 
 def kr6_corrections():

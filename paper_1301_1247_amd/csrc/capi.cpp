@@ -69,6 +69,117 @@ void kr6_corrections(double out[6]) {
   for (int c = 0; c < 6; ++c) out[c] = (double)(a[c][6] / a[c][c]);
 }
 
+// Alpert's hybrid Gauss-trapezoidal correction (Sec. 2.3 names it as the alternative to
+// Kapur-Rokhlin): the grid nodes closer than a to the target are left out and m nodes t_i +- x_j h
+// (weights h w_j) are added on each side.  Exactness for phi(s) ln|s| + psi(s) with phi, psi of degree
+// < 2m follows from the error h^{p+1} [2 zeta(-p) ln h - 2 zeta'(-p)] of the punctured trapezoid rule
+// on |s|^p ln|s|: for even p < 2m,
+//   sum_j w_j x_j^p = sum_{k<a} k^p - zeta(-p),   sum_j w_j x_j^p ln x_j = sum_{k<a} k^p ln k + zeta'(-p),
+// zeta(0) = -1/2, zeta(-p) = 0 (p > 0), zeta'(0) = -ln(2 pi)/2, zeta'(-2q) = (-1)^q (2q)! zeta(2q+1) / (2 (2 pi)^{2q}).
+// Newton's method in long double from x_j = a (j + 1/2) / m, w_j = (a - 1/2) / m, each step halved until
+// the nodes stay positive; returns the nodes ascending.
+// the rule the library uses: 5 off-grid nodes per side, 6 grid nodes left out, 12-point interpolation
+constexpr int kAlpM = 5, kAlpA = 6, kAlpNL = 12;
+
+bool alpert_rule(int m, int a, long double* xo, long double* wo) {
+  const long double pi = std::acos(-1.0L);
+  const int n2 = 2 * m;
+  std::vector<long double> A(m), B(m), x(m), w(m);
+  for (int q = 0; q < m; ++q) {
+    const int p = 2 * q;
+    long double sa = 0, sb = 0;
+    for (int k = 1; k < a; ++k) {
+      const long double kp = std::pow((long double)k, (long double)p);
+      sa += kp;
+      sb += kp * std::log((long double)k);
+    }
+    long double zp;  // zeta'(-p)
+    if (q == 0) {
+      zp = -0.5L * std::log(2.0L * pi);
+    } else {
+      long double fact = 1;
+      for (int t = 2; t <= 2 * q; ++t) fact *= t;
+      zp = ((q & 1) ? -1.0L : 1.0L) * fact * zeta_ld(2 * q + 1) / (2.0L * std::pow(2.0L * pi, (long double)(2 * q)));
+    }
+    A[q] = sa + (q == 0 ? 0.5L : 0.0L);
+    B[q] = sb + zp;
+  }
+  for (int j = 0; j < m; ++j) {
+    x[j] = (long double)a * (j + 0.5L) / m;
+    w[j] = ((long double)a - 0.5L) / m;
+  }
+  bool done = false;
+  int conv = 0;  // steps taken since the step size fell to rounding level (a few more polish the root)
+  for (int it = 0; it < 200 && !done; ++it) {
+    std::vector<long double> J((size_t)n2 * n2), F(n2);
+    for (int q = 0; q < m; ++q) {
+      const int p = 2 * q;
+      long double f1 = -A[q], f2 = -B[q];
+      for (int j = 0; j < m; ++j) {
+        const long double xp = std::pow(x[j], (long double)p), lx = std::log(x[j]);
+        const long double xp1 = p ? std::pow(x[j], (long double)(p - 1)) : 0.0L;
+        f1 += w[j] * xp;
+        f2 += w[j] * xp * lx;
+        J[q * n2 + j] = xp;
+        J[q * n2 + m + j] = w[j] * p * xp1;
+        J[(m + q) * n2 + j] = xp * lx;
+        J[(m + q) * n2 + m + j] = w[j] * std::pow(x[j], (long double)(p - 1)) * (p * lx + 1.0L);
+      }
+      F[q] = f1;
+      F[m + q] = f2;
+    }
+    // Gaussian elimination with partial pivoting: d = J^{-1} F
+    for (int c = 0; c < n2; ++c) {
+      int pr = c;
+      for (int r = c + 1; r < n2; ++r)
+        if (std::fabs(J[r * n2 + c]) > std::fabs(J[pr * n2 + c])) pr = r;
+      if (J[pr * n2 + c] == 0.0L) return false;
+      for (int k = 0; k < n2; ++k) std::swap(J[c * n2 + k], J[pr * n2 + k]);
+      std::swap(F[c], F[pr]);
+      for (int r = c + 1; r < n2; ++r) {
+        const long double f = J[r * n2 + c] / J[c * n2 + c];
+        for (int k = c; k < n2; ++k) J[r * n2 + k] -= f * J[c * n2 + k];
+        F[r] -= f * F[c];
+      }
+    }
+    std::vector<long double> d(n2);
+    for (int r = n2 - 1; r >= 0; --r) {
+      long double t = F[r];
+      for (int k = r + 1; k < n2; ++k) t -= J[r * n2 + k] * d[k];
+      d[r] = t / J[r * n2 + r];
+    }
+    long double lam = 1.0L;
+    std::vector<long double> xn(m);
+    for (int h = 0; h < 60; ++h) {
+      bool pos = true;
+      for (int j = 0; j < m; ++j) {
+        xn[j] = x[j] - lam * d[m + j];
+        pos = pos && xn[j] > 0;
+      }
+      if (pos) break;
+      lam *= 0.5L;
+    }
+    long double step = 0, size = 0;
+    for (int j = 0; j < m; ++j) {
+      step = std::max(step, std::fabs(lam * d[j]) + std::fabs(lam * d[m + j]));
+      size = std::max(size, std::fabs(w[j]) + std::fabs(x[j]));
+      w[j] -= lam * d[j];
+      x[j] = xn[j];
+    }
+    if (lam == 1.0L && step <= 1e-14L * size) ++conv;
+    done = conv >= 4;
+  }
+  if (!done) return false;
+  std::vector<int> ord(m);
+  for (int j = 0; j < m; ++j) ord[j] = j;
+  std::sort(ord.begin(), ord.end(), [&](int p, int q) { return x[p] < x[q]; });
+  for (int j = 0; j < m; ++j) {
+    xo[j] = x[ord[j]];
+    wo[j] = w[ord[j]];
+  }
+  return true;
+}
+
 // Kress weights R(t_m) = -(2 pi / n) sum_{k=1}^{n-1} cos(k t_m) / k - (pi / n^2) cos(n t_m), t_m = 2 pi m / N
 std::vector<double> kress_weights(int64_t N) {
   const int64_t n = N / 2;
@@ -179,7 +290,10 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
   if (!nodes || !weights || !normals) { set_error("hbs_build: NULL geometry pointer"); return HBS_E_INVALID_ARG; }
   if (!(omega > 0) || !std::isfinite(omega)) { set_error("hbs_build: omega must be positive and finite"); return HBS_E_INVALID_ARG; }
   if (!(tol >= 1e-15 && tol <= 1e-2)) { set_error("hbs_build: tol must lie in [1e-15, 1e-2]"); return HBS_E_INVALID_ARG; }
-  if (o.quad != HBS_QUAD_KR6 && o.quad != HBS_QUAD_KRESS) { set_error("hbs_build: unknown quadrature"); return HBS_E_INVALID_ARG; }
+  if (o.quad != HBS_QUAD_KR6 && o.quad != HBS_QUAD_KRESS && o.quad != HBS_QUAD_ALPERT) {
+    set_error("hbs_build: unknown quadrature");
+    return HBS_E_INVALID_ARG;
+  }
   if (o.compress != HBS_COMPRESS_PROXY && o.compress != HBS_COMPRESS_EXACT) { set_error("hbs_build: unknown compression"); return HBS_E_INVALID_ARG; }
   if (o.ptr_mode != HBS_PTR_HOST && o.ptr_mode != HBS_PTR_DEVICE) { set_error("hbs_build: unknown ptr_mode"); return HBS_E_INVALID_ARG; }
   if (o.precision != HBS_FP64 && o.precision != HBS_FP32_PRECOND) { set_error("hbs_build: unknown precision"); return HBS_E_INVALID_ARG; }
@@ -192,6 +306,12 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
     return HBS_E_INVALID_ARG;
   }
   if (o.quad == HBS_QUAD_KR6 && N < 13) { set_error("hbs_build: KR6 needs N >= 13"); return HBS_E_INVALID_ARG; }
+  if (o.quad == HBS_QUAD_ALPERT) {
+    // the corrected band reaches kAlpA + kAlpNL / 2 - 1 = 11 nodes from the target: it must stay inside
+    // the target's box and its index neighbours, and away from its own periodic image
+    if (N < 2 * (kAlpA + kAlpNL / 2) + 1) { set_error("hbs_build: Alpert quadrature needs N >= 25"); return HBS_E_INVALID_ARG; }
+    if (o.leaf_size < kAlpA + kAlpNL / 2) { set_error("hbs_build: Alpert quadrature needs leaf_size >= 12"); return HBS_E_INVALID_ARG; }
+  }
   if (o.quad == HBS_QUAD_KRESS) {
     if (N % 2) { set_error("hbs_build: Kress quadrature needs even N"); return HBS_E_INVALID_ARG; }
     if (!o.curvature) { set_error("hbs_build: Kress quadrature needs opts->curvature"); return HBS_E_INVALID_ARG; }
@@ -265,6 +385,58 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
       return fail(HBS_E_DEVICE);
     }
     G.kressR = h->dkressR.as<double>();
+  }
+  G.alpT = nullptr;
+  G.alpL = nullptr;
+  G.alpn = G.alpnl = G.alpa = 0;
+  if (o.quad == HBS_QUAD_ALPERT) {
+    long double xl[kAlpM], wl[kAlpM];
+    if (!alpert_rule(kAlpM, kAlpA, xl, wl)) {
+      set_error("hbs_build: the Alpert rule's Newton iteration did not converge");
+      return fail(HBS_E_NOT_CONVERGED);
+    }
+    // off-grid node q: u = +x_q (q < m) or -x_{q-m}; 12-point Lagrange stencil at offsets floor(u) - 5 ..
+    const int nq = 2 * kAlpM;
+    std::vector<double> L((size_t)nq * kAlpNL), D((size_t)nq * kAlpNL), wq(nq);
+    for (int q = 0; q < nq; ++q) {
+      const long double u = q < kAlpM ? xl[q] : -xl[q - kAlpM];
+      const int o0 = (int)std::floor((double)u) - kAlpNL / 2 + 1;
+      G.alpo[q] = o0;
+      wq[q] = (double)wl[q % kAlpM];
+      for (int r = 0; r < kAlpNL; ++r) {
+        // L_r(u) and its derivative L_r(u) sum_{t != r} 1 / (u - o_t) (u is never a grid offset)
+        long double v = 1.0L, dsum = 0.0L;
+        for (int t = 0; t < kAlpNL; ++t)
+          if (t != r) {
+            v *= (u - (long double)(o0 + t)) / (long double)(r - t);
+            dsum += 1.0L / (u - (long double)(o0 + t));
+          }
+        L[(size_t)q * kAlpNL + r] = (double)v;
+        D[(size_t)q * kAlpNL + r] = (double)(v * dsum);
+      }
+    }
+    G.alpn = nq;
+    G.alpnl = kAlpNL;
+    G.alpa = kAlpA;
+    if (h->dalp.reserve(sizeof(double) * (2 * L.size() + wq.size())) != hipSuccess ||
+        h->dalpT.reserve(sizeof(cplx) * (size_t)N * nq) != hipSuccess) {
+      set_error("hbs_build: out of device memory (Alpert tables)");
+      return fail(HBS_E_OOM);
+    }
+    double* dl = h->dalp.as<double>();
+    if (hipMemcpy(dl, L.data(), sizeof(double) * L.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dl + L.size(), D.data(), sizeof(double) * D.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dl + 2 * L.size(), wq.data(), sizeof(double) * wq.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("hbs_build: Alpert table upload failed");
+      return fail(HBS_E_DEVICE);
+    }
+    G.alpL = dl;
+    if (launch_alpert_table(G, dl + L.size(), dl + 2 * L.size(), h->dalpT.as<cplx>(), h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+      set_error("hbs_build: Alpert kernel table failed");
+      return fail(HBS_E_DEVICE);
+    }
+    G.alpT = h->dalpT.as<cplx>();
   }
   if (o.rank_predictor) {
     const float* src = o.rank_model ? o.rank_model : kRankModelDefault;
@@ -472,6 +644,18 @@ int qps_hankel01(const double* x, int64_t n, double* out, int32_t ptr_mode) {
   } else {
     CKD(launch_hankel(x, n, reinterpret_cast<cplx*>(out), nullptr));
     CKD(hipDeviceSynchronize());
+  }
+  return HBS_OK;
+}
+
+int qps_alpert_rule(int32_t m, int32_t a, double* x, double* w) {
+  clear_error();
+  if (!x || !w || m < 1 || m > 8 || a < 1 || a > 12) { set_error("qps_alpert_rule: bad arguments"); return HBS_E_INVALID_ARG; }
+  long double xl[8], wl[8];
+  if (!alpert_rule(m, a, xl, wl)) { set_error("qps_alpert_rule: Newton did not converge"); return HBS_E_NOT_CONVERGED; }
+  for (int j = 0; j < m; ++j) {
+    x[j] = (double)xl[j];
+    w[j] = (double)wl[j];
   }
   return HBS_OK;
 }

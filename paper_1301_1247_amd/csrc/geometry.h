@@ -75,6 +75,31 @@ __device__ inline cplx a_entry_kress(const Geo& G, int i, int j) {
   return mkc(a.x + pin * b.x, a.y + pin * b.y);
 }
 
+// Alpert's hybrid Gauss-trapezoidal correction (Sec. 2.3 names it beside Kapur-Rokhlin): the grid
+// nodes closer than a to the target (periodic index distance) are left out, and the off-grid nodes
+// t_i +- x_l h carry the density as its Lagrange interpolant from the G.alpnl grid values at
+// offsets G.alpo[q] .. G.alpo[q] + alpnl - 1 (q = one of the 2m off-grid nodes), weights G.alpL.
+// The kernel part of node q of row i, h w_l K(y_i, z(t_i + u_q h), n(...)) |z'(...)|, is the table
+// G.alpT[i + q N] built once per handle, so
+//   A_ij = delta_ij/2 + [dist(i, j) >= a] K(y_i, y_j, n_j) w_j + sum_q alpT[i, q] L_q(j - i).
+__device__ inline cplx a_entry_alpert(const Geo& G, int i, int j) {
+  const int N = G.N;
+  int d = j - i;
+  if (d > N / 2) d -= N;
+  if (d < -(N - 1) / 2) d += N;
+  cplx v = mkc(i == j ? 0.5 : 0.0, 0.0);
+  if (d >= G.alpa || -d >= G.alpa) {
+    const cplx K = helm_kernel(G.omega, G.x[i] - G.x[j], G.y[i] - G.y[j], G.nx[j], G.ny[j]);
+    v = cadd(v, cscale(K, G.w[j]));
+  }
+  for (int q = 0; q < G.alpn; ++q) {
+    const int r = d - G.alpo[q];
+    if (r >= 0 && r < G.alpnl) v = cadd(v, cscale(G.alpT[i + (size_t)q * N], G.alpL[q * G.alpnl + r]));
+  }
+  return v;
+}
+
 __device__ inline cplx a_entry(const Geo& G, int i, int j) {
+  if (G.quad == HBS_QUAD_ALPERT) return a_entry_alpert(G, i, j);
   return G.quad == HBS_QUAD_KRESS ? a_entry_kress(G, i, j) : a_entry_kr6(G, i, j);
 }

@@ -52,6 +52,7 @@ struct hbs_handle {
   int L = 0;
   std::vector<double> hx, hy, hnx, hny, hw, hkap;
   qps::DevBuf dgeo, dkressR;
+  qps::DevBuf dalp, dalpT;  // Alpert correction: Lagrange weights + node weights, kernel table (N x 2m)
   Geo geo{};
   std::vector<qps::Level> lv;  // lv[1..L]
   int nroot = 0;

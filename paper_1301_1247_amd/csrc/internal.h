@@ -7,6 +7,8 @@
 
 // Geometry of the discretized curve (structure of arrays, device pointers) and the
 // quadrature data needed to evaluate entries of A = I/2 + D - i omega S.
+#define QPS_ALPERT_MAXQ 16
+
 struct Geo {
   const double *x, *y, *nx, *ny, *w;
   const double* kap;     // Kress: signed curvature
@@ -15,6 +17,13 @@ struct Geo {
   int quad;
   double omega;
   double g[6];           // Kapur-Rokhlin corrections, R_m = 1 + g_m
+  // Alpert correction (quad == HBS_QUAD_ALPERT): grid nodes closer than alpa are left out; alpn
+  // off-grid nodes q carry the kernel table alpT[i + q N] and Lagrange weights alpL[q alpnl + r] of
+  // the grid offsets alpo[q] + r (r < alpnl)
+  const cplx* alpT;
+  const double* alpL;
+  int alpn, alpnl, alpa;
+  int alpo[QPS_ALPERT_MAXQ];
 };
 
 // A batch entry of the block evaluator: out[r + c*ld] = A(rows[r], cols[c]), or
@@ -171,6 +180,9 @@ struct ProfScope {
 
 // launchers (device code in kernels_build.hip / gemm.hip / kernels_qp.hip)
 hipError_t launch_eval_blocks(const Geo& g, const BlockDesc* d, int nd, int max_elems, hipStream_t s);
+// Alpert correction: T[i + q N] = wq[q] K(y_i, z_q, n_q) h |z'_q| at the interpolated off-grid node q of row i
+// (D: derivative weights of the interpolants, laid out like Geo::alpL)
+hipError_t launch_alpert_table(const Geo& g, const double* D, const double* wq, cplx* T, hipStream_t s);
 hipError_t launch_proxy(const Geo& g, const ProxyDesc* d, int nd, int max_elems, hipStream_t s);
 hipError_t launch_sketch(const SketchDesc* d, int nd, int max_s, int max_n, uint64_t seed, hipStream_t s);
 // ws: workspace for the few-large-boxes path (one launch per pivot step); nullptr: one workgroup per box

@@ -1006,6 +1006,36 @@ __global__ void k_hankel(const double* __restrict__ x, int64_t n, cplx* __restri
   }
 }
 
+// Kernel table of the Alpert correction, one thread per (node i, off-grid node q): the position at
+// t_i + u_q h is the Lagrange interpolant of the node positions (weights G.alpL, offsets G.alpo[q] ..),
+// its parameter derivative that of the interpolant (weights D, divided by h), whence the speed |z'|,
+// the outward normal (z2', -z1') / |z'| and the quadrature weight h |z'|:
+//   alpT[i + q N] = wq[q] K(y_i, z, n) h |z'|.
+__global__ __launch_bounds__(NT) void k_alpert_table(Geo G, const double* __restrict__ D, const double* __restrict__ wq,
+                                                     cplx* __restrict__ T) {
+  const int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x;
+  const int N = G.N;
+  if (e >= (int64_t)N * G.alpn) return;
+  const int i = (int)(e % N);
+  const int q = (int)(e / N);
+  const double h = 2.0 * QPS_PI / N;
+  double zx = 0, zy = 0, dx = 0, dy = 0;
+  for (int r = 0; r < G.alpnl; ++r) {
+    int k = i + G.alpo[q] + r;
+    k = ((k % N) + N) % N;
+    const double L = G.alpL[q * G.alpnl + r], Dr = D[q * G.alpnl + r];
+    zx += L * G.x[k];
+    zy += L * G.y[k];
+    dx += Dr * G.x[k];
+    dy += Dr * G.y[k];
+  }
+  dx /= h;
+  dy /= h;
+  const double sp = sqrt(dx * dx + dy * dy);
+  const cplx K = helm_kernel(G.omega, G.x[i] - zx, G.y[i] - zy, dy / sp, -dx / sp);
+  T[i + (size_t)q * N] = cscale(K, wq[q] * h * sp);
+}
+
 __global__ void k_entries(Geo G, const int* __restrict__ rows, const int* __restrict__ cols, int64_t n, cplx* __restrict__ out) {
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT)
     out[e] = a_entry(G, rows[e], cols[e]);
@@ -1141,6 +1171,12 @@ hipError_t launch_eval_shift(const Geo& g, const int* rows, int nr, double shift
 hipError_t launch_hankel(const double* x, int64_t n, cplx* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_hankel, dim3(grid_for(n)), dim3(NT), 0, s, x, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_alpert_table(const Geo& g, const double* D, const double* wq, cplx* T, hipStream_t s) {
+  const int64_t n = (int64_t)g.N * g.alpn;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_alpert_table, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, g, D, wq, T);
   return hipGetLastError();
 }
 hipError_t launch_entries(const Geo& g, const int* rows, const int* cols, int64_t n, cplx* out, hipStream_t s) {

@@ -200,3 +200,20 @@ def test_opts_struct_size_matches_binding():
     assert o.mem_limit == 0
     q = B.qp_opts()
     assert q.struct_size == C.sizeof(B.QpOpts)
+
+
+def test_alpert_rule_derived_by_the_library_matches_oracle():
+    """The library derives Alpert's nodes and weights itself (long double Newton); the oracle does
+    it independently in 50-digit arithmetic.  One set of numbers, so they must agree."""
+    from oracle import alpert as al
+    from paper_1301_1247_amd import binding as B
+    for m, a in ((2, 2), (3, 3), (5, 6)):
+        x, w = B.alpert_rule(m, a)
+        xo, wo = al.rule(m, a)
+        assert np.abs(x - xo).max() < 1e-13 and np.abs(w - wo).max() < 1e-13
+
+
+def test_alpert_needs_room_for_its_band():
+    nodes, w, nrm, _ = _geom(256)
+    rc, msg = _build(nodes, w, nrm, 256, quad=2, leaf_size=8)
+    assert rc == -1 and "leaf_size" in msg
