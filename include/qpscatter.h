@@ -67,7 +67,8 @@ typedef struct {
   double far_radius;        /* > 0: every skeleton also represents sources and targets outside the
                                circle of this radius about the centre of the nodes' bounding box
                                (needed by qp_solve with P >= 1, whose neighbour images must lie
-                               outside it, and by qp_opts.compress_walls); 0 = off */
+                               outside it unless image_period is set, and by
+                               qp_opts.compress_walls); 0 = off */
   int32_t precision;        /* HBS_FP64: inverse factors in complex128.  HBS_FP32_PRECOND: the inverse
                                factors of the deep levels are built and applied in complex64 on FP32
                                matrix cores and serve as a preconditioner; skeletons, the forward
@@ -98,6 +99,14 @@ typedef struct {
                                are counted at the size requested from the library's pool); a call
                                that would exceed it fails with HBS_E_OOM before allocating, and
                                hbs_last_error names the limit.  0 = no limit */
+  double image_period;      /* > 0: the skeletons also represent the obstacle's two neighbour images at
+                               +-image_period along x (Sec. 3.2, the near points of Fig. 3.1): the
+                               active points of every image box that comes inside a box's proxy circle
+                               (inside far_radius for a box without proxies) are explicit columns of
+                               its interpolative decomposition, in both directions.  Then
+                               A_{+-1} = U A_{+-1}(J, :) holds however close the images come, and
+                               qp_solve with P = 1 and this period needs no separation of the images
+                               from far_radius.  Needs far_radius > 0; 0 = off */
 } hbs_opts;
 
 typedef struct {
@@ -159,6 +168,8 @@ typedef struct {
   int32_t wood_angles;      /* angles of the last qp_solve solved on a displaced contour */
   int32_t wood_orders;      /* Rayleigh-Bloch waves added for them (summed over Bloch phases) */
   double wood_shift;        /* real-axis crossing of the last displaced contour (0 = none) */
+  int64_t image_samples;    /* image points taken as explicit columns over all boxes and levels
+                               (hbs_opts.image_period) */
 } hbs_stats_t;
 
 void hbs_opts_init(hbs_opts* o);

@@ -301,6 +301,14 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
   if (o.graph != 0 && o.graph != 1) { set_error("hbs_build: graph must be 0 or 1"); return HBS_E_INVALID_ARG; }
   if (o.root_level < 0 || o.root_level > 2) { set_error("hbs_build: root_level must be 0, 1 or 2"); return HBS_E_INVALID_ARG; }
   if (o.rank_scale < 0 || !std::isfinite(o.rank_scale)) { set_error("hbs_build: rank_scale must be >= 0"); return HBS_E_INVALID_ARG; }
+  if (!(o.image_period >= 0) || !std::isfinite(o.image_period)) {
+    set_error("hbs_build: image_period must be finite and >= 0");
+    return HBS_E_INVALID_ARG;
+  }
+  if (o.image_period > 0 && !(o.far_radius > 0)) {
+    set_error("hbs_build: image_period needs far_radius > 0 (the far-field circle represents the images beyond it)");
+    return HBS_E_INVALID_ARG;
+  }
   if (o.rank_predictor && !o.rank_model && kRankModelDefaultN != MLP_NPARAM) {
     set_error("hbs_build: the library has no built-in rank model; pass hbs_opts.rank_model");
     return HBS_E_INVALID_ARG;

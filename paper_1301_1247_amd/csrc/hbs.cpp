@@ -107,6 +107,7 @@ int build(hbs_handle* h) {
     }
   }
   const bool far_on = h->opts.far_radius > 0;
+  const bool img_on = h->opts.image_period > 0;
   const double Rfar = far_on ? std::sqrt(h->robs * h->opts.far_radius) : 0.0;
   const int npfar = far_on ? std::max(pmin, 2 * (int)std::ceil(om * Rfar + std::log(1.0 / h->tol) /
                                                                   std::log(Rfar / h->robs)) + 8) : 0;
@@ -188,6 +189,7 @@ int build(hbs_handle* h) {
   h->stats.rank_fallbacks = 0;
   h->stats.sketch_bytes_max = 0;
   h->stats.cpqr_work = 0.0;
+  h->stats.image_samples = 0;
 
   DevBuf dnear, wt, zb, zb2, kout, tmpY, tmpZt;
   DevBuf& arena = h->arena;
@@ -382,9 +384,9 @@ int build(hbs_handle* h) {
     CK(hipStreamWaitEvent(sf, ev_act, 0));
 
     // ---- compression matrices
-    std::vector<int> nnear(nb), np(nb), npf(nb), m(nb), s(nb);
-    std::vector<int64_t> noff(nb + 1, 0), woff(nb + 1, 0), zoff(nb + 1, 0);
-    std::vector<int> hnear;
+    std::vector<int> nnear(nb), np(nb), npf(nb), m(nb), s(nb), nimg(nb, 0), nimgp(nb, 0);
+    std::vector<int64_t> noff(nb + 1, 0), woff(nb + 1, 0), zoff(nb + 1, 0), ioff(nb + 1, 0);
+    std::vector<int> hnear, himg;
     // candidate boxes from a uniform grid of box centres (cell = the largest near distance), so
     // the near lists cost O(nb) instead of O(nb^2); exact compression takes every box
     double maxrad = 0, gx0 = 1e300, gy0 = 1e300;
@@ -468,7 +470,36 @@ int build(hbs_handle* h) {
       // circle lies inside far_radius, else by proxies on the far-field circle
       const bool inside = !full && std::hypot(V.cx[b] - h->c0x, V.cy[b] - h->c0y) + Rp < h->opts.far_radius;
       npf[b] = (far_on && !inside) ? npfar : 0;
-      m[b] = 2 * cnt + 3 * np[b] + 3 * npf[b];
+      // near points of the neighbour images (Sec. 3.2, Fig. 3.1): the active points of every image
+      // box that comes inside this box's proxy circle (inside far_radius when the box has no
+      // proxies of its own) join the sample in both directions, like the near boxes above; the
+      // images at +d first, then at -d
+      if (img_on)
+        for (int sg = 0; sg < 2; ++sg) {
+          const double sx = sg == 0 ? h->opts.image_period : -h->opts.image_period;
+          cand.clear();
+          if (allc || np[b] == 0) {
+            for (int c = 0; c < nb; ++c) cand.push_back(c);
+          } else {
+            int64_t ix, iy;
+            cell_of(V.cx[b] - sx, V.cy[b], &ix, &iy);
+            for (int64_t jy = std::max<int64_t>(0, iy - 1); jy <= std::min<int64_t>(ncy - 1, iy + 1); ++jy)
+              for (int64_t jx = std::max<int64_t>(0, ix - 1); jx <= std::min<int64_t>(ncx - 1, ix + 1); ++jx)
+                for (int c = head_find(jx + ncx * jy); c >= 0; c = cell_next[c]) cand.push_back(c);
+          }
+          for (int c : cand) {
+            const double ix = V.cx[c] + sx, iy = V.cy[c];
+            const bool nr = np[b] > 0 ? std::hypot(ix - V.cx[b], iy - V.cy[b]) < Rp + V.rad[c]
+                                      : std::hypot(ix - h->c0x, iy - h->c0y) < h->opts.far_radius + V.rad[c];
+            if (!nr) continue;
+            himg.insert(himg.end(), V.hact.begin() + V.aoff[c], V.hact.begin() + V.aoff[c] + V.n[c]);
+            nimg[b] += V.n[c];
+            if (sg == 0) nimgp[b] += V.n[c];
+          }
+        }
+      ioff[b + 1] = ioff[b] + nimg[b];
+      h->stats.image_samples += nimg[b];
+      m[b] = 2 * cnt + 2 * nimg[b] + 3 * np[b] + 3 * npf[b];
       s[b] = (m[b] > 2 * V.n[b] + 8) ? 2 * V.n[b] + 8 : m[b];
       noff[b + 1] = noff[b] + cnt;
       woff[b + 1] = woff[b] + (int64_t)m[b] * V.n[b];
@@ -555,9 +586,11 @@ int build(hbs_handle* h) {
     cplx* dwt = nullptr;
     cplx* dz = nullptr;
     if (!ident) {
-    CK(dnear.reserve(sizeof(int) * std::max<int64_t>(1, noff[nb])));
+    CK(dnear.reserve(sizeof(int) * std::max<int64_t>(1, noff[nb] + ioff[nb])));
     if (noff[nb] > 0)
       CK(hipMemcpyAsync(dnear.p, hnear.data(), sizeof(int) * noff[nb], hipMemcpyHostToDevice, st));
+    if (ioff[nb] > 0)
+      CK(hipMemcpyAsync(dnear.as<int>() + noff[nb], himg.data(), sizeof(int) * ioff[nb], hipMemcpyHostToDevice, st));
     CK(wt.reserve(sizeof(cplx) * std::max<int64_t>(1, woff[nb])));
     dwt = wt.as<cplx>();
     const int* dn = dnear.as<int>();
@@ -571,6 +604,21 @@ int build(hbs_handle* h) {
         bd.push_back({dn + noff[b], dact + V.aoff[b], dwt + woff[b] + nnear[b], nnear[b], n, m[b], 0});
         maxb = std::max(maxb, nnear[b] * n);
       }
+      // image rows [2 nnear, 2 nnear + 2 nimg): sources at the images, then targets there; each
+      // in the +d part and the -d part
+      for (int b = 0; b < nb; ++b) {
+        const int n = V.n[b];
+        const int* ib = dn + noff[nb] + ioff[b];
+        cplx* w0 = dwt + woff[b] + 2 * nnear[b];
+        const int part[2] = {nimgp[b], nimg[b] - nimgp[b]};
+        const double sxs[2] = {h->opts.image_period, -h->opts.image_period};
+        for (int sg = 0, o = 0; sg < 2; o += part[sg], ++sg) {
+          if (part[sg] == 0) continue;
+          bd.push_back({ib + o, dact + V.aoff[b], w0 + o, part[sg], n, m[b], 1, sxs[sg]});
+          bd.push_back({ib + o, dact + V.aoff[b], w0 + nimg[b] + o, part[sg], n, m[b], 0, sxs[sg]});
+          maxb = std::max(maxb, part[sg] * n);
+        }
+      }
       if (!bd.empty()) {
         CK(up_sync(arena, bd, st));
         ProfScope ps("assemble", st, 0.0, 0.0);
@@ -580,13 +628,13 @@ int build(hbs_handle* h) {
       int maxp = 0;
       for (int b = 0; b < nb; ++b) {
         if (np[b] == 0) continue;
-        pd.push_back({dact + V.aoff[b], dwt + woff[b], V.n[b], m[b], 2 * nnear[b], np[b], V.cx[b], V.cy[b],
+        pd.push_back({dact + V.aoff[b], dwt + woff[b], V.n[b], m[b], 2 * nnear[b] + 2 * nimg[b], np[b], V.cx[b], V.cy[b],
                       ratio * V.rad[b]});
         maxp = std::max(maxp, np[b] * V.n[b]);
       }
       for (int b = 0; b < nb; ++b) {
         if (npf[b] == 0) continue;
-        pd.push_back({dact + V.aoff[b], dwt + woff[b], V.n[b], m[b], 2 * nnear[b] + 3 * np[b], npf[b], h->c0x, h->c0y,
+        pd.push_back({dact + V.aoff[b], dwt + woff[b], V.n[b], m[b], 2 * nnear[b] + 2 * nimg[b] + 3 * np[b], npf[b], h->c0x, h->c0y,
                       Rfar});
         maxp = std::max(maxp, npf[b] * V.n[b]);
       }

@@ -33,6 +33,10 @@ struct BlockDesc {
   const int* cols;
   cplx* out;
   int nr, nc, ld, trans;
+  // != 0: the `rows` points stand for their neighbour images translated by (sx, 0) (Sec. 3.2): the
+  // entries are the plain kernel (no quadrature correction), with the image as source (trans = 1)
+  // or as target (trans = 0)
+  double sx;
 };
 
 // Proxy part of the compression matrix of one box: rows [row0, row0 + 3 np) of W^T

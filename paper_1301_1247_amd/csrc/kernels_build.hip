@@ -14,7 +14,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   for (int e = blockIdx.x * NT + threadIdx.x; e < total; e += gridDim.x * NT) {
     const int r = e % d.nr, c = e / d.nr;
     const int gr = d.rows[r], gc = d.cols[c];
-    d.out[r + (size_t)c * d.ld] = d.trans ? a_entry(G, gc, gr) : a_entry(G, gr, gc);
+    cplx v;
+    if (d.sx != 0.0) {
+      // image point y_gr + (sx, 0): source of the field at x_gc (trans) or target of the field of x_gc
+      v = d.trans ? cscale(helm_kernel(G.omega, G.x[gc] - G.x[gr] - d.sx, G.y[gc] - G.y[gr], G.nx[gr], G.ny[gr]), G.w[gr])
+                  : cscale(helm_kernel(G.omega, G.x[gr] + d.sx - G.x[gc], G.y[gr] - G.y[gc], G.nx[gc], G.ny[gc]), G.w[gc]);
+    } else {
+      v = d.trans ? a_entry(G, gc, gr) : a_entry(G, gr, gc);
+    }
+    d.out[r + (size_t)c * d.ld] = v;
   }
 }
 

@@ -101,7 +101,8 @@ int qp_contour_M(const hbs_handle* h, double period, const qp_opts* o) {
 //
 // With P neighbour images (Sec. 2.4) the obstacle block is A~(alpha) = A + sum_{j=+-1} alpha^j A_j.  The
 // skeletons of a handle built with far_radius represent the interaction of every box with sources
-// beyond that radius, so the rows of A_j factor through the nested interpolation U of the tree:
+// beyond that radius, and with image_period also with the images' near points (Sec. 3.2), so the rows
+// of A_j factor through the nested interpolation U of the tree:
 // A_j = U A_j(J, :) with J the root's active set.  Then A~ = A + U R(alpha), R = alpha R_1 + alpha^{-1} R_{-1},
 // and (Eq. 3.2 with the sign of its second term corrected)
 //   A~^{-1} = A^{-1} - V K R A^{-1},  V = A^{-1} U,  K(alpha) = (I + R V)^{-1}  (root-size),
@@ -126,8 +127,11 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
       set_error("qp_solve: P = 1 needs a handle built with hbs_opts.far_radius > 0");
       return HBS_E_INVALID_ARG;
     }
-    if (!(period - h->robs > h->opts.far_radius)) {
-      set_error("qp_solve: the neighbour images come closer than far_radius to the obstacle's centre");
+    // images inside far_radius are represented only by a handle built with their explicit columns
+    const bool imgs = h->opts.image_period > 0 && std::fabs(h->opts.image_period - period) <= 1e-12 * period;
+    if (!imgs && !(period - h->robs > h->opts.far_radius)) {
+      set_error("qp_solve: the neighbour images come closer than far_radius to the obstacle's centre "
+                "(build the handle with hbs_opts.image_period = period)");
       return HBS_E_INVALID_ARG;
     }
   }

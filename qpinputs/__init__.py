@@ -15,6 +15,9 @@ random-Fourier "rough" obstacle, Sec. 6.2; sizes are this project's):
                N = 1e4, omega = 40, 100 angles theta ~ U(-pi/2, 0).
 * ``wavy40``   40 harmonics, a_k ~ U(0, 0.2/k), N = 1e5, omega = 60,
                200 angles on 4 shared Bloch phases.
+* ``star_d1``  the scaling test of Sec. 6.1: r(t) = 0.35 + 0.105 cos 3t, period d = 1 (the
+               neighbour images come within 0.25 of the obstacle), omega = 10, theta = -pi/5;
+               N = 2^17 there, smaller here by default.
 """
 from __future__ import annotations
 
@@ -190,6 +193,9 @@ def workload(name: str) -> Workload:
         c = wavy(130102, 20, 0.3)
         th = random_angles(130102 + 1, 100, 40.0, TWO_PI)
         return Workload("wavy20", c, 10000, 40.0, TWO_PI, th, 1e-10, 64, "kr6")
+    if name == "star_d1":
+        return Workload("star_d1", star(0.35, 0.105, 3), 131072, 10.0, 1.0, np.array([-math.pi / 5]), 1e-10, 64,
+                        "kr6")
     if name == "wavy40":
         c = wavy(130103, 40, 0.2)
         th = shared_phase_angles(60.0, TWO_PI)

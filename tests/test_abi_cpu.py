@@ -193,11 +193,21 @@ def test_mem_limit_refused_before_any_device_allocation():
     assert "mem_limit of 4096 device bytes exceeded" in msg
 
 
+def test_image_period_needs_far_radius():
+    """Neighbour-image columns need the far-field circle (it represents the images beyond
+    far_radius): the combination is refused on the host, as is a negative period."""
+    nodes, w, nrm, _ = _geom()
+    rc, msg = _build(nodes, w, nrm, 256, image_period=1.0)
+    assert rc == -1 and "far_radius" in msg, (rc, msg)
+    rc, msg = _build(nodes, w, nrm, 256, image_period=-1.0, far_radius=2.0)
+    assert rc == -1 and "image_period" in msg, (rc, msg)
+
+
 def test_opts_struct_size_matches_binding():
     from paper_1301_1247_amd import binding as B
     o = B.hbs_opts()
     assert o.struct_size == C.sizeof(B.HbsOpts)
-    assert o.mem_limit == 0
+    assert o.mem_limit == 0 and o.image_period == 0.0
     q = B.qp_opts()
     assert q.struct_size == C.sizeof(B.QpOpts)
 

@@ -1,0 +1,61 @@
+"""The paper's own grating of Sec. 6.1 (star r = 0.35 + 0.105 cos 3t, period d = 1, omega = 10,
+theta = -pi/5) through the C ABI, with P = 1 neighbour images whose near points fall inside the
+proxy circles (Sec. 3.2, Fig. 3.1): a handle built with image_period = d takes them as explicit
+columns of its interpolative decompositions.  Bar: relative error <= 1e-10 of eta and xi
+(2-norm and max-abs) and of the Bragg amplitudes against the oracle's dense P = 1 solution."""
+import math
+
+import numpy as np
+import pytest
+
+import qpinputs
+from oracle import periodic as pq
+from paper_1301_1247_amd.geometry import discretize
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(res, ref, nth):
+    for a in range(nth):
+        for key in ("eta", "xi"):
+            g, r = res[key][:, a], ref[key][:, a]
+            assert np.linalg.norm(g - r) / np.linalg.norm(r) < 1e-10, (key, a)
+            assert np.abs(g - r).max() / np.abs(r).max() < 1e-10, (key, a)
+        n, kn, c, d = ref["bragg"][a]
+        maxm, nm = res["maxmodes"], res["nmodes"][a]
+        assert res["nlo"][a] == n[0] and nm == len(n)
+        scale = max(np.abs(c).max(), np.abs(d).max())
+        assert np.abs(res["bragg"][:nm, a] - c).max() < 1e-10 * scale
+        assert np.abs(res["bragg"][maxm:maxm + nm, a] - d).max() < 1e-10 * scale
+        assert abs(res["flux"][a] - ref["flux"][a]) < 1e-10
+
+
+@pytest.mark.parametrize("N,far", [(2000, 0.6), (4096, 1.0)])
+def test_star_d1_P1_near_images_match_oracle(gpu_lib, N, far):
+    wl = qpinputs.workload("star_d1")
+    thetas = np.array([-math.pi / 5, -1.2, -0.35])
+    nodes, w, nrm, _ = discretize(wl.curve, N)
+    print(f"star_d1 N={N} far_radius={far}", flush=True)
+    h = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-12, far_radius=far, image_period=wl.period)
+    st = h.stats()
+    assert st.image_samples > 0
+    res = h.qp_solve_many(wl.period, thetas, P=1)
+    ref = pq.solve_qp(wl.curve, N, wl.omega, wl.period, thetas, P=1)
+    assert res["M"] == len(ref["contour"].k)
+    _check(res, ref, len(thetas))
+    assert h.stats().walls_compressed == 0
+
+
+def test_star_d1_needs_image_columns(gpu_lib):
+    """Without image_period the neighbour images of the d = 1 grating lie inside far_radius and the
+    P = 1 solve is refused rather than answered from skeletons that do not represent them."""
+    wl = qpinputs.workload("star_d1")
+    nodes, w, nrm, _ = discretize(wl.curve, 2000)
+    h = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-12, far_radius=0.6)
+    with pytest.raises(gpu_lib.HBSError) as e:
+        h.qp_solve_many(wl.period, wl.thetas, P=1)
+    assert e.value.code == -1 and "image_period" in str(e.value)
+    # a handle built for another period does not serve this one
+    h2 = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-12, far_radius=0.6, image_period=1.5)
+    with pytest.raises(gpu_lib.HBSError):
+        h2.qp_solve_many(wl.period, wl.thetas, P=1)
