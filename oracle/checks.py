@@ -34,20 +34,24 @@ class RowSubset:
 
 
 def bordered_residual(curve, N, omega, period, thetas, eta, xi, flux=None, n_rows=48, n_ang=8, chunk=4000,
-                      seed=7, angles=None):
-    """Sampled relative residual of the bordered system (P = 0, KR6 quadrature) for the solutions
-    eta (N x n) and xi (2M x n) of the angles ``thetas`` (n), M from the default contour.
+                      seed=7, angles=None, P=0, h=0.1):
+    """Sampled relative residual of the bordered system (KR6 quadrature; Eq. 2.19, or Eq. 2.21 with
+    P = 1 neighbour images: A~ = A + alpha A_1 + alpha^-1 A_-1 and C~ of Sec. 2.4) for the solutions
+    eta (N x n) and xi (2M x n) of the angles ``thetas`` (n), M from the default contour of spacing h.
 
     n_rows obstacle rows and n_ang angles are drawn from rng(seed) (or ``angles`` given).
     Returns dict(sampled_rel_residual = max over the sampled angles of
     sqrt(|r1|^2 N / n_rows + |r2|^2) / |b|, flux_err_max over every angle when ``flux`` is given,
     rows_sampled, angles_sampled)."""
     disc = nystrom.Discretization(curve, N)
-    ct = periodic.default_contour(disc, omega, period)
+    if P not in (0, 1):
+        raise ValueError("P must be 0 or 1")
+    ct = periodic.default_contour(disc, omega, period, P=P, h=h)
     rng = np.random.default_rng(seed)
     rows = np.sort(rng.choice(N, n_rows, replace=False))
     angs = np.asarray(angles) if angles is not None else rng.choice(len(thetas), n_ang, replace=False)
     Arows = nystrom.matrix_kr6_rows(disc, omega, rows)
+    Anb = {j: nystrom.neighbour_rows(disc, omega, j * period, rows) for j in ((-1, 1) if P else ())}
     sub = RowSubset(disc, rows)
     BL, BR = periodic.wall_B(sub, omega, period, ct)
     eta_s = eta[:, angs]
@@ -55,7 +59,8 @@ def bordered_residual(curve, N, omega, period, thetas, eta, xi, flux=None, n_row
     CRe = 0
     for c0 in range(0, N, chunk):
         sl = np.arange(c0, min(N, c0 + chunk))
-        CL, CR = periodic.wall_C(RowSubset(disc, sl), omega, period, ct)
+        CL, _ = periodic.wall_C(RowSubset(disc, sl), omega, period, ct, shift=P * period)
+        _, CR = periodic.wall_C(RowSubset(disc, sl), omega, period, ct, shift=-P * period)
         CLe = CLe + CL @ eta_s[sl]
         CRe = CRe + CR @ eta_s[sl]
     worst = 0.0
@@ -64,8 +69,9 @@ def bordered_residual(curve, N, omega, period, thetas, eta, xi, flux=None, n_row
         al = periodic.bloch_phase(omega, period, th)
         x = xi[:, a]
         b = periodic.incident(sub, omega, th)[:, 0]
-        r1 = Arows @ eta_s[:, q] + (BL + al * BR) @ x - b
-        r2 = CLe[:, q] - CRe[:, q] / al + periodic.wall_Q(omega, period, al, ct) @ x
+        At = Arows + sum(al ** j * Anb[j] for j in Anb)
+        r1 = At @ eta_s[:, q] + (BL + al * BR) @ x - b
+        r2 = al ** P * CLe[:, q] - al ** (-(P + 1)) * CRe[:, q] + periodic.wall_Q(omega, period, al, ct) @ x
         bn = np.linalg.norm(periodic.incident(disc, omega, th))
         worst = max(worst, math.sqrt(np.sum(np.abs(r1) ** 2) * N / n_rows + np.sum(np.abs(r2) ** 2)) / bn)
     out = {"sampled_rel_residual": float(worst), "rows_sampled": int(n_rows), "angles_sampled": int(len(angs))}

@@ -145,6 +145,13 @@ def neighbour_matrix(disc: Discretization, omega: float, shift: float) -> np.nda
     return kernel(omega, disc.x, src, disc.nrm) * disc.w[None, :]
 
 
+def neighbour_rows(disc: Discretization, omega: float, shift: float, rows) -> np.ndarray:
+    """Rows ``rows`` of ``neighbour_matrix`` (Sec. 2.4), evaluated without forming the others."""
+    rows = np.asarray(rows, dtype=np.int64).reshape(-1)
+    src = disc.x + np.array([shift, 0.0])
+    return kernel(omega, disc.x[rows], src, disc.nrm) * disc.w[None, :]
+
+
 def potential(disc: Discretization, omega: float, eta: np.ndarray, targets: np.ndarray) -> np.ndarray:
     """(D - i omega S) eta at off-surface targets (plain trapezoid; targets well away
     from the curve).  eta may be (N,) or (N, q)."""

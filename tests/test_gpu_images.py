@@ -59,3 +59,19 @@ def test_star_d1_needs_image_columns(gpu_lib):
     h2 = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-12, far_radius=0.6, image_period=1.5)
     with pytest.raises(gpu_lib.HBSError):
         h2.qp_solve_many(wl.period, wl.thetas, P=1)
+
+
+def test_star_d1_paper_size_residual(gpu_lib):
+    """At the paper's N = 2^17 the dense oracle does not fit: sampled rows of the P = 1 bordered
+    system's residual (every wall row, 48 obstacle rows) and the energy balance judge the solution."""
+    from oracle import checks
+    wl = qpinputs.workload("star_d1")
+    thetas = np.array([-math.pi / 5, -1.2, -0.35])
+    nodes, w, nrm, _ = discretize(wl.curve, wl.N)
+    print(f"star_d1 N={wl.N}", flush=True)
+    h = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-12, far_radius=1.0, image_period=wl.period)
+    res = h.qp_solve_many(wl.period, thetas, P=1)
+    v = checks.bordered_residual(wl.curve, wl.N, wl.omega, wl.period, thetas, res["eta"], res["xi"], res["flux"],
+                                 n_rows=48, n_ang=3, P=1)
+    assert v["sampled_rel_residual"] < 1e-11, v
+    assert v["flux_err_max"] < 1e-10, v

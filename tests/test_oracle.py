@@ -221,6 +221,31 @@ def test_kr6_rows_equal_full_matrix_rows():
     assert np.array_equal(ny.matrix_kr6_rows(disc, 40.0, rows), A[rows])
 
 
+def test_neighbour_rows_equal_full_matrix_rows():
+    c = qpinputs.star(0.35, 0.105, 3)
+    disc = ny.Discretization(c, 300)
+    rows = np.array([0, 5, 150, 299])
+    for sh in (1.0, -1.0):
+        assert np.array_equal(ny.neighbour_rows(disc, 10.0, sh, rows), ny.neighbour_matrix(disc, 10.0, sh)[rows])
+
+
+def test_residual_checker_with_neighbour_images():
+    """P = 1 (the d = 1 grating of Sec. 6.1): the dense solution's sampled residual is at rounding
+    level, and a relative change of 1e-6 in one density value shows."""
+    from oracle import checks
+    wl = qpinputs.workload("star_d1")
+    N, th = 300, np.array([-math.pi / 5, -1.2])
+    r = pq.solve_qp(wl.curve, N, wl.omega, wl.period, th, P=1)
+    v = checks.bordered_residual(wl.curve, N, wl.omega, wl.period, th, r["eta"], r["xi"], n_rows=30, n_ang=2,
+                                 chunk=100, P=1)
+    assert v["sampled_rel_residual"] < 1e-12
+    eta = r["eta"].copy()
+    eta[40, :] *= 1.0 + 1e-6
+    v = checks.bordered_residual(wl.curve, N, wl.omega, wl.period, th, eta, r["xi"], n_rows=30, n_ang=2,
+                                 chunk=100, P=1)
+    assert v["sampled_rel_residual"] > 1e-10
+
+
 @pytest.fixture(scope="module")
 def wavy_kr6_qp():
     """A KR6 solution at N = 600 of a rough obstacle, for the residual checker."""
