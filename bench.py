@@ -312,6 +312,8 @@ def main():
                     help="size each box's sketch from the MLP rank prediction (off: worst case 2n + 8)")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="fp32: complex64 inverse factors as a preconditioner, FP64 refinement")
+    ap.add_argument("--defer-root", choices=("on", "off"), default="on",
+                    help="on: the root matrix is inverted in the first solve, batched with its capacitance inversions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the no-predictor and fp32 rates")
@@ -349,6 +351,8 @@ def main():
         c0 = 0.5 * (nodes.max(0) + nodes.min(0))
         base_kw["far_radius"] = 0.9 * (0.5 * wl.period - abs(c0[0]))
     cw = 1 if args.walls == "compressed" else -1
+    # the root inversion runs in the solve's batch of capacitance inversions (build_seconds leaves it out)
+    base_kw["defer_root"] = args.defer_root == "on"
     kw = dict(base_kw, precision=args.precision, rank_predictor=args.rank_predictor == "on")
 
     h, res, t, builds = run_steps(B, torch, wl, t_nodes, t_w, t_nrm, t_th, kw, args.tol, cw, args.steps, args.warmup,
@@ -391,8 +395,11 @@ def main():
                                f"{nang} angles, tol={args.tol:g}, KR6 + proxy compression, {args.precision} factors, "
                                f"{args.walls} walls, rank predictor {args.rank_predictor}",
                    "N": wl.N, "omega": wl.omega, "angles": nang, "contour_M": st.contour_M,
-                   "walls": args.walls, "precision": args.precision, "rank_predictor": args.rank_predictor},
+                   "walls": args.walls, "precision": args.precision, "rank_predictor": args.rank_predictor,
+                   "defer_root": args.defer_root},
         "build_seconds": float(np.median(builds)),
+        "build_seconds_note": ("hbs_build without the root inversion (defer_root: it runs inside the solve)"
+                               if args.defer_root == "on" else "hbs_build including the root inversion"),
         "levels": st.levels, "max_rank": st.max_rank, "root_size": st.root_size, "root_level": st.root_level,
         "refine_iters": st.refine_iters, "refine_residual": st.refine_residual,
         "rank_fallbacks": st.rank_fallbacks, "sketch_bytes_max": st.sketch_bytes_max,

@@ -107,6 +107,12 @@ typedef struct {
                                A_{+-1} = U A_{+-1}(J, :) holds however close the images come, and
                                qp_solve with P = 1 and this period needs no separation of the images
                                from far_radius.  Needs far_radius > 0; 0 = off */
+  int32_t defer_root;       /* 1: hbs_build leaves the inversion of the root matrix (Sec. 4) to the first
+                               call that needs it: qp_solve on compressed walls runs it in one batch with
+                               its Woodbury capacitance inversions, on a second stream while the first
+                               stream applies the tree's upward pass; other calls invert it on entry.
+                               A singular root is then reported by that call (HBS_E_SINGULAR), and
+                               build_seconds leaves the root inversion out.  0 = in hbs_build */
 } hbs_opts;
 
 typedef struct {

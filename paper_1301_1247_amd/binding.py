@@ -41,7 +41,7 @@ class HbsOpts(C.Structure):
                 ("far_radius", C.c_double), ("precision", C.c_int32), ("fp64_top_levels", C.c_int32),
                 ("rank_predictor", C.c_int32), ("rank_scale", C.c_double), ("rank_model", C.c_void_p),
                 ("root_level", C.c_int32), ("graph", C.c_int32), ("mem_limit", C.c_uint64),
-                ("image_period", C.c_double)]
+                ("image_period", C.c_double), ("defer_root", C.c_int32)]
 
 
 class QpOpts(C.Structure):
@@ -159,7 +159,7 @@ class Handle:
     def __init__(self, nodes, weights, normals, omega, tol, quad="kr6", compress=None, leaf_size=64,
                  curvature=None, device=False, stream=None, proxy_ratio=2.0, proxy_min=64, seed=0x5EED1301,
                  far_radius=0.0, precision="fp64", fp64_top_levels=0, rank_predictor=False, rank_scale=1.0,
-                 rank_model=None, root_level=0, graph=False, mem_limit=0, image_period=0.0):
+                 rank_model=None, root_level=0, graph=False, mem_limit=0, image_period=0.0, defer_root=False):
         if compress is None:
             compress = "exact" if quad == "kress" else "proxy"
         self.device = bool(device)
@@ -186,7 +186,7 @@ class Handle:
                      precision={"fp64": 0, "fp32": 1}[precision], fp64_top_levels=int(fp64_top_levels),
                      rank_predictor=1 if rank_predictor else 0, rank_scale=float(rank_scale),
                      root_level=int(root_level), graph=1 if graph else 0, mem_limit=int(mem_limit),
-                     image_period=float(image_period))
+                     image_period=float(image_period), defer_root=1 if defer_root else 0)
         if rank_model is not None:
             rank_model = np.ascontiguousarray(rank_model, dtype=np.float32)
             o.rank_model = rank_model.ctypes.data

@@ -301,6 +301,7 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
   if (o.graph != 0 && o.graph != 1) { set_error("hbs_build: graph must be 0 or 1"); return HBS_E_INVALID_ARG; }
   if (o.root_level < 0 || o.root_level > 2) { set_error("hbs_build: root_level must be 0, 1 or 2"); return HBS_E_INVALID_ARG; }
   if (o.rank_scale < 0 || !std::isfinite(o.rank_scale)) { set_error("hbs_build: rank_scale must be >= 0"); return HBS_E_INVALID_ARG; }
+  if (o.defer_root != 0 && o.defer_root != 1) { set_error("hbs_build: defer_root must be 0 or 1"); return HBS_E_INVALID_ARG; }
   if (!(o.image_period >= 0) || !std::isfinite(o.image_period)) {
     set_error("hbs_build: image_period must be finite and >= 0");
     return HBS_E_INVALID_ARG;

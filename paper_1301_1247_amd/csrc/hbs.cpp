@@ -694,7 +694,7 @@ int build(hbs_handle* h) {
       int ms = 0, mn = 0;
       for (const auto& q : qd) { ms = std::max(ms, q.s); mn = std::max(mn, q.n); }
       ProfScope ps("cpqr", st, fl, 0.0);
-      CK(launch_cpqr(arena.as<CpqrDesc>(), nb, ms, mn, h->tol, kout.as<int>(), st, &cpqrws));
+      CK(launch_cpqr(arena.as<CpqrDesc>(), nb, ms, mn, h->tol, kout.as<int>(), st, &cpqrws, &ps.launches));
     }
     // the side stream: the children's factor chain (their reduced blocks D^ enter this level's
     // diagonal blocks), then this level's diagonal blocks and their inverses.  Enqueued after the
@@ -807,7 +807,10 @@ int build(hbs_handle* h) {
         int* k2 = kout.as<int>() + nb;
         int ms = 0, mn = 0;
         for (const auto& q : qd) { ms = std::max(ms, q.s); mn = std::max(mn, q.n); }
-        CK(launch_cpqr(arena.as<CpqrDesc>(), (int)qd.size(), ms, mn, h->tol, k2, st, &cpqrws));
+        double fl2 = 0;
+        for (const auto& q : qd) fl2 += 8.0 * 2.0 * q.s * (double)q.n * q.n;
+        ProfScope ps2("cpqr", st, fl2, 0.0);
+        CK(launch_cpqr(arena.as<CpqrDesc>(), (int)qd.size(), ms, mn, h->tol, k2, st, &cpqrws, &ps2.launches));
         std::vector<int> hk2(redo.size());
         CK(hipMemcpyAsync(hk2.data(), k2, sizeof(int) * redo.size(), hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));
@@ -911,8 +914,13 @@ int build(hbs_handle* h) {
                                 {V.Dh.as<cplx>() + V.oDh[1], Ri + (int64_t)ka * n + ka, kc, kc, kc, n}};
     CK(up_sync(arena_f, cd, sf));
     CK(launch_copy(arena_f.as<CopyDesc>(), 2, std::max(ka * ka, kc * kc), sf));
-    std::vector<InvDesc> iv = {{Ri, n, n}};
-    CK(inv_batched_flags(arena_f, work_f, iv, sf, flags_for(1, 0, "root matrix")));
+    if (h->opts.defer_root) {
+      h->root_state = 1;  // Ri holds the root matrix until a call needs its inverse
+    } else {
+      std::vector<InvDesc> iv = {{Ri, n, n}};
+      CK(inv_batched_flags(arena_f, work_f, iv, sf, flags_for(1, 0, "root matrix")));
+      h->root_state = 0;
+    }
     V.Dh.release();
     h->factor_bytes += (int64_t)sizeof(cplx) * 2 * n * n;
   }
@@ -1101,8 +1109,17 @@ struct Step {
 // upward results of the same B stay in the handle's workspace between the two calls)
 static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r,
                        bool sync = true, const cplx* root_add = nullptr, cplx* root_up = nullptr, int phase = 0,
-                       const cplx* root_set = nullptr) {
+                       const cplx* root_set = nullptr, hipEvent_t root_wait = nullptr) {
   if (r <= 0) return HBS_OK;
+  // the downward pass alone does not read the root inverse; with root_wait the caller forms it
+  if (inv && phase != 2 && !root_wait) {
+    const int rc = ensure_root(h);
+    if (rc != HBS_OK) return rc;
+  }
+  if (root_wait && h->opts.graph) {
+    set_error("hbs apply: a root wait cannot be captured");
+    return HBS_E_INVALID_ARG;
+  }
   hipStream_t st = h->stream;
   const int L = h->L;
   auto& lv = h->lv;
@@ -1267,6 +1284,11 @@ static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_
     for (size_t ti = p0; ti < p1; ++ti) {
       const Step& t = prog[ti];
       hipError_t e;
+      if (root_wait && ti + 1 == down_begin) {
+        // the root product (the last step before the downward pass) reads the root inverse
+        e = hipStreamWaitEvent(s, root_wait, 0);
+        if (e != hipSuccess) return e;
+      }
       if (t.kind == 0) {
         ProfScope ps2(prof ? "zgemm" : nullptr, s, t.flops, 0.0);
         e = launch_gemm<double>(dd64 + t.off, t.cnt, t.plan, s);
@@ -1356,8 +1378,8 @@ int apply_forward_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64
   return apply_mixed(h, false, h->L, B, ldb, X, ldx, r, false, root_add, root_up);
 }
 
-int apply_inverse_up(hbs_handle* h, const cplx* B, int64_t ldb, int64_t r, cplx* root, int64_t ldr) {
-  int rc = apply_mixed(h, true, h->fp64_top, B, ldb, nullptr, 0, r, false, nullptr, nullptr, 1);
+int apply_inverse_up(hbs_handle* h, const cplx* B, int64_t ldb, int64_t r, cplx* root, int64_t ldr, hipEvent_t root_wait) {
+  int rc = apply_mixed(h, true, h->fp64_top, B, ldb, nullptr, 0, r, false, nullptr, nullptr, 1, nullptr, root_wait);
   if (rc != HBS_OK || r <= 0) return rc;
   const int64_t n = h->nroot;
   CK(hipMemcpy2DAsync(root, sizeof(cplx) * ldr, h->ab_root.p, sizeof(cplx) * n, sizeof(cplx) * n, r, hipMemcpyDeviceToDevice,
@@ -1390,6 +1412,35 @@ int apply_inverse_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64
                         hipMemcpyDeviceToDevice, h->stream));
   }
   if (sync) CK(hipStreamSynchronize(h->stream));
+  return HBS_OK;
+}
+
+int ensure_root(hbs_handle* h) {
+  switch (h->root_state) {
+    case 0:
+      return HBS_OK;
+    case 2: {
+      // inverted on the side stream by an earlier call that could not read its flag
+      int f = 1;
+      CK(hipStreamSynchronize(h->side_stream));
+      CK(hipMemcpy(&f, h->root_flag, sizeof(int), hipMemcpyDeviceToHost));
+      h->root_state = f ? 3 : 0;
+      break;
+    }
+    case 1: {
+      std::vector<InvDesc> iv = {{h->Rinv.as<cplx>(), h->nroot, h->nroot}};
+      bool sing = false;
+      CK(inv_batched(h->arena, h->work, iv, h->stream, &sing));
+      h->root_state = sing ? 3 : 0;
+      break;
+    }
+    default:
+      break;
+  }
+  if (h->root_state != 0) {
+    set_error("singular root matrix (hbs_opts.defer_root: found at the first use of the root inverse)");
+    return HBS_E_SINGULAR;
+  }
   return HBS_OK;
 }
 

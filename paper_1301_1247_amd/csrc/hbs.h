@@ -57,6 +57,10 @@ struct hbs_handle {
   std::vector<qps::Level> lv;  // lv[1..L]
   int nroot = 0;
   qps::DevBuf Rinv, Rfwd;
+  // Rinv: 0 = the root inverse; 1 = still the root matrix (hbs_opts.defer_root); 2 = its inversion is
+  // enqueued on the side stream, flag (device) not yet read; 3 = the root matrix was singular
+  int root_state = 0;
+  const int* root_flag = nullptr;
   int fp64_top = 0;               // levels 1..fp64_top hold complex128 inverse factors, deeper ones complex64
   bool top_identity = false;      // level 1 left uncompressed (root over the level-2 skeletons)
   std::vector<float> rank_model;  // rank-predictor parameters (when hbs_opts.rank_predictor)
@@ -100,7 +104,11 @@ int apply_forward_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64
 // root solution U^T A^{-1} B (nroot x r) copied to root; later the downward pass from root_in
 // (nroot x r, ld nroot) instead of that root solution, writing X.  The upward results of B stay
 // in the handle's apply workspace in between: no other apply may run on the handle meanwhile.
-int apply_inverse_up(hbs_handle* h, const cplx* B, int64_t ldb, int64_t r, cplx* root, int64_t ldr);
+// root_wait (nullable): an event the root product waits for (the root inverse is formed elsewhere)
+int apply_inverse_up(hbs_handle* h, const cplx* B, int64_t ldb, int64_t r, cplx* root, int64_t ldr,
+                     hipEvent_t root_wait = nullptr);
+// bring Rinv to the root inverse (root_state 0) before it is read; HBS_E_SINGULAR for a singular root
+int ensure_root(hbs_handle* h);
 int apply_inverse_down(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r, const cplx* root_in);
 // (sync = false leaves the work stream-ordered on the handle's stream without waiting for it)
 int apply_inverse_root(hbs_handle* h, const cplx* B, int64_t ldb, cplx* X, int64_t ldx, int64_t r, cplx* root, int64_t ldr,

@@ -189,9 +189,10 @@ hipError_t launch_eval_blocks(const Geo& g, const BlockDesc* d, int nd, int max_
 hipError_t launch_alpert_table(const Geo& g, const double* D, const double* wq, cplx* T, hipStream_t s);
 hipError_t launch_proxy(const Geo& g, const ProxyDesc* d, int nd, int max_elems, hipStream_t s);
 hipError_t launch_sketch(const SketchDesc* d, int nd, int max_s, int max_n, uint64_t seed, hipStream_t s);
-// ws: workspace for the few-large-boxes path (one launch per pivot step); nullptr: one workgroup per box
+// ws: workspace for the few-large-boxes path (one launch per pivot step); nullptr: one workgroup per box.
+// launches (nullable): the number of kernel launches issued
 hipError_t launch_cpqr(const CpqrDesc* d, int nd, int max_s, int max_n, double tol, int* k_out, hipStream_t s,
-                       DevBuf* ws = nullptr);
+                       DevBuf* ws = nullptr, int* launches = nullptr);
 hipError_t launch_buildP(const PDesc* d, int nd, int max_elems, hipStream_t s);
 hipError_t launch_copy(const CopyDesc* d, int nd, int max_elems, hipStream_t s);
 hipError_t launch_eye(const CopyDesc* d, int nd, int max_elems, hipStream_t s);  // dst = I (nr x nc)

@@ -1078,7 +1078,7 @@ hipError_t launch_sketch(const SketchDesc* d, int nd, int max_s, int max_n, uint
   hipLaunchKernelGGL(k_sketch, grid, dim3(NT), 0, s, d, seed);
   return hipGetLastError();
 }
-hipError_t launch_cpqr(const CpqrDesc* d, int nd, int max_s, int max_n, double tol, int* k_out, hipStream_t s, DevBuf* ws) {
+hipError_t launch_cpqr(const CpqrDesc* d, int nd, int max_s, int max_n, double tol, int* k_out, hipStream_t s, DevBuf* ws, int* launches) {
   if (nd == 0) return hipSuccess;
   // a few large boxes: one launch per pivot step over workgroups of 16 columns.  A launch costs
   // about as much as a pivot step of the one-workgroup kernel on a 200 x 200 sketch, whose steps
@@ -1111,8 +1111,10 @@ hipError_t launch_cpqr(const CpqrDesc* d, int nd, int max_s, int max_n, double t
     for (int p = 0; p < pmax; ++p) hipLaunchKernelGGL(k_cpqrm_step, dim3(nwg, nd), dim3(256), 0, s, d, W, p, tol);
     hipLaunchKernelGGL(k_cpqrm_gather, dim3(max_n, nd), dim3(256), 0, s, d, W, k_out);
     hipLaunchKernelGGL(k_cpqrm_tsolve, dim3(nd), dim3(1024), 0, s, d, W);
+    if (launches) *launches = pmax + 3;
     return hipGetLastError();
   }
+  if (launches) *launches = 1;
   if (nd >= 256 && max_s <= 512 && max_n <= 256)
     hipLaunchKernelGGL((k_cpqr<256, 512, 256, 0>), dim3(nd), dim3(256), 0, s, d, tol, k_out);
   else

@@ -387,12 +387,30 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
       if (s) (void)hipStreamSynchronize(s);
     }
   } side_join;
+  // an early return after the side stream took the deferred root inversion: read its flag (after the
+  // side stream is joined) so that later calls see the root's state
+  struct RootSettle {
+    hbs_handle* h;
+    ~RootSettle() {
+      if (h->root_state != 2) return;
+      int f = 1;
+      if (hipStreamSynchronize(h->side_stream) == hipSuccess &&
+          hipMemcpy(&f, h->root_flag, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess)
+        h->root_state = f ? 3 : 0;
+      else
+        h->root_state = 3;
+    }
+  } root_settle{h};
   // S(alpha) = Q - C~_J(alpha) H~(alpha) B_J(alpha) with H~ = U^T A~^{-1} U = H - H K(alpha) R(alpha) V (P = 1) or H;
   // Woodbury around the 2 x 2-block-diagonal Q: S^{-1} = [I + Cq K2 B_J(alpha)] Q^{-1},
   // Cq = Q^{-1} C~_J H~, K2 = (I - B_J(alpha) Cq)^{-1}  (root-size inversions only).
   // Issued on stream s with its own descriptor arena and workspaces.
   // dinfo: leave the singularity check to the caller (device flags in wk) instead of waiting
-  auto woodbury = [&](hipStream_t s, DevBuf& ar, DevBuf& ws, DevBuf& wk, int** dinfo) -> int {
+  // With the root inverse still to be formed (hbs_opts.defer_root), P = 0: H = R^{-1} and
+  //   Cq K2 = Q^{-1} C~_J H (I - B_J Q^{-1} C~_J H)^{-1} = Q^{-1} C~_J (R - B_J Q^{-1} C~_J)^{-1},
+  // so Cq = Q^{-1} C~_J and K2 = (R - B_J Cq)^{-1} give the same S^{-1} without R^{-1}, and R itself
+  // joins the capacitance matrices in one batched inversion.
+  auto woodbury = [&](hipStream_t s, DevBuf& ar, DevBuf& ws, DevBuf& wk, int** dinfo, bool defer) -> int {
     const cplx* H = Zt;  // U^T V (nu x nu)
     // every descriptor set first, so that the arena and workspaces are reserved before any launch
     std::vector<GemmDesc> gp1, gp2, gch, gbc;
@@ -409,7 +427,9 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
                        minus1c, zero));
       iv.push_back({K2 + (size_t)g * nu * nu, nu, nu});
     }
-    if (!P) gch = {gd(C1, M2, 0, H, nu, C1H, M2, M2, nu, nu, onec, zero), gd(C2, M2, 0, H, nu, C2H, M2, M2, nu, nu, onec, zero)};
+    if (!P && !defer)
+      gch = {gd(C1, M2, 0, H, nu, C1H, M2, M2, nu, nu, onec, zero), gd(C2, M2, 0, H, nu, C2H, M2, M2, nu, nu, onec, zero)};
+    if (defer) iv.push_back({h->Rinv.as<cplx>(), nu, nu});
     {
       size_t amax = 0, wmax = 0, a, w;
       auto need = [&](const std::vector<GemmDesc>& v) {
@@ -448,6 +468,13 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
         CR(gemm_s(gcq[g]));
         CK(launch_qsolve(Q, d_gco + 3 * g, 0, nu, CH, M2, cq, M2, s));
       }
+    } else if (defer) {
+      // Cq = Q^{-1} (c1 C1_J + c2 C2_J)
+      for (int g = 0; g < ng; ++g) {
+        cplx* cq = Cq + (size_t)g * M2 * nu;
+        CK(launch_lincomb(M2, nu, d_gco + 3 * g + 1, d_gco + 3 * g + 2, 0, C1, M2, C2, M2, nullptr, 0, CH, M2, s));
+        CK(launch_qsolve(Q, d_gco + 3 * g, 0, nu, CH, M2, cq, M2, s));
+      }
     } else {
       // H~ = H for every phase: C~_J H = c1 (C1_J H) + c2 (C2_J H)
       CR(gemm_s(gch));
@@ -458,9 +485,20 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
       }
     }
     CR(gemm_s(gbc));
-    CK(launch_eye_plus(nu, ng, Hs, nu, (int64_t)nu * nu, K2, s));
+    if (defer) {
+      // K2 = R + Hs = R - B_J Cq, the root matrix still in Rinv
+      for (int g = 0; g < ng; ++g)
+        CK(launch_lincomb(nu, nu, d_one, d_one, 0, h->Rinv.as<cplx>(), nu, Hs + (size_t)g * nu * nu, nu, nullptr, 0,
+                          K2 + (size_t)g * nu * nu, nu, s));
+    } else {
+      CK(launch_eye_plus(nu, ng, Hs, nu, (int64_t)nu * nu, K2, s));
+    }
     if (dinfo) {
       CK(inv_batched_async(ar, wk, iv, s, dinfo));
+      if (defer) {
+        h->root_flag = *dinfo + ng;
+        h->root_state = 2;
+      }
       return HBS_OK;
     }
     bool sing = false;
@@ -491,6 +529,10 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
   // without neighbour images the Woodbury factors need only R^{-1}, B_J and C_J: they are formed on
   // the side stream while the main stream applies A^{-1} to the incident fields
   const bool overlap = fastU && !P;
+  // a deferred root inversion joins the side stream's capacitance inversions (graph capture cannot
+  // take the cross-stream wait of the root product)
+  const bool defer = overlap && h->root_state == 1 && !h->opts.graph;
+  if (!defer) CR(ensure_root(h));
   int* side_dinfo = nullptr;  // the side stream's singularity flags (device)
   if (nu && !fastU) {
     // U (N x nroot) = nested interpolation of the identity
@@ -510,7 +552,7 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
     // one application of A^{-1} to [U | b]: X = [V | X_b]; then with H = U^T V,
     //   U^T [X_L | X_R | X_b | V] = [H B_J,L | H B_J,R | U^T X_b | H]  and  G = C_J (that)
     if (fastU) {
-      CK(hipMemcpyAsync(Zt, h->Rinv.p, sizeof(cplx) * (size_t)nu * nu, hipMemcpyDeviceToDevice, st));
+      if (!defer) CK(hipMemcpyAsync(Zt, h->Rinv.p, sizeof(cplx) * (size_t)nu * nu, hipMemcpyDeviceToDevice, st));
       if (overlap) {
         // the side stream waits for R^{-1} and the wall blocks and forms the Woodbury factors while
         // the main stream applies A^{-1}; the main stream waits for them before the first solve with S
@@ -518,12 +560,14 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
         CK(hipEventRecord(h->side_ev[0], st));
         side_join.s = h->side_stream;
         CK(hipStreamWaitEvent(h->side_stream, h->side_ev[0], 0));
-        CR(woodbury(h->side_stream, h->arena_s, h->splitws_s, h->work_s, &side_dinfo));
+        CR(woodbury(h->side_stream, h->arena_s, h->splitws_s, h->work_s, &side_dinfo, defer));
         CK(hipEventRecord(h->side_ev[1], h->side_stream));
       }
       if (overlap) {
         // only the upward pass and the root now: eta comes from one downward pass once xi is known
-        CR(apply_inverse_up(h, Y + (size_t)ycolB * N, N, nang, Zt + (size_t)nu * nu, nu));
+        // (a deferred root inverse: the root product waits for the side stream's batched inversion)
+        CR(apply_inverse_up(h, Y + (size_t)ycolB * N, N, nang, Zt + (size_t)nu * nu, nu, defer ? h->side_ev[1] : nullptr));
+        if (defer) CK(hipMemcpyAsync(Zt, h->Rinv.p, sizeof(cplx) * (size_t)nu * nu, hipMemcpyDeviceToDevice, st));
       } else {
         CR(apply_inverse_root(h, Y + (size_t)ycolB * N, N, X + (size_t)ycolB * N, N, nang, Zt + (size_t)nu * nu, nu));
       }
@@ -633,7 +677,7 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
     }
   }
   if (cw) {
-    if (!overlap) CR(woodbury(st, h->arena, h->splitws, h->work, nullptr));
+    if (!overlap) CR(woodbury(st, h->arena, h->splitws, h->work, nullptr, false));
   } else {
     std::vector<InvDesc> iv;
     for (int g = 0; g < ng; ++g) iv.push_back({S + (size_t)g * M2 * M2, M2, M2});
@@ -833,12 +877,21 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
     CK(launch_colnorm2(N, nang, R1, N, nrm, st));
     CK(launch_colnorm2(M2, nang, R2, M2, nrm + nang, st));
     CK(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * 3 * nang, hipMemcpyDeviceToHost, st));
-    std::vector<int> sinfo(side_dinfo && it == 0 ? ng : 0);
+    // the side stream's flags: the capacitance matrices, then the root matrix when it was deferred
+    const int nflag = ng + (defer ? 1 : 0);
+    std::vector<int> sinfo(side_dinfo && it == 0 ? nflag : 0);
     // the main stream has waited for the side stream's inversion: its flags are final
-    if (!sinfo.empty()) CK(hipMemcpyAsync(sinfo.data(), side_dinfo, sizeof(int) * ng, hipMemcpyDeviceToHost, st));
+    if (!sinfo.empty()) CK(hipMemcpyAsync(sinfo.data(), side_dinfo, sizeof(int) * nflag, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
-    for (int f : sinfo)
-      if (f != 0) {
+    if (!sinfo.empty() && defer) {
+      h->root_state = sinfo[ng] ? 3 : 0;
+      if (sinfo[ng]) {
+        set_error("qp_solve: singular root matrix");
+        return HBS_E_SINGULAR;
+      }
+    }
+    for (int g = 0; g < ng && !sinfo.empty(); ++g)
+      if (sinfo[g] != 0) {
         set_error("qp_solve: singular Schur complement");
         return HBS_E_SINGULAR;
       }
