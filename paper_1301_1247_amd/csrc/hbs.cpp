@@ -600,8 +600,13 @@ int build(hbs_handle* h) {
       for (int b = 0; b < nb; ++b) {
         if (nnear[b] == 0) continue;
         const int n = V.n[b];
-        bd.push_back({dn + noff[b], dact + V.aoff[b], dwt + woff[b], nnear[b], n, m[b], 1});
-        bd.push_back({dn + noff[b], dact + V.aoff[b], dwt + woff[b] + nnear[b], nnear[b], n, m[b], 0});
+        if (h->opts.quad == HBS_QUAD_KR6) {
+          // both directions from one Hankel evaluation per pair (no point of b is near itself)
+          bd.push_back({dn + noff[b], dact + V.aoff[b], dwt + woff[b], nnear[b], n, m[b], 2, 0.0, nnear[b]});
+        } else {
+          bd.push_back({dn + noff[b], dact + V.aoff[b], dwt + woff[b], nnear[b], n, m[b], 1});
+          bd.push_back({dn + noff[b], dact + V.aoff[b], dwt + woff[b] + nnear[b], nnear[b], n, m[b], 0});
+        }
         maxb = std::max(maxb, nnear[b] * n);
       }
       // image rows [2 nnear, 2 nnear + 2 nimg): sources at the images, then targets there; each
@@ -614,8 +619,7 @@ int build(hbs_handle* h) {
         const double sxs[2] = {h->opts.image_period, -h->opts.image_period};
         for (int sg = 0, o = 0; sg < 2; o += part[sg], ++sg) {
           if (part[sg] == 0) continue;
-          bd.push_back({ib + o, dact + V.aoff[b], w0 + o, part[sg], n, m[b], 1, sxs[sg]});
-          bd.push_back({ib + o, dact + V.aoff[b], w0 + nimg[b] + o, part[sg], n, m[b], 0, sxs[sg]});
+          bd.push_back({ib + o, dact + V.aoff[b], w0 + o, part[sg], n, m[b], 2, sxs[sg], nimg[b]});
           maxb = std::max(maxb, part[sg] * n);
         }
       }

@@ -32,11 +32,15 @@ struct BlockDesc {
   const int* rows;
   const int* cols;
   cplx* out;
+  // trans = 1: out[r, c] = A(cols[c], rows[r]); 0: A(rows[r], cols[c]); 2: both, the second block
+  // pair_off rows below the first (one Hankel evaluation serves the two entries of a pair; KR6
+  // quadrature or image points only)
   int nr, nc, ld, trans;
   // != 0: the `rows` points stand for their neighbour images translated by (sx, 0) (Sec. 3.2): the
   // entries are the plain kernel (no quadrature correction), with the image as source (trans = 1)
   // or as target (trans = 0)
   double sx;
+  int pair_off;
 };
 
 // Proxy part of the compression matrix of one box: rows [row0, row0 + 3 np) of W^T

@@ -15,6 +15,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int r = e % d.nr, c = e / d.nr;
     const int gr = d.rows[r], gc = d.cols[c];
     cplx v;
+    if (d.trans == 2) {
+      // the pair A(gc, gr~), A(gr~, gc) (gr~ = gr shifted by sx) from one Hankel evaluation: both
+      // share r = |x_gc - x_gr~|; KR6's correction R depends on (gc - gr) mod N symmetrically
+      const double dx = G.x[gc] - G.x[gr] - d.sx, dy = G.y[gc] - G.y[gr];
+      const double rr = sqrt(dx * dx + dy * dy);
+      cplx h0, h1;
+      hankel01(G.omega * rr, h0, h1);
+      const double q = 0.25 * G.omega;
+      const double nd1 = (G.nx[gr] * dx + G.ny[gr] * dy) / rr;     // source gr~, target gc
+      const double nd2 = -(G.nx[gc] * dx + G.ny[gc] * dy) / rr;    // source gc, target gr~
+      double R = 1.0;
+      if (d.sx == 0.0) {
+        int m = gc - gr;
+        if (m < 0) m += G.N;
+        if (m <= 6) R += G.g[m - 1];
+        else if (m >= G.N - 6) R += G.g[G.N - m - 1];
+      }
+      const cplx k1 = mkc(q * (h0.x - h1.y * nd1), q * (h0.y + h1.x * nd1));
+      const cplx k2 = mkc(q * (h0.x - h1.y * nd2), q * (h0.y + h1.x * nd2));
+      d.out[r + (size_t)c * d.ld] = cscale(k1, R * G.w[gr]);
+      d.out[d.pair_off + r + (size_t)c * d.ld] = cscale(k2, R * G.w[gc]);
+      continue;
+    }
     if (d.sx != 0.0) {
       // image point y_gr + (sx, 0): source of the field at x_gc (trans) or target of the field of x_gc
       v = d.trans ? cscale(helm_kernel(G.omega, G.x[gc] - G.x[gr] - d.sx, G.y[gc] - G.y[gr], G.nx[gr], G.ny[gr]), G.w[gr])
@@ -62,39 +85,41 @@ __global__ __launch_bounds__(NT) void k_proxy(Geo G, const ProxyDesc* __restrict
   }
 }
 
-// complex Rademacher entries (+-1 +- i)/sqrt(2) from a counter-based hash
+// Rademacher signs from a counter-based hash (SplitMix64's finalizer)
 __device__ inline uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
 
-// Z = Omega * W^T, tiles of 32 (sketch rows) x 32 (columns) per workgroup.
+// Z = Omega * W^T with complex Rademacher entries (+-1 +- i)/sqrt(2), tiles of 32 (sketch rows) x 32
+// (columns) per workgroup.  One hash gives the 64 sign bits of a sketch row over a 32-row slice of W.
+// (A real sign matrix would halve the multiply-adds, but it embeds the k complex dimensions of W's
+// row space as 2k real ones, too many for the 2n + 8 rows of the top levels, where k is close to n.)
 __global__ __launch_bounds__(NT) void k_sketch(const SketchDesc* __restrict__ descs, uint64_t seed) {
   const SketchDesc d = descs[blockIdx.z];
   const int q0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
   if (q0 >= d.s || i0 >= d.n) return;
   __shared__ cplx Ws[32][33];
-  __shared__ float Om[32][33][2];
+  __shared__ uint64_t Om[32];
   const int tid = threadIdx.x;
   const int tq = tid % 32, ti = tid / 32;  // each thread: row q0+tq, columns i0+ti+8*c
   cplx acc[4] = {mkc(0, 0), mkc(0, 0), mkc(0, 0), mkc(0, 0)};
   const uint64_t bseed = mix64(seed ^ (0x9E3779B97F4A7C15ull * (uint64_t)(d.box + 1)));
+  constexpr double h = 0.70710678118654752440;
   for (int r0 = 0; r0 < d.m; r0 += 32) {
     for (int e = tid; e < 32 * 32; e += NT) {
       const int rr = e % 32, ii = e / 32;
       const int gr = r0 + rr, gi = i0 + ii;
       Ws[rr][ii] = (gr < d.m && gi < d.n) ? d.wt[gr + (size_t)gi * d.m] : mkc(0, 0);
-      const int qq = e / 32, r2 = e % 32;
-      const uint64_t h = mix64(bseed + 0xD1B54A32D192ED03ull * (uint64_t)(q0 + qq) +
-                               0x8CB92BA72F3D8DD7ull * (uint64_t)(r0 + r2));
-      Om[qq][r2][0] = (h & 1) ? 0.70710678118654752f : -0.70710678118654752f;
-      Om[qq][r2][1] = (h & 2) ? 0.70710678118654752f : -0.70710678118654752f;
     }
+    if (tid < 32)
+      Om[tid] = mix64(bseed + 0xD1B54A32D192ED03ull * (uint64_t)(q0 + tid) + 0x8CB92BA72F3D8DD7ull * (uint64_t)(r0 >> 5));
     __syncthreads();
-#pragma unroll 4
+    const uint64_t bits = Om[tq];
+#pragma unroll 8
     for (int rr = 0; rr < 32; ++rr) {
-      const cplx o = mkc((double)Om[tq][rr][0], (double)Om[tq][rr][1]);
+      const cplx o = mkc(((bits >> (2 * rr)) & 1) ? h : -h, ((bits >> (2 * rr + 1)) & 1) ? h : -h);
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[c] = cfma(o, Ws[rr][ti + 8 * c], acc[c]);
     }

@@ -33,9 +33,12 @@ def wavy():
 
 
 def test_deferred_root_qp_matches_oracle(gpu_lib, wavy):
+    """At the benchmark's ID tolerance 1e-13: with 1e-12 the angle -0.2 (the worst conditioned
+    here) lands at 0.9e-10 to 1.1e-10 of the oracle with or without the deferral, by the draw of
+    the sketches, too close to the bar for a largest-entry check."""
     c, N, om, d, disc, A, g, far = wavy
     thetas = np.array([-1.1, -0.45, -math.acos(0.31), -math.acos(0.31 + 1 / 40), -0.2])
-    h = gpu_lib.Handle(*g, om, 1e-12, far_radius=far, defer_root=True)
+    h = gpu_lib.Handle(*g, om, 1e-13, far_radius=far, defer_root=True)
     res = h.qp_solve_many(d, thetas, compress_walls=1)
     assert h.stats().walls_compressed == 1
     ref = pq.solve_qp(disc, N, om, d, thetas, quad="kr6", A0=A)
