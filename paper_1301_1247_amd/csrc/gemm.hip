@@ -55,26 +55,16 @@ __device__ __forceinline__ void gstore(typename cx<R>::T* p, typename cx<R>::T v
   *(__attribute__((address_space(1))) v2*)p = w;
 }
 
-constexpr int QPS_NXCD = 8;  // accelerator complex dies of an MI355X
-
 template <class R, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const GemmDescT<R>* __restrict__ descs) {
   constexpr int BM = 32 * WM, BN = 32 * WN, NT = 64 * WM * WN;
   constexpr int QA = BM * BK / NT, QB = BK * BN / NT;  // slice elements of op(A) and B per thread
   typedef typename cx<R>::T C_t;
   typedef typename mfma_t<R>::acc acc_t;
-  // XCD-aware order: the dispatcher hands workgroups to the 8 XCDs round-robin in launch order, and
-  // each XCD has its own L2.  Workgroup L of the launch takes item T of an order in which every XCD
-  // owns one contiguous range of (descriptor, tile) items, so the tiles of one descriptor, which
-  // share its operand panels, meet in one L2 instead of each XCD fetching the panels from HBM.
-  const int nx = gridDim.x, total = nx * gridDim.y;
-  const int L = blockIdx.x + blockIdx.y * nx;
-  int T = L;
-  if (total >= 2 * QPS_NXCD) {
-    const int xcd = L % QPS_NXCD, slot = L / QPS_NXCD;
-    const int q = total / QPS_NXCD, r = total % QPS_NXCD;
-    T = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
-  }
+  // XCD-aware order over the (descriptor, tile) items: the tiles of one descriptor, which share its
+  // operand panels, meet in one L2 instead of each XCD fetching the panels from HBM
+  const int nx = gridDim.x;
+  const int T = xcd_item(blockIdx.x + blockIdx.y * nx, nx * gridDim.y);
   const GemmDescT<R> d = descs[T / nx];
   const int tm = (d.m + BM - 1) / BM, tn = (d.n + BN - 1) / BN;
   const int t = T % nx;

@@ -97,8 +97,11 @@ __device__ inline uint64_t mix64(uint64_t z) {
 // (A real sign matrix would halve the multiply-adds, but it embeds the k complex dimensions of W's
 // row space as 2k real ones, too many for the 2n + 8 rows of the top levels, where k is close to n.)
 __global__ __launch_bounds__(NT) void k_sketch(const SketchDesc* __restrict__ descs, uint64_t seed) {
-  const SketchDesc d = descs[blockIdx.z];
-  const int q0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
+  // XCD-aware order: the row tiles of one column tile read the same columns of W
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int T = xcd_item(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+  const SketchDesc d = descs[T / (gx * gy)];
+  const int q0 = (T % gx) * 32, i0 = ((T / gx) % gy) * 32;
   if (q0 >= d.s || i0 >= d.n) return;
   __shared__ cplx Ws[32][33];
   __shared__ uint64_t Om[32];

@@ -27,6 +27,18 @@ __host__ __device__ inline cplx cinv(cplx a) {
   double d = ar * ar + ai * ai;
   return mkc(ar / (d * s), -ai / (d * s));
 }
+// XCD-aware work order: the dispatcher hands the workgroups of a launch to the 8 XCDs of an MI355X
+// round-robin in launch order, and each XCD has its own L2.  Workgroup L (linear, x fastest) of a
+// launch of `total` takes item T of an order in which every XCD owns one contiguous range of items,
+// so neighbouring items (tiles of one matrix, which share its operand panels) meet in one L2.
+constexpr int QPS_NXCD = 8;
+__device__ inline int xcd_item(int L, int total) {
+  if (total < 2 * QPS_NXCD) return L;
+  const int xcd = L % QPS_NXCD, slot = L / QPS_NXCD;
+  const int q = total / QPS_NXCD, r = total % QPS_NXCD;
+  return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
 __device__ inline cplx cexpi(double t) {
   double s, c;
   sincos(t, &s, &c);
