@@ -137,9 +137,9 @@ def test_qp_wavy20_full_size_vs_dense_oracle(gpu_lib, wavy20_ref, walls):
 @pytest.mark.parametrize("root_level", [0, 2])
 def test_qp_wavy20_benchmark_options_vs_dense_oracle(gpu_lib, wavy20_ref, root_level):
     """The benchmark's exact option set at the largest size the dense oracle reaches: rank
-    predictor on, root level automatic (and forced to 2), compressed walls, tol 1e-13, leaves of
-    64, device pointers on the torch stream, and no refinement step (the solution straight from
-    the compressed inverse and the Schur step)."""
+    predictor on, root level automatic (and forced to 2), root inversion deferred into the solve,
+    compressed walls, tol 1e-13, leaves of 64, device pointers on the torch stream, and no
+    refinement step (the solution straight from the compressed inverse and the Schur step)."""
     import torch
     wl, th, ref = wavy20_ref
     N, om, d = wl.N, wl.omega, wl.period
@@ -147,7 +147,7 @@ def test_qp_wavy20_benchmark_options_vs_dense_oracle(gpu_lib, wavy20_ref, root_l
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     h = gpu_lib.Handle(t(nodes), t(w), t(nrm), om, 1e-13, leaf_size=64, device=True,
-                       far_radius=_far_walls(nodes, d), rank_predictor=True, root_level=root_level)
+                       far_radius=_far_walls(nodes, d), rank_predictor=True, root_level=root_level, defer_root=True)
     r = h.qp_solve_many(d, t(th), compress_walls=1, refine_max_iter=-1)
     st = h.stats()
     assert st.walls_compressed == 1 and st.refine_iters == 0
@@ -167,7 +167,7 @@ def test_qp_wavy40_full_size_sampled_residual(gpu_lib, walls, predictor):
     t = lambda a: torch.from_numpy(a).to(dev)
     far = _far_walls(nodes, wl.period) if walls == "compressed" else 0.0
     h = gpu_lib.Handle(t(nodes), t(w), t(nrm), wl.omega, 1e-13, leaf_size=wl.leaf_size, device=True, far_radius=far,
-                       rank_predictor=predictor)
+                       rank_predictor=predictor, defer_root=predictor)
     res = h.qp_solve_many(wl.period, t(wl.thetas), compress_walls=1 if walls == "compressed" else -1,
                           refine_max_iter=-1 if predictor else 0)
     st = h.stats()
