@@ -196,7 +196,8 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
 
 /* out = A^{-1} rhs through the compressed inverse (Eq. 4.3 applied level by level),
  * followed by `refine` steps of iterative refinement against the compressed forward operator.
- *   rhs, out: N x nrhs complex (may not alias). */
+ *   rhs, out: N x nrhs complex (may not alias); nrhs = 0 returns HBS_OK and touches nothing
+ *   (hbs_forward and hbs_apply_noalloc likewise). */
 int hbs_apply(hbs_handle* h, const double* rhs, int64_t nrhs, double* out, int32_t refine);
 
 /* hbs_apply for callers that cannot allocate device memory: code under HIP graph capture, tight
@@ -226,7 +227,8 @@ int hbs_forward(hbs_handle* h, const double* x, int64_t nrhs, double* out);
  *   bragg    (2 mx) x q complex, mx = qp_max_modes(omega, d) (nullable): for angle a, rows
  *            0..n_modes_out[a]-1 hold c_n (Eq. 2.5) and rows mx..mx+n_modes_out[a]-1 hold d_n
  *            (Eq. 2.6) of the propagating orders n = nlo_out[a], nlo_out[a]+1, ...; other rows unset
- *   flux_err q doubles, energy-balance error of Remark 6.1 (nullable) */
+ *   flux_err q doubles, energy-balance error of Remark 6.1 (nullable)
+ * q = 0 returns HBS_OK at once and writes nothing (thetas and eta may then be NULL). */
 int qp_solve(hbs_handle* h, double period, double alpha_re, double alpha_im, const double* thetas,
              int64_t q, const qp_opts* opts, double* eta, double* xi, double* bragg,
              int32_t* nlo_out, int32_t* n_modes_out, double* flux_err);

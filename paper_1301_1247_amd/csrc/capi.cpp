@@ -462,7 +462,9 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
 static int apply_common_(hbs_handle* h, const double* in, int64_t nrhs, double* outp, bool inverse, int refine);
 static int apply_common(hbs_handle* h, const double* in, int64_t nrhs, double* outp, bool inverse, int refine) {
   clear_error();
-  if (!h || !in || !outp || nrhs < 0) { set_error("hbs_apply: bad arguments"); return HBS_E_INVALID_ARG; }
+  if (!h || nrhs < 0) { set_error("hbs_apply: bad arguments"); return HBS_E_INVALID_ARG; }
+  if (nrhs == 0) return HBS_OK;  // no columns: nothing read or written (the pointers may be NULL)
+  if (!in || !outp) { set_error("hbs_apply: bad arguments"); return HBS_E_INVALID_ARG; }
   BudgetScope bscope(&h->budget);
   return budget_status(h, apply_common_(h, in, nrhs, outp, inverse, refine));
 }
@@ -524,7 +526,9 @@ static int qp_common_(hbs_handle* h, double period, const double* thetas, int64_
 static int qp_common(hbs_handle* h, double period, const double* thetas, int64_t n, const qp_opts* opts, bool check,
                      double are, double aim, double* eta, double* xi, double* bragg, int32_t* nlo, int32_t* nm, double* flux) {
   clear_error();
-  if (!h || !thetas || !eta || n <= 0) { set_error("qp_solve: bad arguments"); return HBS_E_INVALID_ARG; }
+  if (!h || n < 0) { set_error("qp_solve: bad arguments"); return HBS_E_INVALID_ARG; }
+  if (n == 0) return HBS_OK;  // no angles: nothing to solve, nothing written
+  if (!thetas || !eta) { set_error("qp_solve: bad arguments"); return HBS_E_INVALID_ARG; }
   BudgetScope bscope(&h->budget);
   return budget_status(h, qp_common_(h, period, thetas, n, opts, check, are, aim, eta, xi, bragg, nlo, nm, flux));
 }

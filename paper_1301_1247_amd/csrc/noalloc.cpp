@@ -132,13 +132,14 @@ using namespace qps;
 
 extern "C" int hbs_apply_noalloc(hbs_handle* h, const double* rhs, int64_t nrhs, double* out, int32_t refine) {
   clear_error();
-  if (!h || !rhs || !out || nrhs < 0) { set_error("hbs_apply_noalloc: bad arguments"); return HBS_E_INVALID_ARG; }
+  if (!h || nrhs < 0) { set_error("hbs_apply_noalloc: bad arguments"); return HBS_E_INVALID_ARG; }
+  if (nrhs == 0) return HBS_OK;  // no columns: nothing read or written (the pointers may be NULL)
+  if (!rhs || !out) { set_error("hbs_apply_noalloc: bad arguments"); return HBS_E_INVALID_ARG; }
   if (h->opts.ptr_mode != HBS_PTR_DEVICE) {
     set_error("hbs_apply_noalloc: needs a handle built with HBS_PTR_DEVICE (rhs and out in device memory)");
     return HBS_E_INVALID_ARG;
   }
   if (refine < 0 || refine > 16) { set_error("hbs_apply_noalloc: refine must lie in [0, 16]"); return HBS_E_INVALID_ARG; }
-  if (nrhs == 0) return HBS_OK;
   if (rhs == out) { set_error("hbs_apply_noalloc: rhs and out may not alias"); return HBS_E_INVALID_ARG; }
   if (nrhs > (int64_t)1 << 30) { set_error("hbs_apply_noalloc: nrhs too large"); return HBS_E_INVALID_ARG; }
   const size_t need = apply_need(h, nrhs, refine);
