@@ -56,15 +56,19 @@ __device__ __forceinline__ void gstore(typename cx<R>::T* p, typename cx<R>::T v
 }
 
 template <class R, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm(const GemmDescT<R>* __restrict__ descs) {
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm(const GemmDescT<R>* __restrict__ descs, int xcd) {
   constexpr int BM = 32 * WM, BN = 32 * WN, NT = 64 * WM * WN;
   constexpr int QA = BM * BK / NT, QB = BK * BN / NT;  // slice elements of op(A) and B per thread
   typedef typename cx<R>::T C_t;
   typedef typename mfma_t<R>::acc acc_t;
-  // XCD-aware order over the (descriptor, tile) items: the tiles of one descriptor, which share its
-  // operand panels, meet in one L2 instead of each XCD fetching the panels from HBM
+  // xcd: XCD-aware order over the (descriptor, tile) items of a batch of independent products (the
+  // per-box products of a level): the tiles of one descriptor, which share its operand panels, meet
+  // in one L2 instead of each XCD fetching the panels.  The K-parts of a product split along K keep
+  // launch order: all XCDs then work on the same K range at once and share it through the
+  // last-level cache (one K-part per XCD measured twice as slow on products with K = 1.3e5).
   const int nx = gridDim.x;
-  const int T = xcd_item(blockIdx.x + blockIdx.y * nx, nx * gridDim.y);
+  const int L = blockIdx.x + blockIdx.y * nx;
+  const int T = xcd ? xcd_item(L, nx * gridDim.y) : L;
   const GemmDescT<R> d = descs[T / nx];
   const int tm = (d.m + BM - 1) / BM, tn = (d.n + BN - 1) / BN;
   const int t = T % nx;
@@ -252,10 +256,10 @@ hipError_t launch_gemm(const GemmDescT<R>* d, int nd, const GemmPlan& p, hipStre
   const dim3 grid(p.tiles, nd);
   GemmTuneTimer tt(p, s);
   switch (p.cfg) {
-    case 0: hipLaunchKernelGGL((k_gemm<R, 2, 2>), grid, dim3(256), 0, s, d); break;
-    case 1: hipLaunchKernelGGL((k_gemm<R, 1, 1>), grid, dim3(64), 0, s, d); break;
-    case 2: hipLaunchKernelGGL((k_gemm<R, 2, 1>), grid, dim3(128), 0, s, d); break;
-    case 3: hipLaunchKernelGGL((k_gemm<R, 1, 2>), grid, dim3(128), 0, s, d); break;
+    case 0: hipLaunchKernelGGL((k_gemm<R, 2, 2>), grid, dim3(256), 0, s, d, p.xcd); break;
+    case 1: hipLaunchKernelGGL((k_gemm<R, 1, 1>), grid, dim3(64), 0, s, d, p.xcd); break;
+    case 2: hipLaunchKernelGGL((k_gemm<R, 2, 1>), grid, dim3(128), 0, s, d, p.xcd); break;
+    case 3: hipLaunchKernelGGL((k_gemm<R, 1, 2>), grid, dim3(128), 0, s, d, p.xcd); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -368,7 +372,8 @@ hipError_t gemm_batched(DevBuf& arena, const std::vector<GemmDescT<R>>& v0, hipS
       v.push_back(h);
     }
   }
-  const GemmPlan plan = gemm_plan(v.data(), v.size());
+  GemmPlan plan = gemm_plan(v.data(), v.size());
+  if (!reds.empty()) plan.xcd = 0;  // K-parts share their K range through the last-level cache
   hipError_t e = upload(arena, v, s);
   if (e != hipSuccess) return e;
   {

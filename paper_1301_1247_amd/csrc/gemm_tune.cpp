@@ -114,6 +114,7 @@ GemmPlan gemm_plan(const GemmDescT<R>* v, size_t nd) {
   int64_t t = 0;
   for (size_t i = 0; i < nd; ++i) t = std::max<int64_t>(t, (int64_t)((v[i].m + bm - 1) / bm) * ((v[i].n + bn - 1) / bn));
   p.tiles = (int)t;
+  p.xcd = nd >= 8 ? 1 : 0;
   return p;
 }
 template GemmPlan gemm_plan<double>(const GemmDesc*, size_t);

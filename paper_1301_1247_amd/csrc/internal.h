@@ -209,6 +209,7 @@ hipError_t launch_gather_idx(const int* src, const int* idx, int* dst, int64_t n
 constexpr int kGemmConfigs = 4;
 struct GemmPlan {
   int cfg, tiles, key;
+  int xcd;  // 1: XCD-aware workgroup order (a batch of >= 8 independent products, none split along K)
 };
 // shape class of a batch: precision (0 complex128, 1 complex64) and ceil(log2) of the largest m,
 // n, k and of the entry count, packed as prec << 24 | m << 18 | n << 12 | k << 6 | count
