@@ -12,7 +12,8 @@ Also reported on the same JSON line:
 * kernel_families: summed HIP-event time per kernel family over the timed steps (events recorded on
   the stream each launch is issued on), its share, and the achieved rate against the family's
   roofline; `roofline` is the family with the largest time, `rooflines` every family above 5%;
-* variants: the same workload without the rank predictor and with the complex64 preconditioner;
+* variants: the same workload without the rank predictor, with the complex64 preconditioner, and
+  with Alpert's quadrature instead of Kapur-Rokhlin's (verified against Alpert rows);
 * c5: the 64-obstacle batch with a predictor trained on 48 obstacles, held-out rate with and without
   the predictor;
 * paper_grating: the paper's own d = 1 star grating (Sec. 6.1) at N = 2^17 with P = 1, build and solve
@@ -110,12 +111,13 @@ def cpu_baseline(wl, n_sample=4000, q_sample=4):
                                               "an estimate, not a measurement"}}
 
 
-def verify(wl, res, n_rows=48, n_ang=8):
+def verify(wl, res, n_rows=48, n_ang=8, quad="kr6"):
     """Sampled rows of the bordered-system residual of the timed solution, by the oracle's checker
-    (exact dense rows of A and B, all rows of C and Q), plus the flux error of every angle."""
+    (exact dense rows of A in the solve's quadrature and of B, all rows of C and Q), plus the flux
+    error of every angle."""
     from oracle import checks
     v = checks.bordered_residual(wl.curve, wl.N, wl.omega, wl.period, wl.thetas, res["eta"], res["xi"],
-                                 res["flux"], n_rows=n_rows, n_ang=n_ang)
+                                 res["flux"], n_rows=n_rows, n_ang=n_ang, quad=quad)
     v["kind"] = "sampled residual of the bordered system (Eq. 2.19) relative to |b|, not a forward error"
     v["ok"] = bool(v["sampled_rel_residual"] <= 1e-10 and v["flux_err_max"] <= 1e-8)
     return v
@@ -416,14 +418,15 @@ def main():
     if not args.no_variants and args.precision == "fp64" and args.rank_predictor == "on":
         variants = {}
         for name, vkw in (("no_rank_predictor", dict(kw, rank_predictor=False)),
-                          ("fp32_preconditioner", dict(kw, precision="fp32"))):
+                          ("fp32_preconditioner", dict(kw, precision="fp32")),
+                          ("alpert_quadrature", dict(kw, quad="alpert"))):
             hv, rv, tv, bv = run_steps(B, torch, wl, t_nodes, t_w, t_nrm, t_th, vkw, args.tol, cw, 3, 1)
             sv = hv.stats()
             vr = {"value": nang * 3 / tv, "unit": "angles/s", "ms_per_step": 1000.0 * tv / 3,
                   "build_seconds": float(np.median(bv)), "refine_iters": sv.refine_iters,
                   "refine_residual": sv.refine_residual, "root_level": sv.root_level}
             if not args.no_verify:
-                vr["verify"] = verify(wl, host_solution(rv))
+                vr["verify"] = verify(wl, host_solution(rv), quad=vkw.get("quad", "kr6"))
                 if not vr["verify"]["ok"]:
                     vr["value"] = None
             variants[name] = vr

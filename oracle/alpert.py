@@ -137,3 +137,36 @@ def matrix_alpert(disc: nystrom.Discretization, omega: float, curve, m=M_DEFAULT
                 A[idx, (idx + oo) % N] += h * wq[j] * kv * sp * ll
     A[idx, idx] += 0.5
     return A
+
+
+def matrix_alpert_rows(disc: nystrom.Discretization, omega: float, curve, rows, m=M_DEFAULT, a=A_DEFAULT) -> np.ndarray:
+    """Rows ``rows`` of ``matrix_alpert``, evaluated without forming the others."""
+    from scipy.special import hankel1
+    N = disc.N
+    h = 2 * math.pi / N
+    rows = np.asarray(rows, dtype=np.int64).reshape(-1)
+    x, wq = rule(m, a)
+    idx = np.arange(N)
+    R = np.arange(len(rows))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        K = nystrom.kernel(omega, disc.x[rows], disc.x, disc.nrm)
+    dist = np.abs(rows[:, None] - idx[None, :])
+    dist = np.minimum(dist, N - dist)
+    A = np.where(dist >= a, K, 0.0) * disc.w[None, :]
+    for j in range(m):
+        for sg in (1.0, -1.0):
+            u = sg * x[j]
+            z, dz, _ = curve.sample(disc.t[rows] + u * h)
+            sp = np.hypot(dz[:, 0], dz[:, 1])
+            nr = np.stack([dz[:, 1], -dz[:, 0]], axis=1) / sp[:, None]
+            dx = disc.x[rows, 0] - z[:, 0]
+            dy = disc.x[rows, 1] - z[:, 1]
+            r = np.hypot(dx, dy)
+            nd = (nr[:, 0] * dx + nr[:, 1] * dy) / r
+            kv = 1j * omega / 4.0 * hankel1(1, omega * r) * nd + omega / 4.0 * hankel1(0, omega * r)
+            o, L = lagrange(u)
+            for oo, ll in zip(o, L):
+                A[R, (rows + oo) % N] += h * wq[j] * kv * sp * ll
+    A[R, rows] += 0.5
+    return A
+

@@ -19,6 +19,7 @@ import math
 
 import numpy as np
 
+from . import alpert
 from . import nystrom
 from . import periodic
 
@@ -34,8 +35,8 @@ class RowSubset:
 
 
 def bordered_residual(curve, N, omega, period, thetas, eta, xi, flux=None, n_rows=48, n_ang=8, chunk=4000,
-                      seed=7, angles=None, P=0, h=0.1):
-    """Sampled relative residual of the bordered system (KR6 quadrature; Eq. 2.19, or Eq. 2.21 with
+                      seed=7, angles=None, P=0, h=0.1, quad="kr6"):
+    """Sampled relative residual of the bordered system (KR6 or, with quad="alpert", Alpert quadrature; Eq. 2.19, or Eq. 2.21 with
     P = 1 neighbour images: A~ = A + alpha A_1 + alpha^-1 A_-1 and C~ of Sec. 2.4) for the solutions
     eta (N x n) and xi (2M x n) of the angles ``thetas`` (n), M from the default contour of spacing h.
 
@@ -50,7 +51,10 @@ def bordered_residual(curve, N, omega, period, thetas, eta, xi, flux=None, n_row
     rng = np.random.default_rng(seed)
     rows = np.sort(rng.choice(N, n_rows, replace=False))
     angs = np.asarray(angles) if angles is not None else rng.choice(len(thetas), n_ang, replace=False)
-    Arows = nystrom.matrix_kr6_rows(disc, omega, rows)
+    if quad not in ("kr6", "alpert"):
+        raise ValueError("quad must be 'kr6' or 'alpert'")
+    Arows = (nystrom.matrix_kr6_rows(disc, omega, rows) if quad == "kr6"
+             else alpert.matrix_alpert_rows(disc, omega, curve, rows))
     Anb = {j: nystrom.neighbour_rows(disc, omega, j * period, rows) for j in ((-1, 1) if P else ())}
     sub = RowSubset(disc, rows)
     BL, BR = periodic.wall_B(sub, omega, period, ct)

@@ -78,3 +78,24 @@ def test_alpert_circle_closed_form_through_gpu(gpu_lib):
         v = np.exp(1j * n * t)
         x = h.apply(v, refine=2)
         assert np.abs(x - v / ny.circle_eigenvalue(om, 1.0, n)).max() < bar * np.abs(x).max()
+
+
+def test_alpert_full_size_sampled_residual(gpu_lib):
+    """The benchmark's workload (N = 1e5, omega = 60, 200 angles, compressed walls, rank predictor,
+    deferred root) with Alpert's quadrature: sampled rows of the bordered residual against the
+    oracle's Alpert rows, and the energy balance of every angle."""
+    import torch
+    from oracle import checks
+    wl = qpinputs.workload("wavy40")
+    nodes, w, nrm, _ = discretize(wl.curve, wl.N)
+    t = lambda a: torch.from_numpy(a).to("cuda")
+    c = 0.5 * (nodes.max(0) + nodes.min(0))
+    far = 0.9 * (0.5 * wl.period - abs(c[0]))
+    h = gpu_lib.Handle(t(nodes), t(w), t(nrm), wl.omega, 1e-13, quad="alpert", leaf_size=64, device=True,
+                       far_radius=far, rank_predictor=True, defer_root=True)
+    res = h.qp_solve_many(wl.period, t(wl.thetas), compress_walls=1)
+    v = checks.bordered_residual(wl.curve, wl.N, wl.omega, wl.period, wl.thetas, res["eta"].T.cpu().numpy(),
+                                 res["xi"].T.cpu().numpy(), res["flux"], n_rows=32, n_ang=8, quad="alpert")
+    print(f"alpert N=1e5 {v}", flush=True)
+    assert v["sampled_rel_residual"] < 1e-10
+    assert v["flux_err_max"] < 1e-8

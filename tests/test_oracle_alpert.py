@@ -103,3 +103,28 @@ def test_alpert_qp_solution_flux_balance():
     A = al.matrix_alpert(disc, wl.omega, wl.curve)
     r = pq.solve_qp(disc, 800, wl.omega, wl.period, wl.thetas, A0=A)
     assert r["flux"][0] < 1e-11
+
+
+def test_alpert_rows_equal_full_matrix_rows():
+    c = qpinputs.wavy(130102, 20, 0.3)
+    disc = ny.Discretization(c, 200)
+    A = al.matrix_alpert(disc, 20.0, c)
+    rows = np.array([0, 1, 5, 100, 198, 199])
+    assert np.array_equal(al.matrix_alpert_rows(disc, 20.0, c, rows), A[rows])
+
+
+def test_residual_checker_alpert_rows():
+    """The sampled residual with Alpert rows is at rounding level for the oracle's own Alpert solution,
+    and far from it for the KR6 solution of the same problem (the two discretizations differ)."""
+    from oracle import checks
+    c = qpinputs.star()
+    N, om, d = 400, 10.0, 2 * math.pi
+    th = np.array([-0.7, -1.1])
+    disc = ny.Discretization(c, N)
+    r = pq.solve_qp(disc, N, om, d, th, A0=al.matrix_alpert(disc, om, c))
+    v = checks.bordered_residual(c, N, om, d, th, r["eta"], r["xi"], n_rows=30, n_ang=2, chunk=100, quad="alpert")
+    assert v["sampled_rel_residual"] < 1e-12
+    r6 = pq.solve_qp(c, N, om, d, th, quad="kr6")
+    v6 = checks.bordered_residual(c, N, om, d, th, r6["eta"], r6["xi"], n_rows=30, n_ang=2, chunk=100, quad="alpert")
+    assert v6["sampled_rel_residual"] > 1e-8
+
