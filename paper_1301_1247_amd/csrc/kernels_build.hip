@@ -10,8 +10,12 @@ constexpr int NT = 256;  // threads per workgroup (4 wavefronts)
 // ---------------------------------------------------------------- block evaluation
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_blocks(Geo G, const BlockDesc* __restrict__ descs) {
   const BlockDesc d = descs[blockIdx.y];
+  // one entry per thread, no grid-stride loop: inside a loop the compiler hoists the Hankel
+  // coefficient tables into scalar registers and spills hundreds of them to vector lanes
   const int total = d.nr * d.nc;
-  for (int e = blockIdx.x * NT + threadIdx.x; e < total; e += gridDim.x * NT) {
+  const int e = blockIdx.x * NT + threadIdx.x;
+  if (e >= total) return;
+  {
     const int r = e % d.nr, c = e / d.nr;
     const int gr = d.rows[r], gc = d.cols[c];
     cplx v;
@@ -36,7 +40,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       const cplx k2 = mkc(q * (h0.x - h1.y * nd2), q * (h0.y + h1.x * nd2));
       d.out[r + (size_t)c * d.ld] = cscale(k1, R * G.w[gr]);
       d.out[d.pair_off + r + (size_t)c * d.ld] = cscale(k2, R * G.w[gc]);
-      continue;
+      return;
     }
     if (d.sx != 0.0) {
       // image point y_gr + (sx, 0): source of the field at x_gc (trans) or target of the field of x_gc
@@ -60,7 +64,10 @@ __global__ __launch_bounds__(NT) void k_proxy(Geo G, const ProxyDesc* __restrict
   const double wp = 2.0 * QPS_PI * d.R / d.np;
   const double swp = sqrt(wp);
   const double q = 0.25 * G.omega;
-  for (int e = blockIdx.x * NT + threadIdx.x; e < total; e += gridDim.x * NT) {
+  // one entry per thread (see k_eval_blocks)
+  const int e = blockIdx.x * NT + threadIdx.x;
+  if (e >= total) return;
+  {
     const int l = e % d.np, i = e / d.np;
     double sn, cs;
     sincos(2.0 * QPS_PI * l / d.np, &sn, &cs);
@@ -1090,13 +1097,13 @@ namespace qps {
 
 hipError_t launch_eval_blocks(const Geo& g, const BlockDesc* d, int nd, int max_elems, hipStream_t s) {
   if (nd == 0 || max_elems == 0) return hipSuccess;
-  dim3 grid(grid_for(max_elems, 256), nd);
+  dim3 grid(grid_for(max_elems, 1 << 30), nd);  // every entry its own thread
   hipLaunchKernelGGL(k_eval_blocks, grid, dim3(NT), 0, s, g, d);
   return hipGetLastError();
 }
 hipError_t launch_proxy(const Geo& g, const ProxyDesc* d, int nd, int max_elems, hipStream_t s) {
   if (nd == 0 || max_elems == 0) return hipSuccess;
-  dim3 grid(grid_for(max_elems, 256), nd);
+  dim3 grid(grid_for(max_elems, 1 << 30), nd);  // every entry its own thread
   hipLaunchKernelGGL(k_proxy, grid, dim3(NT), 0, s, g, d);
   return hipGetLastError();
 }
