@@ -1151,7 +1151,7 @@ hipError_t launch_cpqr(const CpqrDesc* d, int nd, int max_s, int max_n, double t
   }
   if (launches) *launches = 1;
   if (nd >= 256 && max_s <= 512 && max_n <= 256)
-    hipLaunchKernelGGL((k_cpqr<256, 512, 256, 0>), dim3(nd), dim3(256), 0, s, d, tol, k_out);
+    hipLaunchKernelGGL((k_cpqr<256, 512, 256, 8>), dim3(nd), dim3(256), 0, s, d, tol, k_out);
   else
     hipLaunchKernelGGL((k_cpqr<1024, CPQR_MAXS, CPQR_MAXN, 12>), dim3(nd), dim3(1024), 0, s, d, tol, k_out);
   return hipGetLastError();
