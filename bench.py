@@ -323,8 +323,8 @@ def main():
     ap.add_argument("--no-grating", action="store_true", help="skip the paper's d = 1 star grating at N = 2^17")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the sharding design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU (asked for --gpus {args.gpus}); splitting the angles and "
+              "Bloch phases over GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
