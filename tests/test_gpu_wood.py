@@ -125,3 +125,36 @@ def test_kr6_rough_obstacle_near_wood(gpu_lib, walls):
     # N = 2000 at omega = 40 resolves the field to about 1e-5 (energy balance), so only the
     # agreement with the oracle is held to 1e-10 here
     _check_angle(res, 0, disc, om, d, th, st.wood_shift, A, "kr6", physics=False)
+
+
+def test_wood_scheme_at_full_size_agrees_with_undisplaced(gpu_lib):
+    """N = 1e5 (the benchmark's obstacle, omega = 60, compressed walls, predictor, deferred root):
+    angles whose smallest |k_n| lies in [0.9, 1.6], where the undisplaced contour is still
+    accurate, solved once on it and once on the displaced contour with the added Rayleigh-Bloch
+    waves (wood_min_kn = 2 sends them there).  eta is the physical density in both schemes, so
+    the two agree to the 1e-10 bar, and both conserve energy; an exact anomaly in the same call
+    takes the displaced contour by itself."""
+    import torch
+    wl = qpinputs.workload("wavy40")
+    om, d = wl.omega, wl.period
+    kap = [-om + 2 * math.pi * m / d + dk for m, dk in ((3, 0.01), (7, -0.012), (11, 0.014))]
+    ths = [-math.acos(k / om) for k in kap]
+    thw = -math.acos(1 - 2 * math.pi * 9 / (om * d))   # order grazing exactly
+    for th in ths:
+        kx = om * math.cos(th) + 2 * math.pi * np.arange(-40, 41) / d
+        assert 0.9 <= np.sqrt(np.abs(om ** 2 - kx ** 2)).min() <= 1.6
+    nodes, w, nrm, _ = discretize(wl.curve, wl.N)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    c0 = 0.5 * (nodes.max(0) + nodes.min(0))
+    far = 0.9 * (0.5 * d - abs(c0[0]))
+    h = gpu_lib.Handle(t(nodes), t(w), t(nrm), om, 1e-13, leaf_size=64, device=True, far_radius=far,
+                       rank_predictor=True, defer_root=True)
+    r0 = h.qp_solve_many(d, t(np.array(ths)), compress_walls=1)
+    assert h.stats().wood_angles == 0
+    r1 = h.qp_solve_many(d, t(np.array(ths + [thw])), compress_walls=1, wood_min_kn=2.0)
+    st = h.stats()
+    assert st.wood_angles == 4 and st.wood_orders >= 1   # a phase whose shift crosses no pole adds none
+    e0, e1 = r0["eta"].cpu().numpy(), r1["eta"].cpu().numpy()
+    for a in range(len(ths)):
+        assert _cmp(e1[a], e0[a]) < BAR, a
+    assert max(r0["flux"]) < 1e-10 and max(r1["flux"]) < 1e-10
