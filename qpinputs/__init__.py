@@ -133,6 +133,16 @@ def shared_phase_angles(omega: float, period: float, n_phase: int = 4, per_phase
     return np.array(out)
 
 
+def wood_sweep_angles(omega: float, period: float, n: int = 200, groups: int = 21):
+    """The angle sweep of Sec. 6.2: cos(theta) in steps of 2 pi / (groups omega d) from grazing
+    (theta -> -pi), so the Bloch phases repeat with period `groups`.  When omega d / (2 pi) is an
+    integer, every angle of the phase alpha = 1 sits exactly on a Wood's anomaly (some k_n = 0) and
+    its neighbours come close to one."""
+    c = -1.0 + np.arange(1, n + 1) * TWO_PI / (groups * omega * period)
+    c = c[c < 1.0]
+    return -np.arccos(c)
+
+
 def rank_training_set(n: int = 64, seed: int = 4242):
     """Seeded obstacles for fitting and checking the rank predictor (64 by default).
 
