@@ -17,6 +17,8 @@ Modules:
               Kress spectral log-split weights.
   nystrom     curve discretization, kernel, dense A, neighbour images A_j, fields.
   periodic    Sommerfeld contour, B, C, Q, bordered solve, Bragg amplitudes, flux.
+  transmission  the transmission problem of Sec. 5: the interlaced 2 x 2 Mueller-type
+              operator at wavenumbers omega and n omega, its B, C, Bragg amplitudes.
 
 Each function names the passage of the paper it follows.  Readings of passages
 that are silent or misprinted are listed in the module docstrings.
