@@ -113,6 +113,21 @@ typedef struct {
                                stream applies the tree's upward pass; other calls invert it on entry.
                                A singular root is then reported by that call (HBS_E_SINGULAR), and
                                build_seconds leaves the root inversion out.  0 = in hbs_build */
+  double index;             /* > 0: the transmission problem of Sec. 5 instead of the Dirichlet problem:
+                               refractive index n of the obstacle (wavenumber n omega inside, omega
+                               outside), matching conditions of Eqs. 5.3-5.4.  The unknowns are the
+                               densities tau (double layer) and sigma (single layer) of both sides'
+                               potentials, interlaced node by node as Sec. 5.3 asks: 2N unknowns
+                               [tau_1; sigma_1; tau_2; ...], row 2i the value jump at node i and row
+                               2i + 1 minus the normal-derivative jump, so that the operator is
+                               I + [[D0 - D1, S0 - S1], [-(T0 - T1), -(D0* - D1*)]] (T the normal
+                               derivative of D, D* that of S; 0 and 1 the two wavenumbers), every block
+                               with the Kapur-Rokhlin weights.  Every N-sized vector of the other calls
+                               (hbs_apply's rhs, qp_solve's eta) then has 2N rows, and leaf_size counts
+                               unknowns.  Needs HBS_QUAD_KR6, far_radius = 0, image_period = 0 and
+                               rank_predictor = 0; qp_solve takes P = 0 with the wall blocks
+                               uncompressed, and refuses angles near a Wood's anomaly (HBS_E_WOOD).
+                               0 = the Dirichlet problem */
 } hbs_opts;
 
 typedef struct {
@@ -176,6 +191,7 @@ typedef struct {
   double wood_shift;        /* real-axis crossing of the last displaced contour (0 = none) */
   int64_t image_samples;    /* image points taken as explicit columns over all boxes and levels
                                (hbs_opts.image_period) */
+  int64_t unknowns;         /* length of the handle's vectors: N, or 2N for the transmission problem */
 } hbs_stats_t;
 
 void hbs_opts_init(hbs_opts* o);
@@ -293,7 +309,8 @@ int qps_kr6_corrections(double out[6]);
  * long double on the conditions of the generalized Euler-Maclaurin expansion, Sec. 2.3's named
  * alternative to Kapur-Rokhlin); m in [1, 8], a in [1, 12]; HBS_E_NOT_CONVERGED if Newton fails. */
 int qps_alpert_rule(int32_t m, int32_t a, double* x, double* w);
-/* Entries A(rows[t], cols[t]) of the Nystrom matrix of the handle, evaluated on the GPU. */
+/* Entries A(rows[t], cols[t]) of the Nystrom matrix of the handle, evaluated on the GPU (indices of
+ * the handle's unknowns: 0 .. hbs_stats.unknowns - 1). */
 int qps_matrix_entries(hbs_handle* h, const int32_t* rows, const int32_t* cols, int64_t n, double* out);
 /* Batched complex GEMM C_b = A_b B_b (+ C_b if accumulate) on the GPU with the library's
  * MFMA kernel: nbatch equal-size problems, A: m x k, B: k x n, C: m x n, col-major, packed. */

@@ -41,7 +41,7 @@ class HbsOpts(C.Structure):
                 ("far_radius", C.c_double), ("precision", C.c_int32), ("fp64_top_levels", C.c_int32),
                 ("rank_predictor", C.c_int32), ("rank_scale", C.c_double), ("rank_model", C.c_void_p),
                 ("root_level", C.c_int32), ("graph", C.c_int32), ("mem_limit", C.c_uint64),
-                ("image_period", C.c_double), ("defer_root", C.c_int32)]
+                ("image_period", C.c_double), ("defer_root", C.c_int32), ("index", C.c_double)]
 
 
 class QpOpts(C.Structure):
@@ -59,7 +59,8 @@ class HbsStats(C.Structure):
                 ("walls_compressed", C.c_int32), ("rank_fallbacks", C.c_int32), ("sketch_bytes_max", C.c_int64),
                 ("cpqr_work", C.c_double), ("root_level", C.c_int32), ("graph_captures", C.c_int64),
                 ("graph_replays", C.c_int64), ("device_bytes_peak", C.c_int64), ("wood_angles", C.c_int32),
-                ("wood_orders", C.c_int32), ("wood_shift", C.c_double), ("image_samples", C.c_int64)]
+                ("wood_orders", C.c_int32), ("wood_shift", C.c_double), ("image_samples", C.c_int64),
+                ("unknowns", C.c_int64)]
 
 
 _P = C.c_void_p
@@ -159,7 +160,8 @@ class Handle:
     def __init__(self, nodes, weights, normals, omega, tol, quad="kr6", compress=None, leaf_size=64,
                  curvature=None, device=False, stream=None, proxy_ratio=2.0, proxy_min=64, seed=0x5EED1301,
                  far_radius=0.0, precision="fp64", fp64_top_levels=0, rank_predictor=False, rank_scale=1.0,
-                 rank_model=None, root_level=0, graph=False, mem_limit=0, image_period=0.0, defer_root=False):
+                 rank_model=None, root_level=0, graph=False, mem_limit=0, image_period=0.0, defer_root=False,
+                 index=0.0):
         if compress is None:
             compress = "exact" if quad == "kress" else "proxy"
         self.device = bool(device)
@@ -178,6 +180,8 @@ class Handle:
             N = int(weights.shape[0])
             st = stream
         self.N = N
+        # unknowns: two densities per node for the transmission problem (index > 0), interlaced
+        self.NU = 2 * N if index > 0 else N
         self.omega = float(omega)
         o = hbs_opts(quad=QUAD[quad], compress=COMPRESS[compress], leaf_size=int(leaf_size),
                      proxy_ratio=float(proxy_ratio), proxy_min=int(proxy_min),
@@ -186,7 +190,7 @@ class Handle:
                      precision={"fp64": 0, "fp32": 1}[precision], fp64_top_levels=int(fp64_top_levels),
                      rank_predictor=1 if rank_predictor else 0, rank_scale=float(rank_scale),
                      root_level=int(root_level), graph=1 if graph else 0, mem_limit=int(mem_limit),
-                     image_period=float(image_period), defer_root=1 if defer_root else 0)
+                     image_period=float(image_period), defer_root=1 if defer_root else 0, index=float(index))
         if rank_model is not None:
             rank_model = np.ascontiguousarray(rank_model, dtype=np.float32)
             o.rank_model = rank_model.ctypes.data
@@ -213,7 +217,8 @@ class Handle:
         return np.empty((rows, cols), dtype=np.complex128, order="F")
 
     def apply(self, rhs, refine=0):
-        """A^{-1} rhs (N x r).  Host: numpy (N,) or (N, r); device: torch (r, N) complex128 (column-major N x r)."""
+        """A^{-1} rhs (NU x r, NU = the handle's unknowns).  Host: numpy (NU,) or (NU, r); device: torch (r, NU)
+        complex128 (column-major NU x r)."""
         if self.device:
             r = rhs.shape[0] if rhs.dim() == 2 else 1
             out = self._torch.empty_like(rhs)
@@ -260,13 +265,13 @@ class Handle:
             torch = self._torch
             th = thetas.to(device="cuda", dtype=torch.float64).contiguous()
             n = th.shape[0]
-            eta = torch.empty((n, self.N), dtype=torch.complex128, device="cuda")
+            eta = torch.empty((n, self.NU), dtype=torch.complex128, device="cuda")
             xi = torch.empty((n, 2 * M), dtype=torch.complex128, device="cuda")
             bragg = torch.empty((n, 2 * maxm), dtype=torch.complex128, device="cuda")
         else:
             th = np.ascontiguousarray(thetas, dtype=np.float64)
             n = th.shape[0]
-            eta = np.empty((self.N, n), dtype=np.complex128, order="F")
+            eta = np.empty((self.NU, n), dtype=np.complex128, order="F")
             xi = np.empty((2 * M, n), dtype=np.complex128, order="F")
             bragg = np.empty((2 * maxm, n), dtype=np.complex128, order="F")
         nlo = np.zeros(n, dtype=np.int32)

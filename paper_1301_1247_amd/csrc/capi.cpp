@@ -310,6 +310,19 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
     set_error("hbs_build: image_period needs far_radius > 0 (the far-field circle represents the images beyond it)");
     return HBS_E_INVALID_ARG;
   }
+  if (!(o.index >= 0) || !std::isfinite(o.index)) { set_error("hbs_build: index must be finite and >= 0"); return HBS_E_INVALID_ARG; }
+  if (o.index > 0) {
+    // the transmission problem (Sec. 5) is built on the Kapur-Rokhlin operator with proxy or exact
+    // compression; the far-field circle, the image columns and the Dirichlet-trained rank model are
+    // not carried over to it
+    if (o.quad != HBS_QUAD_KR6) { set_error("hbs_build: the transmission problem (index > 0) needs HBS_QUAD_KR6"); return HBS_E_INVALID_ARG; }
+    if (o.far_radius > 0 || o.image_period > 0) {
+      set_error("hbs_build: the transmission problem (index > 0) takes far_radius = 0 and image_period = 0");
+      return HBS_E_INVALID_ARG;
+    }
+    if (o.rank_predictor) { set_error("hbs_build: the transmission problem (index > 0) takes rank_predictor = 0"); return HBS_E_INVALID_ARG; }
+    if (N > ((int64_t)1 << 29)) { set_error("hbs_build: N too large for the transmission problem"); return HBS_E_INVALID_ARG; }
+  }
   if (o.rank_predictor && !o.rank_model && kRankModelDefaultN != MLP_NPARAM) {
     set_error("hbs_build: the library has no built-in rank model; pass hbs_opts.rank_model");
     return HBS_E_INVALID_ARG;
@@ -329,7 +342,10 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
       return HBS_E_INVALID_ARG;
     }
   }
-  if (N < 2 * (int64_t)o.leaf_size) { set_error("hbs_build: N must be at least 2 * leaf_size"); return HBS_E_INVALID_ARG; }
+  if ((o.index > 0 ? 2 : 1) * N < 2 * (int64_t)o.leaf_size) {
+    set_error("hbs_build: the number of unknowns must be at least 2 * leaf_size");
+    return HBS_E_INVALID_ARG;
+  }
   if (N > (int64_t)1 << 30) { set_error("hbs_build: N too large"); return HBS_E_INVALID_ARG; }
   std::vector<double> xy, w, nrm, kap;
   int r;
@@ -351,6 +367,8 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
   h->budget.limit = (size_t)o.mem_limit;
   BudgetScope bscope(&h->budget);
   h->N = N;
+  h->nc = o.index > 0 ? 2 : 1;
+  h->NU = h->nc * N;
   h->omega = omega;
   h->tol = tol;
   h->opts = o;
@@ -385,6 +403,8 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
   G.N = (int)N;
   G.quad = o.quad;
   G.omega = omega;
+  G.two = o.index > 0;
+  G.omega1 = o.index > 0 ? o.index * omega : 0.0;
   kr6_corrections(G.g);
   if (o.quad == HBS_QUAD_KRESS) {
     std::vector<double> R = kress_weights(N);
@@ -472,7 +492,7 @@ static int apply_common_(hbs_handle* h, const double* in, int64_t nrhs, double* 
   if (nrhs == 0) return HBS_OK;
   if (in == outp) { set_error("hbs_apply: rhs and out may not alias"); return HBS_E_INVALID_ARG; }
   hipStream_t st = h->stream;
-  const int64_t N = h->N;
+  const int64_t N = h->NU;
   const size_t bytes = sizeof(cplx) * N * nrhs;
   const cplx* B;
   cplx* X;
@@ -567,7 +587,7 @@ static int qp_common_(hbs_handle* h, double period, const double* thetas, int64_
   if (M <= 0) return HBS_E_INVALID_ARG;
   const int maxm = qps::qp_max_modes_impl(h->omega, period);
   hipStream_t st = h->stream;
-  const int64_t N = h->N;
+  const int64_t N = h->NU;
   DevBuf de, dx, db;
   cplx *pe, *px = nullptr, *pb = nullptr;
   const bool host = h->opts.ptr_mode == HBS_PTR_HOST;
@@ -621,6 +641,7 @@ int hbs_stats(const hbs_handle* h, hbs_stats_t* s) {
   s->struct_size = sizeof(hbs_stats_t);
   s->levels = h->L;
   s->N = h->N;
+  s->unknowns = h->NU;
   s->root_size = h->nroot;
   int mr = 0;
   for (int l = 1; l <= h->L; ++l)
@@ -685,7 +706,7 @@ int qps_matrix_entries(hbs_handle* h, const int32_t* rows, const int32_t* cols, 
   if (!h || !rows || !cols || !out || n < 0) { set_error("qps_matrix_entries: bad arguments"); return HBS_E_INVALID_ARG; }
   if (n == 0) return HBS_OK;
   for (int64_t i = 0; i < n; ++i)
-    if (rows[i] < 0 || rows[i] >= h->N || cols[i] < 0 || cols[i] >= h->N) {
+    if (rows[i] < 0 || rows[i] >= h->NU || cols[i] < 0 || cols[i] >= h->NU) {
       set_error("qps_matrix_entries: index out of range");
       return HBS_E_INVALID_ARG;
     }

@@ -103,3 +103,53 @@ __device__ inline cplx a_entry(const Geo& G, int i, int j) {
   if (G.quad == HBS_QUAD_ALPERT) return a_entry_alpert(G, i, j);
   return G.quad == HBS_QUAD_KRESS ? a_entry_kress(G, i, j) : a_entry_kr6(G, i, j);
 }
+
+// Transmission problem (Sec. 5): the four difference kernels of the interlaced 2 x 2 operator, with
+// H0, H1 taken at k0 r and k1 r (k0 = omega outside, k1 = n omega inside), a = n_x.(x - y)/r,
+// b = n_y.(x - y)/r, nn = n_x.n_y, d1 = k0 H1(k0 r) - k1 H1(k1 r), d0 = k0^2 H0(k0 r) - k1^2 H0(k1 r):
+//   (row 0, col 0)  D0 - D1           = (i/4) b d1
+//   (0, 1)          S0 - S1           = (i/4) [H0(k0 r) - H0(k1 r)]
+//   (1, 0)          -(T0 - T1)        = -(i/4) [a b d0 + (nn - 2 a b) d1 / r]
+//   (1, 1)          -(D0* - D1*)      = (i/4) a d1
+// (T = d^2 G / dn_x dn_y, D* = dG/dn_x; the 1/r^2 parts of T0 and T1 cancel in d1 / r).
+__device__ inline cplx tr_kernel(double k0, double k1, double dx, double dy, double tnx, double tny, double snx,
+                                 double sny, int cr, int cc) {
+  const double r = sqrt(dx * dx + dy * dy);
+  cplx a0, a1, b0, b1;
+  hankel01(k0 * r, a0, a1);
+  hankel01(k1 * r, b0, b1);
+  cplx v;
+  if (cr == 0 && cc == 1) {
+    v = mkc(a0.x - b0.x, a0.y - b0.y);
+  } else {
+    const cplx d1 = mkc(k0 * a1.x - k1 * b1.x, k0 * a1.y - k1 * b1.y);
+    const double a = (tnx * dx + tny * dy) / r, b = (snx * dx + sny * dy) / r;
+    if (cr == 0) {
+      v = cscale(d1, b);
+    } else if (cc == 1) {
+      v = cscale(d1, a);
+    } else {
+      const double k02 = k0 * k0, k12 = k1 * k1;
+      const cplx d0 = mkc(k02 * a0.x - k12 * b0.x, k02 * a0.y - k12 * b0.y);
+      const double ab = a * b, c = (tnx * snx + tny * sny - 2.0 * ab) / r;
+      v = mkc(-(ab * d0.x + c * d1.x), -(ab * d0.y + c * d1.y));
+    }
+  }
+  return mkc(-0.25 * v.y, 0.25 * v.x);  // (i/4) v
+}
+
+// Entry (u, v) of the transmission operator I + K (u = 2 i + c_r, v = 2 j + c_c) with the
+// Kapur-Rokhlin weights R_{(i-j) mod N} of Sec. 2.3 on every block (R_0 = 0: the kernel drops at i = j).
+__device__ inline cplx a_entry_tr(const Geo& G, int u, int v) {
+  const int i = u >> 1, j = v >> 1, cr = u & 1, cc = v & 1;
+  if (i == j) return mkc(cr == cc ? 1.0 : 0.0, 0.0);
+  const cplx K = tr_kernel(G.omega, G.omega1, G.x[i] - G.x[j], G.y[i] - G.y[j], G.nx[i], G.ny[i], G.nx[j], G.ny[j], cr, cc);
+  int m = i - j;
+  if (m < 0) m += G.N;
+  double R = 1.0;
+  if (m <= 6) R += G.g[m - 1];
+  else if (m >= G.N - 6) R += G.g[G.N - m - 1];
+  return cscale(K, R * G.w[j]);
+}
+
+__device__ inline cplx a_entry_any(const Geo& G, int i, int j) { return G.two ? a_entry_tr(G, i, j) : a_entry(G, i, j); }

@@ -68,7 +68,8 @@ int build(hbs_handle* h) {
   hipStream_t st = h->stream;
   const int64_t N = h->N;
   const int leaf = h->opts.leaf_size;
-  int L = (int)std::ceil(std::log2((double)N / (double)leaf));
+  // leaf_size counts unknowns (two per node for the transmission problem); boxes split the nodes
+  int L = (int)std::ceil(std::log2((double)h->NU / (double)leaf));
   if (L < 1) L = 1;
   while ((N >> L) < 2 && L > 1) --L;
   h->L = L;
@@ -84,6 +85,7 @@ int build(hbs_handle* h) {
   const double ratio = h->opts.proxy_ratio;
   const int pmin = h->opts.proxy_min;
   const double om = h->omega;
+  const double om_max = h->geo.two ? std::max(om, h->geo.omega1) : om;  // the proxies resolve both wavenumbers
 
   // far-field circle (neighbour images lie outside radius far_radius about the obstacle's centre)
   {
@@ -362,9 +364,9 @@ int build(hbs_handle* h) {
     V.n.assign(nb, 0);
     V.aoff.assign(nb + 1, 0);
     if (l == L) {
-      for (int b = 0; b < nb; ++b) V.n[b] = V.hi[b] - V.lo[b];
-      V.hact.resize(N);
-      for (int64_t i = 0; i < N; ++i) V.hact[i] = (int)i;
+      for (int b = 0; b < nb; ++b) V.n[b] = (V.hi[b] - V.lo[b]) * h->nc;
+      V.hact.resize(h->NU);
+      for (int64_t i = 0; i < h->NU; ++i) V.hact[i] = (int)i;
     } else {
       Level& C = h->lv[l + 1];
       for (int b = 0; b < nb; ++b) V.n[b] = C.k[2 * b] + C.k[2 * b + 1];
@@ -465,7 +467,7 @@ int build(hbs_handle* h) {
       mind[b] = md;
       nnear[b] = cnt;
       const bool full = (cnt == total_other);
-      np[b] = full ? 0 : std::max(pmin, (int)std::ceil(1.5 * om * Rp) + 50);
+      np[b] = full ? 0 : std::max(pmin, (int)std::ceil(1.5 * om_max * Rp) + 50);
       // sources beyond far_radius must be represented too: by the box's own proxies when its
       // circle lies inside far_radius, else by proxies on the far-field circle
       const bool inside = !full && std::hypot(V.cx[b] - h->c0x, V.cy[b] - h->c0y) + Rp < h->opts.far_radius;
@@ -499,7 +501,7 @@ int build(hbs_handle* h) {
         }
       ioff[b + 1] = ioff[b] + nimg[b];
       h->stats.image_samples += nimg[b];
-      m[b] = 2 * cnt + 2 * nimg[b] + 3 * np[b] + 3 * npf[b];
+      m[b] = 2 * cnt + 2 * nimg[b] + 3 * h->nc * np[b] + 3 * npf[b];
       s[b] = (m[b] > 2 * V.n[b] + 8) ? 2 * V.n[b] + 8 : m[b];
       noff[b + 1] = noff[b] + cnt;
       woff[b + 1] = woff[b] + (int64_t)m[b] * V.n[b];
@@ -600,7 +602,7 @@ int build(hbs_handle* h) {
       for (int b = 0; b < nb; ++b) {
         if (nnear[b] == 0) continue;
         const int n = V.n[b];
-        if (h->opts.quad == HBS_QUAD_KR6) {
+        if (h->opts.quad == HBS_QUAD_KR6 && !h->geo.two) {
           // both directions from one Hankel evaluation per pair (no point of b is near itself)
           bd.push_back({dn + noff[b], dact + V.aoff[b], dwt + woff[b], nnear[b], n, m[b], 2, 0.0, nnear[b]});
         } else {
@@ -1130,7 +1132,7 @@ static int apply_mixed(hbs_handle* h, bool inv, int split, const cplx* B, int64_
   if (!inv) split = L;
   split = std::max(0, std::min(L, split));
   const bool mixed = split < L;  // level L (and maybe more) in complex64
-  const int64_t N = h->N;
+  const int64_t N = h->NU;
   const int rr = (int)r;
   // up[j] (j = 0..L-1) = output of the upward step of level j+1, lv[j+1].ktot rows
   std::vector<int64_t> rows_up(L);

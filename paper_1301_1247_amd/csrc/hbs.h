@@ -45,7 +45,9 @@ struct hbs_handle {
   ~hbs_handle();
   // declared first, so destroyed after every buffer charged to it
   qps::MemBudget budget;
-  int64_t N = 0;
+  int64_t N = 0;   // nodes
+  int64_t NU = 0;  // unknowns: N, or 2N for the transmission problem (two densities per node)
+  int nc = 1;      // unknowns per node
   double omega = 0, tol = 0;
   hbs_opts opts{};
   hipStream_t stream = nullptr;

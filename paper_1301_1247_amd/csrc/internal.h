@@ -16,6 +16,10 @@ struct Geo {
   int N;
   int quad;
   double omega;
+  // transmission problem (Sec. 5): two unknowns per node, u = 2 i + c (c = 0: tau, c = 1: sigma;
+  // row c = 0: value jump, c = 1: minus the normal-derivative jump); omega1 = n omega inside
+  int two;
+  double omega1;
   double g[6];           // Kapur-Rokhlin corrections, R_m = 1 + g_m
   // Alpert correction (quad == HBS_QUAD_ALPERT): grid nodes closer than alpa are left out; alpn
   // off-grid nodes q carry the kernel table alpT[i + q N] and Lagrange weights alpL[q alpnl + r] of
@@ -27,7 +31,8 @@ struct Geo {
 };
 
 // A batch entry of the block evaluator: out[r + c*ld] = A(rows[r], cols[c]), or
-// A(cols[c], rows[r]) when trans != 0.  Index lists hold global node indices.
+// A(cols[c], rows[r]) when trans != 0.  Index lists hold global unknown indices (node indices, or
+// 2 node + component for the transmission problem).
 struct BlockDesc {
   const int* rows;
   const int* cols;
@@ -44,7 +49,7 @@ struct BlockDesc {
 };
 
 // Proxy part of the compression matrix of one box: rows [row0, row0 + 3 np) of W^T
-// (m x n, ld = m) for the n active points `act`.
+// (m x n, ld = m) for the n active unknowns `act` (6 np rows for the transmission problem).
 struct ProxyDesc {
   const int* act;
   cplx* wt;

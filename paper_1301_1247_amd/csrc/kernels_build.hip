@@ -8,6 +8,8 @@ namespace {
 constexpr int NT = 256;  // threads per workgroup (4 wavefronts)
 
 // ---------------------------------------------------------------- block evaluation
+// TWO: the transmission operator (Sec. 5; plain and transposed blocks only)
+template <bool TWO>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_blocks(Geo G, const BlockDesc* __restrict__ descs) {
   const BlockDesc d = descs[blockIdx.y];
   // one entry per thread, no grid-stride loop: inside a loop the compiler hoists the Hankel
@@ -19,6 +21,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int r = e % d.nr, c = e / d.nr;
     const int gr = d.rows[r], gc = d.cols[c];
     cplx v;
+    if (TWO) {
+      d.out[r + (size_t)c * d.ld] = d.trans ? a_entry_tr(G, gc, gr) : a_entry_tr(G, gr, gc);
+      return;
+    }
     if (d.trans == 2) {
       // the pair A(gc, gr~), A(gr~, gc) (gr~ = gr shifted by sx) from one Hankel evaluation: both
       // share r = |x_gc - x_gr~|; KR6's correction R depends on (gc - gr) mod N symmetrically
@@ -50,6 +56,69 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       v = d.trans ? a_entry(G, gc, gr) : a_entry(G, gr, gc);
     }
     d.out[r + (size_t)c * d.ld] = v;
+  }
+}
+
+// Transmission problem (Sec. 5): proxy rows for the unknown u = 2 i + c of the box, at both
+// wavenumbers kq (q = 0: omega, q = 1: n omega), G_q = (i/4) H0(kq r), r = |x_i - p_l|:
+//   row0 + (3q) np + l      incoming single layer: c = 0: G_q(x_i, p_l); c = 1: dG_q/dn_x      (x wp)
+//   row0 + (3q + 1) np + l  incoming double layer: the same row functionals of
+//                           [dG_q/dnu_l - i kq G_q](x_i, p_l)                                  (x wp)
+//   row0 + (3q + 2) np + l  outgoing field on the circle: c = 0: dG_q/dn_y (p_l, x_i);
+//                           c = 1: G_q(p_l, x_i)                                      (x w_i sqrt(wp))
+// The fields that reach a box from outside its proxy circle solve Helmholtz' equation at k0 or k1
+// inside the circle (spanned by the first two groups), and the fields the box sends out are
+// radiating solutions at k0 and k1 fixed by their values on the circle (the third group).
+__global__ __launch_bounds__(NT) void k_proxy_tr(Geo G, const ProxyDesc* __restrict__ descs) {
+  const ProxyDesc d = descs[blockIdx.y];
+  const int total = d.np * d.n;
+  const double wp = 2.0 * QPS_PI * d.R / d.np;
+  const double swp = sqrt(wp);
+  const int e = blockIdx.x * NT + threadIdx.x;
+  if (e >= total) return;
+  const int l = e % d.np, iu = e / d.np;
+  double sn, cs;
+  sincos(2.0 * QPS_PI * l / d.np, &sn, &cs);
+  const double px = d.cx + d.R * cs, py = d.cy + d.R * sn;
+  const int u = d.act[iu], gi = u >> 1, c = u & 1;
+  const double dx = G.x[gi] - px, dy = G.y[gi] - py;  // x_i - p_l
+  const double r = sqrt(dx * dx + dy * dy);
+  const double ni = (G.nx[gi] * dx + G.ny[gi] * dy) / r;  // n_i.(x_i - p)/r
+  const double nu = (cs * dx + sn * dy) / r;              // nu_l.(x_i - p)/r
+  const double nn = G.nx[gi] * cs + G.ny[gi] * sn;
+  cplx* col = d.wt + (size_t)iu * d.m + d.row0;
+  // both Hankel pairs first, in straight-line code (evaluated inside the loop, their coefficient
+  // tables are hoisted into scalar registers and spilled)
+  cplx hh[2][2];
+  hankel01(G.omega * r, hh[0][0], hh[0][1]);
+  hankel01(G.omega1 * r, hh[1][0], hh[1][1]);
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const double k = q ? G.omega1 : G.omega;
+    const cplx h0 = hh[q][0], h1 = hh[q][1];
+    const cplx g = mkc(-0.25 * h0.y, 0.25 * h0.x);                      // G
+    const cplx gh1 = mkc(-0.25 * k * h1.y, 0.25 * k * h1.x);            // (i/4) k H1
+    cplx in1, in2, out;
+    if (c == 0) {
+      in1 = g;
+      // dG/dnu_p = (i/4) k H1 nu.(x - p)/r;  - i k G = (k/4) H0
+      in2 = mkc(gh1.x * nu + 0.25 * k * h0.x, gh1.y * nu + 0.25 * k * h0.y);
+      // dG/dn_y(p, x_i) with target p, source x_i: (i/4) k H1 n_i.(p - x_i)/r
+      out = cscale(gh1, -ni);
+    } else {
+      // dG/dn_x = -(i/4) k H1 n_i.(x - p)/r
+      in1 = cscale(gh1, -ni);
+      // d/dn_x [dG/dnu_p - i k G] = T(x, p; n_i, nu) - i k dG/dn_x,
+      // T = (i/4) [k^2 H0 a b + (k H1 / r)(nn - 2 a b)], a = n_i.(x - p)/r, b = nu.(x - p)/r
+      const double ab = ni * nu, cc = (nn - 2.0 * ab) / r;
+      const cplx T = mkc(-0.25 * (k * k * h0.y * ab + k * h1.y * cc), 0.25 * (k * k * h0.x * ab + k * h1.x * cc));
+      const cplx dx_ = cscale(gh1, -ni);                                // dG/dn_x
+      in2 = mkc(T.x + k * dx_.y, T.y - k * dx_.x);                        // T - i k dG/dn_x
+      out = g;
+    }
+    col[(3 * q) * d.np + l] = cscale(in1, wp);
+    col[(3 * q + 1) * d.np + l] = cscale(in2, wp);
+    col[(3 * q + 2) * d.np + l] = cscale(out, G.w[gi] * swp);
   }
 }
 
@@ -1081,7 +1150,7 @@ __global__ __launch_bounds__(NT) void k_alpert_table(Geo G, const double* __rest
 
 __global__ void k_entries(Geo G, const int* __restrict__ rows, const int* __restrict__ cols, int64_t n, cplx* __restrict__ out) {
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT)
-    out[e] = a_entry(G, rows[e], cols[e]);
+    out[e] = a_entry_any(G, rows[e], cols[e]);
 }
 
 inline int grid_for(int64_t elems, int cap = 4096) {
@@ -1098,13 +1167,19 @@ namespace qps {
 hipError_t launch_eval_blocks(const Geo& g, const BlockDesc* d, int nd, int max_elems, hipStream_t s) {
   if (nd == 0 || max_elems == 0) return hipSuccess;
   dim3 grid(grid_for(max_elems, 1 << 30), nd);  // every entry its own thread
-  hipLaunchKernelGGL(k_eval_blocks, grid, dim3(NT), 0, s, g, d);
+  if (g.two)
+    hipLaunchKernelGGL(k_eval_blocks<true>, grid, dim3(NT), 0, s, g, d);
+  else
+    hipLaunchKernelGGL(k_eval_blocks<false>, grid, dim3(NT), 0, s, g, d);
   return hipGetLastError();
 }
 hipError_t launch_proxy(const Geo& g, const ProxyDesc* d, int nd, int max_elems, hipStream_t s) {
   if (nd == 0 || max_elems == 0) return hipSuccess;
   dim3 grid(grid_for(max_elems, 1 << 30), nd);  // every entry its own thread
-  hipLaunchKernelGGL(k_proxy, grid, dim3(NT), 0, s, g, d);
+  if (g.two)
+    hipLaunchKernelGGL(k_proxy_tr, grid, dim3(NT), 0, s, g, d);
+  else
+    hipLaunchKernelGGL(k_proxy, grid, dim3(NT), 0, s, g, d);
   return hipGetLastError();
 }
 hipError_t launch_sketch(const SketchDesc* d, int nd, int max_s, int max_n, uint64_t seed, hipStream_t s) {

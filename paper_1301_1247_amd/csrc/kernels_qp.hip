@@ -21,15 +21,19 @@ __device__ inline cplx cexpi_c(cplx z) {
 // Y[:, 0:4M] = [B^S_L, B^D_L, B^S_R, B^D_R] with
 //   B^S_W[i,m] = (i/2) wk_m e^{i k_m y_i} e^{i s_m |x_i - x_W|} / s_m,
 //   B^D_W[i,m] = (1/2) sign(x_i - x_W) wk_m e^{i k_m y_i} e^{i s_m |x_i - x_W|}   (Eqs. 2.12-2.13).
+// Transmission problem: row 2i is the value above at node i, row 2i + 1 minus its normal derivative,
+// d/dn e^{i k y + i s |x - x_W|} = i (s sign(x - x_W) n_x + k n_y) e^{...}.
 __global__ __launch_bounds__(NT) void k_gen_B(QPGeo Q, cplx* __restrict__ Y, int64_t ldy) {
-  const int64_t total = (int64_t)Q.N * 4 * Q.M;
+  const int nrow = Q.two ? 2 * Q.N : Q.N;
+  const int64_t total = (int64_t)nrow * 4 * Q.M;
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-    const int i = (int)(e % Q.N);
-    const int col = (int)(e / Q.N);
+    const int i = (int)(e % nrow);
+    const int col = (int)(e / nrow);
     const int wall = col / (2 * Q.M);          // 0 = L, 1 = R
     const int dbl = (col / Q.M) & 1;           // 0 = single, 1 = double
     const int m = col % Q.M;
-    const int nd = Q.idx ? Q.idx[i] : i;
+    const int ii = Q.two ? i >> 1 : i;
+    const int nd = Q.idx ? Q.idx[ii] : ii;
     const double xw = wall ? 0.5 * Q.period : -0.5 * Q.period;
     const double dx = Q.x[nd] + Q.shift - xw;
     const cplx k = Q.k[m], s = Q.s[m], wk = Q.wk[m];
@@ -39,6 +43,12 @@ __global__ __launch_bounds__(NT) void k_gen_B(QPGeo Q, cplx* __restrict__ Y, int
     cplx v;
     if (!dbl) v = cmul(mkc(0.0, 0.5), cmul(ex, cinv(s)));
     else v = cscale(ex, dx > 0 ? 0.5 : -0.5);
+    if (Q.two && (i & 1)) {
+      const double sg = dx > 0 ? 1.0 : -1.0;
+      // -i (s sg n_x + k n_y) v
+      const cplx f = cadd(cscale(s, sg * Q.nx[nd]), cscale(k, Q.ny[nd]));
+      v = cmul(mkc(f.y, -f.x), v);
+    }
     Y[i + (size_t)col * ldy] = v;
   }
 }
@@ -47,14 +57,22 @@ __global__ __launch_bounds__(NT) void k_gen_B(QPGeo Q, cplx* __restrict__ Y, int
 // waves of evanescent orders that the Wood's-anomaly scheme adds as extra right-hand sides
 __global__ __launch_bounds__(NT) void k_gen_inc(QPGeo Q, const double* __restrict__ kx, const double* __restrict__ ky,
                                                 const double* __restrict__ ky_im, int nang, cplx* __restrict__ Y, int64_t ldy) {
-  const int64_t total = (int64_t)Q.N * nang;
+  // transmission problem (Eqs. 5.3-5.4): row 2i = -u^i, row 2i + 1 = +du^i/dn = -i (kx n_x + ky n_y) (-u^i)
+  const int nrow = Q.two ? 2 * Q.N : Q.N;
+  const int64_t total = (int64_t)nrow * nang;
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-    const int i = (int)(e % Q.N);
-    const int a = (int)(e / Q.N);
+    const int r = (int)(e % nrow);
+    const int a = (int)(e / nrow);
+    const int i = Q.two ? r >> 1 : r;
     double s, c;
     sincos(kx[a] * Q.x[i] + ky[a] * Q.y[i], &s, &c);
     const double amp = ky_im ? -exp(-ky_im[a] * Q.y[i]) : -1.0;
-    Y[i + (size_t)a * ldy] = mkc(amp * c, amp * s);
+    cplx v = mkc(amp * c, amp * s);
+    if (Q.two && (r & 1)) {
+      const double f = kx[a] * Q.nx[i] + ky[a] * Q.ny[i];
+      v = mkc(f * v.y, -f * v.x);
+    }
+    Y[r + (size_t)a * ldy] = v;
   }
 }
 
@@ -62,14 +80,19 @@ __global__ __launch_bounds__(NT) void k_gen_inc(QPGeo Q, const double* __restric
 // at node j on dOmega + shift e_1, with E = e^{-i k y_j} e^{i s |x_j - x_W|} / (4 pi), sigma = sign(x_j - x_W):
 //   value = [E (-sigma n_x + (k/s) n_y) + omega E / s] w_j
 //   deriv = [i E (s n_x - k sigma n_y) - i omega E sigma] w_j          (Sec. 2.2, Eq. 2.17)
+// Transmission problem: column 2j carries the double layer alone (value E (-sigma n_x + (k/s) n_y),
+// deriv i E (s n_x - k sigma n_y)) and column 2j + 1 the single layer alone (value i E / s, deriv E
+// sigma), both times w_j: the Dirichlet column is their combination D - i omega S.
 __global__ __launch_bounds__(NT) void k_gen_C(QPGeo Q, int wall, double shift, cplx* __restrict__ C) {
-  const int64_t total = (int64_t)Q.N * Q.M;
+  const int ncol = Q.two ? 2 * Q.N : Q.N;
+  const int64_t total = (int64_t)ncol * Q.M;
   const double xw = wall ? 0.5 * Q.period : -0.5 * Q.period;
   const int ldc = 2 * Q.M;
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int m = (int)(e % Q.M);
     const int j = (int)(e / Q.M);
-    const int nd = Q.idx ? Q.idx[j] : j;
+    const int jj = Q.two ? j >> 1 : j;
+    const int nd = Q.idx ? Q.idx[jj] : jj;
     const double dx = Q.x[nd] + shift - xw;
     const double sg = dx > 0 ? 1.0 : -1.0;
     const cplx k = Q.k[m], s = Q.s[m];
@@ -78,12 +101,19 @@ __global__ __launch_bounds__(NT) void k_gen_C(QPGeo Q, int wall, double shift, c
     const cplx E = cscale(cexpi_c(z), 1.0 / (4.0 * PI));
     const cplx is = cinv(s);
     const double nx = Q.nx[nd], ny = Q.ny[nd], w = Q.w[nd];
+    if (Q.two && (j & 1)) {
+      const cplx ve = cmul(mkc(0.0, 1.0), cmul(E, is));
+      C[m + (size_t)j * ldc] = cscale(ve, w);
+      C[Q.M + m + (size_t)j * ldc] = cscale(E, sg * w);
+      continue;
+    }
+    const double om = Q.two ? 0.0 : Q.omega;  // no single-layer part in a transmission tau column
     // value
     cplx t = cadd(mkc(-sg * nx, 0.0), cscale(cmul(k, is), ny));
-    cplx val = cadd(cmul(E, t), cscale(cmul(E, is), Q.omega));
+    cplx val = cadd(cmul(E, t), cscale(cmul(E, is), om));
     // derivative: i E (s nx - k sg ny) - i omega E sg
     cplx u = csub(cscale(s, nx), cscale(k, sg * ny));
-    cplx der = cmul(mkc(0.0, 1.0), csub(cmul(E, u), cscale(E, Q.omega * sg)));
+    cplx der = cmul(mkc(0.0, 1.0), csub(cmul(E, u), cscale(E, om * sg)));
     C[m + (size_t)j * ldc] = cscale(val, w);
     C[Q.M + m + (size_t)j * ldc] = cscale(der, w);
   }
@@ -345,10 +375,19 @@ __global__ __launch_bounds__(NT) void k_bragg(QPGeo Q, const double* __restrict_
   const cplx* et = eta + (size_t)a * ldeta;
   cplx su = mkc(0, 0), sd = mkc(0, 0);
   for (int j = threadIdx.x; j < Q.N; j += NT) {
-    const cplx we = cscale(et[j], Q.w[j]);
     double s1, c1, s2, c2;
     sincos(-(kn_x * Q.x[j] + kn * Q.y[j]), &s1, &c1);
     sincos(-(kn_x * Q.x[j] - kn * Q.y[j]), &s2, &c2);
+    if (Q.two) {
+      // tau (double layer) with the factors above less the -i omega; sigma (single layer) with 1
+      const cplx wt = cscale(et[2 * j], Q.w[j]), ws = cscale(et[2 * j + 1], Q.w[j]);
+      const cplx fu = cadd(cmul(wt, mkc(0.0, -(kn_x * Q.nx[j] + kn * Q.ny[j]))), ws);
+      const cplx fd = cadd(cmul(wt, mkc(0.0, -kn_x * Q.nx[j] + kn * Q.ny[j])), ws);
+      su = cadd(su, cmul(mkc(c1, s1), fu));
+      sd = cadd(sd, cmul(mkc(c2, s2), fd));
+      continue;
+    }
+    const cplx we = cscale(et[j], Q.w[j]);
     const cplx fu = mkc(0.0, -(kn_x * Q.nx[j] + kn * Q.ny[j]) - Q.omega);
     const cplx fd = mkc(0.0, (-kn_x * Q.nx[j] + kn * Q.ny[j]) - Q.omega);
     su = cadd(su, cmul(we, cmul(mkc(c1, s1), fu)));
@@ -373,12 +412,15 @@ __global__ __launch_bounds__(NT) void k_bragg(QPGeo Q, const double* __restrict_
 // Bragg basis of one Bloch-phase group: the orders shared by its angles are kap_q = kref + 2 pi (qlo + q) / d,
 // q < nq.  E (2 nq x N, col-major): row q = w_j e^{-i(kap_q x_j + k_q y_j)} [-i(kap_q n_x + k_q n_y) - i omega],
 // row nq + q = w_j e^{-i(kap_q x_j - k_q y_j)} [i(-kap_q n_x + k_q n_y) - i omega]; E eta gives the sums of k_bragg.
+// Transmission problem: 2N columns, column 2j (tau) without the -i omega term, column 2j + 1
+// (sigma) with the factor 1.
 __global__ __launch_bounds__(NT) void k_bragg_basis(QPGeo Q, double kref, int qlo, int nq, cplx* __restrict__ E) {
   const int64_t rows = 2 * (int64_t)nq;
-  const int64_t total = rows * Q.N;
+  const int64_t total = rows * (Q.two ? 2 * Q.N : Q.N);
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int r = (int)(e % rows);
-    const int j = (int)(e / rows);
+    const int jc = (int)(e / rows);
+    const int j = Q.two ? jc >> 1 : jc;
     const bool up = r < nq;
     const int q = up ? r : r - nq;
     const double kx = kref + 2.0 * PI * (qlo + q) / Q.period;
@@ -386,7 +428,9 @@ __global__ __launch_bounds__(NT) void k_bragg_basis(QPGeo Q, double kref, int ql
     const double ky = up ? kn : -kn;
     double sn, cs;
     sincos(-(kx * Q.x[j] + ky * Q.y[j]), &sn, &cs);
-    const cplx f = up ? mkc(0.0, -(kx * Q.nx[j] + kn * Q.ny[j]) - Q.omega) : mkc(0.0, (-kx * Q.nx[j] + kn * Q.ny[j]) - Q.omega);
+    const double om = Q.two ? 0.0 : Q.omega;
+    const cplx f = (Q.two && (jc & 1)) ? mkc(1.0, 0.0)
+                   : up ? mkc(0.0, -(kx * Q.nx[j] + kn * Q.ny[j]) - om) : mkc(0.0, (-kx * Q.nx[j] + kn * Q.ny[j]) - om);
     E[e] = cscale(cmul(mkc(cs, sn), f), Q.w[j]);
   }
 }
@@ -441,17 +485,17 @@ inline int grid_for(int64_t elems, int cap = 8192) {
 namespace qps {
 
 hipError_t launch_gen_B(const QPGeo& q, cplx* Y, int64_t ldy, hipStream_t s) {
-  hipLaunchKernelGGL(k_gen_B, dim3(grid_for((int64_t)q.N * 4 * q.M)), dim3(NT), 0, s, q, Y, ldy);
+  hipLaunchKernelGGL(k_gen_B, dim3(grid_for((int64_t)(q.two ? 2 : 1) * q.N * 4 * q.M)), dim3(NT), 0, s, q, Y, ldy);
   return hipGetLastError();
 }
 hipError_t launch_gen_inc(const QPGeo& q, const double* kx, const double* ky, const double* ky_im, int nang, cplx* Y,
                           int64_t ldy, hipStream_t s) {
   if (nang == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gen_inc, dim3(grid_for((int64_t)q.N * nang)), dim3(NT), 0, s, q, kx, ky, ky_im, nang, Y, ldy);
+  hipLaunchKernelGGL(k_gen_inc, dim3(grid_for((int64_t)(q.two ? 2 : 1) * q.N * nang)), dim3(NT), 0, s, q, kx, ky, ky_im, nang, Y, ldy);
   return hipGetLastError();
 }
 hipError_t launch_gen_C(const QPGeo& q, int wall, double shift, cplx* C, hipStream_t s) {
-  hipLaunchKernelGGL(k_gen_C, dim3(grid_for((int64_t)q.N * q.M)), dim3(NT), 0, s, q, wall, shift, C);
+  hipLaunchKernelGGL(k_gen_C, dim3(grid_for((int64_t)(q.two ? 2 : 1) * q.N * q.M)), dim3(NT), 0, s, q, wall, shift, C);
   return hipGetLastError();
 }
 hipError_t launch_form_S(const QPGeo& q, const cplx* coef, int ng, const cplx* G1, const cplx* G2, cplx* S, hipStream_t s) {
@@ -508,7 +552,7 @@ hipError_t launch_bragg(const QPGeo& q, const double* kappa, const int* nlo, con
 }
 hipError_t launch_bragg_basis(const QPGeo& q, double kref, int qlo, int nq, cplx* E, hipStream_t s) {
   if (nq == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bragg_basis, dim3(grid_for((int64_t)2 * nq * q.N)), dim3(NT), 0, s, q, kref, qlo, nq, E);
+  hipLaunchKernelGGL(k_bragg_basis, dim3(grid_for((int64_t)2 * nq * (q.two ? 2 : 1) * q.N)), dim3(NT), 0, s, q, kref, qlo, nq, E);
   return hipGetLastError();
 }
 hipError_t launch_bragg_gather(const QPGeo& q, double kref, int qlo, int nq, const int* slot0, const int* nmodes, int maxmodes,

@@ -99,12 +99,12 @@ size_t apply_need(const hbs_handle* h, int64_t r, int refine) {
   for (int l = 1; l <= L; ++l) up += h->lv[l].ktot;
   for (int l = 1; l < L; ++l) xmax = std::max<int64_t>(xmax, h->lv[l].ntot);
   size_t b = sizeof(cplx) * (size_t)r * (size_t)(up + 2 * xmax + h->nroot);
-  if (refine > 0) b += 2 * sizeof(cplx) * (size_t)h->N * (size_t)r;
+  if (refine > 0) b += 2 * sizeof(cplx) * (size_t)h->NU * (size_t)r;
   return b;
 }
 
 int apply_body(hbs_handle* h, const cplx* B, cplx* X, int64_t r, int refine) {
-  const int64_t N = h->N;
+  const int64_t N = h->NU;
   hipStream_t st = h->stream;
   int rc = apply_inverse(h, B, N, X, N, r);
   if (rc != HBS_OK) return rc;

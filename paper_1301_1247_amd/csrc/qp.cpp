@@ -114,12 +114,16 @@ int qp_contour_M(const hbs_handle* h, double period, const qp_opts* o) {
 int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, const qp_opts* o, const QPCols* cols,
                   cplx* eta_out, cplx* xi_out, cplx* bragg_out, int32_t* nlo_out, int32_t* nm_out, double* flux_out) {
   hipStream_t st = h->stream;
-  const int N = (int)h->N;
+  const int N = (int)h->NU;  // length of the obstacle's vectors (two unknowns per node: transmission)
   const int nang = cols ? (int)cols->kx.size() : (int)th.size();
   const double om = h->omega;
   const int P = o->P;
   if (P != 0 && P != 1) {
     set_error("qp_solve: P must be 0 or 1");
+    return HBS_E_INVALID_ARG;
+  }
+  if (h->nc != 1 && (P != 0 || cols)) {
+    set_error("qp_solve: the transmission problem takes P = 0 (and no displaced-contour columns)");
     return HBS_E_INVALID_ARG;
   }
   if (P == 1) {
@@ -364,10 +368,11 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
   CK(hipMemcpyAsync(dnlo, nlo.data(), sizeof(int) * nang, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(dnm, nm.data(), sizeof(int) * nang, hipMemcpyHostToDevice, st));
 
-  QPGeo Q;
+  QPGeo Q{};
+  Q.two = h->nc == 2;
   Q.x = h->geo.x; Q.y = h->geo.y; Q.nx = h->geo.nx; Q.ny = h->geo.ny; Q.w = h->geo.w;
   Q.k = dcont; Q.s = dcont + M; Q.wk = dcont + 2 * M;
-  Q.N = N; Q.M = M; Q.omega = om; Q.period = period; Q.shift = 0.0;
+  Q.N = (int)h->N; Q.M = M; Q.omega = om; Q.period = period; Q.shift = 0.0;
   Q.idx = nullptr;
   const int* J = h->lv[1].skel.as<int>();  // the root's active set (nroot nodes)
   QPGeo QJ = Q;

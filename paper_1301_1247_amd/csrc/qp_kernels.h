@@ -9,6 +9,9 @@ struct QPGeo {
   const int* idx;  // nullable: row / column i of a generated block is node idx[i] (a skeleton subset)
   int N, M;
   double omega, period, shift;
+  // transmission problem (Sec. 5): vectors over the obstacle have 2N entries, node by node [tau; sigma]
+  // (columns) or [value; minus normal derivative] (rows); the walls see the exterior field only
+  int two;
 };
 
 // An order of the Wood's-anomaly radiation rows: kappa_m = kappa + 2 pi m / d and k_m (complex).

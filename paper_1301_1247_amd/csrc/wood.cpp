@@ -256,7 +256,7 @@ static int solve_wood_group(hbs_handle* h, double period, const std::vector<doub
     DevBuf dcont;
     CK(dcont.reserve(sizeof(cplx) * 3 * M));
     CK(hipMemcpyAsync(dcont.p, cont.data(), sizeof(cplx) * 3 * M, hipMemcpyHostToDevice, st));
-    QPGeo Q;
+    QPGeo Q{};
     Q.x = h->geo.x; Q.y = h->geo.y; Q.nx = h->geo.nx; Q.ny = h->geo.ny; Q.w = h->geo.w;
     Q.k = dcont.as<cplx>(); Q.s = Q.k + M; Q.wk = Q.k + 2 * M;
     Q.N = N; Q.M = M; Q.omega = om; Q.period = period; Q.shift = 0.0; Q.idx = nullptr;
@@ -304,7 +304,7 @@ static int solve_wood_group(hbs_handle* h, double period, const std::vector<doub
   CK(hipMemcpyAsync(dnlo, hnlo.data(), sizeof(int) * q, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(dnm, hnm.data(), sizeof(int) * q, hipMemcpyHostToDevice, st));
   {
-    QPGeo Q;
+    QPGeo Q{};
     Q.x = h->geo.x; Q.y = h->geo.y; Q.nx = h->geo.nx; Q.ny = h->geo.ny; Q.w = h->geo.w;
     Q.k = nullptr; Q.s = nullptr; Q.wk = nullptr;
     Q.N = N; Q.M = M; Q.omega = om; Q.period = period; Q.shift = 0.0; Q.idx = nullptr;
@@ -364,8 +364,10 @@ int qp_solve_impl(hbs_handle* h, double period, const std::vector<double>& th, c
   std::vector<int> normal, near;
   for (int a = 0; a < n; ++a) (min_kn(om, period, om * std::cos(th[a])) < wood ? near : normal).push_back(a);
   if (near.empty()) return qp_solve_core(h, period, th, o, nullptr, eta_out, xi_out, bragg_out, nlo_out, nm_out, flux_out);
-  if (o->wood < 0) {
-    set_error("qp_solve: angle " + std::to_string(th[near[0]]) + " is within wood_min_kn of a Wood's anomaly");
+  if (o->wood < 0 || h->nc != 1) {
+    // the displaced-contour scheme is built for the Dirichlet problem only
+    set_error("qp_solve: angle " + std::to_string(th[near[0]]) + " is within wood_min_kn of a Wood's anomaly" +
+              (h->nc != 1 ? " (the transmission problem has no displaced-contour solve)" : ""));
     return HBS_E_WOOD;
   }
   hipStream_t st = h->stream;

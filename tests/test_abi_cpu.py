@@ -203,11 +203,26 @@ def test_image_period_needs_far_radius():
     assert rc == -1 and "image_period" in msg, (rc, msg)
 
 
+def test_transmission_options_are_checked_on_the_host():
+    """index > 0 (the transmission problem of Sec. 5) is built on the Kapur-Rokhlin operator without
+    the far-field circle, image columns or the Dirichlet-trained rank model: each combination is
+    refused before any GPU work, as is a negative or non-finite index."""
+    nodes, w, nrm, _ = _geom()
+    for kw, word in ((dict(index=-1.0), "index"), (dict(index=float("nan")), "index"),
+                     (dict(index=1.5, quad=1), "KR6"), (dict(index=1.5, quad=2), "KR6"),
+                     (dict(index=1.5, far_radius=2.0), "far_radius"),
+                     (dict(index=1.5, far_radius=2.0, image_period=1.0), "image_period"),
+                     (dict(index=1.5, rank_predictor=1), "rank_predictor"),
+                     (dict(index=1.5, leaf_size=512), "leaf_size")):
+        rc, msg = _build(nodes, w, nrm, 256, **kw)
+        assert rc == -1 and word in msg, (kw, rc, msg)
+
+
 def test_opts_struct_size_matches_binding():
     from paper_1301_1247_amd import binding as B
     o = B.hbs_opts()
     assert o.struct_size == C.sizeof(B.HbsOpts)
-    assert o.mem_limit == 0 and o.image_period == 0.0
+    assert o.mem_limit == 0 and o.image_period == 0.0 and o.index == 0.0
     q = B.qp_opts()
     assert q.struct_size == C.sizeof(B.QpOpts)
 

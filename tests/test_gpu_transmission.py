@@ -1,0 +1,149 @@
+"""Parity of the transmission problem (Sec. 5) on the GPU with the CPU oracle, through the C ABI.
+
+The handle is built with hbs_opts.index = n: 2N interlaced unknowns [tau_i; sigma_i], the 2 x 2
+difference-kernel operator with Kapur-Rokhlin weights.  Bar (floating point): matrix entries to
+rounding; eta and xi within relative 1e-10 of the oracle's dense LU solution after refinement (the
+target stated for the solver), the Bragg amplitudes (sums of 2N terms of eta) within 1e-9 of the
+largest; the bare compressed inverse within 1e-7.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+from scipy.special import hankel1
+
+import qpinputs
+from oracle import nystrom as ny
+from oracle import transmission as tr
+from paper_1301_1247_amd.geometry import discretize
+
+pytestmark = pytest.mark.gpu
+
+OM, IDX, D = 10.0, 1.5, 2 * math.pi
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def star_tr():
+    c = qpinputs.star(1.0, 0.3, 5)
+    N = 700  # 1400 unknowns: a ragged tree of several levels
+    disc = ny.Discretization(c, N)
+    A = tr.matrix(disc, OM, IDX)
+    return c, N, disc, A, sla.lu_factor(A)
+
+
+def test_matrix_entries_match_oracle(gpu_lib, star_tr):
+    c, N, disc, A, _ = star_tr
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, OM, 1e-12, index=IDX)
+    assert h.stats().unknowns == 2 * N
+    rng = np.random.default_rng(11)
+    i = rng.integers(0, 2 * N, 400)
+    j = rng.integers(0, 2 * N, 400)
+    # the diagonal pairs of a node, the corrected band and its wrap-around
+    i = np.concatenate([i, [0, 0, 1, 1, 2, 3, 10, 11, 0, 1, 2 * N - 1, 2 * N - 2]])
+    j = np.concatenate([j, [0, 1, 0, 1, 5, 12, 3, 2, 2 * N - 1, 2 * N - 2, 0, 13]])
+    g = h.matrix_entries(i, j)
+    assert np.abs(g - A[i, j]).max() < 1e-12
+
+
+def test_inverse_and_forward_vs_dense(gpu_lib, star_tr):
+    c, N, disc, A, lu = star_tr
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, OM, 1e-12, index=IDX, leaf_size=64)
+    rng = np.random.default_rng(12)
+    B = rng.standard_normal((2 * N, 5)) + 1j * rng.standard_normal((2 * N, 5))
+    Xe = sla.lu_solve(lu, B)
+    assert _rel(h.apply(B), Xe) < 1e-7
+    assert _rel(h.apply(B, refine=2), Xe) < 1e-10
+    assert _rel(h.forward(Xe), A @ Xe) < 1e-10
+    s = h.stats()
+    assert s.levels >= 3 and s.N == N and s.unknowns == 2 * N
+
+
+def test_exact_compression_agrees(gpu_lib, star_tr):
+    c, N, disc, A, lu = star_tr
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, OM, 1e-12, index=IDX, compress="exact")
+    b = np.exp(1j * np.arange(2 * N) * 0.21)
+    assert _rel(h.apply(b, refine=2), sla.lu_solve(lu, b)) < 1e-10
+
+
+def test_point_sources_reproduced(gpu_lib):
+    """The jumps of a radiating source at omega from inside and a regular field at n omega from outside:
+    the GPU densities reproduce both fields (an exact solution, independent of the oracle's matrix)."""
+    c = qpinputs.star(1.0, 0.3, 5)
+    N = 1600
+    disc = ny.Discretization(c, N)
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, OM, 1e-12, index=IDX)
+    zi, zo, k1 = np.array([0.1, 0.2]), np.array([2.0, 1.5]), IDX * OM
+
+    def G(k, x, z):
+        return 0.25j * hankel1(0, k * np.hypot(x[:, 0] - z[0], x[:, 1] - z[1]))
+
+    def dG(k, x, nr, z):
+        dx = x - z
+        r = np.hypot(dx[:, 0], dx[:, 1])
+        return -0.25j * k * hankel1(1, k * r) * (nr[:, 0] * dx[:, 0] + nr[:, 1] * dx[:, 1]) / r
+
+    f = G(OM, disc.x, zi) - G(k1, disc.x, zo)
+    g = dG(OM, disc.x, disc.nrm, zi) - dG(k1, disc.x, disc.nrm, zo)
+    eta = h.apply(tr.rhs_from_jumps(f, g), refine=2)
+    te = np.array([[1.8, -1.2], [-2.5, 0.3], [0.0, 1.9]])
+    ti = np.array([[0.2, -0.1], [-0.3, 0.25], [0.4, 0.4]])
+    assert np.abs(tr.potential(disc, OM, eta, te) - G(OM, te, zi)).max() < 2e-8
+    assert np.abs(tr.potential(disc, k1, eta, ti) - G(k1, ti, zo)).max() < 2e-8
+
+
+@pytest.mark.parametrize("compress", ["proxy", "exact"])
+def test_qp_solve_matches_oracle(gpu_lib, star_tr, compress):
+    c, N, disc, A, _ = star_tr
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, OM, 1e-12, index=IDX, compress=compress)
+    # two angles sharing a Bloch phase (theta and its mirror about -pi/2) and one on its own
+    ths = np.array([-math.pi / 5, -math.pi + math.pi / 5, -1.2])
+    r = h.qp_solve_many(D, ths, P=0)
+    ref = tr.solve_qp(disc, N, OM, IDX, D, ths, P=0, A0=A)
+    assert r["M"] == len(ref["contour"].k)
+    for a in range(len(ths)):
+        assert _rel(r["eta"][:, a], ref["eta"][:, a]) < 1e-10
+        assert _rel(r["xi"][:, a], ref["xi"][:, a]) < 1e-10
+        n, kn, cc, dd = ref["bragg"][a]
+        nm, mx = r["nmodes"][a], r["maxmodes"]
+        assert nm == len(n) and r["nlo"][a] == n[0]
+        bu, bd = r["bragg"][:nm, a], r["bragg"][mx:mx + nm, a]
+        # each amplitude sums 2N terms of eta: held to 1e-9 of the largest amplitude
+        assert np.abs(bu - cc).max() < 1e-9 * np.abs(cc).max()
+        assert np.abs(bd - dd).max() < 1e-9 * np.abs(dd).max()
+        assert abs(r["flux"][a] - ref["flux"][a]) < 1e-10
+
+
+def test_index_one_leaves_the_field_unscattered(gpu_lib):
+    """n = 1: the operator is the identity and every Bragg amplitude of the scattered field vanishes."""
+    c = qpinputs.star(1.0, 0.3, 5)
+    N = 400
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, OM, 1e-12, index=1.0)
+    r = h.qp_solve_many(D, np.array([-math.pi / 5, -1.1]), P=0)
+    for a in range(2):
+        nm, mx = r["nmodes"][a], r["maxmodes"]
+        assert np.abs(r["bragg"][:nm, a]).max() < 1e-9 and np.abs(r["bragg"][mx:mx + nm, a]).max() < 1e-9
+
+
+def test_refusals(gpu_lib, star_tr):
+    c, N, disc, A, _ = star_tr
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, OM, 1e-10, index=IDX)
+    with pytest.raises(gpu_lib.HBSError) as e:
+        h.qp_solve_many(D, np.array([-math.pi / 5]), P=1)
+    assert e.value.code == -1
+    # an angle next to a Wood's anomaly: k_n = 0 for some order
+    th = -math.acos(1.0 - 2 * math.pi / (OM * D)) + 1e-3
+    with pytest.raises(gpu_lib.HBSError) as e:
+        h.qp_solve_many(D, np.array([th]), P=0)
+    assert e.value.code == -9
