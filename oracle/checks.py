@@ -22,6 +22,7 @@ import numpy as np
 from . import alpert
 from . import nystrom
 from . import periodic
+from . import transmission
 
 
 class RowSubset:
@@ -29,6 +30,7 @@ class RowSubset:
 
     def __init__(self, disc: nystrom.Discretization, rows):
         rows = np.asarray(rows)
+        self.N = len(rows)
         self.x = disc.x[rows]
         self.nrm = disc.nrm[rows]
         self.w = disc.w[rows]
@@ -79,6 +81,50 @@ def bordered_residual(curve, N, omega, period, thetas, eta, xi, flux=None, n_row
         bn = np.linalg.norm(periodic.incident(disc, omega, th))
         worst = max(worst, math.sqrt(np.sum(np.abs(r1) ** 2) * N / n_rows + np.sum(np.abs(r2) ** 2)) / bn)
     out = {"sampled_rel_residual": float(worst), "rows_sampled": int(n_rows), "angles_sampled": int(len(angs))}
+    if flux is not None:
+        out["flux_err_max"] = float(np.max(flux))
+    return out
+
+
+def bordered_residual_tr(curve, N, omega, index, period, thetas, eta, xi, flux=None, n_rows=48, n_ang=8, chunk=4000,
+                         seed=7, angles=None, P=0, h=0.1):
+    """The same sampled residual for the transmission problem of Sec. 5 (``transmission``): eta is
+    2N x n, interlaced; n_rows nodes are drawn and both of their rows (value and normal-derivative
+    jumps) are checked, with A~ = A + alpha A_1 + alpha^-1 A_-1 for P = 1 (exterior field only)."""
+    disc = nystrom.Discretization(curve, N)
+    if P not in (0, 1):
+        raise ValueError("P must be 0 or 1")
+    ct = periodic.default_contour(disc, omega, period, P=P, h=h)
+    rng = np.random.default_rng(seed)
+    nodes = np.sort(rng.choice(N, n_rows, replace=False))
+    rows = np.stack([2 * nodes, 2 * nodes + 1], axis=1).ravel()
+    angs = np.asarray(angles) if angles is not None else rng.choice(len(thetas), min(n_ang, len(thetas)), replace=False)
+    Arows = transmission.matrix_rows(disc, omega, index, rows)
+    Anb = {j: transmission.neighbour_rows(disc, omega, j * period, rows) for j in ((-1, 1) if P else ())}
+    sub = RowSubset(disc, nodes)
+    BL, BR = transmission.wall_B(sub, omega, period, ct)
+    eta_s = eta[:, angs]
+    CLe = 0
+    CRe = 0
+    for c0 in range(0, N, chunk):
+        sl = np.arange(c0, min(N, c0 + chunk))
+        us = np.stack([2 * sl, 2 * sl + 1], axis=1).ravel()
+        CL, _ = transmission.wall_C(RowSubset(disc, sl), omega, period, ct, shift=P * period)
+        _, CR = transmission.wall_C(RowSubset(disc, sl), omega, period, ct, shift=-P * period)
+        CLe = CLe + CL @ eta_s[us]
+        CRe = CRe + CR @ eta_s[us]
+    worst = 0.0
+    for q, a in enumerate(angs):
+        th = thetas[a]
+        al = periodic.bloch_phase(omega, period, th)
+        x = xi[:, a]
+        b = transmission.incident(sub, omega, th)[:, 0]
+        At = Arows + sum(al ** j * Anb[j] for j in Anb)
+        r1 = At @ eta_s[:, q] + (BL + al * BR) @ x - b
+        r2 = al ** P * CLe[:, q] - al ** (-(P + 1)) * CRe[:, q] + periodic.wall_Q(omega, period, al, ct) @ x
+        bn = np.linalg.norm(transmission.incident(disc, omega, th))
+        worst = max(worst, math.sqrt(np.sum(np.abs(r1) ** 2) * N / n_rows + np.sum(np.abs(r2) ** 2)) / bn)
+    out = {"sampled_rel_residual": float(worst), "rows_sampled": int(2 * n_rows), "angles_sampled": int(len(angs))}
     if flux is not None:
         out["flux_err_max"] = float(np.max(flux))
     return out

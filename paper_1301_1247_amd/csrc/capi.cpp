@@ -312,14 +312,9 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
   }
   if (!(o.index >= 0) || !std::isfinite(o.index)) { set_error("hbs_build: index must be finite and >= 0"); return HBS_E_INVALID_ARG; }
   if (o.index > 0) {
-    // the transmission problem (Sec. 5) is built on the Kapur-Rokhlin operator with proxy or exact
-    // compression; the far-field circle, the image columns and the Dirichlet-trained rank model are
-    // not carried over to it
+    // the transmission problem (Sec. 5) is built on the Kapur-Rokhlin operator; the Dirichlet-trained
+    // rank model is not carried over to it
     if (o.quad != HBS_QUAD_KR6) { set_error("hbs_build: the transmission problem (index > 0) needs HBS_QUAD_KR6"); return HBS_E_INVALID_ARG; }
-    if (o.far_radius > 0 || o.image_period > 0) {
-      set_error("hbs_build: the transmission problem (index > 0) takes far_radius = 0 and image_period = 0");
-      return HBS_E_INVALID_ARG;
-    }
     if (o.rank_predictor) { set_error("hbs_build: the transmission problem (index > 0) takes rank_predictor = 0"); return HBS_E_INVALID_ARG; }
     if (N > ((int64_t)1 << 29)) { set_error("hbs_build: N too large for the transmission problem"); return HBS_E_INVALID_ARG; }
   }

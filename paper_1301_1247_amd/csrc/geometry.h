@@ -152,4 +152,33 @@ __device__ inline cplx a_entry_tr(const Geo& G, int u, int v) {
   return cscale(K, R * G.w[j]);
 }
 
+// The exterior field's rows alone (wavenumber k = omega; neighbour images and the far-field circle
+// see only u+): target unknown t = 2 i + c_r at x_i + (tsx, 0), source unknown s = 2 j + c_c at
+// x_j + (ssx, 0), plain trapezoid weight w_j:
+//   (0, 0) dG/dn_y = (i/4) k H1 b,  (0, 1) G = (i/4) H0,
+//   (1, 0) -T = -(i/4) [k^2 H0 a b + (k H1 / r)(nn - 2 a b)],  (1, 1) -dG/dn_x = (i/4) k H1 a.
+__device__ inline cplx a_ext_tr(const Geo& G, int t, int s, double tsx, double ssx) {
+  const int i = t >> 1, j = s >> 1, cr = t & 1, cc = s & 1;
+  const double dx = G.x[i] + tsx - G.x[j] - ssx, dy = G.y[i] - G.y[j];
+  const double r = sqrt(dx * dx + dy * dy);
+  const double k = G.omega;
+  cplx h0, h1;
+  hankel01(k * r, h0, h1);
+  cplx v;
+  if (cr == 0 && cc == 1) {
+    v = h0;
+  } else {
+    const double a = (G.nx[i] * dx + G.ny[i] * dy) / r, b = (G.nx[j] * dx + G.ny[j] * dy) / r;
+    if (cr == 0) {
+      v = cscale(h1, k * b);
+    } else if (cc == 1) {
+      v = cscale(h1, k * a);
+    } else {
+      const double ab = a * b, c = k * (G.nx[i] * G.nx[j] + G.ny[i] * G.ny[j] - 2.0 * ab) / r;
+      v = mkc(-(k * k * ab * h0.x + c * h1.x), -(k * k * ab * h0.y + c * h1.y));
+    }
+  }
+  return cscale(mkc(-0.25 * v.y, 0.25 * v.x), G.w[j]);
+}
+
 __device__ inline cplx a_entry_any(const Geo& G, int i, int j) { return G.two ? a_entry_tr(G, i, j) : a_entry(G, i, j); }

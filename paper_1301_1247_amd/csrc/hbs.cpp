@@ -635,13 +635,14 @@ int build(hbs_handle* h) {
       for (int b = 0; b < nb; ++b) {
         if (np[b] == 0) continue;
         pd.push_back({dact + V.aoff[b], dwt + woff[b], V.n[b], m[b], 2 * nnear[b] + 2 * nimg[b], np[b], V.cx[b], V.cy[b],
-                      ratio * V.rad[b]});
+                      ratio * V.rad[b], 2});
         maxp = std::max(maxp, np[b] * V.n[b]);
       }
       for (int b = 0; b < nb; ++b) {
         if (npf[b] == 0) continue;
-        pd.push_back({dact + V.aoff[b], dwt + woff[b], V.n[b], m[b], 2 * nnear[b] + 2 * nimg[b] + 3 * np[b], npf[b], h->c0x, h->c0y,
-                      Rfar});
+        // the far-field circle stands for the neighbour images, whose fields are exterior ones
+        pd.push_back({dact + V.aoff[b], dwt + woff[b], V.n[b], m[b], 2 * nnear[b] + 2 * nimg[b] + 3 * h->nc * np[b], npf[b],
+                      h->c0x, h->c0y, Rfar, 1});
         maxp = std::max(maxp, npf[b] * V.n[b]);
       }
       if (!pd.empty()) {

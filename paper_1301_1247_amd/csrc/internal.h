@@ -55,6 +55,7 @@ struct ProxyDesc {
   cplx* wt;
   int n, m, row0, np;
   double cx, cy, R;
+  int nk;  // transmission problem: wavenumbers of the proxy rows (2: omega and n omega, 1: omega alone)
 };
 
 // Sketch Z (s x n, ld s) = Omega (s x m) * W^T (m x n, ld m), Omega complex Rademacher.

@@ -22,6 +22,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int gr = d.rows[r], gc = d.cols[c];
     cplx v;
     if (TWO) {
+      if (d.sx != 0.0) {
+        // neighbour-image near points: the pair (image of gr as source of gc; image as target of gc)
+        // through the exterior field only
+        d.out[r + (size_t)c * d.ld] = a_ext_tr(G, gc, gr, 0.0, d.sx);
+        d.out[d.pair_off + r + (size_t)c * d.ld] = a_ext_tr(G, gr, gc, d.sx, 0.0);
+        return;
+      }
       d.out[r + (size_t)c * d.ld] = d.trans ? a_entry_tr(G, gc, gr) : a_entry_tr(G, gr, gc);
       return;
     }
@@ -59,8 +66,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
 }
 
-// Transmission problem (Sec. 5): proxy rows for the unknown u = 2 i + c of the box, at both
-// wavenumbers kq (q = 0: omega, q = 1: n omega), G_q = (i/4) H0(kq r), r = |x_i - p_l|:
+// Transmission problem (Sec. 5): proxy rows for the unknown u = 2 i + c of the box, at the d.nk
+// wavenumbers kq (q = 0: omega, q = 1: n omega; the far-field circle takes the exterior omega
+// alone), G_q = (i/4) H0(kq r), r = |x_i - p_l|:
 //   row0 + (3q) np + l      incoming single layer: c = 0: G_q(x_i, p_l); c = 1: dG_q/dn_x      (x wp)
 //   row0 + (3q + 1) np + l  incoming double layer: the same row functionals of
 //                           [dG_q/dnu_l - i kq G_q](x_i, p_l)                                  (x wp)
@@ -94,6 +102,7 @@ __global__ __launch_bounds__(NT) void k_proxy_tr(Geo G, const ProxyDesc* __restr
   hankel01(G.omega1 * r, hh[1][0], hh[1][1]);
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
+    if (q >= d.nk) break;
     const double k = q ? G.omega1 : G.omega;
     const cplx h0 = hh[q][0], h1 = hh[q][1];
     const cplx g = mkc(-0.25 * h0.y, 0.25 * h0.x);                      // G
@@ -1097,13 +1106,19 @@ __global__ __launch_bounds__(NT) void k_gj_colperm(const InvDescT<R>* __restrict
 
 // out[r + c*ld] = K(y_rows[r], y_c + shift e_1, n_c) w_c for every node c: rows of the plain
 // trapezoid discretization of D - i omega S from a translated copy of the curve (Sec. 2.4, A_j).
+// Transmission problem: rows and columns are unknowns (2N columns) and the entries those of the
+// exterior field alone.
 __global__ __launch_bounds__(NT) void k_eval_shift(Geo G, const int* __restrict__ rows, int nr, double shift,
                                                    cplx* __restrict__ out, int ld) {
-  const int64_t total = (int64_t)nr * G.N;
+  const int64_t total = (int64_t)nr * G.N * (G.two ? 2 : 1);
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int r = (int)(e % nr);
     const int c = (int)(e / nr);
     const int gr = rows[r];
+    if (G.two) {
+      out[r + (size_t)c * ld] = a_ext_tr(G, gr, c, 0.0, shift);
+      continue;
+    }
     const cplx K = helm_kernel(G.omega, G.x[gr] - (G.x[c] + shift), G.y[gr] - G.y[c], G.nx[c], G.ny[c]);
     out[r + (size_t)c * ld] = cscale(K, G.w[c]);
   }
@@ -1285,7 +1300,8 @@ template hipError_t launch_inv<double>(const InvDesc*, int, int, cplx*, int*, in
 template hipError_t launch_inv<float>(const InvDesc32*, int, int, cplxf*, int*, int*, hipStream_t);
 hipError_t launch_eval_shift(const Geo& g, const int* rows, int nr, double shift, cplx* out, int ld, hipStream_t s) {
   if (nr == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_eval_shift, dim3(grid_for((int64_t)nr * g.N, 8192)), dim3(NT), 0, s, g, rows, nr, shift, out, ld);
+  hipLaunchKernelGGL(k_eval_shift, dim3(grid_for((int64_t)nr * g.N * (g.two ? 2 : 1), 8192)), dim3(NT), 0, s, g, rows, nr,
+                     shift, out, ld);
   return hipGetLastError();
 }
 hipError_t launch_hankel(const double* x, int64_t n, cplx* out, hipStream_t s) {

@@ -24,7 +24,8 @@ __device__ inline cplx cexpi_c(cplx z) {
 // Transmission problem: row 2i is the value above at node i, row 2i + 1 minus its normal derivative,
 // d/dn e^{i k y + i s |x - x_W|} = i (s sign(x - x_W) n_x + k n_y) e^{...}.
 __global__ __launch_bounds__(NT) void k_gen_B(QPGeo Q, cplx* __restrict__ Y, int64_t ldy) {
-  const int nrow = Q.two ? 2 * Q.N : Q.N;
+  // rows: every unknown, or the Q.N unknowns idx[] (a skeleton subset)
+  const int nrow = (Q.two && !Q.idx) ? 2 * Q.N : Q.N;
   const int64_t total = (int64_t)nrow * 4 * Q.M;
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int i = (int)(e % nrow);
@@ -32,8 +33,8 @@ __global__ __launch_bounds__(NT) void k_gen_B(QPGeo Q, cplx* __restrict__ Y, int
     const int wall = col / (2 * Q.M);          // 0 = L, 1 = R
     const int dbl = (col / Q.M) & 1;           // 0 = single, 1 = double
     const int m = col % Q.M;
-    const int ii = Q.two ? i >> 1 : i;
-    const int nd = Q.idx ? Q.idx[ii] : ii;
+    const int u = Q.idx ? Q.idx[i] : i;
+    const int nd = Q.two ? u >> 1 : u;
     const double xw = wall ? 0.5 * Q.period : -0.5 * Q.period;
     const double dx = Q.x[nd] + Q.shift - xw;
     const cplx k = Q.k[m], s = Q.s[m], wk = Q.wk[m];
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(NT) void k_gen_B(QPGeo Q, cplx* __restrict__ Y, int
     cplx v;
     if (!dbl) v = cmul(mkc(0.0, 0.5), cmul(ex, cinv(s)));
     else v = cscale(ex, dx > 0 ? 0.5 : -0.5);
-    if (Q.two && (i & 1)) {
+    if (Q.two && (u & 1)) {
       const double sg = dx > 0 ? 1.0 : -1.0;
       // -i (s sg n_x + k n_y) v
       const cplx f = cadd(cscale(s, sg * Q.nx[nd]), cscale(k, Q.ny[nd]));
@@ -84,15 +85,15 @@ __global__ __launch_bounds__(NT) void k_gen_inc(QPGeo Q, const double* __restric
 // deriv i E (s n_x - k sigma n_y)) and column 2j + 1 the single layer alone (value i E / s, deriv E
 // sigma), both times w_j: the Dirichlet column is their combination D - i omega S.
 __global__ __launch_bounds__(NT) void k_gen_C(QPGeo Q, int wall, double shift, cplx* __restrict__ C) {
-  const int ncol = Q.two ? 2 * Q.N : Q.N;
+  const int ncol = (Q.two && !Q.idx) ? 2 * Q.N : Q.N;
   const int64_t total = (int64_t)ncol * Q.M;
   const double xw = wall ? 0.5 * Q.period : -0.5 * Q.period;
   const int ldc = 2 * Q.M;
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int m = (int)(e % Q.M);
     const int j = (int)(e / Q.M);
-    const int jj = Q.two ? j >> 1 : j;
-    const int nd = Q.idx ? Q.idx[jj] : jj;
+    const int uj = Q.idx ? Q.idx[j] : j;
+    const int nd = Q.two ? uj >> 1 : uj;
     const double dx = Q.x[nd] + shift - xw;
     const double sg = dx > 0 ? 1.0 : -1.0;
     const cplx k = Q.k[m], s = Q.s[m];
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(NT) void k_gen_C(QPGeo Q, int wall, double shift, c
     const cplx E = cscale(cexpi_c(z), 1.0 / (4.0 * PI));
     const cplx is = cinv(s);
     const double nx = Q.nx[nd], ny = Q.ny[nd], w = Q.w[nd];
-    if (Q.two && (j & 1)) {
+    if (Q.two && (uj & 1)) {
       const cplx ve = cmul(mkc(0.0, 1.0), cmul(E, is));
       C[m + (size_t)j * ldc] = cscale(ve, w);
       C[Q.M + m + (size_t)j * ldc] = cscale(E, sg * w);
@@ -485,7 +486,7 @@ inline int grid_for(int64_t elems, int cap = 8192) {
 namespace qps {
 
 hipError_t launch_gen_B(const QPGeo& q, cplx* Y, int64_t ldy, hipStream_t s) {
-  hipLaunchKernelGGL(k_gen_B, dim3(grid_for((int64_t)(q.two ? 2 : 1) * q.N * 4 * q.M)), dim3(NT), 0, s, q, Y, ldy);
+  hipLaunchKernelGGL(k_gen_B, dim3(grid_for((int64_t)((q.two && !q.idx) ? 2 : 1) * q.N * 4 * q.M)), dim3(NT), 0, s, q, Y, ldy);
   return hipGetLastError();
 }
 hipError_t launch_gen_inc(const QPGeo& q, const double* kx, const double* ky, const double* ky_im, int nang, cplx* Y,
@@ -495,7 +496,7 @@ hipError_t launch_gen_inc(const QPGeo& q, const double* kx, const double* ky, co
   return hipGetLastError();
 }
 hipError_t launch_gen_C(const QPGeo& q, int wall, double shift, cplx* C, hipStream_t s) {
-  hipLaunchKernelGGL(k_gen_C, dim3(grid_for((int64_t)(q.two ? 2 : 1) * q.N * q.M)), dim3(NT), 0, s, q, wall, shift, C);
+  hipLaunchKernelGGL(k_gen_C, dim3(grid_for((int64_t)((q.two && !q.idx) ? 2 : 1) * q.N * q.M)), dim3(NT), 0, s, q, wall, shift, C);
   return hipGetLastError();
 }
 hipError_t launch_form_S(const QPGeo& q, const cplx* coef, int ng, const cplx* G1, const cplx* G2, cplx* S, hipStream_t s) {

@@ -122,8 +122,8 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
     set_error("qp_solve: P must be 0 or 1");
     return HBS_E_INVALID_ARG;
   }
-  if (h->nc != 1 && (P != 0 || cols)) {
-    set_error("qp_solve: the transmission problem takes P = 0 (and no displaced-contour columns)");
+  if (h->nc != 1 && cols) {
+    set_error("qp_solve: the transmission problem has no displaced-contour solve");
     return HBS_E_INVALID_ARG;
   }
   if (P == 1) {

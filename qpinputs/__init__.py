@@ -18,6 +18,9 @@ random-Fourier "rough" obstacle, Sec. 6.2; sizes are this project's):
 * ``star_d1``  the scaling test of Sec. 6.1: r(t) = 0.35 + 0.105 cos 3t, period d = 1 (the
                neighbour images come within 0.25 of the obstacle), omega = 10, theta = -pi/5;
                N = 2^17 there, smaller here by default.
+* ``star_d1_tr`` the same grating as a transmission problem (Sec. 5, the second case of
+               Sec. 6.1): refractive index n = 1.5 inside the obstacle, N = 2^17 nodes
+               (2^18 unknowns), leaf boxes of 128 unknowns.
 """
 from __future__ import annotations
 
@@ -194,6 +197,7 @@ class Workload:
     tol: float
     leaf_size: int
     quad: str  # "kr6" or "kress"
+    index: float = 0.0  # > 0: transmission problem with this refractive index inside the obstacle
 
 
 def workload(name: str) -> Workload:
@@ -206,6 +210,9 @@ def workload(name: str) -> Workload:
     if name == "star_d1":
         return Workload("star_d1", star(0.35, 0.105, 3), 131072, 10.0, 1.0, np.array([-math.pi / 5]), 1e-10, 64,
                         "kr6")
+    if name == "star_d1_tr":
+        return Workload("star_d1_tr", star(0.35, 0.105, 3), 131072, 10.0, 1.0, np.array([-math.pi / 5]), 1e-10, 128,
+                        "kr6", 1.5)
     if name == "wavy40":
         c = wavy(130103, 40, 0.2)
         th = shared_phase_angles(60.0, TWO_PI)

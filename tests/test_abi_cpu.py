@@ -205,13 +205,13 @@ def test_image_period_needs_far_radius():
 
 def test_transmission_options_are_checked_on_the_host():
     """index > 0 (the transmission problem of Sec. 5) is built on the Kapur-Rokhlin operator without
-    the far-field circle, image columns or the Dirichlet-trained rank model: each combination is
-    refused before any GPU work, as is a negative or non-finite index."""
+    the Dirichlet-trained rank model, and its image columns need the far-field circle like the
+    Dirichlet ones: each combination is refused before any GPU work, as is a negative or
+    non-finite index."""
     nodes, w, nrm, _ = _geom()
     for kw, word in ((dict(index=-1.0), "index"), (dict(index=float("nan")), "index"),
                      (dict(index=1.5, quad=1), "KR6"), (dict(index=1.5, quad=2), "KR6"),
-                     (dict(index=1.5, far_radius=2.0), "far_radius"),
-                     (dict(index=1.5, far_radius=2.0, image_period=1.0), "image_period"),
+                     (dict(index=1.5, image_period=1.0), "far_radius"),
                      (dict(index=1.5, rank_predictor=1), "rank_predictor"),
                      (dict(index=1.5, leaf_size=512), "leaf_size")):
         rc, msg = _build(nodes, w, nrm, 256, **kw)

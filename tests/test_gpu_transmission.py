@@ -147,3 +147,62 @@ def test_refusals(gpu_lib, star_tr):
     with pytest.raises(gpu_lib.HBSError) as e:
         h.qp_solve_many(D, np.array([th]), P=0)
     assert e.value.code == -9
+
+
+@pytest.mark.parametrize("P,defer", [(0, False), (0, True), (1, False)])
+def test_compressed_walls_match_oracle(gpu_lib, star_tr, P, defer):
+    """Wall blocks through the root skeletons (the handle's far_radius circle excludes the walls), with
+    the root inversion deferred into the Woodbury batch, and with the P = 1 images of Sec. 2.4 (exterior
+    field only) in the Woodbury form of Eq. 3.2.  The wall blocks interpolated from the skeleton rows
+    carry the decompositions' error unrefined (the refinement runs on the compressed bordered system),
+    and the transmission operator's rows differ in scale by about k^2 between the value and the
+    normal-derivative jumps: the decompositions take tol 1e-14 here (eta moves by about 3e3 tol)."""
+    c, N, disc, A, _ = star_tr
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, OM, 1e-14, index=IDX, far_radius=2.0, defer_root=defer)
+    ths = np.array([-math.pi / 5, -1.2])
+    r = h.qp_solve_many(D, ths, P=P)
+    assert h.stats().walls_compressed == 1
+    ref = tr.solve_qp(disc, N, OM, IDX, D, ths, P=P, A0=A)
+    for a in range(len(ths)):
+        assert _rel(r["eta"][:, a], ref["eta"][:, a]) < 1e-10
+        assert _rel(r["xi"][:, a], ref["xi"][:, a]) < 1e-10
+        assert abs(r["flux"][a] - ref["flux"][a]) < 1e-10
+
+
+def test_d1_grating_with_near_images_matches_oracle(gpu_lib):
+    """The transmission case of Sec. 6.1 (d = 1: the neighbour images come within 0.09 of the obstacle)
+    at a size the oracle solves densely: P = 1 with the images' near points as explicit columns."""
+    wl = qpinputs.workload("star_d1_tr")
+    N = 600
+    disc = ny.Discretization(wl.curve, N)
+    nodes, w, nrm, _ = discretize(wl.curve, N)
+    h = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-12, index=wl.index, far_radius=1.0, image_period=wl.period,
+                       leaf_size=64)
+    ths = np.array([-math.pi / 5, -1.0])
+    r = h.qp_solve_many(wl.period, ths, P=1, h=0.2)
+    assert h.stats().image_samples > 0
+    ref = tr.solve_qp(disc, N, wl.omega, wl.index, wl.period, ths, P=1, h=0.2)
+    for a in range(len(ths)):
+        assert _rel(r["eta"][:, a], ref["eta"][:, a]) < 1e-10
+        assert _rel(r["xi"][:, a], ref["xi"][:, a]) < 1e-10
+        n, kn, cc, dd = ref["bragg"][a]
+        nm, mx = r["nmodes"][a], r["maxmodes"]
+        assert np.abs(r["bragg"][:nm, a] - cc).max() < 1e-9 * np.abs(cc).max()
+        assert np.abs(r["bragg"][mx:mx + nm, a] - dd).max() < 1e-9 * np.abs(dd).max()
+        assert abs(r["flux"][a] - ref["flux"][a]) < 1e-10
+
+
+def test_d1_grating_full_size(gpu_lib):
+    """N = 2^17 nodes (2^18 unknowns), the size of Sec. 6.1: sampled rows of the bordered residual
+    (exact oracle rows) and the energy balance, both below 1e-10.  The neighbour terms go through the
+    skeletons unrefined (as the compressed walls above), so the decompositions take tol 1e-14."""
+    from oracle import checks
+    wl = qpinputs.workload("star_d1_tr")
+    nodes, w, nrm, _ = discretize(wl.curve, wl.N)
+    h = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-14, index=wl.index, far_radius=1.0, image_period=wl.period,
+                       leaf_size=wl.leaf_size)
+    r = h.qp_solve_many(wl.period, wl.thetas, P=1, h=0.2)
+    v = checks.bordered_residual_tr(wl.curve, wl.N, wl.omega, wl.index, wl.period, wl.thetas, r["eta"], r["xi"],
+                                    r["flux"], n_rows=16, P=1, h=0.2)
+    assert v["sampled_rel_residual"] < 1e-10 and v["flux_err_max"] < 1e-10, v
