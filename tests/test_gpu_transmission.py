@@ -206,3 +206,42 @@ def test_d1_grating_full_size(gpu_lib):
     v = checks.bordered_residual_tr(wl.curve, wl.N, wl.omega, wl.index, wl.period, wl.thetas, r["eta"], r["xi"],
                                     r["flux"], n_rows=16, P=1, h=0.2)
     assert v["sampled_rel_residual"] < 1e-10 and v["flux_err_max"] < 1e-10, v
+
+
+def test_device_pointers_graphs_and_noalloc(gpu_lib, star_tr):
+    """The 2N-long vectors through the device-pointer handle: the graph-captured applies and the
+    no-allocation apply give the plain apply's result, and the qp_solve of the graph handle the
+    plain one's."""
+    import torch
+    c, N, disc, A, lu = star_tr
+    nodes, w, nrm, _ = discretize(c, N)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    h = gpu_lib.Handle(t(nodes), t(w), t(nrm), OM, 1e-12, index=IDX, device=True)
+    hg = gpu_lib.Handle(t(nodes), t(w), t(nrm), OM, 1e-12, index=IDX, device=True, graph=True)
+    rng = np.random.default_rng(13)
+    B = rng.standard_normal((3, 2 * N)) + 1j * rng.standard_normal((3, 2 * N))
+    tb = t(B)
+    x = h.apply(tb, refine=1).cpu().numpy()
+    assert _rel(x.T, sla.lu_solve(lu, B.T)) < 1e-10
+    for _ in range(3):  # captured once, then replayed
+        assert np.abs(hg.apply(tb, refine=1).cpu().numpy() - x).max() <= 1e-12 * np.abs(x).max()
+    xn = h.apply_noalloc(tb, refine=1).cpu().numpy()
+    assert np.abs(xn - x).max() <= 1e-12 * np.abs(x).max()
+    ths = torch.tensor([-math.pi / 5, -1.2], dtype=torch.float64)
+    r0 = h.qp_solve_many(D, ths, P=0)
+    r1 = hg.qp_solve_many(D, ths, P=0)
+    e0, e1 = r0["eta"].cpu().numpy(), r1["eta"].cpu().numpy()
+    assert np.abs(e1 - e0).max() <= 1e-12 * np.abs(e0).max()
+
+
+def test_fp32_preconditioner_refines_to_fp64(gpu_lib, star_tr):
+    """complex64 inverse factors of the deep levels as a preconditioner for the transmission operator:
+    FP64 refinement recovers the 1e-10 bar."""
+    c, N, disc, A, lu = star_tr
+    nodes, w, nrm, _ = discretize(c, N)
+    h = gpu_lib.Handle(nodes, w, nrm, OM, 1e-12, index=IDX, precision="fp32", fp64_top_levels=1)
+    rng = np.random.default_rng(14)
+    B = rng.standard_normal((2 * N, 4)) + 1j * rng.standard_normal((2 * N, 4))
+    Xe = sla.lu_solve(lu, B)
+    assert 1e-9 < _rel(h.apply(B), Xe) < 1e-3
+    assert _rel(h.apply(B, refine=5), Xe) < 1e-10
