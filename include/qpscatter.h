@@ -117,12 +117,15 @@ typedef struct {
                                refractive index n of the obstacle (wavenumber n omega inside, omega
                                outside), matching conditions of Eqs. 5.3-5.4.  The unknowns are the
                                densities tau (double layer) and sigma (single layer) of both sides'
-                               potentials, interlaced node by node as Sec. 5.3 asks: 2N unknowns
+                               potentials (u = D tau + kb S sigma on both sides, kb = max(omega,
+                               n omega)), interlaced node by node as Sec. 5.3 asks: 2N unknowns
                                [tau_1; sigma_1; tau_2; ...], row 2i the value jump at node i and row
-                               2i + 1 minus the normal-derivative jump, so that the operator is
-                               I + [[D0 - D1, S0 - S1], [-(T0 - T1), -(D0* - D1*)]] (T the normal
-                               derivative of D, D* that of S; 0 and 1 the two wavenumbers), every block
-                               with the Kapur-Rokhlin weights.  Every N-sized vector of the other calls
+                               2i + 1 minus the normal-derivative jump divided by kb, so that the
+                               operator is I + [[D0 - D1, kb (S0 - S1)], [-(T0 - T1) / kb,
+                               -(D0* - D1*)]] (T the normal derivative of D, D* that of S; 0 and 1 the
+                               two wavenumbers), every block with the Kapur-Rokhlin weights; the factor
+                               kb brings the four blocks to one size, which the decompositions'
+                               relative tolerance needs.  Every N-sized vector of the other calls
                                (hbs_apply's rhs, qp_solve's eta) then has 2N rows, and leaf_size counts
                                unknowns.  Needs HBS_QUAD_KR6, far_radius = 0, image_period = 0 and
                                rank_predictor = 0; qp_solve takes P = 0 with the wall blocks

@@ -100,17 +100,17 @@ def bordered_residual_tr(curve, N, omega, index, period, thetas, eta, xi, flux=N
     rows = np.stack([2 * nodes, 2 * nodes + 1], axis=1).ravel()
     angs = np.asarray(angles) if angles is not None else rng.choice(len(thetas), min(n_ang, len(thetas)), replace=False)
     Arows = transmission.matrix_rows(disc, omega, index, rows)
-    Anb = {j: transmission.neighbour_rows(disc, omega, j * period, rows) for j in ((-1, 1) if P else ())}
+    Anb = {j: transmission.neighbour_rows(disc, omega, index, j * period, rows) for j in ((-1, 1) if P else ())}
     sub = RowSubset(disc, nodes)
-    BL, BR = transmission.wall_B(sub, omega, period, ct)
+    BL, BR = transmission.wall_B(sub, omega, index, period, ct)
     eta_s = eta[:, angs]
     CLe = 0
     CRe = 0
     for c0 in range(0, N, chunk):
         sl = np.arange(c0, min(N, c0 + chunk))
         us = np.stack([2 * sl, 2 * sl + 1], axis=1).ravel()
-        CL, _ = transmission.wall_C(RowSubset(disc, sl), omega, period, ct, shift=P * period)
-        _, CR = transmission.wall_C(RowSubset(disc, sl), omega, period, ct, shift=-P * period)
+        CL, _ = transmission.wall_C(RowSubset(disc, sl), omega, index, period, ct, shift=P * period)
+        _, CR = transmission.wall_C(RowSubset(disc, sl), omega, index, period, ct, shift=-P * period)
         CLe = CLe + CL @ eta_s[us]
         CRe = CRe + CR @ eta_s[us]
     worst = 0.0
@@ -118,11 +118,11 @@ def bordered_residual_tr(curve, N, omega, index, period, thetas, eta, xi, flux=N
         th = thetas[a]
         al = periodic.bloch_phase(omega, period, th)
         x = xi[:, a]
-        b = transmission.incident(sub, omega, th)[:, 0]
+        b = transmission.incident(sub, omega, index, th)[:, 0]
         At = Arows + sum(al ** j * Anb[j] for j in Anb)
         r1 = At @ eta_s[:, q] + (BL + al * BR) @ x - b
         r2 = al ** P * CLe[:, q] - al ** (-(P + 1)) * CRe[:, q] + periodic.wall_Q(omega, period, al, ct) @ x
-        bn = np.linalg.norm(transmission.incident(disc, omega, th))
+        bn = np.linalg.norm(transmission.incident(disc, omega, index, th))
         worst = max(worst, math.sqrt(np.sum(np.abs(r1) ** 2) * N / n_rows + np.sum(np.abs(r2) ** 2)) / bn)
     out = {"sampled_rel_residual": float(worst), "rows_sampled": int(2 * n_rows), "angles_sampled": int(len(angs))}
     if flux is not None:

@@ -21,6 +21,13 @@ plain Mueller-type one that its text describes (readings, each checked by the te
 * Unknown order: node by node, [tau_1; sigma_1; tau_2; sigma_2; ...] (row 2i: value jump at node
   i, row 2i + 1: minus the normal-derivative jump); the paper's [sigma; tau] naming of the pair is
   a label, the interlacing is what matters.
+* Normalization: with kb = max(omega, n omega) the single layer carries the factor kb,
+  u = D_k tau + kb S_k sigma, and the normal-derivative row is divided by kb.  In the far field
+  D ~ k G, S ~ G, T ~ k^2 G and D* ~ k G, so every block of the operator is then of the size
+  kb G: the interpolative decompositions of the fast solver, whose tolerance is relative to the
+  largest entries, resolve both rows and both densities alike (without it the error grows like
+  tol kb^2).  The jumps become tau + (D0 - D1) tau + kb (S0 - S1) sigma = -u^i and
+  sigma - (T0 - T1) tau / kb - (D0* - D1*) sigma = u^i_n / kb.
 * Quadrature: every one of the four difference kernels has the form phi(s) ln|s| + psi(s) with
   phi, psi smooth (the log part of G0 - G1 is O(r^2 ln r), and T0 - T1 keeps only a log
   singularity), so the Kapur-Rokhlin weights of Sec. 2.3 (R_0 = 0, R_m = 1 + g_m) apply to all four.
@@ -42,10 +49,15 @@ from scipy.special import hankel1
 from . import nystrom, periodic, quadrature
 
 
+def kbar(omega: float, index: float) -> float:
+    """The normalization wavenumber kb = max(omega, n omega) of the module docstring."""
+    return max(omega, index * omega)
+
+
 def kernels(k0: float, k1: float, tx, tn, sy, sn):
     """The four difference kernels of the module docstring at targets tx (normals tn) and sources
-    sy (normals sn): returns (K_vt, K_vs, K_nt, K_ns) = (D0 - D1, S0 - S1, -(T0 - T1), -(D0* - D1*)),
-    unweighted, each (m, n).  Entries with r = 0 are NaN (never used)."""
+    sy (normals sn): returns (K_vt, K_vs, K_nt, K_ns) = (D0 - D1, kb (S0 - S1), -(T0 - T1) / kb,
+    -(D0* - D1*)), kb = max(k0, k1), unweighted, each (m, n).  Entries with r = 0 are NaN (never used)."""
     dx = tx[:, None, 0] - sy[None, :, 0]
     dy = tx[:, None, 1] - sy[None, :, 1]
     r = np.hypot(dx, dy)
@@ -63,12 +75,13 @@ def kernels(k0: float, k1: float, tx, tn, sy, sn):
             T = 0.25j * (k * k * h0 * a * b + (k * h1 / r) * (nn - 2.0 * a * b))
             out.append((dGy, G, T, dGx))
     (d0, s0, t0, x0), (d1, s1, t1, x1) = out
-    return d0 - d1, s0 - s1, -(t0 - t1), -(x0 - x1)
+    kb = max(k0, k1)
+    return d0 - d1, kb * (s0 - s1), -(t0 - t1) / kb, -(x0 - x1)
 
 
-def exterior_kernels(k0: float, tx, tn, sy, sn):
-    """The exterior field's rows alone: (dG/dn_y, G, -T, -dG/dn_x) at wavenumber k0 (the images of
-    Sec. 2.4 and the walls contribute to u+ only)."""
+def exterior_kernels(k0: float, kb: float, tx, tn, sy, sn):
+    """The exterior field's rows alone: (dG/dn_y, kb G, -T / kb, -dG/dn_x) at wavenumber k0 (the
+    images of Sec. 2.4 and the walls contribute to u+ only)."""
     dx = tx[:, None, 0] - sy[None, :, 0]
     dy = tx[:, None, 1] - sy[None, :, 1]
     r = np.hypot(dx, dy)
@@ -78,7 +91,7 @@ def exterior_kernels(k0: float, tx, tn, sy, sn):
     h0 = hankel1(0, k0 * r)
     h1 = hankel1(1, k0 * r)
     T = 0.25j * (k0 * k0 * h0 * a * b + (k0 * h1 / r) * (nn - 2.0 * a * b))
-    return 0.25j * k0 * h1 * b, 0.25j * h0, -T, 0.25j * k0 * h1 * a
+    return 0.25j * k0 * h1 * b, kb * 0.25j * h0, -T / kb, 0.25j * k0 * h1 * a
 
 
 def interlace(Kvt, Kvs, Knt, Kns):
@@ -129,19 +142,19 @@ def matrix_rows(disc: nystrom.Discretization, omega: float, index: float, rows) 
     return out
 
 
-def neighbour_matrix(disc: nystrom.Discretization, omega: float, shift: float) -> np.ndarray:
+def neighbour_matrix(disc: nystrom.Discretization, omega: float, index: float, shift: float) -> np.ndarray:
     """A_j of Sec. 2.4 for the exterior field: plain trapezoid rule from the copy dOmega + shift e_1."""
     src = disc.x + np.array([shift, 0.0])
-    blocks = exterior_kernels(omega, disc.x, disc.nrm, src, disc.nrm)
+    blocks = exterior_kernels(omega, kbar(omega, index), disc.x, disc.nrm, src, disc.nrm)
     return interlace(*[K * disc.w[None, :] for K in blocks])
 
 
-def neighbour_rows(disc: nystrom.Discretization, omega: float, shift: float, rows) -> np.ndarray:
+def neighbour_rows(disc: nystrom.Discretization, omega: float, index: float, shift: float, rows) -> np.ndarray:
     """Rows ``rows`` of ``neighbour_matrix``."""
     rows = np.asarray(rows, dtype=np.int64).reshape(-1)
     nodes = rows // 2
     src = disc.x + np.array([shift, 0.0])
-    blocks = exterior_kernels(omega, disc.x[nodes], disc.nrm[nodes], src, disc.nrm)
+    blocks = exterior_kernels(omega, kbar(omega, index), disc.x[nodes], disc.nrm[nodes], src, disc.nrm)
     out = np.zeros((len(rows), 2 * disc.N), dtype=complex)
     for q, K in enumerate(blocks):
         comp_r, comp_c = divmod(q, 2)
@@ -150,29 +163,29 @@ def neighbour_rows(disc: nystrom.Discretization, omega: float, shift: float, row
     return out
 
 
-def rhs_from_jumps(f, g):
-    """Right-hand side for prescribed jumps u+ - u- = f, u+_n - u-_n = g (rows [f; -g] interlaced)."""
+def rhs_from_jumps(f, g, kb):
+    """Right-hand side for prescribed jumps u+ - u- = f, u+_n - u-_n = g (rows [f; -g / kb] interlaced)."""
     f = np.asarray(f)
     g = np.asarray(g)
     out = np.empty((2 * f.shape[0],) + f.shape[1:], dtype=complex)
     out[0::2] = f
-    out[1::2] = -g
+    out[1::2] = -g / kb
     return out
 
 
-def incident(disc: nystrom.Discretization, omega: float, theta):
+def incident(disc: nystrom.Discretization, omega: float, index: float, theta):
     """Eqs. 5.3-5.4 with u^i = exp(i k.x): jumps -u^i and -u^i_n, interlaced (N x q -> 2N x q)."""
     th = np.atleast_1d(np.asarray(theta, dtype=np.float64))
     kx = omega * np.cos(th)
     ky = omega * np.sin(th)
     ui = np.exp(1j * (np.outer(disc.x[:, 0], kx) + np.outer(disc.x[:, 1], ky)))
     dn = 1j * (np.outer(disc.nrm[:, 0], kx) + np.outer(disc.nrm[:, 1], ky)) * ui
-    return rhs_from_jumps(-ui, -dn)
+    return rhs_from_jumps(-ui, -dn, kbar(omega, index))
 
 
-def potential(disc: nystrom.Discretization, k: float, eta: np.ndarray, targets: np.ndarray,
+def potential(disc: nystrom.Discretization, k: float, kb: float, eta: np.ndarray, targets: np.ndarray,
               shift: float = 0.0) -> np.ndarray:
-    """D_k tau + S_k sigma from the copy dOmega + shift e_1 at off-surface targets (plain trapezoid;
+    """D_k tau + kb S_k sigma from the copy dOmega + shift e_1 at off-surface targets (plain trapezoid;
     targets away from that copy)."""
     dx = targets[:, None, 0] - (disc.x[None, :, 0] + shift)
     dy = targets[:, None, 1] - disc.x[None, :, 1]
@@ -180,12 +193,13 @@ def potential(disc: nystrom.Discretization, k: float, eta: np.ndarray, targets: 
     b = (disc.nrm[None, :, 0] * dx + disc.nrm[None, :, 1] * dy) / r
     D = 0.25j * k * hankel1(1, k * r) * b * disc.w[None, :]
     S = 0.25j * hankel1(0, k * r) * disc.w[None, :]
-    return D @ eta[0::2] + S @ eta[1::2]
+    return D @ eta[0::2] + kb * (S @ eta[1::2])
 
 
-def wall_B(disc, omega, period, ct: periodic.Contour):
+def wall_B(disc, omega, index, period, ct: periodic.Contour):
     """B_L, B_R (2N x 2M): the wall potentials of Eqs. 2.12-2.13 on dOmega, rows [value; minus the
-    normal derivative] interlaced, columns [mu; nu]."""
+    normal derivative over kb] interlaced, columns [mu; nu]."""
+    kb = kbar(omega, index)
     out = []
     nx, ny = disc.nrm[:, 0][:, None], disc.nrm[:, 1][:, None]
     for xw in (-period / 2.0, period / 2.0):
@@ -198,14 +212,15 @@ def wall_B(disc, omega, period, ct: periodic.Contour):
         dBS, dBD = 0.5j * de / ct.s[None, :], 0.5 * sg * de
         B = np.empty((2 * disc.N, 2 * len(ct.k)), dtype=complex)
         B[0::2] = np.hstack([BS, BD])
-        B[1::2] = -np.hstack([dBS, dBD])
+        B[1::2] = -np.hstack([dBS, dBD]) / kb
         out.append(B)
     return out[0], out[1]
 
 
-def wall_C(disc, omega, period, ct: periodic.Contour, shift: float = 0.0):
+def wall_C(disc, omega, index, period, ct: periodic.Contour, shift: float = 0.0):
     """C_L, C_R (2M x 2N): the wall data (value rows, x-derivative rows) of D_{k0} tau (even
-    columns) and S_{k0} sigma (odd columns) from the density on dOmega + shift e_1, as in Eq. 2.17."""
+    columns) and kb S_{k0} sigma (odd columns) from the density on dOmega + shift e_1, as in Eq. 2.17."""
+    kb = kbar(omega, index)
     out = []
     xs = disc.x[:, 0] + shift
     for xw in (-period / 2.0, period / 2.0):
@@ -222,7 +237,7 @@ def wall_C(disc, omega, period, ct: periodic.Contour, shift: float = 0.0):
         derS = E * sg
         C = np.empty((2 * len(ct.k), 2 * disc.N), dtype=complex)
         C[:, 0::2] = np.vstack([valD, derD]) * disc.w[None, :]
-        C[:, 1::2] = np.vstack([valS, derS]) * disc.w[None, :]
+        C[:, 1::2] = kb * np.vstack([valS, derS]) * disc.w[None, :]
         out.append(C)
     return out[0], out[1]
 
@@ -232,20 +247,20 @@ def assemble(disc, omega, index, period, alpha, ct: periodic.Contour, P: int = 0
     A = matrix(disc, omega, index) if A0 is None else A0.copy()
     for j in range(-P, P + 1):
         if j != 0:
-            A = A + alpha ** j * neighbour_matrix(disc, omega, j * period)
-    BL, BR = wall_B(disc, omega, period, ct)
-    CLp, _ = wall_C(disc, omega, period, ct, shift=P * period)
-    _, CRm = wall_C(disc, omega, period, ct, shift=-P * period)
+            A = A + alpha ** j * neighbour_matrix(disc, omega, index, j * period)
+    BL, BR = wall_B(disc, omega, index, period, ct)
+    CLp, _ = wall_C(disc, omega, index, period, ct, shift=P * period)
+    _, CRm = wall_C(disc, omega, index, period, ct, shift=-P * period)
     C = alpha ** P * CLp - alpha ** (-(P + 1)) * CRm
     return periodic.QPSystem(A, BL + alpha * BR, C, periodic.wall_Q(omega, period, alpha, ct), alpha)
 
 
-def bragg_lattice(disc, omega, period, theta, eta, y0):
+def bragg_lattice(disc, omega, index, period, theta, eta, y0):
     """Bragg amplitudes above (c_n) and below (d_n) from eta alone (module docstring)."""
     n, kx, kn = periodic.bragg_orders(omega, period, theta)
     x, y = disc.x[:, 0], disc.x[:, 1]
     nx, ny = disc.nrm[:, 0], disc.nrm[:, 1]
-    wt, ws = disc.w * eta[0::2], disc.w * eta[1::2]
+    wt, ws = disc.w * eta[0::2], kbar(omega, index) * disc.w * eta[1::2]
     pre = 1j * np.exp(1j * kn * y0) / (2 * period * kn)
     eu = np.exp(-1j * (np.outer(kx, x) + np.outer(kn, y)))
     ed = np.exp(-1j * (np.outer(kx, x) - np.outer(kn, y)))
@@ -254,11 +269,11 @@ def bragg_lattice(disc, omega, period, theta, eta, y0):
     return n, kn, c, d
 
 
-def field(disc, omega, period, alpha, ct: periodic.Contour, eta, xi, pts, P=0):
+def field(disc, omega, index, period, alpha, ct: periodic.Contour, eta, xi, pts, P=0):
     """Scattered exterior field in the unit cell away from dOmega: images plus wall potentials."""
     u = np.zeros(len(pts), dtype=complex)
     for j in range(-P, P + 1):
-        u += alpha ** j * potential(disc, omega, eta, pts, shift=j * period)
+        u += alpha ** j * potential(disc, omega, kbar(omega, index), eta, pts, shift=j * period)
     M = len(ct.k)
     mu, nu = xi[:M], xi[M:]
     for xw, fac in ((-period / 2.0, 1.0), (period / 2.0, alpha)):
@@ -268,12 +283,12 @@ def field(disc, omega, period, alpha, ct: periodic.Contour, eta, xi, pts, P=0):
     return u
 
 
-def bragg_sampled(disc, omega, period, alpha, ct, theta, eta, xi, y0, ns=128, P=0):
+def bragg_sampled(disc, omega, index, period, alpha, ct, theta, eta, xi, y0, ns=128, P=0):
     """Bragg amplitudes by sampling the exterior field on y = +-y0 and a DFT (Remarks 2.2-2.3)."""
     n, kx, kn = periodic.bragg_orders(omega, period, theta)
     xl = -period / 2 + (np.arange(ns) + 0.5) * period / ns
-    up = field(disc, omega, period, alpha, ct, eta, xi, np.stack([xl, np.full(ns, y0)], 1), P)
-    dn = field(disc, omega, period, alpha, ct, eta, xi, np.stack([xl, np.full(ns, -y0)], 1), P)
+    up = field(disc, omega, index, period, alpha, ct, eta, xi, np.stack([xl, np.full(ns, y0)], 1), P)
+    dn = field(disc, omega, index, period, alpha, ct, eta, xi, np.stack([xl, np.full(ns, -y0)], 1), P)
     F = np.exp(-1j * np.outer(kx, xl)) / ns
     return n, kn, F @ up, F @ dn
 
@@ -290,9 +305,9 @@ def solve_qp(curve_or_disc, N, omega, index, period, thetas, P=0, h=0.1, A0=None
     for th in np.atleast_1d(thetas):
         al = periodic.bloch_phase(omega, period, th)
         sysm = assemble(disc, omega, index, period, al, ct, P=P, A0=A)
-        eta, xi = periodic.solve_bordered(sysm, incident(disc, omega, th))
+        eta, xi = periodic.solve_bordered(sysm, incident(disc, omega, index, th))
         eta, xi = eta[:, 0], xi[:, 0]
-        nn, kn, c, d = bragg_lattice(disc, omega, period, th, eta, y0)
+        nn, kn, c, d = bragg_lattice(disc, omega, index, period, th, eta, y0)
         etas.append(eta)
         xis.append(xi)
         braggs.append((nn, kn, c, d))

@@ -400,6 +400,7 @@ int hbs_build(const double* nodes, const double* weights, const double* normals,
   G.omega = omega;
   G.two = o.index > 0;
   G.omega1 = o.index > 0 ? o.index * omega : 0.0;
+  G.kbar = o.index > 0 ? std::max(omega, o.index * omega) : 1.0;
   kr6_corrections(G.g);
   if (o.quad == HBS_QUAD_KRESS) {
     std::vector<double> R = kress_weights(N);

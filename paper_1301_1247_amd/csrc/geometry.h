@@ -106,13 +106,15 @@ __device__ inline cplx a_entry(const Geo& G, int i, int j) {
 
 // Transmission problem (Sec. 5): the four difference kernels of the interlaced 2 x 2 operator, with
 // H0, H1 taken at k0 r and k1 r (k0 = omega outside, k1 = n omega inside), a = n_x.(x - y)/r,
-// b = n_y.(x - y)/r, nn = n_x.n_y, d1 = k0 H1(k0 r) - k1 H1(k1 r), d0 = k0^2 H0(k0 r) - k1^2 H0(k1 r):
-//   (row 0, col 0)  D0 - D1           = (i/4) b d1
-//   (0, 1)          S0 - S1           = (i/4) [H0(k0 r) - H0(k1 r)]
-//   (1, 0)          -(T0 - T1)        = -(i/4) [a b d0 + (nn - 2 a b) d1 / r]
-//   (1, 1)          -(D0* - D1*)      = (i/4) a d1
+// b = n_y.(x - y)/r, nn = n_x.n_y, d1 = k0 H1(k0 r) - k1 H1(k1 r), d0 = k0^2 H0(k0 r) - k1^2 H0(k1 r),
+// kb = max(k0, k1) (the single layer carries kb and the normal-derivative row is divided by it, so
+// that all four blocks are of one size in the far field):
+//   (row 0, col 0)  D0 - D1            = (i/4) b d1
+//   (0, 1)          kb (S0 - S1)       = (i/4) kb [H0(k0 r) - H0(k1 r)]
+//   (1, 0)          -(T0 - T1) / kb    = -(i/4) [a b d0 + (nn - 2 a b) d1 / r] / kb
+//   (1, 1)          -(D0* - D1*)       = (i/4) a d1
 // (T = d^2 G / dn_x dn_y, D* = dG/dn_x; the 1/r^2 parts of T0 and T1 cancel in d1 / r).
-__device__ inline cplx tr_kernel(double k0, double k1, double dx, double dy, double tnx, double tny, double snx,
+__device__ inline cplx tr_kernel(double k0, double k1, double kb, double dx, double dy, double tnx, double tny, double snx,
                                  double sny, int cr, int cc) {
   const double r = sqrt(dx * dx + dy * dy);
   cplx a0, a1, b0, b1;
@@ -120,7 +122,7 @@ __device__ inline cplx tr_kernel(double k0, double k1, double dx, double dy, dou
   hankel01(k1 * r, b0, b1);
   cplx v;
   if (cr == 0 && cc == 1) {
-    v = mkc(a0.x - b0.x, a0.y - b0.y);
+    v = mkc(kb * (a0.x - b0.x), kb * (a0.y - b0.y));
   } else {
     const cplx d1 = mkc(k0 * a1.x - k1 * b1.x, k0 * a1.y - k1 * b1.y);
     const double a = (tnx * dx + tny * dy) / r, b = (snx * dx + sny * dy) / r;
@@ -131,8 +133,8 @@ __device__ inline cplx tr_kernel(double k0, double k1, double dx, double dy, dou
     } else {
       const double k02 = k0 * k0, k12 = k1 * k1;
       const cplx d0 = mkc(k02 * a0.x - k12 * b0.x, k02 * a0.y - k12 * b0.y);
-      const double ab = a * b, c = (tnx * snx + tny * sny - 2.0 * ab) / r;
-      v = mkc(-(ab * d0.x + c * d1.x), -(ab * d0.y + c * d1.y));
+      const double ab = a * b, c = (tnx * snx + tny * sny - 2.0 * ab) / r, ikb = 1.0 / kb;
+      v = mkc(-(ab * d0.x + c * d1.x) * ikb, -(ab * d0.y + c * d1.y) * ikb);
     }
   }
   return mkc(-0.25 * v.y, 0.25 * v.x);  // (i/4) v
@@ -143,7 +145,8 @@ __device__ inline cplx tr_kernel(double k0, double k1, double dx, double dy, dou
 __device__ inline cplx a_entry_tr(const Geo& G, int u, int v) {
   const int i = u >> 1, j = v >> 1, cr = u & 1, cc = v & 1;
   if (i == j) return mkc(cr == cc ? 1.0 : 0.0, 0.0);
-  const cplx K = tr_kernel(G.omega, G.omega1, G.x[i] - G.x[j], G.y[i] - G.y[j], G.nx[i], G.ny[i], G.nx[j], G.ny[j], cr, cc);
+  const cplx K = tr_kernel(G.omega, G.omega1, G.kbar, G.x[i] - G.x[j], G.y[i] - G.y[j], G.nx[i], G.ny[i], G.nx[j], G.ny[j],
+                           cr, cc);
   int m = i - j;
   if (m < 0) m += G.N;
   double R = 1.0;
@@ -154,9 +157,9 @@ __device__ inline cplx a_entry_tr(const Geo& G, int u, int v) {
 
 // The exterior field's rows alone (wavenumber k = omega; neighbour images and the far-field circle
 // see only u+): target unknown t = 2 i + c_r at x_i + (tsx, 0), source unknown s = 2 j + c_c at
-// x_j + (ssx, 0), plain trapezoid weight w_j:
-//   (0, 0) dG/dn_y = (i/4) k H1 b,  (0, 1) G = (i/4) H0,
-//   (1, 0) -T = -(i/4) [k^2 H0 a b + (k H1 / r)(nn - 2 a b)],  (1, 1) -dG/dn_x = (i/4) k H1 a.
+// x_j + (ssx, 0), plain trapezoid weight w_j, the normalization kb of tr_kernel:
+//   (0, 0) dG/dn_y = (i/4) k H1 b,  (0, 1) kb G = (i/4) kb H0,
+//   (1, 0) -T / kb = -(i/4) [k^2 H0 a b + (k H1 / r)(nn - 2 a b)] / kb,  (1, 1) -dG/dn_x = (i/4) k H1 a.
 __device__ inline cplx a_ext_tr(const Geo& G, int t, int s, double tsx, double ssx) {
   const int i = t >> 1, j = s >> 1, cr = t & 1, cc = s & 1;
   const double dx = G.x[i] + tsx - G.x[j] - ssx, dy = G.y[i] - G.y[j];
@@ -166,7 +169,7 @@ __device__ inline cplx a_ext_tr(const Geo& G, int t, int s, double tsx, double s
   hankel01(k * r, h0, h1);
   cplx v;
   if (cr == 0 && cc == 1) {
-    v = h0;
+    v = cscale(h0, G.kbar);
   } else {
     const double a = (G.nx[i] * dx + G.ny[i] * dy) / r, b = (G.nx[j] * dx + G.ny[j] * dy) / r;
     if (cr == 0) {
@@ -174,8 +177,8 @@ __device__ inline cplx a_ext_tr(const Geo& G, int t, int s, double tsx, double s
     } else if (cc == 1) {
       v = cscale(h1, k * a);
     } else {
-      const double ab = a * b, c = k * (G.nx[i] * G.nx[j] + G.ny[i] * G.ny[j] - 2.0 * ab) / r;
-      v = mkc(-(k * k * ab * h0.x + c * h1.x), -(k * k * ab * h0.y + c * h1.y));
+      const double ab = a * b, c = k * (G.nx[i] * G.nx[j] + G.ny[i] * G.ny[j] - 2.0 * ab) / r, ikb = 1.0 / G.kbar;
+      v = mkc(-(k * k * ab * h0.x + c * h1.x) * ikb, -(k * k * ab * h0.y + c * h1.y) * ikb);
     }
   }
   return cscale(mkc(-0.25 * v.y, 0.25 * v.x), G.w[j]);

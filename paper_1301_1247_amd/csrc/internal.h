@@ -20,6 +20,7 @@ struct Geo {
   // row c = 0: value jump, c = 1: minus the normal-derivative jump); omega1 = n omega inside
   int two;
   double omega1;
+  double kbar;  // max(omega, omega1): the single layer carries kbar, the normal-derivative row 1/kbar
   double g[6];           // Kapur-Rokhlin corrections, R_m = 1 + g_m
   // Alpert correction (quad == HBS_QUAD_ALPERT): grid nodes closer than alpa are left out; alpn
   // off-grid nodes q carry the kernel table alpT[i + q N] and Lagrange weights alpL[q alpnl + r] of

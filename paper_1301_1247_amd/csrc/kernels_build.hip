@@ -74,6 +74,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 //                           [dG_q/dnu_l - i kq G_q](x_i, p_l)                                  (x wp)
 //   row0 + (3q + 2) np + l  outgoing field on the circle: c = 0: dG_q/dn_y (p_l, x_i);
 //                           c = 1: G_q(p_l, x_i)                                      (x w_i sqrt(wp))
+// with the operator's normalization: the rows of c = 1 (normal-derivative functionals) divided by
+// kbar, and its outgoing single-layer field multiplied by kbar.
 // The fields that reach a box from outside its proxy circle solve Helmholtz' equation at k0 or k1
 // inside the circle (spanned by the first two groups), and the fields the box sends out are
 // radiating solutions at k0 and k1 fixed by their values on the circle (the third group).
@@ -125,9 +127,10 @@ __global__ __launch_bounds__(NT) void k_proxy_tr(Geo G, const ProxyDesc* __restr
       in2 = mkc(T.x + k * dx_.y, T.y - k * dx_.x);                        // T - i k dG/dn_x
       out = g;
     }
-    col[(3 * q) * d.np + l] = cscale(in1, wp);
-    col[(3 * q + 1) * d.np + l] = cscale(in2, wp);
-    col[(3 * q + 2) * d.np + l] = cscale(out, G.w[gi] * swp);
+    const double fin = c ? wp / G.kbar : wp, fout = c ? G.w[gi] * swp * G.kbar : G.w[gi] * swp;
+    col[(3 * q) * d.np + l] = cscale(in1, fin);
+    col[(3 * q + 1) * d.np + l] = cscale(in2, fin);
+    col[(3 * q + 2) * d.np + l] = cscale(out, fout);
   }
 }
 

@@ -21,8 +21,8 @@ __device__ inline cplx cexpi_c(cplx z) {
 // Y[:, 0:4M] = [B^S_L, B^D_L, B^S_R, B^D_R] with
 //   B^S_W[i,m] = (i/2) wk_m e^{i k_m y_i} e^{i s_m |x_i - x_W|} / s_m,
 //   B^D_W[i,m] = (1/2) sign(x_i - x_W) wk_m e^{i k_m y_i} e^{i s_m |x_i - x_W|}   (Eqs. 2.12-2.13).
-// Transmission problem: row 2i is the value above at node i, row 2i + 1 minus its normal derivative,
-// d/dn e^{i k y + i s |x - x_W|} = i (s sign(x - x_W) n_x + k n_y) e^{...}.
+// Transmission problem: row 2i is the value above at node i, row 2i + 1 minus its normal derivative
+// over Q.kb, d/dn e^{i k y + i s |x - x_W|} = i (s sign(x - x_W) n_x + k n_y) e^{...}.
 __global__ __launch_bounds__(NT) void k_gen_B(QPGeo Q, cplx* __restrict__ Y, int64_t ldy) {
   // rows: every unknown, or the Q.N unknowns idx[] (a skeleton subset)
   const int nrow = (Q.two && !Q.idx) ? 2 * Q.N : Q.N;
@@ -46,8 +46,8 @@ __global__ __launch_bounds__(NT) void k_gen_B(QPGeo Q, cplx* __restrict__ Y, int
     else v = cscale(ex, dx > 0 ? 0.5 : -0.5);
     if (Q.two && (u & 1)) {
       const double sg = dx > 0 ? 1.0 : -1.0;
-      // -i (s sg n_x + k n_y) v
-      const cplx f = cadd(cscale(s, sg * Q.nx[nd]), cscale(k, Q.ny[nd]));
+      // -i (s sg n_x + k n_y) v / kb
+      const cplx f = cscale(cadd(cscale(s, sg * Q.nx[nd]), cscale(k, Q.ny[nd])), 1.0 / Q.kb);
       v = cmul(mkc(f.y, -f.x), v);
     }
     Y[i + (size_t)col * ldy] = v;
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(NT) void k_gen_B(QPGeo Q, cplx* __restrict__ Y, int
 // waves of evanescent orders that the Wood's-anomaly scheme adds as extra right-hand sides
 __global__ __launch_bounds__(NT) void k_gen_inc(QPGeo Q, const double* __restrict__ kx, const double* __restrict__ ky,
                                                 const double* __restrict__ ky_im, int nang, cplx* __restrict__ Y, int64_t ldy) {
-  // transmission problem (Eqs. 5.3-5.4): row 2i = -u^i, row 2i + 1 = +du^i/dn = -i (kx n_x + ky n_y) (-u^i)
+  // transmission problem (Eqs. 5.3-5.4): row 2i = -u^i, row 2i + 1 = +(du^i/dn) / kb = -i (kx n_x + ky n_y) (-u^i) / kb
   const int nrow = Q.two ? 2 * Q.N : Q.N;
   const int64_t total = (int64_t)nrow * nang;
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(NT) void k_gen_inc(QPGeo Q, const double* __restric
     const double amp = ky_im ? -exp(-ky_im[a] * Q.y[i]) : -1.0;
     cplx v = mkc(amp * c, amp * s);
     if (Q.two && (r & 1)) {
-      const double f = kx[a] * Q.nx[i] + ky[a] * Q.ny[i];
+      const double f = (kx[a] * Q.nx[i] + ky[a] * Q.ny[i]) / Q.kb;
       v = mkc(f * v.y, -f * v.x);
     }
     Y[r + (size_t)a * ldy] = v;
@@ -82,8 +82,8 @@ __global__ __launch_bounds__(NT) void k_gen_inc(QPGeo Q, const double* __restric
 //   value = [E (-sigma n_x + (k/s) n_y) + omega E / s] w_j
 //   deriv = [i E (s n_x - k sigma n_y) - i omega E sigma] w_j          (Sec. 2.2, Eq. 2.17)
 // Transmission problem: column 2j carries the double layer alone (value E (-sigma n_x + (k/s) n_y),
-// deriv i E (s n_x - k sigma n_y)) and column 2j + 1 the single layer alone (value i E / s, deriv E
-// sigma), both times w_j: the Dirichlet column is their combination D - i omega S.
+// deriv i E (s n_x - k sigma n_y)) and column 2j + 1 the single layer times Q.kb (value i kb E / s,
+// deriv kb E sigma), both times w_j: the Dirichlet column is their combination D - i omega S.
 __global__ __launch_bounds__(NT) void k_gen_C(QPGeo Q, int wall, double shift, cplx* __restrict__ C) {
   const int ncol = (Q.two && !Q.idx) ? 2 * Q.N : Q.N;
   const int64_t total = (int64_t)ncol * Q.M;
@@ -104,8 +104,8 @@ __global__ __launch_bounds__(NT) void k_gen_C(QPGeo Q, int wall, double shift, c
     const double nx = Q.nx[nd], ny = Q.ny[nd], w = Q.w[nd];
     if (Q.two && (uj & 1)) {
       const cplx ve = cmul(mkc(0.0, 1.0), cmul(E, is));
-      C[m + (size_t)j * ldc] = cscale(ve, w);
-      C[Q.M + m + (size_t)j * ldc] = cscale(E, sg * w);
+      C[m + (size_t)j * ldc] = cscale(ve, w * Q.kb);
+      C[Q.M + m + (size_t)j * ldc] = cscale(E, sg * w * Q.kb);
       continue;
     }
     const double om = Q.two ? 0.0 : Q.omega;  // no single-layer part in a transmission tau column
@@ -380,8 +380,8 @@ __global__ __launch_bounds__(NT) void k_bragg(QPGeo Q, const double* __restrict_
     sincos(-(kn_x * Q.x[j] + kn * Q.y[j]), &s1, &c1);
     sincos(-(kn_x * Q.x[j] - kn * Q.y[j]), &s2, &c2);
     if (Q.two) {
-      // tau (double layer) with the factors above less the -i omega; sigma (single layer) with 1
-      const cplx wt = cscale(et[2 * j], Q.w[j]), ws = cscale(et[2 * j + 1], Q.w[j]);
+      // tau (double layer) with the factors above less the -i omega; sigma (single layer) with kb
+      const cplx wt = cscale(et[2 * j], Q.w[j]), ws = cscale(et[2 * j + 1], Q.w[j] * Q.kb);
       const cplx fu = cadd(cmul(wt, mkc(0.0, -(kn_x * Q.nx[j] + kn * Q.ny[j]))), ws);
       const cplx fd = cadd(cmul(wt, mkc(0.0, -kn_x * Q.nx[j] + kn * Q.ny[j])), ws);
       su = cadd(su, cmul(mkc(c1, s1), fu));
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(NT) void k_bragg(QPGeo Q, const double* __restrict_
 // q < nq.  E (2 nq x N, col-major): row q = w_j e^{-i(kap_q x_j + k_q y_j)} [-i(kap_q n_x + k_q n_y) - i omega],
 // row nq + q = w_j e^{-i(kap_q x_j - k_q y_j)} [i(-kap_q n_x + k_q n_y) - i omega]; E eta gives the sums of k_bragg.
 // Transmission problem: 2N columns, column 2j (tau) without the -i omega term, column 2j + 1
-// (sigma) with the factor 1.
+// (sigma) with the factor Q.kb.
 __global__ __launch_bounds__(NT) void k_bragg_basis(QPGeo Q, double kref, int qlo, int nq, cplx* __restrict__ E) {
   const int64_t rows = 2 * (int64_t)nq;
   const int64_t total = rows * (Q.two ? 2 * Q.N : Q.N);
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(NT) void k_bragg_basis(QPGeo Q, double kref, int ql
     double sn, cs;
     sincos(-(kx * Q.x[j] + ky * Q.y[j]), &sn, &cs);
     const double om = Q.two ? 0.0 : Q.omega;
-    const cplx f = (Q.two && (jc & 1)) ? mkc(1.0, 0.0)
+    const cplx f = (Q.two && (jc & 1)) ? mkc(Q.kb, 0.0)
                    : up ? mkc(0.0, -(kx * Q.nx[j] + kn * Q.ny[j]) - om) : mkc(0.0, (-kx * Q.nx[j] + kn * Q.ny[j]) - om);
     E[e] = cscale(cmul(mkc(cs, sn), f), Q.w[j]);
   }

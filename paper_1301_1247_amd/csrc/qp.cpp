@@ -370,6 +370,7 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
 
   QPGeo Q{};
   Q.two = h->nc == 2;
+  Q.kb = h->geo.kbar;
   Q.x = h->geo.x; Q.y = h->geo.y; Q.nx = h->geo.nx; Q.ny = h->geo.ny; Q.w = h->geo.w;
   Q.k = dcont; Q.s = dcont + M; Q.wk = dcont + 2 * M;
   Q.N = (int)h->N; Q.M = M; Q.omega = om; Q.period = period; Q.shift = 0.0;

@@ -12,6 +12,7 @@ struct QPGeo {
   // transmission problem (Sec. 5): vectors over the obstacle have 2N entries, node by node [tau; sigma]
   // (columns) or [value; minus normal derivative] (rows); the walls see the exterior field only
   int two;
+  double kb;  // the transmission normalization max(omega, n omega): sigma columns x kb, derivative rows / kb
 };
 
 // An order of the Wood's-anomaly radiation rows: kappa_m = kappa + 2 pi m / d and k_m (complex).

@@ -93,11 +93,12 @@ def test_point_sources_reproduced(gpu_lib):
 
     f = G(OM, disc.x, zi) - G(k1, disc.x, zo)
     g = dG(OM, disc.x, disc.nrm, zi) - dG(k1, disc.x, disc.nrm, zo)
-    eta = h.apply(tr.rhs_from_jumps(f, g), refine=2)
+    kb = tr.kbar(OM, IDX)
+    eta = h.apply(tr.rhs_from_jumps(f, g, kb), refine=2)
     te = np.array([[1.8, -1.2], [-2.5, 0.3], [0.0, 1.9]])
     ti = np.array([[0.2, -0.1], [-0.3, 0.25], [0.4, 0.4]])
-    assert np.abs(tr.potential(disc, OM, eta, te) - G(OM, te, zi)).max() < 2e-8
-    assert np.abs(tr.potential(disc, k1, eta, ti) - G(k1, ti, zo)).max() < 2e-8
+    assert np.abs(tr.potential(disc, OM, kb, eta, te) - G(OM, te, zi)).max() < 2e-8
+    assert np.abs(tr.potential(disc, k1, kb, eta, ti) - G(k1, ti, zo)).max() < 2e-8
 
 
 @pytest.mark.parametrize("compress", ["proxy", "exact"])

@@ -1,6 +1,7 @@
 """Pins of the transmission oracle (Sec. 5) against what the mathematics fixes, not against itself:
 
-* the four difference kernels against central differences of G_k = (i/4) H0(k r);
+* the four difference kernels (with the normalization kb = max(omega, n omega)) and the exterior
+  rows against central differences of G_k = (i/4) H0(k r);
 * an exact solution of the isolated matching problem: a radiating point source at wavenumber
   omega from inside Omega and a regular field at n omega from a source outside, whose jumps are
   the data; the represented fields reproduce both sources at the discretization's order (this pins
@@ -45,8 +46,13 @@ def test_kernels_match_finite_differences():
              - g(x - hd * nx, y + hd * ny) + g(x - hd * nx, y - hd * ny)) / (4 * hd * hd)
         want.append((dgy, g(x, y), T, dgx))
     (d0, s0, t0, x0), (d1, s1, t1, x1) = want
+    kb = IDX * OM
     got = tr.kernels(OM, IDX * OM, x[None], nx[None], y[None], ny[None])
-    for a, b in zip(got, (d0 - d1, s0 - s1, -(t0 - t1), -(x0 - x1))):
+    for a, b in zip(got, (d0 - d1, kb * (s0 - s1), -(t0 - t1) / kb, -(x0 - x1))):
+        assert abs(a[0, 0] - b) < 1e-6 * max(1.0, abs(b))
+    # the exterior rows alone (images and walls)
+    got = tr.exterior_kernels(OM, kb, x[None], nx[None], y[None], ny[None])
+    for a, b in zip(got, (d0, kb * s0, -t0 / kb, -x0)):
         assert abs(a[0, 0] - b) < 1e-6 * max(1.0, abs(b))
 
 
@@ -66,11 +72,12 @@ def _point_source_error(N):
 
     f = G(OM, d.x, zi) - G(k1, d.x, zo)
     g = dG(OM, d.x, d.nrm, zi) - dG(k1, d.x, d.nrm, zo)
-    eta = tr.solve_isolated(d, OM, IDX, tr.rhs_from_jumps(f, g))
+    kb = tr.kbar(OM, IDX)
+    eta = tr.solve_isolated(d, OM, IDX, tr.rhs_from_jumps(f, g, kb))
     te = np.array([[1.8, -1.2], [-2.5, 0.3], [0.0, 1.9]])
     ti = np.array([[0.2, -0.1], [-0.3, 0.25], [0.4, 0.4]])
-    ee = np.abs(tr.potential(d, OM, eta, te) - G(OM, te, zi)).max()
-    ei = np.abs(tr.potential(d, k1, eta, ti) - G(k1, ti, zo)).max()
+    ee = np.abs(tr.potential(d, OM, kb, eta, te) - G(OM, te, zi)).max()
+    ei = np.abs(tr.potential(d, k1, kb, eta, ti) - G(k1, ti, zo)).max()
     return max(ee, ei)
 
 
@@ -113,7 +120,8 @@ def test_bragg_sampled_equals_lattice(star2pi):
     for q, th in enumerate(ths):
         al = periodic.bloch_phase(OM, 2 * math.pi, th)
         _, _, c, dd = r0["bragg"][q]
-        _, _, cs, ds = tr.bragg_sampled(d, OM, 2 * math.pi, al, r0["contour"], th, r0["eta"][:, q], r0["xi"][:, q], r0["y0"])
+        _, _, cs, ds = tr.bragg_sampled(d, OM, IDX, 2 * math.pi, al, r0["contour"], th, r0["eta"][:, q], r0["xi"][:, q],
+                                        r0["y0"])
         assert np.abs(cs - c).max() < 1e-12 and np.abs(ds - dd).max() < 1e-12
 
 
@@ -121,7 +129,7 @@ def test_rows_agree_with_matrices():
     d = nystrom.Discretization(qpinputs.star(1.0, 0.3, 5), 60)
     rows = np.array([0, 1, 7, 64, 119, 118])
     assert np.array_equal(tr.matrix_rows(d, OM, IDX, rows), tr.matrix(d, OM, IDX)[rows])
-    assert np.array_equal(tr.neighbour_rows(d, OM, 2.5, rows), tr.neighbour_matrix(d, OM, 2.5)[rows])
+    assert np.array_equal(tr.neighbour_rows(d, OM, IDX, 2.5, rows), tr.neighbour_matrix(d, OM, IDX, 2.5)[rows])
 
 
 def test_planted_mistakes_break_the_pins(monkeypatch):
