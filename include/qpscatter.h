@@ -127,9 +127,11 @@ typedef struct {
                                kb brings the four blocks to one size, which the decompositions'
                                relative tolerance needs.  Every N-sized vector of the other calls
                                (hbs_apply's rhs, qp_solve's eta) then has 2N rows, and leaf_size counts
-                               unknowns.  Needs HBS_QUAD_KR6, far_radius = 0, image_period = 0 and
-                               rank_predictor = 0; qp_solve takes P = 0 with the wall blocks
-                               uncompressed, and refuses angles near a Wood's anomaly (HBS_E_WOOD).
+                               unknowns.  Needs HBS_QUAD_KR6 and rank_predictor = 0.  qp_solve takes
+                               P = 0 or 1 and refuses angles near a Wood's anomaly (HBS_E_WOOD).  It
+                               compresses the wall blocks only when compress_walls = 1.  The wall blocks
+                               through the skeletons, and the P = 1 neighbour terms, carry the
+                               decompositions' error about 3e3 times over: use tol 1e-14 with them.
                                0 = the Dirichlet problem */
 } hbs_opts;
 
@@ -151,8 +153,9 @@ typedef struct {
                                tree, valid when the handle's far_radius circle excludes the walls
                                (far_radius <= d/2 - |c_x|, c = centre of the nodes' bounding box).
                                Then A^{-1} is applied to root-size + q columns instead of 4M + q and
-                               no N-sized Schur product is formed.  0 = when valid, 1 = required
-                               (HBS_E_INVALID_ARG otherwise), -1 = never */
+                               no N-sized Schur product is formed.  0 = when valid (the Dirichlet
+                               problem; never for the transmission problem, see hbs_opts.index),
+                               1 = required (HBS_E_INVALID_ARG otherwise), -1 = never */
   int32_t wood;             /* angles within wood_min_kn of a Wood's anomaly (Sec. 2.4, second
                                improvement): 0 = solve them on the Sommerfeld contour displaced to cross
                                the real axis at wood_shift, with one added Rayleigh-Bloch wave and one

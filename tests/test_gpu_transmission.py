@@ -162,13 +162,16 @@ def test_compressed_walls_match_oracle(gpu_lib, star_tr, P, defer):
     nodes, w, nrm, _ = discretize(c, N)
     h = gpu_lib.Handle(nodes, w, nrm, OM, 1e-14, index=IDX, far_radius=2.0, defer_root=defer)
     ths = np.array([-math.pi / 5, -1.2])
-    r = h.qp_solve_many(D, ths, P=P)
+    r0 = h.qp_solve_many(D, ths, P=P)
+    assert h.stats().walls_compressed == 0  # dense unless asked for (the default for this operator)
+    r = h.qp_solve_many(D, ths, P=P, compress_walls=1)
     assert h.stats().walls_compressed == 1
     ref = tr.solve_qp(disc, N, OM, IDX, D, ths, P=P, A0=A)
     for a in range(len(ths)):
-        assert _rel(r["eta"][:, a], ref["eta"][:, a]) < 1e-10
-        assert _rel(r["xi"][:, a], ref["xi"][:, a]) < 1e-10
-        assert abs(r["flux"][a] - ref["flux"][a]) < 1e-10
+        for rr in (r0, r):
+            assert _rel(rr["eta"][:, a], ref["eta"][:, a]) < 1e-10
+            assert _rel(rr["xi"][:, a], ref["xi"][:, a]) < 1e-10
+            assert abs(rr["flux"][a] - ref["flux"][a]) < 1e-10
 
 
 def test_d1_grating_with_near_images_matches_oracle(gpu_lib):
@@ -246,3 +249,20 @@ def test_fp32_preconditioner_refines_to_fp64(gpu_lib, star_tr):
     Xe = sla.lu_solve(lu, B)
     assert 1e-9 < _rel(h.apply(B), Xe) < 1e-3
     assert _rel(h.apply(B, refine=5), Xe) < 1e-10
+
+
+def test_benchmark_obstacle_full_size(gpu_lib):
+    """The benchmark obstacle (40 harmonics, omega = 60) as a transmission problem with index 1.5:
+    k = 90 inside, N = 1e5 nodes (2e5 unknowns), uncompressed walls; sampled exact residual rows
+    and the energy balance of every angle below 1e-10."""
+    import torch
+    from oracle import checks
+    wl = qpinputs.workload("wavy40")
+    nodes, w, nrm, _ = discretize(wl.curve, wl.N)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    h = gpu_lib.Handle(t(nodes), t(w), t(nrm), wl.omega, 1e-13, index=1.5, device=True)
+    ths = wl.thetas[::25]
+    r = h.qp_solve_many(wl.period, t(ths), compress_walls=-1)
+    v = checks.bordered_residual_tr(wl.curve, wl.N, wl.omega, 1.5, wl.period, ths, r["eta"].T.cpu().numpy(),
+                                    r["xi"].T.cpu().numpy(), r["flux"], n_rows=12, n_ang=4)
+    assert v["sampled_rel_residual"] < 1e-10 and v["flux_err_max"] < 1e-10, v
