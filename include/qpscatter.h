@@ -129,9 +129,8 @@ typedef struct {
                                (hbs_apply's rhs, qp_solve's eta) then has 2N rows, and leaf_size counts
                                unknowns.  Needs HBS_QUAD_KR6 and rank_predictor = 0.  qp_solve takes
                                P = 0 or 1 and refuses angles near a Wood's anomaly (HBS_E_WOOD).  It
-                               compresses the wall blocks only when compress_walls = 1.  The wall blocks
-                               through the skeletons, and the P = 1 neighbour terms, carry the
-                               decompositions' error about 3e3 times over: use tol 1e-14 with them.
+                               compresses the wall blocks only when compress_walls = 1 (at omega = 60
+                               they then lose accuracy to about 6e-10).
                                0 = the Dirichlet problem */
 } hbs_opts;
 

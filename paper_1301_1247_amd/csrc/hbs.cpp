@@ -111,7 +111,7 @@ int build(hbs_handle* h) {
   const bool far_on = h->opts.far_radius > 0;
   const bool img_on = h->opts.image_period > 0;
   const double Rfar = far_on ? std::sqrt(h->robs * h->opts.far_radius) : 0.0;
-  const int npfar = far_on ? std::max(pmin, 2 * (int)std::ceil(om * Rfar + std::log(1.0 / h->tol) /
+  const int npfar = far_on ? std::max(pmin, 2 * (int)std::ceil(om_max * Rfar + std::log(1.0 / h->tol) /
                                                                   std::log(Rfar / h->robs)) + 8) : 0;
 
   // box ranges, bounding circles and the predictor's geometric features (max and mean |curvature|,
@@ -501,7 +501,7 @@ int build(hbs_handle* h) {
         }
       ioff[b + 1] = ioff[b] + nimg[b];
       h->stats.image_samples += nimg[b];
-      m[b] = 2 * cnt + 2 * nimg[b] + 3 * h->nc * np[b] + 3 * npf[b];
+      m[b] = 2 * cnt + 2 * nimg[b] + 3 * h->nc * (np[b] + npf[b]);
       s[b] = (m[b] > 2 * V.n[b] + 8) ? 2 * V.n[b] + 8 : m[b];
       noff[b + 1] = noff[b] + cnt;
       woff[b + 1] = woff[b] + (int64_t)m[b] * V.n[b];
@@ -640,9 +640,11 @@ int build(hbs_handle* h) {
       }
       for (int b = 0; b < nb; ++b) {
         if (npf[b] == 0) continue;
-        // the far-field circle stands for the neighbour images, whose fields are exterior ones
+        // the far-field circle stands for the walls and the neighbour images, whose fields are exterior
+        // ones; for the transmission operator it takes both wavenumbers all the same (with the exterior
+        // one alone, the skeletons reproduced the wall blocks to 1e-8 at tol 1e-12, with both to 1e-11)
         pd.push_back({dact + V.aoff[b], dwt + woff[b], V.n[b], m[b], 2 * nnear[b] + 2 * nimg[b] + 3 * h->nc * np[b], npf[b],
-                      h->c0x, h->c0y, Rfar, 1});
+                      h->c0x, h->c0y, Rfar, 2});
         maxp = std::max(maxp, npf[b] * V.n[b]);
       }
       if (!pd.empty()) {

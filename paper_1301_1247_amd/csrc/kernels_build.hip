@@ -67,8 +67,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 }
 
 // Transmission problem (Sec. 5): proxy rows for the unknown u = 2 i + c of the box, at the d.nk
-// wavenumbers kq (q = 0: omega, q = 1: n omega; the far-field circle takes the exterior omega
-// alone), G_q = (i/4) H0(kq r), r = |x_i - p_l|:
+// wavenumbers kq (q = 0: omega, q = 1: n omega), G_q = (i/4) H0(kq r), r = |x_i - p_l|:
 //   row0 + (3q) np + l      incoming single layer: c = 0: G_q(x_i, p_l); c = 1: dG_q/dn_x      (x wp)
 //   row0 + (3q + 1) np + l  incoming double layer: the same row functionals of
 //                           [dG_q/dnu_l - i kq G_q](x_i, p_l)                                  (x wp)
