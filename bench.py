@@ -306,7 +306,7 @@ def grating(B, torch, steps=3, warmup=1):
 def grating_tr(B, torch, steps=3, warmup=1):
     """The transmission case of Sec. 6.1: the same d = 1 star grating with refractive index 1.5 inside
     the obstacle (Sec. 5), N = 2^17 nodes = 2^18 interlaced unknowns, P = 1 with the images' near points
-    as explicit columns, contour spacing 0.2, tol 1e-12.  Build and one-angle solve timed separately;
+    as explicit columns, contour spacing 0.2, tol 1e-13.  Build and one-angle solve timed separately;
     checked by sampled exact rows of the bordered residual and by the energy balance."""
     import numpy as np
     import qpinputs
@@ -319,7 +319,7 @@ def grating_tr(B, torch, steps=3, warmup=1):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     tn, tw, tr, tth = t(nodes), t(w), t(nrm), t(wl.thetas)
     kw = dict(device=True, leaf_size=wl.leaf_size, far_radius=1.0, image_period=wl.period, index=wl.index)
-    hc, tol = 0.2, 1e-12
+    hc, tol = 0.2, 1e-13
     tb, ts = [], []
     for i in range(warmup + steps):
         torch.cuda.synchronize()
@@ -342,7 +342,7 @@ def grating_tr(B, torch, steps=3, warmup=1):
     ok = v["sampled_rel_residual"] < 1e-10 and v["flux_err_max"] < 1e-10
     build, solve = float(np.median(tb)), float(np.median(ts))
     return {"workload": "transmission, index 1.5: star r=0.35+0.105cos3t, d=1, omega=10, theta=-pi/5, N=2^17 "
-                        "(2^18 unknowns), P=1, tol 1e-12, contour spacing 0.2",
+                        "(2^18 unknowns), P=1, tol 1e-13, contour spacing 0.2",
             "build_seconds": build, "solve_seconds": solve, "angles_per_s": 1.0 / solve if ok else None,
             "angles_per_s_incl_build": 1.0 / (build + solve) if ok else None,
             "root_size": st.root_size, "levels": st.levels, "max_rank": st.max_rank,

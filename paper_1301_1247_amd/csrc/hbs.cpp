@@ -503,6 +503,9 @@ int build(hbs_handle* h) {
       h->stats.image_samples += nimg[b];
       m[b] = 2 * cnt + 2 * nimg[b] + 3 * h->nc * (np[b] + npf[b]);
       s[b] = (m[b] > 2 * V.n[b] + 8) ? 2 * V.n[b] + 8 : m[b];
+      // the transmission operator (no rank model): n + 16 sketch rows; its ranks stay below 0.8 n
+      // on every level measured, so the rows exceed the rank by at least 0.2 n + 16
+      if (h->nc == 2) s[b] = std::min(s[b], V.n[b] + 16);
       noff[b + 1] = noff[b] + cnt;
       woff[b + 1] = woff[b] + (int64_t)m[b] * V.n[b];
     }

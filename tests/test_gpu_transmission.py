@@ -202,7 +202,7 @@ def test_d1_grating_full_size(gpu_lib):
     from oracle import checks
     wl = qpinputs.workload("star_d1_tr")
     nodes, w, nrm, _ = discretize(wl.curve, wl.N)
-    h = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-12, index=wl.index, far_radius=1.0, image_period=wl.period,
+    h = gpu_lib.Handle(nodes, w, nrm, wl.omega, 1e-13, index=wl.index, far_radius=1.0, image_period=wl.period,
                        leaf_size=wl.leaf_size)
     r = h.qp_solve_many(wl.period, wl.thetas, P=1, h=0.2)
     v = checks.bordered_residual_tr(wl.curve, wl.N, wl.omega, wl.index, wl.period, wl.thetas, r["eta"], r["xi"],
