@@ -129,8 +129,9 @@ typedef struct {
                                (hbs_apply's rhs, qp_solve's eta) then has 2N rows, and leaf_size counts
                                unknowns.  Needs HBS_QUAD_KR6 and rank_predictor = 0.  qp_solve takes
                                P = 0 or 1 and refuses angles near a Wood's anomaly (HBS_E_WOOD).  It
-                               compresses the wall blocks only when compress_walls = 1 (at omega = 60
-                               they then lose accuracy to about 6e-10).
+                               compresses the wall blocks only when compress_walls = 1 or 2 (at
+                               omega = 60 they then lose accuracy to about 6e-10 with 1; 2 refines
+                               that away).
                                0 = the Dirichlet problem */
 } hbs_opts;
 
@@ -154,7 +155,12 @@ typedef struct {
                                Then A^{-1} is applied to root-size + q columns instead of 4M + q and
                                no N-sized Schur product is formed.  0 = when valid (the Dirichlet
                                problem; never for the transmission problem, see hbs_opts.index),
-                               1 = required (HBS_E_INVALID_ARG otherwise), -1 = never */
+                               1 = required (HBS_E_INVALID_ARG otherwise), -1 = never,
+                               2 = as 1 for the solve, while the refinement's residual takes B and C
+                               uncompressed (formed in full: 16 (4M N + 4M N) bytes more device
+                               memory), so that its corrections remove what the skeletons leave out
+                               of the wall blocks; the displaced-contour solves of Wood's-anomaly
+                               angles take 1 */
   int32_t wood;             /* angles within wood_min_kn of a Wood's anomaly (Sec. 2.4, second
                                improvement): 0 = solve them on the Sommerfeld contour displaced to cross
                                the real axis at wood_shift, with one added Rayleigh-Bloch wave and one
@@ -183,7 +189,8 @@ typedef struct {
   int32_t refine_iters;     /* refinement iterations of the last qp_solve */
   double refine_residual;   /* relative residual after the last qp_solve */
   int32_t contour_M;        /* contour size of the last qp_solve */
-  int32_t walls_compressed; /* 1 if the last qp_solve took B and C through the root skeletons */
+  int32_t walls_compressed; /* 1 if the last qp_solve took B and C through the root skeletons, 2 if
+                               its refinement also took them uncompressed (compress_walls = 2) */
   int32_t rank_fallbacks;   /* boxes whose predicted sketch was too short (rank_predictor) */
   int64_t sketch_bytes_max; /* largest per-level sketch buffer of the build */
   double cpqr_work;         /* sum over boxes of sketch rows x n x k (CPQR cost measure) */

@@ -148,6 +148,10 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
   // the transmission operator takes its wall blocks through the skeletons only on request: there they
   // carry the decompositions' error about 3e3 times over (against about 10 for the Dirichlet operator)
   const bool cw = (h->nc == 1 ? o->compress_walls >= 0 : o->compress_walls > 0) && far_ok;
+  // compress_walls = 2: the solve as with 1, the refinement's residual with the uncompressed wall
+  // blocks (formed in full), so that the corrections remove the error the skeletons give B and C
+  // (the displaced-contour columns take 1)
+  const bool xw = cw && o->compress_walls == 2 && !cols && o->refine_max_iter >= 0;
   QPPlan pl;
   CR(qp_plan(h, period, o, &pl));
   const int M = pl.M, M2 = 2 * M, M4 = 4 * M;
@@ -278,9 +282,11 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
       cw ? sizeof(cplx) * ((size_t)nuu * (M4 + W + Wy + 2 * nang) + (size_t)nr * Wy * 2 + (size_t)N * nang) : 0,
                                                      // 20 B_J, X_c, U^T X, t1, t2, R_{+-1} X, U t
       cw ? sizeof(cplx) * ((size_t)ng * (2 * (size_t)nuu * M2 + 3 * (size_t)nuu * nuu) + 3 * (size_t)M2 * nuu +
-                           (size_t)M2 * nang + 2 * (size_t)nuu * nang) : 0};
+                           (size_t)M2 * nang + 2 * (size_t)nuu * nang) : 0,
                                                      // 21 Woodbury form of S^{-1}: B_J(alpha), Q^{-1} C~ H~, K2, H~,
                                                      //    scratch; C~_J H~; Q^{-1} r; two nu x nang
+      xw ? sizeof(cplx) * ((size_t)N * M4 + (size_t)M2 * N * 2) : 0};
+                                                     // 22 the uncompressed [B_L | B_R], C1, C2 of the residual
   std::vector<size_t> off(sizes.size() + 1, 0);
   for (size_t i = 0; i < sizes.size(); ++i) off[i + 1] = off[i] + ((sizes[i] + 255) / 256) * 256;
   CK(h->scratch.reserve(off.back()));
@@ -356,6 +362,9 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
   cplx* yq = C2H + (size_t)M2 * nuu;        // 2M x nang
   cplx* zq = yq + (size_t)M2 * nang;        // nu x nang
   cplx* zq2 = zq + (size_t)nuu * nang;      // nu x nang
+  cplx* Yx = xw ? (cplx*)(base + off[22]) : nullptr;  // N x 4M: [B_L | B_R]
+  cplx* C1x = xw ? Yx + (size_t)N * M4 : nullptr;      // 2M x N
+  cplx* C2x = xw ? C1x + (size_t)M2 * N : nullptr;     // 2M x N
 
   std::vector<cplx> consts = {onec, minus1c};
   CK(hipMemcpyAsync(dcont, cont.data(), sizeof(cplx) * 3 * M, hipMemcpyHostToDevice, st));
@@ -524,6 +533,11 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
       CK(launch_gen_B(QJ, BJ, nu, st));
       CK(launch_gen_C(QJ, 0, P * period, C1, st));
       CK(launch_gen_C(QJ, 1, -P * period, C2, st));
+      if (xw) {
+        CK(launch_gen_B(Q, Yx, N, st));
+        CK(launch_gen_C(Q, 0, P * period, C1x, st));
+        CK(launch_gen_C(Q, 1, -P * period, C2x, st));
+      }
     } else {
       CK(launch_gen_B(Q, Y, N, st));
       CK(launch_gen_C(Q, 0, P * period, C1, st));
@@ -855,7 +869,7 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
   int iters = 0;
   for (int it = 0; it <= maxit; ++it) {
     // R1 = b - A~ eta - B(alpha) xi ;  R2 = -C~(alpha) eta - Q(alpha) xi
-    if (cw) {
+    if (cw && !xw) {
       // every U-term enters at the root of one forward apply: F = A eta + U (B_J v [+ R(alpha) eta]),
       // and the same apply's upward result at the root is U^T eta (C eta = C_J U^T eta)
       CR(gemm({gd(BJ, nu, 0, stk, M4, t1, nu, nu, nang, M4, onec, zero)}));
@@ -878,8 +892,13 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
       }
       CK(launch_axpby(N, nang, onec, Y + (size_t)ycolB * N, N, zero, R1, N, st));
       CK(launch_axpby(N, nang, minus1c, F, N, onec, R1, N, st));
-      CR(sub_Bv(stk, R1));
-      CR(C_v(eta, T1, T2));
+      if (xw) {
+        CR(gemm({gd(Yx, N, 0, stk, M4, R1, N, N, nang, M4, minus1c, onec)}));
+        CR(gemm({gd(C1x, M2, 0, eta, N, T1, M2, M2, nang, N, onec, zero), gd(C2x, M2, 0, eta, N, T2, M2, M2, nang, N, onec, zero)}));
+      } else {
+        CR(sub_Bv(stk, R1));
+        CR(C_v(eta, T1, T2));
+      }
     }
     CK(launch_resid2(Q, nang, d_al, d_c1, d_c2, T1, T2, xi, R2, st));
     CK(launch_colnorm2(N, nang, R1, N, nrm, st));
@@ -932,7 +951,7 @@ int qp_solve_core(hbs_handle* h, double period, const std::vector<double>& th, c
   h->stats.refine_iters = iters;
   h->stats.refine_residual = relres;
   h->stats.contour_M = M;
-  h->stats.walls_compressed = cw ? 1 : 0;
+  h->stats.walls_compressed = cw ? (xw ? 2 : 1) : 0;
   if (maxit > 0 && relres >= rtol && relres > 1e-8) {
     set_error("qp_solve: refinement stalled at relative residual " + std::to_string(relres));
     return HBS_E_NOT_CONVERGED;

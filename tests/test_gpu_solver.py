@@ -254,6 +254,11 @@ def test_qp_wavy_kr6_parity_compressed_walls(gpu_lib, wavy_small, P):
     res_u = h.qp_solve_many(d, thetas, P=P, compress_walls=-1)
     assert h.stats().walls_compressed == 0
     assert _rel(res_u["eta"], res["eta"]) < 1e-10
+    # compressed solve refined against the uncompressed wall blocks
+    res_x = h.qp_solve_many(d, thetas, P=P, compress_walls=2)
+    assert h.stats().walls_compressed == 2
+    _check_qp(res_x, ref, len(thetas))
+    assert _rel(res_x["eta"], res_u["eta"]) < 1e-10
 
 
 @pytest.mark.parametrize("P", [0, 1])

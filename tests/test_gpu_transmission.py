@@ -157,7 +157,8 @@ def test_compressed_walls_match_oracle(gpu_lib, star_tr, P, defer):
     the root inversion deferred into the Woodbury batch, and with the P = 1 images of Sec. 2.4 (exterior
     field only) in the Woodbury form of Eq. 3.2.  The wall blocks interpolated from the skeleton rows
     carry the decompositions' error unrefined (the refinement runs on the compressed bordered system):
-    this pins the far-field circle's rows at both wavenumbers."""
+    this pins the far-field circle's rows at both wavenumbers.  compress_walls = 2 refines against the
+    uncompressed wall blocks instead."""
     c, N, disc, A, _ = star_tr
     nodes, w, nrm, _ = discretize(c, N)
     h = gpu_lib.Handle(nodes, w, nrm, OM, 1e-12, index=IDX, far_radius=2.0, defer_root=defer)
@@ -166,9 +167,11 @@ def test_compressed_walls_match_oracle(gpu_lib, star_tr, P, defer):
     assert h.stats().walls_compressed == 0  # dense unless asked for (the default for this operator)
     r = h.qp_solve_many(D, ths, P=P, compress_walls=1)
     assert h.stats().walls_compressed == 1
+    r2 = h.qp_solve_many(D, ths, P=P, compress_walls=2)
+    assert h.stats().walls_compressed == 2
     ref = tr.solve_qp(disc, N, OM, IDX, D, ths, P=P, A0=A)
     for a in range(len(ths)):
-        for rr in (r0, r):
+        for rr in (r0, r, r2):
             assert _rel(rr["eta"][:, a], ref["eta"][:, a]) < 1e-10
             assert _rel(rr["xi"][:, a], ref["xi"][:, a]) < 1e-10
             assert abs(rr["flux"][a] - ref["flux"][a]) < 1e-10
@@ -250,18 +253,29 @@ def test_fp32_preconditioner_refines_to_fp64(gpu_lib, star_tr):
     assert _rel(h.apply(B, refine=5), Xe) < 1e-10
 
 
-def test_benchmark_obstacle_full_size(gpu_lib):
+@pytest.mark.parametrize("walls", ["dense", "refined"])
+def test_benchmark_obstacle_full_size(gpu_lib, walls):
     """The benchmark obstacle (40 harmonics, omega = 60) as a transmission problem with index 1.5:
-    k = 90 inside, N = 1e5 nodes (2e5 unknowns), uncompressed walls; sampled exact residual rows
-    and the energy balance of every angle below 1e-10."""
+    k = 90 inside, N = 1e5 nodes (2e5 unknowns); sampled exact residual rows and the energy balance
+    of every angle below 1e-10.  The walls go uncompressed, or through the skeletons of a handle
+    with the far-field circle inside the walls and refined against the uncompressed wall blocks
+    (compress_walls = 2; with 1 they stop near 6e-10 at this frequency)."""
     import torch
     from oracle import checks
     wl = qpinputs.workload("wavy40")
     nodes, w, nrm, _ = discretize(wl.curve, wl.N)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
-    h = gpu_lib.Handle(t(nodes), t(w), t(nrm), wl.omega, 1e-13, index=1.5, device=True)
+    kw = dict(index=1.5, device=True)
+    if walls == "refined":
+        c0 = 0.5 * (nodes.max(0) + nodes.min(0))
+        kw["far_radius"] = 0.9 * (0.5 * wl.period - abs(c0[0]))
+    h = gpu_lib.Handle(t(nodes), t(w), t(nrm), wl.omega, 1e-13, **kw)
     ths = wl.thetas[::25]
-    r = h.qp_solve_many(wl.period, t(ths), compress_walls=-1)
+    r = h.qp_solve_many(wl.period, t(ths), compress_walls=2 if walls == "refined" else -1)
+    st = h.stats()
+    assert st.walls_compressed == (2 if walls == "refined" else 0)
+    if walls == "refined":
+        assert st.refine_iters >= 1
     v = checks.bordered_residual_tr(wl.curve, wl.N, wl.omega, 1.5, wl.period, ths, r["eta"].T.cpu().numpy(),
                                     r["xi"].T.cpu().numpy(), r["flux"], n_rows=12, n_ang=4)
     assert v["sampled_rel_residual"] < 1e-10 and v["flux_err_max"] < 1e-10, v
