@@ -406,6 +406,10 @@ def main():
               "Bloch phases over GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
+    # the library's device-memory cache: each step builds a new handle, and the transmission legs'
+    # handle and solve hold up to 84 GB, beyond the 64 GiB default (they would allocate and free it
+    # every step); 160 GiB (172 GB) leaves about 115 GB of the 288 for the live handle and torch
+    os.environ.setdefault("QPS_POOL_MAX_GB", "160")
     import numpy as np
     import torch
 

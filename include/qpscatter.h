@@ -277,7 +277,8 @@ void hbs_free(hbs_handle* h);                 /* NULL is a no-op */
 const char* hbs_last_error(void);             /* thread-local; "" if none */
 
 /* Device memory of freed handles and workspaces is kept by the library (per device, up to
- * QPS_POOL_MAX_GB GiB, default 64) and reused by later builds and solves.  qps_pool_release
+ * QPS_POOL_MAX_GB GiB, default 64; when the blocks of the latest call do not fit, blocks cached
+ * earlier are returned first) and reused by later builds and solves.  qps_pool_release
  * returns the cached blocks of the current device to HIP; qps_pool_cached_bytes reports them. */
 int qps_pool_release(void);
 int64_t qps_pool_cached_bytes(void);

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <string>
@@ -21,7 +22,8 @@ void clear_error() { g_last_error.clear(); }
 // that handles built and freed in a loop (one per frequency, or per benchmark step) do not pay
 // hipMalloc / hipFree each time.  Sizes are rounded to 1/8 of their power of two; a cached block
 // is reused for requests down to 4/5 of its size.  At most QPS_POOL_MAX_GB (default 64) GiB stay
-// cached per device; a failed hipMalloc returns the cache to the device and retries.
+// cached per device, the most recently released first; a failed hipMalloc returns the cache to the
+// device and retries.
 // A released block may still be read or written by queued work on any stream, so it is only
 // retired: it joins the free list at the next quiescent point (the end of a library call, after
 // one device synchronisation when blocks are pending, or an out-of-memory retry).  Within a call
@@ -52,15 +54,26 @@ size_t round_size(size_t b) {
   return (b + q - 1) / q * q;
 }
 // retired blocks of device dev (the caller has synchronised it) to the free list, or back to the
-// device beyond the cap
+// device beyond the cap.  The retired blocks served the latest call: to make room for them, blocks
+// cached earlier go back to the device first, largest first.
 void flush_retired(int dev) {
   Pool& P = pool();
   std::vector<void*> drop;
   {
     std::lock_guard<std::mutex> lk(P.mu);
+    size_t incoming = 0;
+    for (auto& kv : P.retired[dev])
+      if (kv.first <= P.cap) incoming += kv.first;
+    auto& fl = P.free_blocks[dev];
+    while (!fl.empty() && P.cached[dev] + incoming > P.cap) {
+      auto last = std::prev(fl.end());
+      drop.push_back(last->second);
+      P.cached[dev] -= last->first;
+      fl.erase(last);
+    }
     for (auto& kv : P.retired[dev]) {
       if (P.cached[dev] + kv.first <= P.cap) {
-        P.free_blocks[dev].emplace(kv.first, kv.second);
+        fl.emplace(kv.first, kv.second);
         P.cached[dev] += kv.first;
       } else {
         drop.push_back(kv.second);
