@@ -242,3 +242,33 @@ def test_alpert_needs_room_for_its_band():
     nodes, w, nrm, _ = _geom(256)
     rc, msg = _build(nodes, w, nrm, 256, quad=2, leaf_size=8)
     assert rc == -1 and "leaf_size" in msg
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every field the binding declares sits at the header's offset with the header's size (a C
+    program built against include/qpscatter.h prints offsetof and sizeof of each)."""
+    import shutil
+    import subprocess
+    from paper_1301_1247_amd import binding as B
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = (("hbs_opts", B.HbsOpts), ("qp_opts", B.QpOpts), ("hbs_stats_t", B.HbsStats))
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "qpscatter.h"', "int main(void) {"]
+    for cname, py in structs:
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("%zu %zu\\n", offsetof({cname}, {fname}), sizeof((({cname} *)0)->{fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True,
+                   capture_output=True, text=True)
+    out = iter(subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n"))
+    for cname, py in structs:
+        assert int(next(out)) == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            off, size = map(int, next(out).split())
+            fld = getattr(py, fname)
+            assert (off, size) == (fld.offset, fld.size), (cname, fname)
