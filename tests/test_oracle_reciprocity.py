@@ -69,3 +69,18 @@ def test_planted_phase_error_passes_energy_balance_but_breaks_reciprocity(monkey
     bad = _reciprocity_gap(solve, wl.omega, wl.period, -math.pi / 5, -1)
     assert r["flux"][0] < 1e-6 and ok < 1e-7
     assert bad > 1e-2
+
+
+@pytest.mark.parametrize("quad", ["kress", "alpert"])
+def test_reflection_reciprocity_with_high_order_quadratures(quad):
+    """Kress's spectral rule meets the relation to rounding at N = 128; Alpert's hybrid rule to
+    about 5e-13 at N = 256 (Dirichlet, the same grating and angles)."""
+    from oracle import alpert
+    from oracle import nystrom as ny
+    wl = qpinputs.workload("star_d1")
+    N = 128 if quad == "kress" else 256
+    disc = ny.Discretization(wl.curve, N)
+    A0 = ny.matrix(disc, wl.omega, "kress") if quad == "kress" else alpert.matrix_alpert(disc, wl.omega, wl.curve)
+    solve = lambda ths: pq.solve_qp(disc, N, wl.omega, wl.period, ths, P=1, A0=A0)
+    g = _reciprocity_gap(solve, wl.omega, wl.period, -math.pi / 5, -1)
+    assert g < (1e-12 if quad == "kress" else 5e-12), g
