@@ -8,6 +8,8 @@ What fixes the answer independently of the scheme:
 * At the exact anomaly theta = -arccos(1 - 2 pi / (omega d)) (the angle of the paper's Sec. 6.2)
   and next to it, energy is conserved (Remark 6.1), where the undisplaced scheme loses it.
 * The solution is continuous through the anomaly, with the square-root rate of k_n.
+* Reflection reciprocity between Bloch phases alpha and 1/alpha holds to rounding at the anomaly
+  and next to it.
 * The y-derivative of the kernel matches finite differences.
 """
 import math
@@ -120,3 +122,22 @@ def test_continuity_through_the_anomaly(star):
     d2 = _rel(wood.solve_wood(disc, OM, D, TH_WOOD + 1e-6, quad="kress", A0=A)["eta"], r0)
     assert d2 < d1 < 0.5
     assert 5.0 < d1 / d2 < 20.0                        # 100x smaller step, about 10x closer
+
+
+@pytest.mark.parametrize("offset", [0.0, 1e-3])
+def test_reciprocity_at_and_next_to_the_anomaly(star, offset):
+    """Reflection reciprocity k_p^a c_p^a = k_p^b c_p^b (amplitudes referred to y = 0) between an
+    angle a at (or next to) the anomaly and the angle b whose incidence reverses a's order p = -1;
+    b then sits at the mirrored anomaly.  Both are solved on their displaced contours, and the
+    relation holds to rounding (the derivation is in test_oracle_reciprocity.py)."""
+    disc, A = star
+    tha, p = TH_WOOD + offset, -1
+    kap = OM * math.cos(tha) + 2 * math.pi * p / D
+    thb = -math.acos(-kap / OM)
+    vals = []
+    for th in (tha, thb):
+        r = wood.solve_wood(disc, OM, D, th, quad="kress", A0=A)
+        n, kn, c, d, eps = wood.bragg_and_flux(disc, OM, D, th, r["eta"], r["y0"])
+        i = int(np.nonzero(n == p)[0][0])
+        vals.append(kn[i] * c[i] * np.exp(-1j * kn[i] * r["y0"]))
+    assert abs(vals[0] - vals[1]) < 1e-12 * abs(vals[0])
