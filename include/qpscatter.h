@@ -160,7 +160,7 @@ typedef struct {
                                uncompressed (formed in full: 16 (4M N + 4M N) bytes more device
                                memory), so that its corrections remove what the skeletons leave out
                                of the wall blocks; the displaced-contour solves of Wood's-anomaly
-                               angles take 1 */
+                               angles, and calls with refine_max_iter < 0, take 1 */
   int32_t wood;             /* angles within wood_min_kn of a Wood's anomaly (Sec. 2.4, second
                                improvement): 0 = solve them on the Sommerfeld contour displaced to cross
                                the real axis at wood_shift, with one added Rayleigh-Bloch wave and one
